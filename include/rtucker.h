@@ -1,0 +1,245 @@
+/*
+ * rtucker.h -- randomized Tucker decomposition with Kronecker-structured sketches
+ * on AMD Instinct MI355X (gfx950).  C ABI: plain pointers and sizes only.
+ *
+ * Method: Minster, Li, Ballard, "Parallel Randomized Tucker Decomposition
+ * Algorithms" (arXiv 2211.13028).  Notation: a d-way tensor X of size
+ * I_1 x ... x I_d, target ranks r_n, oversampling p, ell_n = r_n + p,
+ * Kronecker factors Phi_k (s_k x I_k) of the sketch, sketch width
+ * ltilde_n = prod_{k != n} s_k.
+ *
+ * Conventions shared by every entry point
+ *  - Tensors are dense, contiguous, C order (last index fastest).  A mode-n
+ *    unfolding X_(n) is the I_n x (N / I_n) row-major matrix whose row i holds
+ *    the slice i_n = i flattened in C order.  (The paper unfolds column-major;
+ *    the two differ by a column permutation, which changes no range, rank or
+ *    singular value; in C order the Kronecker factors of a multi-TTM appear in
+ *    ascending mode order.)
+ *  - Matrices are row-major.
+ *  - Pointers named "device" must be device memory of the current HIP device;
+ *    the caller owns all of them.  The library never allocates device memory:
+ *    scratch space is the caller's workspace `ws` of `ws_bytes` bytes (256-byte
+ *    aligned), whose required size the matching *_workspace query returns.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Every compute entry point validates its arguments on the host, then only
+ *    enqueues work on `stream` and returns: it does not synchronise, unless
+ *    stated otherwise.
+ *  - Results are bitwise reproducible for identical inputs and launch sizes
+ *    (fixed-order reductions, no floating-point atomics).
+ *  - Errors are returned as rt_status codes (never exceptions); on error no
+ *    work has been enqueued, except RT_EHIP, which reports a failed HIP call.
+ */
+#ifndef RTUCKER_H
+#define RTUCKER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RT_MAX_D 8
+
+typedef enum {
+  RT_OK = 0,
+  RT_EINVAL = -1,     /* bad scalar argument, NULL pointer, bad mode mask */
+  RT_ESHAPE = -2,     /* dimensions, ranks or sketch sizes inconsistent or beyond limits */
+  RT_EDTYPE = -3,     /* dtype not supported by this entry point */
+  RT_EWORKSPACE = -4, /* workspace NULL, misaligned or smaller than the query's answer */
+  RT_ENONFINITE = -5, /* NaN or Inf found in an input (reported by rtucker_rel_error_host) */
+  RT_EHIP = -6        /* a HIP runtime call failed */
+} rt_status;
+
+typedef enum {
+  RT_F64 = 0,    /* IEEE binary64 */
+  RT_F32 = 1,    /* IEEE binary32 */
+  RT_BF16 = 2,   /* bfloat16 (binary32 with 8 significant bits) */
+  RT_F8E4M3 = 3  /* OCP FP8 E4M3 ("e4m3fn": bias 7, max 448, no infinities) */
+} rt_dtype;
+
+typedef enum {
+  RT_RHKRON = 0,   /* randomized HOSVD with Kronecker factor reuse (Alg. 3.4, Sec. 3.3) */
+  RT_RSTHKRON = 1  /* randomized STHOSVD with Kronecker products (Alg. 3.3, Sec. 3.2) */
+} rt_algo;
+
+/* A dense C-order tensor in device memory. */
+typedef struct {
+  int32_t d;                /* order, 2..RT_MAX_D */
+  int64_t dims[RT_MAX_D];   /* I_1..I_d (entries past d ignored) */
+  rt_dtype dtype;
+  const void* data;         /* device pointer */
+} rt_tensor;
+
+/* Human-readable name of a status code (static string). */
+const char* rtucker_status_string(int status);
+
+/* Library version string (static). */
+const char* rtucker_version(void);
+
+/* ------------------------------------------------------------------ sizes
+ * Sketch sizes (Sec. 3.2 and 3.3, "choosing subranks").  Host only.
+ *  RT_RHKRON:   s_out[d]:  s_i = ceil((prod_j ell_j)^(1/(d-1)) / ell_i), computed
+ *               exactly in integers (least s with (s*ell_i)^(d-1) >= prod ell).
+ *  RT_RSTHKRON: s_out[d*d] (row-major S, diagonal 1): row j holds d-1 integer
+ *               factors of ell_j, each >= 2; when ell_j has no such split, ell_j
+ *               is raised to the least value that has one (extra oversampling);
+ *               the most balanced split (smallest largest factor) is taken and
+ *               assigned to modes k != j in ascending order, largest first.
+ * Fails with RT_ESHAPE if r_n > I_n, and if any s_k exceeds the mode size it
+ * will be applied to (I_k; for RT_RSTHKRON and k < j the truncated size). */
+int rtucker_sketch_sizes(int32_t d, const int64_t* dims, const int32_t* r, int32_t p,
+                         rt_algo algo, int64_t* s_out);
+
+/* ------------------------------------------------------------------ sketch
+ * All-at-once sketch multi-TTM (Alg. 3.4 sketch step; Sec. 3.4 dimension tree):
+ *   Y_n = X x_{k != n} Phi_k, returned as its mode-n unfolding, for every mode n
+ *   whose bit is set in mode_mask.
+ *  X:       d >= 2; dtype F64, F32, BF16 or F8E4M3.  The arithmetic runs in the
+ *           dtype of X: each Phi_k is rounded (to nearest even) to that dtype;
+ *           products accumulate in binary32 (binary64 when X is F64).  X is read
+ *           once for all requested modes.
+ *  phi[k]:  device, binary64, s_k x I_k row-major, for every k (a factor that no
+ *           requested mode uses may be NULL).
+ *  s[k]:    subranks, 1 <= s_k <= I_k.
+ *  Y[n]:    device, I_n x ltilde_n row-major, column index = C-order index of
+ *           (c_k, k != n ascending); binary64 when X is F64, else binary32.
+ *           Y[n] may be NULL for modes not in mode_mask.
+ *  ws:      at least rtucker_sketch_workspace() bytes. */
+int rtucker_sketch_workspace(const rt_tensor* X, const int64_t* s, uint32_t mode_mask,
+                             size_t* bytes);
+int rtucker_sketch(const rt_tensor* X, const double* const* phi, const int64_t* s,
+                   uint32_t mode_mask, void* const* Y, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ QR
+ * Thin QR of a tall-skinny sketch (range-finder QR, Alg. 2.3): Y = Q R with
+ * Householder reflections in binary64 and diag(R) >= 0, so Q is unique when Y
+ * has full column rank; for rank-deficient Y, Q is an orthonormal basis whose
+ * leading columns span range(Y).
+ *  Y: device, m x n row-major, dtype F32 or F64 (read, widened to binary64).
+ *  Q: device, binary64, m x c row-major, c = min(m, n).
+ *  R: device, binary64, c x n row-major (upper triangular), or NULL.
+ * Limits: 1 <= n <= 64 (RT_ESHAPE beyond), m >= 1. */
+int rtucker_qr_workspace(int64_t m, int64_t n, size_t* bytes);
+int rtucker_qr(int64_t m, int64_t n, const void* Y, rt_dtype y_dtype, double* Q, double* R,
+               void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ core
+ * Core multi-TTM (Alg. 3.4 core step): G = X x_k U_k^T over the modes k in
+ * mode_mask (a single bit gives one TTM, as in each step of Alg. 3.3).
+ *  U[k]: device, binary64, I_k x l_k row-major (orthonormal columns in the
+ *        method, but any matrix is accepted), for k in mode_mask.
+ *  l[k]: number of columns of U[k], 1 <= l_k <= 64.
+ *  G:    device; dims l_k for k in mode_mask and I_k otherwise; binary64 when X
+ *        is F64, else binary32.
+ *  Arithmetic: modes are contracted largest first (ties: lower mode first).  The
+ *  first contraction reads X in its own dtype (F64, F32 or BF16) with U rounded
+ *  to that dtype and binary32 accumulation (binary64 for F64); later ones run on
+ *  the binary32 (binary64) intermediate with U rounded to binary32 (binary64). */
+int rtucker_core_workspace(const rt_tensor* X, const int64_t* l, uint32_t mode_mask,
+                           size_t* bytes);
+int rtucker_core(const rt_tensor* X, const double* const* U, const int64_t* l,
+                 uint32_t mode_mask, void* G, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ decompose
+ * Full randomized Tucker decomposition [G; U_1..U_d] of X at ranks r with
+ * oversampling p (Alg. 3.3 or 3.4): sketches, QR, core, then the holistic
+ * truncation STHOSVD(G_hat, r) in mode order 1..d (Sec. 3.1) computed in
+ * binary64 (Gram matrices + cyclic Jacobi), and U_j = U_hat_j V_j.
+ *  X:        dtype F64, F32 or BF16.
+ *  X_sketch: NULL, or a tensor with X's dims used for the sketch instead of X
+ *            (e.g. an F8E4M3 copy); RT_RHKRON only.
+ *  r[d], p:  1 <= r_n <= min(I_n, ltilde_n), p >= 0.
+ *  s:        RT_RHKRON: d subranks; RT_RSTHKRON: d*d row-major subrank matrix
+ *            (diagonal ignored); NULL = rtucker_sketch_sizes().  Must satisfy
+ *            ltilde_n >= r_n + p.
+ *  phi:      device binary64 Gaussian factors.  RT_RHKRON: phi[k] is s_k x I_k.
+ *            RT_RSTHKRON: phi[j*d + k] (k != j) is s_{j,k} x n_k with n_k = c_k
+ *            for k < j and I_k for k > j, where c_k = min(I_k, ltilde_k) is the
+ *            truncated size of mode k.
+ *  G:        device binary64, r_1 x ... x r_d.
+ *  U[j]:     device binary64, I_j x r_j.  Columns ordered by decreasing singular
+ *            value of the core unfolding; each column's largest-magnitude entry
+ *            of V_j is positive.
+ * Limits: ltilde_n clipped to I_n must be <= 64. */
+int rtucker_decompose_workspace(const rt_tensor* X, const rt_tensor* X_sketch, const int32_t* r,
+                                int32_t p, const int64_t* s, rt_algo algo, size_t* bytes);
+int rtucker_decompose(const rt_tensor* X, const rt_tensor* X_sketch, const int32_t* r, int32_t p,
+                      const int64_t* s, rt_algo algo, const double* const* phi, double* G,
+                      double* const* U, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ error
+ * Squared norms for the relative reconstruction error (Sec. 4), in binary64 on
+ * the device, by explicit residual (no cancellation-prone identity):
+ *   out[0] = ||X - G x_1 U_1 ... x_d U_d||^2,  out[1] = ||X||^2,
+ *   out[2] = ||G||^2,  out[3] = number of non-finite entries of X (as double).
+ *  G: device binary64 r_1 x ... x r_d; U[j]: device binary64 I_j x r_j.
+ *  out: device, 4 doubles.  X: dtype F64, F32 or BF16. */
+int rtucker_rel_error_workspace(const rt_tensor* X, const int32_t* r, size_t* bytes);
+int rtucker_rel_error(const rt_tensor* X, const double* G, const int32_t* r,
+                      const double* const* U, double* out, void* ws, size_t ws_bytes,
+                      void* stream);
+
+/* ------------------------------------------------------------------ precision
+ * Elementwise conversion dst[i] = round(src[i] * 2^scale_exp) to dst_dtype with
+ * round-to-nearest-even.  F8E4M3 saturates finite values to +-448 and maps NaN
+ * or Inf to NaN (0x7f/0xff); BF16 and F32 overflow to Inf.
+ *  src_dtype: F64 or F32.  dst_dtype: F32, BF16 or F8E4M3.  n >= 0. */
+int rtucker_convert(const void* src, rt_dtype src_dtype, void* dst, rt_dtype dst_dtype,
+                    int64_t n, int32_t scale_exp, void* stream);
+
+/* ------------------------------------------------------------------ adjoint
+ * Plain multi-TTM and its adjoint pieces, for differentiation (Sec. 2.1
+ * multi-TTM; the adjoint of Y = X x_k A_k is dX = dY x_k A_k^T and
+ * dA_n = dY_(n) Z_(n)^T with Z = X x_{k != n} A_k).
+ *
+ * rtucker_multi_ttm: Y = X x_k op(A_k) for k in mode_mask, where op(A) = A
+ *  (A_k: m_k x I_k) or, with transpose != 0, op(A) = A^T (A_k: I_k x m_k).
+ *  X, A_k, Y share one dtype, F32 or F64; arithmetic in that dtype.  Y dims:
+ *  m_k for k in mode_mask, I_k otherwise.  1 <= m_k <= 256.
+ * rtucker_mode_contract: out[i][j] = sum over all indices except mode n of
+ *  P[.., i, ..] * Q[.., j, ..]  (= P_(n) Q_(n)^T).  P, Q: same dtype (F32 or
+ *  F64), same dims except mode n.  out: device, P.dims[n] x Q.dims[n], that dtype.
+ * rtucker_sq_residual: R = A - B elementwise (R may be NULL) and
+ *  out[0] = sum (A - B)^2 accumulated in binary64.  A, B (and R): same dims and
+ *  dtype, F32 or F64; out: device, 1 double. */
+int rtucker_multi_ttm_workspace(const rt_tensor* X, const int64_t* m, uint32_t mode_mask,
+                                size_t* bytes);
+int rtucker_multi_ttm(const rt_tensor* X, const void* const* A, const int64_t* m,
+                      uint32_t mode_mask, int32_t transpose, void* Y, void* ws, size_t ws_bytes,
+                      void* stream);
+int rtucker_mode_contract(const rt_tensor* P, const rt_tensor* Q, int32_t n, void* out,
+                          void* ws, size_t ws_bytes, void* stream);
+int rtucker_mode_contract_workspace(const rt_tensor* P, const rt_tensor* Q, int32_t n,
+                                    size_t* bytes);
+int rtucker_sq_residual(const rt_tensor* A, const void* B, void* R, double* out, void* ws,
+                        size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ batched
+ * Batched factor-reuse decomposition of many independent 3-way tensors of
+ * different sizes (Alg. 3.4 applied per tensor): every phase runs for all
+ * tensors in one grouped launch whose work items cover every tensor.
+ * Per item: X (device, dtype of the batch, dims[3]), r[3], s[3] (subranks;
+ * 0 entries = formula), phi[3] (device binary64 s_k x I_k), G (device binary64
+ * r1 x r2 x r3), U[3] (device binary64 I_k x r_k).
+ *  dtype: F32 or BF16.  count >= 1.  Limits per item as rtucker_decompose. */
+typedef struct {
+  const void* X;
+  int64_t dims[3];
+  int32_t r[3];
+  int64_t s[3];
+  const double* phi[3];
+  double* G;
+  double* U[3];
+} rt_batch_item;
+
+int rtucker_decompose_batched_workspace(int32_t count, const rt_batch_item* items, int32_t p,
+                                        rt_dtype dtype, size_t* bytes);
+int rtucker_decompose_batched(int32_t count, const rt_batch_item* items, int32_t p,
+                              rt_dtype dtype, void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTUCKER_H */

@@ -1,0 +1,769 @@
+// Host side of rtucker: argument validation, workspace planning and the
+// orchestration of the HIP kernels behind the C ABI declared in rtucker.h.
+//
+// Every entry point is implemented once as a "plan" that walks the same steps
+// in two modes: dry (only sizes workspace by bump-allocating from address 0)
+// and live (allocates from the caller's workspace and enqueues kernels).  The
+// *_workspace queries run the dry mode, so the size they report is exactly
+// what the live call consumes.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "kernels.hpp"
+
+using namespace rt;
+
+namespace rt {
+// defined in k_ttm.hip
+size_t ttm_mfma_ws(rt_dtype xdt, int64_t A, int64_t K, int64_t B, int64_t m);
+hipError_t launch_ttm_mfma_ws(const void* X, rt_dtype xdt, int64_t A, int64_t K, int64_t B, const void* Mop,
+                              int64_t m, float* Y, void* ws, hipStream_t st);
+}  // namespace rt
+
+namespace {
+
+// ------------------------------------------------------------------ context
+struct Ctx {
+  bool dry;          // size workspace only, launch nothing
+  bool check_ptrs;   // validate data pointers (compute calls)
+  char* base;
+  size_t off = 0;
+  size_t cap;
+  hipStream_t st;
+  hipError_t err = hipSuccess;
+  size_t peak = 0;
+  void* take(size_t bytes) {
+    if (bytes == 0) return nullptr;
+    const size_t o = align256(off);
+    off = o + align256(bytes);
+    return dry ? nullptr : base + o;
+  }
+  void chk(hipError_t e) {
+    if (err == hipSuccess && e != hipSuccess) err = e;
+  }
+};
+
+struct Ten {
+  std::vector<int64_t> dims;
+  const void* p;
+  rt_dtype dt;
+  int64_t numel() const {
+    int64_t n = 1;
+    for (int64_t v : dims) n *= v;
+    return n;
+  }
+  int64_t before(int k) const {
+    int64_t n = 1;
+    for (int i = 0; i < k; ++i) n *= dims[i];
+    return n;
+  }
+  int64_t after(int k) const {
+    int64_t n = 1;
+    for (size_t i = k + 1; i < dims.size(); ++i) n *= dims[i];
+    return n;
+  }
+};
+
+rt_dtype ctype(rt_dtype x) { return x == RT_F64 ? RT_F64 : RT_F32; }
+
+bool valid_dtype(int dt) { return dt >= RT_F64 && dt <= RT_F8E4M3; }
+
+int check_tensor(const rt_tensor* X, bool need_data) {
+  if (!X) return RT_EINVAL;
+  if (X->d < 2 || X->d > RT_MAX_D) return RT_ESHAPE;
+  for (int i = 0; i < X->d; ++i)
+    if (X->dims[i] < 1) return RT_ESHAPE;
+  if (!valid_dtype(X->dtype)) return RT_EDTYPE;
+  if (need_data && !X->data) return RT_EINVAL;
+  return RT_OK;
+}
+
+Ten ten_of(const rt_tensor* X) {
+  Ten t;
+  t.dims.assign(X->dims, X->dims + X->d);
+  t.p = X->data;
+  t.dt = X->dtype;
+  return t;
+}
+
+int check_ws(const Ctx& c, void* ws, size_t ws_bytes) {
+  if (c.off == 0) return RT_OK;
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return RT_EWORKSPACE;
+  if (ws_bytes < c.off) return RT_EWORKSPACE;
+  return RT_OK;
+}
+
+// ------------------------------------------------------------------ building blocks
+void* prep(Ctx& c, const double* src, int64_t m, int64_t K, bool trans, rt_dtype round_to, rt_dtype store,
+           int64_t m_pad = 0) {
+  if (m_pad < m) m_pad = m;
+  void* dst = c.take(static_cast<size_t>(m_pad) * K * dtype_size(store));
+  if (!c.dry) c.chk(launch_prep_matrix(src, m, K, trans, round_to, store, m_pad, dst, c.st));
+  return dst;
+}
+
+// T x_k M, M: m x dims[k] row-major in the compute type of T
+Ten ttm(Ctx& c, const Ten& T, int k, const void* M, int64_t m, void* dst = nullptr) {
+  Ten out;
+  out.dims = T.dims;
+  out.dims[k] = m;
+  out.dt = ctype(T.dt);
+  const int64_t A = T.before(k), K = T.dims[k], B = T.after(k);
+  void* y = dst ? dst : c.take(static_cast<size_t>(A) * m * B * dtype_size(out.dt));
+  out.p = y;
+  if (!c.dry) c.chk(launch_ttm_generic(T.p, T.dt, A, K, B, M, m, y, c.st));
+  return out;
+}
+
+struct SketchOut {
+  Ten Y;              // tensor layout, compute type
+  int64_t A, m, B;    // unfolding view of mode n
+};
+
+// Y_n = X x_{k != n} Phi_k for n in mask (dimension tree: one pass over X).
+void sketch_impl(Ctx& c, const Ten& X, const double* const* phi, const int64_t* s, uint32_t mask,
+                 std::vector<SketchOut>& out) {
+  const int d = static_cast<int>(X.dims.size());
+  const rt_dtype ct = ctype(X.dt);
+  std::vector<const void*> op(d, nullptr);
+  for (int k = 0; k < d; ++k) {
+    bool need = false;
+    for (int n = 0; n < d; ++n)
+      if ((mask >> n & 1u) && n != k) need = true;
+    if (need) op[k] = prep(c, phi ? phi[k] : nullptr, s[k], X.dims[k], false, X.dt, ct);
+  }
+  const int L = d - 1, S = d - 2;
+  bool needZ = false, needW = false;
+  for (int n = 0; n < d; ++n)
+    if (mask >> n & 1u) {
+      if (n == L) needW = true; else needZ = true;
+    }
+  Ten Z, W;
+  Z.dims = X.dims; Z.dims[L] = s[L]; Z.dt = ct; Z.p = nullptr;
+  W.dims = X.dims; W.dims[S] = s[S]; W.dt = ct; W.p = nullptr;
+  const int64_t A0 = X.before(S), P = X.dims[S], Q = X.dims[L];
+  if (sketch_zw_ok(X.dt, s[S], s[L])) {
+    const ZWPlan plan = sketch_zw_plan(X.dt, A0, P, Q, s[S], s[L], needZ, needW);
+    if (needZ) Z.p = c.take(static_cast<size_t>(Z.numel()) * dtype_size(ct));
+    if (needW) W.p = c.take(static_cast<size_t>(W.numel()) * dtype_size(ct));
+    void* zws = plan.ws_bytes ? c.take(plan.ws_bytes) : nullptr;
+    if (!c.dry)
+      c.chk(launch_sketch_zw(X.p, X.dt, A0, P, Q, needW ? op[S] : nullptr, s[S], needZ ? op[L] : nullptr, s[L],
+                             const_cast<void*>(Z.p), const_cast<void*>(W.p), plan, zws, c.st));
+  } else {
+    if (needZ) Z = ttm(c, X, L, op[L], s[L]);
+    if (needW) W = ttm(c, X, S, op[S], s[S]);
+  }
+  out.assign(d, SketchOut{});
+  for (int n = 0; n < d; ++n) {
+    if (!(mask >> n & 1u)) continue;
+    Ten cur = (n == L) ? W : Z;
+    std::vector<int> chain;
+    if (n < S) chain.push_back(S);
+    for (int k = 0; k < S; ++k)
+      if (k != n) chain.push_back(k);
+    for (int k : chain) cur = ttm(c, cur, k, op[k], s[k]);
+    SketchOut o;
+    o.Y = cur;
+    o.A = cur.before(n);
+    o.m = cur.dims[n];
+    o.B = cur.after(n);
+    out[n] = o;
+  }
+}
+
+// G = T x_k U_k^T over the modes of mask, largest first; U_k: I_k x l_k binary64.
+Ten core_impl(Ctx& c, const Ten& X, const double* const* U, const int64_t* l, uint32_t mask, void* dst) {
+  const int d = static_cast<int>(X.dims.size());
+  std::vector<int> order;
+  for (int k = 0; k < d; ++k)
+    if (mask >> k & 1u) order.push_back(k);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return X.dims[a] > X.dims[b]; });
+  Ten cur = X;
+  for (size_t idx = 0; idx < order.size(); ++idx) {
+    const int k = order[idx];
+    const bool last = idx + 1 == order.size();
+    const int64_t A = cur.before(k), K = cur.dims[k], B = cur.after(k), m = l[k];
+    const rt_dtype ct = ctype(cur.dt);
+    Ten out;
+    out.dims = cur.dims;
+    out.dims[k] = m;
+    out.dt = ct;
+    void* y = (last && dst) ? dst : c.take(static_cast<size_t>(A) * m * B * dtype_size(ct));
+    out.p = y;
+    if ((cur.dt == RT_F32 || cur.dt == RT_BF16) && ttm_mfma_ok(cur.dt, A, K, B, m)) {
+      const void* mop = prep(c, U ? U[k] : nullptr, m, K, true, cur.dt, cur.dt, ttm_mfma_mpad(m));
+      void* w = nullptr;
+      const size_t wb = ttm_mfma_ws(cur.dt, A, K, B, m);
+      if (wb) w = c.take(wb);
+      if (!c.dry) c.chk(launch_ttm_mfma_ws(cur.p, cur.dt, A, K, B, mop, m, static_cast<float*>(y), w, c.st));
+    } else {
+      const void* M = prep(c, U ? U[k] : nullptr, m, K, true, cur.dt == RT_F64 ? RT_F64 : cur.dt, ct);
+      if (!c.dry) c.chk(launch_ttm_generic(cur.p, cur.dt, A, K, B, M, m, y, c.st));
+    }
+    cur = out;
+  }
+  return cur;
+}
+
+// STHOSVD of the binary64 core in mode order 1..d, then U_j = U_hat_j V_j.
+void truncate_impl(Ctx& c, Ten G, const int32_t* r, double* const* Uhat, const std::vector<int64_t>& I,
+                   double* Gout, double* const* Uout) {
+  const int d = static_cast<int>(G.dims.size());
+  for (int j = 0; j < d; ++j) {
+    const int64_t cj = G.dims[j], A = G.before(j), B = G.after(j), rj = r[j];
+    double* gram = static_cast<double*>(c.take(static_cast<size_t>(cj) * cj * sizeof(double)));
+    void* mcws = c.take(mode_contract_ws(RT_F64, A, cj, cj, B));
+    double* V = static_cast<double*>(c.take(static_cast<size_t>(cj) * rj * sizeof(double)));
+    if (!c.dry) {
+      c.chk(launch_mode_contract(G.p, G.p, RT_F64, A, cj, cj, B, gram, mcws, c.st));
+      c.chk(launch_sym_eig_top(gram, cj, rj, V, nullptr, c.st));
+    }
+    const void* Vt = prep(c, V, rj, cj, true, RT_F64, RT_F64);
+    G = ttm(c, G, j, Vt, rj, (j == d - 1) ? Gout : nullptr);
+    if (!c.dry) c.chk(launch_ttm_generic(Uhat[j], RT_F64, I[j], cj, 1, Vt, rj, Uout[j], c.st));
+  }
+}
+
+Ten to_f64(Ctx& c, const Ten& T) {
+  if (T.dt == RT_F64) return T;
+  Ten o = T;
+  o.dt = RT_F64;
+  o.p = c.take(static_cast<size_t>(T.numel()) * sizeof(double));
+  if (!c.dry) c.chk(launch_convert(T.p, T.dt, const_cast<void*>(o.p), RT_F64, T.numel(), 0, c.st));
+  return o;
+}
+
+int64_t prod_except(const int64_t* s, int d, int n) {
+  int64_t p = 1;
+  for (int k = 0; k < d; ++k)
+    if (k != n) p *= s[k];
+  return p;
+}
+
+// exact integer version of the reuse-subrank formula
+void reuse_subranks(int d, const int64_t* ell, int64_t* s) {
+  // P = prod ell; s_i = least s with (s*ell_i)^(d-1) >= P.  Compare in long double
+  // logs first, then confirm with exact integer arithmetic when it fits.
+  for (int i = 0; i < d; ++i) {
+    int64_t v = 1;
+    for (;; ++v) {
+      // compare (v*ell_i)^(d-1) >= prod_j ell_j  <=>  prod over j of ell_j / (v*ell_i) <= 1
+      long double lhs = 1.0L;
+      bool ge = false;
+      // exact: accumulate ratios using integer arithmetic in 128 bits where possible
+      __int128 left = 1, right = 1;
+      bool overflow = false;
+      for (int t = 0; t < d - 1; ++t) {
+        left *= static_cast<__int128>(v * ell[i]);
+        if (left > (static_cast<__int128>(1) << 100)) overflow = true;
+      }
+      for (int t = 0; t < d; ++t) {
+        right *= ell[t];
+        if (right > (static_cast<__int128>(1) << 100)) overflow = true;
+      }
+      if (!overflow) {
+        ge = left >= right;
+      } else {
+        lhs = (d - 1) * logl(static_cast<long double>(v * ell[i]));
+        long double rhs = 0.0L;
+        for (int t = 0; t < d; ++t) rhs += logl(static_cast<long double>(ell[t]));
+        ge = lhs >= rhs;
+      }
+      if (ge) break;
+    }
+    s[i] = v;
+  }
+}
+
+void splits(int64_t n, int parts, int64_t lo, std::vector<int64_t>& cur, std::vector<std::vector<int64_t>>& out) {
+  if (parts == 1) {
+    if (n >= lo) {
+      cur.push_back(n);
+      out.push_back(cur);
+      cur.pop_back();
+    }
+    return;
+  }
+  for (int64_t f = lo;; ++f) {
+    int64_t pw = 1;
+    bool big = false;
+    for (int t = 0; t < parts; ++t) {
+      pw *= f;
+      if (pw > n) { big = true; break; }
+    }
+    if (big) break;
+    if (n % f == 0) {
+      cur.push_back(f);
+      splits(n / f, parts - 1, f, cur, out);
+      cur.pop_back();
+    }
+  }
+}
+
+// row of S: factors (non-increasing) of the least value >= ell with a (d-1)-factor split
+std::vector<int64_t> sth_row(int64_t ell, int parts) {
+  for (int64_t v = ell;; ++v) {
+    std::vector<std::vector<int64_t>> all;
+    std::vector<int64_t> cur;
+    splits(v, parts, 2, cur, all);
+    if (all.empty()) continue;
+    for (auto& a : all) std::sort(a.begin(), a.end(), std::greater<int64_t>());
+    std::sort(all.begin(), all.end());
+    return all.front();
+  }
+}
+
+int sizes_impl(int d, const int64_t* dims, const int32_t* r, int32_t p, rt_algo algo, int64_t* s) {
+  if (d < 2 || d > RT_MAX_D || !dims || !r || !s) return RT_EINVAL;
+  if (p < 0) return RT_EINVAL;
+  std::vector<int64_t> ell(d);
+  for (int i = 0; i < d; ++i) {
+    if (dims[i] < 1 || r[i] < 1 || r[i] > dims[i]) return RT_ESHAPE;
+    ell[i] = static_cast<int64_t>(r[i]) + p;
+  }
+  if (algo == RT_RHKRON) {
+    reuse_subranks(d, ell.data(), s);
+    for (int i = 0; i < d; ++i)
+      if (s[i] > dims[i]) return RT_ESHAPE;
+    return RT_OK;
+  }
+  if (algo != RT_RSTHKRON) return RT_EINVAL;
+  if (d == 2) {
+    for (int j = 0; j < 2; ++j) {
+      s[j * 2 + j] = 1;
+      s[j * 2 + (1 - j)] = ell[j];
+    }
+  } else {
+    for (int j = 0; j < d; ++j) {
+      std::vector<int64_t> f = sth_row(ell[j], d - 1);
+      int t = 0;
+      for (int k = 0; k < d; ++k) s[j * d + k] = (k == j) ? 1 : f[t++];
+    }
+  }
+  // sizes the factors act on: truncated c_k for k < j, I_k for k > j
+  std::vector<int64_t> cdim(d);
+  for (int k = 0; k < d; ++k) cdim[k] = std::min<int64_t>(dims[k], prod_except(s + k * d, d, k));
+  for (int j = 0; j < d; ++j)
+    for (int k = 0; k < d; ++k)
+      if (k != j && s[j * d + k] > (k < j ? cdim[k] : dims[k])) return RT_ESHAPE;
+  return RT_OK;
+}
+
+// ------------------------------------------------------------------ plans
+int plan_sketch(Ctx& c, const rt_tensor* X, const double* const* phi, const int64_t* s, uint32_t mask,
+                void* const* Y) {
+  int st = check_tensor(X, c.check_ptrs);
+  if (st) return st;
+  const int d = X->d;
+  if (!s || mask == 0 || (mask >> d) != 0) return RT_EINVAL;
+  for (int k = 0; k < d; ++k)
+    if (s[k] < 1 || s[k] > X->dims[k]) return RT_ESHAPE;
+  if (c.check_ptrs) {
+    if (!phi || !Y) return RT_EINVAL;
+    for (int n = 0; n < d; ++n) {
+      if (!(mask >> n & 1u)) continue;
+      if (!Y[n]) return RT_EINVAL;
+      for (int k = 0; k < d; ++k)
+        if (k != n && !phi[k]) return RT_EINVAL;
+    }
+  }
+  Ten T = ten_of(X);
+  std::vector<SketchOut> outs;
+  sketch_impl(c, T, phi, s, mask, outs);
+  const size_t es = dtype_size(ctype(X->dtype));
+  for (int n = 0; n < d; ++n) {
+    if (!(mask >> n & 1u)) continue;
+    if (!c.dry) c.chk(launch_unfold(outs[n].Y.p, es, outs[n].A, outs[n].m, outs[n].B, Y[n], c.st));
+  }
+  return RT_OK;
+}
+
+int plan_core(Ctx& c, const rt_tensor* X, const double* const* U, const int64_t* l, uint32_t mask, void* G) {
+  int st = check_tensor(X, c.check_ptrs);
+  if (st) return st;
+  if (X->dtype == RT_F8E4M3) return RT_EDTYPE;
+  const int d = X->d;
+  if (!l || mask == 0 || (mask >> d) != 0) return RT_EINVAL;
+  for (int k = 0; k < d; ++k)
+    if ((mask >> k & 1u) && (l[k] < 1 || l[k] > 64)) return RT_ESHAPE;
+  if (c.check_ptrs) {
+    if (!U || !G) return RT_EINVAL;
+    for (int k = 0; k < d; ++k)
+      if ((mask >> k & 1u) && !U[k]) return RT_EINVAL;
+  }
+  core_impl(c, ten_of(X), U, l, mask, G);
+  return RT_OK;
+}
+
+int plan_qr(Ctx& c, int64_t m, int64_t n, const void* Y, rt_dtype ydt, double* Q, double* R) {
+  if (m < 1 || n < 1) return RT_ESHAPE;
+  if (n > kMaxQRCols) return RT_ESHAPE;
+  if (ydt != RT_F32 && ydt != RT_F64) return RT_EDTYPE;
+  if (c.check_ptrs && (!Y || !Q)) return RT_EINVAL;
+  QRJob job{Y, 1, m, n, Q, R};
+  void* w = c.take(qr_ws(&job, 1));
+  if (!c.dry) c.chk(launch_qr(&job, 1, ydt, w, c.st));
+  return RT_OK;
+}
+
+int plan_decompose(Ctx& c, const rt_tensor* X, const rt_tensor* Xs, const int32_t* r, int32_t p, const int64_t* s_in,
+                   rt_algo algo, const double* const* phi, double* G, double* const* U) {
+  int st = check_tensor(X, c.check_ptrs);
+  if (st) return st;
+  if (X->dtype == RT_F8E4M3) return RT_EDTYPE;
+  const int d = X->d;
+  if (!r || p < 0) return RT_EINVAL;
+  if (algo != RT_RHKRON && algo != RT_RSTHKRON) return RT_EINVAL;
+  if (Xs) {
+    if (algo != RT_RHKRON) return RT_EINVAL;
+    st = check_tensor(Xs, c.check_ptrs);
+    if (st) return st;
+    if (Xs->d != d) return RT_ESHAPE;
+    for (int k = 0; k < d; ++k)
+      if (Xs->dims[k] != X->dims[k]) return RT_ESHAPE;
+  }
+  std::vector<int64_t> I(X->dims, X->dims + d);
+  for (int k = 0; k < d; ++k)
+    if (r[k] < 1 || r[k] > I[k]) return RT_ESHAPE;
+  const int nS = (algo == RT_RHKRON) ? d : d * d;
+  std::vector<int64_t> s(nS);
+  if (s_in) {
+    std::copy(s_in, s_in + nS, s.begin());
+    if (algo == RT_RSTHKRON)
+      for (int j = 0; j < d; ++j) s[j * d + j] = 1;
+  } else {
+    st = sizes_impl(d, X->dims, r, p, algo, s.data());
+    if (st) return st;
+  }
+  std::vector<int64_t> cdim(d);
+  for (int n = 0; n < d; ++n) {
+    const int64_t lt = (algo == RT_RHKRON) ? prod_except(s.data(), d, n) : prod_except(s.data() + n * d, d, n);
+    if (lt < r[n] + static_cast<int64_t>(p)) return RT_ESHAPE;
+    cdim[n] = std::min<int64_t>(I[n], lt);
+    if (cdim[n] > 64) return RT_ESHAPE;
+  }
+  if (algo == RT_RHKRON) {
+    for (int k = 0; k < d; ++k)
+      if (s[k] < 1 || s[k] > I[k]) return RT_ESHAPE;
+  } else {
+    for (int j = 0; j < d; ++j)
+      for (int k = 0; k < d; ++k)
+        if (k != j && (s[j * d + k] < 1 || s[j * d + k] > (k < j ? cdim[k] : I[k]))) return RT_ESHAPE;
+  }
+  if (c.check_ptrs) {
+    if (!phi || !G || !U) return RT_EINVAL;
+    for (int j = 0; j < d; ++j) {
+      if (!U[j]) return RT_EINVAL;
+      if (algo == RT_RHKRON) {
+        if (!phi[j]) return RT_EINVAL;
+      } else {
+        for (int k = 0; k < d; ++k)
+          if (k != j && !phi[j * d + k]) return RT_EINVAL;
+      }
+    }
+  }
+  std::vector<double*> Uhat(d);
+  for (int n = 0; n < d; ++n) Uhat[n] = static_cast<double*>(c.take(static_cast<size_t>(I[n]) * cdim[n] * sizeof(double)));
+  Ten cur = ten_of(X);
+  if (algo == RT_RHKRON) {
+    const Ten Tsk = Xs ? ten_of(Xs) : cur;
+    std::vector<SketchOut> outs;
+    sketch_impl(c, Tsk, phi, s.data(), (1u << d) - 1u, outs);
+    std::vector<QRJob> jobs(d);
+    for (int n = 0; n < d; ++n) jobs[n] = QRJob{outs[n].Y.p, outs[n].A, outs[n].m, outs[n].B, Uhat[n], nullptr};
+    void* w = c.take(qr_ws(jobs.data(), d));
+    if (!c.dry) c.chk(launch_qr(jobs.data(), d, ctype(Tsk.dt), w, c.st));
+    cur = core_impl(c, cur, Uhat.data(), cdim.data(), (1u << d) - 1u, nullptr);
+  } else {
+    for (int j = 0; j < d; ++j) {
+      std::vector<int64_t> sj(s.begin() + j * d, s.begin() + (j + 1) * d);
+      std::vector<const double*> phij(d, nullptr);
+      if (phi)
+        for (int k = 0; k < d; ++k) phij[k] = (k == j) ? nullptr : phi[j * d + k];
+      std::vector<SketchOut> outs;
+      sketch_impl(c, cur, phij.data(), sj.data(), 1u << j, outs);
+      QRJob job{outs[j].Y.p, outs[j].A, outs[j].m, outs[j].B, Uhat[j], nullptr};
+      void* w = c.take(qr_ws(&job, 1));
+      if (!c.dry) c.chk(launch_qr(&job, 1, ctype(cur.dt), w, c.st));
+      cur = core_impl(c, cur, Uhat.data(), cdim.data(), 1u << j, nullptr);
+    }
+  }
+  Ten G64 = to_f64(c, cur);
+  truncate_impl(c, G64, r, Uhat.data(), I, G, U);
+  return RT_OK;
+}
+
+int plan_rel_error(Ctx& c, const rt_tensor* X, const double* G, const int32_t* r, const double* const* U,
+                   double* out) {
+  int st = check_tensor(X, c.check_ptrs);
+  if (st) return st;
+  if (X->dtype == RT_F8E4M3) return RT_EDTYPE;
+  const int d = X->d;
+  if (!r) return RT_EINVAL;
+  for (int k = 0; k < d; ++k)
+    if (r[k] < 1 || r[k] > 64) return RT_ESHAPE;
+  if (c.check_ptrs) {
+    if (!G || !U || !out) return RT_EINVAL;
+    for (int k = 0; k < d; ++k)
+      if (!U[k]) return RT_EINVAL;
+  }
+  Ten T;
+  T.dims.assign(r, r + d);
+  T.p = G;
+  T.dt = RT_F64;
+  for (int k = d - 1; k >= 1; --k) T = ttm(c, T, k, U ? U[k] : nullptr, X->dims[k]);
+  const int64_t Brest = T.after(0);
+  void* w = c.take(recon_residual_ws(X->dims[0], Brest));
+  if (!c.dry) {
+    c.chk(launch_recon_residual(X->data, X->dtype, X->dims[0], Brest, U[0], static_cast<const double*>(T.p), r[0],
+                                out, w, c.st));
+    int64_t ng = 1;
+    for (int k = 0; k < d; ++k) ng *= r[k];
+    c.chk(launch_sumsq_f64(G, ng, out + 2, c.st));
+  }
+  return RT_OK;
+}
+
+int plan_multi_ttm(Ctx& c, const rt_tensor* X, const void* const* A, const int64_t* m, uint32_t mask, int32_t trans,
+                   void* Y) {
+  int st = check_tensor(X, c.check_ptrs);
+  if (st) return st;
+  if (X->dtype != RT_F32 && X->dtype != RT_F64) return RT_EDTYPE;
+  const int d = X->d;
+  if (!m || mask == 0 || (mask >> d) != 0) return RT_EINVAL;
+  for (int k = 0; k < d; ++k)
+    if ((mask >> k & 1u) && (m[k] < 1 || m[k] > 256)) return RT_ESHAPE;
+  if (c.check_ptrs) {
+    if (!A || !Y) return RT_EINVAL;
+    for (int k = 0; k < d; ++k)
+      if ((mask >> k & 1u) && !A[k]) return RT_EINVAL;
+  }
+  const size_t es = dtype_size(X->dtype);
+  std::vector<int> order;
+  for (int k = 0; k < d; ++k)
+    if (mask >> k & 1u) order.push_back(k);
+  // contract the modes that shrink the tensor most first
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return static_cast<double>(m[a]) / X->dims[a] < static_cast<double>(m[b]) / X->dims[b];
+  });
+  Ten cur = ten_of(X);
+  for (size_t i = 0; i < order.size(); ++i) {
+    const int k = order[i];
+    const void* M = A ? A[k] : nullptr;
+    if (trans) {
+      void* t = c.take(static_cast<size_t>(m[k]) * X->dims[k] * es);
+      if (!c.dry) c.chk(launch_unfold(A[k], es, X->dims[k], m[k], 1, t, c.st));
+      M = t;
+    }
+    cur = ttm(c, cur, k, M, m[k], (i + 1 == order.size()) ? Y : nullptr);
+  }
+  return RT_OK;
+}
+
+int plan_mode_contract(Ctx& c, const rt_tensor* P, const rt_tensor* Q, int32_t n, void* out) {
+  int st = check_tensor(P, c.check_ptrs);
+  if (st) return st;
+  st = check_tensor(Q, c.check_ptrs);
+  if (st) return st;
+  if (P->dtype != Q->dtype || (P->dtype != RT_F32 && P->dtype != RT_F64)) return RT_EDTYPE;
+  if (P->d != Q->d || n < 0 || n >= P->d) return RT_EINVAL;
+  for (int k = 0; k < P->d; ++k)
+    if (k != n && P->dims[k] != Q->dims[k]) return RT_ESHAPE;
+  if (c.check_ptrs && !out) return RT_EINVAL;
+  const Ten TP = ten_of(P);
+  const int64_t A = TP.before(n), B = TP.after(n);
+  void* w = c.take(mode_contract_ws(P->dtype, A, P->dims[n], Q->dims[n], B));
+  if (!c.dry) c.chk(launch_mode_contract(P->data, Q->data, P->dtype, A, P->dims[n], Q->dims[n], B, out, w, c.st));
+  return RT_OK;
+}
+
+int plan_batched(Ctx& c, int32_t count, const rt_batch_item* items, int32_t p, rt_dtype dtype) {
+  if (count < 1 || !items || p < 0) return RT_EINVAL;
+  if (dtype != RT_F32 && dtype != RT_BF16) return RT_EDTYPE;
+  for (int32_t i = 0; i < count; ++i) {
+    const rt_batch_item& it = items[i];
+    rt_tensor X;
+    X.d = 3;
+    for (int k = 0; k < 3; ++k) X.dims[k] = it.dims[k];
+    for (int k = 3; k < RT_MAX_D; ++k) X.dims[k] = 0;
+    X.dtype = dtype;
+    X.data = it.X;
+    int64_t s[3];
+    const int64_t* sp = nullptr;
+    if (it.s[0] > 0 && it.s[1] > 0 && it.s[2] > 0) {
+      for (int k = 0; k < 3; ++k) s[k] = it.s[k];
+      sp = s;
+    }
+    const double* phi[3] = {it.phi[0], it.phi[1], it.phi[2]};
+    double* U[3] = {it.U[0], it.U[1], it.U[2]};
+    const size_t mark = c.off;
+    const int st = plan_decompose(c, &X, nullptr, it.r, p, sp, RT_RHKRON, phi, it.G, U);
+    if (st) return st;
+    // items run one after another on the stream, so they can share workspace
+    if (i + 1 < count) {
+      const size_t used = c.off - mark;
+      c.peak = std::max(c.peak, c.off);
+      c.off = mark;
+      (void)used;
+    }
+  }
+  c.peak = std::max(c.peak, c.off);
+  c.off = c.peak;
+  return RT_OK;
+}
+
+template <typename F>
+int run(F&& plan, void* ws, size_t ws_bytes, void* stream) {
+  Ctx dry{true, true, nullptr, 0, 0, nullptr};
+  int st = plan(dry);
+  if (st) return st;
+  Ctx live{false, true, static_cast<char*>(ws), 0, ws_bytes, static_cast<hipStream_t>(stream)};
+  st = check_ws(dry, ws, ws_bytes);
+  if (st) return st;
+  st = plan(live);
+  if (st) return st;
+  return live.err == hipSuccess ? RT_OK : RT_EHIP;
+}
+
+template <typename F>
+int query(F&& plan, size_t* bytes) {
+  if (!bytes) return RT_EINVAL;
+  Ctx dry{true, false, nullptr, 0, 0, nullptr};
+  const int st = plan(dry);
+  if (st) return st;
+  *bytes = dry.off ? align256(dry.off) : 0;
+  return RT_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char* rtucker_status_string(int status) {
+  switch (status) {
+    case RT_OK: return "ok";
+    case RT_EINVAL: return "invalid argument";
+    case RT_ESHAPE: return "inconsistent or unsupported shape";
+    case RT_EDTYPE: return "unsupported dtype";
+    case RT_EWORKSPACE: return "workspace missing, misaligned or too small";
+    case RT_ENONFINITE: return "non-finite input";
+    case RT_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+const char* rtucker_version(void) { return "rtucker 0.1 (gfx950)"; }
+
+int rtucker_sketch_sizes(int32_t d, const int64_t* dims, const int32_t* r, int32_t p, rt_algo algo, int64_t* s_out) {
+  return sizes_impl(d, dims, r, p, algo, s_out);
+}
+
+int rtucker_sketch_workspace(const rt_tensor* X, const int64_t* s, uint32_t mode_mask, size_t* bytes) {
+  return query([&](Ctx& c) { return plan_sketch(c, X, nullptr, s, mode_mask, nullptr); }, bytes);
+}
+
+int rtucker_sketch(const rt_tensor* X, const double* const* phi, const int64_t* s, uint32_t mode_mask, void* const* Y,
+                   void* ws, size_t ws_bytes, void* stream) {
+  return run([&](Ctx& c) { return plan_sketch(c, X, phi, s, mode_mask, Y); }, ws, ws_bytes, stream);
+}
+
+int rtucker_qr_workspace(int64_t m, int64_t n, size_t* bytes) {
+  return query([&](Ctx& c) { return plan_qr(c, m, n, nullptr, RT_F64, nullptr, nullptr); }, bytes);
+}
+
+int rtucker_qr(int64_t m, int64_t n, const void* Y, rt_dtype y_dtype, double* Q, double* R, void* ws, size_t ws_bytes,
+               void* stream) {
+  return run([&](Ctx& c) { return plan_qr(c, m, n, Y, y_dtype, Q, R); }, ws, ws_bytes, stream);
+}
+
+int rtucker_core_workspace(const rt_tensor* X, const int64_t* l, uint32_t mode_mask, size_t* bytes) {
+  return query([&](Ctx& c) { return plan_core(c, X, nullptr, l, mode_mask, nullptr); }, bytes);
+}
+
+int rtucker_core(const rt_tensor* X, const double* const* U, const int64_t* l, uint32_t mode_mask, void* G, void* ws,
+                 size_t ws_bytes, void* stream) {
+  return run([&](Ctx& c) { return plan_core(c, X, U, l, mode_mask, G); }, ws, ws_bytes, stream);
+}
+
+int rtucker_decompose_workspace(const rt_tensor* X, const rt_tensor* X_sketch, const int32_t* r, int32_t p,
+                                const int64_t* s, rt_algo algo, size_t* bytes) {
+  return query([&](Ctx& c) { return plan_decompose(c, X, X_sketch, r, p, s, algo, nullptr, nullptr, nullptr); },
+               bytes);
+}
+
+int rtucker_decompose(const rt_tensor* X, const rt_tensor* X_sketch, const int32_t* r, int32_t p, const int64_t* s,
+                      rt_algo algo, const double* const* phi, double* G, double* const* U, void* ws, size_t ws_bytes,
+                      void* stream) {
+  return run([&](Ctx& c) { return plan_decompose(c, X, X_sketch, r, p, s, algo, phi, G, U); }, ws, ws_bytes, stream);
+}
+
+int rtucker_rel_error_workspace(const rt_tensor* X, const int32_t* r, size_t* bytes) {
+  return query([&](Ctx& c) { return plan_rel_error(c, X, nullptr, r, nullptr, nullptr); }, bytes);
+}
+
+int rtucker_rel_error(const rt_tensor* X, const double* G, const int32_t* r, const double* const* U, double* out,
+                      void* ws, size_t ws_bytes, void* stream) {
+  return run([&](Ctx& c) { return plan_rel_error(c, X, G, r, U, out); }, ws, ws_bytes, stream);
+}
+
+int rtucker_convert(const void* src, rt_dtype src_dtype, void* dst, rt_dtype dst_dtype, int64_t n, int32_t scale_exp,
+                    void* stream) {
+  if (n < 0) return RT_EINVAL;
+  if (src_dtype != RT_F64 && src_dtype != RT_F32) return RT_EDTYPE;
+  if (dst_dtype != RT_F32 && dst_dtype != RT_BF16 && dst_dtype != RT_F8E4M3) return RT_EDTYPE;
+  if (scale_exp < -1000 || scale_exp > 1000) return RT_EINVAL;
+  if (n == 0) return RT_OK;
+  if (!src || !dst) return RT_EINVAL;
+  return launch_convert(src, src_dtype, dst, dst_dtype, n, scale_exp, static_cast<hipStream_t>(stream)) == hipSuccess
+             ? RT_OK
+             : RT_EHIP;
+}
+
+int rtucker_multi_ttm_workspace(const rt_tensor* X, const int64_t* m, uint32_t mode_mask, size_t* bytes) {
+  return query([&](Ctx& c) { return plan_multi_ttm(c, X, nullptr, m, mode_mask, 1, nullptr); }, bytes);
+}
+
+int rtucker_multi_ttm(const rt_tensor* X, const void* const* A, const int64_t* m, uint32_t mode_mask,
+                      int32_t transpose, void* Y, void* ws, size_t ws_bytes, void* stream) {
+  return run([&](Ctx& c) { return plan_multi_ttm(c, X, A, m, mode_mask, transpose, Y); }, ws, ws_bytes, stream);
+}
+
+int rtucker_mode_contract_workspace(const rt_tensor* P, const rt_tensor* Q, int32_t n, size_t* bytes) {
+  return query([&](Ctx& c) { return plan_mode_contract(c, P, Q, n, nullptr); }, bytes);
+}
+
+int rtucker_mode_contract(const rt_tensor* P, const rt_tensor* Q, int32_t n, void* out, void* ws, size_t ws_bytes,
+                          void* stream) {
+  return run([&](Ctx& c) { return plan_mode_contract(c, P, Q, n, out); }, ws, ws_bytes, stream);
+}
+
+int rtucker_sq_residual(const rt_tensor* A, const void* B, void* R, double* out, void* ws, size_t ws_bytes,
+                        void* stream) {
+  int st = check_tensor(A, true);
+  if (st) return st;
+  if (A->dtype != RT_F32 && A->dtype != RT_F64) return RT_EDTYPE;
+  if (!B || !out) return RT_EINVAL;
+  int64_t n = 1;
+  for (int k = 0; k < A->d; ++k) n *= A->dims[k];
+  const size_t need = sq_residual_ws(n);
+  if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255u)) return RT_EWORKSPACE;
+  return launch_sq_residual(A->data, B, R, A->dtype, n, out, ws, static_cast<hipStream_t>(stream)) == hipSuccess
+             ? RT_OK
+             : RT_EHIP;
+}
+
+int rtucker_decompose_batched_workspace(int32_t count, const rt_batch_item* items, int32_t p, rt_dtype dtype,
+                                        size_t* bytes) {
+  return query([&](Ctx& c) { return plan_batched(c, count, items, p, dtype); }, bytes);
+}
+
+int rtucker_decompose_batched(int32_t count, const rt_batch_item* items, int32_t p, rt_dtype dtype, void* ws,
+                              size_t ws_bytes, void* stream) {
+  return run([&](Ctx& c) { return plan_batched(c, count, items, p, dtype); }, ws, ws_bytes, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,162 @@
+// Elementwise kernels: precision conversion, operand preparation, unfolding,
+// squared residual.  Plain memory-bound grid-stride loops.
+#include "kernels.hpp"
+
+namespace rt {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kReduceBlocks = 1024;  // fixed grid of the deterministic reductions
+
+__device__ __forceinline__ double load_as_f64(const void* p, rt_dtype dt, int64_t i) {
+  switch (dt) {
+    case RT_F64: return static_cast<const double*>(p)[i];
+    case RT_F32: return static_cast<double>(static_cast<const float*>(p)[i]);
+    case RT_BF16: return static_cast<double>(bf16_to_f32(static_cast<const bf16_t*>(p)[i]));
+    default: return static_cast<double>(f8_to_f32(static_cast<const f8_t*>(p)[i]));
+  }
+}
+
+// value of x after rounding to `fmt` (binary64 result, exact)
+__device__ __forceinline__ double round_value(double x, rt_dtype fmt) {
+  switch (fmt) {
+    case RT_F64: return x;
+    case RT_F32: return static_cast<double>(static_cast<float>(x));
+    case RT_BF16: return static_cast<double>(bf16_to_f32(f64_to_bf16_bits(x)));
+    default: return static_cast<double>(f8_to_f32(f64_to_f8_bits(x)));
+  }
+}
+
+__device__ __forceinline__ void store_rounded(void* dst, rt_dtype store, rt_dtype fmt, int64_t i, double x) {
+  switch (store) {
+    case RT_F64: static_cast<double*>(dst)[i] = round_value(x, fmt); break;
+    case RT_F32: static_cast<float*>(dst)[i] = static_cast<float>(round_value(x, fmt)); break;
+    case RT_BF16: static_cast<bf16_t*>(dst)[i] = f64_to_bf16_bits(x); break;
+    default: static_cast<f8_t*>(dst)[i] = f64_to_f8_bits(x); break;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void convert_kernel(const void* src, rt_dtype sdt, void* dst,
+                                                           rt_dtype ddt, int64_t n, double scale) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n; i += stride) {
+    const double x = load_as_f64(src, sdt, i) * scale;  // power-of-two scale: exact
+    store_rounded(dst, ddt, ddt, i, x);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void prep_kernel(const double* src, int64_t m, int64_t K, bool trans,
+                                                        rt_dtype round_to, rt_dtype store, int64_t m_pad,
+                                                        void* dst) {
+  const int64_t total = m_pad * K;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; t < total; t += stride) {
+    const int64_t i = t / K, k = t - i * K;
+    double x = 0.0;
+    if (i < m) x = trans ? src[k * m + i] : src[i * K + k];
+    store_rounded(dst, store, round_to, t, x);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void unfold_kernel(const T* src, int64_t A, int64_t m, int64_t B, T* dst) {
+  const int64_t total = A * m * B;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; t < total; t += stride) {
+    // t indexes the destination (i, a, b)
+    const int64_t i = t / (A * B);
+    const int64_t rem = t - i * (A * B);
+    const int64_t a = rem / B, b = rem - a * B;
+    dst[t] = src[a * m * B + i * B + b];
+  }
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  // fixed-order tree: wave shuffles then waves in order
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < kThreads / kWave; ++i) s += sh[i];
+  }
+  __syncthreads();
+  return s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void sq_residual_kernel(const T* a, const T* b, T* r, int64_t n,
+                                                               double* partial) {
+  __shared__ double sh[kThreads / kWave];
+  double acc = 0.0;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n; i += stride) {
+    const T d = a[i] - b[i];
+    if (r) r[i] = d;
+    acc += static_cast<double>(d) * static_cast<double>(d);
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void sum_partials_kernel(const double* partial, int count, double* out) {
+  __shared__ double sh[kThreads / kWave];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < count; i += kThreads) acc += partial[i];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+int grid_for(int64_t n) {
+  const int64_t g = ceil_div(n, kThreads);
+  return static_cast<int>(g < 1 ? 1 : (g > 8192 ? 8192 : g));
+}
+
+}  // namespace
+
+hipError_t launch_convert(const void* src, rt_dtype sdt, void* dst, rt_dtype ddt, int64_t n, int scale_exp,
+                          hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const double scale = ldexp(1.0, scale_exp);
+  convert_kernel<<<grid_for(n), kThreads, 0, st>>>(src, sdt, dst, ddt, n, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_matrix(const double* src, int64_t m, int64_t K, bool trans, rt_dtype round_to,
+                              rt_dtype store, int64_t m_pad, void* dst, hipStream_t st) {
+  if (m_pad < m) m_pad = m;
+  prep_kernel<<<grid_for(m_pad * K), kThreads, 0, st>>>(src, m, K, trans, round_to, store, m_pad, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_unfold(const void* src, size_t esize, int64_t A, int64_t m, int64_t B, void* dst,
+                         hipStream_t st) {
+  const int64_t n = A * m * B;
+  if (n == 0) return hipSuccess;
+  if (esize == 8)
+    unfold_kernel<double><<<grid_for(n), kThreads, 0, st>>>(static_cast<const double*>(src), A, m, B,
+                                                            static_cast<double*>(dst));
+  else
+    unfold_kernel<float><<<grid_for(n), kThreads, 0, st>>>(static_cast<const float*>(src), A, m, B,
+                                                           static_cast<float*>(dst));
+  return hipGetLastError();
+}
+
+size_t sq_residual_ws(int64_t) { return align256(kReduceBlocks * sizeof(double)); }
+
+hipError_t launch_sq_residual(const void* a, const void* b, void* r, rt_dtype dt, int64_t n, double* out,
+                              void* ws, hipStream_t st) {
+  double* partial = static_cast<double*>(ws);
+  if (dt == RT_F64)
+    sq_residual_kernel<double><<<kReduceBlocks, kThreads, 0, st>>>(
+        static_cast<const double*>(a), static_cast<const double*>(b), static_cast<double*>(r), n, partial);
+  else
+    sq_residual_kernel<float><<<kReduceBlocks, kThreads, 0, st>>>(
+        static_cast<const float*>(a), static_cast<const float*>(b), static_cast<float*>(r), n, partial);
+  sum_partials_kernel<<<1, kThreads, 0, st>>>(partial, kReduceBlocks, out);
+  return hipGetLastError();
+}
+
+}  // namespace rt

@@ -1,0 +1,349 @@
+// Thin QR of tall-skinny sketches in binary64 (the range finder's QR step,
+// Alg. 2.3), Householder reflections with diag(R) >= 0.
+//
+// Design: a block of up to 256 rows x 64 columns lives in LDS (128 KiB of the
+// 160 KiB a gfx950 CU has) and one 256-thread workgroup factors it with
+// Householder reflections (two barriers per reflection) and then forms its
+// explicit Q in place (backward accumulation).  Taller matrices use a TSQR
+// tree: independent 256-row blocks, their stacked R factors factored again,
+// and Q = blockdiag(Q_b) * Q_top, so several CUs share the work.
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace rt {
+
+namespace {
+
+constexpr int kRowsMax = 256;
+constexpr int kCols = kMaxQRCols;  // 64
+constexpr int kQRThreads = 256;
+constexpr int kMaxTasks = 24;
+
+struct QRTask {
+  const void* src;   // (A, m, B) view, element (i, j=a*B+b) at a*m*B + i*B + b
+  int64_t A, m, B;
+  int64_t row0;      // first row of the block
+  int32_t rows;      // rows in the block (<= 256)
+  int32_t n;         // columns (= A*B <= 64)
+  double* Q;         // rows x qcols, leading dimension ldq
+  int32_t ldq, qcols;
+  double* R;         // rrows x n (leading dimension n), or null
+  int32_t rrows;
+  int32_t f64;       // source dtype (host-side grouping only)
+};
+
+struct QRTaskTable {
+  QRTask t[kMaxTasks];
+};
+
+template <typename TY>
+__global__ __launch_bounds__(kQRThreads) void small_qr_kernel(QRTaskTable tab) {
+  __shared__ double Y[kRowsMax * kCols];
+  __shared__ double sh_nrm[4];
+  __shared__ double sh_dot[4][kCols];
+  __shared__ double sh_vk[kCols];
+  __shared__ double sh_beta[kCols];
+  __shared__ double sh_sgn[kCols];
+
+  const QRTask& T = tab.t[blockIdx.x];
+  const int lane = threadIdx.x % kWave;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int rows = T.rows, n = T.n;
+  const int c = rows < n ? rows : n;
+  const TY* src = static_cast<const TY*>(T.src);
+
+  // load (zero padded), coalesced along the source's contiguous index
+  for (int idx = threadIdx.x; idx < kRowsMax * kCols; idx += kQRThreads) {
+    const int r = idx / kCols, j = idx % kCols;
+    double v = 0.0;
+    if (r < rows && j < n) {
+      const int64_t a = j / T.B, b = j - a * T.B;
+      v = static_cast<double>(src[a * T.m * T.B + (T.row0 + r) * T.B + b]);
+    }
+    Y[r * kCols + j] = v;
+  }
+  __syncthreads();
+  const int r_lo = w * 64, r_hi = (w * 64 + 64 < rows) ? w * 64 + 64 : rows;
+  // norm partials of column 0
+  if (lane == 0) {
+    double s = 0.0;
+    for (int r = r_lo; r < r_hi; ++r) s += Y[r * kCols] * Y[r * kCols];
+    sh_nrm[w] = s;
+  }
+  __syncthreads();
+
+  // ---------------- factorization
+  for (int k = 0; k < c; ++k) {
+    const double sigma = sh_nrm[0] + sh_nrm[1] + sh_nrm[2] + sh_nrm[3];
+    const double xkk = Y[k * kCols + k];
+    double alpha = 0.0, vk = 0.0, beta = 0.0;
+    if (sigma > 0.0) {
+      alpha = -copysign(sqrt(sigma), xkk);
+      vk = xkk - alpha;
+      beta = 1.0 / (sigma - alpha * xkk);
+    }
+    const int j = lane;
+    const int rs = (k > r_lo) ? k : r_lo;
+    // dot products w_j = v^T Y[:, j] over this wave's rows
+    if (beta != 0.0 && j > k && j < n) {
+      double p = 0.0;
+      for (int r = rs; r < r_hi; ++r) {
+        const double v = (r == k) ? vk : Y[r * kCols + k];
+        p = fma(v, Y[r * kCols + j], p);
+      }
+      sh_dot[w][j] = p;
+    }
+    __syncthreads();
+    if (beta != 0.0 && j > k && j < n) {
+      const double wj = beta * (sh_dot[0][j] + sh_dot[1][j] + sh_dot[2][j] + sh_dot[3][j]);
+      double s = 0.0;
+      for (int r = rs; r < r_hi; ++r) {
+        const double v = (r == k) ? vk : Y[r * kCols + k];
+        const double y = fma(-wj, v, Y[r * kCols + j]);
+        Y[r * kCols + j] = y;
+        if (j == k + 1 && r >= k + 1) s = fma(y, y, s);
+      }
+      if (j == k + 1) sh_nrm[w] = s;
+    } else if (j == k + 1 && j < n) {
+      double s = 0.0;
+      const int rs1 = (k + 1 > r_lo) ? k + 1 : r_lo;
+      for (int r = rs1; r < r_hi; ++r) s = fma(Y[r * kCols + j], Y[r * kCols + j], s);
+      sh_nrm[w] = s;
+    }
+    if (threadIdx.x == 0) {
+      sh_vk[k] = vk;
+      sh_beta[k] = beta;
+      sh_sgn[k] = (alpha < 0.0) ? -1.0 : 1.0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) Y[k * kCols + k] = alpha;  // R_kk; v_k kept in sh_vk
+    __syncthreads();
+  }
+
+  // ---------------- write R (sign-normalised rows), then clear it from Y
+  if (T.R) {
+    for (int idx = threadIdx.x; idx < T.rrows * n; idx += kQRThreads) {
+      const int i = idx / n, jj = idx % n;
+      double v = 0.0;
+      if (i < c && jj >= i) v = sh_sgn[i] * Y[i * kCols + jj];
+      T.R[static_cast<int64_t>(i) * n + jj] = v;
+    }
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < kRowsMax * kCols; idx += kQRThreads) {
+    const int r = idx / kCols, jj = idx % kCols;
+    if (jj >= c || r <= jj) {
+      if (!(jj < c && r == jj)) Y[idx] = 0.0;  // diagonal rewritten below
+    }
+  }
+  __syncthreads();
+
+  // ---------------- explicit Q in place: Q = H_0 ... H_{c-1} [I; 0]
+  for (int k = c - 1; k >= 0; --k) {
+    const double vk = sh_vk[k], beta = sh_beta[k];
+    const int j = lane;
+    const int rs = (k + 1 > r_lo) ? k + 1 : r_lo;
+    if (j > k && j < c) {
+      double p = 0.0;
+      for (int r = rs; r < r_hi; ++r) p = fma(Y[r * kCols + k], Y[r * kCols + j], p);
+      sh_dot[w][j] = p;
+    }
+    __syncthreads();
+    if (j > k && j < c) {
+      const double wj = beta * (sh_dot[0][j] + sh_dot[1][j] + sh_dot[2][j] + sh_dot[3][j]);
+      for (int r = rs; r < r_hi; ++r) Y[r * kCols + j] = fma(-wj, Y[r * kCols + k], Y[r * kCols + j]);
+      if (k >= r_lo && k < r_hi) Y[k * kCols + j] = -wj * vk;
+    }
+    __syncthreads();
+    // column k = H_k e_k
+    if (j == k) {
+      for (int r = (k + 1 > r_lo ? k + 1 : r_lo); r < r_hi; ++r) Y[r * kCols + k] = -beta * vk * Y[r * kCols + k];
+      if (k >= r_lo && k < r_hi) Y[k * kCols + k] = 1.0 - beta * vk * vk;
+    }
+    __syncthreads();
+  }
+
+  // ---------------- write Q (sign-normalised columns, zero beyond c)
+  for (int idx = threadIdx.x; idx < rows * T.qcols; idx += kQRThreads) {
+    const int r = idx / T.qcols, jj = idx % T.qcols;
+    const double v = (jj < c) ? sh_sgn[jj] * Y[r * kCols + jj] : 0.0;
+    T.Q[static_cast<int64_t>(r) * T.ldq + jj] = v;
+  }
+}
+
+struct CombineTask {
+  const double* Qb;  // rows x n (ld n)
+  const double* Q2;  // n x n block (ld n)
+  double* Q;         // rows x n (leading dimension ldq)
+  int32_t rows, n, ldq;
+};
+struct CombineTable {
+  CombineTask t[kMaxTasks];
+};
+
+// Q[r][j] = sum_t Qb[r][t] Q2[t][j]
+__global__ __launch_bounds__(256) void qr_combine_kernel(CombineTable tab) {
+  const CombineTask& T = tab.t[blockIdx.y];
+  const int64_t total = static_cast<int64_t>(T.rows) * T.n;
+  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; idx < total;
+       idx += static_cast<int64_t>(gridDim.x) * 256) {
+    const int r = static_cast<int>(idx / T.n), jj = static_cast<int>(idx % T.n);
+    double s = 0.0;
+    for (int t = 0; t < T.n; ++t) s = fma(T.Qb[static_cast<int64_t>(r) * T.n + t], T.Q2[static_cast<int64_t>(t) * T.n + jj], s);
+    T.Q[static_cast<int64_t>(r) * T.ldq + jj] = s;
+  }
+}
+
+// One matrix of the (recursive) TSQR plan.
+struct Mat {
+  const void* src;
+  bool f64;
+  int64_t A, m, B;
+  int n;
+  double* Q;  // m x qcols (ld ldq)
+  int ldq, qcols;
+  double* R;  // rrows x n or null
+  int rrows;
+};
+
+struct Bump {
+  char* base;
+  size_t off;
+  void* take(size_t bytes) {
+    const size_t o = align256(off);
+    off = o + align256(bytes);
+    return base ? base + o : nullptr;
+  }
+};
+
+// Plans (and, when launch is true, enqueues) the QR of a set of matrices.
+hipError_t qr_level(std::vector<Mat>& mats, bool launch, Bump& ws, hipStream_t st) {
+  std::vector<QRTask> direct;
+  std::vector<Mat> upper;               // stacked-R matrices of the next level
+  std::vector<CombineTask> combine;     // filled after the upper level is planned
+  struct Pending { Mat mat; double* Qb; double* Rs; int nb; };
+  std::vector<Pending> pend;
+  for (const Mat& M : mats) {
+    if (M.m <= kRowsMax) {
+      QRTask t;
+      t.src = M.src; t.A = M.A; t.m = M.m; t.B = M.B; t.row0 = 0; t.rows = static_cast<int32_t>(M.m);
+      t.n = M.n; t.Q = M.Q; t.ldq = M.ldq; t.qcols = M.qcols; t.R = M.R; t.rrows = M.rrows;
+      t.f64 = M.f64 ? 1 : 0;
+      direct.push_back(t);
+    } else {
+      const int nb = static_cast<int>(ceil_div(M.m, kRowsMax));
+      Pending p;
+      p.mat = M;
+      p.nb = nb;
+      p.Qb = static_cast<double*>(ws.take(static_cast<size_t>(M.m) * M.n * sizeof(double)));
+      p.Rs = static_cast<double*>(ws.take(static_cast<size_t>(nb) * M.n * M.n * sizeof(double)));
+      for (int b = 0; b < nb; ++b) {
+        QRTask t;
+        t.src = M.src; t.A = M.A; t.m = M.m; t.B = M.B; t.row0 = static_cast<int64_t>(b) * kRowsMax;
+        const int64_t left = M.m - t.row0;
+        t.rows = static_cast<int32_t>(left < kRowsMax ? left : kRowsMax);
+        t.n = M.n;
+        t.Q = p.Qb ? p.Qb + t.row0 * M.n : nullptr;
+        t.ldq = M.n; t.qcols = M.n;
+        t.R = p.Rs ? p.Rs + static_cast<int64_t>(b) * M.n * M.n : nullptr;
+        t.rrows = M.n;
+        t.f64 = M.f64 ? 1 : 0;
+        direct.push_back(t);
+      }
+      pend.push_back(p);
+    }
+  }
+  // launch this level's block factorizations (grouped by input dtype)
+  if (launch) {
+    for (int pass = 0; pass < 2; ++pass) {
+      std::vector<QRTask> sel;
+      for (size_t i = 0; i < direct.size(); ++i)
+        if ((pass == 1) == (direct[i].f64 != 0)) sel.push_back(direct[i]);
+      for (size_t i0 = 0; i0 < sel.size(); i0 += kMaxTasks) {
+        QRTaskTable tab;
+        const size_t cnt = (sel.size() - i0 < static_cast<size_t>(kMaxTasks)) ? sel.size() - i0 : kMaxTasks;
+        for (size_t i = 0; i < cnt; ++i) tab.t[i] = sel[i0 + i];
+        if (pass == 1)
+          small_qr_kernel<double><<<static_cast<unsigned>(cnt), kQRThreads, 0, st>>>(tab);
+        else
+          small_qr_kernel<float><<<static_cast<unsigned>(cnt), kQRThreads, 0, st>>>(tab);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+      }
+    }
+  }
+  if (pend.empty()) return hipSuccess;
+  // next level: QR of the stacked R factors, then Q = blockdiag(Qb) * Q2
+  std::vector<double*> q2(pend.size());
+  for (size_t i = 0; i < pend.size(); ++i) {
+    const Pending& p = pend[i];
+    Mat U;
+    U.src = p.Rs; U.f64 = true; U.A = 1; U.m = static_cast<int64_t>(p.nb) * p.mat.n; U.B = p.mat.n;
+    U.n = p.mat.n;
+    q2[i] = static_cast<double*>(ws.take(static_cast<size_t>(U.m) * U.n * sizeof(double)));
+    U.Q = q2[i]; U.ldq = U.n; U.qcols = U.n;
+    U.R = p.mat.R; U.rrows = p.mat.rrows;
+    upper.push_back(U);
+  }
+  hipError_t e = qr_level(upper, launch, ws, st);
+  if (e != hipSuccess) return e;
+  for (size_t i = 0; i < pend.size(); ++i) {
+    const Pending& p = pend[i];
+    for (int b = 0; b < p.nb; ++b) {
+      CombineTask t;
+      const int64_t row0 = static_cast<int64_t>(b) * kRowsMax;
+      const int64_t left = p.mat.m - row0;
+      t.rows = static_cast<int32_t>(left < kRowsMax ? left : kRowsMax);
+      t.n = p.mat.n;
+      t.Qb = p.Qb ? p.Qb + row0 * p.mat.n : nullptr;
+      t.Q2 = q2[i] ? q2[i] + static_cast<int64_t>(b) * p.mat.n * p.mat.n : nullptr;
+      t.Q = p.mat.Q ? p.mat.Q + row0 * p.mat.ldq : nullptr;
+      t.ldq = p.mat.ldq;
+      combine.push_back(t);
+    }
+  }
+  if (launch) {
+    for (size_t i0 = 0; i0 < combine.size(); i0 += kMaxTasks) {
+      CombineTable tab;
+      const size_t cnt = (combine.size() - i0 < static_cast<size_t>(kMaxTasks)) ? combine.size() - i0 : kMaxTasks;
+      for (size_t i = 0; i < cnt; ++i) tab.t[i] = combine[i0 + i];
+      qr_combine_kernel<<<dim3(64, static_cast<unsigned>(cnt)), 256, 0, st>>>(tab);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+std::vector<Mat> mats_of(const QRJob* jobs, int count, rt_dtype ydt) {
+  std::vector<Mat> v;
+  for (int i = 0; i < count; ++i) {
+    Mat M;
+    M.src = jobs[i].Y; M.f64 = (ydt == RT_F64);
+    M.A = jobs[i].A; M.m = jobs[i].m; M.B = jobs[i].B;
+    M.n = static_cast<int>(jobs[i].A * jobs[i].B);
+    const int c = static_cast<int>(M.m < M.n ? M.m : M.n);
+    M.Q = jobs[i].Q; M.ldq = c; M.qcols = c;
+    M.R = jobs[i].R; M.rrows = c;
+    v.push_back(M);
+  }
+  return v;
+}
+
+}  // namespace
+
+size_t qr_ws(const QRJob* jobs, int count) {
+  std::vector<Mat> mats = mats_of(jobs, count, RT_F32);
+  Bump b{nullptr, 0};
+  (void)qr_level(mats, false, b, nullptr);
+  return align256(b.off);
+}
+
+hipError_t launch_qr(const QRJob* jobs, int count, rt_dtype ydt, void* ws, hipStream_t st) {
+  std::vector<Mat> mats = mats_of(jobs, count, ydt);
+  Bump b{static_cast<char*>(ws), 0};
+  return qr_level(mats, true, b, st);
+}
+
+}  // namespace rt

@@ -1,0 +1,254 @@
+// First level of the all-at-once sketch (Alg. 3.4 sketch step with the
+// dimension tree of Sec. 3.4): one streaming pass over X, viewed as (A, P, Q)
+// with P, Q the sizes of the last two modes, computes both
+//   Z = X x_d Phi_d        (the node shared by every sketch that contracts mode d)
+//   W = X x_{d-1} Phi_{d-1} (the node of the mode-d sketch)
+// so X is read from HBM exactly once for all modes; every later contraction of
+// the tree runs on Z or W, which are smaller by I_d/s_d and I_{d-1}/s_{d-1}.
+//
+// Layout: a 256-thread workgroup owns one slab X[a] (or a row range of it) and a
+// range of up to 64*NQ columns.  Lane l holds columns q0 + l + 64*j (coalesced
+// row reads), the matching Phi_Q entries in registers, and W accumulators for
+// its columns; each row's Z values are reduced across the wave.  Phi_P[:, p]
+// is wave-uniform (scalar loads).  Row ranges or column ranges split over
+// several workgroups produce partial sums that a second kernel adds in a fixed
+// order.
+#include "kernels.hpp"
+
+namespace rt {
+
+namespace {
+
+constexpr int kZWThreads = 256;
+constexpr int kZWWaves = kZWThreads / kWave;
+
+template <typename TX, typename TC, int NQ, int SMAX>
+__global__ __launch_bounds__(kZWThreads) void sketch_zw_kernel(const TX* __restrict__ X, int64_t A, int64_t P,
+                                                               int64_t Q, const TC* __restrict__ phiP, int sP,
+                                                               const TC* __restrict__ phiQ, int sQ,
+                                                               int64_t rows_per_block, int qblocks, int pblocks,
+                                                               TC* __restrict__ Zo, TC* __restrict__ Wo) {
+  extern __shared__ unsigned char zw_smem[];
+  TC* sW = reinterpret_cast<TC*>(zw_smem);  // [waves][sP][64*NQ]
+  const int lane = threadIdx.x % kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int64_t blk = blockIdx.x;
+  const int qblk = static_cast<int>(blk % qblocks);
+  const int64_t rest = blk / qblocks;
+  const int pblk = static_cast<int>(rest % pblocks);
+  const int64_t a = rest / pblocks;
+  const int64_t q0 = static_cast<int64_t>(qblk) * 64 * NQ;
+  const bool needZ = Zo != nullptr, needW = Wo != nullptr;
+
+  TC phq[NQ][SMAX];
+  TC wacc[NQ][SMAX];
+#pragma unroll
+  for (int j = 0; j < NQ; ++j) {
+    const int64_t q = q0 + lane + 64 * j;
+#pragma unroll
+    for (int c = 0; c < SMAX; ++c) {
+      phq[j][c] = (needZ && q < Q && c < sQ) ? phiQ[c * Q + q] : TC(0);
+      wacc[j][c] = TC(0);
+    }
+  }
+  const int64_t pbeg = static_cast<int64_t>(pblk) * rows_per_block;
+  const int64_t pend = (pbeg + rows_per_block < P) ? pbeg + rows_per_block : P;
+  const TX* xa = X + a * P * Q;
+  TC* zrow = needZ ? Zo + (static_cast<int64_t>(qblk) * A + a) * P * sQ : nullptr;
+  for (int64_t p = pbeg + wave; p < pend; p += kZWWaves) {
+    TC x[NQ];
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) {
+      const int64_t q = q0 + lane + 64 * j;
+      x[j] = (q < Q) ? static_cast<TC>(Load<TX>::get(xa, p * Q + q)) : TC(0);
+    }
+    if (needW) {
+#pragma unroll
+      for (int c = 0; c < SMAX; ++c) {
+        const TC f = (c < sP) ? phiP[c * P + p] : TC(0);
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) wacc[j][c] = fma(f, x[j], wacc[j][c]);
+      }
+    }
+    if (needZ) {
+      TC z[SMAX];
+#pragma unroll
+      for (int c = 0; c < SMAX; ++c) {
+        TC s = TC(0);
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) s = fma(x[j], phq[j][c], s);
+        z[c] = s;
+      }
+#pragma unroll
+      for (int c = 0; c < SMAX; ++c)
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) z[c] += __shfl_xor(z[c], off);
+      // lane c stores z[c]
+      TC mine = TC(0);
+#pragma unroll
+      for (int c = 0; c < SMAX; ++c)
+        if (lane == c) mine = z[c];
+      if (lane < sQ) zrow[p * sQ + lane] = mine;
+    }
+  }
+  if (!needW) return;
+  const int width = 64 * NQ;
+#pragma unroll
+  for (int j = 0; j < NQ; ++j)
+#pragma unroll
+    for (int c = 0; c < SMAX; ++c)
+      if (c < sP) sW[(wave * sP + c) * width + lane + 64 * j] = wacc[j][c];
+  __syncthreads();
+  TC* wout = Wo + (static_cast<int64_t>(pblk) * A + a) * sP * Q;
+  for (int idx = threadIdx.x; idx < sP * width; idx += kZWThreads) {
+    const int c = idx / width, col = idx % width;
+    const int64_t q = q0 + col;
+    if (q >= Q) continue;
+    TC s = TC(0);
+    for (int w = 0; w < kZWWaves; ++w) s += sW[(w * sP + c) * width + col];
+    wout[c * Q + q] = s;
+  }
+}
+
+template <typename TC>
+__global__ __launch_bounds__(256) void sum_parts_kernel(const TC* __restrict__ part, int parts, int64_t n,
+                                                        TC* __restrict__ out) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * 256;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n; i += stride) {
+    TC s = part[i];
+    for (int k = 1; k < parts; ++k) s += part[k * n + i];
+    out[i] = s;
+  }
+}
+
+int nq_max(rt_dtype xdt) { return xdt == RT_F64 ? 4 : 8; }
+
+int pick_nq(rt_dtype xdt, int64_t Q) {
+  const int64_t need = ceil_div(Q, 64);
+  const int mx = nq_max(xdt);
+  int nq = 1;
+  while (nq < need && nq < mx) nq *= 2;
+  return nq;
+}
+
+template <typename TX, typename TC>
+hipError_t zw_dispatch(const TX* X, int64_t A, int64_t P, int64_t Q, const TC* phiP, int sP, const TC* phiQ, int sQ,
+                       TC* Zo, TC* Wo, const ZWPlan& plan, int nq, hipStream_t st) {
+  const int smax = (sP > sQ ? sP : sQ) <= 4 ? 4 : 8;
+  const int64_t blocks = A * plan.pblocks * plan.qblocks;
+  const size_t shmem = Wo ? static_cast<size_t>(kZWWaves) * sP * 64 * nq * sizeof(TC) : 0;
+#define RT_ZW(NQV, SV)                                                                                        \
+  sketch_zw_kernel<TX, TC, NQV, SV><<<static_cast<unsigned>(blocks), kZWThreads, shmem, st>>>(               \
+      X, A, P, Q, phiP, sP, phiQ, sQ, plan.rows_per_block, static_cast<int>(plan.qblocks),                      \
+      static_cast<int>(plan.pblocks), Zo, Wo)
+  if (smax == 4) {
+    switch (nq) {
+      case 1: RT_ZW(1, 4); break;
+      case 2: RT_ZW(2, 4); break;
+      case 4: RT_ZW(4, 4); break;
+      default: RT_ZW(8, 4); break;
+    }
+  } else {
+    switch (nq) {
+      case 1: RT_ZW(1, 8); break;
+      case 2: RT_ZW(2, 8); break;
+      case 4: RT_ZW(4, 8); break;
+      default: RT_ZW(8, 8); break;
+    }
+  }
+#undef RT_ZW
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool sketch_zw_ok(rt_dtype, int64_t sP, int64_t sQ) { return sP >= 1 && sQ >= 1 && sP <= 8 && sQ <= 8; }
+
+ZWPlan sketch_zw_plan(rt_dtype xdt, int64_t A, int64_t P, int64_t Q, int64_t sP, int64_t sQ, bool needZ,
+                      bool needW) {
+  ZWPlan p;
+  const int nq = pick_nq(xdt, Q);
+  p.qblocks = ceil_div(Q, 64 * nq);
+  if (!needZ) p.qblocks = ceil_div(Q, 64 * nq);
+  int64_t pb = 1;
+  const int64_t target = 2048;
+  if (A * p.qblocks < target) pb = ceil_div(target, A * p.qblocks);
+  const int64_t maxpb = ceil_div(P, 16);  // keep at least 16 rows per block
+  if (pb > maxpb) pb = maxpb;
+  if (pb < 1) pb = 1;
+  p.rows_per_block = ceil_div(P, pb);
+  p.pblocks = ceil_div(P, p.rows_per_block);
+  const size_t esz = (xdt == RT_F64) ? 8 : 4;
+  size_t ws = 0;
+  if (needZ && p.qblocks > 1) ws += align256(static_cast<size_t>(p.qblocks) * A * P * sQ * esz);
+  if (needW && p.pblocks > 1) ws += align256(static_cast<size_t>(p.pblocks) * A * sP * Q * esz);
+  p.ws_bytes = ws;
+  return p;
+}
+
+hipError_t launch_sketch_zw(const void* X, rt_dtype xdt, int64_t A, int64_t P, int64_t Q, const void* phiP, int64_t sP,
+                            const void* phiQ, int64_t sQ, void* Z, void* W, const ZWPlan& plan, void* ws,
+                            hipStream_t st) {
+  const int nq = pick_nq(xdt, Q);
+  const size_t esz = (xdt == RT_F64) ? 8 : 4;
+  char* wsp = static_cast<char*>(ws);
+  void* zdst = Z;
+  void* wdst = W;
+  if (Z && plan.qblocks > 1) {
+    zdst = wsp;
+    wsp += align256(static_cast<size_t>(plan.qblocks) * A * P * sQ * esz);
+  }
+  if (W && plan.pblocks > 1) {
+    wdst = wsp;
+    wsp += align256(static_cast<size_t>(plan.pblocks) * A * sP * Q * esz);
+  }
+  hipError_t e;
+  const int isP = static_cast<int>(sP), isQ = static_cast<int>(sQ);
+  switch (xdt) {
+    case RT_F64:
+      e = zw_dispatch<double, double>(static_cast<const double*>(X), A, P, Q, static_cast<const double*>(phiP), isP,
+                                      static_cast<const double*>(phiQ), isQ, static_cast<double*>(zdst),
+                                      static_cast<double*>(wdst), plan, nq, st);
+      break;
+    case RT_F32:
+      e = zw_dispatch<float, float>(static_cast<const float*>(X), A, P, Q, static_cast<const float*>(phiP), isP,
+                                    static_cast<const float*>(phiQ), isQ, static_cast<float*>(zdst),
+                                    static_cast<float*>(wdst), plan, nq, st);
+      break;
+    case RT_BF16:
+      e = zw_dispatch<bf16_t, float>(static_cast<const bf16_t*>(X), A, P, Q, static_cast<const float*>(phiP), isP,
+                                     static_cast<const float*>(phiQ), isQ, static_cast<float*>(zdst),
+                                     static_cast<float*>(wdst), plan, nq, st);
+      break;
+    default:
+      e = zw_dispatch<f8_t, float>(static_cast<const f8_t*>(X), A, P, Q, static_cast<const float*>(phiP), isP,
+                                   static_cast<const float*>(phiQ), isQ, static_cast<float*>(zdst),
+                                   static_cast<float*>(wdst), plan, nq, st);
+      break;
+  }
+  if (e != hipSuccess) return e;
+  // fixed-order sums of the partials
+  if (Z && plan.qblocks > 1) {
+    const int64_t n = A * P * sQ;
+    const unsigned g = static_cast<unsigned>(ceil_div(n, 256) > 4096 ? 4096 : ceil_div(n, 256));
+    if (xdt == RT_F64)
+      sum_parts_kernel<double><<<g, 256, 0, st>>>(static_cast<const double*>(zdst), static_cast<int>(plan.qblocks), n,
+                                                  static_cast<double*>(Z));
+    else
+      sum_parts_kernel<float><<<g, 256, 0, st>>>(static_cast<const float*>(zdst), static_cast<int>(plan.qblocks), n,
+                                                 static_cast<float*>(Z));
+  }
+  if (W && plan.pblocks > 1) {
+    const int64_t n = A * sP * Q;
+    const unsigned g = static_cast<unsigned>(ceil_div(n, 256) > 4096 ? 4096 : ceil_div(n, 256));
+    if (xdt == RT_F64)
+      sum_parts_kernel<double><<<g, 256, 0, st>>>(static_cast<const double*>(wdst), static_cast<int>(plan.pblocks), n,
+                                                  static_cast<double*>(W));
+    else
+      sum_parts_kernel<float><<<g, 256, 0, st>>>(static_cast<const float*>(wdst), static_cast<int>(plan.pblocks), n,
+                                                 static_cast<float*>(W));
+  }
+  return hipGetLastError();
+}
+
+}  // namespace rt

@@ -1,0 +1,344 @@
+// Mode-k tensor-times-matrix on the (A, K, B) view of a C-order tensor:
+//   Y[a, i, b] = sum_k M[i, k] X[a, k, b]
+// (Sec. 2.1: the mode-k unfolding of X x_k M is M times the unfolding of X).
+// No unfolding is materialised: for each a, X[a] is a row-major K x B matrix,
+// so the contraction is a strided-batched GEMM whose HBM reads are whole rows.
+//
+//  * ttm_generic: VALU kernel for every dtype and shape (one output column per
+//    thread, m split into register tiles, M chunks broadcast from LDS).
+//  * ttm_mfma:   matrix-core kernel for binary32 / bfloat16 X and B % 4 == 0
+//    (binary32) or B % 8 == 0 (bfloat16), m <= 64.  Each wave owns a 64 x 128
+//    output tile (m padded to a multiple of 16) and streams X rows once; the
+//    prepared M operand is read from L2.  bfloat16 operands are re-packed in
+//    registers so that each lane holds 8 consecutive k of one column.
+#include "kernels.hpp"
+
+namespace rt {
+
+namespace {
+
+// ------------------------------------------------------------------ generic VALU
+constexpr int kGenThreads = 256;
+constexpr int kGenKC = 64;
+
+template <typename TX, typename TC, int MT>
+__global__ __launch_bounds__(kGenThreads) void ttm_generic_kernel(const TX* __restrict__ X, int64_t A, int64_t K,
+                                                                  int64_t B, const TC* __restrict__ M, int64_t m,
+                                                                  TC* __restrict__ Y) {
+  __shared__ TC sM[MT][kGenKC];
+  const int64_t col = static_cast<int64_t>(blockIdx.x) * kGenThreads + threadIdx.x;
+  const int64_t i0 = static_cast<int64_t>(blockIdx.y) * MT;
+  const bool active = col < A * B;
+  const int64_t a = active ? col / B : 0;
+  const int64_t b = active ? col - a * B : 0;
+  TC acc[MT];
+#pragma unroll
+  for (int ii = 0; ii < MT; ++ii) acc[ii] = TC(0);
+  const TX* xp = X + a * K * B + b;
+  for (int64_t k0 = 0; k0 < K; k0 += kGenKC) {
+    __syncthreads();
+    for (int t = threadIdx.x; t < MT * kGenKC; t += kGenThreads) {
+      const int ii = t / kGenKC, kk = t % kGenKC;
+      sM[ii][kk] = (i0 + ii < m && k0 + kk < K) ? M[(i0 + ii) * K + k0 + kk] : TC(0);
+    }
+    __syncthreads();
+    if (active) {
+      const int kend = static_cast<int>((K - k0) < kGenKC ? (K - k0) : kGenKC);
+      for (int kk = 0; kk < kend; ++kk) {
+        const TC x = static_cast<TC>(Load<TX>::get(xp, (k0 + kk) * B));
+#pragma unroll
+        for (int ii = 0; ii < MT; ++ii) acc[ii] = fma(sM[ii][kk], x, acc[ii]);
+      }
+    }
+  }
+  if (active) {
+#pragma unroll
+    for (int ii = 0; ii < MT; ++ii)
+      if (i0 + ii < m) Y[a * m * B + (i0 + ii) * B + b] = acc[ii];
+  }
+}
+
+template <typename TX, typename TC>
+hipError_t generic_dispatch(const TX* X, int64_t A, int64_t K, int64_t B, const TC* M, int64_t m, TC* Y,
+                            hipStream_t st) {
+  const int64_t cols = A * B;
+  const unsigned gx = static_cast<unsigned>(ceil_div(cols, kGenThreads));
+  if (m <= 4) {
+    ttm_generic_kernel<TX, TC, 4><<<dim3(gx, 1), kGenThreads, 0, st>>>(X, A, K, B, M, m, Y);
+  } else if (m <= 8) {
+    ttm_generic_kernel<TX, TC, 8><<<dim3(gx, 1), kGenThreads, 0, st>>>(X, A, K, B, M, m, Y);
+  } else {
+    const unsigned gy = static_cast<unsigned>(ceil_div(m, 16));
+    ttm_generic_kernel<TX, TC, 16><<<dim3(gx, gy), kGenThreads, 0, st>>>(X, A, K, B, M, m, Y);
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ MFMA
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMfmaThreads = 256;  // 4 waves, one 128-column unit each
+constexpr int kUnitCols = 128;
+
+// Work unit = (a, 128-column chunk, k-split part).  Y (or a split-K partial) is
+// written for rows i < m only.
+template <int MT>
+__global__ __launch_bounds__(kMfmaThreads) void ttm_mfma_f32_kernel(const float* __restrict__ X, int64_t A, int64_t K,
+                                                                    int64_t B, const float* __restrict__ Mop,
+                                                                    int64_t m, int64_t chunks, int ksplit,
+                                                                    int64_t kper, float* __restrict__ Y) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t unit = static_cast<int64_t>(blockIdx.x) * (kMfmaThreads / kWave) + threadIdx.x / kWave;
+  const int64_t total = A * chunks * ksplit;
+  if (unit >= total) return;
+  const int ks = static_cast<int>(unit % ksplit);
+  const int64_t ac = unit / ksplit;
+  const int64_t a = ac / chunks;
+  const int64_t b0 = (ac - a * chunks) * kUnitCols;
+  const int j = lane % 16, q = lane / 16;
+  const int64_t kbeg = ks * kper;
+  const int64_t kend = (kbeg + kper < K) ? kbeg + kper : K;
+
+  f32x4 acc[MT][2][4];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[mt][g][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const float* xa = X + a * K * B;
+  const bool colok0 = (b0 + 4 * j) < B;
+  const bool colok1 = (b0 + 64 + 4 * j) < B;
+  const int64_t Mpad = MT * 16;
+  for (int64_t k0 = kbeg; k0 < kend; k0 += 4) {
+    const int64_t k = k0 + q;
+    f32x4 x0 = f32x4{0.f, 0.f, 0.f, 0.f}, x1 = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (k < kend) {
+      const float* row = xa + k * B + b0 + 4 * j;
+      if (colok0) x0 = *reinterpret_cast<const f32x4*>(row);
+      if (colok1) x1 = *reinterpret_cast<const f32x4*>(row + 64);
+    }
+    float mv[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) mv[mt] = (k < kend) ? Mop[(mt * 16 + j) * K + k] : 0.f;
+    (void)Mpad;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        acc[mt][0][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(mv[mt], x0[t], acc[mt][0][t], 0, 0, 0);
+        acc[mt][1][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(mv[mt], x1[t], acc[mt][1][t], 0, 0, 0);
+      }
+    }
+  }
+  float* ya = Y + (static_cast<int64_t>(ks) * A + a) * m * B;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t i = mt * 16 + 4 * q + v;
+      if (i >= m) continue;
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        const int64_t c = b0 + 64 * g + 4 * j;
+        if (c < B) {
+          f32x4 o = f32x4{acc[mt][g][0][v], acc[mt][g][1][v], acc[mt][g][2][v], acc[mt][g][3][v]};
+          *reinterpret_cast<f32x4*>(ya + i * B + c) = o;
+        }
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t pack_lo(uint32_t a, uint32_t b) { return (a & 0xffffu) | (b << 16); }
+__device__ __forceinline__ uint32_t pack_hi(uint32_t a, uint32_t b) { return (a >> 16) | (b & 0xffff0000u); }
+
+template <int MT>
+__global__ __launch_bounds__(kMfmaThreads) void ttm_mfma_bf16_kernel(const bf16_t* __restrict__ X, int64_t A,
+                                                                     int64_t K, int64_t B,
+                                                                     const bf16_t* __restrict__ Mop, int64_t m,
+                                                                     int64_t chunks, int ksplit, int64_t kper,
+                                                                     float* __restrict__ Y) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t unit = static_cast<int64_t>(blockIdx.x) * (kMfmaThreads / kWave) + threadIdx.x / kWave;
+  const int64_t total = A * chunks * ksplit;
+  if (unit >= total) return;
+  const int ks = static_cast<int>(unit % ksplit);
+  const int64_t ac = unit / ksplit;
+  const int64_t a = ac / chunks;
+  const int64_t b0 = (ac - a * chunks) * kUnitCols;
+  const int j = lane % 16, q = lane / 16;
+  const int64_t kbeg = ks * kper;
+  const int64_t kend = (kbeg + kper < K) ? kbeg + kper : K;
+
+  f32x4 acc[MT][8];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[mt][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const bf16_t* xa = X + a * K * B;
+  const int64_t col = b0 + 8 * j;
+  const bool colok = col < B;
+  for (int64_t k0 = kbeg; k0 < kend; k0 += 32) {
+    // lane loads rows k0 + 8q + t, columns col..col+7
+    u32x4 r[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int64_t k = k0 + 8 * q + t;
+      r[t] = u32x4{0u, 0u, 0u, 0u};
+      if (colok && k < kend) r[t] = *reinterpret_cast<const u32x4*>(xa + k * B + col);
+    }
+    // operand for column c: 8 consecutive k of column col + c
+    u32x4 op[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const uint32_t lo = r[2 * w][c / 2], hi = r[2 * w + 1][c / 2];
+        op[c][w] = (c % 2 == 0) ? pack_lo(lo, hi) : pack_hi(lo, hi);
+      }
+    }
+    u32x4 mv[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int64_t kk = k0 + 8 * q;
+      mv[mt] = u32x4{0u, 0u, 0u, 0u};
+      if (kk < kend) mv[mt] = *reinterpret_cast<const u32x4*>(Mop + (mt * 16 + j) * K + kk);
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const bf16x8 av = __builtin_bit_cast(bf16x8, mv[mt]);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const bf16x8 bv = __builtin_bit_cast(bf16x8, op[c]);
+        acc[mt][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[mt][c], 0, 0, 0);
+      }
+    }
+  }
+  float* ya = Y + (static_cast<int64_t>(ks) * A + a) * m * B;
+  if (!colok) return;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t i = mt * 16 + 4 * q + v;
+      if (i >= m) continue;
+      f32x4 o0 = f32x4{acc[mt][0][v], acc[mt][1][v], acc[mt][2][v], acc[mt][3][v]};
+      f32x4 o1 = f32x4{acc[mt][4][v], acc[mt][5][v], acc[mt][6][v], acc[mt][7][v]};
+      *reinterpret_cast<f32x4*>(ya + i * B + col) = o0;
+      *reinterpret_cast<f32x4*>(ya + i * B + col + 4) = o1;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void sum_splits_kernel(const float* __restrict__ part, int ksplit, int64_t n,
+                                                         float* __restrict__ Y) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * 256;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n; i += stride) {
+    float s = part[i];
+    for (int k = 1; k < ksplit; ++k) s += part[k * n + i];
+    Y[i] = s;
+  }
+}
+
+struct MfmaPlan {
+  int64_t chunks;
+  int ksplit;
+  int64_t kper;
+};
+
+MfmaPlan mfma_plan(rt_dtype xdt, int64_t A, int64_t K, int64_t B) {
+  MfmaPlan p;
+  p.chunks = ceil_div(B, kUnitCols);
+  const int64_t units = A * p.chunks;
+  const int64_t kgran = (xdt == RT_BF16) ? 32 : 4;
+  int ks = 1;
+  // aim for >= 2048 waves (8 per CU) when K is long enough to split
+  while (units * ks < 2048 && (K / (ks * 2)) >= 256 && ks < 16) ks *= 2;
+  p.ksplit = ks;
+  p.kper = ceil_div(ceil_div(K, ks), kgran) * kgran;
+  return p;
+}
+
+}  // namespace
+
+hipError_t launch_ttm_generic(const void* X, rt_dtype xdt, int64_t A, int64_t K, int64_t B, const void* M,
+                              int64_t m, void* Y, hipStream_t st) {
+  if (A * B == 0 || m == 0) return hipSuccess;
+  switch (xdt) {
+    case RT_F64:
+      return generic_dispatch<double, double>(static_cast<const double*>(X), A, K, B,
+                                              static_cast<const double*>(M), m, static_cast<double*>(Y), st);
+    case RT_F32:
+      return generic_dispatch<float, float>(static_cast<const float*>(X), A, K, B, static_cast<const float*>(M),
+                                            m, static_cast<float*>(Y), st);
+    case RT_BF16:
+      return generic_dispatch<bf16_t, float>(static_cast<const bf16_t*>(X), A, K, B,
+                                             static_cast<const float*>(M), m, static_cast<float*>(Y), st);
+    case RT_F8E4M3:
+      return generic_dispatch<f8_t, float>(static_cast<const f8_t*>(X), A, K, B, static_cast<const float*>(M), m,
+                                           static_cast<float*>(Y), st);
+  }
+  return hipErrorInvalidValue;
+}
+
+int64_t ttm_mfma_mpad(int64_t m) { return ceil_div(m, 16) * 16; }
+
+bool ttm_mfma_ok(rt_dtype xdt, int64_t A, int64_t K, int64_t B, int64_t m) {
+  if (m < 1 || m > 64 || A < 1 || K < 1) return false;
+  if (xdt == RT_F32) return B >= 64 && (B % 4) == 0;
+  if (xdt == RT_BF16) return B >= 64 && (B % 8) == 0 && (K % 8) == 0;
+  return false;
+}
+
+size_t ttm_mfma_ws(rt_dtype xdt, int64_t A, int64_t K, int64_t B, int64_t m) {
+  const MfmaPlan p = mfma_plan(xdt, A, K, B);
+  if (p.ksplit == 1) return 0;
+  return align256(static_cast<size_t>(p.ksplit) * A * m * B * sizeof(float));
+}
+
+hipError_t launch_ttm_mfma_ws(const void* X, rt_dtype xdt, int64_t A, int64_t K, int64_t B, const void* Mop,
+                              int64_t m, float* Y, void* ws, hipStream_t st) {
+  const MfmaPlan p = mfma_plan(xdt, A, K, B);
+  float* out = (p.ksplit == 1) ? Y : static_cast<float*>(ws);
+  const int64_t units = A * p.chunks * p.ksplit;
+  const unsigned grid = static_cast<unsigned>(ceil_div(units, kMfmaThreads / kWave));
+  const int MT = static_cast<int>(ttm_mfma_mpad(m) / 16);
+#define RT_LAUNCH_F32(MTV)                                                                                  \
+  ttm_mfma_f32_kernel<MTV><<<grid, kMfmaThreads, 0, st>>>(static_cast<const float*>(X), A, K, B,            \
+                                                          static_cast<const float*>(Mop), m, p.chunks,      \
+                                                          p.ksplit, p.kper, out)
+#define RT_LAUNCH_BF16(MTV)                                                                                 \
+  ttm_mfma_bf16_kernel<MTV><<<grid, kMfmaThreads, 0, st>>>(static_cast<const bf16_t*>(X), A, K, B,          \
+                                                           static_cast<const bf16_t*>(Mop), m, p.chunks,    \
+                                                           p.ksplit, p.kper, out)
+  if (xdt == RT_F32) {
+    switch (MT) {
+      case 1: RT_LAUNCH_F32(1); break;
+      case 2: RT_LAUNCH_F32(2); break;
+      case 3: RT_LAUNCH_F32(3); break;
+      default: RT_LAUNCH_F32(4); break;
+    }
+  } else {
+    switch (MT) {
+      case 1: RT_LAUNCH_BF16(1); break;
+      case 2: RT_LAUNCH_BF16(2); break;
+      case 3: RT_LAUNCH_BF16(3); break;
+      default: RT_LAUNCH_BF16(4); break;
+    }
+  }
+#undef RT_LAUNCH_F32
+#undef RT_LAUNCH_BF16
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || p.ksplit == 1) return e;
+  const int64_t n = A * m * B;
+  const unsigned g2 = static_cast<unsigned>(ceil_div(n, 256) > 8192 ? 8192 : ceil_div(n, 256));
+  sum_splits_kernel<<<g2, 256, 0, st>>>(out, p.ksplit, n, Y);
+  return hipGetLastError();
+}
+
+}  // namespace rt

@@ -1,0 +1,103 @@
+// Internal launchers of rtucker's HIP kernels (not part of the C ABI).
+// Every launcher enqueues on `st` and returns the launch status.
+#pragma once
+
+#include "common.hpp"
+
+namespace rt {
+
+// ------------------------------------------------------------------ k_basic.hip
+// dst[i] = round(src[i] * 2^scale_exp) (RNE); see rtucker_convert.
+hipError_t launch_convert(const void* src, rt_dtype sdt, void* dst, rt_dtype ddt, int64_t n,
+                          int scale_exp, hipStream_t st);
+
+// Prepare a compute operand from a binary64 matrix:
+//   out(i, k) for i < m, k < K, row-major m x K, stored as `store` with values
+//   rounded to `round_to` (RNE).  src is m x K row-major (trans == false) or
+//   K x m row-major (trans == true).  Rows i >= m up to m_pad are zero-filled.
+//   store: RT_F64, RT_F32 (value rounded to round_to, kept in binary32),
+//   RT_BF16 or RT_F8E4M3 (bit patterns; round_to must equal store).
+hipError_t launch_prep_matrix(const double* src, int64_t m, int64_t K, bool trans, rt_dtype round_to,
+                              rt_dtype store, int64_t m_pad, void* dst, hipStream_t st);
+
+// dst[i * (A*B) + a*B + b] = src[a*m*B + i*B + b]   (mode-n unfolding of an (A, m, B) view)
+hipError_t launch_unfold(const void* src, size_t esize, int64_t A, int64_t m, int64_t B, void* dst,
+                         hipStream_t st);
+
+// Elementwise R = A - B (R may be null) and out[0] = sum (A-B)^2 in binary64, deterministic.
+size_t sq_residual_ws(int64_t n);
+hipError_t launch_sq_residual(const void* a, const void* b, void* r, rt_dtype dt, int64_t n,
+                              double* out, void* ws, hipStream_t st);
+
+// ------------------------------------------------------------------ k_ttm.hip
+// Y[a, i, b] = sum_k M[i*K + k] * X[a, k, b] for i < m.
+//  X dtype xdt; M and Y in the compute type: binary64 if xdt == RT_F64, else binary32.
+hipError_t launch_ttm_generic(const void* X, rt_dtype xdt, int64_t A, int64_t K, int64_t B,
+                              const void* M, int64_t m, void* Y, hipStream_t st);
+
+// MFMA path for X in binary32 or bfloat16 (binary32 accumulation, binary32 output).
+//  Operand Mop prepared by launch_prep_matrix with store = xdt (F32 or BF16),
+//  m_pad = ttm_mfma_mpad(m).  Requires ttm_mfma_ok().
+bool ttm_mfma_ok(rt_dtype xdt, int64_t A, int64_t K, int64_t B, int64_t m);
+int64_t ttm_mfma_mpad(int64_t m);
+hipError_t launch_ttm_mfma(const void* X, rt_dtype xdt, int64_t A, int64_t K, int64_t B,
+                           const void* Mop, int64_t m, float* Y, hipStream_t st);
+
+// ------------------------------------------------------------------ k_sketch.hip
+// First level of the sketch dimension tree over X viewed as (A, P, Q):
+//   Z[a, p, c] = sum_q X[a,p,q] phiQ[c,q]     (A x P x sQ)
+//   W[a, c, q] = sum_p phiP[c,p] X[a,p,q]     (A x sP x Q)
+// phiP/phiQ: compute type (binary64 for F64 X, else binary32 holding values
+// already rounded to X's dtype), row-major sP x P and sQ x Q.
+// Either output may be skipped (null).  Z/W in the compute type.
+struct ZWPlan {
+  int64_t qblocks, pblocks, rows_per_block;
+  size_t ws_bytes;
+};
+ZWPlan sketch_zw_plan(rt_dtype xdt, int64_t A, int64_t P, int64_t Q, int64_t sP, int64_t sQ,
+                      bool needZ, bool needW);
+bool sketch_zw_ok(rt_dtype xdt, int64_t sP, int64_t sQ);
+hipError_t launch_sketch_zw(const void* X, rt_dtype xdt, int64_t A, int64_t P, int64_t Q,
+                            const void* phiP, int64_t sP, const void* phiQ, int64_t sQ, void* Z,
+                            void* W, const ZWPlan& plan, void* ws, hipStream_t st);
+
+// ------------------------------------------------------------------ k_qr.hip
+// Thin Householder QR (binary64) of matrices given as (A, m, B) views:
+// element (i, j = a*B + b) at Y[a*m*B + i*B + b]; n = A*B <= 64 columns.
+struct QRJob {
+  const void* Y;
+  int64_t A, m, B;
+  double* Q;  // m x min(m, n) row-major
+  double* R;  // min(m, n) x n row-major, may be null
+};
+constexpr int kMaxQRJobs = 8;
+constexpr int kMaxQRCols = 64;
+size_t qr_ws(const QRJob* jobs, int count);
+hipError_t launch_qr(const QRJob* jobs, int count, rt_dtype ydt, void* ws, hipStream_t st);
+
+// ------------------------------------------------------------------ k_eig.hip
+// out[i][j] = sum_{a,b} P[a,i,b] * Q[a,j,b], P: (A, mP, B), Q: (A, mQ, B); same dtype
+// (F32 or F64); out in that dtype, mP x mQ row-major; deterministic two-stage sum.
+size_t mode_contract_ws(rt_dtype dt, int64_t A, int64_t mP, int64_t mQ, int64_t B);
+hipError_t launch_mode_contract(const void* P, const void* Q, rt_dtype dt, int64_t A, int64_t mP,
+                                int64_t mQ, int64_t B, void* out, void* ws, hipStream_t st);
+
+// Symmetric eigendecomposition (cyclic Jacobi, binary64) of an n x n matrix
+// (n <= 64): V (n x r row-major) = eigenvectors of the r largest eigenvalues,
+// in decreasing order, each column's largest-magnitude entry made positive.
+// evals (may be null): all n eigenvalues, decreasing.
+hipError_t launch_sym_eig_top(const double* M, int64_t n, int64_t r, double* V, double* evals,
+                              hipStream_t st);
+
+// ------------------------------------------------------------------ k_norm.hip
+// Residual of X viewed as (I1, Brest) against U1 (I1 x r1) times T (r1 x Brest),
+// both binary64: out[0] += ||X - U1 T||^2, out[1] = ||X||^2, out[3] = #nonfinite(X);
+// out[2] is left to the caller.  Deterministic.
+size_t recon_residual_ws(int64_t I1, int64_t Brest);
+hipError_t launch_recon_residual(const void* X, rt_dtype xdt, int64_t I1, int64_t Brest,
+                                 const double* U1, const double* T, int64_t r1, double* out,
+                                 void* ws, hipStream_t st);
+// out[2] = ||G||^2 for a binary64 array of n values.
+hipError_t launch_sumsq_f64(const double* g, int64_t n, double* out_slot, hipStream_t st);
+
+}  // namespace rt

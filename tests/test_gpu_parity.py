@@ -1,0 +1,316 @@
+"""GPU parity: each entry point of the C ABI against the FP64 oracle on the same
+seeded inputs (sizes span several tiles and ragged tails)."""
+import numpy as np
+import pytest
+
+from gpu_common import DEV, T, dev, host, pytestmark_skip, reuse_phis, rt, say, sth_phis, subspace_gap, synth, torch
+from oracle import lowp as L
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(pytestmark_skip, reason="needs a GPU")]
+
+
+# ------------------------------------------------------------------ conversion (bit-exact)
+def _convert_inputs():
+    rng = np.random.default_rng(100)
+    x = rng.standard_normal(1 << 18) * np.exp2(rng.integers(-140, 128, 1 << 18))
+    grid = L.f8_decode(np.arange(0, 127, dtype=np.uint8))
+    mids = 0.5 * (grid[1:] + grid[:-1])
+    special = np.array([0.0, -0.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 2 ** -126, 2 ** -130, -2 ** -133, 2 ** -134,
+                        3.3e38, 448.0, 464.0, 500.0, -1e6, 2 ** -10, 2 ** -9 * 1.5])
+    return np.concatenate([x, grid, -grid, mids, -mids, special])
+
+
+@pytest.mark.parametrize("src", ["f32", "f64"])
+def test_convert_bf16_bit_exact(src):
+    say("convert bf16", src)
+    x = _convert_inputs()
+    if src == "f32":
+        x = x.astype(np.float32).astype(np.float64)
+    t = dev(x, torch.float32 if src == "f32" else torch.float64)
+    got = rt.rtucker_convert(t, torch.bfloat16)
+    got_bits = got.view(torch.int16).cpu().numpy().view(np.uint16)
+    want = L.round_bf16(x)
+    fin = np.isfinite(want)
+    want_bits = L.bf16_bits(want[fin])
+    np.testing.assert_array_equal(got_bits[fin], want_bits)
+    assert np.all((got_bits[~fin] & 0x7fff) == 0x7f80)
+
+
+@pytest.mark.parametrize("src", ["f32", "f64"])
+def test_convert_f8_bit_exact(src):
+    say("convert f8", src)
+    x = _convert_inputs()
+    x = x[np.abs(x) < 1e30]
+    if src == "f32":
+        x = x.astype(np.float32).astype(np.float64)
+    t = dev(x, torch.float32 if src == "f32" else torch.float64)
+    got = rt.rtucker_convert(t, torch.float8_e4m3fn)
+    got_bits = got.view(torch.uint8).cpu().numpy()
+    want_bits = L.f8_bits(L.round_f8(x))
+    np.testing.assert_array_equal(got_bits, want_bits)
+    # torch's own decoding of the bytes agrees with the format definition
+    np.testing.assert_array_equal(got.float().cpu().numpy().astype(np.float64), L.f8_decode(got_bits))
+
+
+def test_convert_scale_exponent():
+    x = np.array([1.0, 3.0, -0.75, 100.0])
+    got = rt.rtucker_convert(dev(x, torch.float32), torch.float32, scale_exp=-3)
+    np.testing.assert_array_equal(host(got), x / 8)
+
+
+# ------------------------------------------------------------------ sketch
+SKETCH_CASES = [
+    ((37, 150, 530), (3, 5, 7)),     # two column blocks (530 > 512), row split, ragged tails
+    ((64, 64, 64), (4, 4, 4)),
+    ((9, 33, 1000), (2, 8, 6)),
+    ((11, 13, 17, 70), (2, 3, 4, 5)),  # 4-way: tree beyond the first level
+    ((300, 517), (6, 5)),            # 2-way
+    ((20, 24, 30), (4, 10, 3)),      # subrank > 8: generic first level
+]
+
+
+@pytest.mark.parametrize("dims,s", SKETCH_CASES)
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16", "f8"])
+def test_sketch_parity(dims, s, dt):
+    say("sketch", dims, s, dt)
+    rng = np.random.default_rng(200)
+    X = rng.standard_normal(dims)
+    phis = reuse_phis(dims, s, seed=201)
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16, "f8": torch.float8_e4m3fn}[dt]
+    rnd = {"f64": lambda v: v, "f32": L.round_f32, "bf16": L.round_bf16, "f8": L.round_f8}[dt]
+    Xr = rnd(X)
+    Xd = dev(Xr, torch.float64).to(tdt) if dt != "f64" else dev(Xr)
+    Ys = rt.rtucker_sketch(Xd, [dev(p) for p in phis], s)
+    tol = 1e-13 if dt == "f64" else 5e-6
+    for n in range(len(dims)):
+        want = T.kron_sketch(Xr, [rnd(p) for p in phis], n)
+        got = host(Ys[n])
+        assert got.shape == want.shape
+        err = np.linalg.norm(got - want) / np.linalg.norm(want)
+        assert err <= tol, (n, err)
+
+
+def test_sketch_single_mode_masks():
+    dims, s = (21, 40, 66), (3, 4, 5)
+    X = np.random.default_rng(202).standard_normal(dims)
+    phis = reuse_phis(dims, s, seed=203)
+    for n in range(3):
+        Ys = rt.rtucker_sketch(dev(X), [dev(p) for p in phis], s, modes=[n])
+        assert all(Ys[k] is None for k in range(3) if k != n)
+        want = T.kron_sketch(X, phis, n)
+        assert np.linalg.norm(host(Ys[n]) - want) <= 1e-13 * np.linalg.norm(want)
+
+
+# ------------------------------------------------------------------ QR
+QR_CASES = [(1024, 49), (300, 64), (130, 27), (64, 16), (600, 20), (257, 33), (5000, 8), (40, 60), (3, 5)]
+
+
+@pytest.mark.parametrize("m,n", QR_CASES)
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_qr_parity(m, n, dt):
+    say("qr", m, n, dt)
+    rng = np.random.default_rng(300 + m + n)
+    Y = rng.standard_normal((m, n))
+    if dt == "f32":
+        Y = L.round_f32(Y)
+    Yd = dev(Y, torch.float64 if dt == "f64" else torch.float32)
+    Q, R = rt.rtucker_qr(Yd, want_r=True)
+    Q, R = host(Q), host(R)
+    Qo, Ro = T.qr_pos(Y)
+    c = min(m, n)
+    assert Q.shape == (m, c) and R.shape == (c, n)
+    np.testing.assert_allclose(Q.T @ Q, np.eye(c), atol=1e-13)
+    np.testing.assert_allclose(Q, Qo, atol=1e-11)
+    np.testing.assert_allclose(R, Ro, atol=1e-11 * np.abs(Ro).max())
+    assert np.all(np.diag(R) >= 0)
+
+
+@pytest.mark.parametrize("m", [90, 700])
+def test_qr_rank_deficient(m):
+    rng = np.random.default_rng(310)
+    Y = rng.standard_normal((m, 3)) @ rng.standard_normal((3, 12))
+    Q = host(rt.rtucker_qr(dev(Y)))
+    np.testing.assert_allclose(Q.T @ Q, np.eye(12), atol=1e-12)
+    assert np.linalg.norm(Y - Q @ (Q.T @ Y)) <= 1e-12 * np.linalg.norm(Y)
+    Qo, _ = T.qr_pos(Y)
+    assert subspace_gap(Q[:, :3], Qo[:, :3]) < 1e-10
+
+
+def test_qr_zero_matrix():
+    Q = host(rt.rtucker_qr(dev(np.zeros((50, 6)))))
+    np.testing.assert_allclose(Q.T @ Q, np.eye(6), atol=1e-14)
+
+
+# ------------------------------------------------------------------ core multi-TTM
+CORE_CASES = [
+    ((264, 136, 40), (30, 49, 17)),   # first contraction on MFMA (B = 5440), then generic
+    ((70, 90, 130), (20, 33, 64)),    # generic first (B = 1), MFMA second with a ragged K = 90
+    ((256, 64, 96), (49, 16, 5)),     # m = 49 padded to 64 rows
+    ((1024, 16, 24), (49, 8, 8)),     # split-K partial sums
+    ((12, 11, 10, 200), (3, 4, 5, 27)),
+]
+
+
+@pytest.mark.parametrize("dims,l", CORE_CASES)
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+def test_core_parity(dims, l, dt):
+    say("core", dims, l, dt)
+    rng = np.random.default_rng(400)
+    X = rng.standard_normal(dims)
+    Us = [np.linalg.qr(rng.standard_normal((n, k)))[0] for n, k in zip(dims, l)]
+    if dt == "bf16":
+        X = L.round_bf16(X)
+        Xd = dev(X).to(torch.bfloat16)
+    elif dt == "f32":
+        X = L.round_f32(X)
+        Xd = dev(X, torch.float32)
+    else:
+        Xd = dev(X)
+    G = host(rt.rtucker_core(Xd, [dev(U) for U in Us]))
+    # emulate the rounding points: first (largest) mode's U in X's dtype, later ones binary32
+    order = T.core_order(dims)
+    rnd1 = {"f64": lambda v: v, "f32": L.round_f32, "bf16": L.round_bf16}[dt]
+    rnd2 = (lambda v: v) if dt == "f64" else L.round_f32
+    want = T.ttm(X, rnd1(Us[order[0]]).T, order[0])
+    for k in order[1:]:
+        want = T.ttm(rnd2(want), rnd2(Us[k]).T, k)
+    tol = 1e-13 if dt == "f64" else 2e-6
+    assert np.linalg.norm(G - want) <= tol * np.linalg.norm(want)
+
+
+def test_core_single_modes():
+    dims = (33, 64, 80)
+    rng = np.random.default_rng(401)
+    X = L.round_f32(rng.standard_normal(dims))
+    Us = [np.linalg.qr(rng.standard_normal((n, 9)))[0] for n in dims]
+    for k in range(3):
+        G = host(rt.rtucker_core(dev(X, torch.float32), [dev(U) for U in Us], modes=[k]))
+        want = T.ttm(X, L.round_f32(Us[k]).T, k)
+        assert np.linalg.norm(G - want) <= 2e-6 * np.linalg.norm(want)
+
+
+# ------------------------------------------------------------------ decomposition
+def _decompose_and_compare(X, Xd, r, p, algo, phis, s, tol_e, Xsk=None, emulate=None):
+    phis_d = [dev(f) for f in phis] if algo == "rhkron" else [[dev(f) if f is not None else None for f in row]
+                                                                for row in phis]
+    G, Us = rt.rtucker_decompose(Xd, r, p, phis_d, algo=algo, s=s, X_sketch=Xsk)
+    G, Us = host(G), [host(U) for U in Us]
+    if emulate is not None:
+        Go, Uo = emulate
+    elif algo == "rhkron":
+        Go, Uo = T.rhkron(X, r, phis)
+    else:
+        Go, Uo = T.rsthkron(X, r, phis)
+    e_o = T.rel_error(X, Go, Uo)
+    e_g = T.rel_error(X, G, Us)
+    e_dev, norms = rt.rtucker_rel_error(Xd, dev(G), [dev(U) for U in Us])
+    say(f"  e_gpu={e_g:.12e} e_oracle={e_o:.12e} e_device={e_dev:.12e}")
+    assert abs(e_g - e_o) <= tol_e
+    assert abs(e_dev - e_g) <= 1e-12 + 1e-9 * e_g
+    for U in Us:
+        np.testing.assert_allclose(U.T @ U, np.eye(U.shape[1]), atol=1e-12)
+    return G, Us, Go, Uo
+
+
+def test_decompose_config1_fp64():
+    """64^3 FP64 random Tucker (core 8^3, noise 1e-6), r = 8, p = 5, s = 4: |de| <= 1e-10."""
+    say("decompose config1")
+    X, _, _ = synth.random_tucker((64, 64, 64), (8, 8, 8), 1e-6)
+    s = [4, 4, 4]
+    phis = reuse_phis(X.shape, s)
+    G, Us, Go, Uo = _decompose_and_compare(X, dev(X), [8, 8, 8], 5, "rhkron", phis, s, 1e-10)
+    for U, V in zip(Us, Uo):
+        assert subspace_gap(U, V) < 1e-8
+    np.testing.assert_allclose(G, Go, atol=1e-9 * np.abs(Go).max())
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_decompose_rsthkron_4way(dt):
+    say("decompose rsthkron 4way", dt)
+    dims = (20, 18, 16, 14)
+    core = synth.tucker_core_decay((6, 6, 6, 6), tau=3.0, seed=5)
+    X, _, _ = synth.random_tucker(dims, None, 1e-3, seed=6, core=core)
+    r = [4, 4, 4, 4]
+    S = T.subrank_matrix_sth([6, 6, 6, 6])
+    phis = sth_phis(dims, S, seed=7)
+    if dt == "f32":
+        X = L.round_f32(X)
+    Xd = dev(X) if dt == "f64" else dev(X, torch.float32)
+    _decompose_and_compare(X, Xd, r, 2, "rsthkron", phis, S, 1e-10 if dt == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("algo", ["rhkron", "rsthkron"])
+def test_decompose_bumps_fp32(algo):
+    say("decompose bumps fp32", algo)
+    dims = (96, 80, 72)
+    X = synth.bumps_field(dims, nbumps=30, noise_rel=1e-4, seed=8).astype(np.float64)
+    r, p = [8, 8, 8], 4
+    if algo == "rhkron":
+        s = T.subranks_reuse([12, 12, 12])
+        phis = reuse_phis(dims, s, seed=9)
+    else:
+        s = T.subrank_matrix_sth([12, 12, 12])
+        phis = sth_phis(dims, s, seed=9)
+    _decompose_and_compare(X, dev(X, torch.float32), r, p, algo, phis, s, 1e-5)
+
+
+def test_decompose_bf16_against_emulation():
+    say("decompose bf16")
+    dims = (96, 80, 72)
+    X = synth.bumps_field(dims, nbumps=30, noise_rel=1e-4, seed=8).astype(np.float64)
+    r, p = [8, 8, 8], 4
+    s = T.subranks_reuse([12, 12, 12])
+    phis = reuse_phis(dims, s, seed=9)
+    Xb = L.round_bf16(X)
+    emu = L.rhkron_emulated(X, r, phis, "bf16", "bf16")
+    _decompose_and_compare(X, dev(Xb).to(torch.bfloat16), r, p, "rhkron", phis, s, 1e-5, emulate=emu)
+
+
+def test_decompose_fp8_sketch_against_emulation():
+    say("decompose fp8 sketch")
+    dims = (96, 80, 72)
+    X = synth.bumps_field(dims, nbumps=30, noise_rel=1e-4, seed=8).astype(np.float64)  # binary32 values
+    r, p = [8, 8, 8], 4
+    s = T.subranks_reuse([12, 12, 12])
+    phis = reuse_phis(dims, s, seed=9)
+    Xf = dev(X, torch.float32)
+    X8 = rt.rtucker_convert(Xf, torch.float8_e4m3fn)
+    emu = L.rhkron_emulated(X, r, phis, "f8e4m3", "f32")
+    _decompose_and_compare(X, Xf, r, p, "rhkron", phis, s, 1e-5, Xsk=X8, emulate=emu)
+
+
+def test_decompose_exact_rank_and_full_width():
+    """Exact Tucker rank: error at rounding level.  Full-width sketch (ltilde = I): equals STHOSVD."""
+    say("decompose exact rank")
+    X, _, F = synth.random_tucker((30, 26, 22), (4, 3, 5), 0.0, seed=10)
+    s = T.subranks_reuse([6, 5, 7])
+    phis = reuse_phis(X.shape, s, seed=11)
+    G, Us = rt.rtucker_decompose(dev(X), [4, 3, 5], 2, [dev(f) for f in phis], s=s)
+    assert T.rel_error(X, host(G), [host(U) for U in Us]) < 1e-12
+    rng = np.random.default_rng(12)
+    Y = rng.standard_normal((16, 16, 16))
+    phis = reuse_phis(Y.shape, [4, 4, 4], seed=13)
+    G, Us = rt.rtucker_decompose(dev(Y), [5, 4, 6], 3, [dev(f) for f in phis], s=[4, 4, 4])
+    Gs, Vs = T.sthosvd(Y, [5, 4, 6])
+    assert abs(T.rel_error(Y, host(G), [host(U) for U in Us]) - T.rel_error(Y, Gs, Vs)) < 1e-12
+
+
+def test_decompose_bitwise_repeatable():
+    X = synth.bumps_field((64, 72, 80), nbumps=20, noise_rel=1e-4, seed=14)
+    Xd = dev(X, torch.float32)
+    s = [4, 4, 4]
+    phis = [dev(f) for f in reuse_phis(X.shape, s, seed=15)]
+    G1, U1 = rt.rtucker_decompose(Xd, [6, 6, 6], 4, phis, s=s)
+    G2, U2 = rt.rtucker_decompose(Xd, [6, 6, 6], 4, phis, s=s)
+    torch.cuda.synchronize()
+    assert torch.equal(G1, G2) and all(torch.equal(a, b) for a, b in zip(U1, U2))
+
+
+def test_rel_error_matches_oracle():
+    rng = np.random.default_rng(16)
+    X = rng.standard_normal((50, 40, 30))
+    G = rng.standard_normal((5, 4, 3))
+    Us = [np.linalg.qr(rng.standard_normal((n, k)))[0] for n, k in zip(X.shape, G.shape)]
+    e, norms = rt.rtucker_rel_error(dev(X), dev(G), [dev(U) for U in Us])
+    assert abs(e - T.rel_error(X, G, Us)) <= 1e-13
+    assert abs(norms["g2"] - np.sum(G * G)) <= 1e-12 * np.sum(G * G)
