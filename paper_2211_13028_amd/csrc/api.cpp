@@ -15,13 +15,6 @@
 
 using namespace rt;
 
-namespace rt {
-// defined in k_ttm.hip
-size_t ttm_mfma_ws(rt_dtype xdt, int64_t A, int64_t K, int64_t B, int64_t m);
-hipError_t launch_ttm_mfma_ws(const void* X, rt_dtype xdt, int64_t A, int64_t K, int64_t B, const void* Mop,
-                              int64_t m, float* Y, void* ws, hipStream_t st);
-}  // namespace rt
-
 namespace {
 
 // ------------------------------------------------------------------ context
@@ -113,7 +106,8 @@ Ten ttm(Ctx& c, const Ten& T, int k, const void* M, int64_t m, void* dst = nullp
   const int64_t A = T.before(k), K = T.dims[k], B = T.after(k);
   void* y = dst ? dst : c.take(static_cast<size_t>(A) * m * B * dtype_size(out.dt));
   out.p = y;
-  if (!c.dry) c.chk(launch_ttm_generic(T.p, T.dt, A, K, B, M, m, y, c.st));
+  void* w = c.take(ttm_generic_ws(T.dt, A, K, B, m));
+  if (!c.dry) c.chk(launch_ttm_generic(T.p, T.dt, A, K, B, M, m, y, w, c.st));
   return out;
 }
 
@@ -149,9 +143,15 @@ void sketch_impl(Ctx& c, const Ten& X, const double* const* phi, const int64_t* 
     if (needZ) Z.p = c.take(static_cast<size_t>(Z.numel()) * dtype_size(ct));
     if (needW) W.p = c.take(static_cast<size_t>(W.numel()) * dtype_size(ct));
     void* zws = plan.ws_bytes ? c.take(plan.ws_bytes) : nullptr;
+    const void* p16 = nullptr;
+    const void* q16 = nullptr;
+    if (plan.mfma) {  // bfloat16 factors padded to 16 rows for the matrix-core pass
+      if (needW) p16 = prep(c, phi ? phi[S] : nullptr, s[S], P, false, RT_BF16, RT_BF16, 16);
+      if (needZ) q16 = prep(c, phi ? phi[L] : nullptr, s[L], Q, false, RT_BF16, RT_BF16, 16);
+    }
     if (!c.dry)
       c.chk(launch_sketch_zw(X.p, X.dt, A0, P, Q, needW ? op[S] : nullptr, s[S], needZ ? op[L] : nullptr, s[L],
-                             const_cast<void*>(Z.p), const_cast<void*>(W.p), plan, zws, c.st));
+                             p16, q16, const_cast<void*>(Z.p), const_cast<void*>(W.p), plan, zws, c.st));
   } else {
     if (needZ) Z = ttm(c, X, L, op[L], s[L]);
     if (needW) W = ttm(c, X, S, op[S], s[S]);
@@ -201,7 +201,8 @@ Ten core_impl(Ctx& c, const Ten& X, const double* const* U, const int64_t* l, ui
       if (!c.dry) c.chk(launch_ttm_mfma_ws(cur.p, cur.dt, A, K, B, mop, m, static_cast<float*>(y), w, c.st));
     } else {
       const void* M = prep(c, U ? U[k] : nullptr, m, K, true, cur.dt == RT_F64 ? RT_F64 : cur.dt, ct);
-      if (!c.dry) c.chk(launch_ttm_generic(cur.p, cur.dt, A, K, B, M, m, y, c.st));
+      void* w = c.take(ttm_generic_ws(cur.dt, A, K, B, m));
+      if (!c.dry) c.chk(launch_ttm_generic(cur.p, cur.dt, A, K, B, M, m, y, w, c.st));
     }
     cur = out;
   }
@@ -223,7 +224,8 @@ void truncate_impl(Ctx& c, Ten G, const int32_t* r, double* const* Uhat, const s
     }
     const void* Vt = prep(c, V, rj, cj, true, RT_F64, RT_F64);
     G = ttm(c, G, j, Vt, rj, (j == d - 1) ? Gout : nullptr);
-    if (!c.dry) c.chk(launch_ttm_generic(Uhat[j], RT_F64, I[j], cj, 1, Vt, rj, Uout[j], c.st));
+    void* w = c.take(ttm_generic_ws(RT_F64, I[j], cj, 1, rj));
+    if (!c.dry) c.chk(launch_ttm_generic(Uhat[j], RT_F64, I[j], cj, 1, Vt, rj, Uout[j], w, c.st));
   }
 }
 

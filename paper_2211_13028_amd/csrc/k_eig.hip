@@ -2,10 +2,8 @@
 //  * mode contraction out = P_(n) Q_(n)^T on (A, m, B) views, which gives the
 //    Gram matrix G_(j) G_(j)^T of the core (P = Q) and the adjoint dA_n;
 //    fixed-order two-stage reduction, so results are bitwise reproducible;
-//  * a symmetric eigensolver for the <= 64 x 64 Gram matrices: parallel cyclic
-//    Jacobi (round-robin pairing, all disjoint rotations of a round applied at
-//    once as 2x2 block updates) in binary64, in one workgroup with the matrix and
-//    the eigenvector accumulator in LDS.
+//  * a symmetric eigensolver for the <= 64 x 64 Gram matrices: pivoted Cholesky
+//    followed by one-sided Jacobi on the Cholesky factor, binary64, one workgroup.
 #include "kernels.hpp"
 
 namespace rt {
@@ -35,22 +33,33 @@ __global__ __launch_bounds__(kMCThreads) void mode_contract_kernel(const T* __re
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[u][v] = T(0);
-  const bool tfast = B >= kMCK;  // choose the loading order that follows memory
-  for (int64_t tb = t0; tb < t1; tb += kMCK) {
+  // loading roles: each thread loads the elements (tt, ii) with tt = lt and ii = li + 16*rep
+  const bool tfast = B >= kMCK;  // follow memory order: t fastest when rows of b are long
+  int lt, li;
+  if (tfast) { lt = threadIdx.x % kMCK; li = threadIdx.x / kMCK; } else { li = threadIdx.x % kMCTile; lt = threadIdx.x / kMCTile; }
+  const int istep = tfast ? (kMCThreads / kMCK) : kMCTile;   // 16 or 64 rows per pass
+  const int tstep = tfast ? kMCK : (kMCThreads / kMCTile);   // 16 or 4 t per pass
+  // incremental (a, b) of this thread's first t, no division inside the loop
+  int64_t ta = (t0 + lt) / B, tb = (t0 + lt) - ((t0 + lt) / B) * B;
+  for (int64_t tbase = t0; tbase < t1; tbase += kMCK) {
     __syncthreads();
-    for (int idx = threadIdx.x; idx < kMCK * kMCTile; idx += kMCThreads) {
-      int tt, ii;
-      if (tfast) { tt = idx % kMCK; ii = idx / kMCK; } else { ii = idx % kMCTile; tt = idx / kMCTile; }
-      const int64_t t = tb + tt;
-      T pv = T(0), qv = T(0);
-      if (t < t1) {
-        const int64_t a = t / B, b = t - a * B;
-        if (i0 + ii < mP) pv = P[a * mP * B + (i0 + ii) * B + b];
-        if (j0 + ii < mQ) qv = Q[a * mQ * B + (j0 + ii) * B + b];
+    for (int tt = lt; tt < kMCK; tt += tstep) {
+      // (a, b) for t = tbase + tt: advance from the thread's running position
+      int64_t a = ta, b = tb + (tt - lt);
+      while (b >= B) { b -= B; ++a; }
+      const int64_t t = tbase + tt;
+      for (int ii = li; ii < kMCTile; ii += istep) {
+        T pv = T(0), qv = T(0);
+        if (t < t1) {
+          if (i0 + ii < mP) pv = P[a * mP * B + (i0 + ii) * B + b];
+          if (j0 + ii < mQ) qv = Q[a * mQ * B + (j0 + ii) * B + b];
+        }
+        sP[tt][ii] = pv;
+        sQ[tt][ii] = qv;
       }
-      sP[tt][ii] = pv;
-      sQ[tt][ii] = qv;
     }
+    tb += kMCK;
+    while (tb >= B) { tb -= B; ++ta; }
     __syncthreads();
 #pragma unroll 4
     for (int tt = 0; tt < kMCK; ++tt) {
@@ -100,7 +109,7 @@ MCPlan mc_plan(int64_t A, int64_t mP, int64_t mQ, int64_t B) {
   int64_t want = 512 / (p.tilesP * p.tilesQ);
   if (want < 1) want = 1;
   int64_t chunk = ceil_div(total, want);
-  if (chunk < 1024) chunk = 1024;
+  if (chunk < 64) chunk = 64;
   chunk = ceil_div(chunk, kMCK) * kMCK;
   p.chunk = chunk;
   p.nchunks = static_cast<int>(ceil_div(total, chunk));
@@ -108,100 +117,185 @@ MCPlan mc_plan(int64_t A, int64_t mP, int64_t mQ, int64_t B) {
   return p;
 }
 
-// ------------------------------------------------------------------ Jacobi
+// ------------------------------------------------------------------ eigensolver
+// Eigenvectors of the symmetric positive semidefinite Gram matrix M = G_(j) G_(j)^T:
+//  1. pivoted outer-product Cholesky M = L L^T (columns of L taken in order of
+//     decreasing remaining diagonal; rows stay in the original order);
+//  2. one-sided (Hestenes) Jacobi on the columns of L: rotate column pairs until
+//     all are mutually orthogonal, so L V = U S with U the eigenvectors of M and
+//     S^2 its eigenvalues (no V is accumulated: the rotated columns are U S).
+// The pivoting grades L, which cuts the number of sweeps roughly in half
+// compared with two-sided Jacobi on M, and the left singular vectors of L are
+// more accurate than eigenvectors of M computed directly.  One round applies the
+// rotations of all disjoint pairs of the circle-method pairing; each pair is
+// owned by 8 lanes (8 rows each), so a round needs one barrier.
 constexpr int kJN = 64;
 constexpr int kJThreads = 256;
-constexpr int kMaxSweeps = 40;
+constexpr int kPairLanes = 8;
+constexpr int kMaxSweeps = 30;
 
-__global__ __launch_bounds__(kJThreads) void jacobi_eig_kernel(const double* __restrict__ M, int n, int r,
-                                                               double* __restrict__ Vout, double* __restrict__ evals) {
-  __shared__ double Am[kJN][kJN + 1];
-  __shared__ double Vm[kJN][kJN + 1];
-  __shared__ double cs[kJN / 2], sn[kJN / 2];
-  __shared__ int pp[kJN / 2], qq[kJN / 2];
+__global__ __launch_bounds__(kJThreads) void eig_onesided_kernel(const double* __restrict__ M, int n, int r,
+                                                                 double* __restrict__ Vout,
+                                                                 double* __restrict__ evals) {
+  __shared__ double Am[kJN][kJN + 1];   // Schur complement during the Cholesky
+  __shared__ double Lc[kJN][kJN];       // columns of L (column-major: Lc[col][row])
+  __shared__ double nrm[kJN];
+  __shared__ int done[kJN];
+  __shared__ int piv_sh;
+  __shared__ double pivval_sh;
   __shared__ int rotated;
   __shared__ int order[kJN];
-  const int N = n + (n & 1);  // even number of players; index n is a zero dummy when n is odd
-  const int half = N / 2;
-  for (int idx = threadIdx.x; idx < kJN * kJN; idx += kJThreads) {
+  __shared__ int rank_sh;
+  __shared__ double vtmp[kJN];
+  const int tid = threadIdx.x;
+  const int lane = tid % kWave;
+  for (int idx = tid; idx < kJN * kJN; idx += kJThreads) {
     const int i = idx / kJN, j = idx % kJN;
     Am[i][j] = (i < n && j < n) ? M[i * n + j] : 0.0;
-    Vm[i][j] = (i == j) ? 1.0 : 0.0;
+    Lc[i][j] = 0.0;
   }
+  if (tid < kJN) done[tid] = (tid < n) ? 0 : 1;
+  if (tid == 0) rank_sh = n;
   __syncthreads();
+  // ---- 1. pivoted Cholesky: column k of L = A[:, p] / sqrt(A[p][p]), p = argmax remaining diagonal
+  double dmax0 = 0.0;
+  for (int i = 0; i < n; ++i) dmax0 = fmax(dmax0, Am[i][i]);
+  for (int k = 0; k < n; ++k) {
+    if (tid < kWave) {
+      double v = -1.0;
+      int idx = kJN;
+      if (lane < n && !done[lane]) { v = Am[lane][lane]; idx = lane; }
+      for (int off = 32; off >= 1; off >>= 1) {
+        const double ov = __shfl_xor(v, off);
+        const int oi = __shfl_xor(idx, off);
+        if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+      }
+      if (lane == 0) { piv_sh = idx; pivval_sh = v; }
+    }
+    __syncthreads();
+    const int p = piv_sh;
+    const double d = pivval_sh;
+    if (!(d > 1e-300 && d > 1e-30 * dmax0)) {  // remaining Schur complement is numerically zero
+      if (tid == 0) rank_sh = k;
+      break;
+    }
+    const double sd = sqrt(d);
+    if (tid < kJN) {
+      const int i = tid;
+      Lc[k][i] = (i < n && !done[i]) ? Am[i][p] / sd : 0.0;
+    }
+    __syncthreads();
+    if (tid == 0) done[p] = 1;
+    for (int idx = tid; idx < n * n; idx += kJThreads) {
+      const int i = idx / n, j = idx % n;
+      Am[i][j] -= Lc[k][i] * Lc[k][j];
+    }
+    __syncthreads();
+  }
+  const int nc = rank_sh;  // columns of L in use
+  // ---- 2. one-sided Jacobi on the nc columns of L
+  const int N = nc + (nc & 1);
+  const int half = N / 2;
+  const int g = tid / kPairLanes, sub = tid % kPairLanes;  // pair group, row block
   for (int sweep = 0; sweep < kMaxSweeps && N > 1; ++sweep) {
-    if (threadIdx.x == 0) rotated = 0;
+    if (tid == 0) rotated = 0;
     __syncthreads();
     for (int round = 0; round < N - 1; ++round) {
-      // phase 1: rotation of each disjoint pair (circle method pairing)
-      if (threadIdx.x < half) {
-        const int i = threadIdx.x;
-        const int a = (i == 0) ? 0 : ((i - 1 + round) % (N - 1)) + 1;
-        const int k2 = N - 1 - i;
-        const int b = ((k2 - 1 + round) % (N - 1)) + 1;
-        const int p = a < b ? a : b, q = a < b ? b : a;
-        const double apq = Am[p][q], app = Am[p][p], aqq = Am[q][q];
-        double c = 1.0, s = 0.0;
-        if (fabs(apq) > 1e-300 && fabs(apq) > 1e-16 * sqrt(fabs(app) * fabs(aqq))) {
-          const double tau = (aqq - app) / (2.0 * apq);
-          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + t * t);
-          s = t * c;
-          rotated = 1;
+      if (g < half) {
+        const int a = (g == 0) ? 0 : ((g - 1 + round) % (N - 1)) + 1;
+        const int b = ((N - 1 - g - 1 + round) % (N - 1)) + 1;
+        const int pc = a < b ? a : b, qc = a < b ? b : a;
+        double x[8], y[8];
+        double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          x[t] = Lc[pc][sub * 8 + t];
+          y[t] = (qc < nc) ? Lc[qc][sub * 8 + t] : 0.0;
+          al = fma(x[t], x[t], al);
+          be = fma(y[t], y[t], be);
+          ga = fma(x[t], y[t], ga);
         }
-        cs[i] = c; sn[i] = s; pp[i] = p; qq[i] = q;
-      }
-      __syncthreads();
-      // phase 2: A <- J^T A J as 2x2 blocks, V <- V J
-      for (int blk = threadIdx.x; blk < half * half; blk += kJThreads) {
-        const int P = blk / half, Qi = blk % half;
-        const int p1 = pp[P], q1 = qq[P], p2 = pp[Qi], q2 = qq[Qi];
-        const double c1 = cs[P], s1 = sn[P], c2 = cs[Qi], s2 = sn[Qi];
-        const double m11 = Am[p1][p2], m12 = Am[p1][q2], m21 = Am[q1][p2], m22 = Am[q1][q2];
-        // rows
-        const double r11 = c1 * m11 - s1 * m21, r12 = c1 * m12 - s1 * m22;
-        const double r21 = s1 * m11 + c1 * m21, r22 = s1 * m12 + c1 * m22;
-        // columns
-        double n11 = c2 * r11 - s2 * r12, n12 = s2 * r11 + c2 * r12;
-        double n21 = c2 * r21 - s2 * r22, n22 = s2 * r21 + c2 * r22;
-        if (P == Qi && s1 != 0.0) { n12 = 0.0; n21 = 0.0; }
-        Am[p1][p2] = n11; Am[p1][q2] = n12; Am[q1][p2] = n21; Am[q1][q2] = n22;
-      }
-      for (int it = threadIdx.x; it < N * half; it += kJThreads) {
-        const int x = it / half, P = it % half;
-        const int p = pp[P], q = qq[P];
-        const double c = cs[P], s = sn[P];
-        const double vp = Vm[x][p], vq = Vm[x][q];
-        Vm[x][p] = c * vp - s * vq;
-        Vm[x][q] = s * vp + c * vq;
+        // sum over the 8 lanes of the pair group (fixed butterfly order)
+        for (int off = 1; off < kPairLanes; off <<= 1) {
+          al += __shfl_xor(al, off);
+          be += __shfl_xor(be, off);
+          ga += __shfl_xor(ga, off);
+        }
+        if (fabs(ga) > 1e-300 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + t * t);
+          const double s = c * t;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            Lc[pc][sub * 8 + u] = c * x[u] - s * y[u];
+            Lc[qc][sub * 8 + u] = s * x[u] + c * y[u];
+          }
+          if (sub == 0) rotated = 1;
+        }
       }
       __syncthreads();
     }
     if (!rotated) break;
     __syncthreads();
   }
-  // order eigenvalues decreasing (ties by index)
-  if (threadIdx.x < n) {
-    const int i = threadIdx.x;
-    const double li = Am[i][i];
-    int rank = 0;
-    for (int j = 0; j < n; ++j) {
-      const double lj = Am[j][j];
-      if (lj > li || (lj == li && j < i)) ++rank;
-    }
-    order[rank] = i;
+  // ---- 3. norms, order (decreasing), normalised columns with the sign rule
+  if (tid < kJN) {
+    double s = 0.0;
+    if (tid < nc)
+      for (int i = 0; i < n; ++i) s = fma(Lc[tid][i], Lc[tid][i], s);
+    nrm[tid] = s;
   }
   __syncthreads();
-  if (evals && threadIdx.x < n) evals[threadIdx.x] = Am[order[threadIdx.x]][order[threadIdx.x]];
-  // output columns with the sign rule: largest |entry| (first on ties) positive
-  if (threadIdx.x < r) {
-    const int k = threadIdx.x, col = order[k];
+  if (tid < n) {
+    const int i = tid;
+    const double li = nrm[i];
+    int rk = 0;
+    for (int j = 0; j < n; ++j) {
+      const double lj = nrm[j];
+      if (lj > li || (lj == li && j < i)) ++rk;
+    }
+    order[rk] = i;
+  }
+  __syncthreads();
+  if (evals && tid < n) evals[tid] = nrm[order[tid]];
+  if (tid == 0) {
+    // columns beyond the numerical rank: complete with unit vectors orthogonalised
+    // against the previous columns (modified Gram-Schmidt), so V stays orthonormal
+    for (int k = 0; k < r; ++k) {
+      const int col = order[k];
+      if (nrm[col] > 0.0 && k < nc) continue;
+      for (int e = 0; e < n; ++e) {
+        double* v = vtmp;
+        for (int i = 0; i < n; ++i) v[i] = (i == e) ? 1.0 : 0.0;
+        for (int pass = 0; pass < 2; ++pass)
+          for (int kk = 0; kk < k; ++kk) {
+            const int cc = order[kk];
+            const double inv = 1.0 / sqrt(nrm[cc]);
+            double dp = 0.0;
+            for (int i = 0; i < n; ++i) dp += Lc[cc][i] * inv * v[i];
+            for (int i = 0; i < n; ++i) v[i] -= dp * Lc[cc][i] * inv;
+          }
+        double nv = 0.0;
+        for (int i = 0; i < n; ++i) nv += v[i] * v[i];
+        if (nv > 0.5) {
+          for (int i = 0; i < n; ++i) Lc[col][i] = v[i] / sqrt(nv);
+          nrm[col] = 1.0;
+          break;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (tid < r) {
+    const int k = tid, col = order[k];
+    const double inv = 1.0 / sqrt(nrm[col]);
     double best = -1.0, sgn = 1.0;
     for (int x = 0; x < n; ++x) {
-      const double v = Vm[x][col];
+      const double v = Lc[col][x];
       if (fabs(v) > best) { best = fabs(v); sgn = (v < 0.0) ? -1.0 : 1.0; }
     }
-    for (int x = 0; x < n; ++x) Vout[x * r + k] = sgn * Vm[x][col];
+    for (int x = 0; x < n; ++x) Vout[x * r + k] = sgn * inv * Lc[col][x];
   }
 }
 
@@ -236,7 +330,7 @@ hipError_t launch_mode_contract(const void* P, const void* Q, rt_dtype dt, int64
 }
 
 hipError_t launch_sym_eig_top(const double* M, int64_t n, int64_t r, double* V, double* evals, hipStream_t st) {
-  jacobi_eig_kernel<<<1, kJThreads, 0, st>>>(M, static_cast<int>(n), static_cast<int>(r), V, evals);
+  eig_onesided_kernel<<<1, kJThreads, 0, st>>>(M, static_cast<int>(n), static_cast<int>(r), V, evals);
   return hipGetLastError();
 }
 

@@ -31,6 +31,7 @@ struct QRTask {
   double* R;         // rrows x n (leading dimension n), or null
   int32_t rrows;
   int32_t f64;       // source dtype (host-side grouping only)
+  const int32_t* flag;  // null, or: run only when *flag != 0 (CholeskyQR2 fallback)
 };
 
 struct QRTaskTable {
@@ -47,6 +48,7 @@ __global__ __launch_bounds__(kQRThreads) void small_qr_kernel(QRTaskTable tab) {
   __shared__ double sh_sgn[kCols];
 
   const QRTask& T = tab.t[blockIdx.x];
+  if (T.flag && *T.flag == 0) return;
   const int lane = threadIdx.x % kWave;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int rows = T.rows, n = T.n;
@@ -177,6 +179,7 @@ struct CombineTask {
   const double* Q2;  // n x n block (ld n)
   double* Q;         // rows x n (leading dimension ldq)
   int32_t rows, n, ldq;
+  const int32_t* flag;
 };
 struct CombineTable {
   CombineTask t[kMaxTasks];
@@ -185,6 +188,7 @@ struct CombineTable {
 // Q[r][j] = sum_t Qb[r][t] Q2[t][j]
 __global__ __launch_bounds__(256) void qr_combine_kernel(CombineTable tab) {
   const CombineTask& T = tab.t[blockIdx.y];
+  if (T.flag && *T.flag == 0) return;
   const int64_t total = static_cast<int64_t>(T.rows) * T.n;
   for (int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; idx < total;
        idx += static_cast<int64_t>(gridDim.x) * 256) {
@@ -192,6 +196,155 @@ __global__ __launch_bounds__(256) void qr_combine_kernel(CombineTable tab) {
     double s = 0.0;
     for (int t = 0; t < T.n; ++t) s = fma(T.Qb[static_cast<int64_t>(r) * T.n + t], T.Q2[static_cast<int64_t>(t) * T.n + jj], s);
     T.Q[static_cast<int64_t>(r) * T.ldq + jj] = s;
+  }
+}
+
+// ------------------------------------------------------------------ CholeskyQR2
+// Fast path for well-conditioned sketches: G = Y^T Y, Y = Q1 R1 (R1 = chol(G)),
+// then the same on Q1, Q = Q1 R2^-1, R = R2 R1 (diag(R) > 0 by construction).
+// Two passes restore orthogonality to rounding level when cond(Y) is below
+// about 1e7.  A Cholesky pivot below 1e-13 of the largest diagonal entry flags
+// the job, and the Householder path (launched conditionally) recomputes it.
+constexpr int kGramRows = 64;
+
+struct CJob {
+  const void* Y;      // source (A, m, B) view (first pass) ; Q1 (m x n, binary64) in the second
+  int64_t A, m, B;
+  int32_t n;
+  double* part;       // chunks x 64 x 64 partial Gram matrices
+  int32_t chunks;
+  double* R1;         // 64 x 64 upper factor of the first pass
+  double* R2;         // second pass
+  double* Q1;         // m x n intermediate
+  double* Q;          // final m x n (ld n)
+  double* Rout;       // n x n or null
+  int32_t* flag;      // 0 = CholeskyQR2 ok, 1 = use Householder
+};
+struct CJobTable {
+  CJob t[kMaxQRJobs];
+};
+
+template <typename TY>
+__device__ __forceinline__ double cq_elem(const CJob& J, bool second, int64_t r, int j) {
+  if (second) return J.Q1[r * J.n + j];
+  const int64_t a = j / J.B, b = j - a * J.B;
+  return static_cast<double>(static_cast<const TY*>(J.Y)[a * J.m * J.B + r * J.B + b]);
+}
+
+// partial Gram of 64-row chunks: part[chunk] = Y[rows]^T Y[rows]
+template <typename TY>
+__global__ __launch_bounds__(256) void cq_gram_kernel(CJobTable tab, int second) {
+  __shared__ double sy[kGramRows][kCols + 1];
+  const CJob& J = tab.t[blockIdx.y];
+  if (static_cast<int>(blockIdx.x) >= J.chunks) return;
+  if (second && *J.flag) return;
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kGramRows;
+  for (int idx = threadIdx.x; idx < kGramRows * kCols; idx += 256) {
+    const int rr = idx / kCols, j = idx % kCols;
+    const int64_t r = r0 + rr;
+    sy[rr][j] = (r < J.m && j < J.n) ? cq_elem<TY>(J, second != 0, r, j) : 0.0;
+  }
+  __syncthreads();
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  double acc[4][4] = {};
+  for (int rr = 0; rr < kGramRows; ++rr) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) { a[u] = sy[rr][ty * 4 + u]; b[u] = sy[rr][tx * 4 + u]; }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+  }
+  double* out = J.part + static_cast<int64_t>(blockIdx.x) * kCols * kCols;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) out[(ty * 4 + u) * kCols + tx * 4 + v] = acc[u][v];
+}
+
+// sum the partials (fixed order) and factor G = R^T R (upper R)
+__global__ __launch_bounds__(256) void cq_chol_kernel(CJobTable tab, int second) {
+  __shared__ double G[kCols][kCols + 1];
+  __shared__ int bad;
+  const CJob& J = tab.t[blockIdx.x];
+  if (second && *J.flag) return;
+  const int n = J.n;
+  for (int idx = threadIdx.x; idx < kCols * kCols; idx += 256) {
+    double s = 0.0;
+    for (int c = 0; c < J.chunks; ++c) s += J.part[static_cast<int64_t>(c) * kCols * kCols + idx];
+    G[idx / kCols][idx % kCols] = s;
+  }
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  double dmax = 0.0;
+  for (int i = 0; i < n; ++i) dmax = fmax(dmax, G[i][i]);
+  for (int k = 0; k < n; ++k) {
+    const double d = G[k][k];
+    if (!(d > 1e-13 * dmax) || !(dmax > 0.0)) {
+      if (threadIdx.x == 0) bad = 1;
+      break;
+    }
+    const double rkk = sqrt(d);
+    __syncthreads();
+    // row k of R: G[k][j] / rkk for j >= k (stored in place)
+    if (static_cast<int>(threadIdx.x) >= k && static_cast<int>(threadIdx.x) < n)
+      G[k][threadIdx.x] = (static_cast<int>(threadIdx.x) == k) ? rkk : G[k][threadIdx.x] / rkk;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < (n - k - 1) * (n - k - 1); idx += 256) {
+      const int i = k + 1 + idx / (n - k - 1), j = k + 1 + idx % (n - k - 1);
+      G[i][j] -= G[k][i] * G[k][j];
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  double* R = second ? J.R2 : J.R1;
+  for (int idx = threadIdx.x; idx < kCols * kCols; idx += 256) {
+    const int i = idx / kCols, j = idx % kCols;
+    R[idx] = (i < n && j < n && j >= i) ? G[i][j] : 0.0;
+  }
+  if (threadIdx.x == 0) {
+    if (!second) *J.flag = bad;
+    else if (bad) *J.flag = 1;
+  }
+}
+
+// row solves q R = y (forward substitution, R upper); pass 1 writes Q1, pass 2 writes Q
+template <typename TY>
+__global__ __launch_bounds__(256) void cq_solve_kernel(CJobTable tab, int second) {
+  __shared__ double R[kCols][kCols + 1];
+  const CJob& J = tab.t[blockIdx.y];
+  if (*J.flag) return;
+  const int n = J.n;
+  const double* Rs = second ? J.R2 : J.R1;
+  for (int idx = threadIdx.x; idx < kCols * kCols; idx += 256) R[idx / kCols][idx % kCols] = Rs[idx];
+  __syncthreads();
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (r >= J.m) return;
+  double q[kCols];
+#pragma unroll
+  for (int j = 0; j < kCols; ++j) {
+    if (j < n) {
+      double y = cq_elem<TY>(J, second != 0, r, j);
+#pragma unroll
+      for (int t = 0; t < j; ++t) y = fma(-q[t], R[t][j], y);
+      q[j] = y / R[j][j];
+    } else {
+      q[j] = 0.0;
+    }
+  }
+  double* out = second ? J.Q : J.Q1;
+#pragma unroll
+  for (int j = 0; j < kCols; ++j)
+    if (j < n) out[r * n + j] = q[j];
+  // R = R2 R1 (upper), written once by block 0 of pass 2
+  if (second && J.Rout && blockIdx.x == 0) {
+    for (int idx = threadIdx.x; idx < n * n; idx += 256) {
+      const int i = idx / n, j = idx % n;
+      double s = 0.0;
+      for (int t = i; t <= j; ++t) s = fma(J.R2[i * kCols + t], J.R1[t * kCols + j], s);
+      J.Rout[idx] = (j >= i) ? s : 0.0;
+    }
   }
 }
 
@@ -205,6 +358,7 @@ struct Mat {
   int ldq, qcols;
   double* R;  // rrows x n or null
   int rrows;
+  const int32_t* flag;
 };
 
 struct Bump {
@@ -230,6 +384,7 @@ hipError_t qr_level(std::vector<Mat>& mats, bool launch, Bump& ws, hipStream_t s
       t.src = M.src; t.A = M.A; t.m = M.m; t.B = M.B; t.row0 = 0; t.rows = static_cast<int32_t>(M.m);
       t.n = M.n; t.Q = M.Q; t.ldq = M.ldq; t.qcols = M.qcols; t.R = M.R; t.rrows = M.rrows;
       t.f64 = M.f64 ? 1 : 0;
+      t.flag = M.flag;
       direct.push_back(t);
     } else {
       const int nb = static_cast<int>(ceil_div(M.m, kRowsMax));
@@ -249,6 +404,7 @@ hipError_t qr_level(std::vector<Mat>& mats, bool launch, Bump& ws, hipStream_t s
         t.R = p.Rs ? p.Rs + static_cast<int64_t>(b) * M.n * M.n : nullptr;
         t.rrows = M.n;
         t.f64 = M.f64 ? 1 : 0;
+        t.flag = M.flag;
         direct.push_back(t);
       }
       pend.push_back(p);
@@ -284,6 +440,7 @@ hipError_t qr_level(std::vector<Mat>& mats, bool launch, Bump& ws, hipStream_t s
     q2[i] = static_cast<double*>(ws.take(static_cast<size_t>(U.m) * U.n * sizeof(double)));
     U.Q = q2[i]; U.ldq = U.n; U.qcols = U.n;
     U.R = p.mat.R; U.rrows = p.mat.rrows;
+    U.flag = p.mat.flag;
     upper.push_back(U);
   }
   hipError_t e = qr_level(upper, launch, ws, st);
@@ -300,6 +457,7 @@ hipError_t qr_level(std::vector<Mat>& mats, bool launch, Bump& ws, hipStream_t s
       t.Q2 = q2[i] ? q2[i] + static_cast<int64_t>(b) * p.mat.n * p.mat.n : nullptr;
       t.Q = p.mat.Q ? p.mat.Q + row0 * p.mat.ldq : nullptr;
       t.ldq = p.mat.ldq;
+      t.flag = p.mat.flag;
       combine.push_back(t);
     }
   }
@@ -316,8 +474,14 @@ hipError_t qr_level(std::vector<Mat>& mats, bool launch, Bump& ws, hipStream_t s
   return hipSuccess;
 }
 
-std::vector<Mat> mats_of(const QRJob* jobs, int count, rt_dtype ydt) {
-  std::vector<Mat> v;
+// Plans (and, when launch is true, enqueues) the QR of a set of jobs:
+// CholeskyQR2 with a Householder fallback for m >= n, Householder otherwise.
+hipError_t qr_plan(const QRJob* jobs, int count, rt_dtype ydt, bool launch, Bump& ws, hipStream_t st) {
+  std::vector<Mat> hh;
+  CJobTable tab;
+  int nc = 0;
+  int max_chunks = 1;
+  int64_t max_m = 1;
   for (int i = 0; i < count; ++i) {
     Mat M;
     M.src = jobs[i].Y; M.f64 = (ydt == RT_F64);
@@ -326,24 +490,55 @@ std::vector<Mat> mats_of(const QRJob* jobs, int count, rt_dtype ydt) {
     const int c = static_cast<int>(M.m < M.n ? M.m : M.n);
     M.Q = jobs[i].Q; M.ldq = c; M.qcols = c;
     M.R = jobs[i].R; M.rrows = c;
-    v.push_back(M);
+    M.flag = nullptr;
+    if (M.m >= M.n && nc < kMaxQRJobs) {
+      CJob J;
+      J.Y = M.src; J.A = M.A; J.m = M.m; J.B = M.B; J.n = M.n;
+      J.chunks = static_cast<int32_t>(ceil_div(M.m, kGramRows));
+      J.part = static_cast<double*>(ws.take(static_cast<size_t>(J.chunks) * kCols * kCols * sizeof(double)));
+      J.R1 = static_cast<double*>(ws.take(kCols * kCols * sizeof(double)));
+      J.R2 = static_cast<double*>(ws.take(kCols * kCols * sizeof(double)));
+      J.Q1 = static_cast<double*>(ws.take(static_cast<size_t>(M.m) * M.n * sizeof(double)));
+      J.flag = static_cast<int32_t*>(ws.take(sizeof(int32_t)));
+      J.Q = M.Q; J.Rout = M.R;
+      M.flag = J.flag;
+      tab.t[nc++] = J;
+      if (J.chunks > max_chunks) max_chunks = J.chunks;
+      if (M.m > max_m) max_m = M.m;
+    }
+    hh.push_back(M);
   }
-  return v;
+  if (launch && nc > 0) {
+    const dim3 g1(max_chunks, nc), g3(static_cast<unsigned>(ceil_div(max_m, 256)), nc);
+    if (ydt == RT_F64) {
+      cq_gram_kernel<double><<<g1, 256, 0, st>>>(tab, 0);
+      cq_chol_kernel<<<nc, 256, 0, st>>>(tab, 0);
+      cq_solve_kernel<double><<<g3, 256, 0, st>>>(tab, 0);
+    } else {
+      cq_gram_kernel<float><<<g1, 256, 0, st>>>(tab, 0);
+      cq_chol_kernel<<<nc, 256, 0, st>>>(tab, 0);
+      cq_solve_kernel<float><<<g3, 256, 0, st>>>(tab, 0);
+    }
+    cq_gram_kernel<double><<<g1, 256, 0, st>>>(tab, 1);
+    cq_chol_kernel<<<nc, 256, 0, st>>>(tab, 1);
+    cq_solve_kernel<double><<<g3, 256, 0, st>>>(tab, 1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return qr_level(hh, launch, ws, st);
 }
 
 }  // namespace
 
 size_t qr_ws(const QRJob* jobs, int count) {
-  std::vector<Mat> mats = mats_of(jobs, count, RT_F32);
   Bump b{nullptr, 0};
-  (void)qr_level(mats, false, b, nullptr);
+  (void)qr_plan(jobs, count, RT_F32, false, b, nullptr);
   return align256(b.off);
 }
 
 hipError_t launch_qr(const QRJob* jobs, int count, rt_dtype ydt, void* ws, hipStream_t st) {
-  std::vector<Mat> mats = mats_of(jobs, count, ydt);
   Bump b{static_cast<char*>(ws), 0};
-  return qr_level(mats, true, b, st);
+  return qr_plan(jobs, count, ydt, true, b, st);
 }
 
 }  // namespace rt

@@ -121,6 +121,129 @@ __global__ __launch_bounds__(256) void sum_parts_kernel(const TC* __restrict__ p
   }
 }
 
+// ------------------------------------------------------------------ bfloat16 on matrix cores
+// Same two contractions on MFMA (v_mfma_f32_16x16x32_bf16, binary32 accumulation):
+//  * W^T tile: out[c][q] = sum_p PhiP[c][p] X[p][q].  Each lane loads an 8 x 8 block
+//    (8 rows, 8 consecutive columns, 16 bytes per row) and re-packs it in registers
+//    into 8 operands holding 8 consecutive p of one column.
+//  * Z tile: out[p][c] = sum_q X[p][q] PhiQ[c][q]: X rows are the A operand
+//    directly (8 consecutive q per lane), read a second time from L1.
+// A wave handles 32-row blocks over a range of up to 512 columns; rows beyond P
+// and operand rows beyond s are zero.  Requires P % 8 == 0, Q % 8 == 0, s <= 8.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kZWColsMfma = 512;
+
+__device__ __forceinline__ u32x4 ld16(const bf16_t* p) { return *reinterpret_cast<const u32x4*>(p); }
+
+__global__ __launch_bounds__(kZWThreads) void sketch_zw_bf16_mfma_kernel(
+    const bf16_t* __restrict__ X, int64_t A, int64_t P, int64_t Q, const bf16_t* __restrict__ phiP, int sP,
+    const bf16_t* __restrict__ phiQ, int sQ, int64_t rows_per_block, int qblocks, int pblocks,
+    float* __restrict__ Zo, float* __restrict__ Wo) {
+  extern __shared__ unsigned char zw_smem[];
+  float* sW = reinterpret_cast<float*>(zw_smem);  // [waves][sP][512]
+  const int lane = threadIdx.x % kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int64_t blk = blockIdx.x;
+  const int qblk = static_cast<int>(blk % qblocks);
+  const int64_t rest = blk / qblocks;
+  const int pblk = static_cast<int>(rest % pblocks);
+  const int64_t a = rest / pblocks;
+  const int64_t q0 = static_cast<int64_t>(qblk) * kZWColsMfma;
+  const int64_t qend = (q0 + kZWColsMfma < Q) ? q0 + kZWColsMfma : Q;
+  const bool needZ = Zo != nullptr, needW = Wo != nullptr;
+  const int li = lane % 16, kg = lane / 16;
+  const int64_t pbeg = static_cast<int64_t>(pblk) * rows_per_block;
+  const int64_t pend = (pbeg + rows_per_block < P) ? pbeg + rows_per_block : P;
+  const bf16_t* xa = X + a * P * Q;
+  float* zrow = needZ ? Zo + (static_cast<int64_t>(qblk) * A + a) * P * sQ : nullptr;
+
+  f32x4 wacc[4][8];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) wacc[u][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int64_t pb = pbeg + 32 * wave; pb < pend; pb += 32 * kZWWaves) {
+    // PhiP operand: row c = li, columns pb + 8 kg .. + 7 (8-row groups lie wholly inside
+    // or outside [pbeg, pend) because P % 8 == 0 and blocks are multiples of 32 rows)
+    const int64_t pc = pb + 8 * kg;
+    const u32x4 pp = (needW && pc < pend) ? ld16(phiP + static_cast<int64_t>(li) * P + pc) : u32x4{0u, 0u, 0u, 0u};
+    f32x4 zacc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t qb = q0 + 128 * u;
+      if (qb >= qend) break;
+      if (needW) {
+        // 8 x 8 block: rows pb + 8 kg + t, columns qb + 8 li .. + 7
+        const int64_t qc = qb + 8 * li;
+        u32x4 r[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int64_t p = pb + 8 * kg + t;
+          r[t] = (p < pend && qc < qend) ? ld16(xa + p * Q + qc) : u32x4{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          u32x4 op;
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            const uint32_t lo = r[2 * w][c / 2], hi = r[2 * w + 1][c / 2];
+            op[w] = (c % 2 == 0) ? ((lo & 0xffffu) | (hi << 16)) : ((lo >> 16) | (hi & 0xffff0000u));
+          }
+          wacc[u][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, pp),
+                                                                __builtin_bit_cast(bf16x8, op), wacc[u][c], 0, 0, 0);
+        }
+      }
+      if (needZ) {
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const int64_t qk = qb + 32 * ks + 8 * kg;
+          const u32x4 bq = (qk < qend) ? ld16(phiQ + static_cast<int64_t>(li) * Q + qk) : u32x4{0u, 0u, 0u, 0u};
+#pragma unroll
+          for (int mt = 0; mt < 2; ++mt) {
+            const int64_t p = pb + 16 * mt + li;
+            const u32x4 xr = (p < pend && qk < qend) ? ld16(xa + p * Q + qk) : u32x4{0u, 0u, 0u, 0u};
+            zacc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, xr),
+                                                                __builtin_bit_cast(bf16x8, bq), zacc[mt], 0, 0, 0);
+          }
+        }
+      }
+    }
+    if (needZ && li < sQ) {
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t p = pb + 16 * mt + 4 * kg + v;
+          if (p < pend) zrow[p * sQ + li] = zacc[mt][v];
+        }
+    }
+  }
+  if (!needW) return;
+  // wave partials of W -> LDS -> fixed-order sum over the 4 waves
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int cp = 4 * kg + v;  // output row (subrank index)
+        if (cp < sP) sW[(wave * sP + cp) * kZWColsMfma + 128 * u + 8 * li + c] = wacc[u][c][v];
+      }
+  __syncthreads();
+  float* wout = Wo + (static_cast<int64_t>(pblk) * A + a) * sP * Q;
+  for (int idx = threadIdx.x; idx < sP * kZWColsMfma; idx += kZWThreads) {
+    const int c = idx / kZWColsMfma, col = idx % kZWColsMfma;
+    const int64_t q = q0 + col;
+    if (q >= qend) continue;
+    float s = 0.f;
+    for (int w = 0; w < kZWWaves; ++w) s += sW[(w * sP + c) * kZWColsMfma + col];
+    wout[c * Q + q] = s;
+  }
+}
+
 int nq_max(rt_dtype xdt) { return xdt == RT_F64 ? 4 : 8; }
 
 int pick_nq(rt_dtype xdt, int64_t Q) {
@@ -167,16 +290,18 @@ bool sketch_zw_ok(rt_dtype, int64_t sP, int64_t sQ) { return sP >= 1 && sQ >= 1 
 ZWPlan sketch_zw_plan(rt_dtype xdt, int64_t A, int64_t P, int64_t Q, int64_t sP, int64_t sQ, bool needZ,
                       bool needW) {
   ZWPlan p;
+  p.mfma = (xdt == RT_BF16) && (P % 8 == 0) && (Q % 8 == 0) && P >= 32;
   const int nq = pick_nq(xdt, Q);
-  p.qblocks = ceil_div(Q, 64 * nq);
-  if (!needZ) p.qblocks = ceil_div(Q, 64 * nq);
+  p.qblocks = p.mfma ? ceil_div(Q, kZWColsMfma) : ceil_div(Q, 64 * nq);
   int64_t pb = 1;
   const int64_t target = 2048;
   if (A * p.qblocks < target) pb = ceil_div(target, A * p.qblocks);
-  const int64_t maxpb = ceil_div(P, 16);  // keep at least 16 rows per block
+  const int64_t rows_min = p.mfma ? 128 : 16;  // keep at least this many rows per block
+  const int64_t maxpb = ceil_div(P, rows_min);
   if (pb > maxpb) pb = maxpb;
   if (pb < 1) pb = 1;
   p.rows_per_block = ceil_div(P, pb);
+  if (p.mfma) p.rows_per_block = ceil_div(p.rows_per_block, 32) * 32;
   p.pblocks = ceil_div(P, p.rows_per_block);
   const size_t esz = (xdt == RT_F64) ? 8 : 4;
   size_t ws = 0;
@@ -187,8 +312,8 @@ ZWPlan sketch_zw_plan(rt_dtype xdt, int64_t A, int64_t P, int64_t Q, int64_t sP,
 }
 
 hipError_t launch_sketch_zw(const void* X, rt_dtype xdt, int64_t A, int64_t P, int64_t Q, const void* phiP, int64_t sP,
-                            const void* phiQ, int64_t sQ, void* Z, void* W, const ZWPlan& plan, void* ws,
-                            hipStream_t st) {
+                            const void* phiQ, int64_t sQ, const void* phiP16, const void* phiQ16, void* Z, void* W,
+                            const ZWPlan& plan, void* ws, hipStream_t st) {
   const int nq = pick_nq(xdt, Q);
   const size_t esz = (xdt == RT_F64) ? 8 : 4;
   char* wsp = static_cast<char*>(ws);
@@ -204,6 +329,15 @@ hipError_t launch_sketch_zw(const void* X, rt_dtype xdt, int64_t A, int64_t P, i
   }
   hipError_t e;
   const int isP = static_cast<int>(sP), isQ = static_cast<int>(sQ);
+  if (plan.mfma) {
+    const int64_t blocks = A * plan.pblocks * plan.qblocks;
+    const size_t shmem = W ? static_cast<size_t>(kZWWaves) * sP * kZWColsMfma * sizeof(float) : 0;
+    sketch_zw_bf16_mfma_kernel<<<static_cast<unsigned>(blocks), kZWThreads, shmem, st>>>(
+        static_cast<const bf16_t*>(X), A, P, Q, static_cast<const bf16_t*>(phiP16), isP,
+        static_cast<const bf16_t*>(phiQ16), isQ, plan.rows_per_block, static_cast<int>(plan.qblocks),
+        static_cast<int>(plan.pblocks), static_cast<float*>(zdst), static_cast<float*>(wdst));
+    e = hipGetLastError();
+  } else
   switch (xdt) {
     case RT_F64:
       e = zw_dispatch<double, double>(static_cast<const double*>(X), A, P, Q, static_cast<const double*>(phiP), isP,

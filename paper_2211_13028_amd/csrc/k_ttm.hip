@@ -24,10 +24,12 @@ constexpr int kGenKC = 64;
 template <typename TX, typename TC, int MT>
 __global__ __launch_bounds__(kGenThreads) void ttm_generic_kernel(const TX* __restrict__ X, int64_t A, int64_t K,
                                                                   int64_t B, const TC* __restrict__ M, int64_t m,
-                                                                  TC* __restrict__ Y) {
+                                                                  int64_t kper, TC* __restrict__ Y) {
   __shared__ TC sM[MT][kGenKC];
   const int64_t col = static_cast<int64_t>(blockIdx.x) * kGenThreads + threadIdx.x;
   const int64_t i0 = static_cast<int64_t>(blockIdx.y) * MT;
+  const int64_t kb = static_cast<int64_t>(blockIdx.z) * kper;
+  const int64_t ke = (kb + kper < K) ? kb + kper : K;
   const bool active = col < A * B;
   const int64_t a = active ? col / B : 0;
   const int64_t b = active ? col - a * B : 0;
@@ -35,15 +37,15 @@ __global__ __launch_bounds__(kGenThreads) void ttm_generic_kernel(const TX* __re
 #pragma unroll
   for (int ii = 0; ii < MT; ++ii) acc[ii] = TC(0);
   const TX* xp = X + a * K * B + b;
-  for (int64_t k0 = 0; k0 < K; k0 += kGenKC) {
+  for (int64_t k0 = kb; k0 < ke; k0 += kGenKC) {
     __syncthreads();
     for (int t = threadIdx.x; t < MT * kGenKC; t += kGenThreads) {
       const int ii = t / kGenKC, kk = t % kGenKC;
-      sM[ii][kk] = (i0 + ii < m && k0 + kk < K) ? M[(i0 + ii) * K + k0 + kk] : TC(0);
+      sM[ii][kk] = (i0 + ii < m && k0 + kk < ke) ? M[(i0 + ii) * K + k0 + kk] : TC(0);
     }
     __syncthreads();
     if (active) {
-      const int kend = static_cast<int>((K - k0) < kGenKC ? (K - k0) : kGenKC);
+      const int kend = static_cast<int>((ke - k0) < kGenKC ? (ke - k0) : kGenKC);
       for (int kk = 0; kk < kend; ++kk) {
         const TC x = static_cast<TC>(Load<TX>::get(xp, (k0 + kk) * B));
 #pragma unroll
@@ -52,25 +54,53 @@ __global__ __launch_bounds__(kGenThreads) void ttm_generic_kernel(const TX* __re
     }
   }
   if (active) {
+    TC* y = Y + static_cast<int64_t>(blockIdx.z) * A * m * B;
 #pragma unroll
     for (int ii = 0; ii < MT; ++ii)
-      if (i0 + ii < m) Y[a * m * B + (i0 + ii) * B + b] = acc[ii];
+      if (i0 + ii < m) y[a * m * B + (i0 + ii) * B + b] = acc[ii];
   }
 }
 
+template <typename TC>
+__global__ __launch_bounds__(256) void generic_sum_kernel(const TC* __restrict__ part, int ksplit, int64_t n,
+                                                          TC* __restrict__ Y) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * 256;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n; i += stride) {
+    TC s = part[i];
+    for (int k = 1; k < ksplit; ++k) s += part[k * n + i];
+    Y[i] = s;
+  }
+}
+
+// split K over grid.z when there are too few output columns to fill the chip
+int generic_ksplit(int64_t A, int64_t K, int64_t B) {
+  const int64_t cols = A * B;
+  int ks = 1;
+  while (cols * ks < 131072 && K / (2 * ks) >= 64 && ks < 64) ks *= 2;
+  return ks;
+}
+
 template <typename TX, typename TC>
-hipError_t generic_dispatch(const TX* X, int64_t A, int64_t K, int64_t B, const TC* M, int64_t m, TC* Y,
+hipError_t generic_dispatch(const TX* X, int64_t A, int64_t K, int64_t B, const TC* M, int64_t m, TC* Y, TC* ws,
                             hipStream_t st) {
   const int64_t cols = A * B;
   const unsigned gx = static_cast<unsigned>(ceil_div(cols, kGenThreads));
+  const int ks = generic_ksplit(A, K, B);
+  const int64_t kper = ceil_div(K, ks);
+  TC* out = (ks > 1) ? ws : Y;
   if (m <= 4) {
-    ttm_generic_kernel<TX, TC, 4><<<dim3(gx, 1), kGenThreads, 0, st>>>(X, A, K, B, M, m, Y);
+    ttm_generic_kernel<TX, TC, 4><<<dim3(gx, 1, ks), kGenThreads, 0, st>>>(X, A, K, B, M, m, kper, out);
   } else if (m <= 8) {
-    ttm_generic_kernel<TX, TC, 8><<<dim3(gx, 1), kGenThreads, 0, st>>>(X, A, K, B, M, m, Y);
+    ttm_generic_kernel<TX, TC, 8><<<dim3(gx, 1, ks), kGenThreads, 0, st>>>(X, A, K, B, M, m, kper, out);
   } else {
     const unsigned gy = static_cast<unsigned>(ceil_div(m, 16));
-    ttm_generic_kernel<TX, TC, 16><<<dim3(gx, gy), kGenThreads, 0, st>>>(X, A, K, B, M, m, Y);
+    ttm_generic_kernel<TX, TC, 16><<<dim3(gx, gy, ks), kGenThreads, 0, st>>>(X, A, K, B, M, m, kper, out);
   }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || ks == 1) return e;
+  const int64_t n = A * m * B;
+  const unsigned g2 = static_cast<unsigned>(ceil_div(n, 256) > 4096 ? 4096 : ceil_div(n, 256));
+  generic_sum_kernel<TC><<<g2, 256, 0, st>>>(out, ks, n, Y);
   return hipGetLastError();
 }
 
@@ -266,22 +296,30 @@ MfmaPlan mfma_plan(rt_dtype xdt, int64_t A, int64_t K, int64_t B) {
 
 }  // namespace
 
+size_t ttm_generic_ws(rt_dtype xdt, int64_t A, int64_t K, int64_t B, int64_t m) {
+  const int ks = generic_ksplit(A, K, B);
+  if (ks == 1) return 0;
+  return align256(static_cast<size_t>(ks) * A * m * B * (xdt == RT_F64 ? 8 : 4));
+}
+
 hipError_t launch_ttm_generic(const void* X, rt_dtype xdt, int64_t A, int64_t K, int64_t B, const void* M,
-                              int64_t m, void* Y, hipStream_t st) {
+                              int64_t m, void* Y, void* ws, hipStream_t st) {
   if (A * B == 0 || m == 0) return hipSuccess;
   switch (xdt) {
     case RT_F64:
       return generic_dispatch<double, double>(static_cast<const double*>(X), A, K, B,
-                                              static_cast<const double*>(M), m, static_cast<double*>(Y), st);
+                                              static_cast<const double*>(M), m, static_cast<double*>(Y),
+                                              static_cast<double*>(ws), st);
     case RT_F32:
       return generic_dispatch<float, float>(static_cast<const float*>(X), A, K, B, static_cast<const float*>(M),
-                                            m, static_cast<float*>(Y), st);
+                                            m, static_cast<float*>(Y), static_cast<float*>(ws), st);
     case RT_BF16:
       return generic_dispatch<bf16_t, float>(static_cast<const bf16_t*>(X), A, K, B,
-                                             static_cast<const float*>(M), m, static_cast<float*>(Y), st);
+                                             static_cast<const float*>(M), m, static_cast<float*>(Y),
+                                             static_cast<float*>(ws), st);
     case RT_F8E4M3:
       return generic_dispatch<f8_t, float>(static_cast<const f8_t*>(X), A, K, B, static_cast<const float*>(M), m,
-                                           static_cast<float*>(Y), st);
+                                           static_cast<float*>(Y), static_cast<float*>(ws), st);
   }
   return hipErrorInvalidValue;
 }

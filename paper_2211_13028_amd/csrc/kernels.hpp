@@ -32,16 +32,21 @@ hipError_t launch_sq_residual(const void* a, const void* b, void* r, rt_dtype dt
 // ------------------------------------------------------------------ k_ttm.hip
 // Y[a, i, b] = sum_k M[i*K + k] * X[a, k, b] for i < m.
 //  X dtype xdt; M and Y in the compute type: binary64 if xdt == RT_F64, else binary32.
+//  When A*B is small the contraction is split over K and `ws` (ttm_generic_ws bytes)
+//  holds the partial sums, added in a fixed order.
+size_t ttm_generic_ws(rt_dtype xdt, int64_t A, int64_t K, int64_t B, int64_t m);
 hipError_t launch_ttm_generic(const void* X, rt_dtype xdt, int64_t A, int64_t K, int64_t B,
-                              const void* M, int64_t m, void* Y, hipStream_t st);
+                              const void* M, int64_t m, void* Y, void* ws, hipStream_t st);
 
 // MFMA path for X in binary32 or bfloat16 (binary32 accumulation, binary32 output).
 //  Operand Mop prepared by launch_prep_matrix with store = xdt (F32 or BF16),
 //  m_pad = ttm_mfma_mpad(m).  Requires ttm_mfma_ok().
+//  Split-K partial sums use `ws` (ttm_mfma_ws bytes) when the output is too small to fill the chip.
 bool ttm_mfma_ok(rt_dtype xdt, int64_t A, int64_t K, int64_t B, int64_t m);
 int64_t ttm_mfma_mpad(int64_t m);
-hipError_t launch_ttm_mfma(const void* X, rt_dtype xdt, int64_t A, int64_t K, int64_t B,
-                           const void* Mop, int64_t m, float* Y, hipStream_t st);
+size_t ttm_mfma_ws(rt_dtype xdt, int64_t A, int64_t K, int64_t B, int64_t m);
+hipError_t launch_ttm_mfma_ws(const void* X, rt_dtype xdt, int64_t A, int64_t K, int64_t B,
+                              const void* Mop, int64_t m, float* Y, void* ws, hipStream_t st);
 
 // ------------------------------------------------------------------ k_sketch.hip
 // First level of the sketch dimension tree over X viewed as (A, P, Q):
@@ -50,16 +55,20 @@ hipError_t launch_ttm_mfma(const void* X, rt_dtype xdt, int64_t A, int64_t K, in
 // phiP/phiQ: compute type (binary64 for F64 X, else binary32 holding values
 // already rounded to X's dtype), row-major sP x P and sQ x Q.
 // Either output may be skipped (null).  Z/W in the compute type.
+// bfloat16 X with P, Q multiples of 8 runs on matrix cores (plan.mfma) and also
+// needs phiP16 / phiQ16: the factors as bfloat16, zero-padded to 16 rows.
 struct ZWPlan {
   int64_t qblocks, pblocks, rows_per_block;
   size_t ws_bytes;
+  bool mfma;
 };
 ZWPlan sketch_zw_plan(rt_dtype xdt, int64_t A, int64_t P, int64_t Q, int64_t sP, int64_t sQ,
                       bool needZ, bool needW);
 bool sketch_zw_ok(rt_dtype xdt, int64_t sP, int64_t sQ);
 hipError_t launch_sketch_zw(const void* X, rt_dtype xdt, int64_t A, int64_t P, int64_t Q,
-                            const void* phiP, int64_t sP, const void* phiQ, int64_t sQ, void* Z,
-                            void* W, const ZWPlan& plan, void* ws, hipStream_t st);
+                            const void* phiP, int64_t sP, const void* phiQ, int64_t sQ,
+                            const void* phiP16, const void* phiQ16, void* Z, void* W,
+                            const ZWPlan& plan, void* ws, hipStream_t st);
 
 // ------------------------------------------------------------------ k_qr.hip
 // Thin Householder QR (binary64) of matrices given as (A, m, B) views:

@@ -92,7 +92,8 @@ def test_workspace_queries_without_gpu():
     assert big % 256 == 0 and big > 49 * 1024 * 512 * 4
     assert L.rtucker_decompose_workspace(ctypes.byref(X), None, r, 8, None, 1, ctypes.byref(nb)) == 0
     assert L.rtucker_qr_workspace(1024, 49, ctypes.byref(nb)) == 0 and nb.value > 0
-    assert L.rtucker_qr_workspace(200, 49, ctypes.byref(nb)) == 0 and nb.value == 0
+    assert L.rtucker_qr_workspace(200, 49, ctypes.byref(nb)) == 0 and nb.value > 0
+    assert L.rtucker_qr_workspace(40, 60, ctypes.byref(nb)) == 0 and nb.value == 0  # wide: no workspace
     assert L.rtucker_qr_workspace(100, 65, ctypes.byref(nb)) == -2
     l = (ctypes.c_int64 * 3)(49, 49, 49)
     assert L.rtucker_core_workspace(ctypes.byref(X), l, 7, ctypes.byref(nb)) == 0 and nb.value > 49 * 1024 * 512 * 4
