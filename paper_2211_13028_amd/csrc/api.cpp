@@ -27,6 +27,13 @@ struct Ctx {
   hipStream_t st;
   hipError_t err = hipSuccess;
   size_t peak = 0;
+  std::vector<PrepTask> pending;  // operand roundings not yet launched (one batched launch)
+  void flush() {
+    if (!pending.empty()) {
+      if (!dry) chk(launch_prep_batch(pending.data(), static_cast<int>(pending.size()), st));
+      pending.clear();
+    }
+  }
   void* take(size_t bytes) {
     if (bytes == 0) return nullptr;
     const size_t o = align256(off);
@@ -93,12 +100,12 @@ void* prep(Ctx& c, const double* src, int64_t m, int64_t K, bool trans, rt_dtype
            int64_t m_pad = 0) {
   if (m_pad < m) m_pad = m;
   void* dst = c.take(static_cast<size_t>(m_pad) * K * dtype_size(store));
-  if (!c.dry) c.chk(launch_prep_matrix(src, m, K, trans, round_to, store, m_pad, dst, c.st));
+  if (!c.dry) c.pending.push_back(PrepTask{src, m, K, m_pad, trans, round_to, store, dst});
   return dst;
 }
 
-// T x_k M, M: m x dims[k] row-major in the compute type of T
-Ten ttm(Ctx& c, const Ten& T, int k, const void* M, int64_t m, void* dst = nullptr) {
+// T x_k M, M: m x dims[k] row-major (or dims[k] x m with mtrans) in the compute type of T
+Ten ttm(Ctx& c, const Ten& T, int k, const void* M, int64_t m, void* dst = nullptr, bool mtrans = false) {
   Ten out;
   out.dims = T.dims;
   out.dims[k] = m;
@@ -107,7 +114,8 @@ Ten ttm(Ctx& c, const Ten& T, int k, const void* M, int64_t m, void* dst = nullp
   void* y = dst ? dst : c.take(static_cast<size_t>(A) * m * B * dtype_size(out.dt));
   out.p = y;
   void* w = c.take(ttm_generic_ws(T.dt, A, K, B, m));
-  if (!c.dry) c.chk(launch_ttm_generic(T.p, T.dt, A, K, B, M, m, y, w, c.st));
+  c.flush();
+  if (!c.dry) c.chk(launch_ttm_generic(T.p, T.dt, A, K, B, M, m, y, w, c.st, mtrans));
   return out;
 }
 
@@ -149,6 +157,7 @@ void sketch_impl(Ctx& c, const Ten& X, const double* const* phi, const int64_t* 
       if (needW) p16 = prep(c, phi ? phi[S] : nullptr, s[S], P, false, RT_BF16, RT_BF16, 16);
       if (needZ) q16 = prep(c, phi ? phi[L] : nullptr, s[L], Q, false, RT_BF16, RT_BF16, 16);
     }
+    c.flush();
     if (!c.dry)
       c.chk(launch_sketch_zw(X.p, X.dt, A0, P, Q, needW ? op[S] : nullptr, s[S], needZ ? op[L] : nullptr, s[L],
                              p16, q16, const_cast<void*>(Z.p), const_cast<void*>(W.p), plan, zws, c.st));
@@ -181,29 +190,49 @@ Ten core_impl(Ctx& c, const Ten& X, const double* const* U, const int64_t* l, ui
   for (int k = 0; k < d; ++k)
     if (mask >> k & 1u) order.push_back(k);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return X.dims[a] > X.dims[b]; });
-  Ten cur = X;
+  // plan every contraction first so that all operand roundings go out in one launch
+  struct Step { int k; int64_t A, K, B, m; rt_dtype in_dt; bool mfma; const void* op; void* y; void* w; };
+  std::vector<Step> steps;
+  std::vector<int64_t> dims = X.dims;
+  rt_dtype cur_dt = X.dt;
   for (size_t idx = 0; idx < order.size(); ++idx) {
     const int k = order[idx];
     const bool last = idx + 1 == order.size();
-    const int64_t A = cur.before(k), K = cur.dims[k], B = cur.after(k), m = l[k];
-    const rt_dtype ct = ctype(cur.dt);
+    Step st;
+    st.k = k;
+    st.A = 1; for (int i = 0; i < k; ++i) st.A *= dims[i];
+    st.B = 1; for (int i = k + 1; i < d; ++i) st.B *= dims[i];
+    st.K = dims[k];
+    st.m = l[k];
+    st.in_dt = cur_dt;
+    const rt_dtype ct = ctype(cur_dt);
+    st.y = (last && dst) ? dst : c.take(static_cast<size_t>(st.A) * st.m * st.B * dtype_size(ct));
+    st.mfma = (cur_dt == RT_F32 || cur_dt == RT_BF16) && ttm_mfma_ok(cur_dt, st.A, st.K, st.B, st.m);
+    if (st.mfma) {
+      st.op = prep(c, U ? U[k] : nullptr, st.m, st.K, true, cur_dt, cur_dt, ttm_mfma_mpad(st.m));
+      st.w = c.take(ttm_mfma_ws(cur_dt, st.A, st.K, st.B, st.m));
+    } else {
+      st.op = prep(c, U ? U[k] : nullptr, st.m, st.K, true, cur_dt == RT_F64 ? RT_F64 : cur_dt, ct);
+      st.w = c.take(ttm_generic_ws(cur_dt, st.A, st.K, st.B, st.m));
+    }
+    steps.push_back(st);
+    dims[k] = st.m;
+    cur_dt = ct;
+  }
+  c.flush();
+  Ten cur = X;
+  for (const Step& st : steps) {
+    if (!c.dry) {
+      if (st.mfma)
+        c.chk(launch_ttm_mfma_ws(cur.p, cur.dt, st.A, st.K, st.B, st.op, st.m, static_cast<float*>(st.y), st.w, c.st));
+      else
+        c.chk(launch_ttm_generic(cur.p, cur.dt, st.A, st.K, st.B, st.op, st.m, st.y, st.w, c.st));
+    }
     Ten out;
     out.dims = cur.dims;
-    out.dims[k] = m;
-    out.dt = ct;
-    void* y = (last && dst) ? dst : c.take(static_cast<size_t>(A) * m * B * dtype_size(ct));
-    out.p = y;
-    if ((cur.dt == RT_F32 || cur.dt == RT_BF16) && ttm_mfma_ok(cur.dt, A, K, B, m)) {
-      const void* mop = prep(c, U ? U[k] : nullptr, m, K, true, cur.dt, cur.dt, ttm_mfma_mpad(m));
-      void* w = nullptr;
-      const size_t wb = ttm_mfma_ws(cur.dt, A, K, B, m);
-      if (wb) w = c.take(wb);
-      if (!c.dry) c.chk(launch_ttm_mfma_ws(cur.p, cur.dt, A, K, B, mop, m, static_cast<float*>(y), w, c.st));
-    } else {
-      const void* M = prep(c, U ? U[k] : nullptr, m, K, true, cur.dt == RT_F64 ? RT_F64 : cur.dt, ct);
-      void* w = c.take(ttm_generic_ws(cur.dt, A, K, B, m));
-      if (!c.dry) c.chk(launch_ttm_generic(cur.p, cur.dt, A, K, B, M, m, y, w, c.st));
-    }
+    out.dims[st.k] = st.m;
+    out.dt = ctype(cur.dt);
+    out.p = st.y;
     cur = out;
   }
   return cur;
@@ -222,10 +251,9 @@ void truncate_impl(Ctx& c, Ten G, const int32_t* r, double* const* Uhat, const s
       c.chk(launch_mode_contract(G.p, G.p, RT_F64, A, cj, cj, B, gram, mcws, c.st));
       c.chk(launch_sym_eig_top(gram, cj, rj, V, nullptr, c.st));
     }
-    const void* Vt = prep(c, V, rj, cj, true, RT_F64, RT_F64);
-    G = ttm(c, G, j, Vt, rj, (j == d - 1) ? Gout : nullptr);
+    G = ttm(c, G, j, V, rj, (j == d - 1) ? Gout : nullptr, /*mtrans=*/true);
     void* w = c.take(ttm_generic_ws(RT_F64, I[j], cj, 1, rj));
-    if (!c.dry) c.chk(launch_ttm_generic(Uhat[j], RT_F64, I[j], cj, 1, Vt, rj, Uout[j], w, c.st));
+    if (!c.dry) c.chk(launch_ttm_generic(Uhat[j], RT_F64, I[j], cj, 1, V, rj, Uout[j], w, c.st, true));
   }
 }
 
@@ -376,6 +404,7 @@ int plan_sketch(Ctx& c, const rt_tensor* X, const double* const* phi, const int6
   std::vector<SketchOut> outs;
   sketch_impl(c, T, phi, s, mask, outs);
   const size_t es = dtype_size(ctype(X->dtype));
+  c.flush();
   for (int n = 0; n < d; ++n) {
     if (!(mask >> n & 1u)) continue;
     if (!c.dry) c.chk(launch_unfold(outs[n].Y.p, es, outs[n].A, outs[n].m, outs[n].B, Y[n], c.st));
@@ -477,6 +506,7 @@ int plan_decompose(Ctx& c, const rt_tensor* X, const rt_tensor* Xs, const int32_
     std::vector<QRJob> jobs(d);
     for (int n = 0; n < d; ++n) jobs[n] = QRJob{outs[n].Y.p, outs[n].A, outs[n].m, outs[n].B, Uhat[n], nullptr};
     void* w = c.take(qr_ws(jobs.data(), d));
+    c.flush();
     if (!c.dry) c.chk(launch_qr(jobs.data(), d, ctype(Tsk.dt), w, c.st));
     cur = core_impl(c, cur, Uhat.data(), cdim.data(), (1u << d) - 1u, nullptr);
   } else {
@@ -489,6 +519,7 @@ int plan_decompose(Ctx& c, const rt_tensor* X, const rt_tensor* Xs, const int32_
       sketch_impl(c, cur, phij.data(), sj.data(), 1u << j, outs);
       QRJob job{outs[j].Y.p, outs[j].A, outs[j].m, outs[j].B, Uhat[j], nullptr};
       void* w = c.take(qr_ws(&job, 1));
+      c.flush();
       if (!c.dry) c.chk(launch_qr(&job, 1, ctype(cur.dt), w, c.st));
       cur = core_impl(c, cur, Uhat.data(), cdim.data(), 1u << j, nullptr);
     }
@@ -626,6 +657,7 @@ int run(F&& plan, void* ws, size_t ws_bytes, void* stream) {
   st = check_ws(dry, ws, ws_bytes);
   if (st) return st;
   st = plan(live);
+  live.flush();
   if (st) return st;
   return live.err == hipSuccess ? RT_OK : RT_EHIP;
 }

@@ -59,6 +59,18 @@ __global__ __launch_bounds__(kThreads) void prep_kernel(const double* src, int64
   }
 }
 
+__global__ __launch_bounds__(kThreads) void prep_batch_kernel(PrepTable tab) {
+  const PrepTask& T = tab.t[blockIdx.y];
+  const int64_t total = T.m_pad * T.K;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; t < total; t += stride) {
+    const int64_t i = t / T.K, k = t - i * T.K;
+    double x = 0.0;
+    if (i < T.m) x = T.trans ? T.src[k * T.m + i] : T.src[i * T.K + k];
+    store_rounded(T.dst, T.store, T.round_to, t, x);
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void unfold_kernel(const T* src, int64_t A, int64_t m, int64_t B, T* dst) {
   const int64_t total = A * m * B;
@@ -129,6 +141,24 @@ hipError_t launch_prep_matrix(const double* src, int64_t m, int64_t K, bool tran
   if (m_pad < m) m_pad = m;
   prep_kernel<<<grid_for(m_pad * K), kThreads, 0, st>>>(src, m, K, trans, round_to, store, m_pad, dst);
   return hipGetLastError();
+}
+
+hipError_t launch_prep_batch(const PrepTask* tasks, int count, hipStream_t st) {
+  for (int i0 = 0; i0 < count; i0 += kMaxPrepTasks) {
+    PrepTable tab;
+    const int cnt = (count - i0 < kMaxPrepTasks) ? count - i0 : kMaxPrepTasks;
+    int64_t most = 1;
+    for (int i = 0; i < cnt; ++i) {
+      tab.t[i] = tasks[i0 + i];
+      const int64_t n = tasks[i0 + i].m_pad * tasks[i0 + i].K;
+      if (n > most) most = n;
+    }
+    const int64_t g = ceil_div(most, kThreads);
+    prep_batch_kernel<<<dim3(static_cast<unsigned>(g > 256 ? 256 : g), cnt), kThreads, 0, st>>>(tab);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_unfold(const void* src, size_t esize, int64_t A, int64_t m, int64_t B, void* dst,

@@ -133,12 +133,48 @@ constexpr int kJN = 64;
 constexpr int kJThreads = 256;
 constexpr int kPairLanes = 8;
 constexpr int kMaxSweeps = 30;
+constexpr int kLStride = 72;  // doubles per column of L in LDS (padding spreads banks)
+
+// DPP moves on the two halves of a binary64 value
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int64_t u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(u & 0xffffffff), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo));
+}
+// sum over aligned groups of 8 lanes; every lane of a group gets bitwise the same value
+__device__ __forceinline__ double group8_sum(double v) {
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror: lane i <- lane 7-i within 8
+  return v;
+}
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+// argmax (ties: lowest index) within each row of 16 lanes; all lanes of a row end with the result
+__device__ __forceinline__ void argmax_row16(double& v, int& idx) {
+#define RT_STEP(CTRL)                                                   \
+  {                                                                     \
+    const double ov = dpp_f64<CTRL>(v);                                 \
+    const int oi = dpp_i32<CTRL>(idx);                                  \
+    if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }          \
+  }
+  RT_STEP(0xB1)   // quad_perm [1,0,3,2]
+  RT_STEP(0x4E)   // quad_perm [2,3,0,1]
+  RT_STEP(0x141)  // row_half_mirror
+  RT_STEP(0x140)  // row_mirror
+#undef RT_STEP
+}
 
 __global__ __launch_bounds__(kJThreads) void eig_onesided_kernel(const double* __restrict__ M, int n, int r,
                                                                  double* __restrict__ Vout,
                                                                  double* __restrict__ evals) {
   __shared__ double Am[kJN][kJN + 1];   // Schur complement during the Cholesky
-  __shared__ double Lc[kJN][kJN];       // columns of L (column-major: Lc[col][row])
+  __shared__ double Lc[kJN * kLStride];  // columns of L: Lc[col * kLStride + row]
   __shared__ double nrm[kJN];
   __shared__ int done[kJN];
   __shared__ int piv_sh;
@@ -149,11 +185,12 @@ __global__ __launch_bounds__(kJThreads) void eig_onesided_kernel(const double* _
   __shared__ double vtmp[kJN];
   const int tid = threadIdx.x;
   const int lane = tid % kWave;
+  const int tx = tid % 16, ty = tid / 16;  // 4x4 block of the 64x64 matrix per thread
   for (int idx = tid; idx < kJN * kJN; idx += kJThreads) {
     const int i = idx / kJN, j = idx % kJN;
     Am[i][j] = (i < n && j < n) ? M[i * n + j] : 0.0;
-    Lc[i][j] = 0.0;
   }
+  for (int idx = tid; idx < kJN * kLStride; idx += kJThreads) Lc[idx] = 0.0;
   if (tid < kJN) done[tid] = (tid < n) ? 0 : 1;
   if (tid == 0) rank_sh = n;
   __syncthreads();
@@ -165,12 +202,19 @@ __global__ __launch_bounds__(kJThreads) void eig_onesided_kernel(const double* _
       double v = -1.0;
       int idx = kJN;
       if (lane < n && !done[lane]) { v = Am[lane][lane]; idx = lane; }
-      for (int off = 32; off >= 1; off >>= 1) {
-        const double ov = __shfl_xor(v, off);
-        const int oi = __shfl_xor(idx, off);
-        if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+      argmax_row16(v, idx);
+      // combine the four rows of 16 lanes (uniform values via readlane)
+      double bv = -1.0;
+      int bi = kJN;
+      for (int rw = 0; rw < 4; ++rw) {
+        const double rv = __longlong_as_double(
+            (static_cast<int64_t>(__builtin_amdgcn_readlane(static_cast<int>(__double_as_longlong(v) >> 32), 16 * rw))
+             << 32) |
+            static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(__double_as_longlong(v) & 0xffffffff), 16 * rw)));
+        const int ri = __builtin_amdgcn_readlane(idx, 16 * rw);
+        if (rv > bv || (rv == bv && ri < bi)) { bv = rv; bi = ri; }
       }
-      if (lane == 0) { piv_sh = idx; pivval_sh = v; }
+      if (lane == 0) { piv_sh = bi; pivval_sh = bv; }
     }
     __syncthreads();
     const int p = piv_sh;
@@ -180,23 +224,28 @@ __global__ __launch_bounds__(kJThreads) void eig_onesided_kernel(const double* _
       break;
     }
     const double sd = sqrt(d);
-    if (tid < kJN) {
-      const int i = tid;
-      Lc[k][i] = (i < n && !done[i]) ? Am[i][p] / sd : 0.0;
+    const double inv_d = 1.0 / d;
+    if (tid < kJN) Lc[k * kLStride + tid] = (tid < n && !done[tid]) ? Am[tid][p] / sd : 0.0;
+    double ai[4], aj[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = ty * 4 + u, j = tx * 4 + u;
+      ai[u] = (i < n && !done[i]) ? Am[i][p] : 0.0;
+      aj[u] = (j < n && !done[j]) ? Am[j][p] * inv_d : 0.0;
     }
-    __syncthreads();
+    __syncthreads();  // column p read by everyone before the update
     if (tid == 0) done[p] = 1;
-    for (int idx = tid; idx < n * n; idx += kJThreads) {
-      const int i = idx / n, j = idx % n;
-      Am[i][j] -= Lc[k][i] * Lc[k][j];
-    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Am[ty * 4 + u][tx * 4 + v] = fma(-ai[u], aj[v], Am[ty * 4 + u][tx * 4 + v]);
     __syncthreads();
   }
   const int nc = rank_sh;  // columns of L in use
-  // ---- 2. one-sided Jacobi on the nc columns of L
+  // ---- 2. one-sided Jacobi on the nc columns of L (lane `sub` of a pair group owns rows sub + 8t)
   const int N = nc + (nc & 1);
   const int half = N / 2;
-  const int g = tid / kPairLanes, sub = tid % kPairLanes;  // pair group, row block
+  const int g = tid / kPairLanes, sub = tid % kPairLanes;
   for (int sweep = 0; sweep < kMaxSweeps && N > 1; ++sweep) {
     if (tid == 0) rotated = 0;
     __syncthreads();
@@ -205,31 +254,30 @@ __global__ __launch_bounds__(kJThreads) void eig_onesided_kernel(const double* _
         const int a = (g == 0) ? 0 : ((g - 1 + round) % (N - 1)) + 1;
         const int b = ((N - 1 - g - 1 + round) % (N - 1)) + 1;
         const int pc = a < b ? a : b, qc = a < b ? b : a;
+        double* xp = Lc + pc * kLStride + sub;
+        double* yp = Lc + qc * kLStride + sub;
         double x[8], y[8];
         double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
-          x[t] = Lc[pc][sub * 8 + t];
-          y[t] = (qc < nc) ? Lc[qc][sub * 8 + t] : 0.0;
+          x[t] = xp[8 * t];
+          y[t] = yp[8 * t];
           al = fma(x[t], x[t], al);
           be = fma(y[t], y[t], be);
           ga = fma(x[t], y[t], ga);
         }
-        // sum over the 8 lanes of the pair group (fixed butterfly order)
-        for (int off = 1; off < kPairLanes; off <<= 1) {
-          al += __shfl_xor(al, off);
-          be += __shfl_xor(be, off);
-          ga += __shfl_xor(ga, off);
-        }
-        if (fabs(ga) > 1e-300 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+        al = group8_sum(al);
+        be = group8_sum(be);
+        ga = group8_sum(ga);
+        if (fabs(ga) > 1e-300 && ga * ga > 1e-30 * (al * be)) {
           const double zeta = (be - al) / (2.0 * ga);
-          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double c = 1.0 / sqrt(1.0 + t * t);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
+          const double c = rsqrt(fma(t, t, 1.0));
           const double s = c * t;
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
-            Lc[pc][sub * 8 + u] = c * x[u] - s * y[u];
-            Lc[qc][sub * 8 + u] = s * x[u] + c * y[u];
+            xp[8 * u] = c * x[u] - s * y[u];
+            yp[8 * u] = s * x[u] + c * y[u];
           }
           if (sub == 0) rotated = 1;
         }
@@ -243,7 +291,7 @@ __global__ __launch_bounds__(kJThreads) void eig_onesided_kernel(const double* _
   if (tid < kJN) {
     double s = 0.0;
     if (tid < nc)
-      for (int i = 0; i < n; ++i) s = fma(Lc[tid][i], Lc[tid][i], s);
+      for (int i = 0; i < n; ++i) s = fma(Lc[tid * kLStride + i], Lc[tid * kLStride + i], s);
     nrm[tid] = s;
   }
   __syncthreads();
@@ -273,13 +321,13 @@ __global__ __launch_bounds__(kJThreads) void eig_onesided_kernel(const double* _
             const int cc = order[kk];
             const double inv = 1.0 / sqrt(nrm[cc]);
             double dp = 0.0;
-            for (int i = 0; i < n; ++i) dp += Lc[cc][i] * inv * v[i];
-            for (int i = 0; i < n; ++i) v[i] -= dp * Lc[cc][i] * inv;
+            for (int i = 0; i < n; ++i) dp += Lc[cc * kLStride + i] * inv * v[i];
+            for (int i = 0; i < n; ++i) v[i] -= dp * Lc[cc * kLStride + i] * inv;
           }
         double nv = 0.0;
         for (int i = 0; i < n; ++i) nv += v[i] * v[i];
         if (nv > 0.5) {
-          for (int i = 0; i < n; ++i) Lc[col][i] = v[i] / sqrt(nv);
+          for (int i = 0; i < n; ++i) Lc[col * kLStride + i] = v[i] / sqrt(nv);
           nrm[col] = 1.0;
           break;
         }
@@ -292,10 +340,10 @@ __global__ __launch_bounds__(kJThreads) void eig_onesided_kernel(const double* _
     const double inv = 1.0 / sqrt(nrm[col]);
     double best = -1.0, sgn = 1.0;
     for (int x = 0; x < n; ++x) {
-      const double v = Lc[col][x];
+      const double v = Lc[col * kLStride + x];
       if (fabs(v) > best) { best = fabs(v); sgn = (v < 0.0) ? -1.0 : 1.0; }
     }
-    for (int x = 0; x < n; ++x) Vout[x * r + k] = sgn * inv * Lc[col][x];
+    for (int x = 0; x < n; ++x) Vout[x * r + k] = sgn * inv * Lc[col * kLStride + x];
   }
 }
 

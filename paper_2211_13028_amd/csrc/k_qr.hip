@@ -208,14 +208,15 @@ __global__ __launch_bounds__(256) void qr_combine_kernel(CombineTable tab) {
 constexpr int kGramRows = 64;
 
 struct CJob {
-  const void* Y;      // source (A, m, B) view (first pass) ; Q1 (m x n, binary64) in the second
+  const void* Y;      // source (A, m, B) view
   int64_t A, m, B;
   int32_t n;
-  double* part;       // chunks x 64 x 64 partial Gram matrices
+  double* part;       // 2 x chunks x 64 x 64 partial Gram matrices (one set per pass)
   int32_t chunks;
   double* R1;         // 64 x 64 upper factor of the first pass
   double* R2;         // second pass
-  double* Q1;         // m x n intermediate
+  double* Ri;         // 64 x 64 inverse of the current pass's factor
+  double* Q1;         // m x n intermediate (binary64)
   double* Q;          // final m x n (ld n)
   double* Rout;       // n x n or null
   int32_t* flag;      // 0 = CholeskyQR2 ok, 1 = use Householder
@@ -225,24 +226,22 @@ struct CJobTable {
 };
 
 template <typename TY>
-__device__ __forceinline__ double cq_elem(const CJob& J, bool second, int64_t r, int j) {
-  if (second) return J.Q1[r * J.n + j];
+__device__ __forceinline__ double cq_src(const CJob& J, int64_t r, int j) {
   const int64_t a = j / J.B, b = j - a * J.B;
   return static_cast<double>(static_cast<const TY*>(J.Y)[a * J.m * J.B + r * J.B + b]);
 }
 
-// partial Gram of 64-row chunks: part[chunk] = Y[rows]^T Y[rows]
+// partial Gram of one 64-row chunk of Y (first pass)
 template <typename TY>
-__global__ __launch_bounds__(256) void cq_gram_kernel(CJobTable tab, int second) {
+__global__ __launch_bounds__(256) void cq_gram_kernel(CJobTable tab) {
   __shared__ double sy[kGramRows][kCols + 1];
   const CJob& J = tab.t[blockIdx.y];
   if (static_cast<int>(blockIdx.x) >= J.chunks) return;
-  if (second && *J.flag) return;
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kGramRows;
   for (int idx = threadIdx.x; idx < kGramRows * kCols; idx += 256) {
     const int rr = idx / kCols, j = idx % kCols;
     const int64_t r = r0 + rr;
-    sy[rr][j] = (r < J.m && j < J.n) ? cq_elem<TY>(J, second != 0, r, j) : 0.0;
+    sy[rr][j] = (r < J.m && j < J.n) ? cq_src<TY>(J, r, j) : 0.0;
   }
   __syncthreads();
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
@@ -263,89 +262,171 @@ __global__ __launch_bounds__(256) void cq_gram_kernel(CJobTable tab, int second)
     for (int v = 0; v < 4; ++v) out[(ty * 4 + u) * kCols + tx * 4 + v] = acc[u][v];
 }
 
-// sum the partials (fixed order) and factor G = R^T R (upper R)
+template <int CTRL>
+__device__ __forceinline__ double qr_dpp(double v) {
+  const int64_t u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(u & 0xffffffff), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo));
+}
+
+// sum the partials (fixed order), factor G = R^T R (upper R) and invert R
 __global__ __launch_bounds__(256) void cq_chol_kernel(CJobTable tab, int second) {
   __shared__ double G[kCols][kCols + 1];
+  __shared__ double Rs[kCols][kCols + 1];
+  __shared__ double Ri[kCols][kCols + 1];
+  __shared__ double rinv[kCols];
   __shared__ int bad;
   const CJob& J = tab.t[blockIdx.x];
-  if (second && *J.flag) return;
+  if (*J.flag) return;  // cleared by cq_reset_kernel before the first pass
   const int n = J.n;
+  const double* part = J.part + (second ? static_cast<int64_t>(J.chunks) * kCols * kCols : 0);
   for (int idx = threadIdx.x; idx < kCols * kCols; idx += 256) {
-    double s = 0.0;
-    for (int c = 0; c < J.chunks; ++c) s += J.part[static_cast<int64_t>(c) * kCols * kCols + idx];
-    G[idx / kCols][idx % kCols] = s;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int c = 0;
+    for (; c + 4 <= J.chunks; c += 4) {
+      s0 += part[static_cast<int64_t>(c) * kCols * kCols + idx];
+      s1 += part[static_cast<int64_t>(c + 1) * kCols * kCols + idx];
+      s2 += part[static_cast<int64_t>(c + 2) * kCols * kCols + idx];
+      s3 += part[static_cast<int64_t>(c + 3) * kCols * kCols + idx];
+    }
+    for (; c < J.chunks; ++c) s0 += part[static_cast<int64_t>(c) * kCols * kCols + idx];
+    G[idx / kCols][idx % kCols] = (s0 + s1) + (s2 + s3);
+    Rs[idx / kCols][idx % kCols] = 0.0;
+    Ri[idx / kCols][idx % kCols] = 0.0;
   }
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
   double dmax = 0.0;
   for (int i = 0; i < n; ++i) dmax = fmax(dmax, G[i][i]);
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  // right-looking Cholesky, one barrier per step: row k of R goes to Rs, the
+  // trailing matrix is updated in place with G[k][.] / G[k][k]
   for (int k = 0; k < n; ++k) {
     const double d = G[k][k];
     if (!(d > 1e-13 * dmax) || !(dmax > 0.0)) {
       if (threadIdx.x == 0) bad = 1;
       break;
     }
+    const double inv_d = 1.0 / d;
     const double rkk = sqrt(d);
-    __syncthreads();
-    // row k of R: G[k][j] / rkk for j >= k (stored in place)
     if (static_cast<int>(threadIdx.x) >= k && static_cast<int>(threadIdx.x) < n)
-      G[k][threadIdx.x] = (static_cast<int>(threadIdx.x) == k) ? rkk : G[k][threadIdx.x] / rkk;
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < (n - k - 1) * (n - k - 1); idx += 256) {
-      const int i = k + 1 + idx / (n - k - 1), j = k + 1 + idx % (n - k - 1);
-      G[i][j] -= G[k][i] * G[k][j];
-    }
+      Rs[k][threadIdx.x] = G[k][threadIdx.x] / rkk;
+    double gki[4], gkj[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) { gki[u] = G[k][ty * 4 + u]; gkj[u] = G[k][tx * 4 + u] * inv_d; }
+    __syncthreads();  // everyone has read row k before it (and the rest) is updated
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = ty * 4 + u, j = tx * 4 + v;
+        if (i > k && j > k) G[i][j] = fma(-gki[u], gkj[v], G[i][j]);
+      }
     __syncthreads();
   }
+  if (bad) {
+    if (threadIdx.x == 0) *J.flag = 1;
+    return;
+  }
+  // R^-1 (upper), rows from the bottom up; four lanes share each column's dot product
+  if (static_cast<int>(threadIdx.x) < n) rinv[threadIdx.x] = 1.0 / Rs[threadIdx.x][threadIdx.x];
   __syncthreads();
+  {
+    const int j = threadIdx.x / 4, qd = threadIdx.x % 4;
+    for (int i = n - 1; i >= 0; --i) {
+      double s = 0.0;
+      if (j < n && j > i)
+        for (int t = i + 1 + qd; t <= j; t += 4) s = fma(Rs[i][t], Ri[t][j], s);
+      s += qr_dpp<0xB1>(s);  // quad_perm [1,0,3,2]
+      s += qr_dpp<0x4E>(s);  // quad_perm [2,3,0,1]
+      if (qd == 0 && j < n && j >= i) Ri[i][j] = (j == i) ? rinv[i] : -s * rinv[i];
+      __syncthreads();
+    }
+  }
   double* R = second ? J.R2 : J.R1;
   for (int idx = threadIdx.x; idx < kCols * kCols; idx += 256) {
     const int i = idx / kCols, j = idx % kCols;
-    R[idx] = (i < n && j < n && j >= i) ? G[i][j] : 0.0;
+    R[idx] = (i < n && j < n && j >= i) ? Rs[i][j] : 0.0;
+    J.Ri[idx] = Ri[i][j];
   }
-  if (threadIdx.x == 0) {
-    if (!second) *J.flag = bad;
-    else if (bad) *J.flag = 1;
-  }
-}
-
-// row solves q R = y (forward substitution, R upper); pass 1 writes Q1, pass 2 writes Q
-template <typename TY>
-__global__ __launch_bounds__(256) void cq_solve_kernel(CJobTable tab, int second) {
-  __shared__ double R[kCols][kCols + 1];
-  const CJob& J = tab.t[blockIdx.y];
-  if (*J.flag) return;
-  const int n = J.n;
-  const double* Rs = second ? J.R2 : J.R1;
-  for (int idx = threadIdx.x; idx < kCols * kCols; idx += 256) R[idx / kCols][idx % kCols] = Rs[idx];
-  __syncthreads();
-  const int64_t r = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (r >= J.m) return;
-  double q[kCols];
-#pragma unroll
-  for (int j = 0; j < kCols; ++j) {
-    if (j < n) {
-      double y = cq_elem<TY>(J, second != 0, r, j);
-#pragma unroll
-      for (int t = 0; t < j; ++t) y = fma(-q[t], R[t][j], y);
-      q[j] = y / R[j][j];
-    } else {
-      q[j] = 0.0;
-    }
-  }
-  double* out = second ? J.Q : J.Q1;
-#pragma unroll
-  for (int j = 0; j < kCols; ++j)
-    if (j < n) out[r * n + j] = q[j];
-  // R = R2 R1 (upper), written once by block 0 of pass 2
-  if (second && J.Rout && blockIdx.x == 0) {
+  if (second && J.Rout) {
     for (int idx = threadIdx.x; idx < n * n; idx += 256) {
       const int i = idx / n, j = idx % n;
       double s = 0.0;
-      for (int t = i; t <= j; ++t) s = fma(J.R2[i * kCols + t], J.R1[t * kCols + j], s);
+      for (int t = i; t <= j; ++t) s = fma(Rs[i][t], J.R1[t * kCols + j], s);
       J.Rout[idx] = (j >= i) ? s : 0.0;
     }
   }
+}
+
+// 64 rows of Q = Y R^-1 per workgroup; the first pass also stores Q1 and its partial Gram
+template <typename TY>
+__global__ __launch_bounds__(256) void cq_apply_kernel(CJobTable tab, int second) {
+  __shared__ double sy[kGramRows][kCols + 1];
+  __shared__ double sr[kCols][kCols + 1];
+  const CJob& J = tab.t[blockIdx.y];
+  if (static_cast<int>(blockIdx.x) >= J.chunks) return;
+  if (*J.flag) return;
+  const int n = J.n;
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kGramRows;
+  for (int idx = threadIdx.x; idx < kGramRows * kCols; idx += 256) {
+    const int rr = idx / kCols, j = idx % kCols;
+    const int64_t r = r0 + rr;
+    double v = 0.0;
+    if (r < J.m && j < n) v = second ? J.Q1[r * n + j] : cq_src<TY>(J, r, j);
+    sy[rr][j] = v;
+    sr[idx / kCols][idx % kCols] = J.Ri[idx];
+  }
+  __syncthreads();
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  double acc[4][4] = {};
+  for (int t = 0; t < kCols; ++t) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) { a[u] = sy[ty * 4 + u][t]; b[u] = sr[t][tx * 4 + u]; }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+  }
+  double* out = second ? J.Q : J.Q1;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t r = r0 + ty * 4 + u;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int j = tx * 4 + v;
+      if (r < J.m && j < n) out[r * n + j] = acc[u][v];
+    }
+  }
+  if (second) return;
+  // partial Gram of these Q1 rows for the second pass
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sy[ty * 4 + u][tx * 4 + v] = (r0 + ty * 4 + u < J.m) ? acc[u][v] : 0.0;
+  __syncthreads();
+  double g[4][4] = {};
+  for (int rr = 0; rr < kGramRows; ++rr) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) { a[u] = sy[rr][ty * 4 + u]; b[u] = sy[rr][tx * 4 + u]; }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) g[u][v] = fma(a[u], b[v], g[u][v]);
+  }
+  double* gp = J.part + (static_cast<int64_t>(J.chunks) + blockIdx.x) * kCols * kCols;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) gp[(ty * 4 + u) * kCols + tx * 4 + v] = g[u][v];
+}
+
+__global__ void cq_reset_kernel(CJobTable tab, int count) {
+  if (static_cast<int>(threadIdx.x) < count) *tab.t[threadIdx.x].flag = 0;
 }
 
 // One matrix of the (recursive) TSQR plan.
@@ -495,9 +576,10 @@ hipError_t qr_plan(const QRJob* jobs, int count, rt_dtype ydt, bool launch, Bump
       CJob J;
       J.Y = M.src; J.A = M.A; J.m = M.m; J.B = M.B; J.n = M.n;
       J.chunks = static_cast<int32_t>(ceil_div(M.m, kGramRows));
-      J.part = static_cast<double*>(ws.take(static_cast<size_t>(J.chunks) * kCols * kCols * sizeof(double)));
+      J.part = static_cast<double*>(ws.take(2 * static_cast<size_t>(J.chunks) * kCols * kCols * sizeof(double)));
       J.R1 = static_cast<double*>(ws.take(kCols * kCols * sizeof(double)));
       J.R2 = static_cast<double*>(ws.take(kCols * kCols * sizeof(double)));
+      J.Ri = static_cast<double*>(ws.take(kCols * kCols * sizeof(double)));
       J.Q1 = static_cast<double*>(ws.take(static_cast<size_t>(M.m) * M.n * sizeof(double)));
       J.flag = static_cast<int32_t*>(ws.take(sizeof(int32_t)));
       J.Q = M.Q; J.Rout = M.R;
@@ -509,19 +591,20 @@ hipError_t qr_plan(const QRJob* jobs, int count, rt_dtype ydt, bool launch, Bump
     hh.push_back(M);
   }
   if (launch && nc > 0) {
-    const dim3 g1(max_chunks, nc), g3(static_cast<unsigned>(ceil_div(max_m, 256)), nc);
+    const dim3 g1(max_chunks, nc);
+    (void)max_m;
+    cq_reset_kernel<<<1, 64, 0, st>>>(tab, nc);
     if (ydt == RT_F64) {
-      cq_gram_kernel<double><<<g1, 256, 0, st>>>(tab, 0);
+      cq_gram_kernel<double><<<g1, 256, 0, st>>>(tab);
       cq_chol_kernel<<<nc, 256, 0, st>>>(tab, 0);
-      cq_solve_kernel<double><<<g3, 256, 0, st>>>(tab, 0);
+      cq_apply_kernel<double><<<g1, 256, 0, st>>>(tab, 0);
     } else {
-      cq_gram_kernel<float><<<g1, 256, 0, st>>>(tab, 0);
+      cq_gram_kernel<float><<<g1, 256, 0, st>>>(tab);
       cq_chol_kernel<<<nc, 256, 0, st>>>(tab, 0);
-      cq_solve_kernel<float><<<g3, 256, 0, st>>>(tab, 0);
+      cq_apply_kernel<float><<<g1, 256, 0, st>>>(tab, 0);
     }
-    cq_gram_kernel<double><<<g1, 256, 0, st>>>(tab, 1);
     cq_chol_kernel<<<nc, 256, 0, st>>>(tab, 1);
-    cq_solve_kernel<double><<<g3, 256, 0, st>>>(tab, 1);
+    cq_apply_kernel<double><<<g1, 256, 0, st>>>(tab, 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

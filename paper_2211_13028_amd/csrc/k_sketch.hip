@@ -137,12 +137,21 @@ constexpr int kZWColsMfma = 512;
 
 __device__ __forceinline__ u32x4 ld16(const bf16_t* p) { return *reinterpret_cast<const u32x4*>(p); }
 
+__device__ __forceinline__ void load_w_tile(u32x4 (&r)[8], const bf16_t* xa, int64_t Q, int64_t pb, int64_t pend,
+                                            int64_t qc, int64_t qend, int kg) {
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int64_t p = pb + 8 * kg + t;
+    r[t] = (p < pend && qc < qend) ? ld16(xa + p * Q + qc) : u32x4{0u, 0u, 0u, 0u};
+  }
+}
+
 __global__ __launch_bounds__(kZWThreads) void sketch_zw_bf16_mfma_kernel(
     const bf16_t* __restrict__ X, int64_t A, int64_t P, int64_t Q, const bf16_t* __restrict__ phiP, int sP,
     const bf16_t* __restrict__ phiQ, int sQ, int64_t rows_per_block, int qblocks, int pblocks,
     float* __restrict__ Zo, float* __restrict__ Wo) {
   extern __shared__ unsigned char zw_smem[];
-  float* sW = reinterpret_cast<float*>(zw_smem);  // [waves][sP][512]
+  float* sW = reinterpret_cast<float*>(zw_smem);  // [sP][512], accumulated wave by wave
   const int lane = threadIdx.x % kWave;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int64_t blk = blockIdx.x;
@@ -152,6 +161,7 @@ __global__ __launch_bounds__(kZWThreads) void sketch_zw_bf16_mfma_kernel(
   const int64_t a = rest / pblocks;
   const int64_t q0 = static_cast<int64_t>(qblk) * kZWColsMfma;
   const int64_t qend = (q0 + kZWColsMfma < Q) ? q0 + kZWColsMfma : Q;
+  const int nqb = static_cast<int>((qend - q0 + 127) / 128);
   const bool needZ = Zo != nullptr, needW = Wo != nullptr;
   const int li = lane % 16, kg = lane / 16;
   const int64_t pbeg = static_cast<int64_t>(pblk) * rows_per_block;
@@ -165,82 +175,99 @@ __global__ __launch_bounds__(kZWThreads) void sketch_zw_bf16_mfma_kernel(
 #pragma unroll
     for (int c = 0; c < 8; ++c) wacc[u][c] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  for (int64_t pb = pbeg + 32 * wave; pb < pend; pb += 32 * kZWWaves) {
-    // PhiP operand: row c = li, columns pb + 8 kg .. + 7 (8-row groups lie wholly inside
-    // or outside [pbeg, pend) because P % 8 == 0 and blocks are multiples of 32 rows)
-    const int64_t pc = pb + 8 * kg;
-    const u32x4 pp = (needW && pc < pend) ? ld16(phiP + static_cast<int64_t>(li) * P + pc) : u32x4{0u, 0u, 0u, 0u};
-    f32x4 zacc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+  // software pipeline over (row block, column block): the W tile of the next step is
+  // requested before the current step's MFMAs
+  const int64_t pstep = 32 * kZWWaves;
+  int64_t pb = pbeg + 32 * wave;
+  int u = 0;
+  u32x4 rcur[8];
+  if (needW && pb < pend) load_w_tile(rcur, xa, Q, pb, pend, q0 + 8 * li, qend, kg);
+  f32x4 zacc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+  while (pb < pend) {
+    const int64_t qb = q0 + 128 * u;
+    int64_t pbn = pb;
+    int un = u + 1;
+    if (un >= nqb) { un = 0; pbn = pb + pstep; }
+    u32x4 rnext[8];
+    if (needW && pbn < pend) load_w_tile(rnext, xa, Q, pbn, pend, q0 + 128 * un + 8 * li, qend, kg);
+    if (needZ) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t qb = q0 + 128 * u;
-      if (qb >= qend) break;
-      if (needW) {
-        // 8 x 8 block: rows pb + 8 kg + t, columns qb + 8 li .. + 7
-        const int64_t qc = qb + 8 * li;
-        u32x4 r[8];
+      for (int ks = 0; ks < 4; ++ks) {
+        const int64_t qk = qb + 32 * ks + 8 * kg;
+        const u32x4 bq = (qk < qend) ? ld16(phiQ + static_cast<int64_t>(li) * Q + qk) : u32x4{0u, 0u, 0u, 0u};
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int64_t p = pb + 8 * kg + t;
-          r[t] = (p < pend && qc < qend) ? ld16(xa + p * Q + qc) : u32x4{0u, 0u, 0u, 0u};
-        }
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          u32x4 op;
-#pragma unroll
-          for (int w = 0; w < 4; ++w) {
-            const uint32_t lo = r[2 * w][c / 2], hi = r[2 * w + 1][c / 2];
-            op[w] = (c % 2 == 0) ? ((lo & 0xffffu) | (hi << 16)) : ((lo >> 16) | (hi & 0xffff0000u));
-          }
-          wacc[u][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, pp),
-                                                                __builtin_bit_cast(bf16x8, op), wacc[u][c], 0, 0, 0);
-        }
-      }
-      if (needZ) {
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          const int64_t qk = qb + 32 * ks + 8 * kg;
-          const u32x4 bq = (qk < qend) ? ld16(phiQ + static_cast<int64_t>(li) * Q + qk) : u32x4{0u, 0u, 0u, 0u};
-#pragma unroll
-          for (int mt = 0; mt < 2; ++mt) {
-            const int64_t p = pb + 16 * mt + li;
-            const u32x4 xr = (p < pend && qk < qend) ? ld16(xa + p * Q + qk) : u32x4{0u, 0u, 0u, 0u};
-            zacc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, xr),
-                                                                __builtin_bit_cast(bf16x8, bq), zacc[mt], 0, 0, 0);
-          }
+        for (int mt = 0; mt < 2; ++mt) {
+          const int64_t p = pb + 16 * mt + li;
+          const u32x4 xr = (p < pend && qk < qend) ? ld16(xa + p * Q + qk) : u32x4{0u, 0u, 0u, 0u};
+          zacc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, xr),
+                                                              __builtin_bit_cast(bf16x8, bq), zacc[mt], 0, 0, 0);
         }
       }
     }
-    if (needZ && li < sQ) {
+    if (needW) {
+      // PhiP operand: row c = li, columns pb + 8 kg .. + 7 (8-row groups lie wholly inside or
+      // outside [pbeg, pend) because P % 8 == 0 and blocks are multiples of 32 rows)
+      const int64_t pc = pb + 8 * kg;
+      const u32x4 pp = (pc < pend) ? ld16(phiP + static_cast<int64_t>(li) * P + pc) : u32x4{0u, 0u, 0u, 0u};
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt)
+      for (int c = 0; c < 8; ++c) {
+        u32x4 op;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t p = pb + 16 * mt + 4 * kg + v;
-          if (p < pend) zrow[p * sQ + li] = zacc[mt][v];
+        for (int w = 0; w < 4; ++w) {
+          const uint32_t lo = rcur[2 * w][c / 2], hi = rcur[2 * w + 1][c / 2];
+          op[w] = (c % 2 == 0) ? ((lo & 0xffffu) | (hi << 16)) : ((lo >> 16) | (hi & 0xffff0000u));
         }
+        // u is runtime; select the accumulator set without dynamic register indexing
+#pragma unroll
+        for (int uu = 0; uu < 4; ++uu)
+          if (uu == u)
+            wacc[uu][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, pp),
+                                                                   __builtin_bit_cast(bf16x8, op), wacc[uu][c], 0, 0,
+                                                                   0);
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) rcur[t] = rnext[t];
     }
+    if (un == 0) {  // row block finished: store Z
+      if (needZ && li < sQ) {
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t p = pb + 16 * mt + 4 * kg + v;
+            if (p < pend) zrow[p * sQ + li] = zacc[mt][v];
+          }
+      }
+      zacc[0] = f32x4{0.f, 0.f, 0.f, 0.f};
+      zacc[1] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    pb = pbn;
+    u = un;
   }
   if (!needW) return;
-  // wave partials of W -> LDS -> fixed-order sum over the 4 waves
+  // fixed-order sum of the four waves' partials in one sP x 512 LDS buffer
+  for (int w = 0; w < kZWWaves; ++w) {
+    if (wave == w) {
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+      for (int uu = 0; uu < 4; ++uu)
 #pragma unroll
-    for (int c = 0; c < 8; ++c)
+        for (int c = 0; c < 8; ++c)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int cp = 4 * kg + v;  // output row (subrank index)
-        if (cp < sP) sW[(wave * sP + cp) * kZWColsMfma + 128 * u + 8 * li + c] = wacc[u][c][v];
-      }
-  __syncthreads();
+          for (int v = 0; v < 4; ++v) {
+            const int cp = 4 * kg + v;
+            if (cp < sP) {
+              float* dst = &sW[cp * kZWColsMfma + 128 * uu + 8 * li + c];
+              *dst = (w == 0) ? wacc[uu][c][v] : *dst + wacc[uu][c][v];
+            }
+          }
+    }
+    __syncthreads();
+  }
   float* wout = Wo + (static_cast<int64_t>(pblk) * A + a) * sP * Q;
   for (int idx = threadIdx.x; idx < sP * kZWColsMfma; idx += kZWThreads) {
     const int c = idx / kZWColsMfma, col = idx % kZWColsMfma;
     const int64_t q = q0 + col;
-    if (q >= qend) continue;
-    float s = 0.f;
-    for (int w = 0; w < kZWWaves; ++w) s += sW[(w * sP + c) * kZWColsMfma + col];
-    wout[c * Q + q] = s;
+    if (q < qend) wout[c * Q + q] = sW[idx];
   }
 }
 
@@ -331,7 +358,7 @@ hipError_t launch_sketch_zw(const void* X, rt_dtype xdt, int64_t A, int64_t P, i
   const int isP = static_cast<int>(sP), isQ = static_cast<int>(sQ);
   if (plan.mfma) {
     const int64_t blocks = A * plan.pblocks * plan.qblocks;
-    const size_t shmem = W ? static_cast<size_t>(kZWWaves) * sP * kZWColsMfma * sizeof(float) : 0;
+    const size_t shmem = W ? static_cast<size_t>(sP) * kZWColsMfma * sizeof(float) : 0;
     sketch_zw_bf16_mfma_kernel<<<static_cast<unsigned>(blocks), kZWThreads, shmem, st>>>(
         static_cast<const bf16_t*>(X), A, P, Q, static_cast<const bf16_t*>(phiP16), isP,
         static_cast<const bf16_t*>(phiQ16), isQ, plan.rows_per_block, static_cast<int>(plan.qblocks),

@@ -24,7 +24,7 @@ constexpr int kGenKC = 64;
 template <typename TX, typename TC, int MT>
 __global__ __launch_bounds__(kGenThreads) void ttm_generic_kernel(const TX* __restrict__ X, int64_t A, int64_t K,
                                                                   int64_t B, const TC* __restrict__ M, int64_t m,
-                                                                  int64_t kper, TC* __restrict__ Y) {
+                                                                  int64_t kper, bool mtrans, TC* __restrict__ Y) {
   __shared__ TC sM[MT][kGenKC];
   const int64_t col = static_cast<int64_t>(blockIdx.x) * kGenThreads + threadIdx.x;
   const int64_t i0 = static_cast<int64_t>(blockIdx.y) * MT;
@@ -41,7 +41,8 @@ __global__ __launch_bounds__(kGenThreads) void ttm_generic_kernel(const TX* __re
     __syncthreads();
     for (int t = threadIdx.x; t < MT * kGenKC; t += kGenThreads) {
       const int ii = t / kGenKC, kk = t % kGenKC;
-      sM[ii][kk] = (i0 + ii < m && k0 + kk < ke) ? M[(i0 + ii) * K + k0 + kk] : TC(0);
+      sM[ii][kk] = (i0 + ii < m && k0 + kk < ke) ? (mtrans ? M[(k0 + kk) * m + i0 + ii] : M[(i0 + ii) * K + k0 + kk])
+                                                 : TC(0);
     }
     __syncthreads();
     if (active) {
@@ -82,19 +83,19 @@ int generic_ksplit(int64_t A, int64_t K, int64_t B) {
 
 template <typename TX, typename TC>
 hipError_t generic_dispatch(const TX* X, int64_t A, int64_t K, int64_t B, const TC* M, int64_t m, TC* Y, TC* ws,
-                            hipStream_t st) {
+                            hipStream_t st, bool mtrans) {
   const int64_t cols = A * B;
   const unsigned gx = static_cast<unsigned>(ceil_div(cols, kGenThreads));
   const int ks = generic_ksplit(A, K, B);
   const int64_t kper = ceil_div(K, ks);
   TC* out = (ks > 1) ? ws : Y;
   if (m <= 4) {
-    ttm_generic_kernel<TX, TC, 4><<<dim3(gx, 1, ks), kGenThreads, 0, st>>>(X, A, K, B, M, m, kper, out);
+    ttm_generic_kernel<TX, TC, 4><<<dim3(gx, 1, ks), kGenThreads, 0, st>>>(X, A, K, B, M, m, kper, mtrans, out);
   } else if (m <= 8) {
-    ttm_generic_kernel<TX, TC, 8><<<dim3(gx, 1, ks), kGenThreads, 0, st>>>(X, A, K, B, M, m, kper, out);
+    ttm_generic_kernel<TX, TC, 8><<<dim3(gx, 1, ks), kGenThreads, 0, st>>>(X, A, K, B, M, m, kper, mtrans, out);
   } else {
     const unsigned gy = static_cast<unsigned>(ceil_div(m, 16));
-    ttm_generic_kernel<TX, TC, 16><<<dim3(gx, gy, ks), kGenThreads, 0, st>>>(X, A, K, B, M, m, kper, out);
+    ttm_generic_kernel<TX, TC, 16><<<dim3(gx, gy, ks), kGenThreads, 0, st>>>(X, A, K, B, M, m, kper, mtrans, out);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || ks == 1) return e;
@@ -303,23 +304,23 @@ size_t ttm_generic_ws(rt_dtype xdt, int64_t A, int64_t K, int64_t B, int64_t m) 
 }
 
 hipError_t launch_ttm_generic(const void* X, rt_dtype xdt, int64_t A, int64_t K, int64_t B, const void* M,
-                              int64_t m, void* Y, void* ws, hipStream_t st) {
+                              int64_t m, void* Y, void* ws, hipStream_t st, bool mtrans) {
   if (A * B == 0 || m == 0) return hipSuccess;
   switch (xdt) {
     case RT_F64:
       return generic_dispatch<double, double>(static_cast<const double*>(X), A, K, B,
                                               static_cast<const double*>(M), m, static_cast<double*>(Y),
-                                              static_cast<double*>(ws), st);
+                                              static_cast<double*>(ws), st, mtrans);
     case RT_F32:
       return generic_dispatch<float, float>(static_cast<const float*>(X), A, K, B, static_cast<const float*>(M),
-                                            m, static_cast<float*>(Y), static_cast<float*>(ws), st);
+                                            m, static_cast<float*>(Y), static_cast<float*>(ws), st, mtrans);
     case RT_BF16:
       return generic_dispatch<bf16_t, float>(static_cast<const bf16_t*>(X), A, K, B,
                                              static_cast<const float*>(M), m, static_cast<float*>(Y),
-                                             static_cast<float*>(ws), st);
+                                             static_cast<float*>(ws), st, mtrans);
     case RT_F8E4M3:
       return generic_dispatch<f8_t, float>(static_cast<const f8_t*>(X), A, K, B, static_cast<const float*>(M), m,
-                                           static_cast<float*>(Y), static_cast<float*>(ws), st);
+                                           static_cast<float*>(Y), static_cast<float*>(ws), st, mtrans);
   }
   return hipErrorInvalidValue;
 }

@@ -20,6 +20,20 @@ hipError_t launch_convert(const void* src, rt_dtype sdt, void* dst, rt_dtype ddt
 hipError_t launch_prep_matrix(const double* src, int64_t m, int64_t K, bool trans, rt_dtype round_to,
                               rt_dtype store, int64_t m_pad, void* dst, hipStream_t st);
 
+// Several launch_prep_matrix jobs in one launch.
+struct PrepTask {
+  const double* src;
+  int64_t m, K, m_pad;
+  bool trans;
+  rt_dtype round_to, store;
+  void* dst;
+};
+constexpr int kMaxPrepTasks = 16;
+struct PrepTable {
+  PrepTask t[kMaxPrepTasks];
+};
+hipError_t launch_prep_batch(const PrepTask* tasks, int count, hipStream_t st);
+
 // dst[i * (A*B) + a*B + b] = src[a*m*B + i*B + b]   (mode-n unfolding of an (A, m, B) view)
 hipError_t launch_unfold(const void* src, size_t esize, int64_t A, int64_t m, int64_t B, void* dst,
                          hipStream_t st);
@@ -32,11 +46,13 @@ hipError_t launch_sq_residual(const void* a, const void* b, void* r, rt_dtype dt
 // ------------------------------------------------------------------ k_ttm.hip
 // Y[a, i, b] = sum_k M[i*K + k] * X[a, k, b] for i < m.
 //  X dtype xdt; M and Y in the compute type: binary64 if xdt == RT_F64, else binary32.
+//  With mtrans, M is stored K x m row-major (M[k*m + i]) instead.
 //  When A*B is small the contraction is split over K and `ws` (ttm_generic_ws bytes)
 //  holds the partial sums, added in a fixed order.
 size_t ttm_generic_ws(rt_dtype xdt, int64_t A, int64_t K, int64_t B, int64_t m);
 hipError_t launch_ttm_generic(const void* X, rt_dtype xdt, int64_t A, int64_t K, int64_t B,
-                              const void* M, int64_t m, void* Y, void* ws, hipStream_t st);
+                              const void* M, int64_t m, void* Y, void* ws, hipStream_t st,
+                              bool mtrans = false);
 
 // MFMA path for X in binary32 or bfloat16 (binary32 accumulation, binary32 output).
 //  Operand Mop prepared by launch_prep_matrix with store = xdt (F32 or BF16),
