@@ -246,6 +246,8 @@ __global__ __launch_bounds__(kJThreads) void eig_onesided_kernel(const double* _
   const int N = nc + (nc & 1);
   const int half = N / 2;
   const int g = tid / kPairLanes, sub = tid % kPairLanes;
+  const double tol = (n > 8 ? n : 8) * 2.220446049250313e-16;
+  const double tol2 = tol * tol;
   for (int sweep = 0; sweep < kMaxSweeps && N > 1; ++sweep) {
     if (tid == 0) rotated = 0;
     __syncthreads();
@@ -269,7 +271,8 @@ __global__ __launch_bounds__(kJThreads) void eig_onesided_kernel(const double* _
         al = group8_sum(al);
         be = group8_sum(be);
         ga = group8_sum(ga);
-        if (fabs(ga) > 1e-300 && ga * ga > 1e-30 * (al * be)) {
+        // rotate unless the pair is orthogonal to the rounding level of an n-term dot product
+        if (fabs(ga) > 1e-300 && ga * ga > tol2 * (al * be)) {
           const double zeta = (be - al) / (2.0 * ga);
           const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
           const double c = rsqrt(fma(t, t, 1.0));

@@ -215,7 +215,6 @@ struct CJob {
   int32_t chunks;
   double* R1;         // 64 x 64 upper factor of the first pass
   double* R2;         // second pass
-  double* Ri;         // 64 x 64 inverse of the current pass's factor
   double* Q1;         // m x n intermediate (binary64)
   double* Q;          // final m x n (ld n)
   double* Rout;       // n x n or null
@@ -274,8 +273,6 @@ __device__ __forceinline__ double qr_dpp(double v) {
 __global__ __launch_bounds__(256) void cq_chol_kernel(CJobTable tab, int second) {
   __shared__ double G[kCols][kCols + 1];
   __shared__ double Rs[kCols][kCols + 1];
-  __shared__ double Ri[kCols][kCols + 1];
-  __shared__ double rinv[kCols];
   __shared__ int bad;
   const CJob& J = tab.t[blockIdx.x];
   if (*J.flag) return;  // cleared by cq_reset_kernel before the first pass
@@ -293,7 +290,6 @@ __global__ __launch_bounds__(256) void cq_chol_kernel(CJobTable tab, int second)
     for (; c < J.chunks; ++c) s0 += part[static_cast<int64_t>(c) * kCols * kCols + idx];
     G[idx / kCols][idx % kCols] = (s0 + s1) + (s2 + s3);
     Rs[idx / kCols][idx % kCols] = 0.0;
-    Ri[idx / kCols][idx % kCols] = 0.0;
   }
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
@@ -329,26 +325,10 @@ __global__ __launch_bounds__(256) void cq_chol_kernel(CJobTable tab, int second)
     if (threadIdx.x == 0) *J.flag = 1;
     return;
   }
-  // R^-1 (upper), rows from the bottom up; four lanes share each column's dot product
-  if (static_cast<int>(threadIdx.x) < n) rinv[threadIdx.x] = 1.0 / Rs[threadIdx.x][threadIdx.x];
-  __syncthreads();
-  {
-    const int j = threadIdx.x / 4, qd = threadIdx.x % 4;
-    for (int i = n - 1; i >= 0; --i) {
-      double s = 0.0;
-      if (j < n && j > i)
-        for (int t = i + 1 + qd; t <= j; t += 4) s = fma(Rs[i][t], Ri[t][j], s);
-      s += qr_dpp<0xB1>(s);  // quad_perm [1,0,3,2]
-      s += qr_dpp<0x4E>(s);  // quad_perm [2,3,0,1]
-      if (qd == 0 && j < n && j >= i) Ri[i][j] = (j == i) ? rinv[i] : -s * rinv[i];
-      __syncthreads();
-    }
-  }
   double* R = second ? J.R2 : J.R1;
   for (int idx = threadIdx.x; idx < kCols * kCols; idx += 256) {
     const int i = idx / kCols, j = idx % kCols;
     R[idx] = (i < n && j < n && j >= i) ? Rs[i][j] : 0.0;
-    J.Ri[idx] = Ri[i][j];
   }
   if (second && J.Rout) {
     for (int idx = threadIdx.x; idx < n * n; idx += 256) {
@@ -360,54 +340,57 @@ __global__ __launch_bounds__(256) void cq_chol_kernel(CJobTable tab, int second)
   }
 }
 
-// 64 rows of Q = Y R^-1 per workgroup; the first pass also stores Q1 and its partial Gram
+// 64 rows of Q = Y R^-1 per workgroup by forward substitution q R = y, four lanes
+// per row sharing each dot product (quad DPP sums); the first pass also stores Q1
+// and the partial Gram of its rows
 template <typename TY>
 __global__ __launch_bounds__(256) void cq_apply_kernel(CJobTable tab, int second) {
   __shared__ double sy[kGramRows][kCols + 1];
   __shared__ double sr[kCols][kCols + 1];
+  __shared__ double rinv[kCols];
   const CJob& J = tab.t[blockIdx.y];
   if (static_cast<int>(blockIdx.x) >= J.chunks) return;
   if (*J.flag) return;
   const int n = J.n;
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kGramRows;
+  const double* Rg = second ? J.R2 : J.R1;
   for (int idx = threadIdx.x; idx < kGramRows * kCols; idx += 256) {
     const int rr = idx / kCols, j = idx % kCols;
     const int64_t r = r0 + rr;
     double v = 0.0;
     if (r < J.m && j < n) v = second ? J.Q1[r * n + j] : cq_src<TY>(J, r, j);
     sy[rr][j] = v;
-    sr[idx / kCols][idx % kCols] = J.Ri[idx];
+    sr[rr][j] = Rg[idx];
+  }
+  __syncthreads();
+  if (static_cast<int>(threadIdx.x) < n) rinv[threadIdx.x] = 1.0 / sr[threadIdx.x][threadIdx.x];
+  __syncthreads();
+  {
+    const int rr = threadIdx.x / 4, qd = threadIdx.x % 4;
+    for (int j = 0; j < n; ++j) {
+      double s = 0.0;
+      for (int t = qd; t < j; t += 4) s = fma(sy[rr][t], sr[t][j], s);
+      s += qr_dpp<0xB1>(s);  // quad_perm [1,0,3,2]
+      s += qr_dpp<0x4E>(s);  // quad_perm [2,3,0,1]
+      if (qd == 0) sy[rr][j] = (sy[rr][j] - s) * rinv[j];
+      __builtin_amdgcn_wave_barrier();  // the quad's next step reads this value
+    }
+  }
+  __syncthreads();
+  double* out = second ? J.Q : J.Q1;
+  for (int idx = threadIdx.x; idx < kGramRows * kCols; idx += 256) {
+    const int rr = idx / kCols, j = idx % kCols;
+    const int64_t r = r0 + rr;
+    if (r < J.m && j < n) out[r * n + j] = sy[rr][j];
+  }
+  if (second) return;
+  // partial Gram of these Q1 rows for the second pass (rows past m are zero)
+  for (int idx = threadIdx.x; idx < kGramRows * kCols; idx += 256) {
+    const int rr = idx / kCols, j = idx % kCols;
+    if (r0 + rr >= J.m || j >= n) sy[rr][j] = 0.0;
   }
   __syncthreads();
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  double acc[4][4] = {};
-  for (int t = 0; t < kCols; ++t) {
-    double a[4], b[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) { a[u] = sy[ty * 4 + u][t]; b[u] = sr[t][tx * 4 + u]; }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
-  }
-  double* out = second ? J.Q : J.Q1;
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int64_t r = r0 + ty * 4 + u;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int j = tx * 4 + v;
-      if (r < J.m && j < n) out[r * n + j] = acc[u][v];
-    }
-  }
-  if (second) return;
-  // partial Gram of these Q1 rows for the second pass
-  __syncthreads();
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) sy[ty * 4 + u][tx * 4 + v] = (r0 + ty * 4 + u < J.m) ? acc[u][v] : 0.0;
-  __syncthreads();
   double g[4][4] = {};
   for (int rr = 0; rr < kGramRows; ++rr) {
     double a[4], b[4];
@@ -579,7 +562,6 @@ hipError_t qr_plan(const QRJob* jobs, int count, rt_dtype ydt, bool launch, Bump
       J.part = static_cast<double*>(ws.take(2 * static_cast<size_t>(J.chunks) * kCols * kCols * sizeof(double)));
       J.R1 = static_cast<double*>(ws.take(kCols * kCols * sizeof(double)));
       J.R2 = static_cast<double*>(ws.take(kCols * kCols * sizeof(double)));
-      J.Ri = static_cast<double*>(ws.take(kCols * kCols * sizeof(double)));
       J.Q1 = static_cast<double*>(ws.take(static_cast<size_t>(M.m) * M.n * sizeof(double)));
       J.flag = static_cast<int32_t*>(ws.take(sizeof(int32_t)));
       J.Q = M.Q; J.Rout = M.R;

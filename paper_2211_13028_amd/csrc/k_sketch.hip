@@ -137,21 +137,16 @@ constexpr int kZWColsMfma = 512;
 
 __device__ __forceinline__ u32x4 ld16(const bf16_t* p) { return *reinterpret_cast<const u32x4*>(p); }
 
-__device__ __forceinline__ void load_w_tile(u32x4 (&r)[8], const bf16_t* xa, int64_t Q, int64_t pb, int64_t pend,
-                                            int64_t qc, int64_t qend, int kg) {
-#pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    const int64_t p = pb + 8 * kg + t;
-    r[t] = (p < pend && qc < qend) ? ld16(xa + p * Q + qc) : u32x4{0u, 0u, 0u, 0u};
-  }
-}
+constexpr int kTileStride = 136;  // bf16 per staged row: 128 columns + 8 padding (spreads LDS banks)
 
 __global__ __launch_bounds__(kZWThreads) void sketch_zw_bf16_mfma_kernel(
     const bf16_t* __restrict__ X, int64_t A, int64_t P, int64_t Q, const bf16_t* __restrict__ phiP, int sP,
     const bf16_t* __restrict__ phiQ, int sQ, int64_t rows_per_block, int qblocks, int pblocks,
     float* __restrict__ Zo, float* __restrict__ Wo) {
-  extern __shared__ unsigned char zw_smem[];
-  float* sW = reinterpret_cast<float*>(zw_smem);  // [sP][512], accumulated wave by wave
+  // per wave: one 32 x 128 tile staged row-major; after the loop the same memory
+  // holds the sP x 512 sum of the waves' W partials
+  __shared__ bf16_t tile[kZWWaves][32 * kTileStride];
+  float* sW = reinterpret_cast<float*>(&tile[0][0]);
   const int lane = threadIdx.x % kWave;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int64_t blk = blockIdx.x;
@@ -161,13 +156,13 @@ __global__ __launch_bounds__(kZWThreads) void sketch_zw_bf16_mfma_kernel(
   const int64_t a = rest / pblocks;
   const int64_t q0 = static_cast<int64_t>(qblk) * kZWColsMfma;
   const int64_t qend = (q0 + kZWColsMfma < Q) ? q0 + kZWColsMfma : Q;
-  const int nqb = static_cast<int>((qend - q0 + 127) / 128);
   const bool needZ = Zo != nullptr, needW = Wo != nullptr;
   const int li = lane % 16, kg = lane / 16;
   const int64_t pbeg = static_cast<int64_t>(pblk) * rows_per_block;
   const int64_t pend = (pbeg + rows_per_block < P) ? pbeg + rows_per_block : P;
   const bf16_t* xa = X + a * P * Q;
   float* zrow = needZ ? Zo + (static_cast<int64_t>(qblk) * A + a) * P * sQ : nullptr;
+  bf16_t* my = tile[wave];
 
   f32x4 wacc[4][8];
 #pragma unroll
@@ -175,77 +170,72 @@ __global__ __launch_bounds__(kZWThreads) void sketch_zw_bf16_mfma_kernel(
 #pragma unroll
     for (int c = 0; c < 8; ++c) wacc[u][c] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  // software pipeline over (row block, column block): the W tile of the next step is
-  // requested before the current step's MFMAs
-  const int64_t pstep = 32 * kZWWaves;
-  int64_t pb = pbeg + 32 * wave;
-  int u = 0;
-  u32x4 rcur[8];
-  if (needW && pb < pend) load_w_tile(rcur, xa, Q, pb, pend, q0 + 8 * li, qend, kg);
-  f32x4 zacc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
-  while (pb < pend) {
-    const int64_t qb = q0 + 128 * u;
-    int64_t pbn = pb;
-    int un = u + 1;
-    if (un >= nqb) { un = 0; pbn = pb + pstep; }
-    u32x4 rnext[8];
-    if (needW && pbn < pend) load_w_tile(rnext, xa, Q, pbn, pend, q0 + 128 * un + 8 * li, qend, kg);
-    if (needZ) {
+  for (int64_t pb = pbeg + 32 * wave; pb < pend; pb += 32 * kZWWaves) {
+    // PhiP operand: row c = li, columns pb + 8 kg .. + 7 (8-row groups lie wholly inside or
+    // outside [pbeg, pend) because P % 8 == 0 and blocks are multiples of 32 rows)
+    const int64_t pc = pb + 8 * kg;
+    const u32x4 pp = (needW && pc < pend) ? ld16(phiP + static_cast<int64_t>(li) * P + pc) : u32x4{0u, 0u, 0u, 0u};
+    f32x4 zacc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        const int64_t qk = qb + 32 * ks + 8 * kg;
-        const u32x4 bq = (qk < qend) ? ld16(phiQ + static_cast<int64_t>(li) * Q + qk) : u32x4{0u, 0u, 0u, 0u};
+    for (int u = 0; u < 4; ++u) {
+      const int64_t qb = q0 + 128 * u;
+      if (qb >= qend) break;
+      // 8 x 8 block per lane: rows pb + 8 kg + t, columns qb + 8 li .. + 7
+      const int64_t qc = qb + 8 * li;
+      u32x4 r[8];
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt) {
-          const int64_t p = pb + 16 * mt + li;
-          const u32x4 xr = (p < pend && qk < qend) ? ld16(xa + p * Q + qk) : u32x4{0u, 0u, 0u, 0u};
-          zacc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, xr),
-                                                              __builtin_bit_cast(bf16x8, bq), zacc[mt], 0, 0, 0);
-        }
+      for (int t = 0; t < 8; ++t) {
+        const int64_t p = pb + 8 * kg + t;
+        r[t] = (p < pend && qc < qend) ? ld16(xa + p * Q + qc) : u32x4{0u, 0u, 0u, 0u};
       }
-    }
-    if (needW) {
-      // PhiP operand: row c = li, columns pb + 8 kg .. + 7 (8-row groups lie wholly inside or
-      // outside [pbeg, pend) because P % 8 == 0 and blocks are multiples of 32 rows)
-      const int64_t pc = pb + 8 * kg;
-      const u32x4 pp = (pc < pend) ? ld16(phiP + static_cast<int64_t>(li) * P + pc) : u32x4{0u, 0u, 0u, 0u};
+      if (needZ) {  // stage the tile row-major for the Z operand
+        __builtin_amdgcn_wave_barrier();  // previous step's reads of the staging area stay above
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        u32x4 op;
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-          const uint32_t lo = rcur[2 * w][c / 2], hi = rcur[2 * w + 1][c / 2];
-          op[w] = (c % 2 == 0) ? ((lo & 0xffffu) | (hi << 16)) : ((lo >> 16) | (hi & 0xffff0000u));
-        }
-        // u is runtime; select the accumulator set without dynamic register indexing
-#pragma unroll
-        for (int uu = 0; uu < 4; ++uu)
-          if (uu == u)
-            wacc[uu][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, pp),
-                                                                   __builtin_bit_cast(bf16x8, op), wacc[uu][c], 0, 0,
-                                                                   0);
+        for (int t = 0; t < 8; ++t)
+          *reinterpret_cast<u32x4*>(my + (8 * kg + t) * kTileStride + 8 * li) = r[t];
+        __builtin_amdgcn_wave_barrier();  // cross-lane: stores before the reads below
       }
+      if (needW) {
 #pragma unroll
-      for (int t = 0; t < 8; ++t) rcur[t] = rnext[t];
-    }
-    if (un == 0) {  // row block finished: store Z
-      if (needZ && li < sQ) {
+        for (int c = 0; c < 8; ++c) {
+          u32x4 op;
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int64_t p = pb + 16 * mt + 4 * kg + v;
-            if (p < pend) zrow[p * sQ + li] = zacc[mt][v];
+          for (int w = 0; w < 4; ++w) {
+            const uint32_t lo = r[2 * w][c / 2], hi = r[2 * w + 1][c / 2];
+            op[w] = (c % 2 == 0) ? ((lo & 0xffffu) | (hi << 16)) : ((lo >> 16) | (hi & 0xffff0000u));
           }
+          wacc[u][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, pp),
+                                                                __builtin_bit_cast(bf16x8, op), wacc[u][c], 0, 0, 0);
+        }
       }
-      zacc[0] = f32x4{0.f, 0.f, 0.f, 0.f};
-      zacc[1] = f32x4{0.f, 0.f, 0.f, 0.f};
+      if (needZ) {
+        // the wave reads back its own staging area (LDS operations of a wave complete in order)
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const int64_t qk = qb + 32 * ks + 8 * kg;
+          const u32x4 bq = (qk < qend) ? ld16(phiQ + static_cast<int64_t>(li) * Q + qk) : u32x4{0u, 0u, 0u, 0u};
+#pragma unroll
+          for (int mt = 0; mt < 2; ++mt) {
+            const u32x4 xr = *reinterpret_cast<const u32x4*>(my + (16 * mt + li) * kTileStride + 32 * ks + 8 * kg);
+            zacc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, xr),
+                                                                __builtin_bit_cast(bf16x8, bq), zacc[mt], 0, 0, 0);
+          }
+        }
+      }
     }
-    pb = pbn;
-    u = un;
+    if (needZ && li < sQ) {
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t p = pb + 16 * mt + 4 * kg + v;
+          if (p < pend) zrow[p * sQ + li] = zacc[mt][v];
+        }
+    }
   }
   if (!needW) return;
-  // fixed-order sum of the four waves' partials in one sP x 512 LDS buffer
+  // fixed-order sum of the four waves' partials (the staging tiles are reused)
+  __syncthreads();
   for (int w = 0; w < kZWWaves; ++w) {
     if (wave == w) {
 #pragma unroll
@@ -358,8 +348,7 @@ hipError_t launch_sketch_zw(const void* X, rt_dtype xdt, int64_t A, int64_t P, i
   const int isP = static_cast<int>(sP), isQ = static_cast<int>(sQ);
   if (plan.mfma) {
     const int64_t blocks = A * plan.pblocks * plan.qblocks;
-    const size_t shmem = W ? static_cast<size_t>(sP) * kZWColsMfma * sizeof(float) : 0;
-    sketch_zw_bf16_mfma_kernel<<<static_cast<unsigned>(blocks), kZWThreads, shmem, st>>>(
+    sketch_zw_bf16_mfma_kernel<<<static_cast<unsigned>(blocks), kZWThreads, 0, st>>>(
         static_cast<const bf16_t*>(X), A, P, Q, static_cast<const bf16_t*>(phiP16), isP,
         static_cast<const bf16_t*>(phiQ16), isQ, plan.rows_per_block, static_cast<int>(plan.qblocks),
         static_cast<int>(plan.pblocks), static_cast<float*>(zdst), static_cast<float*>(wdst));
