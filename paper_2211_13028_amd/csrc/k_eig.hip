@@ -170,79 +170,73 @@ __device__ __forceinline__ void argmax_row16(double& v, int& idx) {
 #undef RT_STEP
 }
 
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const int64_t u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(u & 0xffffffff), lane);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(u >> 32), lane);
+  return __longlong_as_double((static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo));
+}
+
 __global__ __launch_bounds__(kJThreads) void eig_onesided_kernel(const double* __restrict__ M, int n, int r,
                                                                  double* __restrict__ Vout,
                                                                  double* __restrict__ evals) {
-  __shared__ double Am[kJN][kJN + 1];   // Schur complement during the Cholesky
-  __shared__ double Lc[kJN * kLStride];  // columns of L: Lc[col * kLStride + row]
+  __shared__ double Lc[kJN * kLStride];  // columns of L: Lc[col * kLStride + row] (rows in sorted order)
   __shared__ double nrm[kJN];
-  __shared__ int done[kJN];
-  __shared__ int piv_sh;
-  __shared__ double pivval_sh;
+  __shared__ int perm[kJN];              // sorted position -> original index
   __shared__ int rotated;
   __shared__ int order[kJN];
   __shared__ int rank_sh;
   __shared__ double vtmp[kJN];
   const int tid = threadIdx.x;
   const int lane = tid % kWave;
-  const int tx = tid % 16, ty = tid / 16;  // 4x4 block of the 64x64 matrix per thread
-  for (int idx = tid; idx < kJN * kJN; idx += kJThreads) {
-    const int i = idx / kJN, j = idx % kJN;
-    Am[i][j] = (i < n && j < n) ? M[i * n + j] : 0.0;
-  }
   for (int idx = tid; idx < kJN * kLStride; idx += kJThreads) Lc[idx] = 0.0;
-  if (tid < kJN) done[tid] = (tid < n) ? 0 : 1;
-  if (tid == 0) rank_sh = n;
-  __syncthreads();
-  // ---- 1. pivoted Cholesky: column k of L = A[:, p] / sqrt(A[p][p]), p = argmax remaining diagonal
-  double dmax0 = 0.0;
-  for (int i = 0; i < n; ++i) dmax0 = fmax(dmax0, Am[i][i]);
-  for (int k = 0; k < n; ++k) {
-    if (tid < kWave) {
-      double v = -1.0;
-      int idx = kJN;
-      if (lane < n && !done[lane]) { v = Am[lane][lane]; idx = lane; }
-      argmax_row16(v, idx);
-      // combine the four rows of 16 lanes (uniform values via readlane)
-      double bv = -1.0;
-      int bi = kJN;
-      for (int rw = 0; rw < 4; ++rw) {
-        const double rv = __longlong_as_double(
-            (static_cast<int64_t>(__builtin_amdgcn_readlane(static_cast<int>(__double_as_longlong(v) >> 32), 16 * rw))
-             << 32) |
-            static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(__double_as_longlong(v) & 0xffffffff), 16 * rw)));
-        const int ri = __builtin_amdgcn_readlane(idx, 16 * rw);
-        if (rv > bv || (rv == bv && ri < bi)) { bv = rv; bi = ri; }
-      }
-      if (lane == 0) { piv_sh = bi; pivval_sh = bv; }
+  // ---- 0. symmetric permutation sorting the diagonal decreasingly (a one-off pivot order)
+  if (tid < kWave) {
+    const double di = (lane < n) ? M[lane * n + lane] : -1.0;
+    int rk = 0;
+    for (int j = 0; j < n; ++j) {
+      const double dj = M[j * n + j];
+      if (dj > di || (dj == di && j < lane)) ++rk;
     }
-    __syncthreads();
-    const int p = piv_sh;
-    const double d = pivval_sh;
-    if (!(d > 1e-300 && d > 1e-30 * dmax0)) {  // remaining Schur complement is numerically zero
-      if (tid == 0) rank_sh = k;
-      break;
-    }
-    const double sd = sqrt(d);
-    const double inv_d = 1.0 / d;
-    if (tid < kJN) Lc[k * kLStride + tid] = (tid < n && !done[tid]) ? Am[tid][p] / sd : 0.0;
-    double ai[4], aj[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = ty * 4 + u, j = tx * 4 + u;
-      ai[u] = (i < n && !done[i]) ? Am[i][p] : 0.0;
-      aj[u] = (j < n && !done[j]) ? Am[j][p] * inv_d : 0.0;
-    }
-    __syncthreads();  // column p read by everyone before the update
-    if (tid == 0) done[p] = 1;
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Am[ty * 4 + u][tx * 4 + v] = fma(-ai[u], aj[v], Am[ty * 4 + u][tx * 4 + v]);
-    __syncthreads();
+    if (lane < n) perm[rk] = lane;
   }
+  __syncthreads();
+  // ---- 1. Cholesky of the permuted matrix by wave 0, column j of A in lane j's registers;
+  //         row k of L is broadcast with readlane (static register indices: loop unrolled)
+  if (tid < kWave) {
+    const int j = lane;
+    const int pj = (j < n) ? perm[j] : 0;
+    double a[kJN];
+#pragma unroll
+    for (int i = 0; i < kJN; ++i) a[i] = (i < n && j < n) ? M[perm[i < n ? i : 0] * n + pj] : 0.0;
+    double dmax = 0.0;
+#pragma unroll
+    for (int i = 0; i < kJN; ++i) dmax = fmax(dmax, readlane_f64(a[i], i));
+    int rank = n;
+#pragma unroll
+    for (int k = 0; k < kJN; ++k) {
+      if (k < n && rank == n) {
+        const double d = readlane_f64(a[k], k);
+        if (!(d > 1e-300 && d > 1e-30 * dmax)) {
+          rank = k;
+        } else {
+          const double inv_sd = rsqrt(d);
+          // L[j][k] = A[j][k] / sqrt(d) for j >= k (lane j holds A[k][j] = A[j][k])
+          const double l = (j > k) ? a[k] * inv_sd : ((j == k) ? d * inv_sd : 0.0);
+          Lc[k * kLStride + j] = l;
+#pragma unroll
+          for (int i = k + 1; i < kJN; ++i) {
+            const double lik = readlane_f64(a[i], k) * inv_sd;  // L[i][k]
+            a[i] = fma(-lik, l, a[i]);
+          }
+        }
+      }
+    }
+    if (lane == 0) rank_sh = rank;
+  }
+  __syncthreads();
   const int nc = rank_sh;  // columns of L in use
-  // ---- 2. one-sided Jacobi on the nc columns of L (lane `sub` of a pair group owns rows sub + 8t)
+  // ---- 2. one-sided Jacobi on the nc columns of L; lane `sub` of a pair group owns rows 8*sub .. 8*sub+7
   const int N = nc + (nc & 1);
   const int half = N / 2;
   const int g = tid / kPairLanes, sub = tid % kPairLanes;
@@ -251,46 +245,59 @@ __global__ __launch_bounds__(kJThreads) void eig_onesided_kernel(const double* _
   for (int sweep = 0; sweep < kMaxSweeps && N > 1; ++sweep) {
     if (tid == 0) rotated = 0;
     __syncthreads();
+    // circle-method positions of this group's pair, advanced without division
+    int a_pos = (g == 0) ? 0 : g;                  // position g holds player g at round 0
+    int b_pos = N - 1 - g;
     for (int round = 0; round < N - 1; ++round) {
       if (g < half) {
-        const int a = (g == 0) ? 0 : ((g - 1 + round) % (N - 1)) + 1;
-        const int b = ((N - 1 - g - 1 + round) % (N - 1)) + 1;
-        const int pc = a < b ? a : b, qc = a < b ? b : a;
-        double* xp = Lc + pc * kLStride + sub;
-        double* yp = Lc + qc * kLStride + sub;
-        double x[8], y[8];
+        const int pc = a_pos < b_pos ? a_pos : b_pos, qc = a_pos < b_pos ? b_pos : a_pos;
+        double* xp = Lc + pc * kLStride + 8 * sub;
+        double* yp = Lc + qc * kLStride + 8 * sub;
+        double2 x2[4], y2[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          x2[t] = reinterpret_cast<const double2*>(xp)[t];
+          y2[t] = reinterpret_cast<const double2*>(yp)[t];
+        }
         double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          x[t] = xp[8 * t];
-          y[t] = yp[8 * t];
-          al = fma(x[t], x[t], al);
-          be = fma(y[t], y[t], be);
-          ga = fma(x[t], y[t], ga);
+        for (int t = 0; t < 4; ++t) {
+          al = fma(x2[t].x, x2[t].x, al); al = fma(x2[t].y, x2[t].y, al);
+          be = fma(y2[t].x, y2[t].x, be); be = fma(y2[t].y, y2[t].y, be);
+          ga = fma(x2[t].x, y2[t].x, ga); ga = fma(x2[t].y, y2[t].y, ga);
         }
         al = group8_sum(al);
         be = group8_sum(be);
         ga = group8_sum(ga);
         // rotate unless the pair is orthogonal to the rounding level of an n-term dot product
         if (fabs(ga) > 1e-300 && ga * ga > tol2 * (al * be)) {
-          const double zeta = (be - al) / (2.0 * ga);
-          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
+          // tan of the rotation angle: t = sign(u v) |v| / (|u| + sqrt(u^2 + v^2)), u = be - al, v = 2 ga
+          const double u = be - al, v = 2.0 * ga;
+          const double h = sqrt(fma(u, u, v * v));
+          double t = fabs(v) / (fabs(u) + h);
+          if ((u < 0.0) != (v < 0.0) && u != 0.0) t = -t;
           const double c = rsqrt(fma(t, t, 1.0));
           const double s = c * t;
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            xp[8 * u] = c * x[u] - s * y[u];
-            yp[8 * u] = s * x[u] + c * y[u];
+          for (int q = 0; q < 4; ++q) {
+            double2 nx, ny;
+            nx.x = c * x2[q].x - s * y2[q].x;  nx.y = c * x2[q].y - s * y2[q].y;
+            ny.x = s * x2[q].x + c * y2[q].x;  ny.y = s * x2[q].y + c * y2[q].y;
+            reinterpret_cast<double2*>(xp)[q] = nx;
+            reinterpret_cast<double2*>(yp)[q] = ny;
           }
           if (sub == 0) rotated = 1;
         }
       }
+      // next round: every position except 0 advances by one player (wrapping N-1 -> 1)
+      if (g != 0) a_pos = (a_pos == N - 1) ? 1 : a_pos + 1;
+      b_pos = (b_pos == N - 1) ? 1 : b_pos + 1;
       __syncthreads();
     }
     if (!rotated) break;
     __syncthreads();
   }
-  // ---- 3. norms, order (decreasing), normalised columns with the sign rule
+  // ---- 3. norms, order (decreasing), normalised columns (rows back in original order), sign rule
   if (tid < kJN) {
     double s = 0.0;
     if (tid < nc)
@@ -341,12 +348,16 @@ __global__ __launch_bounds__(kJThreads) void eig_onesided_kernel(const double* _
   if (tid < r) {
     const int k = tid, col = order[k];
     const double inv = 1.0 / sqrt(nrm[col]);
+    // sign rule on the vector in original row order: largest |entry| (first on ties) positive
     double best = -1.0, sgn = 1.0;
     for (int x = 0; x < n; ++x) {
-      const double v = Lc[col * kLStride + x];
+      // find the sorted position of original row x
+      double v = 0.0;
+      for (int i = 0; i < n; ++i)
+        if (perm[i] == x) v = Lc[col * kLStride + i];
       if (fabs(v) > best) { best = fabs(v); sgn = (v < 0.0) ? -1.0 : 1.0; }
     }
-    for (int x = 0; x < n; ++x) Vout[x * r + k] = sgn * inv * Lc[col * kLStride + x];
+    for (int i = 0; i < n; ++i) Vout[perm[i] * r + k] = sgn * inv * Lc[col * kLStride + i];
   }
 }
 
