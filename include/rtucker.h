@@ -200,20 +200,29 @@ int rtucker_convert(const void* src, rt_dtype src_dtype, void* dst, rt_dtype dst
  * rtucker_mode_contract: out[i][j] = sum over all indices except mode n of
  *  P[.., i, ..] * Q[.., j, ..]  (= P_(n) Q_(n)^T).  P, Q: same dtype (F32 or
  *  F64), same dims except mode n.  out: device, P.dims[n] x Q.dims[n], that dtype.
+ *  With accumulate != 0 the result is added to what out holds (out += ...), so
+ *  the two contributions to a factor used twice sum without another call.
  * rtucker_sq_residual: R = A - B elementwise (R may be NULL) and
  *  out[0] = sum (A - B)^2 accumulated in binary64.  A, B (and R): same dims and
- *  dtype, F32 or F64; out: device, 1 double. */
+ *  dtype, F32 or F64; out: device, 1 double.  ws: device, >= 8192 bytes,
+ *  256-byte aligned (partial sums of the fixed-order reduction).
+ * rtucker_scaled_diff: out = alpha * g[0] * (A - B) elementwise, the adjoint of
+ *  the squared residual (dA = 2 g R, dB = -2 g R) and of its projected form.
+ *  g: device binary64 scalar or NULL (= 1); B: NULL means 0.  A, B, out: same
+ *  dims and dtype (F32 or F64); out may alias A or B. */
 int rtucker_multi_ttm_workspace(const rt_tensor* X, const int64_t* m, uint32_t mode_mask,
                                 size_t* bytes);
 int rtucker_multi_ttm(const rt_tensor* X, const void* const* A, const int64_t* m,
                       uint32_t mode_mask, int32_t transpose, void* Y, void* ws, size_t ws_bytes,
                       void* stream);
-int rtucker_mode_contract(const rt_tensor* P, const rt_tensor* Q, int32_t n, void* out,
-                          void* ws, size_t ws_bytes, void* stream);
+int rtucker_mode_contract(const rt_tensor* P, const rt_tensor* Q, int32_t n, int32_t accumulate,
+                          void* out, void* ws, size_t ws_bytes, void* stream);
 int rtucker_mode_contract_workspace(const rt_tensor* P, const rt_tensor* Q, int32_t n,
                                     size_t* bytes);
 int rtucker_sq_residual(const rt_tensor* A, const void* B, void* R, double* out, void* ws,
                         size_t ws_bytes, void* stream);
+int rtucker_scaled_diff(const rt_tensor* A, const void* B, const double* g, double alpha, void* out,
+                        void* stream);
 
 /* ------------------------------------------------------------------ batched
  * Batched factor-reuse decomposition of many independent 3-way tensors of

@@ -70,10 +70,12 @@ _SIGS = {
                                          ctypes.c_void_p]),
     "rtucker_mode_contract_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                                        ctypes.c_void_p]),
-    "rtucker_mode_contract": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
-                                             ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "rtucker_mode_contract": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "rtucker_sq_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "rtucker_scaled_diff": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                           ctypes.c_void_p, ctypes.c_void_p]),
     "rtucker_decompose_batched_workspace": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
                                                            ctypes.c_int, ctypes.c_void_p]),
     "rtucker_decompose_batched": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int,
@@ -345,17 +347,21 @@ def rtucker_multi_ttm(X, As, modes=None, transpose: bool = False):
     return Y
 
 
-def rtucker_mode_contract(P, Q, n: int):
-    """out = P_(n) Q_(n)^T (sum over every index but mode n)."""
+def rtucker_mode_contract(P, Q, n: int, out=None):
+    """P_(n) Q_(n)^T (sum over every index but mode n); added to `out` when it is given."""
     torch = _torch()
     pt, qt = _tensor(P), _tensor(Q)
     nb = ctypes.c_size_t()
     _check(lib().rtucker_mode_contract_workspace(ctypes.byref(pt), ctypes.byref(qt), int(n), ctypes.byref(nb)),
            "rtucker_mode_contract_workspace")
-    out = torch.empty((P.shape[n], Q.shape[n]), dtype=P.dtype, device=P.device)
+    acc = out is not None
+    if out is None:
+        out = torch.empty((P.shape[n], Q.shape[n]), dtype=P.dtype, device=P.device)
+    elif tuple(out.shape) != (P.shape[n], Q.shape[n]) or out.dtype != P.dtype or not out.is_contiguous():
+        raise RtuckerError("rtucker_mode_contract: out has the wrong shape, dtype or layout")
     ws, wb = _workspace(nb.value, P.device)
-    _check(lib().rtucker_mode_contract(ctypes.byref(pt), ctypes.byref(qt), int(n), _ptr(out), _ptr(ws), wb,
-                                       _stream(P.device)), "rtucker_mode_contract")
+    _check(lib().rtucker_mode_contract(ctypes.byref(pt), ctypes.byref(qt), int(n), 1 if acc else 0, _ptr(out),
+                                       _ptr(ws), wb, _stream(P.device)), "rtucker_mode_contract")
     return out
 
 
@@ -372,6 +378,21 @@ def rtucker_sq_residual(A, B, want_r: bool = True):
     _check(lib().rtucker_sq_residual(ctypes.byref(at), _ptr(B.contiguous()), _ptr(R), _ptr(out), _ptr(ws), wb,
                                      _stream(A.device)), "rtucker_sq_residual")
     return out, R
+
+
+def rtucker_scaled_diff(A, B=None, g=None, alpha: float = 1.0, out=None):
+    """out = alpha * g * (A - B) elementwise (g: device float64 scalar tensor or None = 1; B None = 0)."""
+    torch = _torch()
+    at = _tensor(A)
+    if B is not None and (B.shape != A.shape or B.dtype != A.dtype or not B.is_contiguous()):
+        raise RtuckerError("rtucker_scaled_diff: B must match A")
+    if g is not None and (g.dtype != torch.float64 or g.numel() != 1 or g.device != A.device):
+        raise RtuckerError("rtucker_scaled_diff: g must be one float64 value on A's device")
+    if out is None:
+        out = torch.empty_like(A)
+    _check(lib().rtucker_scaled_diff(ctypes.byref(at), _ptr(B), _ptr(g), float(alpha), _ptr(out),
+                                     _stream(A.device)), "rtucker_scaled_diff")
+    return out
 
 
 def make_batch_items(Xs, ranks, phis, Gs, Us, s=None):

@@ -1,0 +1,148 @@
+"""Differentiable multi-TTM (Sec. 2.1) on the rtucker kernels.
+
+The adjoint of Y = X x_1 op(A_1) ... x_d op(A_d) is
+    dX   = dY x_k op(A_k)^T                        (one multi-TTM)
+    dA_n = dY_(n) Z_(n)^T,  Z = X x_{k != n} op(A_k)  (a mode contraction)
+and Z is recomputed in the backward pass instead of being kept from the
+forward pass.  Every product runs in the library's HIP kernels through the
+C ABI; these classes only order the calls.
+
+* ``MultiTTM``     -- Y = X x_k op(A_k) over the modes whose factor is given.
+* ``SqResidual``   -- L = sum (A - B)^2 (binary64 accumulation).
+* ``ProjectionLoss`` -- L = ||X - (X x_k U_k^T) x_k U_k||^2, the Tucker
+  reconstruction loss with fixed factors, with its whole backward pass fused
+  into library calls (no gradient is summed outside the kernels).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import (rtucker_mode_contract, rtucker_multi_ttm, rtucker_scaled_diff, rtucker_sq_residual)
+
+
+def _modes(As):
+    return [k for k, A in enumerate(As) if A is not None]
+
+
+def _contig(t):
+    return t if t.is_contiguous() else t.contiguous()
+
+
+class MultiTTM(torch.autograd.Function):
+    """Y = X x_k op(A_k) for every k with A_k given (None skips the mode).
+
+    op(A) = A with A_k of shape m_k x I_k, or A^T (A_k: I_k x m_k) when
+    ``transpose`` is true.  X and the A_k: float32 or float64, one dtype.
+    """
+
+    @staticmethod
+    def forward(ctx, X, transpose, *As):
+        modes = _modes(As)
+        ctx.transpose = bool(transpose)
+        ctx.modes = modes
+        ctx.d = X.dim()
+        X = _contig(X)
+        As = [None if A is None else _contig(A) for A in As]
+        ctx.save_for_backward(X, *[As[k] for k in modes])
+        return rtucker_multi_ttm(X, As, modes, ctx.transpose)
+
+    @staticmethod
+    def backward(ctx, dY):
+        X, *sel = ctx.saved_tensors
+        d, modes, tr = ctx.d, ctx.modes, ctx.transpose
+        As = [None] * d
+        for k, A in zip(modes, sel):
+            As[k] = A
+        dY = _contig(dY)
+        dX = None
+        if ctx.needs_input_grad[0]:
+            dX = rtucker_multi_ttm(dY, As, modes, not tr)
+        dAs = [None] * d
+        for k in modes:
+            if not ctx.needs_input_grad[2 + k]:
+                continue
+            others = [j for j in modes if j != k]
+            Z = rtucker_multi_ttm(X, As, others, tr) if others else X
+            # op(A_k) = A_k: dA_k = dY_(k) Z_(k)^T;  op(A_k) = A_k^T: its transpose
+            dAs[k] = rtucker_mode_contract(Z, dY, k) if tr else rtucker_mode_contract(dY, Z, k)
+        return (dX, None, *dAs)
+
+
+class SqResidual(torch.autograd.Function):
+    """L = sum (A - B)^2 as a float64 scalar; dA = 2 g (A - B), dB = -2 g (A - B)."""
+
+    @staticmethod
+    def forward(ctx, A, B):
+        out, R = rtucker_sq_residual(_contig(A), _contig(B), want_r=True)
+        ctx.save_for_backward(R)
+        return out.view(())
+
+    @staticmethod
+    def backward(ctx, g):
+        (R,) = ctx.saved_tensors
+        g = _contig(g.reshape(1))
+        dA = rtucker_scaled_diff(R, None, g, 2.0) if ctx.needs_input_grad[0] else None
+        dB = rtucker_scaled_diff(R, None, g, -2.0) if ctx.needs_input_grad[1] else None
+        return dA, dB
+
+
+class ProjectionLoss(torch.autograd.Function):
+    """L = ||X - X_hat||^2 with G = X x_k U_k^T and X_hat = G x_k U_k (U_k: I_k x r_k).
+
+    Backward, with R = X - X_hat, g the incoming gradient and P R = (R x_k U_k^T) x_k U_k:
+        dX   = 2 g (R - P R)
+        dU_k = -2 g [ R_(k) Z_(k)^T + Z'_(k) (R x_j U_j^T)_(k)^T ]
+    where Z = G x_{j != k} U_j and Z' = X x_{j != k} U_j^T are recomputed.
+    """
+
+    @staticmethod
+    def forward(ctx, X, *Us):
+        X = _contig(X)
+        Us = [_contig(U) for U in Us]
+        G = rtucker_multi_ttm(X, Us, None, True)
+        Xh = rtucker_multi_ttm(G, Us, None, False)
+        out, R = rtucker_sq_residual(X, Xh, want_r=True)
+        del Xh
+        ctx.save_for_backward(X, G, R, *Us)
+        return out.view(())
+
+    @staticmethod
+    def backward(ctx, gL):
+        X, G, R, *Us = ctx.saved_tensors
+        d = X.dim()
+        g = _contig(gL.reshape(1))
+        RG = rtucker_multi_ttm(R, Us, None, True)  # R x_k U_k^T (= dG / (-2 g))
+        dX = None
+        if ctx.needs_input_grad[0]:
+            PR = rtucker_multi_ttm(RG, Us, None, False)
+            dX = rtucker_scaled_diff(R, PR, g, 2.0)
+            del PR
+        dUs = [None] * d
+        for k in range(d):
+            if not ctx.needs_input_grad[1 + k]:
+                continue
+            rest = [U if j != k else None for j, U in enumerate(Us)]
+            others = [j for j in range(d) if j != k]
+            Z = rtucker_multi_ttm(G, rest, others, False) if others else G
+            acc = rtucker_mode_contract(R, Z, k)
+            del Z
+            Zp = rtucker_multi_ttm(X, rest, others, True) if others else X
+            rtucker_mode_contract(Zp, RG, k, out=acc)
+            del Zp
+            dUs[k] = rtucker_scaled_diff(acc, None, g, -2.0, out=acc)
+        return (dX, *dUs)
+
+
+def multi_ttm(X, As, transpose: bool = False):
+    """Differentiable Y = X x_k op(A_k) (None entries skip a mode)."""
+    return MultiTTM.apply(X, transpose, *As)
+
+
+def sq_residual(A, B):
+    """Differentiable sum (A - B)^2 (float64 scalar)."""
+    return SqResidual.apply(A, B)
+
+
+def projection_loss(X, Us):
+    """Differentiable ||X - (X x_k U_k^T) x_k U_k||^2 (float64 scalar)."""
+    return ProjectionLoss.apply(X, *Us)

@@ -80,6 +80,21 @@ int check_tensor(const rt_tensor* X, bool need_data) {
   return RT_OK;
 }
 
+// elementwise entry points: any order 1..8, empty dimensions allowed
+int check_flat(const rt_tensor* X, int64_t* n) {
+  if (!X) return RT_EINVAL;
+  if (X->d < 1 || X->d > RT_MAX_D) return RT_ESHAPE;
+  int64_t cnt = 1;
+  for (int i = 0; i < X->d; ++i) {
+    if (X->dims[i] < 0) return RT_ESHAPE;
+    cnt *= X->dims[i];
+  }
+  if (X->dtype != RT_F32 && X->dtype != RT_F64) return RT_EDTYPE;
+  if (cnt > 0 && !X->data) return RT_EINVAL;
+  *n = cnt;
+  return RT_OK;
+}
+
 Ten ten_of(const rt_tensor* X) {
   Ten t;
   t.dims.assign(X->dims, X->dims + X->d);
@@ -578,9 +593,14 @@ int plan_multi_ttm(Ctx& c, const rt_tensor* X, const void* const* A, const int64
   std::vector<int> order;
   for (int k = 0; k < d; ++k)
     if (mask >> k & 1u) order.push_back(k);
-  // contract the modes that shrink the tensor most first
+  // contract the modes that shrink the tensor most first.  Among equal ratios a
+  // shrinking step goes first on the slowest mode (the full-size read is then a
+  // contraction over long contiguous rows) and an expanding step goes last on it
+  // (the full-size write is then coalesced).
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    return static_cast<double>(m[a]) / X->dims[a] < static_cast<double>(m[b]) / X->dims[b];
+    const double ra = static_cast<double>(m[a]) / X->dims[a], rb = static_cast<double>(m[b]) / X->dims[b];
+    if (ra != rb) return ra < rb;
+    return ra <= 1.0 ? a < b : a > b;
   });
   Ten cur = ten_of(X);
   for (size_t i = 0; i < order.size(); ++i) {
@@ -596,7 +616,7 @@ int plan_multi_ttm(Ctx& c, const rt_tensor* X, const void* const* A, const int64
   return RT_OK;
 }
 
-int plan_mode_contract(Ctx& c, const rt_tensor* P, const rt_tensor* Q, int32_t n, void* out) {
+int plan_mode_contract(Ctx& c, const rt_tensor* P, const rt_tensor* Q, int32_t n, bool acc, void* out) {
   int st = check_tensor(P, c.check_ptrs);
   if (st) return st;
   st = check_tensor(Q, c.check_ptrs);
@@ -609,7 +629,7 @@ int plan_mode_contract(Ctx& c, const rt_tensor* P, const rt_tensor* Q, int32_t n
   const Ten TP = ten_of(P);
   const int64_t A = TP.before(n), B = TP.after(n);
   void* w = c.take(mode_contract_ws(P->dtype, A, P->dims[n], Q->dims[n], B));
-  if (!c.dry) c.chk(launch_mode_contract(P->data, Q->data, P->dtype, A, P->dims[n], Q->dims[n], B, out, w, c.st));
+  if (!c.dry) c.chk(launch_mode_contract(P->data, Q->data, P->dtype, A, P->dims[n], Q->dims[n], B, out, w, c.st, acc));
   return RT_OK;
 }
 
@@ -767,25 +787,34 @@ int rtucker_multi_ttm(const rt_tensor* X, const void* const* A, const int64_t* m
 }
 
 int rtucker_mode_contract_workspace(const rt_tensor* P, const rt_tensor* Q, int32_t n, size_t* bytes) {
-  return query([&](Ctx& c) { return plan_mode_contract(c, P, Q, n, nullptr); }, bytes);
+  return query([&](Ctx& c) { return plan_mode_contract(c, P, Q, n, false, nullptr); }, bytes);
 }
 
-int rtucker_mode_contract(const rt_tensor* P, const rt_tensor* Q, int32_t n, void* out, void* ws, size_t ws_bytes,
-                          void* stream) {
-  return run([&](Ctx& c) { return plan_mode_contract(c, P, Q, n, out); }, ws, ws_bytes, stream);
+int rtucker_mode_contract(const rt_tensor* P, const rt_tensor* Q, int32_t n, int32_t accumulate, void* out, void* ws,
+                          size_t ws_bytes, void* stream) {
+  return run([&](Ctx& c) { return plan_mode_contract(c, P, Q, n, accumulate != 0, out); }, ws, ws_bytes, stream);
 }
 
 int rtucker_sq_residual(const rt_tensor* A, const void* B, void* R, double* out, void* ws, size_t ws_bytes,
                         void* stream) {
-  int st = check_tensor(A, true);
+  int64_t n = 0;
+  const int st = check_flat(A, &n);
   if (st) return st;
-  if (A->dtype != RT_F32 && A->dtype != RT_F64) return RT_EDTYPE;
-  if (!B || !out) return RT_EINVAL;
-  int64_t n = 1;
-  for (int k = 0; k < A->d; ++k) n *= A->dims[k];
+  if ((n > 0 && !B) || !out) return RT_EINVAL;
   const size_t need = sq_residual_ws(n);
   if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255u)) return RT_EWORKSPACE;
   return launch_sq_residual(A->data, B, R, A->dtype, n, out, ws, static_cast<hipStream_t>(stream)) == hipSuccess
+             ? RT_OK
+             : RT_EHIP;
+}
+
+int rtucker_scaled_diff(const rt_tensor* A, const void* B, const double* g, double alpha, void* out,
+                        void* stream) {
+  int64_t n = 0;
+  const int st = check_flat(A, &n);
+  if (st) return st;
+  if (n > 0 && !out) return RT_EINVAL;
+  return launch_scaled_diff(A->data, B, g, alpha, A->dtype, n, out, static_cast<hipStream_t>(stream)) == hipSuccess
              ? RT_OK
              : RT_EHIP;
 }

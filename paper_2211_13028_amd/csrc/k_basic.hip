@@ -113,6 +113,19 @@ __global__ __launch_bounds__(kThreads) void sq_residual_kernel(const T* a, const
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
+// out = alpha * g[0] * (a - b); g and b may be null (then 1 and 0)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void scaled_diff_kernel(const T* __restrict__ a, const T* __restrict__ b,
+                                                               const double* __restrict__ g, double alpha,
+                                                               int64_t n, T* __restrict__ out) {
+  const T f = static_cast<T>(g ? alpha * g[0] : alpha);
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n; i += stride) {
+    const T d = b ? a[i] - b[i] : a[i];
+    out[i] = f * d;
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void sum_partials_kernel(const double* partial, int count, double* out) {
   __shared__ double sh[kThreads / kWave];
   double acc = 0.0;
@@ -186,6 +199,20 @@ hipError_t launch_sq_residual(const void* a, const void* b, void* r, rt_dtype dt
     sq_residual_kernel<float><<<kReduceBlocks, kThreads, 0, st>>>(
         static_cast<const float*>(a), static_cast<const float*>(b), static_cast<float*>(r), n, partial);
   sum_partials_kernel<<<1, kThreads, 0, st>>>(partial, kReduceBlocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scaled_diff(const void* a, const void* b, const double* g, double alpha, rt_dtype dt, int64_t n,
+                              void* out, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  if (dt == RT_F64)
+    scaled_diff_kernel<double><<<grid_for(n), kThreads, 0, st>>>(static_cast<const double*>(a),
+                                                                static_cast<const double*>(b), g, alpha, n,
+                                                                static_cast<double*>(out));
+  else
+    scaled_diff_kernel<float><<<grid_for(n), kThreads, 0, st>>>(static_cast<const float*>(a),
+                                                               static_cast<const float*>(b), g, alpha, n,
+                                                               static_cast<float*>(out));
   return hipGetLastError();
 }
 

@@ -83,7 +83,8 @@ __global__ __launch_bounds__(kMCThreads) void mode_contract_kernel(const T* __re
 
 template <typename T>
 __global__ __launch_bounds__(256) void mode_contract_reduce(const T* __restrict__ part, int nchunks, int tiles,
-                                                            int tilesQ, int64_t mP, int64_t mQ, T* __restrict__ out) {
+                                                            int tilesQ, int64_t mP, int64_t mQ, bool accumulate,
+                                                            T* __restrict__ out) {
   const int64_t total = mP * mQ;
   for (int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; idx < total;
        idx += static_cast<int64_t>(gridDim.x) * 256) {
@@ -92,7 +93,7 @@ __global__ __launch_bounds__(256) void mode_contract_reduce(const T* __restrict_
     const int64_t off = (i % kMCTile) * kMCTile + (j % kMCTile);
     T s = T(0);
     for (int c = 0; c < nchunks; ++c) s += part[(static_cast<int64_t>(c) * tiles + tile) * kMCTile * kMCTile + off];
-    out[idx] = s;
+    out[idx] = accumulate ? out[idx] + s : s;
   }
 }
 
@@ -369,7 +370,7 @@ size_t mode_contract_ws(rt_dtype dt, int64_t A, int64_t mP, int64_t mQ, int64_t 
 }
 
 hipError_t launch_mode_contract(const void* P, const void* Q, rt_dtype dt, int64_t A, int64_t mP, int64_t mQ,
-                                int64_t B, void* out, void* ws, hipStream_t st) {
+                                int64_t B, void* out, void* ws, hipStream_t st, bool accumulate) {
   const MCPlan p = mc_plan(A, mP, mQ, B);
   const int tiles = p.tilesP * p.tilesQ;
   const dim3 grid(tiles, p.nchunks);
@@ -380,13 +381,13 @@ hipError_t launch_mode_contract(const void* P, const void* Q, rt_dtype dt, int64
                                                               static_cast<const double*>(Q), A, mP, mQ, B, p.chunk,
                                                               p.tilesQ, static_cast<double*>(ws));
     mode_contract_reduce<double><<<g2, 256, 0, st>>>(static_cast<const double*>(ws), p.nchunks, tiles, p.tilesQ, mP,
-                                                     mQ, static_cast<double*>(out));
+                                                     mQ, accumulate, static_cast<double*>(out));
   } else {
     mode_contract_kernel<float><<<grid, kMCThreads, 0, st>>>(static_cast<const float*>(P),
                                                              static_cast<const float*>(Q), A, mP, mQ, B, p.chunk,
                                                              p.tilesQ, static_cast<float*>(ws));
     mode_contract_reduce<float><<<g2, 256, 0, st>>>(static_cast<const float*>(ws), p.nchunks, tiles, p.tilesQ, mP,
-                                                    mQ, static_cast<float*>(out));
+                                                    mQ, accumulate, static_cast<float*>(out));
   }
   return hipGetLastError();
 }

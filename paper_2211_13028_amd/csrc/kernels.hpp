@@ -42,6 +42,9 @@ hipError_t launch_unfold(const void* src, size_t esize, int64_t A, int64_t m, in
 size_t sq_residual_ws(int64_t n);
 hipError_t launch_sq_residual(const void* a, const void* b, void* r, rt_dtype dt, int64_t n,
                               double* out, void* ws, hipStream_t st);
+// out[i] = alpha * g[0] * (a[i] - b[i]) in dt (F32 or F64); g null means 1, b null means 0.
+hipError_t launch_scaled_diff(const void* a, const void* b, const double* g, double alpha, rt_dtype dt,
+                              int64_t n, void* out, hipStream_t st);
 
 // ------------------------------------------------------------------ k_ttm.hip
 // Y[a, i, b] = sum_k M[i*K + k] * X[a, k, b] for i < m.
@@ -104,8 +107,10 @@ hipError_t launch_qr(const QRJob* jobs, int count, rt_dtype ydt, void* ws, hipSt
 // out[i][j] = sum_{a,b} P[a,i,b] * Q[a,j,b], P: (A, mP, B), Q: (A, mQ, B); same dtype
 // (F32 or F64); out in that dtype, mP x mQ row-major; deterministic two-stage sum.
 size_t mode_contract_ws(rt_dtype dt, int64_t A, int64_t mP, int64_t mQ, int64_t B);
+// With accumulate, out += P_(n) Q_(n)^T instead.
 hipError_t launch_mode_contract(const void* P, const void* Q, rt_dtype dt, int64_t A, int64_t mP,
-                                int64_t mQ, int64_t B, void* out, void* ws, hipStream_t st);
+                                int64_t mQ, int64_t B, void* out, void* ws, hipStream_t st,
+                                bool accumulate = false);
 
 // Symmetric eigendecomposition (cyclic Jacobi, binary64) of an n x n matrix
 // (n <= 64): V (n x r row-major) = eigenvectors of the r largest eigenvalues,

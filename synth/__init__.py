@@ -70,6 +70,12 @@ def random_tucker(dims, core_dims, noise_rel: float, seed: int = DATA_SEED, core
     return _add_noise(rng, x, noise_rel), core, factors
 
 
+def fixed_factors(dims, ranks, seed: int = FIXED_U_SEED):
+    """Orthonormal I_k x r_k factors drawn independently of any tensor (QR of N(0,1))."""
+    rng = np.random.default_rng(seed)
+    return [orthonormal(rng, int(n), int(r)) for n, r in zip(dims, ranks)]
+
+
 def superdiagonal(n: int, d: int = 3, rate: float = 0.4, terms: int | None = None, seed: int = DATA_SEED):
     """Super-diagonal core with entries rate**(i-1), rotated by random orthogonal matrices.
 
