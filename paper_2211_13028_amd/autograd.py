@@ -89,10 +89,13 @@ class SqResidual(torch.autograd.Function):
 class ProjectionLoss(torch.autograd.Function):
     """L = ||X - X_hat||^2 with G = X x_k U_k^T and X_hat = G x_k U_k (U_k: I_k x r_k).
 
-    Backward, with R = X - X_hat, g the incoming gradient and P R = (R x_k U_k^T) x_k U_k:
-        dX   = 2 g (R - P R)
-        dU_k = -2 g [ R_(k) Z_(k)^T + Z'_(k) (R x_j U_j^T)_(k)^T ]
-    where Z = G x_{j != k} U_j and Z' = X x_{j != k} U_j^T are recomputed.
+    Backward, with R = X - X_hat, g the incoming gradient, S_k = R x_{j != k} U_j^T,
+    Z'_k = X x_{j != k} U_j^T and RG = R x_j U_j^T:
+        dX   = 2 g (R - RG x_j U_j)
+        dU_k = -2 g [ (S_k)_(k) G_(k)^T + (Z'_k)_(k) RG_(k)^T ]
+    (the first term is R_(k) (G x_{j != k} U_j)_(k)^T with the expansion moved
+    onto R).  S_k and Z'_k are recomputed from two full-size passes each (over the
+    first and the last mode), shared by all k.
     """
 
     @staticmethod
@@ -107,29 +110,44 @@ class ProjectionLoss(torch.autograd.Function):
         return out.view(())
 
     @staticmethod
+    def _all_but_one(T, Us):
+        """[T x_{j != k} U_j^T for every k]: two passes over T (first and last mode)."""
+        d = T.dim()
+        L = d - 1
+
+        def shrink(src, modes):
+            if not modes:
+                return src
+            return rtucker_multi_ttm(src, [Us[j] if j in modes else None for j in range(d)], modes, True)
+
+        TL = shrink(T, [L])
+        T0 = shrink(T, [0])
+        outs = [shrink(TL, [j for j in range(L) if j != k]) for k in range(L)]
+        outs.append(shrink(T0, list(range(1, L))))
+        return outs
+
+    @staticmethod
     def backward(ctx, gL):
         X, G, R, *Us = ctx.saved_tensors
         d = X.dim()
         g = _contig(gL.reshape(1))
-        RG = rtucker_multi_ttm(R, Us, None, True)  # R x_k U_k^T (= dG / (-2 g))
+        need_u = any(ctx.needs_input_grad[1:])
+        S = ProjectionLoss._all_but_one(R, Us)
+        RG = rtucker_multi_ttm(S[0], [Us[0]] + [None] * (d - 1), [0], True)  # R x_j U_j^T (= dG / (-2 g))
         dX = None
         if ctx.needs_input_grad[0]:
             PR = rtucker_multi_ttm(RG, Us, None, False)
             dX = rtucker_scaled_diff(R, PR, g, 2.0)
             del PR
         dUs = [None] * d
-        for k in range(d):
-            if not ctx.needs_input_grad[1 + k]:
-                continue
-            rest = [U if j != k else None for j, U in enumerate(Us)]
-            others = [j for j in range(d) if j != k]
-            Z = rtucker_multi_ttm(G, rest, others, False) if others else G
-            acc = rtucker_mode_contract(R, Z, k)
-            del Z
-            Zp = rtucker_multi_ttm(X, rest, others, True) if others else X
-            rtucker_mode_contract(Zp, RG, k, out=acc)
-            del Zp
-            dUs[k] = rtucker_scaled_diff(acc, None, g, -2.0, out=acc)
+        if need_u:
+            Zp = ProjectionLoss._all_but_one(X, Us)
+            for k in range(d):
+                if not ctx.needs_input_grad[1 + k]:
+                    continue
+                acc = rtucker_mode_contract(S[k], G, k)
+                rtucker_mode_contract(Zp[k], RG, k, out=acc)
+                dUs[k] = rtucker_scaled_diff(acc, None, g, -2.0, out=acc)
         return (dX, *dUs)
 
 

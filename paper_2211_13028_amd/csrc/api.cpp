@@ -606,13 +606,34 @@ int plan_multi_ttm(Ctx& c, const rt_tensor* X, const void* const* A, const int64
   for (size_t i = 0; i < order.size(); ++i) {
     const int k = order[i];
     const void* M = A ? A[k] : nullptr;
-    if (trans) {
-      void* t = c.take(static_cast<size_t>(m[k]) * X->dims[k] * es);
-      if (!c.dry) c.chk(launch_unfold(A[k], es, X->dims[k], m[k], 1, t, c.st));
-      M = t;
+    void* dst = (i + 1 == order.size()) ? Y : nullptr;
+    const int64_t Ab = cur.before(k), K = cur.dims[k], Bb = cur.after(k);
+    const bool mf = X->dtype == RT_F32 && ttm_mfma_ok(RT_F32, Ab, K, Bb, m[k]);
+    const bool last = X->dtype == RT_F32 && !mf && Bb == 1 && ttm_mfma_last_ok(Ab, K, m[k]);
+    if (mf || last) {
+      // matrix cores: operand packed to a multiple of 16 rows, binary32 accumulation
+      const int64_t mp = ttm_mfma_mpad(m[k]);
+      float* op = static_cast<float*>(c.take(static_cast<size_t>(mp) * K * es));
+      Ten out;
+      out.dims = cur.dims;
+      out.dims[k] = m[k];
+      out.dt = RT_F32;
+      out.p = dst ? dst : c.take(static_cast<size_t>(Ab) * m[k] * Bb * es);
+      void* w = c.take(last ? ttm_mfma_last_ws(Ab, K, m[k]) : ttm_mfma_ws(RT_F32, Ab, K, Bb, m[k]));
+      if (!c.dry) {
+        float* y = static_cast<float*>(const_cast<void*>(out.p));
+        c.chk(launch_pack_f32(static_cast<const float*>(M), m[k], K, trans != 0, mp, op, c.st));
+        if (last)
+          c.chk(launch_ttm_mfma_last(static_cast<const float*>(cur.p), Ab, K, op, m[k], y, w, c.st));
+        else
+          c.chk(launch_ttm_mfma_ws(cur.p, RT_F32, Ab, K, Bb, op, m[k], y, w, c.st));
+      }
+      cur = out;
+    } else {
+      cur = ttm(c, cur, k, M, m[k], dst, trans != 0);
     }
-    cur = ttm(c, cur, k, M, m[k], (i + 1 == order.size()) ? Y : nullptr);
   }
+  (void)es;
   return RT_OK;
 }
 

@@ -71,6 +71,17 @@ __global__ __launch_bounds__(kThreads) void prep_batch_kernel(PrepTable tab) {
   }
 }
 
+// f32 operand of the matrix-core TTM from a caller's f32 matrix: rows >= m zero
+__global__ __launch_bounds__(kThreads) void pack_f32_kernel(const float* __restrict__ src, int64_t m, int64_t K,
+                                                            bool trans, int64_t m_pad, float* __restrict__ dst) {
+  const int64_t total = m_pad * K;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; t < total; t += stride) {
+    const int64_t i = t / K, k = t - i * K;
+    dst[t] = (i < m) ? (trans ? src[k * m + i] : src[i * K + k]) : 0.f;
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void unfold_kernel(const T* src, int64_t A, int64_t m, int64_t B, T* dst) {
   const int64_t total = A * m * B;
@@ -172,6 +183,13 @@ hipError_t launch_prep_batch(const PrepTask* tasks, int count, hipStream_t st) {
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_pack_f32(const float* src, int64_t m, int64_t K, bool trans, int64_t m_pad, float* dst,
+                           hipStream_t st) {
+  if (m_pad < m) m_pad = m;
+  pack_f32_kernel<<<grid_for(m_pad * K), kThreads, 0, st>>>(src, m, K, trans, m_pad, dst);
+  return hipGetLastError();
 }
 
 hipError_t launch_unfold(const void* src, size_t esize, int64_t A, int64_t m, int64_t B, void* dst,

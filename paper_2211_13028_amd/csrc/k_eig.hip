@@ -81,20 +81,117 @@ __global__ __launch_bounds__(kMCThreads) void mode_contract_kernel(const T* __re
     for (int v = 0; v < 4; ++v) out[(ty * 4 + u) * kMCTile + tx * 4 + v] = acc[u][v];
 }
 
+// out = sum over chunks of the partial tiles: 16 lanes per output element, each
+// summing every 16th chunk, then a fixed butterfly (deterministic order).
 template <typename T>
 __global__ __launch_bounds__(256) void mode_contract_reduce(const T* __restrict__ part, int nchunks, int tiles,
                                                             int tilesQ, int64_t mP, int64_t mQ, bool accumulate,
                                                             T* __restrict__ out) {
   const int64_t total = mP * mQ;
-  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; idx < total;
-       idx += static_cast<int64_t>(gridDim.x) * 256) {
-    const int64_t i = idx / mQ, j = idx - i * mQ;
+  const int sub = threadIdx.x % 16;
+  const int64_t idx = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) / 16;
+  const bool valid = idx < total;
+  T s = T(0);
+  int64_t i = 0, j = 0;
+  if (valid) {
+    i = idx / mQ;
+    j = idx - i * mQ;
     const int tile = static_cast<int>((i / kMCTile) * tilesQ + (j / kMCTile));
     const int64_t off = (i % kMCTile) * kMCTile + (j % kMCTile);
-    T s = T(0);
-    for (int c = 0; c < nchunks; ++c) s += part[(static_cast<int64_t>(c) * tiles + tile) * kMCTile * kMCTile + off];
-    out[idx] = accumulate ? out[idx] + s : s;
+    for (int c = sub; c < nchunks; c += 16) s += part[(static_cast<int64_t>(c) * tiles + tile) * kMCTile * kMCTile + off];
   }
+#pragma unroll
+  for (int o = 8; o >= 1; o >>= 1) s += __shfl_xor(s, o, 16);
+  if (valid && sub == 0) out[idx] = accumulate ? out[idx] + s : s;
+}
+
+// binary32 mode contraction on matrix cores.  A workgroup owns a 64 x 64 output
+// tile and a range of the contracted index t = (a, b); it stages 32 t at a time
+// of both operands in LDS (loads follow memory order: along b when rows are long,
+// along the mode index otherwise) and each wave accumulates a 16 x 64 strip with
+// 16x16x4 MFMAs.  Output: one 64 x 64 partial tile per (chunk, tile).
+typedef float mc_f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kMCT = 32;
+constexpr int kMCStride = kMCT + 1;
+
+__global__ __launch_bounds__(256) void mode_contract_mfma_kernel(const float* __restrict__ P,
+                                                                 const float* __restrict__ Q, int64_t A, int64_t mP,
+                                                                 int64_t mQ, int64_t B, int64_t chunk, int tilesQ,
+                                                                 float* __restrict__ part) {
+  __shared__ float sP[kMCTile * kMCStride];
+  __shared__ float sQ[kMCTile * kMCStride];
+  const int tile = blockIdx.x;
+  const int ti = tile / tilesQ, tj = tile % tilesQ;
+  const int64_t i0 = static_cast<int64_t>(ti) * kMCTile, j0 = static_cast<int64_t>(tj) * kMCTile;
+  const int64_t total = A * B;
+  const int64_t t0 = static_cast<int64_t>(blockIdx.y) * chunk;
+  const int64_t t1 = (t0 + chunk < total) ? t0 + chunk : total;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int r16 = lane % 16, q = lane / 16;
+  const int64_t nP = (mP - i0 < kMCTile) ? mP - i0 : kMCTile;  // valid rows of this tile
+  const int64_t nQ = (mQ - j0 < kMCTile) ? mQ - j0 : kMCTile;
+  const int njt = static_cast<int>((nQ + 15) / 16);
+  const bool wave_rows = 16 * wave < nP;
+  mc_f32x4 acc[4];
+#pragma unroll
+  for (int js = 0; js < 4; ++js) acc[js] = mc_f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const bool tfast = B >= kMCT;
+  // tfast: thread loads t = tb + (tid % 32) for rows tid/32 + 8 r;
+  // otherwise: row tid % 64, t = tb + tid/64 + 4 r (consecutive threads: consecutive rows)
+  const int lt = tfast ? threadIdx.x % kMCT : threadIdx.x / kMCTile;
+  const int li = tfast ? threadIdx.x / kMCT : threadIdx.x % kMCTile;
+  int64_t a = (t0 + lt) / B, b = (t0 + lt) - ((t0 + lt) / B) * B;
+  const int64_t da = 4 / B, db = 4 % B;  // a step of 4 in t, for rows shorter than 32
+  for (int64_t tb = t0; tb < t1; tb += kMCT) {
+    __syncthreads();
+    if (tfast) {
+      const int64_t t = tb + lt;
+      const bool tin = t < t1;
+      const float* pp = P + a * mP * B + (i0 + li) * B + b;
+      const float* qp = Q + a * mQ * B + (j0 + li) * B + b;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int ii = li + 8 * r;
+        sP[ii * kMCStride + lt] = (tin && ii < nP) ? pp[static_cast<int64_t>(8 * r) * B] : 0.f;
+        sQ[ii * kMCStride + lt] = (tin && ii < nQ) ? qp[static_cast<int64_t>(8 * r) * B] : 0.f;
+      }
+      b += kMCT;
+      if (b >= B) { b -= B; ++a; }
+    } else {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int tt = lt + 4 * r;
+        const bool tin = tb + tt < t1;
+        sP[li * kMCStride + tt] = (tin && li < nP) ? P[a * mP * B + (i0 + li) * B + b] : 0.f;
+        sQ[li * kMCStride + tt] = (tin && li < nQ) ? Q[a * mQ * B + (j0 + li) * B + b] : 0.f;
+        a += da;
+        b += db;
+        if (b >= B) { b -= B; ++a; }
+      }
+    }
+    __syncthreads();
+    if (wave_rows) {
+#pragma unroll
+      for (int k0 = 0; k0 < kMCT; k0 += 4) {
+        const float av = sP[(16 * wave + r16) * kMCStride + k0 + q];
+#pragma unroll
+        for (int js = 0; js < 4; ++js)
+          if (js < njt) {
+            const float bv = sQ[(16 * js + r16) * kMCStride + k0 + q];
+            acc[js] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[js], 0, 0, 0);
+          }
+      }
+    }
+  }
+  if (!wave_rows) return;
+  float* out = part + (static_cast<int64_t>(blockIdx.y) * gridDim.x + tile) * kMCTile * kMCTile;
+#pragma unroll
+  for (int js = 0; js < 4; ++js)
+    if (js < njt) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[(16 * wave + 4 * q + v) * kMCTile + 16 * js + r16] = acc[js][v];
+    }
 }
 
 struct MCPlan {
@@ -102,16 +199,20 @@ struct MCPlan {
   int64_t chunk;
 };
 
-MCPlan mc_plan(int64_t A, int64_t mP, int64_t mQ, int64_t B) {
+MCPlan mc_plan(rt_dtype dt, int64_t A, int64_t mP, int64_t mQ, int64_t B) {
   MCPlan p;
   p.tilesP = static_cast<int>(ceil_div(mP, kMCTile));
   p.tilesQ = static_cast<int>(ceil_div(mQ, kMCTile));
   const int64_t total = A * B;
-  int64_t want = 512 / (p.tilesP * p.tilesQ);
+  // binary32 runs on matrix cores and is bound by the operand read: aim for
+  // about 4 workgroups per CU; binary64 (small Gram matrices) keeps ~512
+  const int64_t target = (dt == RT_F32) ? 1024 : 512;
+  const int64_t gran = (dt == RT_F32) ? kMCT : kMCK;
+  int64_t want = target / (p.tilesP * p.tilesQ);
   if (want < 1) want = 1;
   int64_t chunk = ceil_div(total, want);
   if (chunk < 64) chunk = 64;
-  chunk = ceil_div(chunk, kMCK) * kMCK;
+  chunk = ceil_div(chunk, gran) * gran;
   p.chunk = chunk;
   p.nchunks = static_cast<int>(ceil_div(total, chunk));
   if (p.nchunks < 1) p.nchunks = 1;
@@ -365,17 +466,17 @@ __global__ __launch_bounds__(kJThreads) void eig_onesided_kernel(const double* _
 }  // namespace
 
 size_t mode_contract_ws(rt_dtype dt, int64_t A, int64_t mP, int64_t mQ, int64_t B) {
-  const MCPlan p = mc_plan(A, mP, mQ, B);
+  const MCPlan p = mc_plan(dt, A, mP, mQ, B);
   return align256(static_cast<size_t>(p.nchunks) * p.tilesP * p.tilesQ * kMCTile * kMCTile * dtype_size(dt));
 }
 
 hipError_t launch_mode_contract(const void* P, const void* Q, rt_dtype dt, int64_t A, int64_t mP, int64_t mQ,
                                 int64_t B, void* out, void* ws, hipStream_t st, bool accumulate) {
-  const MCPlan p = mc_plan(A, mP, mQ, B);
+  const MCPlan p = mc_plan(dt, A, mP, mQ, B);
   const int tiles = p.tilesP * p.tilesQ;
   const dim3 grid(tiles, p.nchunks);
   const int64_t n = mP * mQ;
-  const unsigned g2 = static_cast<unsigned>(ceil_div(n, 256) > 1024 ? 1024 : ceil_div(n, 256));
+  const unsigned g2 = static_cast<unsigned>(ceil_div(n * 16, 256));
   if (dt == RT_F64) {
     mode_contract_kernel<double><<<grid, kMCThreads, 0, st>>>(static_cast<const double*>(P),
                                                               static_cast<const double*>(Q), A, mP, mQ, B, p.chunk,
@@ -383,9 +484,8 @@ hipError_t launch_mode_contract(const void* P, const void* Q, rt_dtype dt, int64
     mode_contract_reduce<double><<<g2, 256, 0, st>>>(static_cast<const double*>(ws), p.nchunks, tiles, p.tilesQ, mP,
                                                      mQ, accumulate, static_cast<double*>(out));
   } else {
-    mode_contract_kernel<float><<<grid, kMCThreads, 0, st>>>(static_cast<const float*>(P),
-                                                             static_cast<const float*>(Q), A, mP, mQ, B, p.chunk,
-                                                             p.tilesQ, static_cast<float*>(ws));
+    mode_contract_mfma_kernel<<<grid, 256, 0, st>>>(static_cast<const float*>(P), static_cast<const float*>(Q), A,
+                                                    mP, mQ, B, p.chunk, p.tilesQ, static_cast<float*>(ws));
     mode_contract_reduce<float><<<g2, 256, 0, st>>>(static_cast<const float*>(ws), p.nchunks, tiles, p.tilesQ, mP,
                                                     mQ, accumulate, static_cast<float*>(out));
   }

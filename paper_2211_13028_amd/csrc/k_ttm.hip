@@ -26,7 +26,7 @@ __global__ __launch_bounds__(kGenThreads) void ttm_generic_kernel(const TX* __re
                                                                   int64_t B, const TC* __restrict__ M, int64_t m,
                                                                   int64_t kper, bool mtrans, TC* __restrict__ Y) {
   __shared__ TC sM[MT][kGenKC];
-  const int64_t col = static_cast<int64_t>(blockIdx.x) * kGenThreads + threadIdx.x;
+  const int64_t col = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t i0 = static_cast<int64_t>(blockIdx.y) * MT;
   const int64_t kb = static_cast<int64_t>(blockIdx.z) * kper;
   const int64_t ke = (kb + kper < K) ? kb + kper : K;
@@ -39,7 +39,7 @@ __global__ __launch_bounds__(kGenThreads) void ttm_generic_kernel(const TX* __re
   const TX* xp = X + a * K * B + b;
   for (int64_t k0 = kb; k0 < ke; k0 += kGenKC) {
     __syncthreads();
-    for (int t = threadIdx.x; t < MT * kGenKC; t += kGenThreads) {
+    for (int t = threadIdx.x; t < MT * kGenKC; t += blockDim.x) {
       const int ii = t / kGenKC, kk = t % kGenKC;
       sM[ii][kk] = (i0 + ii < m && k0 + kk < ke) ? (mtrans ? M[(k0 + kk) * m + i0 + ii] : M[(i0 + ii) * K + k0 + kk])
                                                  : TC(0);
@@ -85,17 +85,19 @@ template <typename TX, typename TC>
 hipError_t generic_dispatch(const TX* X, int64_t A, int64_t K, int64_t B, const TC* M, int64_t m, TC* Y, TC* ws,
                             hipStream_t st, bool mtrans) {
   const int64_t cols = A * B;
-  const unsigned gx = static_cast<unsigned>(ceil_div(cols, kGenThreads));
+  // few output columns: one-wave blocks, so that more CUs share the work
+  const int threads = cols < 32768 ? kWave : kGenThreads;
+  const unsigned gx = static_cast<unsigned>(ceil_div(cols, threads));
   const int ks = generic_ksplit(A, K, B);
   const int64_t kper = ceil_div(K, ks);
   TC* out = (ks > 1) ? ws : Y;
   if (m <= 4) {
-    ttm_generic_kernel<TX, TC, 4><<<dim3(gx, 1, ks), kGenThreads, 0, st>>>(X, A, K, B, M, m, kper, mtrans, out);
+    ttm_generic_kernel<TX, TC, 4><<<dim3(gx, 1, ks), threads, 0, st>>>(X, A, K, B, M, m, kper, mtrans, out);
   } else if (m <= 8) {
-    ttm_generic_kernel<TX, TC, 8><<<dim3(gx, 1, ks), kGenThreads, 0, st>>>(X, A, K, B, M, m, kper, mtrans, out);
+    ttm_generic_kernel<TX, TC, 8><<<dim3(gx, 1, ks), threads, 0, st>>>(X, A, K, B, M, m, kper, mtrans, out);
   } else {
     const unsigned gy = static_cast<unsigned>(ceil_div(m, 16));
-    ttm_generic_kernel<TX, TC, 16><<<dim3(gx, gy, ks), kGenThreads, 0, st>>>(X, A, K, B, M, m, kper, mtrans, out);
+    ttm_generic_kernel<TX, TC, 16><<<dim3(gx, gy, ks), threads, 0, st>>>(X, A, K, B, M, m, kper, mtrans, out);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || ks == 1) return e;
@@ -182,6 +184,64 @@ __global__ __launch_bounds__(kMfmaThreads) void ttm_mfma_f32_kernel(const float*
       }
     }
   }
+}
+
+// Last-mode contraction (B == 1): Y[a, i] = sum_k X[a, k] M[i, k], a GEMM with
+// the long contiguous rows of X as the reduction axis.  A wave owns 64 rows of X
+// (four 16-row MFMA tiles) and reads them with 16-byte loads along k; the packed
+// operand supplies the 16-row tiles of M.  Requires K % 4 == 0.
+template <int MT>
+__global__ __launch_bounds__(kMfmaThreads) void ttm_mfma_f32_last_kernel(const float* __restrict__ X, int64_t A,
+                                                                         int64_t K, const float* __restrict__ Mop,
+                                                                         int64_t m, int ksplit, int64_t kper,
+                                                                         float* __restrict__ Y) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t unit = static_cast<int64_t>(blockIdx.x) * (kMfmaThreads / kWave) + threadIdx.x / kWave;
+  const int64_t groups = (A + 63) / 64;
+  if (unit >= groups * ksplit) return;
+  const int ks = static_cast<int>(unit % ksplit);
+  const int64_t a0 = (unit / ksplit) * 64;
+  const int r16 = lane % 16, q = lane / 16;
+  const int64_t kbeg = ks * kper;
+  const int64_t kend = (kbeg + kper < K) ? kbeg + kper : K;
+  f32x4 acc[MT][4];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int at = 0; at < 4; ++at) acc[mt][at] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t k0 = kbeg; k0 < kend; k0 += 16) {
+    const int64_t k = k0 + 4 * q;
+    const bool kin = k < kend;
+    f32x4 xv[4], mv[MT];
+#pragma unroll
+    for (int at = 0; at < 4; ++at) {
+      const int64_t a = a0 + 16 * at + r16;
+      xv[at] = (kin && a < A) ? *reinterpret_cast<const f32x4*>(X + a * K + k) : f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+      mv[mt] = kin ? *reinterpret_cast<const f32x4*>(Mop + (16 * mt + r16) * K + k) : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int at = 0; at < 4; ++at)
+          acc[mt][at] = __builtin_amdgcn_mfma_f32_16x16x4f32(mv[mt][c], xv[at][c], acc[mt][at], 0, 0, 0);
+  }
+  float* y = Y + static_cast<int64_t>(ks) * A * m;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int at = 0; at < 4; ++at) {
+      const int64_t a = a0 + 16 * at + r16;
+      if (a >= A) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t i = 16 * mt + 4 * q + v;
+        if (i < m) y[a * m + i] = acc[mt][at][v];
+      }
+    }
 }
 
 __device__ __forceinline__ uint32_t pack_lo(uint32_t a, uint32_t b) { return (a & 0xffffu) | (b << 16); }
@@ -282,14 +342,26 @@ struct MfmaPlan {
   int64_t kper;
 };
 
-MfmaPlan mfma_plan(rt_dtype xdt, int64_t A, int64_t K, int64_t B) {
+MfmaPlan mfma_plan(rt_dtype xdt, int64_t A, int64_t K, int64_t B, int64_t m) {
   MfmaPlan p;
   p.chunks = ceil_div(B, kUnitCols);
   const int64_t units = A * p.chunks;
   const int64_t kgran = (xdt == RT_BF16) ? 32 : 4;
   int ks = 1;
-  // aim for >= 2048 waves (8 per CU) when K is long enough to split
-  while (units * ks < 2048 && (K / (ks * 2)) >= 256 && ks < 16) ks *= 2;
+  // aim for >= 2048 waves (8 per CU) when K is long enough to split; short K
+  // (>= 64 per part) is split too while the partial sums stay under a quarter
+  // of the input read
+  // (an input that stays in the caches may split down to 32 per part)
+  const int64_t in_bytes = A * K * B * (xdt == RT_BF16 ? 2 : 4);
+  const bool cached = in_bytes <= (int64_t(32) << 20);
+  while (units * ks < 2048 && ks < 16) {
+    const int64_t kp = K / (ks * 2);
+    const int64_t part_bytes = 2 * ks * A * m * B * 4;
+    if (kp >= 256 || (kp >= 64 && part_bytes * 4 <= in_bytes) || (cached && kp >= 32 && part_bytes <= in_bytes))
+      ks *= 2;
+    else
+      break;
+  }
   p.ksplit = ks;
   p.kper = ceil_div(ceil_div(K, ks), kgran) * kgran;
   return p;
@@ -335,14 +407,14 @@ bool ttm_mfma_ok(rt_dtype xdt, int64_t A, int64_t K, int64_t B, int64_t m) {
 }
 
 size_t ttm_mfma_ws(rt_dtype xdt, int64_t A, int64_t K, int64_t B, int64_t m) {
-  const MfmaPlan p = mfma_plan(xdt, A, K, B);
+  const MfmaPlan p = mfma_plan(xdt, A, K, B, m);
   if (p.ksplit == 1) return 0;
   return align256(static_cast<size_t>(p.ksplit) * A * m * B * sizeof(float));
 }
 
 hipError_t launch_ttm_mfma_ws(const void* X, rt_dtype xdt, int64_t A, int64_t K, int64_t B, const void* Mop,
                               int64_t m, float* Y, void* ws, hipStream_t st) {
-  const MfmaPlan p = mfma_plan(xdt, A, K, B);
+  const MfmaPlan p = mfma_plan(xdt, A, K, B, m);
   float* out = (p.ksplit == 1) ? Y : static_cast<float*>(ws);
   const int64_t units = A * p.chunks * p.ksplit;
   const unsigned grid = static_cast<unsigned>(ceil_div(units, kMfmaThreads / kWave));
@@ -375,6 +447,53 @@ hipError_t launch_ttm_mfma_ws(const void* X, rt_dtype xdt, int64_t A, int64_t K,
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || p.ksplit == 1) return e;
   const int64_t n = A * m * B;
+  const unsigned g2 = static_cast<unsigned>(ceil_div(n, 256) > 8192 ? 8192 : ceil_div(n, 256));
+  sum_splits_kernel<<<g2, 256, 0, st>>>(out, p.ksplit, n, Y);
+  return hipGetLastError();
+}
+
+bool ttm_mfma_last_ok(int64_t A, int64_t K, int64_t m) { return A >= 1 && m >= 1 && m <= 64 && K >= 4 && K % 4 == 0; }
+
+namespace {
+struct LastPlan {
+  int ksplit;
+  int64_t kper;
+};
+LastPlan last_plan(int64_t A, int64_t K, int64_t m) {
+  LastPlan p;
+  const int64_t units = ceil_div(A, 64);
+  int ks = 1;
+  while (units * ks < 2048 && K / (ks * 2) >= 64 && ks < 16 && 2 * ks * A * m * 4 <= A * K * 4) ks *= 2;
+  p.ksplit = ks;
+  p.kper = ceil_div(ceil_div(K, ks), 16) * 16;
+  return p;
+}
+}  // namespace
+
+size_t ttm_mfma_last_ws(int64_t A, int64_t K, int64_t m) {
+  const LastPlan p = last_plan(A, K, m);
+  return p.ksplit == 1 ? 0 : align256(static_cast<size_t>(p.ksplit) * A * m * sizeof(float));
+}
+
+hipError_t launch_ttm_mfma_last(const float* X, int64_t A, int64_t K, const float* Mop, int64_t m, float* Y,
+                                void* ws, hipStream_t st) {
+  const LastPlan p = last_plan(A, K, m);
+  float* out = (p.ksplit == 1) ? Y : static_cast<float*>(ws);
+  const int64_t units = ceil_div(A, 64) * p.ksplit;
+  const unsigned grid = static_cast<unsigned>(ceil_div(units, kMfmaThreads / kWave));
+  const int MT = static_cast<int>(ttm_mfma_mpad(m) / 16);
+#define RT_LAUNCH_LAST(MTV) \
+  ttm_mfma_f32_last_kernel<MTV><<<grid, kMfmaThreads, 0, st>>>(X, A, K, Mop, m, p.ksplit, p.kper, out)
+  switch (MT) {
+    case 1: RT_LAUNCH_LAST(1); break;
+    case 2: RT_LAUNCH_LAST(2); break;
+    case 3: RT_LAUNCH_LAST(3); break;
+    default: RT_LAUNCH_LAST(4); break;
+  }
+#undef RT_LAUNCH_LAST
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || p.ksplit == 1) return e;
+  const int64_t n = A * m;
   const unsigned g2 = static_cast<unsigned>(ceil_div(n, 256) > 8192 ? 8192 : ceil_div(n, 256));
   sum_splits_kernel<<<g2, 256, 0, st>>>(out, p.ksplit, n, Y);
   return hipGetLastError();

@@ -34,6 +34,10 @@ struct PrepTable {
 };
 hipError_t launch_prep_batch(const PrepTask* tasks, int count, hipStream_t st);
 
+// dst (m_pad x K row-major, binary32) = src (m x K, or K x m with trans), rows >= m zero.
+hipError_t launch_pack_f32(const float* src, int64_t m, int64_t K, bool trans, int64_t m_pad, float* dst,
+                           hipStream_t st);
+
 // dst[i * (A*B) + a*B + b] = src[a*m*B + i*B + b]   (mode-n unfolding of an (A, m, B) view)
 hipError_t launch_unfold(const void* src, size_t esize, int64_t A, int64_t m, int64_t B, void* dst,
                          hipStream_t st);
@@ -66,6 +70,13 @@ int64_t ttm_mfma_mpad(int64_t m);
 size_t ttm_mfma_ws(rt_dtype xdt, int64_t A, int64_t K, int64_t B, int64_t m);
 hipError_t launch_ttm_mfma_ws(const void* X, rt_dtype xdt, int64_t A, int64_t K, int64_t B,
                               const void* Mop, int64_t m, float* Y, void* ws, hipStream_t st);
+
+// Matrix-core contraction of the last mode (B == 1): Y[a, i] = sum_k X[a, k] Mop[i, k],
+// X binary32 A x K row-major, Mop packed to ttm_mfma_mpad(m) rows; K % 4 == 0, m <= 64.
+bool ttm_mfma_last_ok(int64_t A, int64_t K, int64_t m);
+size_t ttm_mfma_last_ws(int64_t A, int64_t K, int64_t m);
+hipError_t launch_ttm_mfma_last(const float* X, int64_t A, int64_t K, const float* Mop, int64_t m, float* Y,
+                                void* ws, hipStream_t st);
 
 // ------------------------------------------------------------------ k_sketch.hip
 // First level of the sketch dimension tree over X viewed as (A, P, Q):

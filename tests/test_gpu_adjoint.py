@@ -186,3 +186,28 @@ def test_scaled_diff_and_sq_residual():
         assert abs(float(host(s)[0]) - want) <= 1e-12 * want
     empty = torch.empty(0, dtype=torch.float32, device="cuda:0")
     rt.rtucker_scaled_diff(empty)
+
+
+@pytest.mark.parametrize("dt,tol", [(torch.float64, 1e-13), (torch.float32, 3e-6)])
+@pytest.mark.parametrize("shapeP,shapeQ,n", [
+    ((256, 64, 48), (24, 64, 48), 0),     # long contiguous rows
+    ((40, 130, 3), (40, 70, 3), 1),       # rows of 3: loads along the mode index
+    ((33, 17, 200), (33, 17, 5), 2),      # last mode: rows of 1
+    ((7, 2, 9, 65), (7, 2, 9, 1), 3),
+    ((2, 1000), (3, 1000), 0),
+    ((1000, 2), (1000, 3), 1),
+    ((5, 300, 37), (5, 9, 37), 1),        # 37-long rows, ragged 32-wide stages
+])
+def test_mode_contract_layouts(dt, tol, shapeP, shapeQ, n):
+    say("mode_contract", shapeP, shapeQ, n, dt)
+    rng = np.random.default_rng(41)
+    Pm, Qm = rng.standard_normal(shapeP), rng.standard_normal(shapeQ)
+    from oracle import tucker as T
+    want = T.unfold(Pm, n) @ T.unfold(Qm, n).T
+    got = rt.rtucker_mode_contract(dev(Pm, dt), dev(Qm, dt), n)
+    assert _rel(host(got), want) <= tol
+    # accumulate into an existing result
+    base = rng.standard_normal(want.shape)
+    acc = dev(base, dt)
+    rt.rtucker_mode_contract(dev(Pm, dt), dev(Qm, dt), n, out=acc)
+    assert _rel(host(acc), base + want) <= tol
