@@ -122,31 +122,43 @@ __global__ __launch_bounds__(256) void sum_parts_kernel(const TC* __restrict__ p
 }
 
 // ------------------------------------------------------------------ bfloat16 on matrix cores
-// Same two contractions on MFMA (v_mfma_f32_16x16x32_bf16, binary32 accumulation):
-//  * W^T tile: out[c][q] = sum_p PhiP[c][p] X[p][q].  Each lane loads an 8 x 8 block
-//    (8 rows, 8 consecutive columns, 16 bytes per row) and re-packs it in registers
-//    into 8 operands holding 8 consecutive p of one column.
-//  * Z tile: out[p][c] = sum_q X[p][q] PhiQ[c][q]: X rows are the A operand
-//    directly (8 consecutive q per lane), read a second time from L1.
-// A wave handles 32-row blocks over a range of up to 512 columns; rows beyond P
-// and operand rows beyond s are zero.  Requires P % 8 == 0, Q % 8 == 0, s <= 8.
+// Same two contractions on MFMA (v_mfma_f32_16x16x32_bf16, binary32 accumulation).
+// A workgroup of four waves covers 512 columns of a row range; wave w owns the
+// 128 columns q0 + 128 w .. + 127 and all waves step through the rows together,
+// 32 at a time:
+//  * W^T tile: out[c][q] = sum_p PhiP[c][p] X[p][q].  Each lane loads an 8 x 8
+//    block (8 rows, 8 consecutive columns, 16 bytes per row) and re-packs it in
+//    registers into 8 operands holding 8 consecutive p of one column; the wave
+//    keeps its 16 x 128 accumulator for the whole row range (no cross-wave sum).
+//  * Z tile: out[p][c] = sum_q X[p][q] PhiQ[c][q] over the wave's 128 columns,
+//    with the X rows staged row-major in the wave's LDS area as the A operand;
+//    the four waves' partial Z rows are added in LDS in a fixed order, one
+//    barrier per step (double-buffered partials).
+// The next 32 rows are loaded while the current ones are used.  Rows beyond P and
+// operand rows beyond s are zero.  Requires P % 8 == 0, Q % 8 == 0, s <= 8.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kZWColsMfma = 512;
+constexpr int kTileStride = 136;  // bf16 per staged row: 128 columns + 8 padding (spreads LDS banks)
 
 __device__ __forceinline__ u32x4 ld16(const bf16_t* p) { return *reinterpret_cast<const u32x4*>(p); }
 
-constexpr int kTileStride = 136;  // bf16 per staged row: 128 columns + 8 padding (spreads LDS banks)
+__device__ __forceinline__ void load_block(const bf16_t* xa, int64_t Q, int64_t p0, int64_t pend, int64_t qc,
+                                           bool colok, u32x4 (&r)[8]) {
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int64_t p = p0 + t;
+    r[t] = (colok && p < pend) ? ld16(xa + p * Q + qc) : u32x4{0u, 0u, 0u, 0u};
+  }
+}
 
-__global__ __launch_bounds__(kZWThreads) void sketch_zw_bf16_mfma_kernel(
+__global__ __launch_bounds__(kZWThreads) __attribute__((amdgpu_waves_per_eu(3))) void sketch_zw_bf16_mfma_kernel(
     const bf16_t* __restrict__ X, int64_t A, int64_t P, int64_t Q, const bf16_t* __restrict__ phiP, int sP,
     const bf16_t* __restrict__ phiQ, int sQ, int64_t rows_per_block, int qblocks, int pblocks,
     float* __restrict__ Zo, float* __restrict__ Wo) {
-  // per wave: one 32 x 128 tile staged row-major; after the loop the same memory
-  // holds the sP x 512 sum of the waves' W partials
   __shared__ bf16_t tile[kZWWaves][32 * kTileStride];
-  float* sW = reinterpret_cast<float*>(&tile[0][0]);
+  __shared__ float zpart[2][kZWWaves][32 * 16];
   const int lane = threadIdx.x % kWave;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int64_t blk = blockIdx.x;
@@ -156,108 +168,93 @@ __global__ __launch_bounds__(kZWThreads) void sketch_zw_bf16_mfma_kernel(
   const int64_t a = rest / pblocks;
   const int64_t q0 = static_cast<int64_t>(qblk) * kZWColsMfma;
   const int64_t qend = (q0 + kZWColsMfma < Q) ? q0 + kZWColsMfma : Q;
+  const int64_t qw = q0 + 128 * wave;  // this wave's columns
   const bool needZ = Zo != nullptr, needW = Wo != nullptr;
   const int li = lane % 16, kg = lane / 16;
   const int64_t pbeg = static_cast<int64_t>(pblk) * rows_per_block;
   const int64_t pend = (pbeg + rows_per_block < P) ? pbeg + rows_per_block : P;
   const bf16_t* xa = X + a * P * Q;
-  float* zrow = needZ ? Zo + (static_cast<int64_t>(qblk) * A + a) * P * sQ : nullptr;
   bf16_t* my = tile[wave];
+  const int64_t qc = qw + 8 * li;
+  const bool colok = qc < qend;
 
-  f32x4 wacc[4][8];
+  // loop-invariant PhiQ operands of the Z product: row c = li, 8 columns per k group
+  u32x4 bq[4];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int ks = 0; ks < 4; ++ks) {
+    const int64_t qk = qw + 32 * ks + 8 * kg;
+    bq[ks] = (needZ && qk < qend) ? ld16(phiQ + static_cast<int64_t>(li) * Q + qk) : u32x4{0u, 0u, 0u, 0u};
+  }
+  f32x4 wacc[8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) wacc[u][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int c = 0; c < 8; ++c) wacc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  for (int64_t pb = pbeg + 32 * wave; pb < pend; pb += 32 * kZWWaves) {
-    // PhiP operand: row c = li, columns pb + 8 kg .. + 7 (8-row groups lie wholly inside or
-    // outside [pbeg, pend) because P % 8 == 0 and blocks are multiples of 32 rows)
-    const int64_t pc = pb + 8 * kg;
-    const u32x4 pp = (needW && pc < pend) ? ld16(phiP + static_cast<int64_t>(li) * P + pc) : u32x4{0u, 0u, 0u, 0u};
-    f32x4 zacc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+  u32x4 rn[8];
+  load_block(xa, Q, pbeg + 8 * kg, pend, qc, colok, rn);
+  int buf = 0;
+  for (int64_t pb = pbeg; pb < pend; pb += 32) {
+    u32x4 r[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t qb = q0 + 128 * u;
-      if (qb >= qend) break;
-      // 8 x 8 block per lane: rows pb + 8 kg + t, columns qb + 8 li .. + 7
-      const int64_t qc = qb + 8 * li;
-      u32x4 r[8];
+    for (int t = 0; t < 8; ++t) r[t] = rn[t];
+    if (pb + 32 < pend) load_block(xa, Q, pb + 32 + 8 * kg, pend, qc, colok, rn);
+    if (needW) {
+      // PhiP operand: row c = li, columns pb + 8 kg .. + 7 (8-row groups lie wholly
+      // inside or outside [pbeg, pend) because P % 8 == 0 and steps are 32 rows)
+      const int64_t pc = pb + 8 * kg;
+      const u32x4 pp = (pc < pend) ? ld16(phiP + static_cast<int64_t>(li) * P + pc) : u32x4{0u, 0u, 0u, 0u};
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int64_t p = pb + 8 * kg + t;
-        r[t] = (p < pend && qc < qend) ? ld16(xa + p * Q + qc) : u32x4{0u, 0u, 0u, 0u};
-      }
-      if (needZ) {  // stage the tile row-major for the Z operand
-        __builtin_amdgcn_wave_barrier();  // previous step's reads of the staging area stay above
+      for (int c = 0; c < 8; ++c) {
+        u32x4 op;
 #pragma unroll
-        for (int t = 0; t < 8; ++t)
-          *reinterpret_cast<u32x4*>(my + (8 * kg + t) * kTileStride + 8 * li) = r[t];
-        __builtin_amdgcn_wave_barrier();  // cross-lane: stores before the reads below
-      }
-      if (needW) {
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          u32x4 op;
-#pragma unroll
-          for (int w = 0; w < 4; ++w) {
-            const uint32_t lo = r[2 * w][c / 2], hi = r[2 * w + 1][c / 2];
-            op[w] = (c % 2 == 0) ? ((lo & 0xffffu) | (hi << 16)) : ((lo >> 16) | (hi & 0xffff0000u));
-          }
-          wacc[u][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, pp),
-                                                                __builtin_bit_cast(bf16x8, op), wacc[u][c], 0, 0, 0);
+        for (int w = 0; w < 4; ++w) {
+          const uint32_t lo = r[2 * w][c / 2], hi = r[2 * w + 1][c / 2];
+          op[w] = (c % 2 == 0) ? ((lo & 0xffffu) | (hi << 16)) : ((lo >> 16) | (hi & 0xffff0000u));
         }
-      }
-      if (needZ) {
-        // the wave reads back its own staging area (LDS operations of a wave complete in order)
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          const int64_t qk = qb + 32 * ks + 8 * kg;
-          const u32x4 bq = (qk < qend) ? ld16(phiQ + static_cast<int64_t>(li) * Q + qk) : u32x4{0u, 0u, 0u, 0u};
-#pragma unroll
-          for (int mt = 0; mt < 2; ++mt) {
-            const u32x4 xr = *reinterpret_cast<const u32x4*>(my + (16 * mt + li) * kTileStride + 32 * ks + 8 * kg);
-            zacc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, xr),
-                                                                __builtin_bit_cast(bf16x8, bq), zacc[mt], 0, 0, 0);
-          }
-        }
+        wacc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, pp),
+                                                          __builtin_bit_cast(bf16x8, op), wacc[c], 0, 0, 0);
       }
     }
-    if (needZ && li < sQ) {
+    if (needZ) {
+      __builtin_amdgcn_wave_barrier();  // the previous step's reads of the staging area stay above
+#pragma unroll
+      for (int t = 0; t < 8; ++t) *reinterpret_cast<u32x4*>(my + (8 * kg + t) * kTileStride + 8 * li) = r[t];
+      __builtin_amdgcn_wave_barrier();  // cross-lane: stores before the reads below
+      f32x4 zacc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+          const u32x4 xr = *reinterpret_cast<const u32x4*>(my + (16 * mt + li) * kTileStride + 32 * ks + 8 * kg);
+          zacc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, xr),
+                                                              __builtin_bit_cast(bf16x8, bq[ks]), zacc[mt], 0, 0, 0);
+        }
+      // partial Z rows of this wave: D layout row 16 mt + 4 kg + v, column c = li
+      float* zp = zpart[buf][wave];
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t p = pb + 16 * mt + 4 * kg + v;
-          if (p < pend) zrow[p * sQ + li] = zacc[mt][v];
-        }
+        for (int v = 0; v < 4; ++v) zp[(16 * mt + 4 * kg + v) * 16 + li] = zacc[mt][v];
+      __syncthreads();
+      // wave w finishes rows 8 w .. 8 w + 7 of the step: lane -> (row, c < 8)
+      const int row = 8 * wave + lane / 8, c = lane % 8;
+      const int64_t p = pb + row;
+      float z = zpart[buf][0][row * 16 + c];
+#pragma unroll
+      for (int w = 1; w < kZWWaves; ++w) z += zpart[buf][w][row * 16 + c];
+      if (c < sQ && p < pend) Zo[((static_cast<int64_t>(qblk) * A + a) * P + p) * sQ + c] = z;
+      buf ^= 1;
     }
   }
-  if (!needW) return;
-  // fixed-order sum of the four waves' partials (the staging tiles are reused)
-  __syncthreads();
-  for (int w = 0; w < kZWWaves; ++w) {
-    if (wave == w) {
-#pragma unroll
-      for (int uu = 0; uu < 4; ++uu)
-#pragma unroll
-        for (int c = 0; c < 8; ++c)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int cp = 4 * kg + v;
-            if (cp < sP) {
-              float* dst = &sW[cp * kZWColsMfma + 128 * uu + 8 * li + c];
-              *dst = (w == 0) ? wacc[uu][c][v] : *dst + wacc[uu][c][v];
-            }
-          }
-    }
-    __syncthreads();
-  }
+  if (!needW || !colok) return;
+  // W^T accumulators: row cp = 4 kg + v, column qc + c
   float* wout = Wo + (static_cast<int64_t>(pblk) * A + a) * sP * Q;
-  for (int idx = threadIdx.x; idx < sP * kZWColsMfma; idx += kZWThreads) {
-    const int c = idx / kZWColsMfma, col = idx % kZWColsMfma;
-    const int64_t q = q0 + col;
-    if (q < qend) wout[c * Q + q] = sW[idx];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int cp = 4 * kg + v;
+    if (cp >= sP) continue;
+    float* dst = wout + static_cast<int64_t>(cp) * Q + qc;
+    *reinterpret_cast<f32x4*>(dst) = f32x4{wacc[0][v], wacc[1][v], wacc[2][v], wacc[3][v]};
+    *reinterpret_cast<f32x4*>(dst + 4) = f32x4{wacc[4][v], wacc[5][v], wacc[6][v], wacc[7][v]};
   }
 }
 
@@ -310,15 +307,38 @@ ZWPlan sketch_zw_plan(rt_dtype xdt, int64_t A, int64_t P, int64_t Q, int64_t sP,
   p.mfma = (xdt == RT_BF16) && (P % 8 == 0) && (Q % 8 == 0) && P >= 32;
   const int nq = pick_nq(xdt, Q);
   p.qblocks = p.mfma ? ceil_div(Q, kZWColsMfma) : ceil_div(Q, 64 * nq);
-  int64_t pb = 1;
-  const int64_t target = 2048;
-  if (A * p.qblocks < target) pb = ceil_div(target, A * p.qblocks);
-  const int64_t rows_min = p.mfma ? 128 : 16;  // keep at least this many rows per block
-  const int64_t maxpb = ceil_div(P, rows_min);
-  if (pb > maxpb) pb = maxpb;
-  if (pb < 1) pb = 1;
-  p.rows_per_block = ceil_div(P, pb);
-  if (p.mfma) p.rows_per_block = ceil_div(p.rows_per_block, 32) * 32;
+  if (p.mfma) {
+    // Row split for the matrix-core pass: 768 workgroups are resident at once
+    // (3 per CU).  Cost in units of "one row per resident workgroup":
+    //   rounds(pb) * rows_per_block  +  partial-W traffic of pb row ranges,
+    // with the W partials (written and re-read, binary32) converted at the
+    // 1 KiB of X that one row of 512 bfloat16 columns is.
+    const int64_t resident = 768;
+    const double row_bytes = static_cast<double>(resident) * kZWColsMfma * 2;
+    double best = 0.0;
+    int64_t best_rows = 0;
+    for (int64_t pb = 1; pb <= 64; ++pb) {
+      const int64_t rows = ceil_div(ceil_div(P, pb), 32) * 32;
+      const int64_t pbs = ceil_div(P, rows);
+      if (pbs != pb || (pb > 1 && rows < 128)) continue;
+      const int64_t wgs = A * p.qblocks * pb;
+      const double t = static_cast<double>(ceil_div(wgs, resident)) * rows +
+                       (pb > 1 && needW ? 2.0 * pb * A * sP * Q * 4.0 / row_bytes : 0.0);
+      if (best_rows == 0 || t < best) {
+        best = t;
+        best_rows = rows;
+      }
+    }
+    p.rows_per_block = best_rows ? best_rows : ceil_div(P, 32) * 32;
+  } else {
+    int64_t pb = 1;
+    const int64_t target = 2048;
+    if (A * p.qblocks < target) pb = ceil_div(target, A * p.qblocks);
+    const int64_t maxpb = ceil_div(P, 16);  // keep at least 16 rows per block
+    if (pb > maxpb) pb = maxpb;
+    if (pb < 1) pb = 1;
+    p.rows_per_block = ceil_div(P, pb);
+  }
   p.pblocks = ceil_div(P, p.rows_per_block);
   const size_t esz = (xdt == RT_F64) ? 8 : 4;
   size_t ws = 0;
