@@ -221,21 +221,24 @@ MCPlan mc_plan(rt_dtype dt, int64_t A, int64_t mP, int64_t mQ, int64_t B) {
 
 // ------------------------------------------------------------------ eigensolver
 // Eigenvectors of the symmetric positive semidefinite Gram matrix M = G_(j) G_(j)^T:
-//  1. pivoted outer-product Cholesky M = L L^T (columns of L taken in order of
-//     decreasing remaining diagonal; rows stay in the original order);
+//  1. Cholesky with complete (diagonal) pivoting, M(p, p) = L L^T, taking at each
+//     step the largest remaining diagonal entry; this is the R factor of a
+//     column-pivoted QR of G_(j)^T, so L is strongly graded;
 //  2. one-sided (Hestenes) Jacobi on the columns of L: rotate column pairs until
 //     all are mutually orthogonal, so L V = U S with U the eigenvectors of M and
 //     S^2 its eigenvalues (no V is accumulated: the rotated columns are U S).
-// The pivoting grades L, which cuts the number of sweeps roughly in half
-// compared with two-sided Jacobi on M, and the left singular vectors of L are
-// more accurate than eigenvectors of M computed directly.  One round applies the
-// rotations of all disjoint pairs of the circle-method pairing; each pair is
-// owned by 8 lanes (8 rows each), so a round needs one barrier.
+// Jacobi on the transposed R factor of a pivoted QR converges in a few sweeps,
+// and the left singular vectors of L are more accurate than eigenvectors of M
+// computed directly.  One round applies the rotations of all disjoint pairs of
+// the circle-method pairing; each pair is owned by 8 lanes (8 rows each), so a
+// round needs one barrier.  Rotation parameters use only reciprocal square
+// roots (hardware estimate + two Newton steps), no division or square root.
 constexpr int kJN = 64;
 constexpr int kJThreads = 256;
 constexpr int kPairLanes = 8;
 constexpr int kMaxSweeps = 30;
 constexpr int kLStride = 72;  // doubles per column of L in LDS (padding spreads banks)
+constexpr int kAStride = 65;  // doubles per row of the working matrix
 
 // DPP moves on the two halves of a binary64 value
 template <int CTRL>
@@ -279,12 +282,28 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
   return __longlong_as_double((static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo));
 }
 
+// 1/sqrt(x) for normal x > 0: hardware estimate refined by two Newton steps
+// (each roughly doubles the correct bits), accurate to a few units in the last place.
+__device__ __forceinline__ double rsq_refined(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(x * y, y, -1.0);  // x y^2 - 1
+    y = fma(-0.5 * y, e, y);
+  }
+  return y;
+}
+
 __global__ __launch_bounds__(kJThreads) void eig_onesided_kernel(const double* __restrict__ M, int n, int r,
                                                                  double* __restrict__ Vout,
                                                                  double* __restrict__ evals) {
-  __shared__ double Lc[kJN * kLStride];  // columns of L: Lc[col * kLStride + row] (rows in sorted order)
+  __shared__ double Am[kJN * kAStride];  // Schur complement during the Cholesky (original indices)
+  __shared__ double Lc[kJN * kLStride];  // columns of L: Lc[col * kLStride + row] (original row order)
+  __shared__ double lcol[kJN];
   __shared__ double nrm[kJN];
-  __shared__ int perm[kJN];              // sorted position -> original index
+  __shared__ int used[kJN];
+  __shared__ int piv_sh;
+  __shared__ double pivd_sh;
   __shared__ int rotated;
   __shared__ int order[kJN];
   __shared__ int rank_sh;
@@ -292,51 +311,66 @@ __global__ __launch_bounds__(kJThreads) void eig_onesided_kernel(const double* _
   const int tid = threadIdx.x;
   const int lane = tid % kWave;
   for (int idx = tid; idx < kJN * kLStride; idx += kJThreads) Lc[idx] = 0.0;
-  // ---- 0. symmetric permutation sorting the diagonal decreasingly (a one-off pivot order)
-  if (tid < kWave) {
-    const double di = (lane < n) ? M[lane * n + lane] : -1.0;
-    int rk = 0;
-    for (int j = 0; j < n; ++j) {
-      const double dj = M[j * n + j];
-      if (dj > di || (dj == di && j < lane)) ++rk;
-    }
-    if (lane < n) perm[rk] = lane;
+  for (int idx = tid; idx < n * n; idx += kJThreads) {
+    const int i = idx / n, j = idx - (idx / n) * n;
+    Am[i * kAStride + j] = M[idx];
   }
+  if (tid < kJN) used[tid] = (tid < n) ? 0 : 1;
+  if (tid == 0) rank_sh = n;
   __syncthreads();
-  // ---- 1. Cholesky of the permuted matrix by wave 0, column j of A in lane j's registers;
-  //         row k of L is broadcast with readlane (static register indices: loop unrolled)
+  // ---- 1. Cholesky with complete pivoting; column k of L is stored in original row order
+  double dmax = 0.0;
   if (tid < kWave) {
-    const int j = lane;
-    const int pj = (j < n) ? perm[j] : 0;
-    double a[kJN];
+    double dv = (lane < n) ? Am[lane * kAStride + lane] : 0.0;
+    int di = lane;
+    argmax_row16(dv, di);
+    dmax = fmax(fmax(readlane_f64(dv, 0), readlane_f64(dv, 16)), fmax(readlane_f64(dv, 32), readlane_f64(dv, 48)));
+  }
+  for (int k = 0; k < n; ++k) {
+    if (tid < kWave) {
+      double dv = (used[lane] == 0) ? Am[lane * kAStride + lane] : -1.0;
+      int di = lane;
+      argmax_row16(dv, di);
+      // combine the four rows of 16 lanes in a fixed order (ties: lowest index)
+      double best = readlane_f64(dv, 0);
+      int bi = __builtin_amdgcn_readlane(di, 0);
 #pragma unroll
-    for (int i = 0; i < kJN; ++i) a[i] = (i < n && j < n) ? M[perm[i < n ? i : 0] * n + pj] : 0.0;
-    double dmax = 0.0;
-#pragma unroll
-    for (int i = 0; i < kJN; ++i) dmax = fmax(dmax, readlane_f64(a[i], i));
-    int rank = n;
-#pragma unroll
-    for (int k = 0; k < kJN; ++k) {
-      if (k < n && rank == n) {
-        const double d = readlane_f64(a[k], k);
-        if (!(d > 1e-300 && d > 1e-30 * dmax)) {
-          rank = k;
+      for (int row = 1; row < 4; ++row) {
+        const double ov = readlane_f64(dv, 16 * row);
+        const int oi = __builtin_amdgcn_readlane(di, 16 * row);
+        if (ov > best) { best = ov; bi = oi; }
+      }
+      if (lane == 0) {
+        if (!(best > 1e-300 && best > 1e-30 * dmax)) {
+          rank_sh = k;
+          piv_sh = -1;
         } else {
-          const double inv_sd = rsqrt(d);
-          // L[j][k] = A[j][k] / sqrt(d) for j >= k (lane j holds A[k][j] = A[j][k])
-          const double l = (j > k) ? a[k] * inv_sd : ((j == k) ? d * inv_sd : 0.0);
-          Lc[k * kLStride + j] = l;
-#pragma unroll
-          for (int i = k + 1; i < kJN; ++i) {
-            const double lik = readlane_f64(a[i], k) * inv_sd;  // L[i][k]
-            a[i] = fma(-lik, l, a[i]);
-          }
+          piv_sh = bi;
+          pivd_sh = best;
+          used[bi] = 1;
         }
       }
     }
-    if (lane == 0) rank_sh = rank;
+    __syncthreads();
+    const int p = piv_sh;
+    if (p < 0) break;
+    const double d = pivd_sh;
+    const double inv = rsq_refined(d);
+    if (tid < n) {
+      // L[i][k] = A[i][p] / sqrt(d) for rows not yet pivoted; sqrt(d) on the pivot row
+      const double l = (tid == p) ? d * inv : (used[tid] ? 0.0 : Am[tid * kAStride + p] * inv);
+      lcol[tid] = l;
+      Lc[k * kLStride + tid] = l;
+    }
+    __syncthreads();
+    // rank-1 update of the remaining Schur complement (rows/columns not yet pivoted)
+    if (lane < n && !used[lane]) {
+      const double lj = lcol[lane];
+      for (int i = tid / kWave; i < n; i += kJThreads / kWave)
+        if (!used[i]) Am[i * kAStride + lane] = fma(-lcol[i], lj, Am[i * kAStride + lane]);
+    }
+    __syncthreads();
   }
-  __syncthreads();
   const int nc = rank_sh;  // columns of L in use
   // ---- 2. one-sided Jacobi on the nc columns of L; lane `sub` of a pair group owns rows 8*sub .. 8*sub+7
   const int N = nc + (nc & 1);
@@ -373,13 +407,19 @@ __global__ __launch_bounds__(kJThreads) void eig_onesided_kernel(const double* _
         ga = group8_sum(ga);
         // rotate unless the pair is orthogonal to the rounding level of an n-term dot product
         if (fabs(ga) > 1e-300 && ga * ga > tol2 * (al * be)) {
-          // tan of the rotation angle: t = sign(u v) |v| / (|u| + sqrt(u^2 + v^2)), u = be - al, v = 2 ga
-          const double u = be - al, v = 2.0 * ga;
-          const double h = sqrt(fma(u, u, v * v));
-          double t = fabs(v) / (fabs(u) + h);
-          if ((u < 0.0) != (v < 0.0) && u != 0.0) t = -t;
-          const double c = rsqrt(fma(t, t, 1.0));
-          const double s = c * t;
+          // tan(2 phi) = v / u with u = be - al, v = 2 ga; smallest rotation |phi| <= pi/4:
+          //   cos 2phi = |u| / h,  cos phi = sqrt((1 + cos 2phi) / 2),
+          //   sin phi = sign(u v) |v| / (2 h cos phi),  h = sqrt(u^2 + v^2).
+          // u and v are first scaled by (about) 1 / max(|u|, |v|) to keep h^2 in range.
+          const double u0 = be - al, v0 = 2.0 * ga;
+          const double sc = __builtin_amdgcn_rcp(fmax(fabs(u0), fabs(v0)));
+          const double u = fabs(u0) * sc, v = fabs(v0) * sc;
+          const double rh = rsq_refined(fma(u, u, v * v));  // 1 / h
+          const double w = fma(0.5 * u, rh, 0.5);             // cos^2 phi
+          const double iw = rsq_refined(w);                   // 1 / cos phi
+          const double c = w * iw;
+          double s = 0.5 * v * rh * iw;
+          if ((u0 < 0.0) != (v0 < 0.0) && u0 != 0.0) s = -s;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             double2 nx, ny;
@@ -399,7 +439,7 @@ __global__ __launch_bounds__(kJThreads) void eig_onesided_kernel(const double* _
     if (!rotated) break;
     __syncthreads();
   }
-  // ---- 3. norms, order (decreasing), normalised columns (rows back in original order), sign rule
+  // ---- 3. norms, order (decreasing), normalised columns, sign rule
   if (tid < kJN) {
     double s = 0.0;
     if (tid < nc)
@@ -450,16 +490,13 @@ __global__ __launch_bounds__(kJThreads) void eig_onesided_kernel(const double* _
   if (tid < r) {
     const int k = tid, col = order[k];
     const double inv = 1.0 / sqrt(nrm[col]);
-    // sign rule on the vector in original row order: largest |entry| (first on ties) positive
+    // sign rule: largest |entry| (first on ties) positive
     double best = -1.0, sgn = 1.0;
     for (int x = 0; x < n; ++x) {
-      // find the sorted position of original row x
-      double v = 0.0;
-      for (int i = 0; i < n; ++i)
-        if (perm[i] == x) v = Lc[col * kLStride + i];
+      const double v = Lc[col * kLStride + x];
       if (fabs(v) > best) { best = fabs(v); sgn = (v < 0.0) ? -1.0 : 1.0; }
     }
-    for (int i = 0; i < n; ++i) Vout[perm[i] * r + k] = sgn * inv * Lc[col * kLStride + i];
+    for (int i = 0; i < n; ++i) Vout[i * r + k] = sgn * inv * Lc[col * kLStride + i];
   }
 }
 
