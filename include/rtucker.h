@@ -59,8 +59,8 @@ typedef enum {
 } rt_dtype;
 
 typedef enum {
-  RT_RHKRON = 0,   /* randomized HOSVD with Kronecker factor reuse (Alg. 3.4, Sec. 3.3) */
-  RT_RSTHKRON = 1  /* randomized STHOSVD with Kronecker products (Alg. 3.3, Sec. 3.2) */
+  RT_RHKRON = 0,   /* randomized HOSVD with Kronecker factor reuse (Alg. 4.4, Sec. 4.3) */
+  RT_RSTHKRON = 1  /* randomized STHOSVD with Kronecker products (Alg. 4.3, Sec. 4.2) */
 } rt_algo;
 
 /* A dense C-order tensor in device memory. */
@@ -78,7 +78,7 @@ const char* rtucker_status_string(int status);
 const char* rtucker_version(void);
 
 /* ------------------------------------------------------------------ sizes
- * Sketch sizes (Sec. 3.2 and 3.3, "choosing subranks").  Host only.
+ * Sketch sizes (Sec. 4.2 and 4.3, "choosing subranks").  Host only.
  *  RT_RHKRON:   s_out[d]:  s_i = ceil((prod_j ell_j)^(1/(d-1)) / ell_i), computed
  *               exactly in integers (least s with (s*ell_i)^(d-1) >= prod ell).
  *  RT_RSTHKRON: s_out[d*d] (row-major S, diagonal 1): row j holds d-1 integer
@@ -92,7 +92,7 @@ int rtucker_sketch_sizes(int32_t d, const int64_t* dims, const int32_t* r, int32
                          rt_algo algo, int64_t* s_out);
 
 /* ------------------------------------------------------------------ sketch
- * All-at-once sketch multi-TTM (Alg. 3.4 sketch step; Sec. 3.4 dimension tree):
+ * All-at-once sketch multi-TTM (Alg. 4.4 sketch step; Sec. 4.4 dimension tree):
  *   Y_n = X x_{k != n} Phi_k, returned as its mode-n unfolding, for every mode n
  *   whose bit is set in mode_mask.
  *  X:       d >= 2; dtype F64, F32, BF16 or F8E4M3.  The arithmetic runs in the
@@ -125,8 +125,8 @@ int rtucker_qr(int64_t m, int64_t n, const void* Y, rt_dtype y_dtype, double* Q,
                void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------ core
- * Core multi-TTM (Alg. 3.4 core step): G = X x_k U_k^T over the modes k in
- * mode_mask (a single bit gives one TTM, as in each step of Alg. 3.3).
+ * Core multi-TTM (Alg. 4.4 core step): G = X x_k U_k^T over the modes k in
+ * mode_mask (a single bit gives one TTM, as in each step of Alg. 4.3).
  *  U[k]: device, binary64, I_k x l_k row-major (orthonormal columns in the
  *        method, but any matrix is accepted), for k in mode_mask.
  *  l[k]: number of columns of U[k], 1 <= l_k <= 64.
@@ -143,8 +143,8 @@ int rtucker_core(const rt_tensor* X, const double* const* U, const int64_t* l,
 
 /* ------------------------------------------------------------------ decompose
  * Full randomized Tucker decomposition [G; U_1..U_d] of X at ranks r with
- * oversampling p (Alg. 3.3 or 3.4): sketches, QR, core, then the holistic
- * truncation STHOSVD(G_hat, r) in mode order 1..d (Sec. 3.1) computed in
+ * oversampling p (Alg. 4.3 or 3.4): sketches, QR, core, then the holistic
+ * truncation STHOSVD(G_hat, r) in mode order 1..d (Sec. 4.1) computed in
  * binary64 (Gram matrices + cyclic Jacobi), and U_j = U_hat_j V_j.
  *  X:        dtype F64, F32 or BF16.
  *  X_sketch: NULL, or a tensor with X's dims used for the sketch instead of X
@@ -169,7 +169,7 @@ int rtucker_decompose(const rt_tensor* X, const rt_tensor* X_sketch, const int32
                       double* const* U, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------ error
- * Squared norms for the relative reconstruction error (Sec. 4), in binary64 on
+ * Squared norms for the relative reconstruction error (Sec. 5), in binary64 on
  * the device, by explicit residual (no cancellation-prone identity):
  *   out[0] = ||X - G x_1 U_1 ... x_d U_d||^2,  out[1] = ||X||^2,
  *   out[2] = ||G||^2,  out[3] = number of non-finite entries of X (as double).
@@ -226,7 +226,7 @@ int rtucker_scaled_diff(const rt_tensor* A, const void* B, const double* g, doub
 
 /* ------------------------------------------------------------------ batched
  * Batched factor-reuse decomposition of many independent 3-way tensors of
- * different sizes (Alg. 3.4 applied per tensor): every phase runs for all
+ * different sizes (Alg. 4.4 applied per tensor): every phase runs for all
  * tensors in one grouped launch whose work items cover every tensor.
  * Per item: X (device, dtype of the batch, dims[3]), r[3], s[3] (subranks;
  * 0 entries = formula), phi[3] (device binary64 s_k x I_k), G (device binary64

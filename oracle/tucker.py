@@ -14,11 +14,11 @@ are unchanged, and the Kronecker factors of a multi-TTM appear in ascending
 mode order (Sec. 2.1, multi-TTM unfolding identity).
 
 Readings of the paper taken here (each also listed with the design notes):
-  * "rHKron" is the factor-reuse algorithm (Alg. 3.4, Sec. 3.3): one Phi_k per mode.
+  * "rHKron" is the factor-reuse algorithm (Alg. 4.4, Sec. 4.3): one Phi_k per mode.
   * The number of columns of U_hat_n is every column of the sketch,
     ltilde_n = prod_{k != n} s_k (clipped to I_n); it is never cut back to r_n + p
-    (Sec. 3.2, "choosing subranks": a larger product is extra oversampling).
-  * The subrank formula of Sec. 3.3 is read with the product over k != j and the
+    (Sec. 4.2, "choosing subranks": a larger product is extra oversampling).
+  * The subrank formula of Sec. 4.3 is read with the product over k != j and the
     (d-1)-th root.
   * QR factors are normalised so that diag(R) >= 0.
   * STHOSVD takes modes in order 1..d; singular vector signs are fixed so that
@@ -71,11 +71,11 @@ def fold(M: np.ndarray, n: int, shape) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------
-# Sketch sizes (Sec. 3.2 and Sec. 3.3, "choosing subranks")
+# Sketch sizes (Sec. 4.2 and Sec. 4.3, "choosing subranks")
 # --------------------------------------------------------------------------
 
 def subranks_reuse(ell) -> list[int]:
-    """Subrank vector of the factor-reuse algorithm (Sec. 3.3).
+    """Subrank vector of the factor-reuse algorithm (Sec. 4.3).
 
     s_i = ceil( (prod_j ell_j)^(1/(d-1)) / ell_i ), evaluated exactly in
     integers: s_i is the least s with (s * ell_i)^(d-1) >= prod_j ell_j.
@@ -95,7 +95,7 @@ def subranks_reuse(ell) -> list[int]:
 
 
 def sketch_widths(s) -> list[int]:
-    """ltilde_n = prod_{k != n} s_k: number of columns of the mode-n sketch (Sec. 3.2)."""
+    """ltilde_n = prod_{k != n} s_k: number of columns of the mode-n sketch (Sec. 4.2)."""
     return [prod(int(v) for i, v in enumerate(s) if i != n) for n in range(len(s))]
 
 
@@ -114,7 +114,7 @@ def _factor_splits(n: int, parts: int, lo: int = 2):
 
 
 def subrank_row_sth(ell_j: int, parts: int) -> tuple[int, ...]:
-    """One row of the subrank matrix for the sequentially truncated algorithm (Sec. 3.2).
+    """One row of the subrank matrix for the sequentially truncated algorithm (Sec. 4.2).
 
     The row is made of ``parts`` = d-1 integer factors of ell_j; when ell_j has no
     such split the oversampling is raised: ell_j is increased to the least value
@@ -218,7 +218,7 @@ def core_order(dims) -> list[int]:
 
 
 def rhkron(X: np.ndarray, r, phis, *, return_parts: bool = False):
-    """Randomized HOSVD with Kronecker factor reuse (Alg. 3.4, Sec. 3.3).
+    """Randomized HOSVD with Kronecker factor reuse (Alg. 4.4, Sec. 4.3).
 
     ``phis[k]`` is Phi_k (s_k x I_k).  For every mode n: sketch
     Y = X x_{k != n} Phi_k, thin QR of Y_(n) gives U_hat_n.  Then
@@ -242,7 +242,7 @@ def rhkron(X: np.ndarray, r, phis, *, return_parts: bool = False):
 
 
 def sth_phi_shapes(dims, S):
-    """Shapes of Phi_{j,k} for the sequentially truncated algorithm (Sec. 3.2).
+    """Shapes of Phi_{j,k} for the sequentially truncated algorithm (Sec. 4.2).
 
     Phi_{j,k} is s_{j,k} x (current size of mode k at step j): the truncated size
     c_k = min(I_k, prod_{i != k} s_{k,i}) for k < j, the original I_k for k > j.
@@ -263,7 +263,7 @@ def sth_phi_shapes(dims, S):
 
 
 def rsthkron(X: np.ndarray, r, phis, *, return_parts: bool = False):
-    """Randomized STHOSVD with Kronecker products (Alg. 3.3, Sec. 3.2).
+    """Randomized STHOSVD with Kronecker products (Alg. 4.3, Sec. 4.2).
 
     ``phis[j][k]`` is Phi_{j,k}.  For j = 1..d: Y = G_hat x_{k != j} Phi_{j,k},
     thin QR of Y_(j) gives U_hat_j, and G_hat <- G_hat x_j U_hat_j^T.  Then
@@ -286,7 +286,7 @@ def rsthkron(X: np.ndarray, r, phis, *, return_parts: bool = False):
 
 
 # --------------------------------------------------------------------------
-# Error (Sec. 4)
+# Error (Sec. 5)
 # --------------------------------------------------------------------------
 
 def reconstruct(G: np.ndarray, Us) -> np.ndarray:

@@ -1,4 +1,4 @@
-// Core truncation pieces (Alg. 2.2 applied to the small core, Sec. 3.1):
+// Core truncation pieces (Alg. 2.2 applied to the small core, Sec. 4.1):
 //  * mode contraction out = P_(n) Q_(n)^T on (A, m, B) views, which gives the
 //    Gram matrix G_(j) G_(j)^T of the core (P = Q) and the adjoint dA_n;
 //    fixed-order two-stage reduction, so results are bitwise reproducible;

@@ -1,4 +1,4 @@
-// Relative reconstruction error by explicit residual, in binary64 (Sec. 4):
+// Relative reconstruction error by explicit residual, in binary64 (Sec. 5):
 // the host contracts all modes but the first into T = G x_2 U_2 ... x_d U_d
 // (r1 x prod_{k>1} I_k), and this kernel streams X once, reconstructing each
 // element as U_1[i, :] . T[:, b] and accumulating ||X - X_hat||^2, ||X||^2 and the

@@ -1,5 +1,5 @@
-// First level of the all-at-once sketch (Alg. 3.4 sketch step with the
-// dimension tree of Sec. 3.4): one streaming pass over X, viewed as (A, P, Q)
+// First level of the all-at-once sketch (Alg. 4.4 sketch step with the
+// dimension tree of Sec. 4.4): one streaming pass over X, viewed as (A, P, Q)
 // with P, Q the sizes of the last two modes, computes both
 //   Z = X x_d Phi_d        (the node shared by every sketch that contracts mode d)
 //   W = X x_{d-1} Phi_{d-1} (the node of the mode-d sketch)

@@ -79,7 +79,7 @@ def fixed_factors(dims, ranks, seed: int = FIXED_U_SEED):
 def superdiagonal(n: int, d: int = 3, rate: float = 0.4, terms: int | None = None, seed: int = DATA_SEED):
     """Super-diagonal core with entries rate**(i-1), rotated by random orthogonal matrices.
 
-    This is the accuracy workload of the paper's accuracy experiment (Sec. 6.1):
+    This is the accuracy workload of the paper's accuracy experiment (Sec. 7.1):
     geometric decay 0.4, largest entry 1.  ``terms`` (default n) entries are kept.
     Returns (X, lambdas, factors).
     """

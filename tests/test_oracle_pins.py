@@ -52,7 +52,7 @@ def test_ttm_brute_force_3way():
 @pytest.mark.parametrize("dims", [(5, 6, 7), (3, 4, 5, 6)])
 def test_kronecker_unfolding_identity(dims):
     """Sketch multi-TTM equals X_(n) times the transposed Kronecker product of the Phi_k,
-    k != n, in ascending mode order for C-order unfoldings (Sec. 2.1 identity; Sec. 3.2
+    k != n, in ascending mode order for C-order unfoldings (Sec. 2.1 identity; Sec. 4.2
     definition of Omega_j as a Kronecker product)."""
     rng = np.random.default_rng(11)
     X = rng.standard_normal(dims)
@@ -154,7 +154,7 @@ def test_printed_reuse_vectors_feasible():
 
 
 def test_subrank_rows_match_paper_multisets():
-    """With p = 5 the row rule reproduces every printed row of S as a multiset (Sec. 6.5, 6.6)."""
+    """With p = 5 the row rule reproduces every printed row of S as a multiset (Sec. 7.5, 7.6)."""
     g = read_golden("subranks.txt")
     for name, rkey in (("miranda", "miranda_r"), ("sp", "sp_r")):
         r = [int(v) for v in g[rkey]]
@@ -199,7 +199,7 @@ def test_qr_pos_matches_gram_schmidt():
 
 def test_sthosvd_closed_form_e1():
     """Orthogonally decomposable tensor with lambda_i = 0.4^(i-1): STHOSVD at rank 10 has
-    relative error 0.4^10 = 1.048576e-4, printed as 0.000104858 (Sec. 6.1)."""
+    relative error 0.4^10 = 1.048576e-4, printed as 0.000104858 (Sec. 7.1)."""
     g = read_golden("e1_accuracy.txt")
     X, lam, _ = synth.superdiagonal(48, terms=48, seed=5)
     G, Us = T.sthosvd(X, [10, 10, 10])
@@ -213,7 +213,7 @@ def test_sthosvd_closed_form_e1():
 
 
 def test_sthosvd_error_bound_and_subspace():
-    """STHOSVD error^2 <= sum_j sum_{i > r_j} sigma_i^2(X_(j)) (Sec. 4, core bound), and the
+    """STHOSVD error^2 <= sum_j sum_{i > r_j} sigma_i^2(X_(j)) (Sec. 5, core bound), and the
     mode-1 factor spans the leading left singular subspace."""
     rng = np.random.default_rng(19)
     X = rng.standard_normal((9, 8, 7)) * np.exp(-np.arange(7))[None, None, :]
@@ -280,7 +280,7 @@ def test_full_width_sketch_equals_sthosvd():
 
 
 def test_norm_identity_and_orthonormality():
-    """||X - X_hat||^2 = ||X||^2 - ||G||^2 when U_j are orthonormal and G = X x_j U_j^T (Sec. 4)."""
+    """||X - X_hat||^2 = ||X||^2 - ||G||^2 when U_j are orthonormal and G = X x_j U_j^T (Sec. 5)."""
     X, _, _ = synth.random_tucker((24, 20, 16), (5, 5, 5), 1e-2, seed=26)
     s = T.subranks_reuse([9, 9, 9])
     G, Us = T.rhkron(X, [5, 5, 5], _phis_reuse(X.shape, s, 27))
@@ -307,8 +307,8 @@ def test_core_singular_values_bounded_by_input():
 
 
 def test_error_split_and_projection_lemma():
-    """eps_total <= eps_rand + eps_core (Sec. 4), eps_core equals the STHOSVD error of G_hat, and
-    ||X - X x_j P_j||^2 = sum_j ||X x_{i<j} P_i x_j (I - P_j)||^2 (projection lemma, Sec. 4.2)."""
+    """eps_total <= eps_rand + eps_core (Sec. 5), eps_core equals the STHOSVD error of G_hat, and
+    ||X - X x_j P_j||^2 = sum_j ||X x_{i<j} P_i x_j (I - P_j)||^2 (projection lemma, Sec. 5.2)."""
     X, _, _ = synth.random_tucker((18, 16, 14), (6, 6, 6), 5e-2, seed=30)
     r = [4, 4, 4]
     s = T.subranks_reuse([7, 7, 7])
@@ -344,7 +344,7 @@ def test_rsthkron_phi_shapes_follow_truncation():
 
 
 def test_rsthkron_sketch_is_on_truncated_core():
-    """Step j sketches the partially truncated core G_hat (Alg. 3.3): check mode-2 step by hand."""
+    """Step j sketches the partially truncated core G_hat (Alg. 4.3): check mode-2 step by hand."""
     rng = np.random.default_rng(32)
     X = rng.standard_normal((10, 9, 8))
     S = [[1, 2, 3], [3, 1, 2], [2, 3, 1]]
@@ -361,7 +361,7 @@ def test_rsthkron_sketch_is_on_truncated_core():
 
 @pytest.mark.slow
 def test_e1_distribution_matches_paper():
-    """Accuracy experiment (Sec. 6.1) at reduced size.  With Gaussian Phi and
+    """Accuracy experiment (Sec. 7.1) at reduced size.  With Gaussian Phi and
     X = diag(0.4^(i-1)) x_k Q_k, the sketch only sees Phi_k Q_k, which is Gaussian for any
     n >= number of terms, so the error distribution does not depend on n; 64^3 stands in
     for 500^3 (terms beyond the 40th are below double precision)."""
