@@ -230,12 +230,16 @@ MCPlan mc_plan(rt_dtype dt, int64_t A, int64_t mP, int64_t mQ, int64_t B) {
 // Jacobi on the transposed R factor of a pivoted QR converges in a few sweeps,
 // and the left singular vectors of L are more accurate than eigenvectors of M
 // computed directly.  One round applies the rotations of all disjoint pairs of
-// the circle-method pairing; each pair is owned by 8 lanes (8 rows each), so a
-// round needs one barrier.  Rotation parameters use only reciprocal square
-// roots (hardware estimate + two Newton steps), no division or square root.
+// the circle-method pairing; each pair is owned by a row of 16 lanes (4 rows of L
+// each), so a round needs one barrier and two waves share each SIMD, which hides
+// much of the latency of the dependent binary64 operations.  Rotation parameters
+// use only reciprocal square roots (hardware estimate + two Newton steps), no
+// division or square root.
 constexpr int kJN = 64;
-constexpr int kJThreads = 256;
-constexpr int kPairLanes = 8;
+constexpr int kJThreads = 512;
+constexpr int kJWaves = kJThreads / kWave;
+constexpr int kPairLanes = 16;
+constexpr int kPairRows = kJN / kPairLanes;  // rows of a column per lane
 constexpr int kMaxSweeps = 30;
 constexpr int kLStride = 72;  // doubles per column of L in LDS (padding spreads banks)
 constexpr int kAStride = 65;  // doubles per row of the working matrix
@@ -248,11 +252,12 @@ __device__ __forceinline__ double dpp_f64(double v) {
   const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(u >> 32), CTRL, 0xF, 0xF, false);
   return __longlong_as_double((static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo));
 }
-// sum over aligned groups of 8 lanes; every lane of a group gets bitwise the same value
-__device__ __forceinline__ double group8_sum(double v) {
+// sum over aligned groups of 16 lanes (a DPP row); every lane of a group gets bitwise the same value
+__device__ __forceinline__ double group16_sum(double v) {
   v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
   v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
   v += dpp_f64<0x141>(v);  // row_half_mirror: lane i <- lane 7-i within 8
+  v += dpp_f64<0x140>(v);  // row_mirror: lane i <- lane 15-i within 16
   return v;
 }
 
@@ -275,11 +280,27 @@ __device__ __forceinline__ void argmax_row16(double& v, int& idx) {
 #undef RT_STEP
 }
 
+
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
   const int64_t u = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane(static_cast<int>(u & 0xffffffff), lane);
   const int hi = __builtin_amdgcn_readlane(static_cast<int>(u >> 32), lane);
   return __longlong_as_double((static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo));
+}
+
+// argmax over the whole wave (ties: lowest index); every lane ends with the result
+__device__ __forceinline__ void argmax64(double& v, int& idx) {
+  argmax_row16(v, idx);
+  double best = readlane_f64(v, 0);
+  int bi = __builtin_amdgcn_readlane(idx, 0);
+#pragma unroll
+  for (int row = 1; row < 4; ++row) {
+    const double ov = readlane_f64(v, 16 * row);
+    const int oi = __builtin_amdgcn_readlane(idx, 16 * row);
+    if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+  }
+  v = best;
+  idx = bi;
 }
 
 // 1/sqrt(x) for normal x > 0: hardware estimate refined by two Newton steps
@@ -299,80 +320,63 @@ __global__ __launch_bounds__(kJThreads) void eig_onesided_kernel(const double* _
                                                                  double* __restrict__ evals) {
   __shared__ double Am[kJN * kAStride];  // Schur complement during the Cholesky (original indices)
   __shared__ double Lc[kJN * kLStride];  // columns of L: Lc[col * kLStride + row] (original row order)
-  __shared__ double lcol[kJN];
   __shared__ double nrm[kJN];
-  __shared__ int used[kJN];
-  __shared__ int piv_sh;
-  __shared__ double pivd_sh;
   __shared__ int rotated;
   __shared__ int order[kJN];
-  __shared__ int rank_sh;
   __shared__ double vtmp[kJN];
   const int tid = threadIdx.x;
   const int lane = tid % kWave;
+  const int wv = tid / kWave;
   for (int idx = tid; idx < kJN * kLStride; idx += kJThreads) Lc[idx] = 0.0;
+  for (int idx = tid; idx < kJN * kAStride; idx += kJThreads) Am[idx] = 0.0;
+  __syncthreads();
   for (int idx = tid; idx < n * n; idx += kJThreads) {
     const int i = idx / n, j = idx - (idx / n) * n;
     Am[i * kAStride + j] = M[idx];
   }
-  if (tid < kJN) used[tid] = (tid < n) ? 0 : 1;
-  if (tid == 0) rank_sh = n;
   __syncthreads();
-  // ---- 1. Cholesky with complete pivoting; column k of L is stored in original row order
-  double dmax = 0.0;
-  if (tid < kWave) {
-    double dv = (lane < n) ? Am[lane * kAStride + lane] : 0.0;
-    int di = lane;
-    argmax_row16(dv, di);
-    dmax = fmax(fmax(readlane_f64(dv, 0), readlane_f64(dv, 16)), fmax(readlane_f64(dv, 32), readlane_f64(dv, 48)));
-  }
+  // ---- 1. Cholesky with complete pivoting; column k of L is stored in original row order.
+  //         Thread (wave w, lane j) owns column j on rows w, w + 8, ...  In a step the pivot
+  //         column is only read; the pivot row is set to zero, so rows pivoted earlier give
+  //         zero multipliers without any masking.  Every wave keeps the whole remaining
+  //         diagonal in registers (lane j: entry j, updated with the same arithmetic as the
+  //         matrix) and picks the next pivot itself, so a step needs a single barrier.
+  double dj = (lane < n) ? Am[lane * kAStride + lane] : -1.0;
+  double d = dj;
+  int p = lane;
+  argmax64(d, p);
+  const double dmax = d;
+  int nc = n;
   for (int k = 0; k < n; ++k) {
-    if (tid < kWave) {
-      double dv = (used[lane] == 0) ? Am[lane * kAStride + lane] : -1.0;
-      int di = lane;
-      argmax_row16(dv, di);
-      // combine the four rows of 16 lanes in a fixed order (ties: lowest index)
-      double best = readlane_f64(dv, 0);
-      int bi = __builtin_amdgcn_readlane(di, 0);
-#pragma unroll
-      for (int row = 1; row < 4; ++row) {
-        const double ov = readlane_f64(dv, 16 * row);
-        const int oi = __builtin_amdgcn_readlane(di, 16 * row);
-        if (ov > best) { best = ov; bi = oi; }
-      }
-      if (lane == 0) {
-        if (!(best > 1e-300 && best > 1e-30 * dmax)) {
-          rank_sh = k;
-          piv_sh = -1;
-        } else {
-          piv_sh = bi;
-          pivd_sh = best;
-          used[bi] = 1;
-        }
-      }
+    if (!(d > 1e-300 && d > 1e-30 * dmax)) {
+      nc = k;
+      break;
     }
-    __syncthreads();
-    const int p = piv_sh;
-    if (p < 0) break;
-    const double d = pivd_sh;
     const double inv = rsq_refined(d);
-    if (tid < n) {
-      // L[i][k] = A[i][p] / sqrt(d) for rows not yet pivoted; sqrt(d) on the pivot row
-      const double l = (tid == p) ? d * inv : (used[tid] ? 0.0 : Am[tid * kAStride + p] * inv);
-      lcol[tid] = l;
-      Lc[k * kLStride + tid] = l;
+    // multipliers L[i][k] = A[i][p] / sqrt(d) (A[p][p] = d gives sqrt(d) on the pivot row)
+    const double lj = Am[lane * kAStride + p] * inv;
+    if (wv == 0 && lane < n) Lc[k * kLStride + lane] = lj;
+    if (lane < n && lane != p) {
+      // all loads first (the pivot column is not written in this step), then the stores
+      double li[kJN / kJWaves], av[kJN / kJWaves];
+#pragma unroll
+      for (int t = 0; t < kJN / kJWaves; ++t) {
+        li[t] = Am[(wv + kJWaves * t) * kAStride + p];
+        av[t] = Am[(wv + kJWaves * t) * kAStride + lane];
+      }
+#pragma unroll
+      for (int t = 0; t < kJN / kJWaves; ++t) {
+        const int i = wv + kJWaves * t;
+        Am[i * kAStride + lane] = (i == p) ? 0.0 : fma(-li[t] * inv, lj, av[t]);
+      }
     }
-    __syncthreads();
-    // rank-1 update of the remaining Schur complement (rows/columns not yet pivoted)
-    if (lane < n && !used[lane]) {
-      const double lj = lcol[lane];
-      for (int i = tid / kWave; i < n; i += kJThreads / kWave)
-        if (!used[i]) Am[i * kAStride + lane] = fma(-lcol[i], lj, Am[i * kAStride + lane]);
-    }
+    dj = (lane == p || dj < 0.0) ? -1.0 : fma(-lj, lj, dj);
+    d = dj;
+    p = lane;
+    argmax64(d, p);
     __syncthreads();
   }
-  const int nc = rank_sh;  // columns of L in use
-  // ---- 2. one-sided Jacobi on the nc columns of L; lane `sub` of a pair group owns rows 8*sub .. 8*sub+7
+  // ---- 2. one-sided Jacobi on the nc columns of L; lane `sub` of a pair group owns rows 4*sub .. 4*sub+3
   const int N = nc + (nc & 1);
   const int half = N / 2;
   const int g = tid / kPairLanes, sub = tid % kPairLanes;
@@ -387,24 +391,24 @@ __global__ __launch_bounds__(kJThreads) void eig_onesided_kernel(const double* _
     for (int round = 0; round < N - 1; ++round) {
       if (g < half) {
         const int pc = a_pos < b_pos ? a_pos : b_pos, qc = a_pos < b_pos ? b_pos : a_pos;
-        double* xp = Lc + pc * kLStride + 8 * sub;
-        double* yp = Lc + qc * kLStride + 8 * sub;
-        double2 x2[4], y2[4];
+        double* xp = Lc + pc * kLStride + kPairRows * sub;
+        double* yp = Lc + qc * kLStride + kPairRows * sub;
+        double2 x2[kPairRows / 2], y2[kPairRows / 2];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
+        for (int t = 0; t < kPairRows / 2; ++t) {
           x2[t] = reinterpret_cast<const double2*>(xp)[t];
           y2[t] = reinterpret_cast<const double2*>(yp)[t];
         }
         double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
+        for (int t = 0; t < kPairRows / 2; ++t) {
           al = fma(x2[t].x, x2[t].x, al); al = fma(x2[t].y, x2[t].y, al);
           be = fma(y2[t].x, y2[t].x, be); be = fma(y2[t].y, y2[t].y, be);
           ga = fma(x2[t].x, y2[t].x, ga); ga = fma(x2[t].y, y2[t].y, ga);
         }
-        al = group8_sum(al);
-        be = group8_sum(be);
-        ga = group8_sum(ga);
+        al = group16_sum(al);
+        be = group16_sum(be);
+        ga = group16_sum(ga);
         // rotate unless the pair is orthogonal to the rounding level of an n-term dot product
         if (fabs(ga) > 1e-300 && ga * ga > tol2 * (al * be)) {
           // tan(2 phi) = v / u with u = be - al, v = 2 ga; smallest rotation |phi| <= pi/4:
@@ -421,7 +425,7 @@ __global__ __launch_bounds__(kJThreads) void eig_onesided_kernel(const double* _
           double s = 0.5 * v * rh * iw;
           if ((u0 < 0.0) != (v0 < 0.0) && u0 != 0.0) s = -s;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
+          for (int q = 0; q < kPairRows / 2; ++q) {
             double2 nx, ny;
             nx.x = c * x2[q].x - s * y2[q].x;  nx.y = c * x2[q].y - s * y2[q].y;
             ny.x = s * x2[q].x + c * y2[q].x;  ny.y = s * x2[q].y + c * y2[q].y;
