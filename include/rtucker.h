@@ -226,12 +226,28 @@ int rtucker_scaled_diff(const rt_tensor* A, const void* B, const double* g, doub
 
 /* ------------------------------------------------------------------ batched
  * Batched factor-reuse decomposition of many independent 3-way tensors of
- * different sizes (Alg. 4.4 applied per tensor): every phase runs for all
- * tensors in one grouped launch whose work items cover every tensor.
+ * different sizes (Alg. 4.4, Sec. 4.3, applied to each tensor): every phase
+ * (operand rounding, sketch pass, sketch contractions, QR, core contractions,
+ * truncation Gram / eigensolver / contractions) runs for all tensors in one
+ * grouped launch, about 25 launches whatever the batch size.
  * Per item: X (device, dtype of the batch, dims[3]), r[3], s[3] (subranks;
  * 0 entries = formula), phi[3] (device binary64 s_k x I_k), G (device binary64
  * r1 x r2 x r3), U[3] (device binary64 I_k x r_k).
- *  dtype: F32 or BF16.  count >= 1.  Limits per item as rtucker_decompose. */
+ *  dtype: F32 or BF16.  count >= 1.  Limits per item: I_k <= 256, s_k <= 8,
+ *  sketch widths prod_{k != n} s_k <= 64 and >= r_n + p.
+ *  Workspace: rtucker_decompose_batched_workspace (independent of tuning); the
+ *  first part of it holds the job tables.
+ * rtucker_decompose_batched: writes the job tables into ws (a blocking host to
+ *  device copy) and enqueues all phases on `stream`.
+ * rtucker_decompose_batched_upload: only writes the job tables (blocking).
+ * rtucker_decompose_batched_launch: only enqueues the kernels, reading the
+ *  tables left in ws by an upload with the same arguments.  It copies nothing
+ *  from the host and allocates nothing, so it can be captured in a graph.
+ * rtucker_decompose_batched_autotune: times the whole batch for each row tile
+ *  of the first core contraction (8, 16, 32 rows), keeps the fastest for this
+ *  batch signature (sizes, ranks, subranks, p, dtype) for the rest of the
+ *  process, writes it to *chosen (nullable), and leaves the matching tables in ws.
+ *  It synchronises `stream`. */
 typedef struct {
   const void* X;
   int64_t dims[3];
@@ -246,6 +262,13 @@ int rtucker_decompose_batched_workspace(int32_t count, const rt_batch_item* item
                                         rt_dtype dtype, size_t* bytes);
 int rtucker_decompose_batched(int32_t count, const rt_batch_item* items, int32_t p,
                               rt_dtype dtype, void* ws, size_t ws_bytes, void* stream);
+int rtucker_decompose_batched_upload(int32_t count, const rt_batch_item* items, int32_t p,
+                                     rt_dtype dtype, void* ws, size_t ws_bytes, void* stream);
+int rtucker_decompose_batched_launch(int32_t count, const rt_batch_item* items, int32_t p,
+                                     rt_dtype dtype, void* ws, size_t ws_bytes, void* stream);
+int rtucker_decompose_batched_autotune(int32_t count, const rt_batch_item* items, int32_t p,
+                                       rt_dtype dtype, void* ws, size_t ws_bytes, void* stream,
+                                       int32_t* chosen);
 
 #ifdef __cplusplus
 }

@@ -80,6 +80,13 @@ _SIGS = {
                                                            ctypes.c_int, ctypes.c_void_p]),
     "rtucker_decompose_batched": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int,
                                                  ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "rtucker_decompose_batched_upload": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int,
+                                                        ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "rtucker_decompose_batched_launch": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int,
+                                                        ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "rtucker_decompose_batched_autotune": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                                                          ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
+                                                          ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -431,3 +438,57 @@ def rtucker_decompose_batched(Xs, ranks, p, phis, s=None, Gs=None, Us=None, ws=N
     _check(lib().rtucker_decompose_batched(len(Xs), items, int(p), dt, _ptr(ws), wb, _stream(dev)),
            "rtucker_decompose_batched")
     return Gs, Us
+
+
+class Batch:
+    """A batch of 3-way tensors decomposed together by the grouped launches.
+
+    Holds the item table, the outputs (G_i, U_i: float64) and the workspace, so
+    that ``launch`` enqueues the whole batch with no host-device copy (it can be
+    captured in a graph) once ``upload`` has written the job tables.
+    """
+
+    def __init__(self, Xs, ranks, p, phis, s=None):
+        torch = _torch()
+        self.Xs, self.ranks, self.p, self.phis = list(Xs), [tuple(int(v) for v in r) for r in ranks], int(p), phis
+        self.device = self.Xs[0].device
+        self.dt = dtype_code(self.Xs[0])
+        for X in self.Xs:
+            if dtype_code(X) != self.dt or X.dim() != 3 or not X.is_contiguous():
+                raise RtuckerError("Batch: every tensor must be a contiguous 3-way tensor of one dtype")
+        self.Gs = [torch.empty(r, dtype=torch.float64, device=self.device) for r in self.ranks]
+        self.Us = [[torch.empty((int(X.shape[k]), r[k]), dtype=torch.float64, device=self.device) for k in range(3)]
+                   for X, r in zip(self.Xs, self.ranks)]
+        self.items = make_batch_items(self.Xs, self.ranks, phis, self.Gs, self.Us, s)
+        nb = ctypes.c_size_t()
+        _check(lib().rtucker_decompose_batched_workspace(len(self.Xs), self.items, self.p, self.dt, ctypes.byref(nb)),
+               "rtucker_decompose_batched_workspace")
+        self.ws, self.wb = _workspace(nb.value, self.device)
+
+    def _args(self):
+        return (len(self.Xs), self.items, self.p, self.dt, _ptr(self.ws), self.wb, _stream(self.device))
+
+    def run(self):
+        _check(lib().rtucker_decompose_batched(*self._args()), "rtucker_decompose_batched")
+        return self.Gs, self.Us
+
+    def upload(self):
+        _check(lib().rtucker_decompose_batched_upload(*self._args()), "rtucker_decompose_batched_upload")
+
+    def launch(self):
+        _check(lib().rtucker_decompose_batched_launch(*self._args()), "rtucker_decompose_batched_launch")
+        return self.Gs, self.Us
+
+    def autotune(self) -> int:
+        chosen = ctypes.c_int32()
+        _check(lib().rtucker_decompose_batched_autotune(*self._args(), ctypes.byref(chosen)),
+               "rtucker_decompose_batched_autotune")
+        return int(chosen.value)
+
+    def capture(self):
+        """A torch CUDA graph whose replay runs ``launch`` (the tables must be uploaded)."""
+        torch = _torch()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.launch()
+        return g

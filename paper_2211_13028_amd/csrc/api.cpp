@@ -9,6 +9,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "kernels.hpp"
@@ -654,39 +656,259 @@ int plan_mode_contract(Ctx& c, const rt_tensor* P, const rt_tensor* Q, int32_t n
   return RT_OK;
 }
 
-int plan_batched(Ctx& c, int32_t count, const rt_batch_item* items, int32_t p, rt_dtype dtype) {
+// ------------------------------------------------------------------ batched decomposition
+// Alg. 4.4 for many independent 3-way tensors of different sizes: each phase
+// runs for every tensor in one grouped launch (see kernels.hpp), ~25 launches in
+// all whatever the batch size.  The job tables are built on the host and live at
+// the start of the workspace; `upload` copies them there (blocking), and the
+// launch-only mode uses tables already in place, so it performs no host-device
+// copies and can be captured in a graph.
+struct BatchTune {
+  int core_mt = 16;    // row tile of the first core contraction (8, 16 or 32)
+};
+
+enum class BatchMode { kFull, kUploadOnly, kLaunchOnly };
+
+struct TableBuf {
+  std::vector<unsigned char> bytes;
+  template <typename T>
+  size_t add(const std::vector<T>& v) {
+    const size_t off = align256(bytes.size());
+    bytes.resize(off + v.size() * sizeof(T));
+    if (!v.empty()) std::memcpy(bytes.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+  }
+};
+
+int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t p, rt_dtype dtype,
+                      const BatchTune& tune, BatchMode mode) {
   if (count < 1 || !items || p < 0) return RT_EINVAL;
   if (dtype != RT_F32 && dtype != RT_BF16) return RT_EDTYPE;
+  if (tune.core_mt != 8 && tune.core_mt != 16 && tune.core_mt != 32) return RT_EINVAL;
+  const int d = 3;
+  struct It {
+    int64_t I[3], s[3], c[3];
+    int32_t r[3];
+    int order[3];
+  };
+  std::vector<It> its(count);
   for (int32_t i = 0; i < count; ++i) {
-    const rt_batch_item& it = items[i];
-    rt_tensor X;
-    X.d = 3;
-    for (int k = 0; k < 3; ++k) X.dims[k] = it.dims[k];
-    for (int k = 3; k < RT_MAX_D; ++k) X.dims[k] = 0;
-    X.dtype = dtype;
-    X.data = it.X;
-    int64_t s[3];
-    const int64_t* sp = nullptr;
-    if (it.s[0] > 0 && it.s[1] > 0 && it.s[2] > 0) {
-      for (int k = 0; k < 3; ++k) s[k] = it.s[k];
-      sp = s;
+    const rt_batch_item& b = items[i];
+    It& t = its[i];
+    for (int k = 0; k < d; ++k) {
+      t.I[k] = b.dims[k];
+      t.r[k] = b.r[k];
+      if (t.I[k] < 1 || t.r[k] < 1 || t.r[k] > t.I[k]) return RT_ESHAPE;
     }
-    const double* phi[3] = {it.phi[0], it.phi[1], it.phi[2]};
-    double* U[3] = {it.U[0], it.U[1], it.U[2]};
-    const size_t mark = c.off;
-    const int st = plan_decompose(c, &X, nullptr, it.r, p, sp, RT_RHKRON, phi, it.G, U);
-    if (st) return st;
-    // items run one after another on the stream, so they can share workspace
-    if (i + 1 < count) {
-      const size_t used = c.off - mark;
-      c.peak = std::max(c.peak, c.off);
-      c.off = mark;
-      (void)used;
+    if (t.I[2] > 256) return RT_ESHAPE;  // one slab row per workgroup in the sketch pass
+    if (b.s[0] > 0 && b.s[1] > 0 && b.s[2] > 0) {
+      for (int k = 0; k < d; ++k) t.s[k] = b.s[k];
+    } else {
+      const int st = sizes_impl(d, t.I, t.r, p, RT_RHKRON, t.s);
+      if (st) return st;
+    }
+    for (int k = 0; k < d; ++k) {
+      if (t.s[k] < 1 || t.s[k] > t.I[k] || t.s[k] > 8) return RT_ESHAPE;
+    }
+    for (int n = 0; n < d; ++n) {
+      const int64_t lt = prod_except(t.s, d, n);
+      if (lt < t.r[n] + static_cast<int64_t>(p) || lt > 64) return RT_ESHAPE;
+      t.c[n] = std::min<int64_t>(t.I[n], lt);
+      if (t.I[n] > 256) return RT_ESHAPE;
+    }
+    for (int k = 0; k < d; ++k) t.order[k] = k;
+    std::stable_sort(t.order, t.order + d, [&](int a, int b2) { return t.I[a] > t.I[b2]; });
+    if (c.check_ptrs) {
+      if (!b.X || !b.G) return RT_EINVAL;
+      for (int k = 0; k < d; ++k)
+        if (!b.phi[k] || !b.U[k]) return RT_EINVAL;
     }
   }
-  c.peak = std::max(c.peak, c.off);
-  c.off = c.peak;
+  const rt_dtype ct = RT_F32;
+  const size_t xs = dtype_size(dtype);
+  (void)xs;
+  // ---- buffers and jobs
+  std::vector<PrepTask> prep_sk, prep_core;
+  std::vector<GZwJob> zw;
+  std::vector<GTtmJob> tree, core[3], gttm[3], uttm[3];
+  std::vector<GQrJob> qr;
+  std::vector<GCopyJob> cp;
+  std::vector<GGramJob> gram[3];
+  std::vector<GEigJob> eig[3];
+  int64_t max_prep_sk = 1, max_prep_core = 1, max_cp = 1;
+  // the table region comes first; its size is fixed by the job counts
+  const size_t n_jobs_bytes =
+      align256(sizeof(PrepTask) * 3 * count) * 2 + align256(sizeof(GZwJob) * count) +
+      align256(sizeof(GTtmJob) * 3 * count) + align256(sizeof(GQrJob) * 3 * count) +
+      3 * align256(sizeof(GTtmJob) * count) + align256(sizeof(GCopyJob) * count) +
+      3 * (align256(sizeof(GGramJob) * count) + align256(sizeof(GEigJob) * count) +
+           2 * align256(sizeof(GTtmJob) * count)) + 4096;
+  char* tables = static_cast<char*>(c.take(n_jobs_bytes));
+  int64_t zw_blocks = 0, tree_blocks = 0, core_blocks[3] = {0, 0, 0}, g_blocks[3] = {0, 0, 0},
+          u_blocks[3] = {0, 0, 0};
+  const int core_mt_first = tune.core_mt;
+  for (int32_t i = 0; i < count; ++i) {
+    const rt_batch_item& b = items[i];
+    const It& t = its[i];
+    const int64_t I0 = t.I[0], I1 = t.I[1], I2 = t.I[2];
+    // sketch operands Phi_k rounded to the tensor's dtype, binary32 storage
+    float* op[3];
+    for (int k = 0; k < d; ++k) {
+      op[k] = static_cast<float*>(c.take(static_cast<size_t>(t.s[k]) * t.I[k] * 4));
+      prep_sk.push_back(PrepTask{b.phi[k], t.s[k], t.I[k], t.s[k], false, dtype, ct, op[k]});
+      max_prep_sk = std::max<int64_t>(max_prep_sk, t.s[k] * t.I[k]);
+    }
+    // first sketch level: Z = X x_3 Phi_3, W = X x_2 Phi_2 (one pass over X)
+    float* Z = static_cast<float*>(c.take(static_cast<size_t>(I0) * I1 * t.s[2] * 4));
+    float* W = static_cast<float*>(c.take(static_cast<size_t>(I0) * t.s[1] * I2 * 4));
+    zw.push_back(GZwJob{b.X, op[1], op[2], Z, W, I0, I1, I2, zw_blocks, static_cast<int32_t>(t.s[1]),
+                        static_cast<int32_t>(t.s[2])});
+    zw_blocks += I0;
+    // the three sketches: Y_1 = Z x_2 Phi_2, Y_2 = Z x_1 Phi_1, Y_3 = W x_1 Phi_1
+    float* Y0 = static_cast<float*>(c.take(static_cast<size_t>(I0) * t.s[1] * t.s[2] * 4));
+    float* Y1 = static_cast<float*>(c.take(static_cast<size_t>(t.s[0]) * I1 * t.s[2] * 4));
+    float* Y2 = static_cast<float*>(c.take(static_cast<size_t>(t.s[0]) * t.s[1] * I2 * 4));
+    auto add_tree = [&](const void* X, int64_t A, int64_t K, int64_t B, const void* M, int64_t m, void* Y) {
+      GTtmJob j{X, M, Y, A, K, B, m, tree_blocks, ceil_div(A * B, kWave), ceil_div(m, 8), 0, 0};
+      tree_blocks += ttm_grouped_blocks(A, B, m, 8);
+      tree.push_back(j);
+    };
+    add_tree(Z, I0, I1, t.s[2], op[1], t.s[1], Y0);
+    add_tree(Z, 1, I0, I1 * t.s[2], op[0], t.s[0], Y1);
+    add_tree(W, 1, I0, t.s[1] * I2, op[0], t.s[0], Y2);
+    // thin QR of each sketch unfolding -> U_hat_n (I_n x c_n, binary64)
+    double* Uh[3];
+    const void* Ys[3] = {Y0, Y1, Y2};
+    const int64_t YA[3] = {1, t.s[0], t.s[0] * t.s[1]};
+    const int64_t YB[3] = {t.s[1] * t.s[2], t.s[2], 1};
+    for (int n = 0; n < d; ++n) {
+      Uh[n] = static_cast<double*>(c.take(static_cast<size_t>(t.I[n]) * t.c[n] * 8));
+      qr.push_back(GQrJob{Ys[n], YA[n], t.I[n], YB[n], Uh[n], static_cast<int32_t>(YA[n] * YB[n]),
+                          static_cast<int32_t>(t.c[n])});
+    }
+    // core: G_hat = X x_k U_hat_k^T, largest mode first; operands rounded to the input dtype of each step
+    int64_t dims[3] = {I0, I1, I2};
+    const void* cur = b.X;
+    for (int stp = 0; stp < d; ++stp) {
+      const int k = t.order[stp];
+      const rt_dtype in_dt = (stp == 0) ? dtype : ct;
+      float* cop = static_cast<float*>(c.take(static_cast<size_t>(t.c[k]) * t.I[k] * 4));
+      prep_core.push_back(PrepTask{Uh[k], t.c[k], t.I[k], t.c[k], true, in_dt, ct, cop});
+      max_prep_core = std::max<int64_t>(max_prep_core, t.c[k] * t.I[k]);
+      int64_t A = 1, B = 1;
+      for (int q = 0; q < k; ++q) A *= dims[q];
+      for (int q = k + 1; q < d; ++q) B *= dims[q];
+      float* y = static_cast<float*>(c.take(static_cast<size_t>(A) * t.c[k] * B * 4));
+      const int mt = (stp == 0) ? core_mt_first : 16;
+      core[stp].push_back(GTtmJob{cur, cop, y, A, t.I[k], B, t.c[k], core_blocks[stp], ceil_div(A * B, kWave),
+                                  ceil_div(t.c[k], mt), 0, 0});
+      core_blocks[stp] += ttm_grouped_blocks(A, B, t.c[k], mt);
+      dims[k] = t.c[k];
+      cur = y;
+    }
+    // binary64 copy of the core for the truncation
+    const int64_t ng = t.c[0] * t.c[1] * t.c[2];
+    double* g64 = static_cast<double*>(c.take(static_cast<size_t>(ng) * 8));
+    cp.push_back(GCopyJob{static_cast<const float*>(cur), g64, ng});
+    max_cp = std::max<int64_t>(max_cp, ng);
+    // truncation STHOSVD(G_hat, r) in mode order 1..3, then U_j = U_hat_j V_j
+    int64_t gd[3] = {t.c[0], t.c[1], t.c[2]};
+    const double* gcur = g64;
+    for (int j = 0; j < d; ++j) {
+      const int64_t cj = gd[j];
+      int64_t A = 1, B = 1;
+      for (int q = 0; q < j; ++q) A *= gd[q];
+      for (int q = j + 1; q < d; ++q) B *= gd[q];
+      double* M = static_cast<double*>(c.take(static_cast<size_t>(cj) * cj * 8));
+      double* V = static_cast<double*>(c.take(static_cast<size_t>(cj) * t.r[j] * 8));
+      gram[j].push_back(GGramJob{gcur, M, A, cj, B});
+      eig[j].push_back(GEigJob{M, V, static_cast<int32_t>(cj), t.r[j]});
+      double* gnext = (j == d - 1) ? b.G : static_cast<double*>(c.take(static_cast<size_t>(A) * t.r[j] * B * 8));
+      gttm[j].push_back(GTtmJob{gcur, V, gnext, A, cj, B, t.r[j], g_blocks[j], ceil_div(A * B, kWave),
+                                ceil_div(t.r[j], 16), 1, 0});
+      g_blocks[j] += ttm_grouped_blocks(A, B, t.r[j], 16);
+      uttm[j].push_back(GTtmJob{Uh[j], V, b.U[j], t.I[j], cj, 1, t.r[j], u_blocks[j], ceil_div(t.I[j], kWave),
+                                ceil_div(t.r[j], 16), 1, 0});
+      u_blocks[j] += ttm_grouped_blocks(t.I[j], 1, t.r[j], 16);
+      gd[j] = t.r[j];
+      gcur = gnext;
+    }
+  }
+  // ---- tables
+  TableBuf tb;
+  const size_t o_psk = tb.add(prep_sk), o_zw = tb.add(zw), o_tree = tb.add(tree), o_qr = tb.add(qr),
+               o_pcore = tb.add(prep_core);
+  size_t o_core[3], o_gram[3], o_eig[3], o_g[3], o_u[3];
+  for (int q = 0; q < 3; ++q) o_core[q] = tb.add(core[q]);
+  const size_t o_cp = tb.add(cp);
+  for (int j = 0; j < 3; ++j) {
+    o_gram[j] = tb.add(gram[j]);
+    o_eig[j] = tb.add(eig[j]);
+    o_g[j] = tb.add(gttm[j]);
+    o_u[j] = tb.add(uttm[j]);
+  }
+  if (tb.bytes.size() > n_jobs_bytes) return RT_EINVAL;  // internal sizing error
+  if (c.dry) return RT_OK;
+  if (mode != BatchMode::kLaunchOnly) {
+    c.chk(hipMemcpyWithStream(tables, tb.bytes.data(), tb.bytes.size(), hipMemcpyHostToDevice, c.st));
+    if (mode == BatchMode::kUploadOnly) return RT_OK;
+  }
+  auto at = [&](size_t off) { return tables + off; };
+  const hipStream_t st = c.st;
+  c.chk(launch_prep_grouped(reinterpret_cast<const PrepTask*>(at(o_psk)), static_cast<int>(prep_sk.size()),
+                            max_prep_sk, st));
+  c.chk(launch_sketch_zw_grouped(reinterpret_cast<const GZwJob*>(at(o_zw)), count, zw_blocks, dtype, st));
+  c.chk(launch_ttm_grouped(reinterpret_cast<const GTtmJob*>(at(o_tree)), static_cast<int>(tree.size()), tree_blocks,
+                           RT_F32, 8, st));
+  c.chk(launch_qr_grouped(reinterpret_cast<const GQrJob*>(at(o_qr)), static_cast<int>(qr.size()), RT_F32, st));
+  c.chk(launch_prep_grouped(reinterpret_cast<const PrepTask*>(at(o_pcore)), static_cast<int>(prep_core.size()),
+                            max_prep_core, st));
+  for (int q = 0; q < 3; ++q)
+    c.chk(launch_ttm_grouped(reinterpret_cast<const GTtmJob*>(at(o_core[q])), count, core_blocks[q],
+                             q == 0 ? dtype : RT_F32, q == 0 ? core_mt_first : 16, st));
+  c.chk(launch_copy_f64_grouped(reinterpret_cast<const GCopyJob*>(at(o_cp)), count, max_cp, st));
+  for (int j = 0; j < 3; ++j) {
+    c.chk(launch_gram_grouped(reinterpret_cast<const GGramJob*>(at(o_gram[j])), count, st));
+    c.chk(launch_eig_grouped(reinterpret_cast<const GEigJob*>(at(o_eig[j])), count, st));
+    c.chk(launch_ttm_grouped(reinterpret_cast<const GTtmJob*>(at(o_g[j])), count, g_blocks[j], RT_F64, 16, st));
+    c.chk(launch_ttm_grouped(reinterpret_cast<const GTtmJob*>(at(o_u[j])), count, u_blocks[j], RT_F64, 16, st));
+  }
   return RT_OK;
+}
+
+// tuned settings per batch signature (sizes, ranks, subranks, p, dtype), process-wide
+std::mutex g_tune_mu;
+std::map<uint64_t, BatchTune> g_tune;
+
+uint64_t batch_key(int32_t count, const rt_batch_item* items, int32_t p, rt_dtype dtype) {
+  uint64_t h = 1469598103934665603ull;  // FNV-1a
+  auto mix = [&](int64_t v) {
+    for (int b = 0; b < 8; ++b) {
+      h ^= static_cast<uint64_t>(v >> (8 * b)) & 0xffu;
+      h *= 1099511628211ull;
+    }
+  };
+  mix(count);
+  mix(p);
+  mix(dtype);
+  for (int32_t i = 0; i < count && items; ++i)
+    for (int k = 0; k < 3; ++k) {
+      mix(items[i].dims[k]);
+      mix(items[i].r[k]);
+      mix(items[i].s[k]);
+    }
+  return h;
+}
+
+BatchTune tune_for(int32_t count, const rt_batch_item* items, int32_t p, rt_dtype dtype) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(batch_key(count, items, p, dtype));
+  return it == g_tune.end() ? BatchTune{} : it->second;
+}
+
+int plan_batched(Ctx& c, int32_t count, const rt_batch_item* items, int32_t p, rt_dtype dtype,
+                 BatchMode mode = BatchMode::kFull) {
+  return plan_batched_impl(c, count, items, p, dtype, tune_for(count, items, p, dtype), mode);
 }
 
 template <typename F>
@@ -848,6 +1070,69 @@ int rtucker_decompose_batched_workspace(int32_t count, const rt_batch_item* item
 int rtucker_decompose_batched(int32_t count, const rt_batch_item* items, int32_t p, rt_dtype dtype, void* ws,
                               size_t ws_bytes, void* stream) {
   return run([&](Ctx& c) { return plan_batched(c, count, items, p, dtype); }, ws, ws_bytes, stream);
+}
+
+int rtucker_decompose_batched_upload(int32_t count, const rt_batch_item* items, int32_t p, rt_dtype dtype, void* ws,
+                                     size_t ws_bytes, void* stream) {
+  return run([&](Ctx& c) { return plan_batched(c, count, items, p, dtype, BatchMode::kUploadOnly); }, ws, ws_bytes,
+             stream);
+}
+
+int rtucker_decompose_batched_launch(int32_t count, const rt_batch_item* items, int32_t p, rt_dtype dtype, void* ws,
+                                     size_t ws_bytes, void* stream) {
+  return run([&](Ctx& c) { return plan_batched(c, count, items, p, dtype, BatchMode::kLaunchOnly); }, ws, ws_bytes,
+             stream);
+}
+
+int rtucker_decompose_batched_autotune(int32_t count, const rt_batch_item* items, int32_t p, rt_dtype dtype,
+                                       void* ws, size_t ws_bytes, void* stream, int32_t* chosen) {
+  const int cand[3] = {8, 16, 32};
+  float best_ms = -1.0f;
+  int best = 16;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return RT_EHIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return RT_EHIP;
+  }
+  int status = RT_OK;
+  for (int ci = 0; ci < 3 && status == RT_OK; ++ci) {
+    BatchTune tune;
+    tune.core_mt = cand[ci];
+    auto plan = [&](Ctx& c, BatchMode m) { return plan_batched_impl(c, count, items, p, dtype, tune, m); };
+    status = run([&](Ctx& c) { return plan(c, BatchMode::kUploadOnly); }, ws, ws_bytes, stream);
+    if (status) break;
+    status = run([&](Ctx& c) { return plan(c, BatchMode::kLaunchOnly); }, ws, ws_bytes, stream);  // warm-up
+    if (status) break;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    if (hipEventRecord(e0, st) != hipSuccess) { status = RT_EHIP; break; }
+    for (int rep = 0; rep < 3 && status == RT_OK; ++rep)
+      status = run([&](Ctx& c) { return plan(c, BatchMode::kLaunchOnly); }, ws, ws_bytes, stream);
+    if (status) break;
+    float ms = 0.0f;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      status = RT_EHIP;
+      break;
+    }
+    if (best_ms < 0.0f || ms < best_ms) {
+      best_ms = ms;
+      best = cand[ci];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (status) return status;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    BatchTune t;
+    t.core_mt = best;
+    g_tune[batch_key(count, items, p, dtype)] = t;
+  }
+  if (chosen) *chosen = best;
+  // leave the tables of the chosen setting in the workspace for a following launch-only call
+  return run([&](Ctx& c) { return plan_batched(c, count, items, p, dtype, BatchMode::kUploadOnly); }, ws, ws_bytes,
+             stream);
 }
 
 }  // extern "C"

@@ -82,6 +82,25 @@ __global__ __launch_bounds__(kThreads) void pack_f32_kernel(const float* __restr
   }
 }
 
+__global__ __launch_bounds__(kThreads) void prep_grouped_kernel(const PrepTask* __restrict__ tasks) {
+  const PrepTask T = tasks[blockIdx.y];
+  const int64_t total = T.m_pad * T.K;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; t < total; t += stride) {
+    const int64_t i = t / T.K, k = t - i * T.K;
+    double x = 0.0;
+    if (i < T.m) x = T.trans ? T.src[k * T.m + i] : T.src[i * T.K + k];
+    store_rounded(T.dst, T.store, T.round_to, t, x);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void copy_f64_grouped_kernel(const GCopyJob* __restrict__ jobs) {
+  const GCopyJob J = jobs[blockIdx.y];
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; t < J.n; t += stride)
+    J.dst[t] = static_cast<double>(J.src[t]);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void unfold_kernel(const T* src, int64_t A, int64_t m, int64_t B, T* dst) {
   const int64_t total = A * m * B;
@@ -189,6 +208,21 @@ hipError_t launch_pack_f32(const float* src, int64_t m, int64_t K, bool trans, i
                            hipStream_t st) {
   if (m_pad < m) m_pad = m;
   pack_f32_kernel<<<grid_for(m_pad * K), kThreads, 0, st>>>(src, m, K, trans, m_pad, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_grouped(const PrepTask* tasks, int count, int64_t max_elems, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  const int64_t g = ceil_div(max_elems, kThreads);
+  prep_grouped_kernel<<<dim3(static_cast<unsigned>(g > 64 ? 64 : (g < 1 ? 1 : g)), count), kThreads, 0, st>>>(tasks);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_f64_grouped(const GCopyJob* jobs, int count, int64_t max_elems, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  const int64_t g = ceil_div(max_elems, kThreads);
+  copy_f64_grouped_kernel<<<dim3(static_cast<unsigned>(g > 64 ? 64 : (g < 1 ? 1 : g)), count), kThreads, 0, st>>>(
+      jobs);
   return hipGetLastError();
 }
 

@@ -15,20 +15,16 @@ constexpr int kMCTile = 64;
 constexpr int kMCK = 16;
 constexpr int kMCThreads = 256;
 
+// one 64 x 64 output tile (rows i0.., columns j0..) summed over t in [t0, t1);
+// thread (ty, tx) accumulates rows 4 ty.., columns 4 tx..
 template <typename T>
-__global__ __launch_bounds__(kMCThreads) void mode_contract_kernel(const T* __restrict__ P, const T* __restrict__ Q,
-                                                                   int64_t A, int64_t mP, int64_t mQ, int64_t B,
-                                                                   int64_t chunk, int tilesQ, T* __restrict__ part) {
+__device__ __forceinline__ void mode_contract_tile(const T* __restrict__ P, const T* __restrict__ Q, int64_t A,
+                                                   int64_t mP, int64_t mQ, int64_t B, int64_t t0, int64_t t1,
+                                                   int64_t i0, int64_t j0, T (&acc)[4][4]) {
   __shared__ T sP[kMCK][kMCTile + 1];
   __shared__ T sQ[kMCK][kMCTile + 1];
-  const int tile = blockIdx.x;
-  const int ti = tile / tilesQ, tj = tile % tilesQ;
-  const int64_t i0 = static_cast<int64_t>(ti) * kMCTile, j0 = static_cast<int64_t>(tj) * kMCTile;
-  const int64_t total = A * B;
-  const int64_t t0 = static_cast<int64_t>(blockIdx.y) * chunk;
-  const int64_t t1 = (t0 + chunk < total) ? t0 + chunk : total;
+  (void)A;
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;  // 4x4 outputs per thread
-  T acc[4][4];
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -74,11 +70,41 @@ __global__ __launch_bounds__(kMCThreads) void mode_contract_kernel(const T* __re
         for (int v = 0; v < 4; ++v) acc[u][v] = fma(pv[u], qv[v], acc[u][v]);
     }
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kMCThreads) void mode_contract_kernel(const T* __restrict__ P, const T* __restrict__ Q,
+                                                                   int64_t A, int64_t mP, int64_t mQ, int64_t B,
+                                                                   int64_t chunk, int tilesQ, T* __restrict__ part) {
+  const int tile = blockIdx.x;
+  const int ti = tile / tilesQ, tj = tile % tilesQ;
+  const int64_t i0 = static_cast<int64_t>(ti) * kMCTile, j0 = static_cast<int64_t>(tj) * kMCTile;
+  const int64_t total = A * B;
+  const int64_t t0 = static_cast<int64_t>(blockIdx.y) * chunk;
+  const int64_t t1 = (t0 + chunk < total) ? t0 + chunk : total;
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  T acc[4][4];
+  mode_contract_tile<T>(P, Q, A, mP, mQ, B, t0, t1, i0, j0, acc);
   T* out = part + (static_cast<int64_t>(blockIdx.y) * gridDim.x + tile) * kMCTile * kMCTile;
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) out[(ty * 4 + u) * kMCTile + tx * 4 + v] = acc[u][v];
+}
+
+// Gram matrix of one binary64 (A, m, B) view per workgroup (m <= 64), batched
+__global__ __launch_bounds__(kMCThreads) void gram_grouped_kernel(const GGramJob* __restrict__ jobs) {
+  const GGramJob J = jobs[blockIdx.x];
+  double acc[4][4];
+  mode_contract_tile<double>(J.G, J.G, J.A, J.m, J.m, J.B, 0, J.A * J.B, 0, 0, acc);
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t i = ty * 4 + u, j = tx * 4 + v;
+      if (i < J.m && j < J.m) J.out[i * J.m + j] = acc[u][v];
+    }
 }
 
 // out = sum over chunks of the partial tiles: 16 lanes per output element, each
@@ -315,9 +341,8 @@ __device__ __forceinline__ double rsq_refined(double x) {
   return y;
 }
 
-__global__ __launch_bounds__(kJThreads) void eig_onesided_kernel(const double* __restrict__ M, int n, int r,
-                                                                 double* __restrict__ Vout,
-                                                                 double* __restrict__ evals) {
+__device__ __forceinline__ void eig_body(const double* __restrict__ M, int n, int r, double* __restrict__ Vout,
+                                         double* __restrict__ evals) {
   __shared__ double Am[kJN * kAStride];  // Schur complement during the Cholesky (original indices)
   __shared__ double Lc[kJN * kLStride];  // columns of L: Lc[col * kLStride + row] (original row order)
   __shared__ double nrm[kJN];
@@ -504,6 +529,17 @@ __global__ __launch_bounds__(kJThreads) void eig_onesided_kernel(const double* _
   }
 }
 
+__global__ __launch_bounds__(kJThreads) void eig_onesided_kernel(const double* __restrict__ M, int n, int r,
+                                                                 double* __restrict__ Vout,
+                                                                 double* __restrict__ evals) {
+  eig_body(M, n, r, Vout, evals);
+}
+
+__global__ __launch_bounds__(kJThreads) void eig_grouped_kernel(const GEigJob* __restrict__ jobs) {
+  const GEigJob J = jobs[blockIdx.x];
+  eig_body(J.M, J.n, J.r, J.V, nullptr);
+}
+
 }  // namespace
 
 size_t mode_contract_ws(rt_dtype dt, int64_t A, int64_t mP, int64_t mQ, int64_t B) {
@@ -535,6 +571,18 @@ hipError_t launch_mode_contract(const void* P, const void* Q, rt_dtype dt, int64
 
 hipError_t launch_sym_eig_top(const double* M, int64_t n, int64_t r, double* V, double* evals, hipStream_t st) {
   eig_onesided_kernel<<<1, kJThreads, 0, st>>>(M, static_cast<int>(n), static_cast<int>(r), V, evals);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_grouped(const GGramJob* jobs, int count, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  gram_grouped_kernel<<<static_cast<unsigned>(count), kMCThreads, 0, st>>>(jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_eig_grouped(const GEigJob* jobs, int count, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  eig_grouped_kernel<<<static_cast<unsigned>(count), kJThreads, 0, st>>>(jobs);
   return hipGetLastError();
 }
 

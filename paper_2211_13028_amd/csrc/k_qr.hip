@@ -39,7 +39,7 @@ struct QRTaskTable {
 };
 
 template <typename TY>
-__global__ __launch_bounds__(kQRThreads) void small_qr_kernel(QRTaskTable tab) {
+__device__ __forceinline__ void small_qr_body(const QRTask& T) {
   __shared__ double Y[kRowsMax * kCols];
   __shared__ double sh_nrm[4];
   __shared__ double sh_dot[4][kCols];
@@ -47,8 +47,6 @@ __global__ __launch_bounds__(kQRThreads) void small_qr_kernel(QRTaskTable tab) {
   __shared__ double sh_beta[kCols];
   __shared__ double sh_sgn[kCols];
 
-  const QRTask& T = tab.t[blockIdx.x];
-  if (T.flag && *T.flag == 0) return;
   const int lane = threadIdx.x % kWave;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int rows = T.rows, n = T.n;
@@ -172,6 +170,35 @@ __global__ __launch_bounds__(kQRThreads) void small_qr_kernel(QRTaskTable tab) {
     const double v = (jj < c) ? sh_sgn[jj] * Y[r * kCols + jj] : 0.0;
     T.Q[static_cast<int64_t>(r) * T.ldq + jj] = v;
   }
+}
+
+template <typename TY>
+__global__ __launch_bounds__(kQRThreads) void small_qr_kernel(QRTaskTable tab) {
+  const QRTask& T = tab.t[blockIdx.x];
+  if (T.flag && *T.flag == 0) return;
+  small_qr_body<TY>(T);
+}
+
+// one job per workgroup, jobs in device memory (batched decomposition)
+template <typename TY>
+__global__ __launch_bounds__(kQRThreads) void small_qr_grouped_kernel(const GQrJob* __restrict__ jobs) {
+  const GQrJob J = jobs[blockIdx.x];
+  QRTask T;
+  T.src = J.Y;
+  T.A = J.A;
+  T.m = J.m;
+  T.B = J.B;
+  T.row0 = 0;
+  T.rows = static_cast<int32_t>(J.m);
+  T.n = J.n;
+  T.Q = J.Q;
+  T.ldq = J.qcols;
+  T.qcols = J.qcols;
+  T.R = nullptr;
+  T.rrows = 0;
+  T.f64 = 0;
+  T.flag = nullptr;
+  small_qr_body<TY>(T);
 }
 
 struct CombineTask {
@@ -604,6 +631,15 @@ size_t qr_ws(const QRJob* jobs, int count) {
 hipError_t launch_qr(const QRJob* jobs, int count, rt_dtype ydt, void* ws, hipStream_t st) {
   Bump b{static_cast<char*>(ws), 0};
   return qr_plan(jobs, count, ydt, true, b, st);
+}
+
+hipError_t launch_qr_grouped(const GQrJob* jobs, int count, rt_dtype ydt, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  if (ydt == RT_F64)
+    small_qr_grouped_kernel<double><<<static_cast<unsigned>(count), kQRThreads, 0, st>>>(jobs);
+  else
+    small_qr_grouped_kernel<float><<<static_cast<unsigned>(count), kQRThreads, 0, st>>>(jobs);
+  return hipGetLastError();
 }
 
 }  // namespace rt

@@ -110,6 +110,84 @@ __global__ __launch_bounds__(kZWThreads) void sketch_zw_kernel(const TX* __restr
   }
 }
 
+// grouped form for many small tensors: one workgroup per slab X[a] of a job
+// (all rows, all Q <= 256 columns), so no partial sums are needed
+template <typename TX>
+__global__ __launch_bounds__(kZWThreads) void sketch_zw_grouped_kernel(const GZwJob* __restrict__ jobs, int count) {
+  constexpr int NQ = 4, SMAX = 8;
+  __shared__ float sW[kZWWaves][SMAX][64 * NQ];
+  const int64_t blk = blockIdx.x;
+  const GZwJob J = jobs[find_job(jobs, count, blk)];
+  const int64_t a = blk - J.blk0;
+  const int64_t P = J.P, Q = J.Q;
+  const int sP = J.sP, sQ = J.sQ;
+  const int lane = threadIdx.x % kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const bool needZ = J.Z != nullptr, needW = J.W != nullptr;
+  float phq[NQ][SMAX];
+  float wacc[NQ][SMAX];
+#pragma unroll
+  for (int j = 0; j < NQ; ++j) {
+    const int64_t q = lane + 64 * j;
+#pragma unroll
+    for (int c = 0; c < SMAX; ++c) {
+      phq[j][c] = (needZ && q < Q && c < sQ) ? J.phiQ[c * Q + q] : 0.f;
+      wacc[j][c] = 0.f;
+    }
+  }
+  const TX* xa = static_cast<const TX*>(J.X) + a * P * Q;
+  float* zrow = needZ ? J.Z + a * P * sQ : nullptr;
+  for (int64_t p = wave; p < P; p += kZWWaves) {
+    float x[NQ];
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) {
+      const int64_t q = lane + 64 * j;
+      x[j] = (q < Q) ? static_cast<float>(Load<TX>::get(xa, p * Q + q)) : 0.f;
+    }
+    if (needW) {
+#pragma unroll
+      for (int c = 0; c < SMAX; ++c) {
+        const float f = (c < sP) ? J.phiP[c * P + p] : 0.f;
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) wacc[j][c] = fmaf(f, x[j], wacc[j][c]);
+      }
+    }
+    if (needZ) {
+      float z[SMAX];
+#pragma unroll
+      for (int c = 0; c < SMAX; ++c) {
+        float sum = 0.f;
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) sum = fmaf(x[j], phq[j][c], sum);
+        z[c] = sum;
+      }
+#pragma unroll
+      for (int c = 0; c < SMAX; ++c)
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) z[c] += __shfl_xor(z[c], off);
+      float mine = 0.f;
+#pragma unroll
+      for (int c = 0; c < SMAX; ++c)
+        if (lane == c) mine = z[c];
+      if (lane < sQ) zrow[p * sQ + lane] = mine;
+    }
+  }
+  if (!needW) return;
+#pragma unroll
+  for (int j = 0; j < NQ; ++j)
+#pragma unroll
+    for (int c = 0; c < SMAX; ++c) sW[wave][c][lane + 64 * j] = wacc[j][c];
+  __syncthreads();
+  float* wout = J.W + a * sP * Q;
+  for (int idx = threadIdx.x; idx < sP * 64 * NQ; idx += kZWThreads) {
+    const int c = idx / (64 * NQ), col = idx % (64 * NQ);
+    if (col >= Q) continue;
+    float sum = 0.f;
+    for (int w = 0; w < kZWWaves; ++w) sum += sW[w][c][col];
+    wout[c * Q + col] = sum;
+  }
+}
+
 template <typename TC>
 __global__ __launch_bounds__(256) void sum_parts_kernel(const TC* __restrict__ part, int parts, int64_t n,
                                                         TC* __restrict__ out) {
@@ -418,6 +496,19 @@ hipError_t launch_sketch_zw(const void* X, rt_dtype xdt, int64_t A, int64_t P, i
       sum_parts_kernel<float><<<g, 256, 0, st>>>(static_cast<const float*>(wdst), static_cast<int>(plan.pblocks), n,
                                                  static_cast<float*>(W));
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_sketch_zw_grouped(const GZwJob* jobs, int count, int64_t total_blocks, rt_dtype xdt,
+                                    hipStream_t st) {
+  if (count == 0 || total_blocks == 0) return hipSuccess;
+  const unsigned g = static_cast<unsigned>(total_blocks);
+  if (xdt == RT_F32)
+    sketch_zw_grouped_kernel<float><<<g, kZWThreads, 0, st>>>(jobs, count);
+  else if (xdt == RT_BF16)
+    sketch_zw_grouped_kernel<bf16_t><<<g, kZWThreads, 0, st>>>(jobs, count);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -107,6 +107,52 @@ hipError_t generic_dispatch(const TX* X, int64_t A, int64_t K, int64_t B, const 
   return hipGetLastError();
 }
 
+// grouped form: job found by binary search over blk0; one wave per workgroup
+
+template <typename TX, typename TC, int MT>
+__global__ __launch_bounds__(kWave) void ttm_grouped_kernel(const GTtmJob* __restrict__ jobs, int count) {
+  __shared__ TC sM[MT][kGenKC];
+  const int64_t blk = blockIdx.x;
+  const GTtmJob J = jobs[find_job(jobs, count, blk)];
+  const int64_t local = blk - J.blk0;
+  const int64_t cb = local / J.mtiles, mtile = local - cb * J.mtiles;
+  const int64_t A = J.A, K = J.K, B = J.B, m = J.m;
+  const TX* X = static_cast<const TX*>(J.X);
+  const TC* M = static_cast<const TC*>(J.M);
+  const int64_t col = cb * kWave + threadIdx.x;
+  const int64_t i0 = mtile * MT;
+  const bool active = col < A * B;
+  const int64_t a = active ? col / B : 0;
+  const int64_t b = active ? col - a * B : 0;
+  TC acc[MT];
+#pragma unroll
+  for (int ii = 0; ii < MT; ++ii) acc[ii] = TC(0);
+  const TX* xp = X + a * K * B + b;
+  for (int64_t k0 = 0; k0 < K; k0 += kGenKC) {
+    __syncthreads();
+    for (int t = threadIdx.x; t < MT * kGenKC; t += kWave) {
+      const int ii = t / kGenKC, kk = t % kGenKC;
+      sM[ii][kk] = (i0 + ii < m && k0 + kk < K) ? (J.mtrans ? M[(k0 + kk) * m + i0 + ii] : M[(i0 + ii) * K + k0 + kk])
+                                                : TC(0);
+    }
+    __syncthreads();
+    if (active) {
+      const int kend = static_cast<int>((K - k0) < kGenKC ? (K - k0) : kGenKC);
+      for (int kk = 0; kk < kend; ++kk) {
+        const TC x = static_cast<TC>(Load<TX>::get(xp, (k0 + kk) * B));
+#pragma unroll
+        for (int ii = 0; ii < MT; ++ii) acc[ii] = fma(sM[ii][kk], x, acc[ii]);
+      }
+    }
+  }
+  if (active) {
+    TC* y = static_cast<TC*>(J.Y);
+#pragma unroll
+    for (int ii = 0; ii < MT; ++ii)
+      if (i0 + ii < m) y[a * m * B + (i0 + ii) * B + b] = acc[ii];
+  }
+}
+
 // ------------------------------------------------------------------ MFMA
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -496,6 +542,34 @@ hipError_t launch_ttm_mfma_last(const float* X, int64_t A, int64_t K, const floa
   const int64_t n = A * m;
   const unsigned g2 = static_cast<unsigned>(ceil_div(n, 256) > 8192 ? 8192 : ceil_div(n, 256));
   sum_splits_kernel<<<g2, 256, 0, st>>>(out, p.ksplit, n, Y);
+  return hipGetLastError();
+}
+
+int64_t ttm_grouped_blocks(int64_t A, int64_t B, int64_t m, int mt) {
+  return ceil_div(A * B, kWave) * ceil_div(m, mt);
+}
+
+hipError_t launch_ttm_grouped(const GTtmJob* jobs, int count, int64_t total_blocks, rt_dtype xdt, int mt,
+                              hipStream_t st) {
+  if (count == 0 || total_blocks == 0) return hipSuccess;
+  const unsigned g = static_cast<unsigned>(total_blocks);
+#define RT_G(TX, TC, MTV) ttm_grouped_kernel<TX, TC, MTV><<<g, kWave, 0, st>>>(jobs, count)
+  // the row tile must be exactly the one the block counts were computed with
+  if (mt != 8 && mt != 16 && mt != 32) return hipErrorInvalidValue;
+  switch (xdt) {
+    case RT_F64:
+      if (mt == 8) RT_G(double, double, 8); else if (mt == 16) RT_G(double, double, 16); else RT_G(double, double, 32);
+      break;
+    case RT_F32:
+      if (mt == 8) RT_G(float, float, 8); else if (mt == 16) RT_G(float, float, 16); else RT_G(float, float, 32);
+      break;
+    case RT_BF16:
+      if (mt == 8) RT_G(bf16_t, float, 8); else if (mt == 16) RT_G(bf16_t, float, 16); else RT_G(bf16_t, float, 32);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef RT_G
   return hipGetLastError();
 }
 

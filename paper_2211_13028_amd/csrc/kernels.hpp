@@ -141,4 +141,75 @@ hipError_t launch_recon_residual(const void* X, rt_dtype xdt, int64_t I1, int64_
 // out[2] = ||G||^2 for a binary64 array of n values.
 hipError_t launch_sumsq_f64(const double* g, int64_t n, double* out_slot, hipStream_t st);
 
+// ------------------------------------------------------------------ grouped launches
+// For the batched decomposition: each launcher below runs many independent jobs
+// of one kind in a single launch.  The job table lives in device memory; job j
+// owns the workgroups [blk0_j, blk0_j + blocks_j) of a flat grid, and each
+// workgroup finds its job by binary search over blk0 (ascending).
+
+// k_basic.hip: operand rounding (PrepTask per job, blockIdx.y = job) and
+// binary32 -> binary64 copies.
+hipError_t launch_prep_grouped(const PrepTask* tasks, int count, int64_t max_elems, hipStream_t st);
+struct GCopyJob {
+  const float* src;
+  double* dst;
+  int64_t n;
+};
+hipError_t launch_copy_f64_grouped(const GCopyJob* jobs, int count, int64_t max_elems, hipStream_t st);
+
+// k_ttm.hip: generic TTM jobs (as launch_ttm_generic, no split-K).  Each job's
+// workgroups cover ceil(A*B / 64) column blocks times ceil(m / mt) row tiles
+// (column-block major, so the tiles of one column block run together).
+struct GTtmJob {
+  const void* X;
+  const void* M;
+  void* Y;
+  int64_t A, K, B, m;
+  int64_t blk0, colblocks, mtiles;
+  int32_t mtrans, pad;
+};
+int64_t ttm_grouped_blocks(int64_t A, int64_t B, int64_t m, int mt);
+hipError_t launch_ttm_grouped(const GTtmJob* jobs, int count, int64_t total_blocks, rt_dtype xdt, int mt,
+                              hipStream_t st);
+
+// k_sketch.hip: first sketch level (Z and W) per 3-way tensor (A, P, Q), one
+// workgroup per slab a; Q <= 256, s <= 8.  Operands in binary32.
+struct GZwJob {
+  const void* X;
+  const float* phiP;
+  const float* phiQ;
+  float* Z;
+  float* W;
+  int64_t A, P, Q;
+  int64_t blk0;
+  int32_t sP, sQ;
+};
+hipError_t launch_sketch_zw_grouped(const GZwJob* jobs, int count, int64_t total_blocks, rt_dtype xdt,
+                                    hipStream_t st);
+
+// k_qr.hip: thin Householder QR of (A, m, B) views with m <= 256 rows and
+// n = A*B <= 64 columns, one workgroup per job; Q: m x qcols (qcols = min(m, n)).
+struct GQrJob {
+  const void* Y;
+  int64_t A, m, B;
+  double* Q;
+  int32_t n, qcols;
+};
+hipError_t launch_qr_grouped(const GQrJob* jobs, int count, rt_dtype ydt, hipStream_t st);
+
+// k_eig.hip: Gram matrices out = G_(n) G_(n)^T of binary64 (A, m, B) views
+// (m <= 64), and the eigensolver of launch_sym_eig_top, one workgroup per job.
+struct GGramJob {
+  const double* G;
+  double* out;
+  int64_t A, m, B;
+};
+hipError_t launch_gram_grouped(const GGramJob* jobs, int count, hipStream_t st);
+struct GEigJob {
+  const double* M;
+  double* V;
+  int32_t n, r;
+};
+hipError_t launch_eig_grouped(const GEigJob* jobs, int count, hipStream_t st);
+
 }  // namespace rt

@@ -152,3 +152,16 @@ def batch_specs(count: int = 512, lo: int = 32, hi: int = 192, rlo: int = 4, rhi
     dims = rng.integers(lo, hi + 1, size=(count, 3))
     ranks = rng.integers(rlo, rhi + 1, size=(count, 3))
     return [tuple(int(v) for v in a) for a in dims], [tuple(int(v) for v in b) for b in ranks]
+
+
+def batch_tensor(i: int, dims, ranks, noise_rel: float = 1e-4, seed: int = DATA_SEED):
+    """Item i of a batch: a random Tucker tensor of Tucker rank ``ranks`` plus noise (float64)."""
+    x, _, _ = random_tucker(dims, ranks, noise_rel, seed=seed * 1_000_003 + i)
+    return x
+
+
+def batch_phis(dims_list, s_list, seed: int = PHI_SEED):
+    """Phi_k (s_k x I_k) for every item of a batch, drawn item by item in mode order."""
+    shapes = [(s[k], d[k]) for d, s in zip(dims_list, s_list) for k in range(3)]
+    flat = gaussians(seed, shapes)
+    return [flat[3 * i:3 * i + 3] for i in range(len(dims_list))]

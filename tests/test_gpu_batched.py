@@ -1,0 +1,122 @@
+"""GPU parity of the batched decomposition (grouped launches): every item
+against the FP64 oracle run on the same Phi, for uneven shapes of the
+many-small-tensors workload (dims U{32..192}^3, ranks U{4..16}^3, p = 4),
+plus graph capture, the autotuner and argument validation."""
+import numpy as np
+import pytest
+
+from gpu_common import dev, host, pytestmark_skip, rt, say, synth, torch
+from oracle import lowp as LP
+from oracle import tucker as T
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(pytestmark_skip, reason="needs a GPU")]
+
+P_OVER = 4
+
+
+def _batch(count, lo=32, hi=192, seed=synth.DATA_SEED, extra=()):
+    dims, ranks = synth.batch_specs(count, lo, hi, 4, 16, seed=seed)
+    dims = list(dims) + [e[0] for e in extra]
+    ranks = list(ranks) + [e[1] for e in extra]
+    s = [rt.rtucker_sketch_sizes(d, r, P_OVER, "rhkron") for d, r in zip(dims, ranks)]
+    phis = synth.batch_phis(dims, s)
+    Xs = [synth.batch_tensor(i, d, r, 1e-4, seed=seed) for i, (d, r) in enumerate(zip(dims, ranks))]
+    return dims, ranks, s, phis, Xs
+
+
+def _device_phis(phis):
+    return [[dev(f) for f in ph] for ph in phis]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_batched_matches_oracle(dtype):
+    # uneven sizes, including dims that are not multiples of 8 and a clipped sketch (I_k < prod s)
+    dims, ranks, s, phis, Xs = _batch(10, 32, 96, extra=[((17, 40, 33), (4, 5, 6)), ((12, 100, 9), (4, 4, 4))])
+    say("batched", dtype, len(Xs), "items")
+    tdt = torch.float32 if dtype == "f32" else torch.bfloat16
+    Xd = [rt.rtucker_convert(dev(X, torch.float32), tdt) if dtype == "bf16" else dev(X, torch.float32) for X in Xs]
+    B = rt.Batch(Xd, ranks, P_OVER, _device_phis(phis))
+    Gs, Us = B.run()
+    for i, X in enumerate(Xs):
+        Xseen = host(Xd[i])  # the values the device decomposed
+        e_dev = T.rel_error(Xseen, host(Gs[i]), [host(u) for u in Us[i]])
+        if dtype == "f32":
+            G, U = T.rhkron(Xseen, list(ranks[i]), phis[i])
+            e_or = T.rel_error(Xseen, G, U)
+        else:
+            G, U = LP.rhkron_emulated(Xseen, list(ranks[i]), phis[i], "bf16", "bf16")
+            e_or = T.rel_error(Xseen, G, U)
+        assert abs(e_dev - e_or) <= 1e-5, (i, dims[i], ranks[i], e_dev, e_or)
+        for k in range(3):
+            u = host(Us[i][k])
+            assert np.max(np.abs(u.T @ u - np.eye(ranks[i][k]))) < 1e-10
+
+
+def test_batched_equals_single_tensor_path():
+    dims, ranks, s, phis, Xs = _batch(6, 40, 120, seed=7)
+    Xd = [dev(X, torch.float32) for X in Xs]
+    B = rt.Batch(Xd, ranks, P_OVER, _device_phis(phis))
+    Gs, Us = B.run()
+    for i in range(len(Xs)):
+        G1, U1 = rt.rtucker_decompose(Xd[i], list(ranks[i]), P_OVER, [dev(f) for f in phis[i]], s=s[i])
+        e_b, _ = rt.rtucker_rel_error(Xd[i], Gs[i], Us[i])
+        e_s, _ = rt.rtucker_rel_error(Xd[i], G1, U1)
+        assert abs(e_b - e_s) <= 1e-6
+
+
+def test_batched_graph_replay_and_autotune():
+    dims, ranks, s, phis, Xs = _batch(8, 32, 80, seed=11)
+    Xd = [dev(X, torch.float32) for X in Xs]
+    B = rt.Batch(Xd, ranks, P_OVER, _device_phis(phis))
+    Gs, Us = B.run()
+    ref_G = [host(g).copy() for g in Gs]
+    ref_U = [[host(u).copy() for u in us] for us in Us]
+    chosen = B.autotune()
+    assert chosen in (8, 16, 32)
+    B.upload()
+    g = B.capture()
+    for rep in range(3):
+        for t in Gs:
+            t.fill_(float("nan"))  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i in range(len(Xs)):
+            if chosen == 16:  # same tiling as the reference: bitwise equal
+                assert np.array_equal(host(Gs[i]), ref_G[i])
+            else:
+                assert np.allclose(host(Gs[i]), ref_G[i], rtol=1e-4, atol=1e-6 * np.abs(ref_G[i]).max())
+            for k in range(3):
+                a, b = host(Us[i][k]), ref_U[i][k]
+                assert np.linalg.norm(a @ a.T - b @ b.T, 2) < 1e-4
+
+
+def test_batched_full_size_sampled():
+    """512 tensors of the many-small-tensors workload in FP32; 12 items checked against the oracle."""
+    count = 512
+    dims, ranks = synth.batch_specs(count)
+    s = [rt.rtucker_sketch_sizes(d, r, P_OVER, "rhkron") for d, r in zip(dims, ranks)]
+    phis = synth.batch_phis(dims, s)
+    say("batched full size: generating", count, "tensors")
+    Xd = [dev(synth.batch_tensor(i, d, r), torch.float32) for i, (d, r) in enumerate(zip(dims, ranks))]
+    B = rt.Batch(Xd, ranks, P_OVER, _device_phis(phis))
+    Gs, Us = B.run()
+    torch.cuda.synchronize()
+    for i in range(count):
+        assert bool(torch.isfinite(Gs[i]).all())
+    for i in np.random.default_rng(5).choice(count, 12, replace=False):
+        Xseen = host(Xd[i])
+        e_dev = T.rel_error(Xseen, host(Gs[i]), [host(u) for u in Us[i]])
+        G, U = T.rhkron(Xseen, list(ranks[i]), phis[i])
+        assert abs(e_dev - T.rel_error(Xseen, G, U)) <= 1e-5
+
+
+def test_batched_validation():
+    X = torch.zeros((20, 300, 20), dtype=torch.float32, device="cuda:0")
+    phis = [[dev(np.ones((2, 20))), dev(np.ones((2, 300))), dev(np.ones((2, 20)))]]
+    with pytest.raises(rt.RtuckerError):
+        rt.Batch([X], [(2, 2, 2)], 1, phis, s=[(2, 2, 2)]).run()  # a mode longer than 256
+    X = torch.zeros((20, 30, 20), dtype=torch.float32, device="cuda:0")
+    phis = [[dev(np.ones((9, 20))), dev(np.ones((2, 30))), dev(np.ones((2, 20)))]]
+    with pytest.raises(rt.RtuckerError):
+        rt.Batch([X], [(2, 2, 2)], 1, phis, s=[(9, 2, 2)]).run()  # subrank above 8
