@@ -60,6 +60,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="time only the headline BF16 path")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the 128^4 rSTHKron, 256^3 adjoint and 512-tensor batch measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note, "
@@ -164,20 +166,35 @@ def main():
         fl = 2 * ell[0] * N
         kernels[f"core_ttm1_{tag}"] = {"ms": ms, "GB/s": byts / ms / 1e6, "TFLOP/s": fl / ms / 1e9,
                                        "alg_bytes": byts, "alg_flops": fl}
-        # sketch pass (Z/W streaming pass + small tree contractions + unfold)
+        # the streaming sketch pass: Z = X x3 Phi3 and W = X x2 Phi2 in one read of X
+        # (launches: operand rounding, the pass, and the fixed-order sum of its row-range partials)
+        Zb = torch.empty((DIMS[0], DIMS[1], s[2]), dtype=torch.float32, device=dev)
+        Wb = torch.empty((DIMS[0], s[1], DIMS[2]), dtype=torch.float32, device=dev)
+        Zb, Wb = rt.rtucker_sketch_pass(X, phis[1], phis[2], Z=Zb, W=Wb)
+        ms = kernel_time(lambda: rt.rtucker_sketch_pass(X, phis[1], phis[2], Z=Zb, W=Wb))
+        byts = N * esz + (Zb.numel() + Wb.numel()) * 4
+        fl = 2 * N * (s[1] + s[2])
+        kernels[f"sketch_pass_{tag}"] = {"ms": ms, "GB/s": byts / ms / 1e6, "TFLOP/s": fl / ms / 1e9,
+                                         "alg_bytes": byts, "alg_flops": fl}
+        # the whole sketch call (pass + the small contractions of the tree + unfolds)
         ms = kernel_time(lambda: rt.rtucker_sketch(X, phis, s))
         zbytes = (DIMS[0] * DIMS[1] * s[2] + DIMS[0] * s[1] * DIMS[2]) * 4
         byts = N * esz + zbytes
         fl = sk_flops
         kernels[f"sketch_{tag}"] = {"ms": ms, "GB/s": byts / ms / 1e6, "TFLOP/s": fl / ms / 1e9,
                                     "alg_bytes": byts, "alg_flops": fl}
+        del Zb, Wb
 
-    # dominant kernel of the headline (BF16) step
-    dom = max(("core_ttm1_bf16", "sketch_bf16"), key=lambda k: kernels[k]["ms"])
+    # dominant kernel of the headline (BF16) step: the larger of the sketch pass and the first core contraction
+    dom = max(("core_ttm1_bf16", "sketch_pass_bf16"), key=lambda k: kernels[k]["ms"])
     kd = kernels[dom]
     achieved = kd["GB/s"] * 1e9
     roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved / 1e9, 1), "peak": HBM_PEAK / 1e9,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4), "traffic": None}
+
+    extras = {}
+    if not args.no_extras:
+        extras = run_extras(rt, synth, torch, dev, time_steps, log)
 
     # ---------------------------------------------------------------- CPU baseline (oracle, whole workload)
     cpu = None
@@ -220,8 +237,90 @@ def main():
         "paths": {k: {"ms": round(v["ms"], 4), "rel_err": v["rel_err"]} for k, v in results.items()},
         "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kernels.items()},
+        "other_workloads": extras,
     }
     print(json.dumps(out))
+
+
+def run_extras(rt, synth, torch, dev, time_steps, log):
+    """The other workloads, timed beside the headline (not part of its value)."""
+    from paper_2211_13028_amd import autograd as RA
+    out = {}
+    # ---- 128^4 FP32, decaying 16^4 core, rSTHKron with subranks 3 (sketch width 27), r = 16, p = 6
+    dims4, r4 = (128, 128, 128, 128), (16, 16, 16, 16)
+    log("generating the 128^4 tensor ...")
+    core = synth.tucker_core_decay((16, 16, 16, 16), 6.0, seed=synth.DATA_SEED)
+    X4h, _, _ = synth.random_tucker(dims4, (16, 16, 16, 16), 1e-3, seed=synth.DATA_SEED, core=core)
+    X4 = torch.from_numpy(X4h.astype(np.float32)).to(dev)
+    del X4h
+    S4 = [[1 if k == j else 3 for k in range(4)] for j in range(4)]
+    cdim = [min(dims4[k], 27) for k in range(4)]
+    shapes = [None if k == j else (3, cdim[k] if k < j else dims4[k]) for j in range(4) for k in range(4)]
+    flat = synth.gaussians(synth.PHI_SEED, shapes)
+    ph4 = [[None if f is None else torch.from_numpy(f).to(dev) for f in flat[j * 4:(j + 1) * 4]] for j in range(4)]
+    for tag, X in (("f32", X4), ("bf16", rt.rtucker_convert(X4, torch.bfloat16))):
+        nb = rt.rtucker_decompose_workspace(X, r4, 6, "rsthkron", S4)
+        ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
+        G = torch.empty(r4, dtype=torch.float64, device=dev)
+        Us = [torch.empty((128, 16), dtype=torch.float64, device=dev) for _ in range(4)]
+
+        def fn():
+            rt.rtucker_decompose(X, r4, 6, ph4, algo="rsthkron", s=S4, G=G, Us=Us, ws=ws)
+        log(f"timing 128^4 rSTHKron {tag} ...")
+        ms = time_steps(fn, 10, 2)
+        e, _ = rt.rtucker_rel_error(X4, G, Us)
+        out[f"rsthkron_128^4_{tag}"] = {"ms": round(ms, 4), "rel_err": e}
+        del ws
+    del X4
+    torch.cuda.empty_cache()
+    # ---- 256^3 FP32 projection loss, fixed rank-24 factors: forward + hand-written backward
+    n3, rr = 256, 24
+    X3h, _, _ = synth.random_tucker((n3, n3, n3), (rr, rr, rr), 1e-6, seed=synth.DATA_SEED)
+    X3 = torch.from_numpy(X3h.astype(np.float32)).to(dev).requires_grad_(True)
+    U3 = [torch.from_numpy(u.astype(np.float32)).to(dev).requires_grad_(True)
+          for u in synth.fixed_factors((n3, n3, n3), (rr, rr, rr))]
+
+    def step():
+        X3.grad = None
+        for u in U3:
+            u.grad = None
+        RA.projection_loss(X3, U3).backward()
+    log("timing the 256^3 projection loss forward + backward ...")
+    ms = time_steps(step, 20, 3)
+    # algorithmic traffic: X read by the forward (G, then the residual) and by the backward
+    # recomputation (2 passes); R written and read 4 times; X_hat, P R and dX written once each
+    nbytes = X3.numel() * 4
+    alg = nbytes * (2 + 2) + nbytes * (1 + 4) + nbytes * 3
+    out["projection_loss_256^3_f32"] = {"ms": round(ms, 4), "alg_bytes": alg, "GB/s": round(alg / ms / 1e6, 1),
+                                        "hbm_frac": round(alg / ms / 1e6 / (HBM_PEAK / 1e9), 4)}
+    del X3, U3
+    torch.cuda.empty_cache()
+    # ---- 512 tensors, dims U{32..192}^3, ranks U{4..16}^3, p = 4, grouped launches
+    count = 512
+    dims, ranks = synth.batch_specs(count)
+    sb = [rt.rtucker_sketch_sizes(d, r, 4, "rhkron") for d, r in zip(dims, ranks)]
+    phis = synth.batch_phis(dims, sb)
+    log("generating the 512-tensor batch ...")
+    X32 = [torch.from_numpy(synth.batch_tensor(i, d, r).astype(np.float32)).to(dev)
+           for i, (d, r) in enumerate(zip(dims, ranks))]
+    php = [[torch.from_numpy(f).to(dev) for f in ph] for ph in phis]
+    nel = sum(int(x.numel()) for x in X32)
+    for tag, Xs in (("f32", X32), ("bf16", [rt.rtucker_convert(x, torch.bfloat16) for x in X32])):
+        B = rt.Batch(Xs, ranks, 4, php)
+        B.run()
+        mt = B.autotune()
+        B.upload()
+        log(f"timing the 512-tensor batch {tag} ...")
+        ms = time_steps(B.launch, 10, 2)
+        esz = 4 if tag == "f32" else 2
+        alg = 2 * nel * esz  # two reads of every tensor: the sketch pass and the first core contraction
+        errs = [rt.rtucker_rel_error(X32[i], B.Gs[i], B.Us[i])[0] for i in range(0, count, 64)]
+        out[f"batch512_{tag}"] = {"ms": round(ms, 4), "tensors_per_s": round(count / (ms / 1e3), 1),
+                                  "alg_bytes": alg, "GB/s": round(alg / ms / 1e6, 1),
+                                  "hbm_frac": round(alg / ms / 1e6 / (HBM_PEAK / 1e9), 4), "core_row_tile": mt,
+                                  "max_rel_err_sampled": max(errs)}
+        del B
+    return out
 
 
 if __name__ == "__main__":

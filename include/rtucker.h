@@ -111,6 +111,21 @@ int rtucker_sketch_workspace(const rt_tensor* X, const int64_t* s, uint32_t mode
 int rtucker_sketch(const rt_tensor* X, const double* const* phi, const int64_t* s,
                    uint32_t mode_mask, void* const* Y, void* ws, size_t ws_bytes, void* stream);
 
+/* The single streaming pass of that sketch: the two children of the root of the
+ * dimension tree (Sec. 4.4), computed together in one read of X,
+ *   Z = X x_d Phi_d          (dims of X with the last mode replaced by s_last)
+ *   W = X x_{d-1} Phi_{d-1}  (dims of X with mode d-1 replaced by s_prev)
+ * with the same operand rounding and accumulation as rtucker_sketch.  Every
+ * sketch of a mode is Z or W contracted further by small factors.
+ *  phi_prev: device binary64 s_prev x I_{d-1}; phi_last: s_last x I_d.
+ *  Z, W: device, compute type (binary64 for F64 X, else binary32), C order;
+ *  either may be NULL (not computed; its factor may then be NULL too).
+ *  ws: at least rtucker_sketch_pass_workspace() bytes (sized for both outputs). */
+int rtucker_sketch_pass_workspace(const rt_tensor* X, int64_t s_prev, int64_t s_last, size_t* bytes);
+int rtucker_sketch_pass(const rt_tensor* X, const double* phi_prev, int64_t s_prev,
+                        const double* phi_last, int64_t s_last, void* Z, void* W, void* ws,
+                        size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------------ QR
  * Thin QR of a tall-skinny sketch (range-finder QR, Alg. 2.3): Y = Q R with
  * Householder reflections in binary64 and diag(R) >= 0, so Q is unique when Y

@@ -47,6 +47,10 @@ _SIGS = {
     "rtucker_sketch_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p]),
     "rtucker_sketch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "rtucker_sketch_pass_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p]),
+    "rtucker_sketch_pass": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                           ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_size_t, ctypes.c_void_p]),
     "rtucker_qr_workspace": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p]),
     "rtucker_qr": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
@@ -221,6 +225,30 @@ def rtucker_sketch(X, phis, s: Sequence[int], modes=None):
     _check(lib().rtucker_sketch(ctypes.byref(xt), _ptrs(phis), _i64(s), mask, _ptrs(Ys), _ptr(ws), wb,
                                 _stream(X.device)), "rtucker_sketch")
     return Ys
+
+
+def rtucker_sketch_pass(X, phi_prev, phi_last, Z=None, W=None, ws=None, want=(True, True)):
+    """(Z, W) = (X x_d Phi_d, X x_{d-1} Phi_{d-1}) in one pass over X (either skipped via ``want``)."""
+    torch = _torch()
+    d = X.dim()
+    xt = _tensor(X)
+    s_prev, s_last = int(phi_prev.shape[0]), int(phi_last.shape[0])
+    ct = torch.float64 if X.dtype == torch.float64 else torch.float32
+    if want[0] and Z is None:
+        Z = torch.empty(tuple(X.shape[:-1]) + (s_last,), dtype=ct, device=X.device)
+    if want[1] and W is None:
+        W = torch.empty(tuple(X.shape[:d - 2]) + (s_prev, X.shape[-1]), dtype=ct, device=X.device)
+    if ws is None:
+        nb = ctypes.c_size_t()
+        _check(lib().rtucker_sketch_pass_workspace(ctypes.byref(xt), s_prev, s_last, ctypes.byref(nb)),
+               "rtucker_sketch_pass_workspace")
+        ws, wb = _workspace(nb.value, X.device)
+    else:
+        wb = int(ws.numel())
+    _check(lib().rtucker_sketch_pass(ctypes.byref(xt), _ptr(phi_prev), s_prev, _ptr(phi_last), s_last,
+                                     _ptr(Z if want[0] else None), _ptr(W if want[1] else None), _ptr(ws), wb,
+                                     _stream(X.device)), "rtucker_sketch_pass")
+    return (Z if want[0] else None), (W if want[1] else None)
 
 
 def rtucker_qr(Y, want_r: bool = False):

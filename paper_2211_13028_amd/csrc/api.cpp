@@ -429,6 +429,43 @@ int plan_sketch(Ctx& c, const rt_tensor* X, const double* const* phi, const int6
   return RT_OK;
 }
 
+// the first level of the sketch's dimension tree alone: Z = X x_L Phi_L, W = X x_S Phi_S
+int plan_sketch_pass(Ctx& c, const rt_tensor* X, const double* phiS, int64_t sS, const double* phiL, int64_t sL,
+                     void* Z, void* W, bool wantZ, bool wantW) {
+  int st = check_tensor(X, c.check_ptrs);
+  if (st) return st;
+  const int d = X->d;
+  const int S = d - 2, L = d - 1;
+  if (!wantZ && !wantW) return RT_EINVAL;
+  if (wantW && (sS < 1 || sS > X->dims[S])) return RT_ESHAPE;
+  if (wantZ && (sL < 1 || sL > X->dims[L])) return RT_ESHAPE;
+  if (c.check_ptrs && ((wantZ && (!Z || !phiL)) || (wantW && (!W || !phiS)))) return RT_EINVAL;
+  const Ten T = ten_of(X);
+  const rt_dtype ct = ctype(X->dtype);
+  const int64_t sP = wantW ? sS : 1, sQ = wantZ ? sL : 1;
+  const void* opS = wantW ? prep(c, phiS, sS, X->dims[S], false, X->dtype, ct) : nullptr;
+  const void* opL = wantZ ? prep(c, phiL, sL, X->dims[L], false, X->dtype, ct) : nullptr;
+  if (sketch_zw_ok(X->dtype, sP, sQ)) {
+    const int64_t A0 = T.before(S), P = X->dims[S], Q = X->dims[L];
+    const ZWPlan plan = sketch_zw_plan(X->dtype, A0, P, Q, sP, sQ, wantZ, wantW);
+    void* zws = plan.ws_bytes ? c.take(plan.ws_bytes) : nullptr;
+    const void* p16 = nullptr;
+    const void* q16 = nullptr;
+    if (plan.mfma) {
+      if (wantW) p16 = prep(c, phiS, sS, P, false, RT_BF16, RT_BF16, 16);
+      if (wantZ) q16 = prep(c, phiL, sL, Q, false, RT_BF16, RT_BF16, 16);
+    }
+    c.flush();
+    if (!c.dry)
+      c.chk(launch_sketch_zw(X->data, X->dtype, A0, P, Q, opS, sP, opL, sQ, p16, q16, wantZ ? Z : nullptr,
+                             wantW ? W : nullptr, plan, zws, c.st));
+  } else {
+    if (wantZ) ttm(c, T, L, opL, sL, Z);
+    if (wantW) ttm(c, T, S, opS, sS, W);
+  }
+  return RT_OK;
+}
+
 int plan_core(Ctx& c, const rt_tensor* X, const double* const* U, const int64_t* l, uint32_t mask, void* G) {
   int st = check_tensor(X, c.check_ptrs);
   if (st) return st;
@@ -1049,6 +1086,17 @@ int rtucker_sq_residual(const rt_tensor* A, const void* B, void* R, double* out,
   return launch_sq_residual(A->data, B, R, A->dtype, n, out, ws, static_cast<hipStream_t>(stream)) == hipSuccess
              ? RT_OK
              : RT_EHIP;
+}
+
+int rtucker_sketch_pass_workspace(const rt_tensor* X, int64_t s_prev, int64_t s_last, size_t* bytes) {
+  return query([&](Ctx& c) { return plan_sketch_pass(c, X, nullptr, s_prev, nullptr, s_last, nullptr, nullptr, true, true); },
+               bytes);
+}
+
+int rtucker_sketch_pass(const rt_tensor* X, const double* phi_prev, int64_t s_prev, const double* phi_last,
+                        int64_t s_last, void* Z, void* W, void* ws, size_t ws_bytes, void* stream) {
+  return run([&](Ctx& c) { return plan_sketch_pass(c, X, phi_prev, s_prev, phi_last, s_last, Z, W, Z != nullptr, W != nullptr); },
+             ws, ws_bytes, stream);
 }
 
 int rtucker_scaled_diff(const rt_tensor* A, const void* B, const double* g, double alpha, void* out,

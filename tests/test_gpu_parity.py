@@ -317,3 +317,33 @@ def test_rel_error_matches_oracle():
     e, norms = rt.rtucker_rel_error(dev(X), dev(G), [dev(U) for U in Us])
     assert abs(e - T.rel_error(X, G, Us)) <= 1e-13
     assert abs(norms["g2"] - np.sum(G * G)) <= 1e-12 * np.sum(G * G)
+
+
+# ------------------------------------------------------------------ the streaming sketch pass alone
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("shape,sp,sl", [((37, 150, 530), 7, 7), ((64, 64, 64), 4, 4), ((11, 13, 17, 70), 3, 5),
+                                         ((20, 24, 30), 9, 10), ((1024, 1024 // 8, 512 // 4), 7, 7)])
+def test_sketch_pass(dtype, shape, sp, sl):
+    say("sketch pass", shape, sp, sl, dtype)
+    rng = np.random.default_rng(51)
+    X = rng.standard_normal(shape)
+    Pp, Pl = rng.standard_normal((sp, shape[-2])), rng.standard_normal((sl, shape[-1]))
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dtype]
+    Xd = dev(X, torch.float64).to(tdt) if dtype != "bf16" else rt.rtucker_convert(dev(X, torch.float32), tdt)
+    Z, W = rt.rtucker_sketch_pass(Xd, dev(Pp), dev(Pl))
+    Xs = host(Xd)
+    if dtype == "bf16":
+        Pp_, Pl_ = L.round_bf16(Pp), L.round_bf16(Pl)
+    elif dtype == "f32":
+        Pp_, Pl_ = Pp.astype(np.float32).astype(np.float64), Pl.astype(np.float32).astype(np.float64)
+    else:
+        Pp_, Pl_ = Pp, Pl
+    d = len(shape)
+    Zr = T.ttm(Xs, Pl_, d - 1)
+    Wr = T.ttm(Xs, Pp_, d - 2)
+    tol = 1e-13 if dtype == "f64" else 2e-6
+    assert np.linalg.norm(host(Z) - Zr) <= tol * np.linalg.norm(Zr)
+    assert np.linalg.norm(host(W) - Wr) <= tol * np.linalg.norm(Wr)
+    # one output only
+    Z2, W2 = rt.rtucker_sketch_pass(Xd, dev(Pp), dev(Pl), want=(True, False))
+    assert W2 is None and np.array_equal(host(Z2), host(Z))
