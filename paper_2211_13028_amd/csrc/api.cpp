@@ -171,8 +171,8 @@ void sketch_impl(Ctx& c, const Ten& X, const double* const* phi, const int64_t* 
     const void* p16 = nullptr;
     const void* q16 = nullptr;
     if (plan.mfma) {  // bfloat16 factors padded to 16 rows for the matrix-core pass
-      if (needW) p16 = prep(c, phi ? phi[S] : nullptr, s[S], P, false, RT_BF16, RT_BF16, 16);
-      if (needZ) q16 = prep(c, phi ? phi[L] : nullptr, s[L], Q, false, RT_BF16, RT_BF16, 16);
+      if (needW) p16 = prep(c, phi ? phi[S] : nullptr, s[S], P, false, X.dt, RT_BF16, 16);
+      if (needZ) q16 = prep(c, phi ? phi[L] : nullptr, s[L], Q, false, X.dt, RT_BF16, 16);
     }
     c.flush();
     if (!c.dry)
@@ -452,8 +452,8 @@ int plan_sketch_pass(Ctx& c, const rt_tensor* X, const double* phiS, int64_t sS,
     const void* p16 = nullptr;
     const void* q16 = nullptr;
     if (plan.mfma) {
-      if (wantW) p16 = prep(c, phiS, sS, P, false, RT_BF16, RT_BF16, 16);
-      if (wantZ) q16 = prep(c, phiL, sL, Q, false, RT_BF16, RT_BF16, 16);
+      if (wantW) p16 = prep(c, phiS, sS, P, false, X->dtype, RT_BF16, 16);
+      if (wantZ) q16 = prep(c, phiL, sL, Q, false, X->dtype, RT_BF16, 16);
     }
     c.flush();
     if (!c.dry)

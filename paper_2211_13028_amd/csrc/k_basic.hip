@@ -32,7 +32,8 @@ __device__ __forceinline__ void store_rounded(void* dst, rt_dtype store, rt_dtyp
   switch (store) {
     case RT_F64: static_cast<double*>(dst)[i] = round_value(x, fmt); break;
     case RT_F32: static_cast<float*>(dst)[i] = static_cast<float>(round_value(x, fmt)); break;
-    case RT_BF16: static_cast<bf16_t*>(dst)[i] = f64_to_bf16_bits(x); break;
+    // a bfloat16 store of a value rounded to FP8 first is exact (matrix-core operands of FP8 data)
+    case RT_BF16: static_cast<bf16_t*>(dst)[i] = f64_to_bf16_bits(fmt == RT_BF16 ? x : round_value(x, fmt)); break;
     default: static_cast<f8_t*>(dst)[i] = f64_to_f8_bits(x); break;
   }
 }

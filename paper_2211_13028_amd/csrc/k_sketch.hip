@@ -199,8 +199,10 @@ __global__ __launch_bounds__(256) void sum_parts_kernel(const TC* __restrict__ p
   }
 }
 
-// ------------------------------------------------------------------ bfloat16 on matrix cores
+// ------------------------------------------------------------------ bfloat16 / FP8 on matrix cores
 // Same two contractions on MFMA (v_mfma_f32_16x16x32_bf16, binary32 accumulation).
+// FP8 e4m3 data is widened exactly to bfloat16 as it is loaded, so it streams at
+// one byte per element and multiplies as the FP8 values themselves.
 // A workgroup of four waves covers 512 columns of a row range; wave w owns the
 // 128 columns q0 + 128 w .. + 127 and all waves step through the rows together,
 // 32 at a time:
@@ -222,17 +224,51 @@ constexpr int kTileStride = 136;  // bf16 per staged row: 128 columns + 8 paddin
 
 __device__ __forceinline__ u32x4 ld16(const bf16_t* p) { return *reinterpret_cast<const u32x4*>(p); }
 
-__device__ __forceinline__ void load_block(const bf16_t* xa, int64_t Q, int64_t p0, int64_t pend, int64_t qc,
-                                           bool colok, u32x4 (&r)[8]) {
+// Raw loads of an 8-row x 8-column block (row t: 8 consecutive columns) and their
+// widening to bfloat16 pairs.  The widening happens when a prefetched block is
+// used, so the loads stay in flight across the previous step.
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+template <typename TX>
+struct BlockIO;
+
+template <>
+struct BlockIO<bf16_t> {
+  typedef u32x4 raw_t;  // 8 bfloat16
+  static __device__ __forceinline__ raw_t load(const bf16_t* p) { return *reinterpret_cast<const u32x4*>(p); }
+  static __device__ __forceinline__ raw_t zero() { return u32x4{0u, 0u, 0u, 0u}; }
+  static __device__ __forceinline__ u32x4 widen(raw_t v) { return v; }
+};
+
+// FP8 e4m3: 8 bytes per row, widened exactly to bfloat16 (every e4m3 value is a
+// bfloat16 value) by the hardware conversion, so the products are the FP8 ones
+template <>
+struct BlockIO<f8_t> {
+  typedef u32x2 raw_t;
+  static __device__ __forceinline__ raw_t load(const f8_t* p) { return *reinterpret_cast<const u32x2*>(p); }
+  static __device__ __forceinline__ raw_t zero() { return u32x2{0u, 0u}; }
+  static __device__ __forceinline__ u32x4 widen(raw_t v) {
+    return u32x4{__builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(v[0], 1.0f, false)),
+                 __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(v[0], 1.0f, true)),
+                 __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(v[1], 1.0f, false)),
+                 __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(v[1], 1.0f, true))};
+  }
+};
+
+template <typename TX>
+__device__ __forceinline__ void load_block(const TX* xa, int64_t Q, int64_t p0, int64_t pend, int64_t qc, bool colok,
+                                           typename BlockIO<TX>::raw_t (&r)[8]) {
 #pragma unroll
   for (int t = 0; t < 8; ++t) {
     const int64_t p = p0 + t;
-    r[t] = (colok && p < pend) ? ld16(xa + p * Q + qc) : u32x4{0u, 0u, 0u, 0u};
+    r[t] = (colok && p < pend) ? BlockIO<TX>::load(xa + p * Q + qc) : BlockIO<TX>::zero();
   }
 }
 
+template <typename TX>
 __global__ __launch_bounds__(kZWThreads) __attribute__((amdgpu_waves_per_eu(3))) void sketch_zw_bf16_mfma_kernel(
-    const bf16_t* __restrict__ X, int64_t A, int64_t P, int64_t Q, const bf16_t* __restrict__ phiP, int sP,
+    const TX* __restrict__ X, int64_t A, int64_t P, int64_t Q, const bf16_t* __restrict__ phiP, int sP,
     const bf16_t* __restrict__ phiQ, int sQ, int64_t rows_per_block, int qblocks, int pblocks,
     float* __restrict__ Zo, float* __restrict__ Wo) {
   __shared__ bf16_t tile[kZWWaves][32 * kTileStride];
@@ -251,7 +287,7 @@ __global__ __launch_bounds__(kZWThreads) __attribute__((amdgpu_waves_per_eu(3)))
   const int li = lane % 16, kg = lane / 16;
   const int64_t pbeg = static_cast<int64_t>(pblk) * rows_per_block;
   const int64_t pend = (pbeg + rows_per_block < P) ? pbeg + rows_per_block : P;
-  const bf16_t* xa = X + a * P * Q;
+  const TX* xa = X + a * P * Q;
   bf16_t* my = tile[wave];
   const int64_t qc = qw + 8 * li;
   const bool colok = qc < qend;
@@ -267,13 +303,13 @@ __global__ __launch_bounds__(kZWThreads) __attribute__((amdgpu_waves_per_eu(3)))
 #pragma unroll
   for (int c = 0; c < 8; ++c) wacc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  u32x4 rn[8];
+  typename BlockIO<TX>::raw_t rn[8];
   load_block(xa, Q, pbeg + 8 * kg, pend, qc, colok, rn);
   int buf = 0;
   for (int64_t pb = pbeg; pb < pend; pb += 32) {
     u32x4 r[8];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) r[t] = rn[t];
+    for (int t = 0; t < 8; ++t) r[t] = BlockIO<TX>::widen(rn[t]);
     if (pb + 32 < pend) load_block(xa, Q, pb + 32 + 8 * kg, pend, qc, colok, rn);
     if (needW) {
       // PhiP operand: row c = li, columns pb + 8 kg .. + 7 (8-row groups lie wholly
@@ -382,7 +418,7 @@ bool sketch_zw_ok(rt_dtype, int64_t sP, int64_t sQ) { return sP >= 1 && sQ >= 1 
 ZWPlan sketch_zw_plan(rt_dtype xdt, int64_t A, int64_t P, int64_t Q, int64_t sP, int64_t sQ, bool needZ,
                       bool needW) {
   ZWPlan p;
-  p.mfma = (xdt == RT_BF16) && (P % 8 == 0) && (Q % 8 == 0) && P >= 32;
+  p.mfma = (xdt == RT_BF16 || xdt == RT_F8E4M3) && (P % 8 == 0) && (Q % 8 == 0) && P >= 32;
   const int nq = pick_nq(xdt, Q);
   p.qblocks = p.mfma ? ceil_div(Q, kZWColsMfma) : ceil_div(Q, 64 * nq);
   if (p.mfma) {
@@ -446,10 +482,16 @@ hipError_t launch_sketch_zw(const void* X, rt_dtype xdt, int64_t A, int64_t P, i
   const int isP = static_cast<int>(sP), isQ = static_cast<int>(sQ);
   if (plan.mfma) {
     const int64_t blocks = A * plan.pblocks * plan.qblocks;
-    sketch_zw_bf16_mfma_kernel<<<static_cast<unsigned>(blocks), kZWThreads, 0, st>>>(
-        static_cast<const bf16_t*>(X), A, P, Q, static_cast<const bf16_t*>(phiP16), isP,
-        static_cast<const bf16_t*>(phiQ16), isQ, plan.rows_per_block, static_cast<int>(plan.qblocks),
-        static_cast<int>(plan.pblocks), static_cast<float*>(zdst), static_cast<float*>(wdst));
+    if (xdt == RT_F8E4M3)
+      sketch_zw_bf16_mfma_kernel<f8_t><<<static_cast<unsigned>(blocks), kZWThreads, 0, st>>>(
+          static_cast<const f8_t*>(X), A, P, Q, static_cast<const bf16_t*>(phiP16), isP,
+          static_cast<const bf16_t*>(phiQ16), isQ, plan.rows_per_block, static_cast<int>(plan.qblocks),
+          static_cast<int>(plan.pblocks), static_cast<float*>(zdst), static_cast<float*>(wdst));
+    else
+      sketch_zw_bf16_mfma_kernel<bf16_t><<<static_cast<unsigned>(blocks), kZWThreads, 0, st>>>(
+          static_cast<const bf16_t*>(X), A, P, Q, static_cast<const bf16_t*>(phiP16), isP,
+          static_cast<const bf16_t*>(phiQ16), isQ, plan.rows_per_block, static_cast<int>(plan.qblocks),
+          static_cast<int>(plan.pblocks), static_cast<float*>(zdst), static_cast<float*>(wdst));
     e = hipGetLastError();
   } else
   switch (xdt) {

@@ -16,7 +16,8 @@ hipError_t launch_convert(const void* src, rt_dtype sdt, void* dst, rt_dtype ddt
 //   rounded to `round_to` (RNE).  src is m x K row-major (trans == false) or
 //   K x m row-major (trans == true).  Rows i >= m up to m_pad are zero-filled.
 //   store: RT_F64, RT_F32 (value rounded to round_to, kept in binary32),
-//   RT_BF16 or RT_F8E4M3 (bit patterns; round_to must equal store).
+//   RT_BF16 (bit patterns; round_to BF16, or F8E4M3 whose values bfloat16 holds exactly)
+//   or RT_F8E4M3 (bit patterns; round_to must be F8E4M3).
 hipError_t launch_prep_matrix(const double* src, int64_t m, int64_t K, bool trans, rt_dtype round_to,
                               rt_dtype store, int64_t m_pad, void* dst, hipStream_t st);
 
@@ -85,8 +86,9 @@ hipError_t launch_ttm_mfma_last(const float* X, int64_t A, int64_t K, const floa
 // phiP/phiQ: compute type (binary64 for F64 X, else binary32 holding values
 // already rounded to X's dtype), row-major sP x P and sQ x Q.
 // Either output may be skipped (null).  Z/W in the compute type.
-// bfloat16 X with P, Q multiples of 8 runs on matrix cores (plan.mfma) and also
-// needs phiP16 / phiQ16: the factors as bfloat16, zero-padded to 16 rows.
+// bfloat16 or FP8 e4m3 X with P, Q multiples of 8 runs on matrix cores (plan.mfma)
+// and also needs phiP16 / phiQ16: the factors rounded to X's dtype, stored as
+// bfloat16 (exact), zero-padded to 16 rows.
 struct ZWPlan {
   int64_t qblocks, pblocks, rows_per_block;
   size_t ws_bytes;

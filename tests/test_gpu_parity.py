@@ -320,7 +320,7 @@ def test_rel_error_matches_oracle():
 
 
 # ------------------------------------------------------------------ the streaming sketch pass alone
-@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f8"])
 @pytest.mark.parametrize("shape,sp,sl", [((37, 150, 530), 7, 7), ((64, 64, 64), 4, 4), ((11, 13, 17, 70), 3, 5),
                                          ((20, 24, 30), 9, 10), ((1024, 1024 // 8, 512 // 4), 7, 7)])
 def test_sketch_pass(dtype, shape, sp, sl):
@@ -328,12 +328,17 @@ def test_sketch_pass(dtype, shape, sp, sl):
     rng = np.random.default_rng(51)
     X = rng.standard_normal(shape)
     Pp, Pl = rng.standard_normal((sp, shape[-2])), rng.standard_normal((sl, shape[-1]))
-    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dtype]
-    Xd = dev(X, torch.float64).to(tdt) if dtype != "bf16" else rt.rtucker_convert(dev(X, torch.float32), tdt)
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16, "f8": torch.float8_e4m3fn}[dtype]
+    if dtype in ("f64", "f32"):
+        Xd = dev(X, torch.float64).to(tdt)
+    else:
+        Xd = rt.rtucker_convert(dev(X, torch.float32), tdt)
     Z, W = rt.rtucker_sketch_pass(Xd, dev(Pp), dev(Pl))
-    Xs = host(Xd)
+    Xs = host(Xd) if dtype != "f8" else L.f8_decode(Xd.view(torch.uint8).cpu().numpy())
     if dtype == "bf16":
         Pp_, Pl_ = L.round_bf16(Pp), L.round_bf16(Pl)
+    elif dtype == "f8":
+        Pp_, Pl_ = L.round_f8(Pp), L.round_f8(Pl)
     elif dtype == "f32":
         Pp_, Pl_ = Pp.astype(np.float32).astype(np.float64), Pl.astype(np.float32).astype(np.float64)
     else:
