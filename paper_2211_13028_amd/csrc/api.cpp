@@ -153,11 +153,14 @@ void sketch_impl(Ctx& c, const Ten& X, const double* const* phi, const int64_t* 
       if ((mask >> n & 1u) && n != k) need = true;
     if (need) op[k] = prep(c, phi ? phi[k] : nullptr, s[k], X.dims[k], false, X.dt, ct);
   }
+  // tree: Z = X x_L Phi_L serves only mode S; W = X x_S Phi_S serves every other mode
+  // (W is the smaller node whenever s_S I_L <= I_S s_L, and its first contraction
+  // for modes n < S is over its contiguous last mode)
   const int L = d - 1, S = d - 2;
   bool needZ = false, needW = false;
   for (int n = 0; n < d; ++n)
     if (mask >> n & 1u) {
-      if (n == L) needW = true; else needZ = true;
+      if (n == S) needZ = true; else needW = true;
     }
   Ten Z, W;
   Z.dims = X.dims; Z.dims[L] = s[L]; Z.dt = ct; Z.p = nullptr;
@@ -170,7 +173,7 @@ void sketch_impl(Ctx& c, const Ten& X, const double* const* phi, const int64_t* 
     void* zws = plan.ws_bytes ? c.take(plan.ws_bytes) : nullptr;
     const void* p16 = nullptr;
     const void* q16 = nullptr;
-    if (plan.mfma) {  // bfloat16 factors padded to 16 rows for the matrix-core pass
+    if (plan.mfma) {  // factors rounded to X's dtype, bfloat16 storage, padded to 16 rows
       if (needW) p16 = prep(c, phi ? phi[S] : nullptr, s[S], P, false, X.dt, RT_BF16, 16);
       if (needZ) q16 = prep(c, phi ? phi[L] : nullptr, s[L], Q, false, X.dt, RT_BF16, 16);
     }
@@ -182,15 +185,40 @@ void sketch_impl(Ctx& c, const Ten& X, const double* const* phi, const int64_t* 
     if (needZ) Z = ttm(c, X, L, op[L], s[L]);
     if (needW) W = ttm(c, X, S, op[S], s[S]);
   }
+  // the small contractions of the tree: on matrix cores when the node is binary32
+  std::vector<const void*> opm(d, nullptr);
+  auto tree_ttm = [&](const Ten& cur, int k) -> Ten {
+    const int64_t Ab = cur.before(k), K = cur.dims[k], Bb = cur.after(k), m = s[k];
+    const bool mf = ct == RT_F32 && ttm_mfma_ok(RT_F32, Ab, K, Bb, m);
+    const bool last = ct == RT_F32 && !mf && Bb == 1 && ttm_mfma_last_ok(Ab, K, m);
+    if (!mf && !last) return ttm(c, cur, k, op[k], m);
+    if (!opm[k]) opm[k] = prep(c, phi ? phi[k] : nullptr, m, K, false, X.dt, RT_F32, ttm_mfma_mpad(m));
+    Ten o;
+    o.dims = cur.dims;
+    o.dims[k] = m;
+    o.dt = RT_F32;
+    o.p = c.take(static_cast<size_t>(Ab) * m * Bb * sizeof(float));
+    void* w = c.take(last ? ttm_mfma_last_ws(Ab, K, m) : ttm_mfma_ws(RT_F32, Ab, K, Bb, m));
+    c.flush();
+    if (!c.dry) {
+      float* y = static_cast<float*>(const_cast<void*>(o.p));
+      if (last)
+        c.chk(launch_ttm_mfma_last(static_cast<const float*>(cur.p), Ab, K, static_cast<const float*>(opm[k]), m, y,
+                                   w, c.st));
+      else
+        c.chk(launch_ttm_mfma_ws(cur.p, RT_F32, Ab, K, Bb, opm[k], m, y, w, c.st));
+    }
+    return o;
+  };
   out.assign(d, SketchOut{});
   for (int n = 0; n < d; ++n) {
     if (!(mask >> n & 1u)) continue;
-    Ten cur = (n == L) ? W : Z;
+    Ten cur = (n == S) ? Z : W;
     std::vector<int> chain;
-    if (n < S) chain.push_back(S);
+    if (n < S) chain.push_back(L);
     for (int k = 0; k < S; ++k)
       if (k != n) chain.push_back(k);
-    for (int k : chain) cur = ttm(c, cur, k, op[k], s[k]);
+    for (int k : chain) cur = tree_ttm(cur, k);
     SketchOut o;
     o.Y = cur;
     o.A = cur.before(n);

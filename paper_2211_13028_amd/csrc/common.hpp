@@ -116,6 +116,18 @@ inline size_t dtype_size(rt_dtype t) {
   return 0;
 }
 
+// 1/sqrt(x) for normal x > 0: hardware estimate refined by two Newton steps
+// (each roughly doubles the correct bits), accurate to a few units in the last place.
+__device__ __forceinline__ double rsq_refined(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(x * y, y, -1.0);  // x y^2 - 1
+    y = fma(-0.5 * y, e, y);
+  }
+  return y;
+}
+
 // index of the job owning flat workgroup `blk` in a grouped launch: the last job
 // whose first workgroup blk0 is <= blk (jobs sorted by blk0)
 template <typename T>

@@ -329,17 +329,6 @@ __device__ __forceinline__ void argmax64(double& v, int& idx) {
   idx = bi;
 }
 
-// 1/sqrt(x) for normal x > 0: hardware estimate refined by two Newton steps
-// (each roughly doubles the correct bits), accurate to a few units in the last place.
-__device__ __forceinline__ double rsq_refined(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-#pragma unroll
-  for (int it = 0; it < 2; ++it) {
-    const double e = fma(x * y, y, -1.0);  // x y^2 - 1
-    y = fma(-0.5 * y, e, y);
-  }
-  return y;
-}
 
 __device__ __forceinline__ void eig_body(const double* __restrict__ M, int n, int r, double* __restrict__ Vout,
                                          double* __restrict__ evals) {

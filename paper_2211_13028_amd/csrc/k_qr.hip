@@ -300,55 +300,71 @@ __device__ __forceinline__ double qr_dpp(double v) {
 __global__ __launch_bounds__(256) void cq_chol_kernel(CJobTable tab, int second) {
   __shared__ double G[kCols][kCols + 1];
   __shared__ double Rs[kCols][kCols + 1];
-  __shared__ int bad;
   const CJob& J = tab.t[blockIdx.x];
   if (*J.flag) return;  // cleared by cq_reset_kernel before the first pass
   const int n = J.n;
   const double* part = J.part + (second ? static_cast<int64_t>(J.chunks) * kCols * kCols : 0);
-  for (int idx = threadIdx.x; idx < kCols * kCols; idx += 256) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int c = 0;
-    for (; c + 4 <= J.chunks; c += 4) {
-      s0 += part[static_cast<int64_t>(c) * kCols * kCols + idx];
-      s1 += part[static_cast<int64_t>(c + 1) * kCols * kCols + idx];
-      s2 += part[static_cast<int64_t>(c + 2) * kCols * kCols + idx];
-      s3 += part[static_cast<int64_t>(c + 3) * kCols * kCols + idx];
+  {
+    // sum of the chunk partials in chunk order; each thread owns 16 entries and issues
+    // the loads of two chunks at once, so a few memory latencies cover the whole sum
+    constexpr int kPer = kCols * kCols / 256;
+    double acc[kPer];
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) acc[e] = 0.0;
+#pragma unroll 2
+    for (int c = 0; c < J.chunks; ++c) {
+      const double* pc = part + static_cast<int64_t>(c) * kCols * kCols + threadIdx.x;
+      double v[kPer];
+#pragma unroll
+      for (int e = 0; e < kPer; ++e) v[e] = pc[256 * e];
+#pragma unroll
+      for (int e = 0; e < kPer; ++e) acc[e] += v[e];
     }
-    for (; c < J.chunks; ++c) s0 += part[static_cast<int64_t>(c) * kCols * kCols + idx];
-    G[idx / kCols][idx % kCols] = (s0 + s1) + (s2 + s3);
-    Rs[idx / kCols][idx % kCols] = 0.0;
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      const int idx = threadIdx.x + 256 * e;
+      G[idx / kCols][idx % kCols] = acc[e];
+      Rs[idx / kCols][idx % kCols] = 0.0;
+    }
   }
-  if (threadIdx.x == 0) bad = 0;
   __syncthreads();
+  bool broke = false;
   double dmax = 0.0;
   for (int i = 0; i < n; ++i) dmax = fmax(dmax, G[i][i]);
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  // right-looking Cholesky, one barrier per step: row k of R goes to Rs, the
-  // trailing matrix is updated in place with G[k][.] / G[k][k]
+  // right-looking Cholesky, one barrier per step: row k of R = G[k][.] / sqrt(G[k][k])
+  // goes to Rs and the trailing matrix loses the outer product of that row.  Row k is
+  // only read in step k (the update touches rows and columns > k), so the barrier
+  // that ends step k is the only one needed.
   for (int k = 0; k < n; ++k) {
     const double d = G[k][k];
-    if (!(d > 1e-13 * dmax) || !(dmax > 0.0)) {
-      if (threadIdx.x == 0) bad = 1;
+    if (!(d > 1e-13 * dmax) || !(dmax > 0.0)) {  // every thread sees the same d: uniform exit
+      broke = true;
       break;
     }
-    const double inv_d = 1.0 / d;
-    const double rkk = sqrt(d);
+    const double inv_s = rsq_refined(d);
     if (static_cast<int>(threadIdx.x) >= k && static_cast<int>(threadIdx.x) < n)
-      Rs[k][threadIdx.x] = G[k][threadIdx.x] / rkk;
-    double gki[4], gkj[4];
+      Rs[k][threadIdx.x] = G[k][threadIdx.x] * inv_s;
+    double li[4], lj[4], g[4][4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) { gki[u] = G[k][ty * 4 + u]; gkj[u] = G[k][tx * 4 + u] * inv_d; }
-    __syncthreads();  // everyone has read row k before it (and the rest) is updated
+    for (int u = 0; u < 4; ++u) {
+      li[u] = G[k][ty * 4 + u] * inv_s;
+      lj[u] = G[k][tx * 4 + u] * inv_s;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) g[u][v] = G[ty * 4 + u][tx * 4 + v];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = ty * 4 + u, j = tx * 4 + v;
-        if (i > k && j > k) G[i][j] = fma(-gki[u], gkj[v], G[i][j]);
+        if (i > k && j > k) G[i][j] = fma(-li[u], lj[v], g[u][v]);
       }
     __syncthreads();
   }
-  if (bad) {
+  if (broke) {
     if (threadIdx.x == 0) *J.flag = 1;
     return;
   }
@@ -358,10 +374,13 @@ __global__ __launch_bounds__(256) void cq_chol_kernel(CJobTable tab, int second)
     R[idx] = (i < n && j < n && j >= i) ? Rs[i][j] : 0.0;
   }
   if (second && J.Rout) {
+    // R = R2 R1 with R1 staged in LDS (the Gram array is free now)
+    for (int idx = threadIdx.x; idx < n * kCols; idx += 256) G[idx / kCols][idx % kCols] = J.R1[idx];
+    __syncthreads();
     for (int idx = threadIdx.x; idx < n * n; idx += 256) {
       const int i = idx / n, j = idx % n;
       double s = 0.0;
-      for (int t = i; t <= j; ++t) s = fma(Rs[i][t], J.R1[t * kCols + j], s);
+      for (int t = i; t <= j; ++t) s = fma(Rs[i][t], G[t][j], s);
       J.Rout[idx] = (j >= i) ? s : 0.0;
     }
   }
