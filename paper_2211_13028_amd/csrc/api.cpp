@@ -173,9 +173,10 @@ void sketch_impl(Ctx& c, const Ten& X, const double* const* phi, const int64_t* 
     void* zws = plan.ws_bytes ? c.take(plan.ws_bytes) : nullptr;
     const void* p16 = nullptr;
     const void* q16 = nullptr;
-    if (plan.mfma) {  // factors rounded to X's dtype, bfloat16 storage, padded to 16 rows
-      if (needW) p16 = prep(c, phi ? phi[S] : nullptr, s[S], P, false, X.dt, RT_BF16, 16);
-      if (needZ) q16 = prep(c, phi ? phi[L] : nullptr, s[L], Q, false, X.dt, RT_BF16, 16);
+    if (plan.mfma) {  // factors rounded to X's dtype (bfloat16 storage unless binary32), padded to 16 rows
+      const rt_dtype st16 = (X.dt == RT_F32) ? RT_F32 : RT_BF16;
+      if (needW) p16 = prep(c, phi ? phi[S] : nullptr, s[S], P, false, X.dt, st16, 16);
+      if (needZ) q16 = prep(c, phi ? phi[L] : nullptr, s[L], Q, false, X.dt, st16, 16);
     }
     c.flush();
     if (!c.dry)
@@ -480,8 +481,9 @@ int plan_sketch_pass(Ctx& c, const rt_tensor* X, const double* phiS, int64_t sS,
     const void* p16 = nullptr;
     const void* q16 = nullptr;
     if (plan.mfma) {
-      if (wantW) p16 = prep(c, phiS, sS, P, false, X->dtype, RT_BF16, 16);
-      if (wantZ) q16 = prep(c, phiL, sL, Q, false, X->dtype, RT_BF16, 16);
+      const rt_dtype st16 = (X->dtype == RT_F32) ? RT_F32 : RT_BF16;
+      if (wantW) p16 = prep(c, phiS, sS, P, false, X->dtype, st16, 16);
+      if (wantZ) q16 = prep(c, phiL, sL, Q, false, X->dtype, st16, 16);
     }
     c.flush();
     if (!c.dry)

@@ -116,6 +116,12 @@ inline size_t dtype_size(rt_dtype t) {
   return 0;
 }
 
+// Workgroup barrier ordering LDS only: it waits for this wave's LDS operations but
+// not for its outstanding global loads, so prefetches stay in flight across it
+// (__syncthreads also drains every global access of the wave).  Use only where
+// the waves exchange data through LDS alone.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // 1/sqrt(x) for normal x > 0: hardware estimate refined by two Newton steps
 // (each roughly doubles the correct bits), accurate to a few units in the last place.
 __device__ __forceinline__ double rsq_refined(double x) {

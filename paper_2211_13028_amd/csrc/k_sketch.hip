@@ -348,7 +348,7 @@ __global__ __launch_bounds__(kZWThreads) __attribute__((amdgpu_waves_per_eu(3)))
       for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
         for (int v = 0; v < 4; ++v) zp[(16 * mt + 4 * kg + v) * 16 + li] = zacc[mt][v];
-      __syncthreads();
+      lds_barrier();  // the next rows' loads stay in flight
       // wave w finishes rows 8 w .. 8 w + 7 of the step: lane -> (row, c < 8)
       const int row = 8 * wave + lane / 8, c = lane % 8;
       const int64_t p = pb + row;
@@ -369,6 +369,128 @@ __global__ __launch_bounds__(kZWThreads) __attribute__((amdgpu_waves_per_eu(3)))
     float* dst = wout + static_cast<int64_t>(cp) * Q + qc;
     *reinterpret_cast<f32x4*>(dst) = f32x4{wacc[0][v], wacc[1][v], wacc[2][v], wacc[3][v]};
     *reinterpret_cast<f32x4*>(dst + 4) = f32x4{wacc[4][v], wacc[5][v], wacc[6][v], wacc[7][v]};
+  }
+}
+
+// ------------------------------------------------------------------ binary32 on matrix cores
+// The same pass for binary32 X with v_mfma_f32_16x16x4f32.  Wave w owns 128
+// columns; all waves step through 16 rows at a time.  Lane (li, kg) loads row
+// 4t + kg of each row quad t as two 16-byte groups (columns 4 li.. and 64 + 4 li..):
+//  * W^T: A = PhiP[c][p] (one value per lane), B = the loaded groups, component c
+//    giving columns 4 n + c, so four MFMAs cover 64 columns per row quad;
+//  * Z: the 16 x 128 tile is staged row-major in the wave's LDS area and read back
+//    with lane (row li, 4 consecutive columns at 4 kg) as A; PhiQ (read from the
+//    caches) is B.  Partial Z rows are added across the waves in LDS (fixed order).
+// Requires Q % 4 == 0; P, A arbitrary; s <= 16.
+constexpr int kF32Stride = 132;  // floats per staged row: 128 + 4 padding
+
+__global__ __launch_bounds__(kZWThreads) __attribute__((amdgpu_waves_per_eu(3))) void sketch_zw_f32_mfma_kernel(
+    const float* __restrict__ X, int64_t A, int64_t P, int64_t Q, const float* __restrict__ phiP, int sP,
+    const float* __restrict__ phiQ, int sQ, int64_t rows_per_block, int qblocks, int pblocks,
+    float* __restrict__ Zo, float* __restrict__ Wo) {
+  __shared__ float tile[kZWWaves][16 * kF32Stride];
+  __shared__ float zpart[2][kZWWaves][16 * 16];
+  const int lane = threadIdx.x % kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int64_t blk = blockIdx.x;
+  const int qblk = static_cast<int>(blk % qblocks);
+  const int64_t rest = blk / qblocks;
+  const int pblk = static_cast<int>(rest % pblocks);
+  const int64_t a = rest / pblocks;
+  const int64_t q0 = static_cast<int64_t>(qblk) * kZWColsMfma;
+  const int64_t qend = (q0 + kZWColsMfma < Q) ? q0 + kZWColsMfma : Q;
+  const int64_t qw = q0 + 128 * wave;
+  const bool needZ = Zo != nullptr, needW = Wo != nullptr;
+  const int li = lane % 16, kg = lane / 16;
+  const int64_t pbeg = static_cast<int64_t>(pblk) * rows_per_block;
+  const int64_t pend = (pbeg + rows_per_block < P) ? pbeg + rows_per_block : P;
+  const float* xa = X + a * P * Q;
+  float* my = tile[wave];
+  const int64_t qc[2] = {qw + 4 * li, qw + 64 + 4 * li};
+  const bool ok[2] = {qc[0] < qend, qc[1] < qend};
+
+  f32x4 wacc[2][4];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) wacc[j][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  auto load_step = [&](int64_t pb, f32x4 (&r)[4][2]) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t p = pb + 4 * t + kg;
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        r[t][j] = (ok[j] && p < pend) ? *reinterpret_cast<const f32x4*>(xa + p * Q + qc[j]) : f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  f32x4 rn[4][2];
+  load_step(pbeg, rn);
+  int buf = 0;
+  for (int64_t pb = pbeg; pb < pend; pb += 16) {
+    f32x4 r[4][2];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) r[t][j] = rn[t][j];
+    if (pb + 16 < pend) load_step(pb + 16, rn);
+    if (needW) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t p = pb + 4 * t + kg;
+        const float pp = (p < pend) ? phiP[static_cast<int64_t>(li) * P + p] : 0.f;
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            wacc[j][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(pp, r[t][j][c], wacc[j][c], 0, 0, 0);
+      }
+    }
+    if (needZ) {
+      __builtin_amdgcn_wave_barrier();  // the previous step's reads of the staging area stay above
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) *reinterpret_cast<f32x4*>(my + (4 * t + kg) * kF32Stride + 64 * j + 4 * li) = r[t][j];
+      __builtin_amdgcn_wave_barrier();  // cross-lane: stores before the reads below
+      f32x4 zacc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kb = 0; kb < 8; ++kb) {
+        // PhiQ[li][qw + 16 kb + 4 kg .. + 3]: a small operand re-read from the caches each step
+        // (holding it in registers would cost the occupancy)
+        const int64_t qk = qw + 16 * kb + 4 * kg;
+        const f32x4 bq = (qk < qend) ? *reinterpret_cast<const f32x4*>(phiQ + static_cast<int64_t>(li) * Q + qk)
+                                     : f32x4{0.f, 0.f, 0.f, 0.f};
+        const f32x4 xr = *reinterpret_cast<const f32x4*>(my + li * kF32Stride + 16 * kb + 4 * kg);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) zacc = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[c], bq[c], zacc, 0, 0, 0);
+      }
+      float* zp = zpart[buf][wave];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) zp[(4 * kg + v) * 16 + li] = zacc[v];
+      lds_barrier();  // the next rows' loads stay in flight
+      // wave w finishes rows 4 w .. 4 w + 3 of the step: lane -> (row, c)
+      const int row = 4 * wave + lane / 16, c = lane % 16;
+      const int64_t p = pb + row;
+      float z = zpart[buf][0][row * 16 + c];
+#pragma unroll
+      for (int w = 1; w < kZWWaves; ++w) z += zpart[buf][w][row * 16 + c];
+      if (c < sQ && p < pend) Zo[((static_cast<int64_t>(qblk) * A + a) * P + p) * sQ + c] = z;
+      buf ^= 1;
+    }
+  }
+  if (!needW) return;
+  float* wout = Wo + (static_cast<int64_t>(pblk) * A + a) * sP * Q;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    if (!ok[j]) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int cp = 4 * kg + v;
+      if (cp < sP)
+        *reinterpret_cast<f32x4*>(wout + static_cast<int64_t>(cp) * Q + qc[j]) =
+            f32x4{wacc[j][0][v], wacc[j][1][v], wacc[j][2][v], wacc[j][3][v]};
+    }
   }
 }
 
@@ -418,7 +540,9 @@ bool sketch_zw_ok(rt_dtype, int64_t sP, int64_t sQ) { return sP >= 1 && sQ >= 1 
 ZWPlan sketch_zw_plan(rt_dtype xdt, int64_t A, int64_t P, int64_t Q, int64_t sP, int64_t sQ, bool needZ,
                       bool needW) {
   ZWPlan p;
-  p.mfma = (xdt == RT_BF16 || xdt == RT_F8E4M3) && (P % 8 == 0) && (Q % 8 == 0) && P >= 32;
+  const bool mf16 = (xdt == RT_BF16 || xdt == RT_F8E4M3) && (P % 8 == 0) && (Q % 8 == 0) && P >= 32;
+  const bool mf32 = (xdt == RT_F32) && (Q % 4 == 0) && P >= 16;
+  p.mfma = mf16 || mf32;
   const int nq = pick_nq(xdt, Q);
   p.qblocks = p.mfma ? ceil_div(Q, kZWColsMfma) : ceil_div(Q, 64 * nq);
   if (p.mfma) {
@@ -428,11 +552,12 @@ ZWPlan sketch_zw_plan(rt_dtype xdt, int64_t A, int64_t P, int64_t Q, int64_t sP,
     // with the W partials (written and re-read, binary32) converted at the
     // 1 KiB of X that one row of 512 bfloat16 columns is.
     const int64_t resident = 768;
-    const double row_bytes = static_cast<double>(resident) * kZWColsMfma * 2;
+    const int64_t step = mf32 ? 16 : 32;  // rows per step of the kernel
+    const double row_bytes = static_cast<double>(resident) * kZWColsMfma * (mf32 ? 4 : 2);
     double best = 0.0;
     int64_t best_rows = 0;
     for (int64_t pb = 1; pb <= 64; ++pb) {
-      const int64_t rows = ceil_div(ceil_div(P, pb), 32) * 32;
+      const int64_t rows = ceil_div(ceil_div(P, pb), step) * step;
       const int64_t pbs = ceil_div(P, rows);
       if (pbs != pb || (pb > 1 && rows < 128)) continue;
       const int64_t wgs = A * p.qblocks * pb;
@@ -443,7 +568,7 @@ ZWPlan sketch_zw_plan(rt_dtype xdt, int64_t A, int64_t P, int64_t Q, int64_t sP,
         best_rows = rows;
       }
     }
-    p.rows_per_block = best_rows ? best_rows : ceil_div(P, 32) * 32;
+    p.rows_per_block = best_rows ? best_rows : ceil_div(P, step) * step;
   } else {
     int64_t pb = 1;
     const int64_t target = 2048;
@@ -482,7 +607,12 @@ hipError_t launch_sketch_zw(const void* X, rt_dtype xdt, int64_t A, int64_t P, i
   const int isP = static_cast<int>(sP), isQ = static_cast<int>(sQ);
   if (plan.mfma) {
     const int64_t blocks = A * plan.pblocks * plan.qblocks;
-    if (xdt == RT_F8E4M3)
+    if (xdt == RT_F32)
+      sketch_zw_f32_mfma_kernel<<<static_cast<unsigned>(blocks), kZWThreads, 0, st>>>(
+          static_cast<const float*>(X), A, P, Q, static_cast<const float*>(phiP16), isP,
+          static_cast<const float*>(phiQ16), isQ, plan.rows_per_block, static_cast<int>(plan.qblocks),
+          static_cast<int>(plan.pblocks), static_cast<float*>(zdst), static_cast<float*>(wdst));
+    else if (xdt == RT_F8E4M3)
       sketch_zw_bf16_mfma_kernel<f8_t><<<static_cast<unsigned>(blocks), kZWThreads, 0, st>>>(
           static_cast<const f8_t*>(X), A, P, Q, static_cast<const bf16_t*>(phiP16), isP,
           static_cast<const bf16_t*>(phiQ16), isQ, plan.rows_per_block, static_cast<int>(plan.qblocks),
