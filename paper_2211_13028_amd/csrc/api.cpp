@@ -798,7 +798,9 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
   std::vector<PrepTask> prep_sk, prep_core;
   std::vector<GZwJob> zw;
   std::vector<GTtmJob> tree, core[3], gttm[3], uttm[3];
-  std::vector<GQrJob> qr;
+  std::vector<GQrJob> qr_hh, qr_fb;
+  std::vector<GCholQRJob> qr_cq;
+  int max_chunks = 1;
   std::vector<GCopyJob> cp;
   std::vector<GGramJob> gram[3];
   std::vector<GEigJob> eig[3];
@@ -806,7 +808,8 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
   // the table region comes first; its size is fixed by the job counts
   const size_t n_jobs_bytes =
       align256(sizeof(PrepTask) * 3 * count) * 2 + align256(sizeof(GZwJob) * count) +
-      align256(sizeof(GTtmJob) * 3 * count) + align256(sizeof(GQrJob) * 3 * count) +
+      align256(sizeof(GTtmJob) * 3 * count) + 2 * align256(sizeof(GQrJob) * 3 * count) +
+      align256(sizeof(GCholQRJob) * 3 * count) +
       3 * align256(sizeof(GTtmJob) * count) + align256(sizeof(GCopyJob) * count) +
       3 * (align256(sizeof(GGramJob) * count) + align256(sizeof(GEigJob) * count) +
            2 * align256(sizeof(GTtmJob) * count)) + 4096;
@@ -850,8 +853,24 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
     const int64_t YB[3] = {t.s[1] * t.s[2], t.s[2], 1};
     for (int n = 0; n < d; ++n) {
       Uh[n] = static_cast<double*>(c.take(static_cast<size_t>(t.I[n]) * t.c[n] * 8));
-      qr.push_back(GQrJob{Ys[n], YA[n], t.I[n], YB[n], Uh[n], static_cast<int32_t>(YA[n] * YB[n]),
-                          static_cast<int32_t>(t.c[n])});
+      const int64_t ncol = YA[n] * YB[n];
+      if (t.I[n] >= ncol) {
+        // CholeskyQR2 (tall sketch), with the Householder kernel as its fallback
+        const int64_t chunks = ceil_div(t.I[n], 64);
+        double* part = static_cast<double*>(c.take(static_cast<size_t>(2 * chunks) * 64 * 64 * 8));
+        double* R1 = static_cast<double*>(c.take(64 * 64 * 8));
+        double* R2 = static_cast<double*>(c.take(64 * 64 * 8));
+        double* Q1 = static_cast<double*>(c.take(static_cast<size_t>(t.I[n]) * ncol * 8));
+        int32_t* flag = static_cast<int32_t*>(c.take(sizeof(int32_t)));
+        qr_cq.push_back(GCholQRJob{Ys[n], YA[n], t.I[n], YB[n], static_cast<int32_t>(ncol), part,
+                                   static_cast<int32_t>(chunks), R1, R2, Q1, Uh[n], nullptr, flag});
+        qr_fb.push_back(GQrJob{Ys[n], YA[n], t.I[n], YB[n], Uh[n], static_cast<int32_t>(ncol),
+                               static_cast<int32_t>(t.c[n]), flag});
+        max_chunks = std::max<int>(max_chunks, static_cast<int>(chunks));
+      } else {
+        qr_hh.push_back(GQrJob{Ys[n], YA[n], t.I[n], YB[n], Uh[n], static_cast<int32_t>(ncol),
+                               static_cast<int32_t>(t.c[n]), nullptr});
+      }
     }
     // core: G_hat = X x_k U_hat_k^T, largest mode first; operands rounded to the input dtype of each step
     int64_t dims[3] = {I0, I1, I2};
@@ -903,8 +922,8 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
   }
   // ---- tables
   TableBuf tb;
-  const size_t o_psk = tb.add(prep_sk), o_zw = tb.add(zw), o_tree = tb.add(tree), o_qr = tb.add(qr),
-               o_pcore = tb.add(prep_core);
+  const size_t o_psk = tb.add(prep_sk), o_zw = tb.add(zw), o_tree = tb.add(tree), o_cq = tb.add(qr_cq),
+               o_hh = tb.add(qr_hh), o_fb = tb.add(qr_fb), o_pcore = tb.add(prep_core);
   size_t o_core[3], o_gram[3], o_eig[3], o_g[3], o_u[3];
   for (int q = 0; q < 3; ++q) o_core[q] = tb.add(core[q]);
   const size_t o_cp = tb.add(cp);
@@ -927,7 +946,10 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
   c.chk(launch_sketch_zw_grouped(reinterpret_cast<const GZwJob*>(at(o_zw)), count, zw_blocks, dtype, st));
   c.chk(launch_ttm_grouped(reinterpret_cast<const GTtmJob*>(at(o_tree)), static_cast<int>(tree.size()), tree_blocks,
                            RT_F32, 8, st));
-  c.chk(launch_qr_grouped(reinterpret_cast<const GQrJob*>(at(o_qr)), static_cast<int>(qr.size()), RT_F32, st));
+  c.chk(launch_cholqr2_grouped(reinterpret_cast<const GCholQRJob*>(at(o_cq)), static_cast<int>(qr_cq.size()),
+                               max_chunks, RT_F32, st));
+  c.chk(launch_qr_grouped(reinterpret_cast<const GQrJob*>(at(o_hh)), static_cast<int>(qr_hh.size()), RT_F32, st));
+  c.chk(launch_qr_grouped(reinterpret_cast<const GQrJob*>(at(o_fb)), static_cast<int>(qr_fb.size()), RT_F32, st));
   c.chk(launch_prep_grouped(reinterpret_cast<const PrepTask*>(at(o_pcore)), static_cast<int>(prep_core.size()),
                             max_prep_core, st));
   for (int q = 0; q < 3; ++q)

@@ -183,6 +183,7 @@ __global__ __launch_bounds__(kQRThreads) void small_qr_kernel(QRTaskTable tab) {
 template <typename TY>
 __global__ __launch_bounds__(kQRThreads) void small_qr_grouped_kernel(const GQrJob* __restrict__ jobs) {
   const GQrJob J = jobs[blockIdx.x];
+  if (J.flag && *J.flag == 0) return;
   QRTask T;
   T.src = J.Y;
   T.A = J.A;
@@ -234,21 +235,19 @@ __global__ __launch_bounds__(256) void qr_combine_kernel(CombineTable tab) {
 // the job, and the Householder path (launched conditionally) recomputes it.
 constexpr int kGramRows = 64;
 
-struct CJob {
-  const void* Y;      // source (A, m, B) view
-  int64_t A, m, B;
-  int32_t n;
-  double* part;       // 2 x chunks x 64 x 64 partial Gram matrices (one set per pass)
-  int32_t chunks;
-  double* R1;         // 64 x 64 upper factor of the first pass
-  double* R2;         // second pass
-  double* Q1;         // m x n intermediate (binary64)
-  double* Q;          // final m x n (ld n)
-  double* Rout;       // n x n or null
-  int32_t* flag;      // 0 = CholeskyQR2 ok, 1 = use Householder
-};
+using CJob = GCholQRJob;
 struct CJobTable {
   CJob t[kMaxQRJobs];
+};
+// job access for the by-value table of a single decomposition and for a job
+// array in device memory (batched decomposition)
+struct CTabVal {
+  CJobTable v;
+  __device__ const CJob& operator[](int i) const { return v.t[i]; }
+};
+struct CTabPtr {
+  const CJob* p;
+  __device__ const CJob& operator[](int i) const { return p[i]; }
 };
 
 template <typename TY>
@@ -258,10 +257,10 @@ __device__ __forceinline__ double cq_src(const CJob& J, int64_t r, int j) {
 }
 
 // partial Gram of one 64-row chunk of Y (first pass)
-template <typename TY>
-__global__ __launch_bounds__(256) void cq_gram_kernel(CJobTable tab) {
+template <typename TY, typename TAB>
+__global__ __launch_bounds__(256) void cq_gram_kernel(TAB tab) {
   __shared__ double sy[kGramRows][kCols + 1];
-  const CJob& J = tab.t[blockIdx.y];
+  const CJob& J = tab[blockIdx.y];
   if (static_cast<int>(blockIdx.x) >= J.chunks) return;
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kGramRows;
   for (int idx = threadIdx.x; idx < kGramRows * kCols; idx += 256) {
@@ -297,10 +296,11 @@ __device__ __forceinline__ double qr_dpp(double v) {
 }
 
 // sum the partials (fixed order), factor G = R^T R (upper R) and invert R
-__global__ __launch_bounds__(256) void cq_chol_kernel(CJobTable tab, int second) {
+template <typename TAB>
+__global__ __launch_bounds__(256) void cq_chol_kernel(TAB tab, int second) {
   __shared__ double G[kCols][kCols + 1];
   __shared__ double Rs[kCols][kCols + 1];
-  const CJob& J = tab.t[blockIdx.x];
+  const CJob& J = tab[blockIdx.x];
   if (*J.flag) return;  // cleared by cq_reset_kernel before the first pass
   const int n = J.n;
   const double* part = J.part + (second ? static_cast<int64_t>(J.chunks) * kCols * kCols : 0);
@@ -389,12 +389,12 @@ __global__ __launch_bounds__(256) void cq_chol_kernel(CJobTable tab, int second)
 // 64 rows of Q = Y R^-1 per workgroup by forward substitution q R = y, four lanes
 // per row sharing each dot product (quad DPP sums); the first pass also stores Q1
 // and the partial Gram of its rows
-template <typename TY>
-__global__ __launch_bounds__(256) void cq_apply_kernel(CJobTable tab, int second) {
+template <typename TY, typename TAB>
+__global__ __launch_bounds__(256) void cq_apply_kernel(TAB tab, int second) {
   __shared__ double sy[kGramRows][kCols + 1];
   __shared__ double sr[kCols][kCols + 1];
   __shared__ double rinv[kCols];
-  const CJob& J = tab.t[blockIdx.y];
+  const CJob& J = tab[blockIdx.y];
   if (static_cast<int>(blockIdx.x) >= J.chunks) return;
   if (*J.flag) return;
   const int n = J.n;
@@ -454,8 +454,10 @@ __global__ __launch_bounds__(256) void cq_apply_kernel(CJobTable tab, int second
     for (int v = 0; v < 4; ++v) gp[(ty * 4 + u) * kCols + tx * 4 + v] = g[u][v];
 }
 
-__global__ void cq_reset_kernel(CJobTable tab, int count) {
-  if (static_cast<int>(threadIdx.x) < count) *tab.t[threadIdx.x].flag = 0;
+template <typename TAB>
+__global__ void cq_reset_kernel(TAB tab, int count) {
+  const int i = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i < count) *tab[i].flag = 0;
 }
 
 // One matrix of the (recursive) TSQR plan.
@@ -621,18 +623,19 @@ hipError_t qr_plan(const QRJob* jobs, int count, rt_dtype ydt, bool launch, Bump
   if (launch && nc > 0) {
     const dim3 g1(max_chunks, nc);
     (void)max_m;
-    cq_reset_kernel<<<1, 64, 0, st>>>(tab, nc);
+    const CTabVal tv{tab};
+    cq_reset_kernel<<<1, 64, 0, st>>>(tv, nc);
     if (ydt == RT_F64) {
-      cq_gram_kernel<double><<<g1, 256, 0, st>>>(tab);
-      cq_chol_kernel<<<nc, 256, 0, st>>>(tab, 0);
-      cq_apply_kernel<double><<<g1, 256, 0, st>>>(tab, 0);
+      cq_gram_kernel<double><<<g1, 256, 0, st>>>(tv);
+      cq_chol_kernel<<<nc, 256, 0, st>>>(tv, 0);
+      cq_apply_kernel<double><<<g1, 256, 0, st>>>(tv, 0);
     } else {
-      cq_gram_kernel<float><<<g1, 256, 0, st>>>(tab);
-      cq_chol_kernel<<<nc, 256, 0, st>>>(tab, 0);
-      cq_apply_kernel<float><<<g1, 256, 0, st>>>(tab, 0);
+      cq_gram_kernel<float><<<g1, 256, 0, st>>>(tv);
+      cq_chol_kernel<<<nc, 256, 0, st>>>(tv, 0);
+      cq_apply_kernel<float><<<g1, 256, 0, st>>>(tv, 0);
     }
-    cq_chol_kernel<<<nc, 256, 0, st>>>(tab, 1);
-    cq_apply_kernel<double><<<g1, 256, 0, st>>>(tab, 1);
+    cq_chol_kernel<<<nc, 256, 0, st>>>(tv, 1);
+    cq_apply_kernel<double><<<g1, 256, 0, st>>>(tv, 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -658,6 +661,25 @@ hipError_t launch_qr_grouped(const GQrJob* jobs, int count, rt_dtype ydt, hipStr
     small_qr_grouped_kernel<double><<<static_cast<unsigned>(count), kQRThreads, 0, st>>>(jobs);
   else
     small_qr_grouped_kernel<float><<<static_cast<unsigned>(count), kQRThreads, 0, st>>>(jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_cholqr2_grouped(const GCholQRJob* jobs, int count, int max_chunks, rt_dtype ydt, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  const CTabPtr tp{jobs};
+  const dim3 g1(static_cast<unsigned>(max_chunks), static_cast<unsigned>(count));
+  cq_reset_kernel<<<static_cast<unsigned>(ceil_div(count, 256)), 256, 0, st>>>(tp, count);
+  if (ydt == RT_F64) {
+    cq_gram_kernel<double><<<g1, 256, 0, st>>>(tp);
+    cq_chol_kernel<<<count, 256, 0, st>>>(tp, 0);
+    cq_apply_kernel<double><<<g1, 256, 0, st>>>(tp, 0);
+  } else {
+    cq_gram_kernel<float><<<g1, 256, 0, st>>>(tp);
+    cq_chol_kernel<<<count, 256, 0, st>>>(tp, 0);
+    cq_apply_kernel<float><<<g1, 256, 0, st>>>(tp, 0);
+  }
+  cq_chol_kernel<<<count, 256, 0, st>>>(tp, 1);
+  cq_apply_kernel<double><<<g1, 256, 0, st>>>(tp, 1);
   return hipGetLastError();
 }
 

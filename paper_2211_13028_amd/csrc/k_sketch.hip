@@ -494,6 +494,106 @@ __global__ __launch_bounds__(kZWThreads) __attribute__((amdgpu_waves_per_eu(3)))
   }
 }
 
+// grouped form on matrix cores: one wave per slab X[a] of a job, all rows and all
+// Q <= 256 columns (arbitrary P and Q, element loads with bounds), binary32 MFMA
+// (bfloat16 data is widened exactly; its products are exact in binary32).  Per
+// 16-row step, lane (li, kg) holds row 4 t + kg of each row quad t, columns
+// 64 cb + 4 li .. + 3 of each 64-column block cb: W^T accumulates with four MFMAs per
+// (quad, block); the rows are staged in LDS and read back as the A operand of Z.
+constexpr int kGStride = 260;  // floats per staged row: 256 + 4 padding
+
+template <typename TX>
+__global__ __launch_bounds__(kWave) void sketch_zw_grouped_mfma_kernel(const GZwJob* __restrict__ jobs, int count) {
+  __shared__ float tile[16 * kGStride];
+  const int64_t blk = blockIdx.x;
+  const GZwJob J = jobs[find_job(jobs, count, blk)];
+  const int64_t a = blk - J.blk0;
+  const int64_t P = J.P, Q = J.Q;
+  const int sP = J.sP, sQ = J.sQ;
+  const int lane = threadIdx.x;
+  const int li = lane % 16, kg = lane / 16;
+  const bool needZ = J.Z != nullptr, needW = J.W != nullptr;
+  const TX* xa = static_cast<const TX*>(J.X) + a * P * Q;
+  const int ncb = static_cast<int>((Q + 63) / 64);  // 64-column blocks in use (<= 4)
+  f32x4 wacc[4][4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) wacc[cb][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float* zout = needZ ? J.Z + a * P * sQ : nullptr;
+  for (int64_t pb = 0; pb < P; pb += 16) {
+    f32x4 r[4][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t p = pb + 4 * t + kg;
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int64_t q = 64 * cb + 4 * li + c;
+          r[t][cb][c] = (cb < ncb && p < P && q < Q) ? static_cast<float>(Load<TX>::get(xa, p * Q + q)) : 0.f;
+        }
+    }
+    if (needW) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t p = pb + 4 * t + kg;
+        const float pp = (p < P && li < sP) ? J.phiP[static_cast<int64_t>(li) * P + p] : 0.f;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+          if (cb < ncb) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+              wacc[cb][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(pp, r[t][cb][c], wacc[cb][c], 0, 0, 0);
+          }
+      }
+    }
+    if (needZ) {
+      __builtin_amdgcn_wave_barrier();  // the previous step's reads of the staging area stay above
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+          if (cb < ncb) *reinterpret_cast<f32x4*>(tile + (4 * t + kg) * kGStride + 64 * cb + 4 * li) = r[t][cb];
+      __builtin_amdgcn_wave_barrier();  // cross-lane: stores before the reads below
+      f32x4 zacc = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int kb = 0; kb < 4 * ncb; ++kb) {
+        const f32x4 xr = *reinterpret_cast<const f32x4*>(tile + li * kGStride + 16 * kb + 4 * kg);
+        f32x4 bq;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int64_t q = 16 * kb + 4 * kg + c;
+          bq[c] = (q < Q && li < sQ) ? J.phiQ[static_cast<int64_t>(li) * Q + q] : 0.f;
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) zacc = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[c], bq[c], zacc, 0, 0, 0);
+      }
+      // D layout: row 4 kg + v of the step, column c = li
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t p = pb + 4 * kg + v;
+        if (p < P && li < sQ) zout[p * sQ + li] = zacc[v];
+      }
+    }
+  }
+  if (!needW) return;
+  float* wout = J.W + a * sP * Q;
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    if (cb >= ncb) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int cp = 4 * kg + v;
+      if (cp >= sP) continue;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int64_t q = 64 * cb + 4 * li + c;
+        if (q < Q) wout[static_cast<int64_t>(cp) * Q + q] = wacc[cb][c][v];
+      }
+    }
+  }
+}
+
 int nq_max(rt_dtype xdt) { return xdt == RT_F64 ? 4 : 8; }
 
 int pick_nq(rt_dtype xdt, int64_t Q) {
@@ -676,9 +776,9 @@ hipError_t launch_sketch_zw_grouped(const GZwJob* jobs, int count, int64_t total
   if (count == 0 || total_blocks == 0) return hipSuccess;
   const unsigned g = static_cast<unsigned>(total_blocks);
   if (xdt == RT_F32)
-    sketch_zw_grouped_kernel<float><<<g, kZWThreads, 0, st>>>(jobs, count);
+    sketch_zw_grouped_mfma_kernel<float><<<g, kWave, 0, st>>>(jobs, count);
   else if (xdt == RT_BF16)
-    sketch_zw_grouped_kernel<bf16_t><<<g, kZWThreads, 0, st>>>(jobs, count);
+    sketch_zw_grouped_mfma_kernel<bf16_t><<<g, kWave, 0, st>>>(jobs, count);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -191,13 +191,34 @@ hipError_t launch_sketch_zw_grouped(const GZwJob* jobs, int count, int64_t total
 
 // k_qr.hip: thin Householder QR of (A, m, B) views with m <= 256 rows and
 // n = A*B <= 64 columns, one workgroup per job; Q: m x qcols (qcols = min(m, n)).
+// With flag set, a job runs only when *flag != 0 (the Householder fallback of CholeskyQR2).
 struct GQrJob {
   const void* Y;
   int64_t A, m, B;
   double* Q;
   int32_t n, qcols;
+  const int32_t* flag;
 };
 hipError_t launch_qr_grouped(const GQrJob* jobs, int count, rt_dtype ydt, hipStream_t st);
+// CholeskyQR2 of (A, m, B) views with m >= n = A*B <= 64 (the single-decomposition
+// path's fast QR), many jobs per launch.  Per job: part = 2 x chunks x 64 x 64
+// binary64 (chunks = ceil(m / 64)), R1, R2: 64 x 64, Q1: m x n, Q: m x n (ld n),
+// Rout (may be null): n x n, flag: set to 1 when a Cholesky pivot breaks down (the
+// job must then be redone by the Householder kernel).
+struct GCholQRJob {
+  const void* Y;
+  int64_t A, m, B;
+  int32_t n;
+  double* part;
+  int32_t chunks;
+  double* R1;
+  double* R2;
+  double* Q1;
+  double* Q;
+  double* Rout;
+  int32_t* flag;
+};
+hipError_t launch_cholqr2_grouped(const GCholQRJob* jobs, int count, int max_chunks, rt_dtype ydt, hipStream_t st);
 
 // k_eig.hip: Gram matrices out = G_(n) G_(n)^T of binary64 (A, m, B) views
 // (m <= 64), and the eigensolver of launch_sym_eig_top, one workgroup per job.

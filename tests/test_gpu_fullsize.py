@@ -98,3 +98,31 @@ def test_fullsize_decompose_error(work, path):
     for U in Us:
         Uh = host(U)
         np.testing.assert_allclose(Uh.T @ Uh, np.eye(32), atol=1e-12)
+
+
+def test_fullsize_rsthkron_128_4way():
+    """128^4 FP32 tensor with a decaying 16^4 core, rSTHKron with every subrank 3, r = 16,
+    p = 6, in the launch configuration the benchmark times: error against the FP64 oracle,
+    and BF16 against the binary32 result (rSTHKron has no emulated oracle; BF16 only has to
+    stay within its rounding floor)."""
+    dims4, r4 = (128, 128, 128, 128), [16, 16, 16, 16]
+    say("full size: generating the 128^4 tensor")
+    core = synth.tucker_core_decay((16, 16, 16, 16), 6.0, seed=synth.DATA_SEED)
+    Xh, _, _ = synth.random_tucker(dims4, (16, 16, 16, 16), 1e-3, seed=synth.DATA_SEED, core=core)
+    Xh = Xh.astype(np.float32)
+    S = [[1 if k == j else 3 for k in range(4)] for j in range(4)]
+    shapes = T.sth_phi_shapes(dims4, S)
+    flat = synth.gaussians(synth.PHI_SEED, [sh for row in shapes for sh in row])
+    ph = [flat[j * 4:(j + 1) * 4] for j in range(4)]
+    X32 = torch.from_numpy(Xh).to(DEV)
+    phd = [[None if f is None else dev(f) for f in row] for row in ph]
+    G, Us = rt.rtucker_decompose(X32, r4, 6, phd, algo="rsthkron", s=S)
+    e_dev, _ = rt.rtucker_rel_error(X32, G, Us)
+    say("full size: 128^4 oracle")
+    Go, Uo = T.rsthkron(Xh.astype(np.float64), r4, ph)
+    e_or = T.rel_error(Xh.astype(np.float64), Go, Uo)
+    assert abs(e_dev - e_or) <= 1e-5, (e_dev, e_or)
+    X16 = rt.rtucker_convert(X32, torch.bfloat16)
+    G16, U16 = rt.rtucker_decompose(X16, r4, 6, phd, algo="rsthkron", s=S)
+    e16, _ = rt.rtucker_rel_error(X32, G16, U16)
+    assert e_dev <= e16 <= e_dev + 1e-2
