@@ -805,15 +805,6 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
   std::vector<GGramJob> gram[3];
   std::vector<GEigJob> eig[3];
   int64_t max_prep_sk = 1, max_prep_core = 1, max_cp = 1;
-  // the table region comes first; its size is fixed by the job counts
-  const size_t n_jobs_bytes =
-      align256(sizeof(PrepTask) * 3 * count) * 2 + align256(sizeof(GZwJob) * count) +
-      align256(sizeof(GTtmJob) * 3 * count) + 2 * align256(sizeof(GQrJob) * 3 * count) +
-      align256(sizeof(GCholQRJob) * 3 * count) +
-      3 * align256(sizeof(GTtmJob) * count) + align256(sizeof(GCopyJob) * count) +
-      3 * (align256(sizeof(GGramJob) * count) + align256(sizeof(GEigJob) * count) +
-           2 * align256(sizeof(GTtmJob) * count)) + 4096;
-  char* tables = static_cast<char*>(c.take(n_jobs_bytes));
   int64_t zw_blocks = 0, tree_blocks = 0, core_blocks[3] = {0, 0, 0}, g_blocks[3] = {0, 0, 0},
           u_blocks[3] = {0, 0, 0};
   const int core_mt_first = tune.core_mt;
@@ -831,9 +822,10 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
     // first sketch level: Z = X x_3 Phi_3, W = X x_2 Phi_2 (one pass over X)
     float* Z = static_cast<float*>(c.take(static_cast<size_t>(I0) * I1 * t.s[2] * 4));
     float* W = static_cast<float*>(c.take(static_cast<size_t>(I0) * t.s[1] * I2 * 4));
+    const int64_t spb = std::max<int64_t>(1, std::min<int64_t>(8, I0 / 24));  // slabs per workgroup
     zw.push_back(GZwJob{b.X, op[1], op[2], Z, W, I0, I1, I2, zw_blocks, static_cast<int32_t>(t.s[1]),
-                        static_cast<int32_t>(t.s[2])});
-    zw_blocks += I0;
+                        static_cast<int32_t>(t.s[2]), static_cast<int32_t>(spb), 0});
+    zw_blocks += ceil_div(I0, spb);
     // the three sketches: Y_1 = Z x_2 Phi_2, Y_2 = Z x_1 Phi_1, Y_3 = W x_1 Phi_1
     float* Y0 = static_cast<float*>(c.take(static_cast<size_t>(I0) * t.s[1] * t.s[2] * 4));
     float* Y1 = static_cast<float*>(c.take(static_cast<size_t>(t.s[0]) * I1 * t.s[2] * 4));
@@ -920,20 +912,39 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
       gcur = gnext;
     }
   }
-  // ---- tables
+  // ---- tables (job arrays and workgroup -> job maps), placed after every buffer
+  auto ttm_map = [](const std::vector<GTtmJob>& jobs) {
+    std::vector<int32_t> m;
+    for (size_t j = 0; j < jobs.size(); ++j) m.insert(m.end(), jobs[j].colblocks * jobs[j].mtiles, static_cast<int32_t>(j));
+    return m;
+  };
+  std::vector<int32_t> zw_map;
+  for (size_t j = 0; j < zw.size(); ++j)
+    zw_map.insert(zw_map.end(), ceil_div(zw[j].A, zw[j].spb), static_cast<int32_t>(j));
   TableBuf tb;
   const size_t o_psk = tb.add(prep_sk), o_zw = tb.add(zw), o_tree = tb.add(tree), o_cq = tb.add(qr_cq),
                o_hh = tb.add(qr_hh), o_fb = tb.add(qr_fb), o_pcore = tb.add(prep_core);
   size_t o_core[3], o_gram[3], o_eig[3], o_g[3], o_u[3];
-  for (int q = 0; q < 3; ++q) o_core[q] = tb.add(core[q]);
+  size_t m_core[3], m_g[3], m_u[3];
+  for (int q = 0; q < 3; ++q) {
+    o_core[q] = tb.add(core[q]);
+    m_core[q] = tb.add(ttm_map(core[q]));
+  }
   const size_t o_cp = tb.add(cp);
   for (int j = 0; j < 3; ++j) {
     o_gram[j] = tb.add(gram[j]);
     o_eig[j] = tb.add(eig[j]);
     o_g[j] = tb.add(gttm[j]);
+    m_g[j] = tb.add(ttm_map(gttm[j]));
     o_u[j] = tb.add(uttm[j]);
+    m_u[j] = tb.add(ttm_map(uttm[j]));
   }
-  if (tb.bytes.size() > n_jobs_bytes) return RT_EINVAL;  // internal sizing error
+  const size_t m_zw = tb.add(zw_map), m_tree = tb.add(ttm_map(tree));
+  // the same workspace serves every row tile of the first core contraction: reserve the
+  // map of the smallest tile (most workgroups)
+  size_t worst = 0;
+  for (const GTtmJob& j : core[0]) worst += static_cast<size_t>(j.colblocks * (ceil_div(j.m, 8) - j.mtiles)) * 4;
+  char* tables = static_cast<char*>(c.take(tb.bytes.size() + align256(worst)));
   if (c.dry) return RT_OK;
   if (mode != BatchMode::kLaunchOnly) {
     c.chk(hipMemcpyWithStream(tables, tb.bytes.data(), tb.bytes.size(), hipMemcpyHostToDevice, c.st));
@@ -943,9 +954,10 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
   const hipStream_t st = c.st;
   c.chk(launch_prep_grouped(reinterpret_cast<const PrepTask*>(at(o_psk)), static_cast<int>(prep_sk.size()),
                             max_prep_sk, st));
-  c.chk(launch_sketch_zw_grouped(reinterpret_cast<const GZwJob*>(at(o_zw)), count, zw_blocks, dtype, st));
-  c.chk(launch_ttm_grouped(reinterpret_cast<const GTtmJob*>(at(o_tree)), static_cast<int>(tree.size()), tree_blocks,
-                           RT_F32, 8, st));
+  auto imap = [&](size_t off) { return reinterpret_cast<const int32_t*>(at(off)); };
+  c.chk(launch_sketch_zw_grouped(reinterpret_cast<const GZwJob*>(at(o_zw)), imap(m_zw), count, zw_blocks, dtype, st));
+  c.chk(launch_ttm_grouped(reinterpret_cast<const GTtmJob*>(at(o_tree)), imap(m_tree), static_cast<int>(tree.size()),
+                           tree_blocks, RT_F32, 8, st));
   c.chk(launch_cholqr2_grouped(reinterpret_cast<const GCholQRJob*>(at(o_cq)), static_cast<int>(qr_cq.size()),
                                max_chunks, RT_F32, st));
   c.chk(launch_qr_grouped(reinterpret_cast<const GQrJob*>(at(o_hh)), static_cast<int>(qr_hh.size()), RT_F32, st));
@@ -953,14 +965,16 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
   c.chk(launch_prep_grouped(reinterpret_cast<const PrepTask*>(at(o_pcore)), static_cast<int>(prep_core.size()),
                             max_prep_core, st));
   for (int q = 0; q < 3; ++q)
-    c.chk(launch_ttm_grouped(reinterpret_cast<const GTtmJob*>(at(o_core[q])), count, core_blocks[q],
-                             q == 0 ? dtype : RT_F32, q == 0 ? core_mt_first : 16, st));
+    c.chk(launch_ttm_grouped(reinterpret_cast<const GTtmJob*>(at(o_core[q])), imap(m_core[q]), count,
+                             core_blocks[q], q == 0 ? dtype : RT_F32, q == 0 ? core_mt_first : 16, st));
   c.chk(launch_copy_f64_grouped(reinterpret_cast<const GCopyJob*>(at(o_cp)), count, max_cp, st));
   for (int j = 0; j < 3; ++j) {
     c.chk(launch_gram_grouped(reinterpret_cast<const GGramJob*>(at(o_gram[j])), count, st));
     c.chk(launch_eig_grouped(reinterpret_cast<const GEigJob*>(at(o_eig[j])), count, st));
-    c.chk(launch_ttm_grouped(reinterpret_cast<const GTtmJob*>(at(o_g[j])), count, g_blocks[j], RT_F64, 16, st));
-    c.chk(launch_ttm_grouped(reinterpret_cast<const GTtmJob*>(at(o_u[j])), count, u_blocks[j], RT_F64, 16, st));
+    c.chk(launch_ttm_grouped(reinterpret_cast<const GTtmJob*>(at(o_g[j])), imap(m_g[j]), count, g_blocks[j], RT_F64,
+                             16, st));
+    c.chk(launch_ttm_grouped(reinterpret_cast<const GTtmJob*>(at(o_u[j])), imap(m_u[j]), count, u_blocks[j], RT_F64,
+                             16, st));
   }
   return RT_OK;
 }

@@ -134,16 +134,5 @@ __device__ __forceinline__ double rsq_refined(double x) {
   return y;
 }
 
-// index of the job owning flat workgroup `blk` in a grouped launch: the last job
-// whose first workgroup blk0 is <= blk (jobs sorted by blk0)
-template <typename T>
-__device__ __forceinline__ int find_job(const T* __restrict__ jobs, int count, int64_t blk) {
-  int lo = 0, hi = count - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) / 2;
-    if (jobs[mid].blk0 <= blk) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
 
 }  // namespace rt

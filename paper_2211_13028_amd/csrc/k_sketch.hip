@@ -110,84 +110,6 @@ __global__ __launch_bounds__(kZWThreads) void sketch_zw_kernel(const TX* __restr
   }
 }
 
-// grouped form for many small tensors: one workgroup per slab X[a] of a job
-// (all rows, all Q <= 256 columns), so no partial sums are needed
-template <typename TX>
-__global__ __launch_bounds__(kZWThreads) void sketch_zw_grouped_kernel(const GZwJob* __restrict__ jobs, int count) {
-  constexpr int NQ = 4, SMAX = 8;
-  __shared__ float sW[kZWWaves][SMAX][64 * NQ];
-  const int64_t blk = blockIdx.x;
-  const GZwJob J = jobs[find_job(jobs, count, blk)];
-  const int64_t a = blk - J.blk0;
-  const int64_t P = J.P, Q = J.Q;
-  const int sP = J.sP, sQ = J.sQ;
-  const int lane = threadIdx.x % kWave;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const bool needZ = J.Z != nullptr, needW = J.W != nullptr;
-  float phq[NQ][SMAX];
-  float wacc[NQ][SMAX];
-#pragma unroll
-  for (int j = 0; j < NQ; ++j) {
-    const int64_t q = lane + 64 * j;
-#pragma unroll
-    for (int c = 0; c < SMAX; ++c) {
-      phq[j][c] = (needZ && q < Q && c < sQ) ? J.phiQ[c * Q + q] : 0.f;
-      wacc[j][c] = 0.f;
-    }
-  }
-  const TX* xa = static_cast<const TX*>(J.X) + a * P * Q;
-  float* zrow = needZ ? J.Z + a * P * sQ : nullptr;
-  for (int64_t p = wave; p < P; p += kZWWaves) {
-    float x[NQ];
-#pragma unroll
-    for (int j = 0; j < NQ; ++j) {
-      const int64_t q = lane + 64 * j;
-      x[j] = (q < Q) ? static_cast<float>(Load<TX>::get(xa, p * Q + q)) : 0.f;
-    }
-    if (needW) {
-#pragma unroll
-      for (int c = 0; c < SMAX; ++c) {
-        const float f = (c < sP) ? J.phiP[c * P + p] : 0.f;
-#pragma unroll
-        for (int j = 0; j < NQ; ++j) wacc[j][c] = fmaf(f, x[j], wacc[j][c]);
-      }
-    }
-    if (needZ) {
-      float z[SMAX];
-#pragma unroll
-      for (int c = 0; c < SMAX; ++c) {
-        float sum = 0.f;
-#pragma unroll
-        for (int j = 0; j < NQ; ++j) sum = fmaf(x[j], phq[j][c], sum);
-        z[c] = sum;
-      }
-#pragma unroll
-      for (int c = 0; c < SMAX; ++c)
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) z[c] += __shfl_xor(z[c], off);
-      float mine = 0.f;
-#pragma unroll
-      for (int c = 0; c < SMAX; ++c)
-        if (lane == c) mine = z[c];
-      if (lane < sQ) zrow[p * sQ + lane] = mine;
-    }
-  }
-  if (!needW) return;
-#pragma unroll
-  for (int j = 0; j < NQ; ++j)
-#pragma unroll
-    for (int c = 0; c < SMAX; ++c) sW[wave][c][lane + 64 * j] = wacc[j][c];
-  __syncthreads();
-  float* wout = J.W + a * sP * Q;
-  for (int idx = threadIdx.x; idx < sP * 64 * NQ; idx += kZWThreads) {
-    const int c = idx / (64 * NQ), col = idx % (64 * NQ);
-    if (col >= Q) continue;
-    float sum = 0.f;
-    for (int w = 0; w < kZWWaves; ++w) sum += sW[w][c][col];
-    wout[c * Q + col] = sum;
-  }
-}
-
 template <typename TC>
 __global__ __launch_bounds__(256) void sum_parts_kernel(const TC* __restrict__ part, int parts, int64_t n,
                                                         TC* __restrict__ out) {
@@ -494,7 +416,7 @@ __global__ __launch_bounds__(kZWThreads) __attribute__((amdgpu_waves_per_eu(3)))
   }
 }
 
-// grouped form on matrix cores: one wave per slab X[a] of a job, all rows and all
+// grouped form on matrix cores: one wave per run of `spb` slabs X[a] of a job, all rows and all
 // Q <= 256 columns (arbitrary P and Q, element loads with bounds), binary32 MFMA
 // (bfloat16 data is widened exactly; its products are exact in binary32).  Per
 // 16-row step, lane (li, kg) holds row 4 t + kg of each row quad t, columns
@@ -503,92 +425,96 @@ __global__ __launch_bounds__(kZWThreads) __attribute__((amdgpu_waves_per_eu(3)))
 constexpr int kGStride = 260;  // floats per staged row: 256 + 4 padding
 
 template <typename TX>
-__global__ __launch_bounds__(kWave) void sketch_zw_grouped_mfma_kernel(const GZwJob* __restrict__ jobs, int count) {
+__global__ __launch_bounds__(kWave) void sketch_zw_grouped_mfma_kernel(const GZwJob* __restrict__ jobs,
+                                                                        const int32_t* __restrict__ blkjob) {
   __shared__ float tile[16 * kGStride];
   const int64_t blk = blockIdx.x;
-  const GZwJob J = jobs[find_job(jobs, count, blk)];
-  const int64_t a = blk - J.blk0;
-  const int64_t P = J.P, Q = J.Q;
-  const int sP = J.sP, sQ = J.sQ;
-  const int lane = threadIdx.x;
-  const int li = lane % 16, kg = lane / 16;
-  const bool needZ = J.Z != nullptr, needW = J.W != nullptr;
-  const TX* xa = static_cast<const TX*>(J.X) + a * P * Q;
-  const int ncb = static_cast<int>((Q + 63) / 64);  // 64-column blocks in use (<= 4)
-  f32x4 wacc[4][4];
+  const GZwJob J = jobs[blkjob[blk]];
+  const int64_t a_beg = (blk - J.blk0) * J.spb;
+  const int64_t a_end = (a_beg + J.spb < J.A) ? a_beg + J.spb : J.A;
+  for (int64_t a = a_beg; a < a_end; ++a) {
+    const int64_t P = J.P, Q = J.Q;
+    const int sP = J.sP, sQ = J.sQ;
+    const int lane = threadIdx.x;
+    const int li = lane % 16, kg = lane / 16;
+    const bool needZ = J.Z != nullptr, needW = J.W != nullptr;
+    const TX* xa = static_cast<const TX*>(J.X) + a * P * Q;
+    const int ncb = static_cast<int>((Q + 63) / 64);  // 64-column blocks in use (<= 4)
+    f32x4 wacc[4][4];
 #pragma unroll
-  for (int cb = 0; cb < 4; ++cb)
+    for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) wacc[cb][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-  float* zout = needZ ? J.Z + a * P * sQ : nullptr;
-  for (int64_t pb = 0; pb < P; pb += 16) {
-    f32x4 r[4][4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int64_t p = pb + 4 * t + kg;
-#pragma unroll
-      for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int64_t q = 64 * cb + 4 * li + c;
-          r[t][cb][c] = (cb < ncb && p < P && q < Q) ? static_cast<float>(Load<TX>::get(xa, p * Q + q)) : 0.f;
-        }
-    }
-    if (needW) {
+      for (int c = 0; c < 4; ++c) wacc[cb][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float* zout = needZ ? J.Z + a * P * sQ : nullptr;
+    for (int64_t pb = 0; pb < P; pb += 16) {
+      f32x4 r[4][4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int64_t p = pb + 4 * t + kg;
-        const float pp = (p < P && li < sP) ? J.phiP[static_cast<int64_t>(li) * P + p] : 0.f;
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb)
-          if (cb < ncb) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-              wacc[cb][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(pp, r[t][cb][c], wacc[cb][c], 0, 0, 0);
+          for (int c = 0; c < 4; ++c) {
+            const int64_t q = 64 * cb + 4 * li + c;
+            r[t][cb][c] = (cb < ncb && p < P && q < Q) ? static_cast<float>(Load<TX>::get(xa, p * Q + q)) : 0.f;
           }
       }
-    }
-    if (needZ) {
-      __builtin_amdgcn_wave_barrier();  // the previous step's reads of the staging area stay above
+      if (needW) {
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
+        for (int t = 0; t < 4; ++t) {
+          const int64_t p = pb + 4 * t + kg;
+          const float pp = (p < P && li < sP) ? J.phiP[static_cast<int64_t>(li) * P + p] : 0.f;
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb)
-          if (cb < ncb) *reinterpret_cast<f32x4*>(tile + (4 * t + kg) * kGStride + 64 * cb + 4 * li) = r[t][cb];
-      __builtin_amdgcn_wave_barrier();  // cross-lane: stores before the reads below
-      f32x4 zacc = f32x4{0.f, 0.f, 0.f, 0.f};
-      for (int kb = 0; kb < 4 * ncb; ++kb) {
-        const f32x4 xr = *reinterpret_cast<const f32x4*>(tile + li * kGStride + 16 * kb + 4 * kg);
-        f32x4 bq;
+          for (int cb = 0; cb < 4; ++cb)
+            if (cb < ncb) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int64_t q = 16 * kb + 4 * kg + c;
-          bq[c] = (q < Q && li < sQ) ? J.phiQ[static_cast<int64_t>(li) * Q + q] : 0.f;
+              for (int c = 0; c < 4; ++c)
+                wacc[cb][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(pp, r[t][cb][c], wacc[cb][c], 0, 0, 0);
+            }
         }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) zacc = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[c], bq[c], zacc, 0, 0, 0);
       }
-      // D layout: row 4 kg + v of the step, column c = li
+      if (needZ) {
+        __builtin_amdgcn_wave_barrier();  // the previous step's reads of the staging area stay above
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb)
+            if (cb < ncb) *reinterpret_cast<f32x4*>(tile + (4 * t + kg) * kGStride + 64 * cb + 4 * li) = r[t][cb];
+        __builtin_amdgcn_wave_barrier();  // cross-lane: stores before the reads below
+        f32x4 zacc = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int kb = 0; kb < 4 * ncb; ++kb) {
+          const f32x4 xr = *reinterpret_cast<const f32x4*>(tile + li * kGStride + 16 * kb + 4 * kg);
+          f32x4 bq;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const int64_t q = 16 * kb + 4 * kg + c;
+            bq[c] = (q < Q && li < sQ) ? J.phiQ[static_cast<int64_t>(li) * Q + q] : 0.f;
+          }
+#pragma unroll
+          for (int c = 0; c < 4; ++c) zacc = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[c], bq[c], zacc, 0, 0, 0);
+        }
+        // D layout: row 4 kg + v of the step, column c = li
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t p = pb + 4 * kg + v;
+          if (p < P && li < sQ) zout[p * sQ + li] = zacc[v];
+        }
+      }
+    }
+    if (!needW) continue;
+    float* wout = J.W + a * sP * Q;
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      if (cb >= ncb) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t p = pb + 4 * kg + v;
-        if (p < P && li < sQ) zout[p * sQ + li] = zacc[v];
-      }
-    }
-  }
-  if (!needW) return;
-  float* wout = J.W + a * sP * Q;
+        const int cp = 4 * kg + v;
+        if (cp >= sP) continue;
 #pragma unroll
-  for (int cb = 0; cb < 4; ++cb) {
-    if (cb >= ncb) continue;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int cp = 4 * kg + v;
-      if (cp >= sP) continue;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int64_t q = 64 * cb + 4 * li + c;
-        if (q < Q) wout[static_cast<int64_t>(cp) * Q + q] = wacc[cb][c][v];
+        for (int c = 0; c < 4; ++c) {
+          const int64_t q = 64 * cb + 4 * li + c;
+          if (q < Q) wout[static_cast<int64_t>(cp) * Q + q] = wacc[cb][c][v];
+        }
       }
     }
   }
@@ -771,14 +697,14 @@ hipError_t launch_sketch_zw(const void* X, rt_dtype xdt, int64_t A, int64_t P, i
   return hipGetLastError();
 }
 
-hipError_t launch_sketch_zw_grouped(const GZwJob* jobs, int count, int64_t total_blocks, rt_dtype xdt,
-                                    hipStream_t st) {
+hipError_t launch_sketch_zw_grouped(const GZwJob* jobs, const int32_t* blkjob, int count, int64_t total_blocks,
+                                    rt_dtype xdt, hipStream_t st) {
   if (count == 0 || total_blocks == 0) return hipSuccess;
   const unsigned g = static_cast<unsigned>(total_blocks);
   if (xdt == RT_F32)
-    sketch_zw_grouped_mfma_kernel<float><<<g, kWave, 0, st>>>(jobs, count);
+    sketch_zw_grouped_mfma_kernel<float><<<g, kWave, 0, st>>>(jobs, blkjob);
   else if (xdt == RT_BF16)
-    sketch_zw_grouped_mfma_kernel<bf16_t><<<g, kWave, 0, st>>>(jobs, count);
+    sketch_zw_grouped_mfma_kernel<bf16_t><<<g, kWave, 0, st>>>(jobs, blkjob);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

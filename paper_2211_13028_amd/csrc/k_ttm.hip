@@ -110,10 +110,11 @@ hipError_t generic_dispatch(const TX* X, int64_t A, int64_t K, int64_t B, const 
 // grouped form: job found by binary search over blk0; one wave per workgroup
 
 template <typename TX, typename TC, int MT>
-__global__ __launch_bounds__(kWave) void ttm_grouped_kernel(const GTtmJob* __restrict__ jobs, int count) {
+__global__ __launch_bounds__(kWave) void ttm_grouped_kernel(const GTtmJob* __restrict__ jobs,
+                                                             const int32_t* __restrict__ blkjob) {
   __shared__ TC sM[MT][kGenKC];
   const int64_t blk = blockIdx.x;
-  const GTtmJob J = jobs[find_job(jobs, count, blk)];
+  const GTtmJob J = jobs[blkjob[blk]];
   const int64_t local = blk - J.blk0;
   const int64_t cb = local / J.mtiles, mtile = local - cb * J.mtiles;
   const int64_t A = J.A, K = J.K, B = J.B, m = J.m;
@@ -549,11 +550,11 @@ int64_t ttm_grouped_blocks(int64_t A, int64_t B, int64_t m, int mt) {
   return ceil_div(A * B, kWave) * ceil_div(m, mt);
 }
 
-hipError_t launch_ttm_grouped(const GTtmJob* jobs, int count, int64_t total_blocks, rt_dtype xdt, int mt,
-                              hipStream_t st) {
+hipError_t launch_ttm_grouped(const GTtmJob* jobs, const int32_t* blkjob, int count, int64_t total_blocks,
+                              rt_dtype xdt, int mt, hipStream_t st) {
   if (count == 0 || total_blocks == 0) return hipSuccess;
   const unsigned g = static_cast<unsigned>(total_blocks);
-#define RT_G(TX, TC, MTV) ttm_grouped_kernel<TX, TC, MTV><<<g, kWave, 0, st>>>(jobs, count)
+#define RT_G(TX, TC, MTV) ttm_grouped_kernel<TX, TC, MTV><<<g, kWave, 0, st>>>(jobs, blkjob)
   // the row tile must be exactly the one the block counts were computed with
   if (mt != 8 && mt != 16 && mt != 32) return hipErrorInvalidValue;
   switch (xdt) {

@@ -146,8 +146,8 @@ hipError_t launch_sumsq_f64(const double* g, int64_t n, double* out_slot, hipStr
 // ------------------------------------------------------------------ grouped launches
 // For the batched decomposition: each launcher below runs many independent jobs
 // of one kind in a single launch.  The job table lives in device memory; job j
-// owns the workgroups [blk0_j, blk0_j + blocks_j) of a flat grid, and each
-// workgroup finds its job by binary search over blk0 (ascending).
+// owns the workgroups [blk0_j, blk0_j + blocks_j) of a flat grid.  Where jobs
+// own many workgroups, a device map blkjob[workgroup] = job replaces a search.
 
 // k_basic.hip: operand rounding (PrepTask per job, blockIdx.y = job) and
 // binary32 -> binary64 copies.
@@ -171,11 +171,11 @@ struct GTtmJob {
   int32_t mtrans, pad;
 };
 int64_t ttm_grouped_blocks(int64_t A, int64_t B, int64_t m, int mt);
-hipError_t launch_ttm_grouped(const GTtmJob* jobs, int count, int64_t total_blocks, rt_dtype xdt, int mt,
-                              hipStream_t st);
+hipError_t launch_ttm_grouped(const GTtmJob* jobs, const int32_t* blkjob, int count, int64_t total_blocks,
+                              rt_dtype xdt, int mt, hipStream_t st);
 
 // k_sketch.hip: first sketch level (Z and W) per 3-way tensor (A, P, Q), one
-// workgroup per slab a; Q <= 256, s <= 8.  Operands in binary32.
+// one-wave workgroup per run of spb slabs; Q <= 256, s <= 16.  Operands binary32.
 struct GZwJob {
   const void* X;
   const float* phiP;
@@ -185,9 +185,10 @@ struct GZwJob {
   int64_t A, P, Q;
   int64_t blk0;
   int32_t sP, sQ;
+  int32_t spb, pad;
 };
-hipError_t launch_sketch_zw_grouped(const GZwJob* jobs, int count, int64_t total_blocks, rt_dtype xdt,
-                                    hipStream_t st);
+hipError_t launch_sketch_zw_grouped(const GZwJob* jobs, const int32_t* blkjob, int count, int64_t total_blocks,
+                                    rt_dtype xdt, hipStream_t st);
 
 // k_qr.hip: thin Householder QR of (A, m, B) views with m <= 256 rows and
 // n = A*B <= 64 columns, one workgroup per job; Q: m x qcols (qcols = min(m, n)).
