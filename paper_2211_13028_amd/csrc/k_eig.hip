@@ -335,7 +335,7 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ M, int n, in
   __shared__ double Am[kJN * kAStride];  // Schur complement during the Cholesky (original indices)
   __shared__ double Lc[kJN * kLStride];  // columns of L: Lc[col * kLStride + row] (original row order)
   __shared__ double nrm[kJN];
-  __shared__ int rotated;
+  __shared__ int rotated, not_tiny;
   __shared__ int order[kJN];
   __shared__ double vtmp[kJN];
   const int tid = threadIdx.x;
@@ -396,8 +396,15 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ M, int n, in
   const int g = tid / kPairLanes, sub = tid % kPairLanes;
   const double tol = (n > 8 ? n : 8) * 2.220446049250313e-16;
   const double tol2 = tol * tol;
+  // Near convergence a sweep squares the largest relative off-diagonal product, so a
+  // sweep in which none exceeded 1e-9 leaves them all far below tol: the verifying sweep
+  // that would rotate nothing is skipped.
+  const double thr2 = 1e-18;
   for (int sweep = 0; sweep < kMaxSweeps && N > 1; ++sweep) {
-    if (tid == 0) rotated = 0;
+    if (tid == 0) {
+      rotated = 0;
+      not_tiny = 0;
+    }
     __syncthreads();
     // circle-method positions of this group's pair, advanced without division
     int a_pos = (g == 0) ? 0 : g;                  // position g holds player g at round 0
@@ -446,7 +453,10 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ M, int n, in
             reinterpret_cast<double2*>(xp)[q] = nx;
             reinterpret_cast<double2*>(yp)[q] = ny;
           }
-          if (sub == 0) rotated = 1;
+          if (sub == 0) {
+            rotated = 1;
+            if (ga * ga > thr2 * (al * be)) not_tiny = 1;
+          }
         }
       }
       // next round: every position except 0 advances by one player (wrapping N-1 -> 1)
@@ -454,7 +464,7 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ M, int n, in
       b_pos = (b_pos == N - 1) ? 1 : b_pos + 1;
       __syncthreads();
     }
-    if (!rotated) break;
+    if (!rotated || !not_tiny) break;
     __syncthreads();
   }
   // ---- 3. norms, order (decreasing), normalised columns, sign rule
