@@ -258,9 +258,12 @@ MCPlan mc_plan(rt_dtype dt, int64_t A, int64_t mP, int64_t mQ, int64_t B) {
 // computed directly.  One round applies the rotations of all disjoint pairs of
 // the circle-method pairing; each pair is owned by a row of 16 lanes (4 rows of L
 // each), so a round needs one barrier and two waves share each SIMD, which hides
-// much of the latency of the dependent binary64 operations.  Rotation parameters
-// use only reciprocal square roots (hardware estimate + two Newton steps), no
-// division or square root.
+// part of the latency of the dependent binary64 operations.  A round is bound by
+// the dependent chain of one pair, so the rotation angle is found in binary32
+// (any angle gives an exactly orthogonal rotation; a slightly wrong one only
+// leaves a residual product of about 1e-7 of the old one, which later rotations
+// remove) and only cos phi = 1 / sqrt(1 + tan^2 phi) is computed to full binary64
+// accuracy, with sin phi = tan phi cos phi, so that c^2 + s^2 = 1 to rounding.
 constexpr int kJN = 64;
 constexpr int kJThreads = 512;
 constexpr int kJWaves = kJThreads / kWave;
@@ -270,15 +273,18 @@ constexpr int kMaxSweeps = 30;
 constexpr int kLStride = 72;  // doubles per column of L in LDS (padding spreads banks)
 constexpr int kAStride = 65;  // doubles per row of the working matrix
 
-// DPP moves on the two halves of a binary64 value
+// DPP moves on the two halves of a binary64 value (every source lane used here
+// lies inside the row, so bound_ctrl never takes effect and no old value is needed)
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
   const int64_t u = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(u & 0xffffffff), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(u >> 32), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(static_cast<int>(u & 0xffffffff), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(static_cast<int>(u >> 32), CTRL, 0xF, 0xF, true);
   return __longlong_as_double((static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo));
 }
-// sum over aligned groups of 16 lanes (a DPP row); every lane of a group gets bitwise the same value
+// sum over aligned groups of 16 lanes (a DPP row); every lane of a group gets bitwise the
+// same value (each step adds a value to its partner's with the operands swapped, and
+// addition commutes)
 __device__ __forceinline__ double group16_sum(double v) {
   v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
   v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
@@ -286,10 +292,27 @@ __device__ __forceinline__ double group16_sum(double v) {
   v += dpp_f64<0x140>(v);  // row_mirror: lane i <- lane 15-i within 16
   return v;
 }
+// three such sums, stage by stage, so that the three dependent chains overlap
+__device__ __forceinline__ void group16_sum3(double& a, double& b, double& c) {
+#define RT_STAGE(CTRL)                   \
+  {                                      \
+    const double da = dpp_f64<CTRL>(a);  \
+    const double db = dpp_f64<CTRL>(b);  \
+    const double dc = dpp_f64<CTRL>(c);  \
+    a += da;                             \
+    b += db;                             \
+    c += dc;                             \
+  }
+  RT_STAGE(0xB1)
+  RT_STAGE(0x4E)
+  RT_STAGE(0x141)
+  RT_STAGE(0x140)
+#undef RT_STAGE
+}
 
 template <int CTRL>
 __device__ __forceinline__ int dpp_i32(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
 }
 // argmax (ties: lowest index) within each row of 16 lanes; all lanes of a row end with the result
 __device__ __forceinline__ void argmax_row16(double& v, int& idx) {
@@ -335,7 +358,8 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ M, int n, in
   __shared__ double Am[kJN * kAStride];  // Schur complement during the Cholesky (original indices)
   __shared__ double Lc[kJN * kLStride];  // columns of L: Lc[col * kLStride + row] (original row order)
   __shared__ double nrm[kJN];
-  __shared__ int rotated, not_tiny;
+  __shared__ int active;
+  __shared__ double tau2s;
   __shared__ int order[kJN];
   __shared__ double vtmp[kJN];
   const int tid = threadIdx.x;
@@ -400,12 +424,17 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ M, int n, in
   // sweep in which none exceeded 1e-9 leaves them all far below tol: the verifying sweep
   // that would rotate nothing is skipped.
   const double thr2 = 1e-18;
+  // Only the r columns of largest norm are returned.  A pair of two columns that both
+  // lie below the r-th largest norm only mixes directions inside the discarded subspace,
+  // so it does not hold up the stopping test (it is still rotated).  tau2 is the r-th
+  // largest squared norm, taken from the last round of the previous sweep, in which
+  // every column is in a pair; sweep 0 counts every pair.
+  double tau2 = 0.0;
+  if (tid == 0) tau2s = 0.0;
   for (int sweep = 0; sweep < kMaxSweeps && N > 1; ++sweep) {
-    if (tid == 0) {
-      rotated = 0;
-      not_tiny = 0;
-    }
+    if (tid == 0) active = 0;
     __syncthreads();
+    if (sweep > 0) tau2 = tau2s;
     // circle-method positions of this group's pair, advanced without division
     int a_pos = (g == 0) ? 0 : g;                  // position g holds player g at round 0
     int b_pos = N - 1 - g;
@@ -427,23 +456,24 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ M, int n, in
           be = fma(y2[t].x, y2[t].x, be); be = fma(y2[t].y, y2[t].y, be);
           ga = fma(x2[t].x, y2[t].x, ga); ga = fma(x2[t].y, y2[t].y, ga);
         }
-        al = group16_sum(al);
-        be = group16_sum(be);
-        ga = group16_sum(ga);
+        group16_sum3(al, be, ga);
+        if (round == N - 2 && sub == 0) {
+          nrm[pc] = al;
+          nrm[qc] = be;
+        }
         // rotate unless the pair is orthogonal to the rounding level of an n-term dot product
         if (fabs(ga) > 1e-300 && ga * ga > tol2 * (al * be)) {
           // tan(2 phi) = v / u with u = be - al, v = 2 ga; smallest rotation |phi| <= pi/4:
-          //   cos 2phi = |u| / h,  cos phi = sqrt((1 + cos 2phi) / 2),
-          //   sin phi = sign(u v) |v| / (2 h cos phi),  h = sqrt(u^2 + v^2).
-          // u and v are first scaled by (about) 1 / max(|u|, |v|) to keep h^2 in range.
+          //   |tan phi| = |v| / (|u| + sqrt(u^2 + v^2)),  sign = sign(u v) (+ for u = 0).
+          // u and v are scaled exactly by a power of two to |.| <= 1 before going to binary32.
           const double u0 = be - al, v0 = 2.0 * ga;
-          const double sc = __builtin_amdgcn_rcp(fmax(fabs(u0), fabs(v0)));
-          const double u = fabs(u0) * sc, v = fabs(v0) * sc;
-          const double rh = rsq_refined(fma(u, u, v * v));  // 1 / h
-          const double w = fma(0.5 * u, rh, 0.5);             // cos^2 phi
-          const double iw = rsq_refined(w);                   // 1 / cos phi
-          const double c = w * iw;
-          double s = 0.5 * v * rh * iw;
+          const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(u0), fabs(v0)));
+          const float uf = static_cast<float>(__builtin_amdgcn_ldexp(fabs(u0), -ex));
+          const float vf = static_cast<float>(__builtin_amdgcn_ldexp(fabs(v0), -ex));
+          const float hf = __builtin_amdgcn_sqrtf(fmaf(uf, uf, vf * vf));
+          const double t = static_cast<double>(vf * __builtin_amdgcn_rcpf(uf + hf));
+          const double c = rsq_refined(fma(t, t, 1.0));
+          double s = t * c;
           if ((u0 < 0.0) != (v0 < 0.0) && u0 != 0.0) s = -s;
 #pragma unroll
           for (int q = 0; q < kPairRows / 2; ++q) {
@@ -453,10 +483,7 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ M, int n, in
             reinterpret_cast<double2*>(xp)[q] = nx;
             reinterpret_cast<double2*>(yp)[q] = ny;
           }
-          if (sub == 0) {
-            rotated = 1;
-            if (ga * ga > thr2 * (al * be)) not_tiny = 1;
-          }
+          if (sub == 0 && ga * ga > thr2 * (al * be) && fmax(al, be) >= tau2) active = 1;
         }
       }
       // next round: every position except 0 advances by one player (wrapping N-1 -> 1)
@@ -464,7 +491,17 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ M, int n, in
       b_pos = (b_pos == N - 1) ? 1 : b_pos + 1;
       __syncthreads();
     }
-    if (!rotated || !not_tiny) break;
+    if (!active) break;
+    // r-th largest squared norm (ties: lower index first) for the next sweep's test
+    if (tid < N) {
+      const double li = nrm[tid];
+      int rk = 0;
+      for (int j = 0; j < N; ++j) {
+        const double lj = nrm[j];
+        rk += (lj > li || (lj == li && j < tid)) ? 1 : 0;
+      }
+      if (rk == r - 1) tau2s = li;
+    }
     __syncthreads();
   }
   // ---- 3. norms, order (decreasing), normalised columns, sign rule
