@@ -310,25 +310,6 @@ __device__ __forceinline__ void group16_sum3(double& a, double& b, double& c) {
 #undef RT_STAGE
 }
 
-template <int CTRL>
-__device__ __forceinline__ int dpp_i32(int v) {
-  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
-}
-// argmax (ties: lowest index) within each row of 16 lanes; all lanes of a row end with the result
-__device__ __forceinline__ void argmax_row16(double& v, int& idx) {
-#define RT_STEP(CTRL)                                                   \
-  {                                                                     \
-    const double ov = dpp_f64<CTRL>(v);                                 \
-    const int oi = dpp_i32<CTRL>(idx);                                  \
-    if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }          \
-  }
-  RT_STEP(0xB1)   // quad_perm [1,0,3,2]
-  RT_STEP(0x4E)   // quad_perm [2,3,0,1]
-  RT_STEP(0x141)  // row_half_mirror
-  RT_STEP(0x140)  // row_mirror
-#undef RT_STEP
-}
-
 
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
   const int64_t u = __double_as_longlong(v);
@@ -337,19 +318,32 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
   return __longlong_as_double((static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo));
 }
 
-// argmax over the whole wave (ties: lowest index); every lane ends with the result
+// DPP broadcast of the last lane of a row into the rows of ROW_MASK (other rows keep v)
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_bcast_f64(double v) {
+  const int64_t u = __double_as_longlong(v);
+  const int l = static_cast<int>(u & 0xffffffff), h = static_cast<int>(u >> 32);
+  const int lo = __builtin_amdgcn_update_dpp(l, l, CTRL, ROW_MASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(h, h, CTRL, ROW_MASK, 0xF, false);
+  return __longlong_as_double((static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo));
+}
+
+// argmax over the whole wave; every lane ends with the value and its lane.  The lane
+// number (reversed) replaces the 6 lowest mantissa bits, so one binary64 max per step
+// carries the index along; values that agree to 46 bits count as ties, which go to the
+// lowest lane.  The returned value is the unmodified one of the chosen lane.
 __device__ __forceinline__ void argmax64(double& v, int& idx) {
-  argmax_row16(v, idx);
-  double best = readlane_f64(v, 0);
-  int bi = __builtin_amdgcn_readlane(idx, 0);
-#pragma unroll
-  for (int row = 1; row < 4; ++row) {
-    const double ov = readlane_f64(v, 16 * row);
-    const int oi = __builtin_amdgcn_readlane(idx, 16 * row);
-    if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-  }
-  v = best;
-  idx = bi;
+  const int lane = static_cast<int>(threadIdx.x % kWave);
+  double k = __longlong_as_double((__double_as_longlong(v) & ~static_cast<int64_t>(63)) | (63 - lane));
+  k = fmax(k, dpp_f64<0xB1>(k));   // quad_perm [1,0,3,2]
+  k = fmax(k, dpp_f64<0x4E>(k));   // quad_perm [2,3,0,1]
+  k = fmax(k, dpp_f64<0x141>(k));  // row_half_mirror
+  k = fmax(k, dpp_f64<0x140>(k));  // row_mirror: every lane of a row holds the row's maximum
+  k = fmax(k, dpp_bcast_f64<0x142, 0xA>(k));  // row_bcast:15 -> rows 1, 3
+  k = fmax(k, dpp_bcast_f64<0x143, 0xC>(k));  // row_bcast:31 -> rows 2, 3 (row 3: all)
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(__double_as_longlong(k) & 0xffffffff), kWave - 1);
+  idx = 63 - (lo & 63);
+  v = readlane_f64(v, idx);
 }
 
 
