@@ -563,29 +563,30 @@ __device__ __forceinline__ void eig_jacobi(const double* __restrict__ M, int n, 
 // ------------------------------------------------------------------ tridiagonal eigensolver
 // The r <= 32 leading eigenpairs of the Gram matrix, in four phases on one workgroup:
 //  1. Householder reduction to tridiagonal form, T = Q^T A Q with Q = H_0 ... H_{n-3};
-//  2. the r largest eigenvalues of T by multisection: 16 lanes per eigenvalue evaluate the
+//  2. the r largest eigenvalues of T by multisection: 8 lanes per eigenvalue evaluate the
 //     Sturm count (sign changes of the leading principal minors, a three-term recurrence
-//     rescaled by powers of two) at 15 interior points of its bracket, which shrinks 17x
+//     rescaled by powers of two) at 8 interior points of its bracket, which shrinks 9x
 //     per step;
 //  3. eigenvectors of T by inverse iteration, one lane per eigenvalue: LU of T - lambda I
-//     with partial pivoting (tiny pivots raised to eps |T|), three solves from a fixed
+//     with partial pivoting (tiny pivots raised to eps |T|), two solves from a fixed
 //     pseudo-random start vector;
-//  4. one Loewdin step Z <- Z (I - E/2 + 3 E^2 / 8), E = Z^T Z - I, then V = Q Z.
+//  4. one Loewdin step Z <- Z (I - E/2 + 3 E^2 / 8), E = Z^T Z - I, skipped when Z is
+//     orthonormal to rounding already, then V = Q Z.
 // The result is accepted only when ||E|| <= 1e-6 (the series is then exact to rounding)
 // and every residual |T z - lambda z| is below 1e-12 |T|; otherwise, for example for
 // repeated or numerically zero eigenvalues, whose inverse-iteration vectors are not
 // independent, the caller falls back to the Jacobi solver.  The phases are sequential
 // chains of about 50 steps each instead of the ~350 rounds of Jacobi sweeps.
 constexpr int kTriMaxR = 32;
-constexpr int kMsGroup = 16;   // lanes per eigenvalue in the multisection
-constexpr int kMsIters = 14;   // 17^14 > 2^57: the bracket reaches rounding level of |T|
-constexpr int kInvIters = 3;
+constexpr int kMsGroup = 8;    // lanes per eigenvalue in the multisection (r <= 32: four waves)
+constexpr int kMsIters = 18;   // 9^18 > 2^57: the bracket reaches rounding level of |T|
+constexpr int kInvIters = 2;
 constexpr int kEStride = kTriMaxR + 1;
 // scratch region B (doubles): five n x 32 arrays of the inverse iteration; aliased by the
 // per-wave vectors and partial sums of phase 1, by E and F of phase 4, and by the Jacobi L
 constexpr int kTriB = 5 * kJN * kTriMaxR;
 static_assert(kTriB >= kJN * kLStride, "Jacobi columns must fit the tridiagonal scratch");
-static_assert(kTriB >= 2 * kJWaves * kJN + kJWaves * kJN, "phase-1 scratch must fit");
+static_assert(kTriB >= 2 * kJWaves * (kJN + 1) + kJWaves * kJN, "phase-1 scratch must fit");  // (4 waves use less)
 
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ double dpp_rows_f64(double v, double old) {
@@ -635,35 +636,98 @@ __device__ __forceinline__ double start_value(int i, int m) {
 // make LDS data written by other lanes of this wave visible to the next reads of this wave
 __device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
-// number of eigenvalues of T (diagonal d, squared off-diagonal e2) below x
+// Number of eigenvalues of T below x: sign changes along the leading principal minors
+// p_i = (d_i - x) p_{i-1} - e2_{i-1} p_{i-2}.  The arrays are padded past n - 1 with
+// d = 2^200 and e2 = 0, where the minors keep their sign, so the loop runs in whole
+// blocks of four with the next block's loads in flight; an exact power-of-two rescaling
+// after each block keeps the minors in range.
 __device__ __forceinline__ int sturm_count(const double* __restrict__ d, const double* __restrict__ e2, int n,
                                            double x) {
+  // A minor that is exactly zero is counted as non-negative.  With e_{i-1} != 0 the next
+  // minor then has the opposite sign of the one before the zero, which gives the same
+  // total as the usual convention; a zero next to a split of T (e = 0) can miscount,
+  // and the caller's residual check then rejects the eigenvalue.
   double p0 = 1.0, p1 = d[0] - x;
-  if (p1 == 0.0) p1 = -0x1p-900;  // a zero minor takes the sign opposite to its predecessor
   bool neg1 = p1 < 0.0;
   int cnt = neg1 ? 1 : 0;
-  for (int i = 1; i < n; ++i) {
-    double p2 = fma(d[i] - x, p1, -e2[i - 1] * p0);
-    if (p2 == 0.0) p2 = neg1 ? 0x1p-900 : -0x1p-900;
-    const bool neg2 = p2 < 0.0;
-    cnt += (neg2 != neg1) ? 1 : 0;
-    p0 = p1;
-    p1 = p2;
-    neg1 = neg2;
-    if ((i & 3) == 3) {  // exact rescaling keeps the minors in range
-      const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(p0), fabs(p1)));
-      p0 = __builtin_amdgcn_ldexp(p0, -ex);
-      p1 = __builtin_amdgcn_ldexp(p1, -ex);
+  double dn[4], en[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    dn[t] = d[1 + t];
+    en[t] = e2[t];
+  }
+  for (int i = 1; i < n; i += 4) {
+    double dc[4], ec[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      dc[t] = dn[t];
+      ec[t] = en[t];
+      dn[t] = d[i + 4 + t];
+      en[t] = e2[i + 3 + t];
     }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const double p2 = fma(dc[t] - x, p1, -ec[t] * p0);
+      const bool neg2 = p2 < 0.0;
+      cnt += (neg2 != neg1) ? 1 : 0;
+      p0 = p1;
+      p1 = p2;
+      neg1 = neg2;
+    }
+    const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(p0), fabs(p1)));
+    p0 = __builtin_amdgcn_ldexp(p0, -ex);
+    p1 = __builtin_amdgcn_ldexp(p1, -ex);
   }
   return cnt;
+}
+
+// Householder step helpers: a wave owns the columns j0, j0 + 4, ... (S slots, slots past
+// the last column map to the zero padding column kJN).  hh_matvec returns this lane's
+// partial (A v)_lane and keeps the A entries for hh_update, which applies
+// A <- A - v w^T - w v^T to the same entries.
+constexpr int kP1Waves = 4;
+constexpr int kP1Slots = kJN / kP1Waves;
+template <int S>
+__device__ __forceinline__ double hh_matvec(const double* __restrict__ Am, const double* __restrict__ myvw,
+                                            int lane, int j0, double (&av)[kP1Slots]) {
+  double vv[S];
+#pragma unroll
+  for (int t = 0; t < S; ++t) {
+    const int j = j0 + kP1Waves * t;
+    const int jj = j < kJN ? j : kJN;
+    av[t] = Am[lane * kAStride + jj];
+    vv[t] = myvw[jj * 2];
+  }
+  double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+  for (int t = 0; t < S; t += 2) {
+    a0 = fma(av[t], vv[t], a0);
+    a1 = fma(av[t + 1], vv[t + 1], a1);
+  }
+  return a0 + a1;
+}
+template <int S>
+__device__ __forceinline__ void hh_update(double* __restrict__ Am, const double* __restrict__ myvw, int lane,
+                                          int j0, const double (&av)[kP1Slots], double v, double w) {
+  double2 q[S];
+#pragma unroll
+  for (int t = 0; t < S; ++t) {
+    const int j = j0 + kP1Waves * t;
+    q[t] = *reinterpret_cast<const double2*>(myvw + (j < kJN ? j : kJN) * 2);
+  }
+#pragma unroll
+  for (int t = 0; t < S; ++t) {
+    const int j = j0 + kP1Waves * t;
+    Am[lane * kAStride + (j < kJN ? j : kJN)] = fma(-v, q[t].y, fma(-w, q[t].x, av[t]));
+  }
 }
 
 // Returns true (uniformly over the workgroup) when V and evals were written.
 __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n, int r, double* __restrict__ Vout,
                                             double* __restrict__ evals, double* __restrict__ Am,
                                             double* __restrict__ B) {
-  __shared__ double dS[kJN], eS[kJN], e2S[kJN], tauS[kJN], lamS[kJN], sgnS[kJN];
+  constexpr int kPad = kJN + 8;  // tridiagonal arrays padded for the blocked Sturm loop
+  __shared__ double dS[kPad], eS[kPad], e2S[kPad], tauS[kJN], lamS[kJN];
   __shared__ double bounds[3];
   __shared__ unsigned long long ebits, rbits;
   const int tid = threadIdx.x;
@@ -673,7 +737,11 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
   const double dmax = wave_max_f64(lane < n ? fabs(M[lane * n + lane]) : 0.0);
   if (!(dmax > 0.0) || !(dmax < 1e300)) return false;  // zero or non-finite: Jacobi path
   const int ex = __builtin_amdgcn_frexp_exp(dmax);
+  constexpr int kVW = kJN + 1;                 // per-wave (v, w) copies; entry kJN stays (0, 0)
+  double* vw = B;                              // [wave][kVW][2]
+  double* part = B + 2 * kP1Waves * kVW;       // [wave][row]
   for (int idx = tid; idx < kJN * kAStride; idx += kJThreads) Am[idx] = 0.0;
+  for (int idx = tid; idx < 2 * kP1Waves * kVW; idx += kJThreads) vw[idx] = 0.0;
   if (tid == 0) {
     ebits = 0;
     rbits = 0;
@@ -684,55 +752,74 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
     Am[i * kAStride + j] = __builtin_amdgcn_ldexp(M[idx], -ex);
   }
   __syncthreads();
-  // ---- 1. Householder tridiagonalisation.  Column j of the trailing block belongs to wave
-  //         j mod 8 (matrix-vector product and update); v and w travel through a per-wave
-  //         copy in LDS, so only the partial products need a barrier.
-  double* vw = B;                           // [wave][row][2]: (v_j, w_j)
-  double* part = B + 2 * kJWaves * kJN;     // [wave][row]
+  // ---- 1. Householder tridiagonalisation on four waves (one per SIMD: the step is bound by
+  //         instruction issue, and the reflector is computed redundantly by every wave).
+  //         Column j of the trailing block belongs to wave j mod 4; v and w travel through a
+  //         per-wave copy in LDS, so only the partial products need a barrier.  Rows and
+  //         columns past n are zero and carry v = w = 0, and a column slot past the last real
+  //         column maps to the zero padding column kJN, so the slots of a wave are unrolled
+  //         without bounds tests and their loads are issued together.
   for (int k = 0; k + 2 < n; ++k) {
+    const bool worker = wv < kP1Waves;
     const bool live = lane > k && lane < n;
-    const double x = live ? Am[lane * kAStride + k] : 0.0;
-    const double sigma = wave_sum_f64((lane > k + 1 && lane < n) ? x * x : 0.0);
-    const double alpha = readlane_f64(x, k + 1);
-    double tk = 0.0, ek = alpha, v = (lane == k + 1) ? 1.0 : 0.0;
-    const int j0 = k + 1 + ((wv - (k + 1)) % kJWaves + kJWaves) % kJWaves;
-    if (sigma != 0.0) {
-      // H x = beta e_1 with beta = -sign(alpha) mu, mu = |x|; tau = 1 + |alpha| / mu and
-      // v = x / (alpha - beta) = sign(alpha) x / (|alpha| + mu), v_{k+1} = 1
-      const double s2 = fma(alpha, alpha, sigma);
-      const double rs = rsq_refined(s2);
-      const double mu = s2 * rs;
-      ek = alpha >= 0.0 ? -mu : mu;
-      tk = fma(fabs(alpha), rs, 1.0);
-      const double sc = (alpha >= 0.0 ? 1.0 : -1.0) * rcp_refined(fabs(alpha) + mu);
-      if (lane > k + 1 && lane < n) v = x * sc;
-      vw[(wv * kJN + lane) * 2] = v;
-      wave_lds_sync();
+    double x = 0.0, sigma = 0.0, alpha = 0.0, tk = 0.0, ek = 0.0, v = 0.0;
+    const int j0 = k + 1 + ((wv - (k + 1)) % kP1Waves + kP1Waves) % kP1Waves;
+    const int span = n - (k + 1);  // live columns; a wave owns at most ceil(span / 4)
+    double* myvw = vw + wv * kVW * 2;
+    double av[kP1Slots];
+    if (worker) {
+      x = live ? Am[lane * kAStride + k] : 0.0;
+      sigma = wave_sum_f64((lane > k + 1 && lane < n) ? x * x : 0.0);
+      alpha = readlane_f64(x, k + 1);
+      ek = alpha;
+      v = (lane == k + 1) ? 1.0 : 0.0;
       double acc = 0.0;
-      for (int j = j0; j < n; j += kJWaves) acc = fma(Am[lane * kAStride + j], vw[(wv * kJN + j) * 2], acc);
+      if (sigma != 0.0) {
+        // H x = beta e_1 with beta = -sign(alpha) mu, mu = |x|; tau = 1 + |alpha| / mu and
+        // v = x / (alpha - beta) = sign(alpha) x / (|alpha| + mu), v_{k+1} = 1
+        const double s2 = fma(alpha, alpha, sigma);
+        const double rs = rsq_refined(s2);
+        const double mu = s2 * rs;
+        ek = alpha >= 0.0 ? -mu : mu;
+        tk = fma(fabs(alpha), rs, 1.0);
+        const double sc = (alpha >= 0.0 ? 1.0 : -1.0) * rcp_refined(fabs(alpha) + mu);
+        if (lane > k + 1 && lane < n) v = x * sc;
+        myvw[lane * 2] = v;
+        wave_lds_sync();
+        if (span > 32)
+          acc = hh_matvec<kP1Slots>(Am, myvw, lane, j0, av);
+        else if (span > 16)
+          acc = hh_matvec<kP1Slots / 2>(Am, myvw, lane, j0, av);
+        else
+          acc = hh_matvec<kP1Slots / 4>(Am, myvw, lane, j0, av);
+      }
       part[wv * kJN + lane] = acc;
-      __syncthreads();
-      double p = 0.0;
-#pragma unroll
-      for (int w2 = 0; w2 < kJWaves; ++w2) p += part[w2 * kJN + lane];
-      p = live ? tk * p : 0.0;
-      const double K = 0.5 * tk * wave_sum_f64(p * v);
-      const double w = fma(-K, v, p);
-      vw[(wv * kJN + lane) * 2 + 1] = w;
-      wave_lds_sync();
-      if (lane < n)
-        for (int j = j0; j < n; j += kJWaves) {
-          const double2 q = *reinterpret_cast<const double2*>(vw + (wv * kJN + j) * 2);
-          double* a = Am + lane * kAStride + j;
-          *a = fma(-v, q.y, fma(-w, q.x, *a));
-        }
     }
-    if (wv == 0) {
-      if (lane > k + 1 && lane < n) Am[lane * kAStride + k] = v;  // Householder vector below the subdiagonal
-      if (lane == 0) {
-        tauS[k] = tk;
-        eS[k] = ek;
-        dS[k] = Am[k * kAStride + k];
+    __syncthreads();
+    if (worker) {
+      if (sigma != 0.0) {
+        double p = 0.0;
+#pragma unroll
+        for (int w2 = 0; w2 < kP1Waves; ++w2) p += part[w2 * kJN + lane];
+        p = live ? tk * p : 0.0;
+        const double K = 0.5 * tk * wave_sum_f64(p * v);
+        const double w = fma(-K, v, p);
+        myvw[lane * 2 + 1] = w;
+        wave_lds_sync();
+        if (span > 32)
+          hh_update<kP1Slots>(Am, myvw, lane, j0, av, v, w);
+        else if (span > 16)
+          hh_update<kP1Slots / 2>(Am, myvw, lane, j0, av, v, w);
+        else
+          hh_update<kP1Slots / 4>(Am, myvw, lane, j0, av, v, w);
+      }
+      if (wv == 0) {
+        if (lane > k + 1 && lane < n) Am[lane * kAStride + k] = v;  // Householder vector below the subdiagonal
+        if (lane == 0) {
+          tauS[k] = tk;
+          eS[k] = ek;
+          dS[k] = Am[k * kAStride + k];
+        }
       }
     }
     __syncthreads();
@@ -743,7 +830,11 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
     dS[n - 1] = Am[(n - 1) * kAStride + n - 1];
   }
   __syncthreads();
-  if (tid < n) e2S[tid] = (tid < n - 1) ? eS[tid] * eS[tid] : 0.0;
+  for (int i = tid; i < kPad; i += kJThreads) {
+    if (i >= n) dS[i] = 0x1p200;  // padding: the minors keep their sign (see sturm_count)
+    e2S[i] = (i < n - 1) ? eS[i] * eS[i] : 0.0;
+    if (i >= n - 1) eS[i] = 0.0;
+  }
   if (wv == 0) {
     // Gershgorin interval and |T|
     const double el = (lane > 0 && lane < n) ? fabs(eS[lane - 1]) : 0.0;
@@ -761,7 +852,7 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
   }
   __syncthreads();
   // ---- 2. multisection: group g brackets the g-th largest eigenvalue
-  {
+  if (tid < kMsGroup * kTriMaxR) {
     const int g = tid / kMsGroup, sub = tid % kMsGroup;
     const int target = n - 1 - g;  // count(x) > target  <=>  x above the g-th largest
     double a = bounds[0], b = bounds[1];
@@ -770,7 +861,8 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
       const double wd = b - a;
       const int cnt = (g < r) ? sturm_count(dS, e2S, n, fma(wd, cl, a)) : 0;
       const unsigned long long bal = __ballot(cnt > target);
-      const unsigned bits = static_cast<unsigned>(bal >> (kMsGroup * (g % (kWave / kMsGroup)))) & 0xFFFFu;
+      const unsigned bits =
+          static_cast<unsigned>(bal >> (kMsGroup * (g % (kWave / kMsGroup)))) & ((1u << kMsGroup) - 1u);
       const int l = bits ? __builtin_ctz(bits) : kMsGroup;
       const double na = (l == 0) ? a : fma(wd, static_cast<double>(l) / (kMsGroup + 1), a);
       const double nb = (l == kMsGroup) ? b : fma(wd, static_cast<double>(l + 1) / (kMsGroup + 1), a);
@@ -780,59 +872,54 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
     if (g < r && sub == 0) lamS[g] = 0.5 * (a + b);
   }
   __syncthreads();
-  // ---- 3. inverse iteration, lane m of wave 0 for eigenvalue m
+  // ---- 3. inverse iteration, lane m of wave 0 for eigenvalue m.  Loops run over rows with
+  //         the row data for the next iterations loaded ahead (unrolled by four).
   auto F = [&](int f, int i, int m) -> double& { return B[(f * kJN + i) * kTriMaxR + m]; };
   constexpr int IU0 = 0, U1 = 1, U2 = 2, ML = 3, ZZ = 4;
   if (wv == 0 && lane < r) {
     const int m = lane;
     const double lm = lamS[m];
     const double pert = 2.220446049250313e-16 * bounds[2];
-    const auto clampp = [&](double u) { return fabs(u) >= pert ? u : (u < 0.0 ? -pert : pert); };
-    double cd = dS[0] - lm, cs = (n > 1) ? eS[0] : 0.0;
+    const double rpert = 1.0 / pert;
+    double cd = dS[0] - lm, cs = eS[0];
     unsigned long long piv = 0;
+#pragma unroll 4
     for (int i = 0; i + 1 < n; ++i) {
-      const double sb = eS[i], nd = dS[i + 1] - lm, ns = (i + 2 < n) ? eS[i + 1] : 0.0;
-      if (fabs(sb) > fabs(cd)) {  // swap rows i and i + 1
-        piv |= 1ull << i;
-        const double u0 = clampp(sb);
-        const double ri = rcp_refined(u0);
-        const double mm = cd * ri;
-        F(IU0, i, m) = ri;
-        F(U1, i, m) = nd;
-        F(U2, i, m) = ns;
-        F(ML, i, m) = mm;
-        cd = fma(-mm, nd, cs);
-        cs = -mm * ns;
-      } else {
-        const double u0 = clampp(cd);
-        const double ri = rcp_refined(u0);
-        const double mm = sb * ri;
-        F(IU0, i, m) = ri;
-        F(U1, i, m) = cs;
-        F(U2, i, m) = 0.0;
-        F(ML, i, m) = mm;
-        cd = fma(-mm, cs, nd);
-        cs = ns;
-      }
+      const double sb = eS[i], nd = dS[i + 1] - lm, ns = eS[i + 1];  // eS is zero past n - 2
+      const bool sw = fabs(sb) > fabs(cd);
+      const double u0 = sw ? sb : cd;
+      double ri = rcp_refined(u0);
+      if (!(fabs(u0) >= pert)) ri = (u0 < 0.0) ? -rpert : rpert;  // tiny pivot raised to eps |T|
+      const double mm = (sw ? cd : sb) * ri;
+      F(IU0, i, m) = ri;
+      F(U1, i, m) = sw ? nd : cs;
+      F(U2, i, m) = sw ? ns : 0.0;
+      F(ML, i, m) = mm;
+      const double ncd = sw ? fma(-mm, nd, cs) : fma(-mm, cs, nd);
+      cs = sw ? -mm * ns : ns;
+      cd = ncd;
+      piv |= static_cast<unsigned long long>(sw) << i;
     }
-    F(IU0, n - 1, m) = rcp_refined(clampp(cd));
-    F(U1, n - 1, m) = 0.0;
-    F(U2, n - 1, m) = 0.0;
+    {
+      double ri = rcp_refined(cd);
+      if (!(fabs(cd) >= pert)) ri = (cd < 0.0) ? -rpert : rpert;
+      F(IU0, n - 1, m) = ri;
+      F(U1, n - 1, m) = 0.0;
+      F(U2, n - 1, m) = 0.0;
+    }
     for (int i = 0; i < n; ++i) F(ZZ, i, m) = start_value(i, m);
     for (int it = 0; it < kInvIters; ++it) {
       double yi = F(ZZ, 0, m);
+#pragma unroll 4
       for (int i = 0; i + 1 < n; ++i) {
         const double yn = F(ZZ, i + 1, m), mm = F(ML, i, m);
-        if ((piv >> i) & 1ull) {
-          F(ZZ, i, m) = yn;
-          yi = fma(-mm, yn, yi);
-        } else {
-          F(ZZ, i, m) = yi;
-          yi = fma(-mm, yi, yn);
-        }
+        const bool sw = (piv >> i) & 1ull;
+        F(ZZ, i, m) = sw ? yn : yi;
+        yi = sw ? fma(-mm, yn, yi) : fma(-mm, yi, yn);
       }
       F(ZZ, n - 1, m) = yi;
       double z1 = 0.0, z2 = 0.0, mx = 0.0;
+#pragma unroll 4
       for (int i = n - 1; i >= 0; --i) {
         const double zi = fma(-F(U1, i, m), z1, fma(-F(U2, i, m), z2, F(ZZ, i, m))) * F(IU0, i, m);
         F(ZZ, i, m) = zi;
@@ -841,61 +928,45 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
         mx = fmax(mx, fabs(zi));
       }
       const int ez = (mx > 0.0) ? __builtin_amdgcn_frexp_exp(mx) : 0;
+#pragma unroll 4
       for (int i = 0; i < n; ++i) F(ZZ, i, m) = __builtin_amdgcn_ldexp(F(ZZ, i, m), -ez);
     }
-    double ss = 0.0;
-    for (int i = 0; i < n; ++i) ss = fma(F(ZZ, i, m), F(ZZ, i, m), ss);
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll 4
+    for (int i = 0; i < n; ++i) {
+      const double zi = F(ZZ, i, m);
+      if (i & 1) s1 = fma(zi, zi, s1); else s0 = fma(zi, zi, s0);
+    }
+    const double ss = s0 + s1;
     const double inv = (ss > 0.0) ? rsq_refined(ss) : 0.0;
+#pragma unroll 4
     for (int i = 0; i < n; ++i) F(ZZ, i, m) *= inv;
   }
   __syncthreads();
-  // ---- 4. Loewdin orthonormalisation of Z, residual check, back-transformation
-  double* E = B;                          // r x r, stride kEStride (inverse-iteration factors are dead now)
+  // ---- 4. orthogonality check E = Z^T Z - I (upper triangle) and residual check
+  double* E = B;                          // r x r, stride kEStride (the LU factors are dead now)
   double* Fm = B + kTriMaxR * kEStride;   // I - E/2 + 3 E^2 / 8
   double emax = 0.0;
   for (int q = tid; q < r * r; q += kJThreads) {
     const int a = q / r, c = q - (q / r) * r;
-    double s0 = 0.0, s1 = 0.0;
+    if (c < a) continue;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int i = 0;
-    for (; i + 1 < n; i += 2) {
+#pragma unroll 2
+    for (; i + 3 < n; i += 4) {
       s0 = fma(F(ZZ, i, a), F(ZZ, i, c), s0);
       s1 = fma(F(ZZ, i + 1, a), F(ZZ, i + 1, c), s1);
+      s2 = fma(F(ZZ, i + 2, a), F(ZZ, i + 2, c), s2);
+      s3 = fma(F(ZZ, i + 3, a), F(ZZ, i + 3, c), s3);
     }
-    if (i < n) s0 = fma(F(ZZ, i, a), F(ZZ, i, c), s0);
-    const double eac = (s0 + s1) - (a == c ? 1.0 : 0.0);
+    for (; i < n; ++i) s0 = fma(F(ZZ, i, a), F(ZZ, i, c), s0);
+    const double eac = ((s0 + s1) + (s2 + s3)) - (a == c ? 1.0 : 0.0);
     E[a * kEStride + c] = eac;
+    E[c * kEStride + a] = eac;
     emax = fmax(emax, fabs(eac));
   }
-  if (!(emax <= 1.0)) emax = 1.0;  // NaN or large: reject below
-  atomicMax(&ebits, static_cast<unsigned long long>(__double_as_longlong(emax)));
-  __syncthreads();
-  for (int q = tid; q < r * r; q += kJThreads) {
-    const int a = q / r, c = q - (q / r) * r;
-    double s = 0.0;
-    for (int b2 = 0; b2 < r; ++b2) s = fma(E[a * kEStride + b2], E[b2 * kEStride + c], s);
-    Fm[a * kEStride + c] = fma(0.375, s, fma(-0.5, E[a * kEStride + c], a == c ? 1.0 : 0.0));
-  }
-  __syncthreads();
   constexpr int kPer = (kJN * kTriMaxR + kJThreads - 1) / kJThreads;
-  double zn[kPer];
-#pragma unroll
-  for (int t = 0; t < kPer; ++t) {
-    const int q = tid + t * kJThreads;
-    const int i = q / kTriMaxR, m = q % kTriMaxR;
-    double s = 0.0;
-    if (i < n && m < r)
-      for (int c = 0; c < r; ++c) s = fma(F(ZZ, i, c), Fm[c * kEStride + m], s);
-    zn[t] = s;
-  }
-  __syncthreads();
   double rmax = 0.0;
-#pragma unroll
-  for (int t = 0; t < kPer; ++t) {
-    const int q = tid + t * kJThreads;
-    const int i = q / kTriMaxR, m = q % kTriMaxR;
-    if (i < n && m < r) F(ZZ, i, m) = zn[t];
-  }
-  __syncthreads();
 #pragma unroll
   for (int t = 0; t < kPer; ++t) {
     const int q = tid + t * kJThreads;
@@ -907,13 +978,45 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
       rmax = fmax(rmax, fabs(tz));
     }
   }
+  if (!(emax <= 1.0)) emax = 1.0;  // NaN or large: rejected below
   if (!(rmax <= 1.0)) rmax = 1.0;
+  atomicMax(&ebits, static_cast<unsigned long long>(__double_as_longlong(emax)));
   atomicMax(&rbits, static_cast<unsigned long long>(__double_as_longlong(rmax)));
   __syncthreads();
   const double em = __longlong_as_double(static_cast<long long>(ebits));
   const double rm = __longlong_as_double(static_cast<long long>(rbits));
   if (!(em <= 1e-6 && rm <= 1e-12 * bounds[2])) return false;  // uniform
-  // V = H_0 ... H_{n-3} Z: 16 lanes per column, 4 rows per lane, reflectors applied last to first
+  if (em > 32.0 * 2.220446049250313e-16) {
+    // one Loewdin step Z <- Z (I - E/2 + 3 E^2 / 8): orthonormal to O(|E|^3)
+    for (int q = tid; q < r * r; q += kJThreads) {
+      const int a = q / r, c = q - (q / r) * r;
+      double sacc = 0.0;
+      for (int b2 = 0; b2 < r; ++b2) sacc = fma(E[a * kEStride + b2], E[b2 * kEStride + c], sacc);
+      Fm[a * kEStride + c] = fma(0.375, sacc, fma(-0.5, E[a * kEStride + c], a == c ? 1.0 : 0.0));
+    }
+    __syncthreads();
+    double zn[kPer];
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const int q = tid + t * kJThreads;
+      const int i = q / kTriMaxR, m = q % kTriMaxR;
+      double sacc = 0.0;
+      if (i < n && m < r)
+        for (int c = 0; c < r; ++c) sacc = fma(F(ZZ, i, c), Fm[c * kEStride + m], sacc);
+      zn[t] = sacc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const int q = tid + t * kJThreads;
+      const int i = q / kTriMaxR, m = q % kTriMaxR;
+      if (i < n && m < r) F(ZZ, i, m) = zn[t];
+    }
+    __syncthreads();
+  }
+  // ---- 5. V = H_0 ... H_{n-3} Z: 16 lanes per column, 4 rows per lane, reflectors applied
+  //         last to first with the next reflector's entries loaded ahead; then the sign rule
+  //         (largest |entry|, first on ties, positive) by a group argmax.
   {
     const int gm = tid / kPairLanes, sb = tid % kPairLanes;
     double zr[kPairRows];
@@ -922,46 +1025,79 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
       const int row = kPairRows * sb + t;
       zr[t] = (gm < r && row < n) ? F(ZZ, row, gm) : 0.0;
     }
-    for (int k = n - 3; k >= 0; --k) {
-      const double tk = tauS[k];
-      if (tk == 0.0) continue;
-      double vr[kPairRows];
-      double s = 0.0;
+    const auto vload = [&](int k, double (&vr)[kPairRows]) {
 #pragma unroll
       for (int t = 0; t < kPairRows; ++t) {
         const int row = kPairRows * sb + t;
-        vr[t] = (row == k + 1) ? 1.0 : ((row > k + 1 && row < n) ? Am[row * kAStride + k] : 0.0);
-        s = fma(vr[t], zr[t], s);
+        const double a = Am[row * kAStride + k];
+        vr[t] = (row == k + 1) ? 1.0 : ((row > k + 1 && row < n) ? a : 0.0);
       }
-      s = group16_sum(s);
-      const double f = tk * s;
+    };
+    double vn[kPairRows];
+    double tn = 0.0;
+    if (n >= 3) {
+      vload(n - 3, vn);
+      tn = tauS[n - 3];
+    }
+    for (int k = n - 3; k >= 0; --k) {
+      double vr[kPairRows];
+#pragma unroll
+      for (int t = 0; t < kPairRows; ++t) vr[t] = vn[t];
+      const double tk = tn;
+      if (k > 0) {
+        vload(k - 1, vn);
+        tn = tauS[k - 1];
+      }
+      double sacc = 0.0;
+#pragma unroll
+      for (int t = 0; t < kPairRows; ++t) sacc = fma(vr[t], zr[t], sacc);
+      const double f = tk * group16_sum(sacc);
 #pragma unroll
       for (int t = 0; t < kPairRows; ++t) zr[t] = fma(-f, vr[t], zr[t]);
     }
-    __syncthreads();
+    // group argmax of |entry| with the first row on ties
+    double best = -1.0;
+    int brow = kJN;
+    double bval = 0.0;
 #pragma unroll
     for (int t = 0; t < kPairRows; ++t) {
       const int row = kPairRows * sb + t;
-      if (gm < r && row < n) F(ZZ, row, gm) = zr[t];
-    }
-  }
-  __syncthreads();
-  if (tid < r) {  // sign rule: largest |entry| (first on ties) positive
-    double best = -1.0, sg = 1.0;
-    for (int i = 0; i < n; ++i) {
-      const double v = F(ZZ, i, tid);
-      if (fabs(v) > best) {
-        best = fabs(v);
-        sg = (v < 0.0) ? -1.0 : 1.0;
+      if (row < n && fabs(zr[t]) > best) {
+        best = fabs(zr[t]);
+        brow = row;
+        bval = zr[t];
       }
     }
-    sgnS[tid] = sg;
-    if (evals) evals[tid] = __builtin_amdgcn_ldexp(lamS[tid], ex);
+#define RT_STEP(CTRL)                                                        \
+  {                                                                          \
+    const double ob = dpp_f64<CTRL>(best);                                   \
+    const int orow = __builtin_amdgcn_mov_dpp(brow, CTRL, 0xF, 0xF, true);   \
+    const double ov = dpp_f64<CTRL>(bval);                                   \
+    if (ob > best || (ob == best && orow < brow)) {                          \
+      best = ob;                                                             \
+      brow = orow;                                                           \
+      bval = ov;                                                             \
+    }                                                                        \
   }
+    RT_STEP(0xB1)
+    RT_STEP(0x4E)
+    RT_STEP(0x141)
+    RT_STEP(0x140)
+#undef RT_STEP
+    const double sg = (bval < 0.0) ? -1.0 : 1.0;
+    if (gm < r) {
+#pragma unroll
+      for (int t = 0; t < kPairRows; ++t) {
+        const int row = kPairRows * sb + t;
+        if (row < n) F(ZZ, row, gm) = sg * zr[t];
+      }
+    }
+  }
+  if (evals && tid < r) evals[tid] = __builtin_amdgcn_ldexp(lamS[tid], ex);
   __syncthreads();
   for (int q = tid; q < n * r; q += kJThreads) {
     const int i = q / r, m = q - (q / r) * r;
-    Vout[q] = sgnS[m] * F(ZZ, i, m);
+    Vout[q] = F(ZZ, i, m);
   }
   return true;
 }
