@@ -586,7 +586,6 @@ constexpr int kEStride = kTriMaxR + 1;
 // per-wave vectors and partial sums of phase 1, by E and F of phase 4, and by the Jacobi L
 constexpr int kTriB = 5 * kJN * kTriMaxR;
 static_assert(kTriB >= kJN * kLStride, "Jacobi columns must fit the tridiagonal scratch");
-static_assert(kTriB >= 2 * kJWaves * (kJN + 1) + kJWaves * kJN, "phase-1 scratch must fit");  // (4 waves use less)
 
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ double dpp_rows_f64(double v, double old) {
@@ -681,46 +680,9 @@ __device__ __forceinline__ int sturm_count(const double* __restrict__ d, const d
   return cnt;
 }
 
-// Householder step helpers: a wave owns the columns j0, j0 + 4, ... (S slots, slots past
-// the last column map to the zero padding column kJN).  hh_matvec returns this lane's
-// partial (A v)_lane and keeps the A entries for hh_update, which applies
-// A <- A - v w^T - w v^T to the same entries.
 constexpr int kP1Waves = 4;
-constexpr int kP1Slots = kJN / kP1Waves;
-template <int S>
-__device__ __forceinline__ double hh_matvec(const double* __restrict__ Am, const double* __restrict__ myvw,
-                                            int lane, int j0, double (&av)[kP1Slots]) {
-  double vv[S];
-#pragma unroll
-  for (int t = 0; t < S; ++t) {
-    const int j = j0 + kP1Waves * t;
-    const int jj = j < kJN ? j : kJN;
-    av[t] = Am[lane * kAStride + jj];
-    vv[t] = myvw[jj * 2];
-  }
-  double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-  for (int t = 0; t < S; t += 2) {
-    a0 = fma(av[t], vv[t], a0);
-    a1 = fma(av[t + 1], vv[t + 1], a1);
-  }
-  return a0 + a1;
-}
-template <int S>
-__device__ __forceinline__ void hh_update(double* __restrict__ Am, const double* __restrict__ myvw, int lane,
-                                          int j0, const double (&av)[kP1Slots], double v, double w) {
-  double2 q[S];
-#pragma unroll
-  for (int t = 0; t < S; ++t) {
-    const int j = j0 + kP1Waves * t;
-    q[t] = *reinterpret_cast<const double2*>(myvw + (j < kJN ? j : kJN) * 2);
-  }
-#pragma unroll
-  for (int t = 0; t < S; ++t) {
-    const int j = j0 + kP1Waves * t;
-    Am[lane * kAStride + (j < kJN ? j : kJN)] = fma(-v, q[t].y, fma(-w, q[t].x, av[t]));
-  }
-}
+constexpr int kP1Cols = kJN / kP1Waves;  // matrix columns held in registers per wave
+static_assert(kTriB >= 3 * kP1Waves * kJN + kJN, "phase-1 scratch must fit");
 
 // Returns true (uniformly over the workgroup) when V and evals were written.
 __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n, int r, double* __restrict__ Vout,
@@ -737,41 +699,39 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
   const double dmax = wave_max_f64(lane < n ? fabs(M[lane * n + lane]) : 0.0);
   if (!(dmax > 0.0) || !(dmax < 1e300)) return false;  // zero or non-finite: Jacobi path
   const int ex = __builtin_amdgcn_frexp_exp(dmax);
-  constexpr int kVW = kJN + 1;                 // per-wave (v, w) copies; entry kJN stays (0, 0)
-  double* vw = B;                              // [wave][kVW][2]
-  double* part = B + 2 * kP1Waves * kVW;       // [wave][row]
+  // scratch in B: per-wave copies of v and w, partial products, and the published column
+  double* vbuf = B;                               // [wave][kJN]
+  double* wbuf = B + kP1Waves * kJN;              // [wave][kJN]
+  double* part = B + 2 * kP1Waves * kJN;          // [wave][kJN]
+  double* colbuf = B + 3 * kP1Waves * kJN;        // [kJN]: column k of the current matrix
   for (int idx = tid; idx < kJN * kAStride; idx += kJThreads) Am[idx] = 0.0;
-  for (int idx = tid; idx < 2 * kP1Waves * kVW; idx += kJThreads) vw[idx] = 0.0;
   if (tid == 0) {
     ebits = 0;
     rbits = 0;
   }
-  __syncthreads();
-  for (int idx = tid; idx < n * n; idx += kJThreads) {
-    const int i = idx / n, j = idx - (idx / n) * n;
-    Am[i * kAStride + j] = __builtin_amdgcn_ldexp(M[idx], -ex);
+  // ---- 1. Householder tridiagonalisation on four waves (one per SIMD).  Wave w keeps the
+  //         columns 16 w .. 16 w + 15 of the matrix in registers (lane = row) for the whole
+  //         reduction, so the matrix-vector product and the rank-2 update touch LDS only
+  //         for broadcast reads of v and w.  The owner of column k + 1 publishes it after
+  //         the update of step k; every wave then forms the reflector from it redundantly.
+  //         Rows and columns past n are zero and carry v = w = 0.
+  const bool worker = wv < kP1Waves;
+  double ar[kP1Cols];
+#pragma unroll
+  for (int t = 0; t < kP1Cols; ++t) {
+    const int j = kP1Cols * wv + t;
+    ar[t] = (worker && lane < n && j < n) ? __builtin_amdgcn_ldexp(M[lane * n + j], -ex) : 0.0;
   }
+  if (wv == 0) colbuf[lane] = ar[0];
   __syncthreads();
-  // ---- 1. Householder tridiagonalisation on four waves (one per SIMD: the step is bound by
-  //         instruction issue, and the reflector is computed redundantly by every wave).
-  //         Column j of the trailing block belongs to wave j mod 4; v and w travel through a
-  //         per-wave copy in LDS, so only the partial products need a barrier.  Rows and
-  //         columns past n are zero and carry v = w = 0, and a column slot past the last real
-  //         column maps to the zero padding column kJN, so the slots of a wave are unrolled
-  //         without bounds tests and their loads are issued together.
   for (int k = 0; k + 2 < n; ++k) {
-    const bool worker = wv < kP1Waves;
     const bool live = lane > k && lane < n;
-    double x = 0.0, sigma = 0.0, alpha = 0.0, tk = 0.0, ek = 0.0, v = 0.0;
-    const int j0 = k + 1 + ((wv - (k + 1)) % kP1Waves + kP1Waves) % kP1Waves;
-    const int span = n - (k + 1);  // live columns; a wave owns at most ceil(span / 4)
-    double* myvw = vw + wv * kVW * 2;
-    double av[kP1Slots];
+    double sigma = 0.0, tk = 0.0, v = 0.0;
     if (worker) {
-      x = live ? Am[lane * kAStride + k] : 0.0;
+      const double x = live ? colbuf[lane] : 0.0;
       sigma = wave_sum_f64((lane > k + 1 && lane < n) ? x * x : 0.0);
-      alpha = readlane_f64(x, k + 1);
-      ek = alpha;
+      const double alpha = readlane_f64(x, k + 1);
+      double ek = alpha;
       v = (lane == k + 1) ? 1.0 : 0.0;
       double acc = 0.0;
       if (sigma != 0.0) {
@@ -784,16 +744,27 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
         tk = fma(fabs(alpha), rs, 1.0);
         const double sc = (alpha >= 0.0 ? 1.0 : -1.0) * rcp_refined(fabs(alpha) + mu);
         if (lane > k + 1 && lane < n) v = x * sc;
-        myvw[lane * 2] = v;
+        double* myv = vbuf + wv * kJN;
+        myv[lane] = v;
         wave_lds_sync();
-        if (span > 32)
-          acc = hh_matvec<kP1Slots>(Am, myvw, lane, j0, av);
-        else if (span > 16)
-          acc = hh_matvec<kP1Slots / 2>(Am, myvw, lane, j0, av);
-        else
-          acc = hh_matvec<kP1Slots / 4>(Am, myvw, lane, j0, av);
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int t = 0; t < kP1Cols; t += 2) {
+          const double2 vj = *reinterpret_cast<const double2*>(myv + kP1Cols * wv + t);
+          a0 = fma(ar[t], vj.x, a0);
+          a1 = fma(ar[t + 1], vj.y, a1);
+        }
+        acc = a0 + a1;
       }
       part[wv * kJN + lane] = acc;
+      if (wv == 0) {
+        if (lane > k + 1 && lane < n) Am[lane * kAStride + k] = v;  // Householder vector below the subdiagonal
+        if (lane == 0) {
+          tauS[k] = tk;
+          eS[k] = ek;
+          dS[k] = colbuf[k];
+        }
+      }
     }
     __syncthreads();
     if (worker) {
@@ -804,30 +775,40 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
         p = live ? tk * p : 0.0;
         const double K = 0.5 * tk * wave_sum_f64(p * v);
         const double w = fma(-K, v, p);
-        myvw[lane * 2 + 1] = w;
+        const double* myv = vbuf + wv * kJN;
+        double* myw = wbuf + wv * kJN;
+        myw[lane] = w;
         wave_lds_sync();
-        if (span > 32)
-          hh_update<kP1Slots>(Am, myvw, lane, j0, av, v, w);
-        else if (span > 16)
-          hh_update<kP1Slots / 2>(Am, myvw, lane, j0, av, v, w);
-        else
-          hh_update<kP1Slots / 4>(Am, myvw, lane, j0, av, v, w);
-      }
-      if (wv == 0) {
-        if (lane > k + 1 && lane < n) Am[lane * kAStride + k] = v;  // Householder vector below the subdiagonal
-        if (lane == 0) {
-          tauS[k] = tk;
-          eS[k] = ek;
-          dS[k] = Am[k * kAStride + k];
+#pragma unroll
+        for (int t = 0; t < kP1Cols; t += 2) {
+          const double2 vj = *reinterpret_cast<const double2*>(myv + kP1Cols * wv + t);
+          const double2 wj = *reinterpret_cast<const double2*>(myw + kP1Cols * wv + t);
+          ar[t] = fma(-v, wj.x, fma(-w, vj.x, ar[t]));
+          ar[t + 1] = fma(-v, wj.y, fma(-w, vj.y, ar[t + 1]));
         }
+      }
+      // publish column k + 1 (a wave-uniform register slot)
+      if (wv == (k + 1) / kP1Cols) {
+        const int slot = (k + 1) % kP1Cols;
+        double c = ar[0];
+#pragma unroll
+        for (int t = 1; t < kP1Cols; ++t) c = (t == slot) ? ar[t] : c;
+        colbuf[lane] = c;
       }
     }
     __syncthreads();
   }
+  // the last 2 x 2 block: column n - 2 is published; A[n-1][n-1] sits with its owner
+  if (wv == (n - 1) / kP1Cols && lane == n - 1) {
+    const int slot = (n - 1) % kP1Cols;
+    double c = ar[0];
+#pragma unroll
+    for (int t = 1; t < kP1Cols; ++t) c = (t == slot) ? ar[t] : c;
+    dS[n - 1] = c;
+  }
   if (tid == 0) {
-    dS[n - 2] = Am[(n - 2) * kAStride + n - 2];
-    eS[n - 2] = Am[(n - 1) * kAStride + n - 2];
-    dS[n - 1] = Am[(n - 1) * kAStride + n - 1];
+    dS[n - 2] = colbuf[n - 2];
+    eS[n - 2] = colbuf[n - 1];
   }
   __syncthreads();
   for (int i = tid; i < kPad; i += kJThreads) {
@@ -1104,8 +1085,8 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
 
 __device__ __forceinline__ void eig_body(const double* __restrict__ M, int n, int r, double* __restrict__ Vout,
                                          double* __restrict__ evals) {
-  __shared__ double Am[kJN * kAStride];
-  __shared__ double B[kTriB];
+  __shared__ __align__(16) double Am[kJN * kAStride];
+  __shared__ __align__(16) double B[kTriB];
   if (n >= 3 && r <= kTriMaxR) {
     if (eig_tridiag(M, n, r, Vout, evals, Am, B)) return;
     __syncthreads();
