@@ -850,8 +850,8 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
         // CholeskyQR2 (tall sketch), with the Householder kernel as its fallback
         const int64_t chunks = ceil_div(t.I[n], 64);
         double* part = static_cast<double*>(c.take(static_cast<size_t>(2 * chunks) * 64 * 64 * 8));
-        double* R1 = static_cast<double*>(c.take(64 * 64 * 8));
-        double* R2 = static_cast<double*>(c.take(64 * 64 * 8));
+        double* R1 = static_cast<double*>(c.take(2 * 64 * 64 * 8));  // R1, then R1^-1
+        double* R2 = static_cast<double*>(c.take(2 * 64 * 64 * 8));  // R2, then R2^-1
         double* Q1 = static_cast<double*>(c.take(static_cast<size_t>(t.I[n]) * ncol * 8));
         int32_t* flag = static_cast<int32_t*>(c.take(sizeof(int32_t)));
         qr_cq.push_back(GCholQRJob{Ys[n], YA[n], t.I[n], YB[n], static_cast<int32_t>(ncol), part,

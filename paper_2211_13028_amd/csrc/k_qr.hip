@@ -287,81 +287,108 @@ __global__ __launch_bounds__(256) void cq_gram_kernel(TAB tab) {
     for (int v = 0; v < 4; ++v) out[(ty * 4 + u) * kCols + tx * 4 + v] = acc[u][v];
 }
 
-template <int CTRL>
-__device__ __forceinline__ double qr_dpp(double v) {
-  const int64_t u = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(u & 0xffffffff), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(u >> 32), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double((static_cast<int64_t>(hi) << 32) | static_cast<uint32_t>(lo));
-}
 
-// sum the partials (fixed order), factor G = R^T R (upper R) and invert R
+// Sum the partial Grams (fixed order), factor G = R^T R (upper R) and form R^-1: the
+// symmetric elimination on [G | I] turns the left block into R and the right block into
+// R^-T.  Four waves; thread (wave w, lane j) keeps column j of rows 16 w .. 16 w + 15 of
+// both blocks in registers for the whole factorisation, and the row that is eliminated
+// next is published through LDS (double-buffered), so a step touches LDS only for
+// broadcast reads of that row.  Every wave keeps the diagonal in registers (lane j:
+// G[j][j], updated with the same rounding as the matrix).  R goes to the first kCols^2
+// doubles of the job's R1 / R2 buffer, R^-1 to the second.
 template <typename TAB>
 __global__ __launch_bounds__(256) void cq_chol_kernel(TAB tab, int second) {
-  __shared__ double G[kCols][kCols + 1];
+  constexpr int kW = 256 / kWave;
+  constexpr int kRows = kCols / kW;
+  __shared__ __align__(16) double rowL[2][kCols];
+  __shared__ __align__(16) double rowR[2][kCols];
+  __shared__ double diag[kCols];
   __shared__ double Rs[kCols][kCols + 1];
+  __shared__ double Xs[kCols][kCols + 1];
   const CJob& J = tab[blockIdx.x];
   if (*J.flag) return;  // cleared by cq_reset_kernel before the first pass
   const int n = J.n;
+  const int lane = static_cast<int>(threadIdx.x) % kWave, wv = static_cast<int>(threadIdx.x) / kWave;
   const double* part = J.part + (second ? static_cast<int64_t>(J.chunks) * kCols * kCols : 0);
-  {
-    // sum of the chunk partials in chunk order; each thread owns 16 entries and issues
-    // the loads of two chunks at once, so a few memory latencies cover the whole sum
-    constexpr int kPer = kCols * kCols / 256;
-    double acc[kPer];
+  double gl[kRows], gr[kRows];
 #pragma unroll
-    for (int e = 0; e < kPer; ++e) acc[e] = 0.0;
+  for (int t = 0; t < kRows; ++t) gl[t] = 0.0;
+  // chunk partials in chunk order; the loads of two chunks are in flight together
 #pragma unroll 2
-    for (int c = 0; c < J.chunks; ++c) {
-      const double* pc = part + static_cast<int64_t>(c) * kCols * kCols + threadIdx.x;
-      double v[kPer];
+  for (int c = 0; c < J.chunks; ++c) {
+    const double* pc = part + static_cast<int64_t>(c) * kCols * kCols + kRows * wv * kCols + lane;
+    double v[kRows];
 #pragma unroll
-      for (int e = 0; e < kPer; ++e) v[e] = pc[256 * e];
+    for (int t = 0; t < kRows; ++t) v[t] = pc[t * kCols];
 #pragma unroll
-      for (int e = 0; e < kPer; ++e) acc[e] += v[e];
-    }
+    for (int t = 0; t < kRows; ++t) gl[t] += v[t];
+  }
 #pragma unroll
-    for (int e = 0; e < kPer; ++e) {
-      const int idx = threadIdx.x + 256 * e;
-      G[idx / kCols][idx % kCols] = acc[e];
-      Rs[idx / kCols][idx % kCols] = 0.0;
-    }
+  for (int t = 0; t < kRows; ++t) gr[t] = (kRows * wv + t == lane) ? 1.0 : 0.0;
+  for (int idx = threadIdx.x; idx < kCols * (kCols + 1); idx += 256) {
+    (&Rs[0][0])[idx] = 0.0;
+    (&Xs[0][0])[idx] = 0.0;
+  }
+  if (lane / kRows == wv) {
+    double c = gl[0];
+#pragma unroll
+    for (int t = 1; t < kRows; ++t) c = (t == lane % kRows) ? gl[t] : c;
+    diag[lane] = c;
+  }
+  if (wv == 0) {
+    rowL[0][lane] = gl[0];
+    rowR[0][lane] = gr[0];
   }
   __syncthreads();
+  double dj = (lane < n) ? diag[lane] : 0.0;
+  double dmax = dj;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, off));
   bool broke = false;
-  double dmax = 0.0;
-  for (int i = 0; i < n; ++i) dmax = fmax(dmax, G[i][i]);
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  // right-looking Cholesky, one barrier per step: row k of R = G[k][.] / sqrt(G[k][k])
-  // goes to Rs and the trailing matrix loses the outer product of that row.  Row k is
-  // only read in step k (the update touches rows and columns > k), so the barrier
-  // that ends step k is the only one needed.
   for (int k = 0; k < n; ++k) {
-    const double d = G[k][k];
-    if (!(d > 1e-13 * dmax) || !(dmax > 0.0)) {  // every thread sees the same d: uniform exit
+    const int b = k & 1;
+    const double lk = rowL[b][lane], rk = rowR[b][lane];
+    double li[kRows];
+#pragma unroll
+    for (int t = 0; t < kRows; t += 2) {
+      const double2 q = *reinterpret_cast<const double2*>(&rowL[b][kRows * wv + t]);
+      li[t] = q.x;
+      li[t + 1] = q.y;
+    }
+    const double d = __longlong_as_double(
+        (static_cast<long long>(__builtin_amdgcn_readlane(static_cast<int>(__double_as_longlong(dj) >> 32), k)) << 32) |
+        static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(__double_as_longlong(dj) & 0xffffffff), k)));
+    if (!(d > 1e-13 * dmax) || !(dmax > 0.0)) {  // uniform: every lane holds the same d
       broke = true;
       break;
     }
     const double inv_s = rsq_refined(d);
-    if (static_cast<int>(threadIdx.x) >= k && static_cast<int>(threadIdx.x) < n)
-      Rs[k][threadIdx.x] = G[k][threadIdx.x] * inv_s;
-    double li[4], lj[4], g[4][4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      li[u] = G[k][ty * 4 + u] * inv_s;
-      lj[u] = G[k][tx * 4 + u] * inv_s;
+    const double lj = lk * inv_s, xj = rk * inv_s;
+    if (wv == 0 && lane < n) {
+      if (lane >= k) Rs[k][lane] = lj;  // lane == k: d / sqrt(d)
+      Xs[lane][k] = xj;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) g[u][v] = G[ty * 4 + u][tx * 4 + v];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = ty * 4 + u, j = tx * 4 + v;
-        if (i > k && j > k) G[i][j] = fma(-li[u], lj[v], g[u][v]);
+    for (int t = 0; t < kRows; ++t) {
+      if (kRows * wv + t > k) {
+        const double mult = li[t] * inv_s;
+        gl[t] = fma(-mult, lj, gl[t]);
+        gr[t] = fma(-mult, xj, gr[t]);
       }
+    }
+    if (lane > k) dj = fma(-lj, lj, dj);
+    const int nk = k + 1;
+    if (nk < n && wv == nk / kRows) {
+      const int slot = nk % kRows;
+      double cl = gl[0], cr = gr[0];
+#pragma unroll
+      for (int t = 1; t < kRows; ++t) {
+        cl = (t == slot) ? gl[t] : cl;
+        cr = (t == slot) ? gr[t] : cr;
+      }
+      rowL[nk & 1][lane] = cl;
+      rowR[nk & 1][lane] = cr;
+    }
     __syncthreads();
   }
   if (broke) {
@@ -371,56 +398,73 @@ __global__ __launch_bounds__(256) void cq_chol_kernel(TAB tab, int second) {
   double* R = second ? J.R2 : J.R1;
   for (int idx = threadIdx.x; idx < kCols * kCols; idx += 256) {
     const int i = idx / kCols, j = idx % kCols;
-    R[idx] = (i < n && j < n && j >= i) ? Rs[i][j] : 0.0;
+    const bool in = i < n && j < n && j >= i;
+    R[idx] = in ? Rs[i][j] : 0.0;
+    R[kCols * kCols + idx] = in ? Xs[i][j] : 0.0;
   }
   if (second && J.Rout) {
-    // R = R2 R1 with R1 staged in LDS (the Gram array is free now)
-    for (int idx = threadIdx.x; idx < n * kCols; idx += 256) G[idx / kCols][idx % kCols] = J.R1[idx];
+    // R = R2 R1 with R1 staged in LDS (the inverse array is free now)
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < n * kCols; idx += 256) Xs[idx / kCols][idx % kCols] = J.R1[idx];
     __syncthreads();
     for (int idx = threadIdx.x; idx < n * n; idx += 256) {
       const int i = idx / n, j = idx % n;
-      double s = 0.0;
-      for (int t = i; t <= j; ++t) s = fma(Rs[i][t], G[t][j], s);
-      J.Rout[idx] = (j >= i) ? s : 0.0;
+      double s0 = 0.0, s1 = 0.0;
+      int t = i;
+      for (; t + 1 <= j; t += 2) {
+        s0 = fma(Rs[i][t], Xs[t][j], s0);
+        s1 = fma(Rs[i][t + 1], Xs[t + 1][j], s1);
+      }
+      if (t <= j) s0 = fma(Rs[i][t], Xs[t][j], s0);
+      J.Rout[idx] = (j >= i) ? s0 + s1 : 0.0;
     }
   }
 }
 
-// 64 rows of Q = Y R^-1 per workgroup by forward substitution q R = y, four lanes
-// per row sharing each dot product (quad DPP sums); the first pass also stores Q1
-// and the partial Gram of its rows
+// 64 rows of Q = Y R^-1 per workgroup as a product with the explicit inverse from
+// cq_chol_kernel (4 x 4 outputs per thread); the first pass also stores Q1 and the
+// partial Gram of its rows
 template <typename TY, typename TAB>
 __global__ __launch_bounds__(256) void cq_apply_kernel(TAB tab, int second) {
-  __shared__ double sy[kGramRows][kCols + 1];
-  __shared__ double sr[kCols][kCols + 1];
-  __shared__ double rinv[kCols];
+  constexpr int kS = kCols + 2;  // even row stride keeps the double2 reads aligned
+  __shared__ __align__(16) double sy[kGramRows][kS];
+  __shared__ __align__(16) double sx[kCols][kS];
   const CJob& J = tab[blockIdx.y];
   if (static_cast<int>(blockIdx.x) >= J.chunks) return;
   if (*J.flag) return;
   const int n = J.n;
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kGramRows;
-  const double* Rg = second ? J.R2 : J.R1;
+  const double* Xg = (second ? J.R2 : J.R1) + kCols * kCols;
   for (int idx = threadIdx.x; idx < kGramRows * kCols; idx += 256) {
     const int rr = idx / kCols, j = idx % kCols;
     const int64_t r = r0 + rr;
     double v = 0.0;
     if (r < J.m && j < n) v = second ? J.Q1[r * n + j] : cq_src<TY>(J, r, j);
     sy[rr][j] = v;
-    sr[rr][j] = Rg[idx];
+    sx[rr][j] = Xg[idx];
   }
   __syncthreads();
-  if (static_cast<int>(threadIdx.x) < n) rinv[threadIdx.x] = 1.0 / sr[threadIdx.x][threadIdx.x];
-  __syncthreads();
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   {
-    const int rr = threadIdx.x / 4, qd = threadIdx.x % 4;
-    for (int j = 0; j < n; ++j) {
-      double s = 0.0;
-      for (int t = qd; t < j; t += 4) s = fma(sy[rr][t], sr[t][j], s);
-      s += qr_dpp<0xB1>(s);  // quad_perm [1,0,3,2]
-      s += qr_dpp<0x4E>(s);  // quad_perm [2,3,0,1]
-      if (qd == 0) sy[rr][j] = (sy[rr][j] - s) * rinv[j];
-      __builtin_amdgcn_wave_barrier();  // the quad's next step reads this value
+    double acc[4][4] = {};
+#pragma unroll 4
+    for (int t = 0; t < n; ++t) {
+      double a[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = sy[ty * 4 + u][t];
+      const double2 b0 = *reinterpret_cast<const double2*>(&sx[t][tx * 4]);
+      const double2 b1 = *reinterpret_cast<const double2*>(&sx[t][tx * 4 + 2]);
+      const double b[4] = {b0.x, b0.y, b1.x, b1.y};
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
     }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sy[ty * 4 + u][tx * 4 + v] = acc[u][v];
   }
   __syncthreads();
   double* out = second ? J.Q : J.Q1;
@@ -430,18 +474,17 @@ __global__ __launch_bounds__(256) void cq_apply_kernel(TAB tab, int second) {
     if (r < J.m && j < n) out[r * n + j] = sy[rr][j];
   }
   if (second) return;
-  // partial Gram of these Q1 rows for the second pass (rows past m are zero)
-  for (int idx = threadIdx.x; idx < kGramRows * kCols; idx += 256) {
-    const int rr = idx / kCols, j = idx % kCols;
-    if (r0 + rr >= J.m || j >= n) sy[rr][j] = 0.0;
-  }
-  __syncthreads();
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  // partial Gram of these Q1 rows for the second pass (rows past m and columns past n
+  // are zero: the inputs there were zero)
   double g[4][4] = {};
+#pragma unroll 4
   for (int rr = 0; rr < kGramRows; ++rr) {
-    double a[4], b[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) { a[u] = sy[rr][ty * 4 + u]; b[u] = sy[rr][tx * 4 + u]; }
+    const double2 a0 = *reinterpret_cast<const double2*>(&sy[rr][ty * 4]);
+    const double2 a1 = *reinterpret_cast<const double2*>(&sy[rr][ty * 4 + 2]);
+    const double2 b0 = *reinterpret_cast<const double2*>(&sy[rr][tx * 4]);
+    const double2 b1 = *reinterpret_cast<const double2*>(&sy[rr][tx * 4 + 2]);
+    const double a[4] = {a0.x, a0.y, a1.x, a1.y};
+    const double b[4] = {b0.x, b0.y, b1.x, b1.y};
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -608,8 +651,8 @@ hipError_t qr_plan(const QRJob* jobs, int count, rt_dtype ydt, bool launch, Bump
       J.Y = M.src; J.A = M.A; J.m = M.m; J.B = M.B; J.n = M.n;
       J.chunks = static_cast<int32_t>(ceil_div(M.m, kGramRows));
       J.part = static_cast<double*>(ws.take(2 * static_cast<size_t>(J.chunks) * kCols * kCols * sizeof(double)));
-      J.R1 = static_cast<double*>(ws.take(kCols * kCols * sizeof(double)));
-      J.R2 = static_cast<double*>(ws.take(kCols * kCols * sizeof(double)));
+      J.R1 = static_cast<double*>(ws.take(2 * kCols * kCols * sizeof(double)));  // R1, then R1^-1
+      J.R2 = static_cast<double*>(ws.take(2 * kCols * kCols * sizeof(double)));  // R2, then R2^-1
       J.Q1 = static_cast<double*>(ws.take(static_cast<size_t>(M.m) * M.n * sizeof(double)));
       J.flag = static_cast<int32_t*>(ws.take(sizeof(int32_t)));
       J.Q = M.Q; J.Rout = M.R;

@@ -212,8 +212,8 @@ struct GCholQRJob {
   int32_t n;
   double* part;
   int32_t chunks;
-  double* R1;
-  double* R2;
+  double* R1;  // 2 x 64 x 64: R1, then R1^-1
+  double* R2;  // 2 x 64 x 64: R2, then R2^-1
   double* Q1;
   double* Q;
   double* Rout;
