@@ -682,7 +682,7 @@ __device__ __forceinline__ int sturm_count(const double* __restrict__ d, const d
 
 constexpr int kP1Waves = 4;
 constexpr int kP1Cols = kJN / kP1Waves;  // matrix columns held in registers per wave
-static_assert(kTriB >= 3 * kP1Waves * kJN + kJN, "phase-1 scratch must fit");
+static_assert(kTriB >= 4 * kP1Waves * kJN + kJN * kJN, "phase-1 scratch must fit");
 
 // Returns true (uniformly over the workgroup) when V and evals were written.
 __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n, int r, double* __restrict__ Vout,
@@ -703,7 +703,8 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
   double* vbuf = B;                               // [wave][kJN]
   double* wbuf = B + kP1Waves * kJN;              // [wave][kJN]
   double* part = B + 2 * kP1Waves * kJN;          // [wave][kJN]
-  double* colbuf = B + 3 * kP1Waves * kJN;        // [kJN]: column k of the current matrix
+  double* colfull = B + 4 * kP1Waves * kJN;       // [kJN][kJN]: columns of the current matrix,
+                                                  // refreshed by the wave that owns the next one
   for (int idx = tid; idx < kJN * kAStride; idx += kJThreads) Am[idx] = 0.0;
   if (tid == 0) {
     ebits = 0;
@@ -712,8 +713,9 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
   // ---- 1. Householder tridiagonalisation on four waves (one per SIMD).  Wave w keeps the
   //         columns 16 w .. 16 w + 15 of the matrix in registers (lane = row) for the whole
   //         reduction, so the matrix-vector product and the rank-2 update touch LDS only
-  //         for broadcast reads of v and w.  The owner of column k + 1 publishes it after
-  //         the update of step k; every wave then forms the reflector from it redundantly.
+  //         for broadcast reads of v and w.  After the update of step k the wave that owns
+  //         column k + 1 stores its 16 columns (static register indices; the columns it does
+  //         not change keep their bits), and every wave forms the next reflector from them.
   //         Rows and columns past n are zero and carry v = w = 0.
   const bool worker = wv < kP1Waves;
   double ar[kP1Cols];
@@ -722,13 +724,16 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
     const int j = kP1Cols * wv + t;
     ar[t] = (worker && lane < n && j < n) ? __builtin_amdgcn_ldexp(M[lane * n + j], -ex) : 0.0;
   }
-  if (wv == 0) colbuf[lane] = ar[0];
+  if (wv == 0) {
+#pragma unroll
+    for (int t = 0; t < kP1Cols; ++t) colfull[t * kJN + lane] = ar[t];
+  }
   __syncthreads();
   for (int k = 0; k + 2 < n; ++k) {
     const bool live = lane > k && lane < n;
     double sigma = 0.0, tk = 0.0, v = 0.0;
     if (worker) {
-      const double x = live ? colbuf[lane] : 0.0;
+      const double x = live ? colfull[k * kJN + lane] : 0.0;
       sigma = wave_sum_f64((lane > k + 1 && lane < n) ? x * x : 0.0);
       const double alpha = readlane_f64(x, k + 1);
       double ek = alpha;
@@ -762,7 +767,7 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
         if (lane == 0) {
           tauS[k] = tk;
           eS[k] = ek;
-          dS[k] = colbuf[k];
+          dS[k] = colfull[k * kJN + k];
         }
       }
     }
@@ -787,13 +792,9 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
           ar[t + 1] = fma(-v, wj.y, fma(-w, vj.y, ar[t + 1]));
         }
       }
-      // publish column k + 1 (a wave-uniform register slot)
       if (wv == (k + 1) / kP1Cols) {
-        const int slot = (k + 1) % kP1Cols;
-        double c = ar[0];
 #pragma unroll
-        for (int t = 1; t < kP1Cols; ++t) c = (t == slot) ? ar[t] : c;
-        colbuf[lane] = c;
+        for (int t = 0; t < kP1Cols; ++t) colfull[(kP1Cols * wv + t) * kJN + lane] = ar[t];
       }
     }
     __syncthreads();
@@ -807,8 +808,8 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
     dS[n - 1] = c;
   }
   if (tid == 0) {
-    dS[n - 2] = colbuf[n - 2];
-    eS[n - 2] = colbuf[n - 1];
+    dS[n - 2] = colfull[(n - 2) * kJN + n - 2];
+    eS[n - 2] = colfull[(n - 2) * kJN + n - 1];
   }
   __syncthreads();
   for (int i = tid; i < kPad; i += kJThreads) {

@@ -291,18 +291,18 @@ __global__ __launch_bounds__(256) void cq_gram_kernel(TAB tab) {
 // Sum the partial Grams (fixed order), factor G = R^T R (upper R) and form R^-1: the
 // symmetric elimination on [G | I] turns the left block into R and the right block into
 // R^-T.  Four waves; thread (wave w, lane j) keeps column j of rows 16 w .. 16 w + 15 of
-// both blocks in registers for the whole factorisation, and the row that is eliminated
-// next is published through LDS (double-buffered), so a step touches LDS only for
-// broadcast reads of that row.  Every wave keeps the diagonal in registers (lane j:
+// both blocks in registers for the whole factorisation.  After each step the wave that
+// owns the next pivot row stores all its 16 rows to LDS (static register indices; rows
+// that are not being eliminated keep their values, so concurrent readers of the current
+// row see the same bits), and a step touches LDS only for reads of that row.  Every wave keeps the diagonal in registers (lane j:
 // G[j][j], updated with the same rounding as the matrix).  R goes to the first kCols^2
 // doubles of the job's R1 / R2 buffer, R^-1 to the second.
 template <typename TAB>
 __global__ __launch_bounds__(256) void cq_chol_kernel(TAB tab, int second) {
   constexpr int kW = 256 / kWave;
   constexpr int kRows = kCols / kW;
-  __shared__ __align__(16) double rowL[2][kCols];
-  __shared__ __align__(16) double rowR[2][kCols];
-  __shared__ double diag[kCols];
+  __shared__ __align__(16) double fullL[kCols][kCols];  // the rows of the owner of the next row
+  __shared__ __align__(16) double fullR[kCols][kCols];
   __shared__ double Rs[kCols][kCols + 1];
   __shared__ double Xs[kCols][kCols + 1];
   const CJob& J = tab[blockIdx.x];
@@ -329,29 +329,23 @@ __global__ __launch_bounds__(256) void cq_chol_kernel(TAB tab, int second) {
     (&Rs[0][0])[idx] = 0.0;
     (&Xs[0][0])[idx] = 0.0;
   }
-  if (lane / kRows == wv) {
-    double c = gl[0];
 #pragma unroll
-    for (int t = 1; t < kRows; ++t) c = (t == lane % kRows) ? gl[t] : c;
-    diag[lane] = c;
-  }
-  if (wv == 0) {
-    rowL[0][lane] = gl[0];
-    rowR[0][lane] = gr[0];
+  for (int t = 0; t < kRows; ++t) {
+    fullL[kRows * wv + t][lane] = gl[t];
+    fullR[kRows * wv + t][lane] = gr[t];
   }
   __syncthreads();
-  double dj = (lane < n) ? diag[lane] : 0.0;
+  double dj = (lane < n) ? fullL[lane][lane] : 0.0;
   double dmax = dj;
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, off));
   bool broke = false;
   for (int k = 0; k < n; ++k) {
-    const int b = k & 1;
-    const double lk = rowL[b][lane], rk = rowR[b][lane];
+    const double lk = fullL[k][lane], rk = fullR[k][lane];
     double li[kRows];
 #pragma unroll
     for (int t = 0; t < kRows; t += 2) {
-      const double2 q = *reinterpret_cast<const double2*>(&rowL[b][kRows * wv + t]);
+      const double2 q = *reinterpret_cast<const double2*>(&fullL[k][kRows * wv + t]);
       li[t] = q.x;
       li[t + 1] = q.y;
     }
@@ -379,15 +373,11 @@ __global__ __launch_bounds__(256) void cq_chol_kernel(TAB tab, int second) {
     if (lane > k) dj = fma(-lj, lj, dj);
     const int nk = k + 1;
     if (nk < n && wv == nk / kRows) {
-      const int slot = nk % kRows;
-      double cl = gl[0], cr = gr[0];
 #pragma unroll
-      for (int t = 1; t < kRows; ++t) {
-        cl = (t == slot) ? gl[t] : cl;
-        cr = (t == slot) ? gr[t] : cr;
+      for (int t = 0; t < kRows; ++t) {
+        fullL[kRows * wv + t][lane] = gl[t];
+        fullR[kRows * wv + t][lane] = gr[t];
       }
-      rowL[nk & 1][lane] = cl;
-      rowR[nk & 1][lane] = cr;
     }
     __syncthreads();
   }
