@@ -362,13 +362,13 @@ __global__ __launch_bounds__(256) void cq_chol_kernel(TAB tab, int second) {
       if (lane >= k) Rs[k][lane] = lj;  // lane == k: d / sqrt(d)
       Xs[lane][k] = xj;
     }
+    // every row is updated: rows up to k are final (R and R^-1 took them at their own
+    // step) and are never read again, so no per-row test is needed
 #pragma unroll
     for (int t = 0; t < kRows; ++t) {
-      if (kRows * wv + t > k) {
-        const double mult = li[t] * inv_s;
-        gl[t] = fma(-mult, lj, gl[t]);
-        gr[t] = fma(-mult, xj, gr[t]);
-      }
+      const double mult = li[t] * inv_s;
+      gl[t] = fma(-mult, lj, gl[t]);
+      gr[t] = fma(-mult, xj, gr[t]);
     }
     if (lane > k) dj = fma(-lj, lj, dj);
     const int nk = k + 1;
