@@ -166,6 +166,34 @@ void sketch_impl(Ctx& c, const Ten& X, const double* const* phi, const int64_t* 
   Z.dims = X.dims; Z.dims[L] = s[L]; Z.dt = ct; Z.p = nullptr;
   W.dims = X.dims; W.dims[S] = s[S]; W.dt = ct; W.p = nullptr;
   const int64_t A0 = X.before(S), P = X.dims[S], Q = X.dims[L];
+  // the small contractions of the tree run on matrix cores when the node is binary32;
+  // their padded operands are rounded now, in the same batched launch as the sketch's
+  std::vector<const void*> opm(d, nullptr);
+  const auto tree_kind = [&](const std::vector<int64_t>& dims, int k, bool& mf, bool& last) {
+    int64_t Ab = 1, Bb = 1;
+    for (int i = 0; i < k; ++i) Ab *= dims[i];
+    for (int i = k + 1; i < d; ++i) Bb *= dims[i];
+    mf = ct == RT_F32 && ttm_mfma_ok(RT_F32, Ab, dims[k], Bb, s[k]);
+    last = ct == RT_F32 && !mf && Bb == 1 && ttm_mfma_last_ok(Ab, dims[k], s[k]);
+  };
+  const auto chain_of = [&](int n) {
+    std::vector<int> chain;
+    if (n < S) chain.push_back(L);
+    for (int k = 0; k < S; ++k)
+      if (k != n) chain.push_back(k);
+    return chain;
+  };
+  for (int n = 0; n < d; ++n) {
+    if (!(mask >> n & 1u)) continue;
+    std::vector<int64_t> dims = (n == S) ? Z.dims : W.dims;
+    for (int k : chain_of(n)) {
+      bool mf = false, last = false;
+      tree_kind(dims, k, mf, last);
+      if ((mf || last) && !opm[k])
+        opm[k] = prep(c, phi ? phi[k] : nullptr, s[k], dims[k], false, X.dt, RT_F32, ttm_mfma_mpad(s[k]));
+      dims[k] = s[k];
+    }
+  }
   if (sketch_zw_ok(X.dt, s[S], s[L])) {
     const ZWPlan plan = sketch_zw_plan(X.dt, A0, P, Q, s[S], s[L], needZ, needW);
     if (needZ) Z.p = c.take(static_cast<size_t>(Z.numel()) * dtype_size(ct));
@@ -186,12 +214,10 @@ void sketch_impl(Ctx& c, const Ten& X, const double* const* phi, const int64_t* 
     if (needZ) Z = ttm(c, X, L, op[L], s[L]);
     if (needW) W = ttm(c, X, S, op[S], s[S]);
   }
-  // the small contractions of the tree: on matrix cores when the node is binary32
-  std::vector<const void*> opm(d, nullptr);
   auto tree_ttm = [&](const Ten& cur, int k) -> Ten {
     const int64_t Ab = cur.before(k), K = cur.dims[k], Bb = cur.after(k), m = s[k];
-    const bool mf = ct == RT_F32 && ttm_mfma_ok(RT_F32, Ab, K, Bb, m);
-    const bool last = ct == RT_F32 && !mf && Bb == 1 && ttm_mfma_last_ok(Ab, K, m);
+    bool mf = false, last = false;
+    tree_kind(cur.dims, k, mf, last);
     if (!mf && !last) return ttm(c, cur, k, op[k], m);
     if (!opm[k]) opm[k] = prep(c, phi ? phi[k] : nullptr, m, K, false, X.dt, RT_F32, ttm_mfma_mpad(m));
     Ten o;
@@ -215,11 +241,7 @@ void sketch_impl(Ctx& c, const Ten& X, const double* const* phi, const int64_t* 
   for (int n = 0; n < d; ++n) {
     if (!(mask >> n & 1u)) continue;
     Ten cur = (n == S) ? Z : W;
-    std::vector<int> chain;
-    if (n < S) chain.push_back(L);
-    for (int k = 0; k < S; ++k)
-      if (k != n) chain.push_back(k);
-    for (int k : chain) cur = tree_ttm(cur, k);
+    for (int k : chain_of(n)) cur = tree_ttm(cur, k);
     SketchOut o;
     o.Y = cur;
     o.A = cur.before(n);
@@ -288,6 +310,7 @@ Ten core_impl(Ctx& c, const Ten& X, const double* const* U, const int64_t* l, ui
 void truncate_impl(Ctx& c, Ten G, const int32_t* r, double* const* Uhat, const std::vector<int64_t>& I,
                    double* Gout, double* const* Uout) {
   const int d = static_cast<int>(G.dims.size());
+  std::vector<SmallGemmJob> ups;
   for (int j = 0; j < d; ++j) {
     const int64_t cj = G.dims[j], A = G.before(j), B = G.after(j), rj = r[j];
     double* gram = static_cast<double*>(c.take(static_cast<size_t>(cj) * cj * sizeof(double)));
@@ -298,9 +321,14 @@ void truncate_impl(Ctx& c, Ten G, const int32_t* r, double* const* Uhat, const s
       c.chk(launch_sym_eig_top(gram, cj, rj, V, nullptr, c.st));
     }
     G = ttm(c, G, j, V, rj, (j == d - 1) ? Gout : nullptr, /*mtrans=*/true);
-    void* w = c.take(ttm_generic_ws(RT_F64, I[j], cj, 1, rj));
-    if (!c.dry) c.chk(launch_ttm_generic(Uhat[j], RT_F64, I[j], cj, 1, V, rj, Uout[j], w, c.st, true));
+    if (!c.dry)  // (a workspace query passes no factor arrays)
+      ups.push_back(SmallGemmJob{Uhat[j], V, Uout[j], I[j], static_cast<int32_t>(cj), static_cast<int32_t>(rj)});
   }
+  // the factor updates do not feed the truncation: one launch for all modes at the end
+  if (!c.dry)
+    for (size_t i = 0; i < ups.size(); i += kMaxSmallGemm)
+      c.chk(launch_small_gemm_f64(ups.data() + i, static_cast<int>(std::min<size_t>(kMaxSmallGemm, ups.size() - i)),
+                                  c.st));
 }
 
 Ten to_f64(Ctx& c, const Ten& T) {

@@ -2,8 +2,11 @@
 //  * mode contraction out = P_(n) Q_(n)^T on (A, m, B) views, which gives the
 //    Gram matrix G_(j) G_(j)^T of the core (P = Q) and the adjoint dA_n;
 //    fixed-order two-stage reduction, so results are bitwise reproducible;
-//  * a symmetric eigensolver for the <= 64 x 64 Gram matrices: pivoted Cholesky
-//    followed by one-sided Jacobi on the Cholesky factor, binary64, one workgroup.
+//  * a symmetric eigensolver for the <= 64 x 64 Gram matrices, binary64, one
+//    workgroup: Householder tridiagonalisation + multisection + inverse iteration
+//    for up to 32 leading pairs, with one-sided Jacobi on a pivoted Cholesky factor
+//    as the fallback (clusters, numerically zero eigenvalues, r > 32);
+//  * the small binary64 products U_j = U_hat_j V_j of all modes in one launch.
 #include "kernels.hpp"
 
 namespace rt {
@@ -518,7 +521,7 @@ __device__ __forceinline__ void eig_jacobi(const double* __restrict__ M, int n, 
     order[rk] = i;
   }
   __syncthreads();
-  if (evals && tid < n) evals[tid] = nrm[order[tid]];
+  if (evals && tid < r) evals[tid] = nrm[order[tid]];
   if (tid == 0) {
     // columns beyond the numerical rank: complete with unit vectors orthogonalised
     // against the previous columns (modified Gram-Schmidt), so V stays orthonormal
@@ -1132,6 +1135,66 @@ hipError_t launch_mode_contract(const void* P, const void* Q, rt_dtype dt, int64
     mode_contract_reduce<float><<<g2, 256, 0, st>>>(static_cast<const float*>(ws), p.nchunks, tiles, p.tilesQ, mP,
                                                     mQ, accumulate, static_cast<float*>(out));
   }
+  return hipGetLastError();
+}
+
+namespace {
+struct SmallGemmTable {
+  SmallGemmJob j[kMaxSmallGemm];
+};
+constexpr int kSGRows = 64;
+constexpr int kSGStride = 66;  // even row stride keeps the double2 reads aligned
+// 64 rows of C per workgroup, 4 x 4 outputs per thread, operands staged in LDS
+__global__ __launch_bounds__(256) void small_gemm_f64_kernel(SmallGemmTable tab) {
+  __shared__ __align__(16) double sa[kSGRows][kSGStride];
+  __shared__ __align__(16) double sb[64][kSGStride];
+  const SmallGemmJob& J = tab.j[blockIdx.y];
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kSGRows;
+  if (r0 >= J.m) return;
+  for (int idx = threadIdx.x; idx < kSGRows * 64; idx += 256) {
+    const int rr = idx / 64, c = idx % 64;
+    sa[rr][c] = (r0 + rr < J.m && c < J.k) ? J.A[(r0 + rr) * J.k + c] : 0.0;
+    sb[rr][c] = (rr < J.k && c < J.n) ? J.B[static_cast<int64_t>(rr) * J.n + c] : 0.0;
+  }
+  __syncthreads();
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  double acc[4][4] = {};
+#pragma unroll 4
+  for (int t = 0; t < J.k; ++t) {
+    double a[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] = sa[4 * ty + u][t];
+    const double2 b0 = *reinterpret_cast<const double2*>(&sb[t][4 * tx]);
+    const double2 b1 = *reinterpret_cast<const double2*>(&sb[t][4 * tx + 2]);
+    const double b[4] = {b0.x, b0.y, b1.x, b1.y};
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t r = r0 + 4 * ty + u;
+    if (r >= J.m) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      if (4 * tx + v < J.n) J.C[r * J.n + 4 * tx + v] = acc[u][v];
+  }
+}
+}  // namespace
+
+hipError_t launch_small_gemm_f64(const SmallGemmJob* jobs, int count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  if (count > kMaxSmallGemm) return hipErrorInvalidValue;
+  SmallGemmTable tab;
+  int64_t mmax = 0;
+  for (int i = 0; i < count; ++i) {
+    if (jobs[i].k > 64 || jobs[i].n > 64 || jobs[i].k < 1 || jobs[i].n < 1) return hipErrorInvalidValue;
+    tab.j[i] = jobs[i];
+    if (jobs[i].m > mmax) mmax = jobs[i].m;
+  }
+  const dim3 grid(static_cast<unsigned>(ceil_div(mmax, kSGRows)), static_cast<unsigned>(count));
+  small_gemm_f64_kernel<<<grid, 256, 0, st>>>(tab);
   return hipGetLastError();
 }
 

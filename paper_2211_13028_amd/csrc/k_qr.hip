@@ -262,6 +262,8 @@ __global__ __launch_bounds__(256) void cq_gram_kernel(TAB tab) {
   __shared__ double sy[kGramRows][kCols + 1];
   const CJob& J = tab[blockIdx.y];
   if (static_cast<int>(blockIdx.x) >= J.chunks) return;
+  // the breakdown flag of the job starts cleared (every later kernel reads it)
+  if (blockIdx.x == 0 && threadIdx.x == 0) *J.flag = 0;
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kGramRows;
   for (int idx = threadIdx.x; idx < kGramRows * kCols; idx += 256) {
     const int rr = idx / kCols, j = idx % kCols;
@@ -306,7 +308,7 @@ __global__ __launch_bounds__(256) void cq_chol_kernel(TAB tab, int second) {
   __shared__ double Rs[kCols][kCols + 1];
   __shared__ double Xs[kCols][kCols + 1];
   const CJob& J = tab[blockIdx.x];
-  if (*J.flag) return;  // cleared by cq_reset_kernel before the first pass
+  if (*J.flag) return;  // cleared by cq_gram_kernel before the first pass
   const int n = J.n;
   const int lane = static_cast<int>(threadIdx.x) % kWave, wv = static_cast<int>(threadIdx.x) / kWave;
   const double* part = J.part + (second ? static_cast<int64_t>(J.chunks) * kCols * kCols : 0);
@@ -487,11 +489,6 @@ __global__ __launch_bounds__(256) void cq_apply_kernel(TAB tab, int second) {
     for (int v = 0; v < 4; ++v) gp[(ty * 4 + u) * kCols + tx * 4 + v] = g[u][v];
 }
 
-template <typename TAB>
-__global__ void cq_reset_kernel(TAB tab, int count) {
-  const int i = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
-  if (i < count) *tab[i].flag = 0;
-}
 
 // One matrix of the (recursive) TSQR plan.
 struct Mat {
@@ -657,7 +654,6 @@ hipError_t qr_plan(const QRJob* jobs, int count, rt_dtype ydt, bool launch, Bump
     const dim3 g1(max_chunks, nc);
     (void)max_m;
     const CTabVal tv{tab};
-    cq_reset_kernel<<<1, 64, 0, st>>>(tv, nc);
     if (ydt == RT_F64) {
       cq_gram_kernel<double><<<g1, 256, 0, st>>>(tv);
       cq_chol_kernel<<<nc, 256, 0, st>>>(tv, 0);
@@ -701,7 +697,6 @@ hipError_t launch_cholqr2_grouped(const GCholQRJob* jobs, int count, int max_chu
   if (count == 0) return hipSuccess;
   const CTabPtr tp{jobs};
   const dim3 g1(static_cast<unsigned>(max_chunks), static_cast<unsigned>(count));
-  cq_reset_kernel<<<static_cast<unsigned>(ceil_div(count, 256)), 256, 0, st>>>(tp, count);
   if (ydt == RT_F64) {
     cq_gram_kernel<double><<<g1, 256, 0, st>>>(tp);
     cq_chol_kernel<<<count, 256, 0, st>>>(tp, 0);

@@ -125,10 +125,23 @@ hipError_t launch_mode_contract(const void* P, const void* Q, rt_dtype dt, int64
                                 int64_t mQ, int64_t B, void* out, void* ws, hipStream_t st,
                                 bool accumulate = false);
 
-// Symmetric eigendecomposition (cyclic Jacobi, binary64) of an n x n matrix
-// (n <= 64): V (n x r row-major) = eigenvectors of the r largest eigenvalues,
-// in decreasing order, each column's largest-magnitude entry made positive.
-// evals (may be null): all n eigenvalues, decreasing.
+// Leading eigenpairs (binary64) of a symmetric positive semidefinite n x n matrix
+// (n <= 64): Householder tridiagonalisation, multisection and inverse iteration for
+// r <= 32, one-sided Jacobi on a pivoted Cholesky factor otherwise or when the first
+// method's orthogonality / residual checks fail.  V (n x r row-major) = eigenvectors
+// of the r largest eigenvalues, in decreasing order, each column's largest-magnitude
+// entry (first on ties) made positive.  evals (may be null): those r eigenvalues.
+// C = A B for up to kMaxSmallGemm binary64 jobs in one launch (row-major; A: m x k,
+// B: k x n, k, n <= 64), 64 rows of C per workgroup: the factor updates U_j = U_hat_j V_j.
+constexpr int kMaxSmallGemm = 8;
+struct SmallGemmJob {
+  const double* A;
+  const double* B;
+  double* C;
+  int64_t m;
+  int32_t k, n;
+};
+hipError_t launch_small_gemm_f64(const SmallGemmJob* jobs, int count, hipStream_t st);
 hipError_t launch_sym_eig_top(const double* M, int64_t n, int64_t r, double* V, double* evals,
                               hipStream_t st);
 
