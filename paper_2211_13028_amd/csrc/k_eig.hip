@@ -641,46 +641,60 @@ __device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcn
 // Number of eigenvalues of T below x: sign changes along the leading principal minors
 // p_i = (d_i - x) p_{i-1} - e2_{i-1} p_{i-2}.  The arrays are padded past n - 1 with
 // d = 2^200 and e2 = 0, where the minors keep their sign, so the loop runs in whole
-// blocks of four with the next block's loads in flight; an exact power-of-two rescaling
-// after each block keeps the minors in range.
+// blocks of eight.  Two register buffers alternate (the loop is unrolled by two
+// blocks), so the loads of the next block are in flight during a whole block of
+// arithmetic; an exact power-of-two rescaling after each block keeps the minors in range.
+constexpr int kStBlk = 8;
+__device__ __forceinline__ uint32_t sign_word(double v) {
+  return static_cast<uint32_t>(static_cast<uint64_t>(__double_as_longlong(v)) >> 32);
+}
+// (the sign changes are counted on the high words in vector registers: no mask round trips)
+__device__ __forceinline__ void sturm_steps(const double (&dv)[kStBlk], const double (&ev)[kStBlk], double x,
+                                            double& p0, double& p1, uint32_t& h1, uint32_t& cnt) {
+#pragma unroll
+  for (int t = 0; t < kStBlk; ++t) {
+    const double p2 = fma(dv[t] - x, p1, -ev[t] * p0);
+    const uint32_t h2 = sign_word(p2);
+    cnt += (h2 ^ h1) >> 31;
+    p0 = p1;
+    p1 = p2;
+    h1 = h2;
+  }
+  const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(p0), fabs(p1)));
+  p0 = __builtin_amdgcn_ldexp(p0, -ex);
+  p1 = __builtin_amdgcn_ldexp(p1, -ex);
+}
 __device__ __forceinline__ int sturm_count(const double* __restrict__ d, const double* __restrict__ e2, int n,
                                            double x) {
-  // A minor that is exactly zero is counted as non-negative.  With e_{i-1} != 0 the next
-  // minor then has the opposite sign of the one before the zero, which gives the same
-  // total as the usual convention; a zero next to a split of T (e = 0) can miscount,
-  // and the caller's residual check then rejects the eigenvalue.
+  // A minor that is exactly zero counts with the sign bit it carries.  With e_{i-1} != 0
+  // the next minor has the opposite sign of the one before the zero, so the pair of
+  // transitions adds one change whichever sign the zero takes; a zero next to a split of
+  // T (e = 0) can miscount, and the caller's residual check then rejects the eigenvalue.
   double p0 = 1.0, p1 = d[0] - x;
-  bool neg1 = p1 < 0.0;
-  int cnt = neg1 ? 1 : 0;
-  double dn[4], en[4];
+  uint32_t h1 = sign_word(p1);
+  uint32_t cnt = h1 >> 31;
+  double da[kStBlk], ea[kStBlk], db[kStBlk], eb[kStBlk];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    dn[t] = d[1 + t];
-    en[t] = e2[t];
+  for (int t = 0; t < kStBlk; ++t) {
+    da[t] = d[1 + t];
+    ea[t] = e2[t];
   }
-  for (int i = 1; i < n; i += 4) {
-    double dc[4], ec[4];
+  for (int i = 1; i < n; i += 2 * kStBlk) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      dc[t] = dn[t];
-      ec[t] = en[t];
-      dn[t] = d[i + 4 + t];
-      en[t] = e2[i + 3 + t];
+    for (int t = 0; t < kStBlk; ++t) {
+      db[t] = d[i + kStBlk + t];
+      eb[t] = e2[i + kStBlk - 1 + t];
     }
+    sturm_steps(da, ea, x, p0, p1, h1, cnt);
+    if (i + kStBlk >= n) break;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const double p2 = fma(dc[t] - x, p1, -ec[t] * p0);
-      const bool neg2 = p2 < 0.0;
-      cnt += (neg2 != neg1) ? 1 : 0;
-      p0 = p1;
-      p1 = p2;
-      neg1 = neg2;
+    for (int t = 0; t < kStBlk; ++t) {
+      da[t] = d[i + 2 * kStBlk + t];
+      ea[t] = e2[i + 2 * kStBlk - 1 + t];
     }
-    const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(p0), fabs(p1)));
-    p0 = __builtin_amdgcn_ldexp(p0, -ex);
-    p1 = __builtin_amdgcn_ldexp(p1, -ex);
+    sturm_steps(db, eb, x, p0, p1, h1, cnt);
   }
-  return cnt;
+  return static_cast<int>(cnt);
 }
 
 constexpr int kP1Waves = 4;
@@ -691,7 +705,7 @@ static_assert(kTriB >= 4 * kP1Waves * kJN + kJN * kJN, "phase-1 scratch must fit
 __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n, int r, double* __restrict__ Vout,
                                             double* __restrict__ evals, double* __restrict__ Am,
                                             double* __restrict__ B) {
-  constexpr int kPad = kJN + 8;  // tridiagonal arrays padded for the blocked Sturm loop
+  constexpr int kPad = kJN + 3 * kStBlk;  // tridiagonal arrays padded for the blocked Sturm loop
   __shared__ double dS[kPad], eS[kPad], e2S[kPad], tauS[kJN], lamS[kJN];
   __shared__ double bounds[3];
   __shared__ unsigned long long ebits, rbits;
