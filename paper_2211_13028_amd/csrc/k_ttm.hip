@@ -295,7 +295,8 @@ __device__ __forceinline__ uint32_t pack_lo(uint32_t a, uint32_t b) { return (a 
 __device__ __forceinline__ uint32_t pack_hi(uint32_t a, uint32_t b) { return (a >> 16) | (b & 0xffff0000u); }
 
 template <int MT>
-__global__ __launch_bounds__(kMfmaThreads) void ttm_mfma_bf16_kernel(const bf16_t* __restrict__ X, int64_t A,
+__global__ __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(2))) void ttm_mfma_bf16_kernel(
+    const bf16_t* __restrict__ X, int64_t A,
                                                                      int64_t K, int64_t B,
                                                                      const bf16_t* __restrict__ Mop, int64_t m,
                                                                      int64_t chunks, int ksplit, int64_t kper,
@@ -321,23 +322,25 @@ __global__ __launch_bounds__(kMfmaThreads) void ttm_mfma_bf16_kernel(const bf16_
   const bf16_t* xa = X + a * K * B;
   const int64_t col = b0 + 8 * j;
   const bool colok = col < B;
+  // lane loads rows k0 + 8q + t, columns col..col+7; the next step's rows are loaded
+  // while the current ones are multiplied
+  u32x4 rn[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int64_t k = kbeg + 8 * q + t;
+    rn[t] = u32x4{0u, 0u, 0u, 0u};
+    if (colok && k < kend) rn[t] = *reinterpret_cast<const u32x4*>(xa + k * B + col);
+  }
   for (int64_t k0 = kbeg; k0 < kend; k0 += 32) {
-    // lane loads rows k0 + 8q + t, columns col..col+7
     u32x4 r[8];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int64_t k = k0 + 8 * q + t;
-      r[t] = u32x4{0u, 0u, 0u, 0u};
-      if (colok && k < kend) r[t] = *reinterpret_cast<const u32x4*>(xa + k * B + col);
-    }
-    // operand for column c: 8 consecutive k of column col + c
-    u32x4 op[8];
+    for (int t = 0; t < 8; ++t) r[t] = rn[t];
+    if (k0 + 32 < kend) {
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-#pragma unroll
-      for (int w = 0; w < 4; ++w) {
-        const uint32_t lo = r[2 * w][c / 2], hi = r[2 * w + 1][c / 2];
-        op[c][w] = (c % 2 == 0) ? pack_lo(lo, hi) : pack_hi(lo, hi);
+      for (int t = 0; t < 8; ++t) {
+        const int64_t k = k0 + 32 + 8 * q + t;
+        rn[t] = u32x4{0u, 0u, 0u, 0u};
+        if (colok && k < kend) rn[t] = *reinterpret_cast<const u32x4*>(xa + k * B + col);
       }
     }
     u32x4 mv[MT];
@@ -347,14 +350,21 @@ __global__ __launch_bounds__(kMfmaThreads) void ttm_mfma_bf16_kernel(const bf16_
       mv[mt] = u32x4{0u, 0u, 0u, 0u};
       if (kk < kend) mv[mt] = *reinterpret_cast<const u32x4*>(Mop + (mt * 16 + j) * K + kk);
     }
+    // operand for column c (8 consecutive k of column col + c) is packed just before its
+    // products, which keeps the register count low enough for two waves per SIMD
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      const bf16x8 av = __builtin_bit_cast(bf16x8, mv[mt]);
+    for (int c = 0; c < 8; ++c) {
+      u32x4 op;
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        const bf16x8 bv = __builtin_bit_cast(bf16x8, op[c]);
-        acc[mt][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[mt][c], 0, 0, 0);
+      for (int w = 0; w < 4; ++w) {
+        const uint32_t lo = r[2 * w][c / 2], hi = r[2 * w + 1][c / 2];
+        op[w] = (c % 2 == 0) ? pack_lo(lo, hi) : pack_hi(lo, hi);
       }
+      const bf16x8 bv = __builtin_bit_cast(bf16x8, op);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+        acc[mt][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, mv[mt]), bv, acc[mt][c], 0,
+                                                             0, 0);
     }
   }
   float* ya = Y + (static_cast<int64_t>(ks) * A + a) * m * B;
