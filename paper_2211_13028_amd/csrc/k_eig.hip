@@ -572,7 +572,7 @@ __device__ __forceinline__ void eig_jacobi(const double* __restrict__ M, int n, 
 //     per step;
 //  3. eigenvectors of T by inverse iteration, one lane per eigenvalue: LU of T - lambda I
 //     with partial pivoting (tiny pivots raised to eps |T|), two solves from a fixed
-//     quasi-random start vector;
+//     pseudo-random start vector;
 //  4. one Loewdin step Z <- Z (I - E/2 + 3 E^2 / 8), E = Z^T Z - I, skipped when Z is
 //     orthonormal to rounding already, then V = Q Z.
 // The result is accepted only when ||E|| <= 1e-6 (the series is then exact to rounding)
@@ -623,6 +623,17 @@ __device__ __forceinline__ double rcp_refined(double x) {
 #pragma unroll
   for (int it = 0; it < 2; ++it) y = fma(y, fma(-x, y, 1.0), y);
   return y;
+}
+// fixed pseudo-random start value in [-1/2, 1/2) for row i of eigenvector m
+// (32-bit integer finaliser of MurmurHash3)
+__device__ __forceinline__ double start_value(int i, int m) {
+  uint32_t h = static_cast<uint32_t>(i * 64 + m + 1);
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return static_cast<double>(h) * 0x1p-32 - 0.5;
 }
 // make LDS data written by other lanes of this wave visible to the next reads of this wave
 __device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
@@ -860,8 +871,8 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
     if (g < r && sub == 0) lamS[g] = 0.5 * (a + b);
   }
   __syncthreads();
-  // ---- 3. inverse iteration, lane m of wave 0 for eigenvalue m: the LU factors go to LDS,
-  //         the iterate stays in registers.
+  // ---- 3. inverse iteration, lane m of wave 0 for eigenvalue m.  Loops run over rows with
+  //         the row data for the next iterations loaded ahead (unrolled by four).
   auto F = [&](int f, int i, int m) -> double& { return B[(f * kJN + i) * kTriMaxR + m]; };
   constexpr int IU0 = 0, U1 = 1, U2 = 2, ML = 3, ZZ = 4;
   if (wv == 0 && lane < r) {
@@ -895,54 +906,40 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
       F(U1, n - 1, m) = 0.0;
       F(U2, n - 1, m) = 0.0;
     }
-    // factors of the padding rows n .. kJN - 1 keep z there at zero and leave rows < n
-    // alone, so the solves below run over all kJN rows with z in registers (static indices)
-    for (int i = n; i < kJN; ++i) {
-      F(IU0, i, m) = 1.0;
-      F(U1, i, m) = 0.0;
-      F(U2, i, m) = 0.0;
-    }
-    for (int i = n - 1; i < kJN; ++i) F(ML, i, m) = 0.0;
-    double z[kJN];
-#pragma unroll
-    for (int i = 0; i < kJN; ++i)  // fixed quasi-random start (golden-ratio sequence), zero past n
-      z[i] = (i < n) ? __builtin_amdgcn_fract(fma(static_cast<double>(i), 0.6180339887498949,
-                                                  static_cast<double>(m) * 0.7548776662466927)) - 0.5
-                     : 0.0;
+    for (int i = 0; i < n; ++i) F(ZZ, i, m) = start_value(i, m);
     for (int it = 0; it < kInvIters; ++it) {
-      // (scheduling barriers every 8 rows keep the factor loads from being hoisted all at
-      //  once, which would spill)
-#pragma unroll
-      for (int i = 0; i + 1 < kJN; ++i) {
-        if (i % 8 == 0) __builtin_amdgcn_sched_barrier(0);
-        const double mm = F(ML, i, m);
+      double yi = F(ZZ, 0, m);
+#pragma unroll 4
+      for (int i = 0; i + 1 < n; ++i) {
+        const double yn = F(ZZ, i + 1, m), mm = F(ML, i, m);
         const bool sw = (piv >> i) & 1ull;
-        const double za = z[i], zb = z[i + 1];
-        z[i] = sw ? zb : za;
-        z[i + 1] = sw ? fma(-mm, zb, za) : fma(-mm, za, zb);
+        F(ZZ, i, m) = sw ? yn : yi;
+        yi = sw ? fma(-mm, yn, yi) : fma(-mm, yi, yn);
       }
-      double mx = 0.0;
-#pragma unroll
-      for (int i = kJN - 1; i >= 0; --i) {
-        if (i % 8 == 7) __builtin_amdgcn_sched_barrier(0);
-        double t = z[i];
-        if (i + 2 < kJN) t = fma(-F(U2, i, m), z[i + 2], t);
-        if (i + 1 < kJN) t = fma(-F(U1, i, m), z[i + 1], t);
-        z[i] = t * F(IU0, i, m);
-        mx = fmax(mx, fabs(z[i]));
+      F(ZZ, n - 1, m) = yi;
+      double z1 = 0.0, z2 = 0.0, mx = 0.0;
+#pragma unroll 4
+      for (int i = n - 1; i >= 0; --i) {
+        const double zi = fma(-F(U1, i, m), z1, fma(-F(U2, i, m), z2, F(ZZ, i, m))) * F(IU0, i, m);
+        F(ZZ, i, m) = zi;
+        z2 = z1;
+        z1 = zi;
+        mx = fmax(mx, fabs(zi));
       }
       const int ez = (mx > 0.0) ? __builtin_amdgcn_frexp_exp(mx) : 0;
-#pragma unroll
-      for (int i = 0; i < kJN; ++i) z[i] = __builtin_amdgcn_ldexp(z[i], -ez);
+#pragma unroll 4
+      for (int i = 0; i < n; ++i) F(ZZ, i, m) = __builtin_amdgcn_ldexp(F(ZZ, i, m), -ez);
     }
-    double s4[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int i = 0; i < kJN; ++i) s4[i % 4] = fma(z[i], z[i], s4[i % 4]);
-    const double ss = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll 4
+    for (int i = 0; i < n; ++i) {
+      const double zi = F(ZZ, i, m);
+      if (i & 1) s1 = fma(zi, zi, s1); else s0 = fma(zi, zi, s0);
+    }
+    const double ss = s0 + s1;
     const double inv = (ss > 0.0) ? rsq_refined(ss) : 0.0;
-#pragma unroll
-    for (int i = 0; i < kJN; ++i)
-      if (i < n) F(ZZ, i, m) = z[i] * inv;
+#pragma unroll 4
+    for (int i = 0; i < n; ++i) F(ZZ, i, m) *= inv;
   }
   __syncthreads();
   // ---- 4. orthogonality check E = Z^T Z - I (upper triangle) and residual check
