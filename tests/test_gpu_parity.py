@@ -298,6 +298,33 @@ def test_decompose_exact_rank_and_full_width():
     assert abs(T.rel_error(Y, host(G), [host(U) for U in Us]) - T.rel_error(Y, Gs, Vs)) < 1e-12
 
 
+def test_decompose_rank_above_32_fp64():
+    """r > 32 leading eigenpairs per truncation: the eigensolver's Jacobi path.  |de| <= 1e-10."""
+    say("decompose rank > 32")
+    dims = (72, 70, 68)
+    core = synth.tucker_core_decay((40, 40, 40), tau=12.0, seed=21)
+    X, _, _ = synth.random_tucker(dims, None, 1e-6, seed=22, core=core)
+    r, p = [34, 33, 35], 4
+    s = rt.rtucker_sketch_sizes(dims, r, p)
+    assert all(34 <= int(np.prod([s[k] for k in range(3) if k != n])) <= 64 for n in range(3))
+    phis = reuse_phis(dims, s, seed=23)
+    _decompose_and_compare(X, dev(X), r, p, "rhkron", phis, s, 1e-10)
+
+
+def test_decompose_repeated_singular_values_fp64():
+    """A core whose unfoldings have six equal singular values: the tridiagonal path's checks
+    reject the cluster (inverse iteration gives non-orthogonal vectors there) and the Jacobi
+    path takes over.  The error depends only on the retained subspace: |de| <= 1e-10."""
+    say("decompose repeated singular values")
+    core = np.zeros((6, 6, 6))
+    for i in range(6):
+        core[i, i, i] = 1.0
+    X, _, _ = synth.random_tucker((40, 36, 32), None, 1e-7, seed=24, core=core)
+    s = [4, 4, 4]
+    phis = reuse_phis(X.shape, s, seed=25)
+    _decompose_and_compare(X, dev(X), [6, 6, 6], 3, "rhkron", phis, s, 1e-10)
+
+
 def test_decompose_bitwise_repeatable():
     X = synth.bumps_field((64, 72, 80), nbumps=20, noise_rel=1e-4, seed=14)
     Xd = dev(X, torch.float32)
