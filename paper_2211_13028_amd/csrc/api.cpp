@@ -259,7 +259,7 @@ Ten core_impl(Ctx& c, const Ten& X, const double* const* U, const int64_t* l, ui
     if (mask >> k & 1u) order.push_back(k);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return X.dims[a] > X.dims[b]; });
   // plan every contraction first so that all operand roundings go out in one launch
-  struct Step { int k; int64_t A, K, B, m; rt_dtype in_dt; bool mfma; const void* op; void* y; void* w; };
+  struct Step { int k; int64_t A, K, B, m; rt_dtype in_dt; bool mfma, last; const void* op; void* y; void* w; };
   std::vector<Step> steps;
   std::vector<int64_t> dims = X.dims;
   rt_dtype cur_dt = X.dt;
@@ -276,9 +276,15 @@ Ten core_impl(Ctx& c, const Ten& X, const double* const* U, const int64_t* l, ui
     const rt_dtype ct = ctype(cur_dt);
     st.y = (last && dst) ? dst : c.take(static_cast<size_t>(st.A) * st.m * st.B * dtype_size(ct));
     st.mfma = (cur_dt == RT_F32 || cur_dt == RT_BF16) && ttm_mfma_ok(cur_dt, st.A, st.K, st.B, st.m);
+    // a binary32 contraction over the last mode (B = 1) runs on the matrix-core kernel
+    // for contiguous rows
+    st.last = !st.mfma && cur_dt == RT_F32 && st.B == 1 && ttm_mfma_last_ok(st.A, st.K, st.m);
     if (st.mfma) {
       st.op = prep(c, U ? U[k] : nullptr, st.m, st.K, true, cur_dt, cur_dt, ttm_mfma_mpad(st.m));
       st.w = c.take(ttm_mfma_ws(cur_dt, st.A, st.K, st.B, st.m));
+    } else if (st.last) {
+      st.op = prep(c, U ? U[k] : nullptr, st.m, st.K, true, RT_F32, RT_F32, ttm_mfma_mpad(st.m));
+      st.w = c.take(ttm_mfma_last_ws(st.A, st.K, st.m));
     } else {
       st.op = prep(c, U ? U[k] : nullptr, st.m, st.K, true, cur_dt == RT_F64 ? RT_F64 : cur_dt, ct);
       st.w = c.take(ttm_generic_ws(cur_dt, st.A, st.K, st.B, st.m));
@@ -293,6 +299,9 @@ Ten core_impl(Ctx& c, const Ten& X, const double* const* U, const int64_t* l, ui
     if (!c.dry) {
       if (st.mfma)
         c.chk(launch_ttm_mfma_ws(cur.p, cur.dt, st.A, st.K, st.B, st.op, st.m, static_cast<float*>(st.y), st.w, c.st));
+      else if (st.last)
+        c.chk(launch_ttm_mfma_last(static_cast<const float*>(cur.p), st.A, st.K, static_cast<const float*>(st.op), st.m,
+                                   static_cast<float*>(st.y), st.w, c.st));
       else
         c.chk(launch_ttm_generic(cur.p, cur.dt, st.A, st.K, st.B, st.op, st.m, st.y, st.w, c.st));
     }

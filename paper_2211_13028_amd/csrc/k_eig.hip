@@ -19,7 +19,8 @@ constexpr int kMCK = 16;
 constexpr int kMCThreads = 256;
 
 // one 64 x 64 output tile (rows i0.., columns j0..) summed over t in [t0, t1);
-// thread (ty, tx) accumulates rows 4 ty.., columns 4 tx..
+// thread (ty, tx) accumulates rows 4 ty.., columns 4 tx..  The operands of the next
+// 16 t are loaded into registers while the current 16 are multiplied from LDS.
 template <typename T>
 __device__ __forceinline__ void mode_contract_tile(const T* __restrict__ P, const T* __restrict__ Q, int64_t A,
                                                    int64_t mP, int64_t mQ, int64_t B, int64_t t0, int64_t t1,
@@ -32,45 +33,52 @@ __device__ __forceinline__ void mode_contract_tile(const T* __restrict__ P, cons
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[u][v] = T(0);
-  // loading roles: each thread loads the elements (tt, ii) with tt = lt and ii = li + 16*rep
-  const bool tfast = B >= kMCK;  // follow memory order: t fastest when rows of b are long
+  // loading roles: each thread loads four (tt, ii) elements per 16 t, following memory
+  // order: t fastest when rows of b are long (tt = lt, ii = li + 16 rep), the mode
+  // index fastest otherwise (tt = lt + 4 rep, ii = li)
+  const bool tfast = B >= kMCK;
   int lt, li;
   if (tfast) { lt = threadIdx.x % kMCK; li = threadIdx.x / kMCK; } else { li = threadIdx.x % kMCTile; lt = threadIdx.x / kMCTile; }
-  const int istep = tfast ? (kMCThreads / kMCK) : kMCTile;   // 16 or 64 rows per pass
-  const int tstep = tfast ? kMCK : (kMCThreads / kMCTile);   // 16 or 4 t per pass
   // incremental (a, b) of this thread's first t, no division inside the loop
   int64_t ta = (t0 + lt) / B, tb = (t0 + lt) - ((t0 + lt) / B) * B;
-  for (int64_t tbase = t0; tbase < t1; tbase += kMCK) {
-    __syncthreads();
-    for (int tt = lt; tt < kMCK; tt += tstep) {
-      // (a, b) for t = tbase + tt: advance from the thread's running position
-      int64_t a = ta, b = tb + (tt - lt);
+  T pv[4], qv[4];
+  auto load16 = [&](int64_t tbase) {
+#pragma unroll
+    for (int rep = 0; rep < 4; ++rep) {
+      const int dt = tfast ? 0 : 4 * rep;
+      const int ii = tfast ? li + 16 * rep : li;
+      int64_t a = ta, b = tb + dt;
       while (b >= B) { b -= B; ++a; }
-      const int64_t t = tbase + tt;
-      for (int ii = li; ii < kMCTile; ii += istep) {
-        T pv = T(0), qv = T(0);
-        if (t < t1) {
-          if (i0 + ii < mP) pv = P[a * mP * B + (i0 + ii) * B + b];
-          if (j0 + ii < mQ) qv = Q[a * mQ * B + (j0 + ii) * B + b];
-        }
-        sP[tt][ii] = pv;
-        sQ[tt][ii] = qv;
-      }
+      const bool in = tbase + lt + dt < t1;
+      pv[rep] = (in && i0 + ii < mP) ? P[a * mP * B + (i0 + ii) * B + b] : T(0);
+      qv[rep] = (in && j0 + ii < mQ) ? Q[a * mQ * B + (j0 + ii) * B + b] : T(0);
     }
     tb += kMCK;
     while (tb >= B) { tb -= B; ++ta; }
+  };
+  load16(t0);
+  for (int64_t tbase = t0; tbase < t1; tbase += kMCK) {
     __syncthreads();
+#pragma unroll
+    for (int rep = 0; rep < 4; ++rep) {
+      const int tt = tfast ? lt : lt + 4 * rep;
+      const int ii = tfast ? li + 16 * rep : li;
+      sP[tt][ii] = pv[rep];
+      sQ[tt][ii] = qv[rep];
+    }
+    __syncthreads();
+    if (tbase + kMCK < t1) load16(tbase + kMCK);
 #pragma unroll 4
     for (int tt = 0; tt < kMCK; ++tt) {
-      T pv[4], qv[4];
+      T pr[4], qr[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) pv[u] = sP[tt][ty * 4 + u];
+      for (int u = 0; u < 4; ++u) pr[u] = sP[tt][ty * 4 + u];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) qv[v] = sQ[tt][tx * 4 + v];
+      for (int v = 0; v < 4; ++v) qr[v] = sQ[tt][tx * 4 + v];
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = fma(pv[u], qv[v], acc[u][v]);
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(pr[u], qr[v], acc[u][v]);
     }
   }
 }
@@ -240,7 +248,10 @@ MCPlan mc_plan(rt_dtype dt, int64_t A, int64_t mP, int64_t mQ, int64_t B) {
   int64_t want = target / (p.tilesP * p.tilesQ);
   if (want < 1) want = 1;
   int64_t chunk = ceil_div(total, want);
-  if (chunk < 64) chunk = 64;
+  // binary64 (small Gram matrices): one or two rounds of 16 t per workgroup, so the
+  // contraction is not a chain of load latencies; binary32 keeps 64 t or more
+  const int64_t cmin = (dt == RT_F32) ? 64 : 16;
+  if (chunk < cmin) chunk = cmin;
   chunk = ceil_div(chunk, gran) * gran;
   p.chunk = chunk;
   p.nchunks = static_cast<int>(ceil_div(total, chunk));
@@ -699,7 +710,7 @@ __device__ __forceinline__ int sturm_count(const double* __restrict__ d, const d
 
 constexpr int kP1Waves = 4;
 constexpr int kP1Cols = kJN / kP1Waves;  // matrix columns held in registers per wave
-static_assert(kTriB >= 4 * kP1Waves * kJN + kJN * kJN, "phase-1 scratch must fit");
+static_assert(kTriB >= 4 * kP1Waves * kJN + kJN, "phase-1 scratch must fit");
 
 // Returns true (uniformly over the workgroup) when V and evals were written.
 __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n, int r, double* __restrict__ Vout,
@@ -711,46 +722,47 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
   __shared__ unsigned long long ebits, rbits;
   const int tid = threadIdx.x;
   const int lane = tid % kWave;
-  const int wv = tid / kWave;
+  const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
   // ---- load, scaled by the power of two that brings the largest diagonal entry to [1/2, 1)
   const double dmax = wave_max_f64(lane < n ? fabs(M[lane * n + lane]) : 0.0);
   if (!(dmax > 0.0) || !(dmax < 1e300)) return false;  // zero or non-finite: Jacobi path
   const int ex = __builtin_amdgcn_frexp_exp(dmax);
-  // scratch in B: per-wave copies of v and w, partial products, and the published column
+  // scratch in B: per-wave copies of v and w (in slot order, see below), partial products,
+  // and the column that the next reflector is formed from
   double* vbuf = B;                               // [wave][kJN]
   double* wbuf = B + kP1Waves * kJN;              // [wave][kJN]
   double* part = B + 2 * kP1Waves * kJN;          // [wave][kJN]
-  double* colfull = B + 4 * kP1Waves * kJN;       // [kJN][kJN]: columns of the current matrix,
-                                                  // refreshed by the wave that owns the next one
+  double* colbuf = B + 4 * kP1Waves * kJN;        // [kJN]
   for (int idx = tid; idx < kJN * kAStride; idx += kJThreads) Am[idx] = 0.0;
   if (tid == 0) {
     ebits = 0;
     rbits = 0;
   }
-  // ---- 1. Householder tridiagonalisation on four waves (one per SIMD).  Wave w keeps the
-  //         columns 16 w .. 16 w + 15 of the matrix in registers (lane = row) for the whole
-  //         reduction, so the matrix-vector product and the rank-2 update touch LDS only
-  //         for broadcast reads of v and w.  After the update of step k the wave that owns
-  //         column k + 1 stores its 16 columns (static register indices; the columns it does
-  //         not change keep their bits), and every wave forms the next reflector from them.
-  //         Rows and columns past n are zero and carry v = w = 0.
+  // ---- 1. Householder tridiagonalisation on four waves (one per SIMD).  Column j of the
+  //         matrix lives in registers of wave j % 4, slot j / 4 (lane = row), for the whole
+  //         reduction.  The matrix-vector product and the rank-2 update touch LDS only for
+  //         broadcast reads of v and w, which each wave stores in slot order (entry j at
+  //         (j % 4) 16 + j / 4); v stays in registers from the product to the update.
+  //         After the update of step k the wave that owns column k + 1 publishes that
+  //         column alone, and every wave forms the next reflector from it.  Rows and
+  //         columns past n are zero and carry v = w = 0; finished columns (j <= k) see
+  //         v_j = w_j = 0 and keep their values.
   const bool worker = wv < kP1Waves;
+  const int slot_of_lane = (lane % kP1Waves) * kP1Cols + lane / kP1Waves;
   double ar[kP1Cols];
 #pragma unroll
   for (int t = 0; t < kP1Cols; ++t) {
-    const int j = kP1Cols * wv + t;
+    const int j = kP1Waves * t + wv;
     ar[t] = (worker && lane < n && j < n) ? __builtin_amdgcn_ldexp(M[lane * n + j], -ex) : 0.0;
   }
-  if (wv == 0) {
-#pragma unroll
-    for (int t = 0; t < kP1Cols; ++t) colfull[t * kJN + lane] = ar[t];
-  }
+  if (wv == 0) colbuf[lane] = ar[0];
   __syncthreads();
   for (int k = 0; k + 2 < n; ++k) {
     const bool live = lane > k && lane < n;
     double sigma = 0.0, tk = 0.0, v = 0.0;
+    double vv[kP1Cols];
     if (worker) {
-      const double x = live ? colfull[k * kJN + lane] : 0.0;
+      const double x = live ? colbuf[lane] : 0.0;
       sigma = wave_sum_f64((lane > k + 1 && lane < n) ? x * x : 0.0);
       const double alpha = readlane_f64(x, k + 1);
       double ek = alpha;
@@ -767,12 +779,14 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
         const double sc = (alpha >= 0.0 ? 1.0 : -1.0) * rcp_refined(fabs(alpha) + mu);
         if (lane > k + 1 && lane < n) v = x * sc;
         double* myv = vbuf + wv * kJN;
-        myv[lane] = v;
+        myv[slot_of_lane] = v;
         wave_lds_sync();
         double a0 = 0.0, a1 = 0.0;
 #pragma unroll
         for (int t = 0; t < kP1Cols; t += 2) {
           const double2 vj = *reinterpret_cast<const double2*>(myv + kP1Cols * wv + t);
+          vv[t] = vj.x;
+          vv[t + 1] = vj.y;
           a0 = fma(ar[t], vj.x, a0);
           a1 = fma(ar[t + 1], vj.y, a1);
         }
@@ -784,7 +798,7 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
         if (lane == 0) {
           tauS[k] = tk;
           eS[k] = ek;
-          dS[k] = colfull[k * kJN + k];
+          dS[k] = colbuf[k];
         }
       }
     }
@@ -797,36 +811,36 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
         p = live ? tk * p : 0.0;
         const double K = 0.5 * tk * wave_sum_f64(p * v);
         const double w = fma(-K, v, p);
-        const double* myv = vbuf + wv * kJN;
         double* myw = wbuf + wv * kJN;
-        myw[lane] = w;
+        myw[slot_of_lane] = w;
         wave_lds_sync();
 #pragma unroll
         for (int t = 0; t < kP1Cols; t += 2) {
-          const double2 vj = *reinterpret_cast<const double2*>(myv + kP1Cols * wv + t);
           const double2 wj = *reinterpret_cast<const double2*>(myw + kP1Cols * wv + t);
-          ar[t] = fma(-v, wj.x, fma(-w, vj.x, ar[t]));
-          ar[t + 1] = fma(-v, wj.y, fma(-w, vj.y, ar[t + 1]));
+          ar[t] = fma(-v, wj.x, fma(-w, vv[t], ar[t]));
+          ar[t + 1] = fma(-v, wj.y, fma(-w, vv[t + 1], ar[t + 1]));
         }
       }
-      if (wv == (k + 1) / kP1Cols) {
+      if (wv == (k + 1) % kP1Waves) {
+        const int s = (k + 1) / kP1Waves;
 #pragma unroll
-        for (int t = 0; t < kP1Cols; ++t) colfull[(kP1Cols * wv + t) * kJN + lane] = ar[t];
+        for (int t = 0; t < kP1Cols; ++t)
+          if (t == s) colbuf[lane] = ar[t];
       }
     }
     __syncthreads();
   }
   // the last 2 x 2 block: column n - 2 is published; A[n-1][n-1] sits with its owner
-  if (wv == (n - 1) / kP1Cols && lane == n - 1) {
-    const int slot = (n - 1) % kP1Cols;
+  if (wv == (n - 1) % kP1Waves && lane == n - 1) {
+    const int slot = (n - 1) / kP1Waves;
     double c = ar[0];
 #pragma unroll
     for (int t = 1; t < kP1Cols; ++t) c = (t == slot) ? ar[t] : c;
     dS[n - 1] = c;
   }
   if (tid == 0) {
-    dS[n - 2] = colfull[(n - 2) * kJN + n - 2];
-    eS[n - 2] = colfull[(n - 2) * kJN + n - 1];
+    dS[n - 2] = colbuf[n - 2];
+    eS[n - 2] = colbuf[n - 1];
   }
   __syncthreads();
   for (int i = tid; i < kPad; i += kJThreads) {
@@ -1165,10 +1179,21 @@ __global__ __launch_bounds__(256) void small_gemm_f64_kernel(SmallGemmTable tab)
   const SmallGemmJob& J = tab.j[blockIdx.y];
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kSGRows;
   if (r0 >= J.m) return;
-  for (int idx = threadIdx.x; idx < kSGRows * 64; idx += 256) {
+  // all global loads of both operands are issued before the first LDS store
+  constexpr int kPer = kSGRows * 64 / 256;
+  double va[kPer], vb[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int idx = static_cast<int>(threadIdx.x) + 256 * q;
     const int rr = idx / 64, c = idx % 64;
-    sa[rr][c] = (r0 + rr < J.m && c < J.k) ? J.A[(r0 + rr) * J.k + c] : 0.0;
-    sb[rr][c] = (rr < J.k && c < J.n) ? J.B[static_cast<int64_t>(rr) * J.n + c] : 0.0;
+    va[q] = (r0 + rr < J.m && c < J.k) ? J.A[(r0 + rr) * J.k + c] : 0.0;
+    vb[q] = (rr < J.k && c < J.n) ? J.B[static_cast<int64_t>(rr) * J.n + c] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int idx = static_cast<int>(threadIdx.x) + 256 * q;
+    sa[idx / 64][idx % 64] = va[q];
+    sb[idx / 64][idx % 64] = vb[q];
   }
   __syncthreads();
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;

@@ -265,11 +265,17 @@ __global__ __launch_bounds__(256) void cq_gram_kernel(TAB tab) {
   // the breakdown flag of the job starts cleared (every later kernel reads it)
   if (blockIdx.x == 0 && threadIdx.x == 0) *J.flag = 0;
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kGramRows;
-  for (int idx = threadIdx.x; idx < kGramRows * kCols; idx += 256) {
-    const int rr = idx / kCols, j = idx % kCols;
-    const int64_t r = r0 + rr;
-    sy[rr][j] = (r < J.m && j < J.n) ? cq_src<TY>(J, r, j) : 0.0;
+  // thread: column j of rows rr0 + 4 q; every load is issued before the first LDS store
+  constexpr int kPer = kGramRows * kCols / 256;
+  const int j = static_cast<int>(threadIdx.x) % kCols, rr0 = static_cast<int>(threadIdx.x) / kCols;
+  double yv[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int64_t r = r0 + rr0 + 4 * q;
+    yv[q] = (r < J.m && j < J.n) ? cq_src<TY>(J, r, j) : 0.0;
   }
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) sy[rr0 + 4 * q][j] = yv[q];
   __syncthreads();
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   double acc[4][4] = {};
@@ -427,13 +433,25 @@ __global__ __launch_bounds__(256) void cq_apply_kernel(TAB tab, int second) {
   const int n = J.n;
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kGramRows;
   const double* Xg = (second ? J.R2 : J.R1) + kCols * kCols;
-  for (int idx = threadIdx.x; idx < kGramRows * kCols; idx += 256) {
-    const int rr = idx / kCols, j = idx % kCols;
-    const int64_t r = r0 + rr;
-    double v = 0.0;
-    if (r < J.m && j < n) v = second ? J.Q1[r * n + j] : cq_src<TY>(J, r, j);
-    sy[rr][j] = v;
-    sx[rr][j] = Xg[idx];
+  {
+    // thread: column j of rows rr0 + 4 q; every load is issued before the first LDS store
+    constexpr int kPer = kGramRows * kCols / 256;
+    const int j = static_cast<int>(threadIdx.x) % kCols, rr0 = static_cast<int>(threadIdx.x) / kCols;
+    double yv[kPer], xv[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int rr = rr0 + 4 * q;
+      const int64_t r = r0 + rr;
+      double v = 0.0;
+      if (r < J.m && j < n) v = second ? J.Q1[r * n + j] : cq_src<TY>(J, r, j);
+      yv[q] = v;
+      xv[q] = Xg[rr * kCols + j];
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      sy[rr0 + 4 * q][j] = yv[q];
+      sx[rr0 + 4 * q][j] = xv[q];
+    }
   }
   __syncthreads();
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;

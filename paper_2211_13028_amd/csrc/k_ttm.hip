@@ -21,6 +21,51 @@ namespace {
 constexpr int kGenThreads = 256;
 constexpr int kGenKC = 64;
 
+// acc[ii] += sum over k in [kb, ke) of M(i0 + ii, k) X[a, k, b] for this thread's column
+// (xp = &X[a, 0, b]).  A chunk of M is staged in LDS; its global loads are all issued
+// into registers before the first LDS store, and X is read kXB rows at a time, so the
+// loads of a chunk are in flight together instead of one latency each.
+constexpr int kXB = 8;
+static_assert(kGenKC % kXB == 0, "X blocks must tile the M chunk");
+template <typename TX, typename TC, int MT>
+__device__ __forceinline__ void generic_accumulate(const TX* __restrict__ xp, int64_t B, const TC* __restrict__ M,
+                                                   int64_t m, int64_t K, int64_t i0, int64_t kb, int64_t ke,
+                                                   bool mtrans, bool active, TC (&sM)[MT][kGenKC], TC (&acc)[MT]) {
+  constexpr int kPer = MT * kGenKC / kWave;  // M elements per thread at the smallest block (one wave)
+  const int nth = static_cast<int>(blockDim.x);
+  for (int64_t k0 = kb; k0 < ke; k0 += kGenKC) {
+    TC mv[kPer];
+#pragma unroll
+    for (int rep = 0; rep < kPer; ++rep) {
+      const int t = static_cast<int>(threadIdx.x) + rep * nth;
+      const int ii = t / kGenKC, kk = t % kGenKC;
+      mv[rep] = (t < MT * kGenKC && i0 + ii < m && k0 + kk < ke)
+                    ? (mtrans ? M[(k0 + kk) * m + i0 + ii] : M[(i0 + ii) * K + k0 + kk])
+                    : TC(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int rep = 0; rep < kPer; ++rep) {
+      const int t = static_cast<int>(threadIdx.x) + rep * nth;
+      if (t < MT * kGenKC) sM[t / kGenKC][t % kGenKC] = mv[rep];
+    }
+    __syncthreads();
+    if (active) {
+      const int kend = static_cast<int>((ke - k0) < kGenKC ? (ke - k0) : kGenKC);
+      for (int kk0 = 0; kk0 < kend; kk0 += kXB) {
+        TC xv[kXB];
+#pragma unroll
+        for (int u = 0; u < kXB; ++u)
+          xv[u] = (kk0 + u < kend) ? static_cast<TC>(Load<TX>::get(xp, (k0 + kk0 + u) * B)) : TC(0);
+#pragma unroll
+        for (int u = 0; u < kXB; ++u)
+#pragma unroll
+          for (int ii = 0; ii < MT; ++ii) acc[ii] = fma(sM[ii][kk0 + u], xv[u], acc[ii]);
+      }
+    }
+  }
+}
+
 template <typename TX, typename TC, int MT>
 __global__ __launch_bounds__(kGenThreads) void ttm_generic_kernel(const TX* __restrict__ X, int64_t A, int64_t K,
                                                                   int64_t B, const TC* __restrict__ M, int64_t m,
@@ -36,24 +81,7 @@ __global__ __launch_bounds__(kGenThreads) void ttm_generic_kernel(const TX* __re
   TC acc[MT];
 #pragma unroll
   for (int ii = 0; ii < MT; ++ii) acc[ii] = TC(0);
-  const TX* xp = X + a * K * B + b;
-  for (int64_t k0 = kb; k0 < ke; k0 += kGenKC) {
-    __syncthreads();
-    for (int t = threadIdx.x; t < MT * kGenKC; t += blockDim.x) {
-      const int ii = t / kGenKC, kk = t % kGenKC;
-      sM[ii][kk] = (i0 + ii < m && k0 + kk < ke) ? (mtrans ? M[(k0 + kk) * m + i0 + ii] : M[(i0 + ii) * K + k0 + kk])
-                                                 : TC(0);
-    }
-    __syncthreads();
-    if (active) {
-      const int kend = static_cast<int>((ke - k0) < kGenKC ? (ke - k0) : kGenKC);
-      for (int kk = 0; kk < kend; ++kk) {
-        const TC x = static_cast<TC>(Load<TX>::get(xp, (k0 + kk) * B));
-#pragma unroll
-        for (int ii = 0; ii < MT; ++ii) acc[ii] = fma(sM[ii][kk], x, acc[ii]);
-      }
-    }
-  }
+  generic_accumulate<TX, TC, MT>(X + a * K * B + b, B, M, m, K, i0, kb, ke, mtrans, active, sM, acc);
   if (active) {
     TC* y = Y + static_cast<int64_t>(blockIdx.z) * A * m * B;
 #pragma unroll
@@ -128,24 +156,7 @@ __global__ __launch_bounds__(kWave) void ttm_grouped_kernel(const GTtmJob* __res
   TC acc[MT];
 #pragma unroll
   for (int ii = 0; ii < MT; ++ii) acc[ii] = TC(0);
-  const TX* xp = X + a * K * B + b;
-  for (int64_t k0 = 0; k0 < K; k0 += kGenKC) {
-    __syncthreads();
-    for (int t = threadIdx.x; t < MT * kGenKC; t += kWave) {
-      const int ii = t / kGenKC, kk = t % kGenKC;
-      sM[ii][kk] = (i0 + ii < m && k0 + kk < K) ? (J.mtrans ? M[(k0 + kk) * m + i0 + ii] : M[(i0 + ii) * K + k0 + kk])
-                                                : TC(0);
-    }
-    __syncthreads();
-    if (active) {
-      const int kend = static_cast<int>((K - k0) < kGenKC ? (K - k0) : kGenKC);
-      for (int kk = 0; kk < kend; ++kk) {
-        const TC x = static_cast<TC>(Load<TX>::get(xp, (k0 + kk) * B));
-#pragma unroll
-        for (int ii = 0; ii < MT; ++ii) acc[ii] = fma(sM[ii][kk], x, acc[ii]);
-      }
-    }
-  }
+  generic_accumulate<TX, TC, MT>(X + a * K * B + b, B, M, m, K, i0, 0, K, J.mtrans, active, sM, acc);
   if (active) {
     TC* y = static_cast<TC*>(J.Y);
 #pragma unroll
@@ -161,10 +172,11 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMfmaThreads = 256;  // 4 waves, one 128-column unit each
 constexpr int kUnitCols = 128;
+constexpr bool kPrefetchF32 = true;  // binary32 kernel: next k block loaded during the products
 
 // Work unit = (a, 128-column chunk, k-split part).  Y (or a split-K partial) is
 // written for rows i < m only.
-template <int MT>
+template <int MT, bool VM>
 __global__ __launch_bounds__(kMfmaThreads) void ttm_mfma_f32_kernel(const float* __restrict__ X, int64_t A, int64_t K,
                                                                     int64_t B, const float* __restrict__ Mop,
                                                                     int64_t m, int64_t chunks, int ksplit,
@@ -192,27 +204,72 @@ __global__ __launch_bounds__(kMfmaThreads) void ttm_mfma_f32_kernel(const float*
   const float* xa = X + a * K * B;
   const bool colok0 = (b0 + 4 * j) < B;
   const bool colok1 = (b0 + 64 + 4 * j) < B;
-  const int64_t Mpad = MT * 16;
-  for (int64_t k0 = kbeg; k0 < kend; k0 += 4) {
-    const int64_t k = k0 + q;
-    f32x4 x0 = f32x4{0.f, 0.f, 0.f, 0.f}, x1 = f32x4{0.f, 0.f, 0.f, 0.f};
-    if (k < kend) {
-      const float* row = xa + k * B + b0 + 4 * j;
-      if (colok0) x0 = *reinterpret_cast<const f32x4*>(row);
-      if (colok1) x1 = *reinterpret_cast<const f32x4*>(row + 64);
+  // The wave takes k in blocks of 16.  Product s of a block sums over the four k that
+  // lane groups q = 0..3 hold, k = k0 + 4 q + s, so a lane's share of the M tile for the
+  // whole block is four consecutive k: one 16-byte load per tile when K % 4 == 0 (VM).
+  // The lane loads the X rows k0 + 4 q + s (s = 0..3), columns b0 + 4 j .. and
+  // b0 + 64 + 4 j ...  Loads carry no conditions: a row past kend reads row kend - 1 and
+  // is zeroed before use, and a lane past B reads column b0 (its products land only in
+  // output columns that are not stored).
+  const int64_t c0off = colok0 ? b0 + 4 * j : b0, c1off = colok1 ? b0 + 64 + 4 * j : b0;
+  const f32x4 zero4 = f32x4{0.f, 0.f, 0.f, 0.f};
+  f32x4 n0[4], n1[4];
+  float nw[MT][4];
+  const auto load_block = [&](int64_t k0) {
+    const int64_t kl = k0 + 4 * q;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int64_t kc = (kl + s < kend) ? kl + s : kend - 1;
+      n0[s] = *reinterpret_cast<const f32x4*>(xa + kc * B + c0off);
+      n1[s] = *reinterpret_cast<const f32x4*>(xa + kc * B + c1off);
     }
-    float mv[MT];
+    if constexpr (VM) {
+      // kl is a multiple of 4, so kl < kend <= K gives kl <= K - 4; a block past K reads
+      // the last four k of the row instead (zeroed before use)
+      const int64_t km = (kl <= K - 4) ? kl : K - 4;
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) mv[mt] = (k < kend) ? Mop[(mt * 16 + j) * K + k] : 0.f;
-    (void)Mpad;
+      for (int mt = 0; mt < MT; ++mt) {
+        const f32x4 v = *reinterpret_cast<const f32x4*>(Mop + (mt * 16 + j) * K + km);
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
+        for (int s = 0; s < 4; ++s) nw[mt][s] = v[s];
+      }
+    } else {
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        acc[mt][0][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(mv[mt], x0[t], acc[mt][0][t], 0, 0, 0);
-        acc[mt][1][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(mv[mt], x1[t], acc[mt][1][t], 0, 0, 0);
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) nw[mt][s] = Mop[(mt * 16 + j) * K + ((kl + s < kend) ? kl + s : kend - 1)];
+    }
+  };
+  if (kbeg < kend) load_block(kbeg);
+  for (int64_t k0 = kbeg; k0 < kend; k0 += 16) {
+    f32x4 y0[4], y1[4];
+    float w[4][MT];
+    const int64_t kl = k0 + 4 * q;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const bool kin = kl + s < kend;
+      y0[s] = kin ? n0[s] : zero4;
+      y1[s] = kin ? n1[s] : zero4;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) w[s][mt] = kin ? nw[mt][s] : 0.f;
+    }
+    // the next block's loads go out before this block's products (the scheduler may
+    // move neither the operand take-over below them nor them into the products)
+    __builtin_amdgcn_sched_barrier(0);
+    if (kPrefetchF32) load_block(k0 + 16);  // past kend: rows kend - 1 again, never used
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          acc[mt][0][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[s][mt], y0[s][t], acc[mt][0][t], 0, 0, 0);
+          acc[mt][1][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[s][mt], y1[s][t], acc[mt][1][t], 0, 0, 0);
+        }
       }
     }
+    if (!kPrefetchF32 && k0 + 16 < kend) load_block(k0 + 16);
   }
   float* ya = Y + (static_cast<int64_t>(ks) * A + a) * m * B;
 #pragma unroll
@@ -477,9 +534,14 @@ hipError_t launch_ttm_mfma_ws(const void* X, rt_dtype xdt, int64_t A, int64_t K,
   const unsigned grid = static_cast<unsigned>(ceil_div(units, kMfmaThreads / kWave));
   const int MT = static_cast<int>(ttm_mfma_mpad(m) / 16);
 #define RT_LAUNCH_F32(MTV)                                                                                  \
-  ttm_mfma_f32_kernel<MTV><<<grid, kMfmaThreads, 0, st>>>(static_cast<const float*>(X), A, K, B,            \
-                                                          static_cast<const float*>(Mop), m, p.chunks,      \
-                                                          p.ksplit, p.kper, out)
+  if (K % 4 == 0)                                                                                           \
+    ttm_mfma_f32_kernel<MTV, true><<<grid, kMfmaThreads, 0, st>>>(static_cast<const float*>(X), A, K, B,    \
+                                                                  static_cast<const float*>(Mop), m,        \
+                                                                  p.chunks, p.ksplit, p.kper, out);         \
+  else                                                                                                      \
+    ttm_mfma_f32_kernel<MTV, false><<<grid, kMfmaThreads, 0, st>>>(static_cast<const float*>(X), A, K, B,   \
+                                                                   static_cast<const float*>(Mop), m,       \
+                                                                   p.chunks, p.ksplit, p.kper, out)
 #define RT_LAUNCH_BF16(MTV)                                                                                 \
   ttm_mfma_bf16_kernel<MTV><<<grid, kMfmaThreads, 0, st>>>(static_cast<const bf16_t*>(X), A, K, B,          \
                                                            static_cast<const bf16_t*>(Mop), m, p.chunks,    \
