@@ -252,14 +252,17 @@ void sketch_impl(Ctx& c, const Ten& X, const double* const* phi, const int64_t* 
 }
 
 // G = T x_k U_k^T over the modes of mask, largest first; U_k: I_k x l_k binary64.
-Ten core_impl(Ctx& c, const Ten& X, const double* const* U, const int64_t* l, uint32_t mask, void* dst) {
+// With f64_out, a last contraction on the matrix-core last-mode kernel writes the core as
+// binary64 directly (the same values the separate widening would give).
+Ten core_impl(Ctx& c, const Ten& X, const double* const* U, const int64_t* l, uint32_t mask, void* dst,
+              bool f64_out = false) {
   const int d = static_cast<int>(X.dims.size());
   std::vector<int> order;
   for (int k = 0; k < d; ++k)
     if (mask >> k & 1u) order.push_back(k);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return X.dims[a] > X.dims[b]; });
   // plan every contraction first so that all operand roundings go out in one launch
-  struct Step { int k; int64_t A, K, B, m; rt_dtype in_dt; bool mfma, last; const void* op; void* y; void* w; };
+  struct Step { int k; int64_t A, K, B, m; rt_dtype in_dt; bool mfma, last, wide; const void* op; void* y; void* w; };
   std::vector<Step> steps;
   std::vector<int64_t> dims = X.dims;
   rt_dtype cur_dt = X.dt;
@@ -274,17 +277,19 @@ Ten core_impl(Ctx& c, const Ten& X, const double* const* U, const int64_t* l, ui
     st.m = l[k];
     st.in_dt = cur_dt;
     const rt_dtype ct = ctype(cur_dt);
-    st.y = (last && dst) ? dst : c.take(static_cast<size_t>(st.A) * st.m * st.B * dtype_size(ct));
     st.mfma = (cur_dt == RT_F32 || cur_dt == RT_BF16) && ttm_mfma_ok(cur_dt, st.A, st.K, st.B, st.m);
     // a binary32 contraction over the last mode (B = 1) runs on the matrix-core kernel
     // for contiguous rows
     st.last = !st.mfma && cur_dt == RT_F32 && st.B == 1 && ttm_mfma_last_ok(st.A, st.K, st.m);
+    st.wide = last && f64_out && st.last && !dst;
+    st.y = (last && dst) ? dst
+                         : c.take(static_cast<size_t>(st.A) * st.m * st.B * (st.wide ? sizeof(double) : dtype_size(ct)));
     if (st.mfma) {
       st.op = prep(c, U ? U[k] : nullptr, st.m, st.K, true, cur_dt, cur_dt, ttm_mfma_mpad(st.m));
       st.w = c.take(ttm_mfma_ws(cur_dt, st.A, st.K, st.B, st.m));
     } else if (st.last) {
       st.op = prep(c, U ? U[k] : nullptr, st.m, st.K, true, RT_F32, RT_F32, ttm_mfma_mpad(st.m));
-      st.w = c.take(ttm_mfma_last_ws(st.A, st.K, st.m));
+      st.w = c.take(ttm_mfma_last_ws(st.A, st.K, st.m, st.wide));
     } else {
       st.op = prep(c, U ? U[k] : nullptr, st.m, st.K, true, cur_dt == RT_F64 ? RT_F64 : cur_dt, ct);
       st.w = c.take(ttm_generic_ws(cur_dt, st.A, st.K, st.B, st.m));
@@ -301,14 +306,15 @@ Ten core_impl(Ctx& c, const Ten& X, const double* const* U, const int64_t* l, ui
         c.chk(launch_ttm_mfma_ws(cur.p, cur.dt, st.A, st.K, st.B, st.op, st.m, static_cast<float*>(st.y), st.w, c.st));
       else if (st.last)
         c.chk(launch_ttm_mfma_last(static_cast<const float*>(cur.p), st.A, st.K, static_cast<const float*>(st.op), st.m,
-                                   static_cast<float*>(st.y), st.w, c.st));
+                                   st.wide ? nullptr : static_cast<float*>(st.y), st.w, c.st,
+                                   st.wide ? static_cast<double*>(st.y) : nullptr));
       else
         c.chk(launch_ttm_generic(cur.p, cur.dt, st.A, st.K, st.B, st.op, st.m, st.y, st.w, c.st));
     }
     Ten out;
     out.dims = cur.dims;
     out.dims[st.k] = st.m;
-    out.dt = ctype(cur.dt);
+    out.dt = st.wide ? RT_F64 : ctype(cur.dt);
     out.p = st.y;
     cur = out;
   }
@@ -629,7 +635,7 @@ int plan_decompose(Ctx& c, const rt_tensor* X, const rt_tensor* Xs, const int32_
     void* w = c.take(qr_ws(jobs.data(), d));
     c.flush();
     if (!c.dry) c.chk(launch_qr(jobs.data(), d, ctype(Tsk.dt), w, c.st));
-    cur = core_impl(c, cur, Uhat.data(), cdim.data(), (1u << d) - 1u, nullptr);
+    cur = core_impl(c, cur, Uhat.data(), cdim.data(), (1u << d) - 1u, nullptr, /*f64_out=*/true);
   } else {
     for (int j = 0; j < d; ++j) {
       std::vector<int64_t> sj(s.begin() + j * d, s.begin() + (j + 1) * d);
@@ -642,7 +648,7 @@ int plan_decompose(Ctx& c, const rt_tensor* X, const rt_tensor* Xs, const int32_
       void* w = c.take(qr_ws(&job, 1));
       c.flush();
       if (!c.dry) c.chk(launch_qr(&job, 1, ctype(cur.dt), w, c.st));
-      cur = core_impl(c, cur, Uhat.data(), cdim.data(), 1u << j, nullptr);
+      cur = core_impl(c, cur, Uhat.data(), cdim.data(), 1u << j, nullptr, /*f64_out=*/j == d - 1);
     }
   }
   Ten G64 = to_f64(c, cur);

@@ -440,13 +440,15 @@ __global__ __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(2)
   }
 }
 
+// Y = sum of the split parts in part order (binary32), stored as TO
+template <typename TO>
 __global__ __launch_bounds__(256) void sum_splits_kernel(const float* __restrict__ part, int ksplit, int64_t n,
-                                                         float* __restrict__ Y) {
+                                                         TO* __restrict__ Y) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * 256;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n; i += stride) {
     float s = part[i];
     for (int k = 1; k < ksplit; ++k) s += part[k * n + i];
-    Y[i] = s;
+    Y[i] = static_cast<TO>(s);
   }
 }
 
@@ -567,7 +569,7 @@ hipError_t launch_ttm_mfma_ws(const void* X, rt_dtype xdt, int64_t A, int64_t K,
   if (e != hipSuccess || p.ksplit == 1) return e;
   const int64_t n = A * m * B;
   const unsigned g2 = static_cast<unsigned>(ceil_div(n, 256) > 8192 ? 8192 : ceil_div(n, 256));
-  sum_splits_kernel<<<g2, 256, 0, st>>>(out, p.ksplit, n, Y);
+  sum_splits_kernel<float><<<g2, 256, 0, st>>>(out, p.ksplit, n, Y);
   return hipGetLastError();
 }
 
@@ -589,15 +591,15 @@ LastPlan last_plan(int64_t A, int64_t K, int64_t m) {
 }
 }  // namespace
 
-size_t ttm_mfma_last_ws(int64_t A, int64_t K, int64_t m) {
+size_t ttm_mfma_last_ws(int64_t A, int64_t K, int64_t m, bool f64_out) {
   const LastPlan p = last_plan(A, K, m);
-  return p.ksplit == 1 ? 0 : align256(static_cast<size_t>(p.ksplit) * A * m * sizeof(float));
+  return (p.ksplit == 1 && !f64_out) ? 0 : align256(static_cast<size_t>(p.ksplit) * A * m * sizeof(float));
 }
 
 hipError_t launch_ttm_mfma_last(const float* X, int64_t A, int64_t K, const float* Mop, int64_t m, float* Y,
-                                void* ws, hipStream_t st) {
+                                void* ws, hipStream_t st, double* Y64) {
   const LastPlan p = last_plan(A, K, m);
-  float* out = (p.ksplit == 1) ? Y : static_cast<float*>(ws);
+  float* out = (p.ksplit == 1 && !Y64) ? Y : static_cast<float*>(ws);
   const int64_t units = ceil_div(A, 64) * p.ksplit;
   const unsigned grid = static_cast<unsigned>(ceil_div(units, kMfmaThreads / kWave));
   const int MT = static_cast<int>(ttm_mfma_mpad(m) / 16);
@@ -611,10 +613,13 @@ hipError_t launch_ttm_mfma_last(const float* X, int64_t A, int64_t K, const floa
   }
 #undef RT_LAUNCH_LAST
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || p.ksplit == 1) return e;
+  if (e != hipSuccess || (p.ksplit == 1 && !Y64)) return e;
   const int64_t n = A * m;
   const unsigned g2 = static_cast<unsigned>(ceil_div(n, 256) > 8192 ? 8192 : ceil_div(n, 256));
-  sum_splits_kernel<<<g2, 256, 0, st>>>(out, p.ksplit, n, Y);
+  if (Y64)
+    sum_splits_kernel<double><<<g2, 256, 0, st>>>(out, p.ksplit, n, Y64);
+  else
+    sum_splits_kernel<float><<<g2, 256, 0, st>>>(out, p.ksplit, n, Y);
   return hipGetLastError();
 }
 

@@ -74,10 +74,13 @@ hipError_t launch_ttm_mfma_ws(const void* X, rt_dtype xdt, int64_t A, int64_t K,
 
 // Matrix-core contraction of the last mode (B == 1): Y[a, i] = sum_k X[a, k] Mop[i, k],
 // X binary32 A x K row-major, Mop packed to ttm_mfma_mpad(m) rows; K % 4 == 0, m <= 64.
+// With Y64 given, the result is written as binary64 there instead (the binary32 sum of
+// the split parts, widened exactly), and Y is not used; the workspace query then needs
+// f64_out set.
 bool ttm_mfma_last_ok(int64_t A, int64_t K, int64_t m);
-size_t ttm_mfma_last_ws(int64_t A, int64_t K, int64_t m);
+size_t ttm_mfma_last_ws(int64_t A, int64_t K, int64_t m, bool f64_out = false);
 hipError_t launch_ttm_mfma_last(const float* X, int64_t A, int64_t K, const float* Mop, int64_t m, float* Y,
-                                void* ws, hipStream_t st);
+                                void* ws, hipStream_t st, double* Y64 = nullptr);
 
 // ------------------------------------------------------------------ k_sketch.hip
 // First level of the sketch dimension tree over X viewed as (A, P, Q):
