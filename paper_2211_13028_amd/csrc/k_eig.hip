@@ -920,12 +920,18 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
       F(U1, n - 1, m) = 0.0;
       F(U2, n - 1, m) = 0.0;
     }
-    for (int i = 0; i < n; ++i) F(ZZ, i, m) = start_value(i, m);
+    // Each solve reads the previous iterate scaled by 2^-ez (exact), where 2^ez brackets
+    // its largest entry, so no separate rescaling pass is needed; the first forward
+    // substitution takes the start vector as it goes.
+    int ez = 0;
     for (int it = 0; it < kInvIters; ++it) {
-      double yi = F(ZZ, 0, m);
+      const auto rhs = [&](int i) {
+        return it == 0 ? start_value(i, m) : __builtin_amdgcn_ldexp(F(ZZ, i, m), -ez);
+      };
+      double yi = rhs(0);
 #pragma unroll 4
       for (int i = 0; i + 1 < n; ++i) {
-        const double yn = F(ZZ, i + 1, m), mm = F(ML, i, m);
+        const double yn = rhs(i + 1), mm = F(ML, i, m);
         const bool sw = (piv >> i) & 1ull;
         F(ZZ, i, m) = sw ? yn : yi;
         yi = sw ? fma(-mm, yn, yi) : fma(-mm, yi, yn);
@@ -940,20 +946,18 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
         z1 = zi;
         mx = fmax(mx, fabs(zi));
       }
-      const int ez = (mx > 0.0) ? __builtin_amdgcn_frexp_exp(mx) : 0;
-#pragma unroll 4
-      for (int i = 0; i < n; ++i) F(ZZ, i, m) = __builtin_amdgcn_ldexp(F(ZZ, i, m), -ez);
+      ez = (mx > 0.0) ? __builtin_amdgcn_frexp_exp(mx) : 0;
     }
     double s0 = 0.0, s1 = 0.0;
 #pragma unroll 4
     for (int i = 0; i < n; ++i) {
-      const double zi = F(ZZ, i, m);
+      const double zi = __builtin_amdgcn_ldexp(F(ZZ, i, m), -ez);
       if (i & 1) s1 = fma(zi, zi, s1); else s0 = fma(zi, zi, s0);
     }
     const double ss = s0 + s1;
     const double inv = (ss > 0.0) ? rsq_refined(ss) : 0.0;
 #pragma unroll 4
-    for (int i = 0; i < n; ++i) F(ZZ, i, m) *= inv;
+    for (int i = 0; i < n; ++i) F(ZZ, i, m) = __builtin_amdgcn_ldexp(F(ZZ, i, m), -ez) * inv;
   }
   __syncthreads();
   // ---- 4. orthogonality check E = Z^T Z - I (upper triangle) and residual check
@@ -993,8 +997,13 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
   }
   if (!(emax <= 1.0)) emax = 1.0;  // NaN or large: rejected below
   if (!(rmax <= 1.0)) rmax = 1.0;
-  atomicMax(&ebits, static_cast<unsigned long long>(__double_as_longlong(emax)));
-  atomicMax(&rbits, static_cast<unsigned long long>(__double_as_longlong(rmax)));
+  // wave maxima first: one LDS atomic per wave instead of one per thread on a single word
+  emax = wave_max_f64(emax);
+  rmax = wave_max_f64(rmax);
+  if (lane == 0) {
+    atomicMax(&ebits, static_cast<unsigned long long>(__double_as_longlong(emax)));
+    atomicMax(&rbits, static_cast<unsigned long long>(__double_as_longlong(rmax)));
+  }
   __syncthreads();
   const double em = __longlong_as_double(static_cast<long long>(ebits));
   const double rm = __longlong_as_double(static_cast<long long>(rbits));
