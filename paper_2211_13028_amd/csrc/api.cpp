@@ -214,39 +214,74 @@ void sketch_impl(Ctx& c, const Ten& X, const double* const* phi, const int64_t* 
     if (needZ) Z = ttm(c, X, L, op[L], s[L]);
     if (needW) W = ttm(c, X, S, op[S], s[S]);
   }
-  auto tree_ttm = [&](const Ten& cur, int k) -> Ten {
-    const int64_t Ab = cur.before(k), K = cur.dims[k], Bb = cur.after(k), m = s[k];
-    bool mf = false, last = false;
-    tree_kind(cur.dims, k, mf, last);
-    if (!mf && !last) return ttm(c, cur, k, op[k], m);
-    if (!opm[k]) opm[k] = prep(c, phi ? phi[k] : nullptr, m, K, false, X.dt, RT_F32, ttm_mfma_mpad(m));
-    Ten o;
-    o.dims = cur.dims;
-    o.dims[k] = m;
-    o.dt = RT_F32;
-    o.p = c.take(static_cast<size_t>(Ab) * m * Bb * sizeof(float));
-    void* w = c.take(last ? ttm_mfma_last_ws(Ab, K, m) : ttm_mfma_ws(RT_F32, Ab, K, Bb, m));
+  // second and later levels of the tree: the contractions of one level are independent,
+  // so the binary32 matrix-core ones go out as one grouped launch
+  std::vector<Ten> cur(d);
+  std::vector<std::vector<int>> chains(d);
+  size_t levels = 0;
+  for (int n = 0; n < d; ++n) {
+    if (!(mask >> n & 1u)) continue;
+    cur[n] = (n == S) ? Z : W;
+    chains[n] = chain_of(n);
+    levels = std::max(levels, chains[n].size());
+  }
+  for (size_t lev = 0; lev < levels; ++lev) {
+    std::vector<F32Contraction> group;
+    std::vector<int> generic_modes, last_modes;
+    std::vector<void*> last_ws;
+    std::vector<Ten> next = cur;
+    for (int n = 0; n < d; ++n) {
+      if (!(mask >> n & 1u) || chains[n].size() <= lev) continue;
+      const int k = chains[n][lev];
+      const Ten& t = cur[n];
+      const int64_t Ab = t.before(k), K = t.dims[k], Bb = t.after(k), m = s[k];
+      bool mf = false, last = false;
+      tree_kind(t.dims, k, mf, last);
+      if (!mf && !last) {
+        generic_modes.push_back(n);
+        continue;
+      }
+      if (!opm[k]) opm[k] = prep(c, phi ? phi[k] : nullptr, m, K, false, X.dt, RT_F32, ttm_mfma_mpad(m));
+      Ten o;
+      o.dims = t.dims;
+      o.dims[k] = m;
+      o.dt = RT_F32;
+      o.p = c.take(static_cast<size_t>(Ab) * m * Bb * sizeof(float));
+      void* w = c.take(last ? ttm_mfma_last_ws(Ab, K, m) : ttm_mfma_ws(RT_F32, Ab, K, Bb, m));
+      next[n] = o;
+      if (last) {
+        last_modes.push_back(n);
+        last_ws.push_back(w);
+      } else {
+        group.push_back(F32Contraction{static_cast<const float*>(t.p), Ab, K, Bb, static_cast<const float*>(opm[k]), m,
+                                       static_cast<float*>(const_cast<void*>(o.p)), w});
+      }
+    }
     c.flush();
     if (!c.dry) {
-      float* y = static_cast<float*>(const_cast<void*>(o.p));
-      if (last)
-        c.chk(launch_ttm_mfma_last(static_cast<const float*>(cur.p), Ab, K, static_cast<const float*>(opm[k]), m, y,
-                                   w, c.st));
-      else
-        c.chk(launch_ttm_mfma_ws(cur.p, RT_F32, Ab, K, Bb, opm[k], m, y, w, c.st));
+      for (size_t i = 0; i < last_modes.size(); ++i) {
+        const int n = last_modes[i], k = chains[n][lev];
+        const Ten& t = cur[n];
+        c.chk(launch_ttm_mfma_last(static_cast<const float*>(t.p), t.before(k), t.dims[k],
+                                   static_cast<const float*>(opm[k]), s[k],
+                                   static_cast<float*>(const_cast<void*>(next[n].p)), last_ws[i], c.st));
+      }
+      c.chk(launch_ttm_mfma_f32_group(group.data(), static_cast<int>(group.size()), c.st));
     }
-    return o;
-  };
+    for (int n : generic_modes) {
+      const int k = chains[n][lev];
+      next[n] = ttm(c, cur[n], k, op[k], s[k]);
+    }
+    cur = next;
+  }
   out.assign(d, SketchOut{});
   for (int n = 0; n < d; ++n) {
     if (!(mask >> n & 1u)) continue;
-    Ten cur = (n == S) ? Z : W;
-    for (int k : chain_of(n)) cur = tree_ttm(cur, k);
     SketchOut o;
-    o.Y = cur;
-    o.A = cur.before(n);
-    o.m = cur.dims[n];
-    o.B = cur.after(n);
+    o.Y = cur[n];
+    o.A = cur[n].before(n);
+    o.m = cur[n].dims[n];
+    o.B = cur[n].after(n);
     out[n] = o;
   }
 }

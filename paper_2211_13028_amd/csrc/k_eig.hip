@@ -1037,7 +1037,8 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
     __syncthreads();
   }
   // ---- 5. V = H_0 ... H_{n-3} Z: 16 lanes per column, 4 rows per lane, reflectors applied
-  //         last to first with the next reflector's entries loaded ahead; then the sign rule
+  //         last to first, two per reduction round, with the next pair's entries loaded
+  //         ahead; then the sign rule
   //         (largest |entry|, first on ties, positive) by a group argmax.
   {
     const int gm = tid / kPairLanes, sb = tid % kPairLanes;
@@ -1055,27 +1056,56 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
         vr[t] = (row == k + 1) ? 1.0 : ((row > k + 1 && row < n) ? a : 0.0);
       }
     };
-    double vn[kPairRows];
-    double tn = 0.0;
-    if (n >= 3) {
-      vload(n - 3, vn);
-      tn = tauS[n - 3];
-    }
-    for (int k = n - 3; k >= 0; --k) {
+    // reflectors n - 3 .. 0; an odd one out goes first, the rest in pairs (k, k - 1):
+    // with a = v_k^T z, b = v_{k-1}^T z and c = v_{k-1}^T v_k from one reduction round,
+    // H_{k-1} H_k z = z - f_k v_k - f_{k-1} v_{k-1}, f_k = tau_k a,
+    // f_{k-1} = tau_{k-1} (b - f_k c)
+    int k = n - 3;
+    if ((n - 2) & 1) {
       double vr[kPairRows];
-#pragma unroll
-      for (int t = 0; t < kPairRows; ++t) vr[t] = vn[t];
-      const double tk = tn;
-      if (k > 0) {
-        vload(k - 1, vn);
-        tn = tauS[k - 1];
-      }
+      vload(k, vr);
       double sacc = 0.0;
 #pragma unroll
       for (int t = 0; t < kPairRows; ++t) sacc = fma(vr[t], zr[t], sacc);
-      const double f = tk * group16_sum(sacc);
+      const double f = tauS[k] * group16_sum(sacc);
 #pragma unroll
       for (int t = 0; t < kPairRows; ++t) zr[t] = fma(-f, vr[t], zr[t]);
+      --k;
+    }
+    double na[kPairRows], nb[kPairRows];
+    double nta = 0.0, ntb = 0.0;
+    if (k >= 1) {
+      vload(k, na);
+      vload(k - 1, nb);
+      nta = tauS[k];
+      ntb = tauS[k - 1];
+    }
+    for (; k >= 1; k -= 2) {
+      double va[kPairRows], vb[kPairRows];
+#pragma unroll
+      for (int t = 0; t < kPairRows; ++t) {
+        va[t] = na[t];
+        vb[t] = nb[t];
+      }
+      const double ta = nta, tb = ntb;
+      if (k >= 3) {
+        vload(k - 2, na);
+        vload(k - 3, nb);
+        nta = tauS[k - 2];
+        ntb = tauS[k - 3];
+      }
+      double a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll
+      for (int t = 0; t < kPairRows; ++t) {
+        a = fma(va[t], zr[t], a);
+        b = fma(vb[t], zr[t], b);
+        c = fma(vb[t], va[t], c);
+      }
+      group16_sum3(a, b, c);
+      const double fa = ta * a;
+      const double fb = tb * fma(-fa, c, b);
+#pragma unroll
+      for (int t = 0; t < kPairRows; ++t) zr[t] = fma(-fb, vb[t], fma(-fa, va[t], zr[t]));
     }
     // group argmax of |entry| with the first row on ties
     double best = -1.0;
@@ -1111,16 +1141,11 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
 #pragma unroll
       for (int t = 0; t < kPairRows; ++t) {
         const int row = kPairRows * sb + t;
-        if (row < n) F(ZZ, row, gm) = sg * zr[t];
+        if (row < n) Vout[row * r + gm] = sg * zr[t];
       }
     }
   }
   if (evals && tid < r) evals[tid] = __builtin_amdgcn_ldexp(lamS[tid], ex);
-  __syncthreads();
-  for (int q = tid; q < n * r; q += kJThreads) {
-    const int i = q / r, m = q - (q / r) * r;
-    Vout[q] = F(ZZ, i, m);
-  }
   return true;
 }
 

@@ -176,15 +176,12 @@ constexpr bool kPrefetchF32 = true;  // binary32 kernel: next k block loaded dur
 
 // Work unit = (a, 128-column chunk, k-split part).  Y (or a split-K partial) is
 // written for rows i < m only.
+// One work unit (a wave) of the binary32 contraction; unit < A * chunks * ksplit.
 template <int MT, bool VM>
-__global__ __launch_bounds__(kMfmaThreads) void ttm_mfma_f32_kernel(const float* __restrict__ X, int64_t A, int64_t K,
-                                                                    int64_t B, const float* __restrict__ Mop,
-                                                                    int64_t m, int64_t chunks, int ksplit,
-                                                                    int64_t kper, float* __restrict__ Y) {
+__device__ __forceinline__ void ttm_f32_unit(const float* __restrict__ X, int64_t A, int64_t K, int64_t B,
+                                             const float* __restrict__ Mop, int64_t m, int64_t chunks, int ksplit,
+                                             int64_t kper, float* __restrict__ Y, int64_t unit) {
   const int lane = threadIdx.x % kWave;
-  const int64_t unit = static_cast<int64_t>(blockIdx.x) * (kMfmaThreads / kWave) + threadIdx.x / kWave;
-  const int64_t total = A * chunks * ksplit;
-  if (unit >= total) return;
   const int ks = static_cast<int>(unit % ksplit);
   const int64_t ac = unit / ksplit;
   const int64_t a = ac / chunks;
@@ -287,6 +284,66 @@ __global__ __launch_bounds__(kMfmaThreads) void ttm_mfma_f32_kernel(const float*
         }
       }
     }
+  }
+}
+
+template <int MT, bool VM>
+__global__ __launch_bounds__(kMfmaThreads) void ttm_mfma_f32_kernel(const float* __restrict__ X, int64_t A, int64_t K,
+                                                                    int64_t B, const float* __restrict__ Mop,
+                                                                    int64_t m, int64_t chunks, int ksplit,
+                                                                    int64_t kper, float* __restrict__ Y) {
+  const int64_t unit = static_cast<int64_t>(blockIdx.x) * (kMfmaThreads / kWave) + threadIdx.x / kWave;
+  if (unit >= A * chunks * ksplit) return;
+  ttm_f32_unit<MT, VM>(X, A, K, B, Mop, m, chunks, ksplit, kper, Y, unit);
+}
+
+// Independent binary32 contractions of one shape class in one launch: job q owns the
+// units [unit0_q, unit0_q + A_q chunks_q ksplit_q).
+struct F32Job {
+  const float* X;
+  const float* Mop;
+  float* out;
+  int64_t A, K, B, m, chunks, kper, unit0;
+  int ksplit;
+};
+struct F32JobTable {
+  F32Job j[kMaxF32Group];
+  int count;
+};
+template <int MT, bool VM>
+__global__ __launch_bounds__(kMfmaThreads) void ttm_mfma_f32_grouped_kernel(F32JobTable tab) {
+  const int64_t unit = static_cast<int64_t>(blockIdx.x) * (kMfmaThreads / kWave) + threadIdx.x / kWave;
+  int q = 0;
+  for (int t = 1; t < tab.count; ++t)
+    if (unit >= tab.j[t].unit0) q = t;
+  const F32Job& J = tab.j[q];
+  const int64_t local = unit - J.unit0;
+  if (local >= J.A * J.chunks * J.ksplit) return;
+  ttm_f32_unit<MT, VM>(J.X, J.A, J.K, J.B, J.Mop, J.m, J.chunks, J.ksplit, J.kper, J.out, local);
+}
+
+// Split sums of several jobs in one launch: job q covers the flat indices [off_q, off_q + n_q).
+struct SumJob {
+  const float* part;
+  float* Y;
+  int64_t n, off;
+  int ksplit;
+};
+struct SumJobTable {
+  SumJob j[kMaxF32Group];
+  int count;
+};
+__global__ __launch_bounds__(256) void sum_splits_grouped_kernel(SumJobTable tab, int64_t total) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * 256;
+  for (int64_t g = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; g < total; g += stride) {
+    int q = 0;
+    for (int t = 1; t < tab.count; ++t)
+      if (g >= tab.j[t].off) q = t;
+    const SumJob& J = tab.j[q];
+    const int64_t i = g - J.off;
+    float acc = J.part[i];
+    for (int k = 1; k < J.ksplit; ++k) acc += J.part[k * J.n + i];
+    J.Y[i] = acc;
   }
 }
 
@@ -570,6 +627,75 @@ hipError_t launch_ttm_mfma_ws(const void* X, rt_dtype xdt, int64_t A, int64_t K,
   const int64_t n = A * m * B;
   const unsigned g2 = static_cast<unsigned>(ceil_div(n, 256) > 8192 ? 8192 : ceil_div(n, 256));
   sum_splits_kernel<float><<<g2, 256, 0, st>>>(out, p.ksplit, n, Y);
+  return hipGetLastError();
+}
+
+hipError_t launch_ttm_mfma_f32_group(const F32Contraction* c, int count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  // one launch needs one kernel instance: every job with the same tile count and M load
+  int mt0 = -1;
+  bool vm0 = true, same = count <= kMaxF32Group;
+  for (int i = 0; i < count && same; ++i) {
+    const int mt = static_cast<int>(ttm_mfma_mpad(c[i].m) / 16);
+    const bool vm = c[i].K % 4 == 0;
+    if (i == 0) {
+      mt0 = mt;
+      vm0 = vm;
+    } else if (mt != mt0 || vm != vm0) {
+      same = false;
+    }
+  }
+  if (!same || count == 1) {
+    for (int i = 0; i < count; ++i) {
+      const hipError_t e =
+          launch_ttm_mfma_ws(c[i].X, RT_F32, c[i].A, c[i].K, c[i].B, c[i].Mop, c[i].m, c[i].Y, c[i].ws, st);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  F32JobTable tab{};
+  SumJobTable sums{};
+  tab.count = count;
+  int64_t units = 0, sum_total = 0;
+  for (int i = 0; i < count; ++i) {
+    const MfmaPlan p = mfma_plan(RT_F32, c[i].A, c[i].K, c[i].B, c[i].m);
+    F32Job& J = tab.j[i];
+    J.X = c[i].X;
+    J.Mop = c[i].Mop;
+    J.out = (p.ksplit == 1) ? c[i].Y : static_cast<float*>(c[i].ws);
+    J.A = c[i].A; J.K = c[i].K; J.B = c[i].B; J.m = c[i].m;
+    J.chunks = p.chunks;
+    J.kper = p.kper;
+    J.ksplit = p.ksplit;
+    J.unit0 = units;
+    units += c[i].A * p.chunks * p.ksplit;
+    if (p.ksplit > 1) {
+      SumJob& S = sums.j[sums.count++];
+      S.part = J.out;
+      S.Y = c[i].Y;
+      S.n = c[i].A * c[i].m * c[i].B;
+      S.off = sum_total;
+      S.ksplit = p.ksplit;
+      sum_total += S.n;
+    }
+  }
+  const unsigned grid = static_cast<unsigned>(ceil_div(units, kMfmaThreads / kWave));
+#define RT_LAUNCH_GROUP(MTV)                                                                     \
+  if (vm0)                                                                                       \
+    ttm_mfma_f32_grouped_kernel<MTV, true><<<grid, kMfmaThreads, 0, st>>>(tab);                  \
+  else                                                                                           \
+    ttm_mfma_f32_grouped_kernel<MTV, false><<<grid, kMfmaThreads, 0, st>>>(tab)
+  switch (mt0) {
+    case 1: RT_LAUNCH_GROUP(1); break;
+    case 2: RT_LAUNCH_GROUP(2); break;
+    case 3: RT_LAUNCH_GROUP(3); break;
+    default: RT_LAUNCH_GROUP(4); break;
+  }
+#undef RT_LAUNCH_GROUP
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || sums.count == 0) return e;
+  const unsigned g2 = static_cast<unsigned>(ceil_div(sum_total, 256) > 8192 ? 8192 : ceil_div(sum_total, 256));
+  sum_splits_grouped_kernel<<<g2, 256, 0, st>>>(sums, sum_total);
   return hipGetLastError();
 }
 

@@ -72,6 +72,20 @@ size_t ttm_mfma_ws(rt_dtype xdt, int64_t A, int64_t K, int64_t B, int64_t m);
 hipError_t launch_ttm_mfma_ws(const void* X, rt_dtype xdt, int64_t A, int64_t K, int64_t B,
                               const void* Mop, int64_t m, float* Y, void* ws, hipStream_t st);
 
+// Several independent binary32 contractions (X binary32, M packed as above) in one kernel
+// launch plus one launch for their split sums; jobs whose tile count or M alignment differ
+// from the first job's run as separate launches.
+constexpr int kMaxF32Group = 8;
+struct F32Contraction {
+  const float* X;
+  int64_t A, K, B;
+  const float* Mop;
+  int64_t m;
+  float* Y;
+  void* ws;  // ttm_mfma_ws(RT_F32, A, K, B, m) bytes
+};
+hipError_t launch_ttm_mfma_f32_group(const F32Contraction* c, int count, hipStream_t st);
+
 // Matrix-core contraction of the last mode (B == 1): Y[a, i] = sum_k X[a, k] Mop[i, k],
 // X binary32 A x K row-major, Mop packed to ttm_mfma_mpad(m) rows; K % 4 == 0, m <= 64.
 // With Y64 given, the result is written as binary64 there instead (the binary32 sum of
