@@ -156,7 +156,25 @@ __global__ __launch_bounds__(kWave) void ttm_grouped_kernel(const GTtmJob* __res
   TC acc[MT];
 #pragma unroll
   for (int ii = 0; ii < MT; ++ii) acc[ii] = TC(0);
-  generic_accumulate<TX, TC, MT>(X + a * K * B + b, B, M, m, K, i0, 0, K, J.mtrans, active, sM, acc);
+  // compact loops (few registers, several waves per SIMD for the many small jobs of a batch)
+  const TX* xp = X + a * K * B + b;
+  for (int64_t k0 = 0; k0 < K; k0 += kGenKC) {
+    __syncthreads();
+    for (int t = threadIdx.x; t < MT * kGenKC; t += kWave) {
+      const int ii = t / kGenKC, kk = t % kGenKC;
+      sM[ii][kk] = (i0 + ii < m && k0 + kk < K) ? (J.mtrans ? M[(k0 + kk) * m + i0 + ii] : M[(i0 + ii) * K + k0 + kk])
+                                                : TC(0);
+    }
+    __syncthreads();
+    if (active) {
+      const int kend = static_cast<int>((K - k0) < kGenKC ? (K - k0) : kGenKC);
+      for (int kk = 0; kk < kend; ++kk) {
+        const TC x = static_cast<TC>(Load<TX>::get(xp, (k0 + kk) * B));
+#pragma unroll
+        for (int ii = 0; ii < MT; ++ii) acc[ii] = fma(sM[ii][kk], x, acc[ii]);
+      }
+    }
+  }
   if (active) {
     TC* y = static_cast<TC*>(J.Y);
 #pragma unroll
