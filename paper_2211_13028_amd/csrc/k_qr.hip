@@ -38,6 +38,14 @@ struct QRTaskTable {
   QRTask t[kMaxTasks];
 };
 
+// Offset of column j (< 64) of the mode unfolding of an (A, m, B) view: column j = a B + b
+// starts at a m B + b and advances by B per row.  Each thread computes it once for its
+// column; j < 64, so a 32-bit division does (and none when B > j).
+__device__ __forceinline__ int64_t col_offset(int j, int64_t m, int64_t B) {
+  const int a = (B > j) ? 0 : j / static_cast<int>(B);
+  return static_cast<int64_t>(a) * m * B + (j - static_cast<int64_t>(a) * B);
+}
+
 template <typename TY>
 __device__ __forceinline__ void small_qr_body(const QRTask& T) {
   __shared__ double Y[kRowsMax * kCols];
@@ -53,14 +61,15 @@ __device__ __forceinline__ void small_qr_body(const QRTask& T) {
   const int c = rows < n ? rows : n;
   const TY* src = static_cast<const TY*>(T.src);
 
-  // load (zero padded), coalesced along the source's contiguous index
+  // load (zero padded), coalesced along the source's contiguous index; a thread keeps one
+  // column (kQRThreads is a multiple of kCols)
+  static_assert(kQRThreads % kCols == 0, "one column per thread in the load");
+  const int lj = static_cast<int>(threadIdx.x) % kCols;
+  const TY* scol = src + col_offset(lj, T.m, T.B) + T.row0 * T.B;
   for (int idx = threadIdx.x; idx < kRowsMax * kCols; idx += kQRThreads) {
-    const int r = idx / kCols, j = idx % kCols;
+    const int r = idx / kCols, j = lj;
     double v = 0.0;
-    if (r < rows && j < n) {
-      const int64_t a = j / T.B, b = j - a * T.B;
-      v = static_cast<double>(src[a * T.m * T.B + (T.row0 + r) * T.B + b]);
-    }
+    if (r < rows && j < n) v = static_cast<double>(scol[r * T.B]);
     Y[r * kCols + j] = v;
   }
   __syncthreads();
@@ -250,11 +259,6 @@ struct CTabPtr {
   __device__ const CJob& operator[](int i) const { return p[i]; }
 };
 
-template <typename TY>
-__device__ __forceinline__ double cq_src(const CJob& J, int64_t r, int j) {
-  const int64_t a = j / J.B, b = j - a * J.B;
-  return static_cast<double>(static_cast<const TY*>(J.Y)[a * J.m * J.B + r * J.B + b]);
-}
 
 // partial Gram of one 64-row chunk of Y (first pass)
 template <typename TY, typename TAB>
@@ -268,11 +272,12 @@ __global__ __launch_bounds__(256) void cq_gram_kernel(TAB tab) {
   // thread: column j of rows rr0 + 4 q; every load is issued before the first LDS store
   constexpr int kPer = kGramRows * kCols / 256;
   const int j = static_cast<int>(threadIdx.x) % kCols, rr0 = static_cast<int>(threadIdx.x) / kCols;
+  const TY* ys = static_cast<const TY*>(J.Y) + col_offset(j, J.m, J.B);
   double yv[kPer];
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
     const int64_t r = r0 + rr0 + 4 * q;
-    yv[q] = (r < J.m && j < J.n) ? cq_src<TY>(J, r, j) : 0.0;
+    yv[q] = (r < J.m && j < J.n) ? static_cast<double>(ys[r * J.B]) : 0.0;
   }
 #pragma unroll
   for (int q = 0; q < kPer; ++q) sy[rr0 + 4 * q][j] = yv[q];
@@ -437,13 +442,14 @@ __global__ __launch_bounds__(256) void cq_apply_kernel(TAB tab, int second) {
     // thread: column j of rows rr0 + 4 q; every load is issued before the first LDS store
     constexpr int kPer = kGramRows * kCols / 256;
     const int j = static_cast<int>(threadIdx.x) % kCols, rr0 = static_cast<int>(threadIdx.x) / kCols;
+    const TY* ys = static_cast<const TY*>(J.Y) + col_offset(j, J.m, J.B);
     double yv[kPer], xv[kPer];
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       const int rr = rr0 + 4 * q;
       const int64_t r = r0 + rr;
       double v = 0.0;
-      if (r < J.m && j < n) v = second ? J.Q1[r * n + j] : cq_src<TY>(J, r, j);
+      if (r < J.m && j < n) v = second ? J.Q1[r * n + j] : static_cast<double>(ys[r * J.B]);
       yv[q] = v;
       xv[q] = Xg[rr * kCols + j];
     }
