@@ -388,18 +388,34 @@ __global__ __launch_bounds__(kMfmaThreads) void ttm_mfma_f32_last_kernel(const f
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int at = 0; at < 4; ++at) acc[mt][at] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int64_t k0 = kbeg; k0 < kend; k0 += 16) {
+  // The next 16 k are loaded while the current ones are multiplied.  Loads carry no
+  // conditions: k past kend reads the last four k of the range (zeroed before use; kbeg and
+  // kend are multiples of 4), and a row past A reads row A - 1 (its products land only in
+  // output rows that are not stored).
+  f32x4 nx[4], nw[MT];
+  const auto load = [&](int64_t k0) {
     const int64_t k = k0 + 4 * q;
-    const bool kin = k < kend;
-    f32x4 xv[4], mv[MT];
+    const int64_t kc = (k < kend) ? k : kend - 4;
 #pragma unroll
     for (int at = 0; at < 4; ++at) {
       const int64_t a = a0 + 16 * at + r16;
-      xv[at] = (kin && a < A) ? *reinterpret_cast<const f32x4*>(X + a * K + k) : f32x4{0.f, 0.f, 0.f, 0.f};
+      nx[at] = *reinterpret_cast<const f32x4*>(X + ((a < A) ? a : A - 1) * K + kc);
     }
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-      mv[mt] = kin ? *reinterpret_cast<const f32x4*>(Mop + (16 * mt + r16) * K + k) : f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int mt = 0; mt < MT; ++mt) nw[mt] = *reinterpret_cast<const f32x4*>(Mop + (16 * mt + r16) * K + kc);
+  };
+  if (kbeg < kend) load(kbeg);
+  const f32x4 zero4 = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t k0 = kbeg; k0 < kend; k0 += 16) {
+    const bool kin = k0 + 4 * q < kend;
+    f32x4 xv[4], mv[MT];
+#pragma unroll
+    for (int at = 0; at < 4; ++at) xv[at] = kin ? nx[at] : zero4;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) mv[mt] = kin ? nw[mt] : zero4;
+    __builtin_amdgcn_sched_barrier(0);
+    load(k0 + 16);  // past kend: clamped, never used
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
