@@ -119,10 +119,13 @@ hipError_t generic_dispatch(const TX* X, int64_t A, int64_t K, int64_t B, const 
   const int ks = generic_ksplit(A, K, B);
   const int64_t kper = ceil_div(K, ks);
   TC* out = (ks > 1) ? ws : Y;
-  if (m <= 4) {
-    ttm_generic_kernel<TX, TC, 4><<<dim3(gx, 1, ks), threads, 0, st>>>(X, A, K, B, M, m, kper, mtrans, out);
+  if (m <= 4 || threads == kWave) {
+    // (few output columns: 4-row tiles, so that more waves share the rows of m)
+    const unsigned gy = static_cast<unsigned>(ceil_div(m, 4));
+    ttm_generic_kernel<TX, TC, 4><<<dim3(gx, gy, ks), threads, 0, st>>>(X, A, K, B, M, m, kper, mtrans, out);
   } else if (m <= 8) {
-    ttm_generic_kernel<TX, TC, 8><<<dim3(gx, 1, ks), threads, 0, st>>>(X, A, K, B, M, m, kper, mtrans, out);
+    const unsigned gy = static_cast<unsigned>(ceil_div(m, 8));
+    ttm_generic_kernel<TX, TC, 8><<<dim3(gx, gy, ks), threads, 0, st>>>(X, A, K, B, M, m, kper, mtrans, out);
   } else {
     const unsigned gy = static_cast<unsigned>(ceil_div(m, 16));
     ttm_generic_kernel<TX, TC, 16><<<dim3(gx, gy, ks), threads, 0, st>>>(X, A, K, B, M, m, kper, mtrans, out);
