@@ -353,7 +353,11 @@ __global__ __launch_bounds__(256) void cq_chol_kernel(TAB tab, int second) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, off));
   bool broke = false;
-  for (int k = 0; k < n; ++k) {
+  // the loop is unrolled over k, so the owner of the next pivot row stores that row alone
+  // (its register slot is static), and the other steps' stores are skipped
+#pragma clang loop unroll(full)
+  for (int k = 0; k < kCols; ++k) {
+    if (k >= n || broke) continue;  // uniform
     const double lk = fullL[k][lane], rk = fullR[k][lane];
     double li[kRows];
 #pragma unroll
@@ -367,7 +371,7 @@ __global__ __launch_bounds__(256) void cq_chol_kernel(TAB tab, int second) {
         static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(__double_as_longlong(dj) & 0xffffffff), k)));
     if (!(d > 1e-13 * dmax) || !(dmax > 0.0)) {  // uniform: every lane holds the same d
       broke = true;
-      break;
+      continue;
     }
     const double inv_s = rsq_refined(d);
     const double lj = lk * inv_s, xj = rk * inv_s;
@@ -384,13 +388,9 @@ __global__ __launch_bounds__(256) void cq_chol_kernel(TAB tab, int second) {
       gr[t] = fma(-mult, xj, gr[t]);
     }
     if (lane > k) dj = fma(-lj, lj, dj);
-    const int nk = k + 1;
-    if (nk < n && wv == nk / kRows) {
-#pragma unroll
-      for (int t = 0; t < kRows; ++t) {
-        fullL[kRows * wv + t][lane] = gl[t];
-        fullR[kRows * wv + t][lane] = gr[t];
-      }
+    if (k + 1 < n && wv == (k + 1) / kRows) {
+      fullL[k + 1][lane] = gl[(k + 1) % kRows];
+      fullR[k + 1][lane] = gr[(k + 1) % kRows];
     }
     __syncthreads();
   }
