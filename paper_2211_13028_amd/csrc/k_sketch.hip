@@ -179,16 +179,6 @@ struct BlockIO<f8_t> {
 };
 
 template <typename TX>
-__device__ __forceinline__ void load_block(const TX* xa, int64_t Q, int64_t p0, int64_t pend, int64_t qc, bool colok,
-                                           typename BlockIO<TX>::raw_t (&r)[8]) {
-#pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    const int64_t p = p0 + t;
-    r[t] = (colok && p < pend) ? BlockIO<TX>::load(xa + p * Q + qc) : BlockIO<TX>::zero();
-  }
-}
-
-template <typename TX>
 __global__ __launch_bounds__(kZWThreads) __attribute__((amdgpu_waves_per_eu(3))) void sketch_zw_bf16_mfma_kernel(
     const TX* __restrict__ X, int64_t A, int64_t P, int64_t Q, const bf16_t* __restrict__ phiP, int sP,
     const bf16_t* __restrict__ phiQ, int sQ, int64_t rows_per_block, int qblocks, int pblocks,
@@ -225,31 +215,39 @@ __global__ __launch_bounds__(kZWThreads) __attribute__((amdgpu_waves_per_eu(3)))
 #pragma unroll
   for (int c = 0; c < 8; ++c) wacc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+  // Lane (li, kg) loads rows p0 + 8 kg + t (t < 8), columns qc..qc+7.  Loads carry no
+  // conditions: an 8-row group past pend reads the last 8 rows of the range and a column
+  // group past qend the last 8 columns of the block (8-row groups lie wholly inside or
+  // outside [pbeg, pend) because P % 8 == 0 and steps are 32 rows; Q % 8 == 0); such
+  // values are zeroed when the block is taken over.
+  const int64_t qcc = colok ? qc : qend - 8;
+  // The PhiP operand of the W product (row c = li, columns pc .. pc + 7) comes with the
+  // rows, clamped and zeroed the same way.
   typename BlockIO<TX>::raw_t rn[8];
-  load_block(xa, Q, pbeg + 8 * kg, pend, qc, colok, rn);
+  u32x4 ppn = u32x4{0u, 0u, 0u, 0u};
+  const auto load = [&](int64_t pb) {
+    const int64_t p = pb + 8 * kg;
+    const int64_t pc = (p < pend) ? p : pend - 8;
+    // without W the load reads an entry of PhiQ (in bounds: Z is then computed) and is unused
+    ppn = ld16(needW ? phiP + static_cast<int64_t>(li) * P + pc : phiQ + static_cast<int64_t>(li) * Q + (qend - 8));
+#pragma unroll
+    for (int t = 0; t < 8; ++t) rn[t] = BlockIO<TX>::load(xa + (pc + t) * Q + qcc);
+  };
+  if (pbeg < pend) load(pbeg);
   int buf = 0;
   for (int64_t pb = pbeg; pb < pend; pb += 32) {
+    const int64_t pc = pb + 8 * kg;
+    const bool in = colok && pc < pend;
     u32x4 r[8];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) r[t] = BlockIO<TX>::widen(rn[t]);
-    if (pb + 32 < pend) load_block(xa, Q, pb + 32 + 8 * kg, pend, qc, colok, rn);
-    if (needW) {
-      // PhiP operand: row c = li, columns pb + 8 kg .. + 7 (8-row groups lie wholly
-      // inside or outside [pbeg, pend) because P % 8 == 0 and steps are 32 rows)
-      const int64_t pc = pb + 8 * kg;
-      const u32x4 pp = (pc < pend) ? ld16(phiP + static_cast<int64_t>(li) * P + pc) : u32x4{0u, 0u, 0u, 0u};
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        u32x4 op;
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-          const uint32_t lo = r[2 * w][c / 2], hi = r[2 * w + 1][c / 2];
-          op[w] = (c % 2 == 0) ? ((lo & 0xffffu) | (hi << 16)) : ((lo >> 16) | (hi & 0xffff0000u));
-        }
-        wacc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, pp),
-                                                          __builtin_bit_cast(bf16x8, op), wacc[c], 0, 0, 0);
-      }
+    for (int t = 0; t < 8; ++t) {
+      const u32x4 w = BlockIO<TX>::widen(rn[t]);
+      r[t] = in ? w : u32x4{0u, 0u, 0u, 0u};
     }
+    const u32x4 pp = (pc < pend) ? ppn : u32x4{0u, 0u, 0u, 0u};
+    __builtin_amdgcn_sched_barrier(0);
+    load(pb + 32);  // past pend: clamped, never used
+    __builtin_amdgcn_sched_barrier(0);
     if (needZ) {
       __builtin_amdgcn_wave_barrier();  // the previous step's reads of the staging area stay above
 #pragma unroll
@@ -279,6 +277,19 @@ __global__ __launch_bounds__(kZWThreads) __attribute__((amdgpu_waves_per_eu(3)))
       for (int w = 1; w < kZWWaves; ++w) z += zpart[buf][w][row * 16 + c];
       if (c < sQ && p < pend) Zo[((static_cast<int64_t>(qblk) * A + a) * P + p) * sQ + c] = z;
       buf ^= 1;
+    }
+    if (needW) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        u32x4 op;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          const uint32_t lo = r[2 * w][c / 2], hi = r[2 * w + 1][c / 2];
+          op[w] = (c % 2 == 0) ? ((lo & 0xffffu) | (hi << 16)) : ((lo >> 16) | (hi & 0xffff0000u));
+        }
+        wacc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, pp),
+                                                          __builtin_bit_cast(bf16x8, op), wacc[c], 0, 0, 0);
+      }
     }
   }
   if (!needW || !colok) return;

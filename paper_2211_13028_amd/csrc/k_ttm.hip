@@ -473,34 +473,33 @@ __global__ __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(2)
   const bf16_t* xa = X + a * K * B;
   const int64_t col = b0 + 8 * j;
   const bool colok = col < B;
-  // lane loads rows k0 + 8q + t, columns col..col+7; the next step's rows are loaded
-  // while the current ones are multiplied
-  u32x4 rn[8];
+  // Lane loads rows k0 + 8q + t (t < 8) of columns col..col+7 and the matching 8 k of M.
+  // The next 32 k are loaded while the current ones are multiplied.  Loads carry no
+  // conditions: a block past kend reads the last 8 k of the range (zeroed before use; kbeg
+  // and kend are multiples of 8), and a column block past B reads the last 8 columns (its
+  // products land only in output columns that are not stored).
+  const int64_t colc = colok ? col : B - 8;
+  u32x4 rn[8], nw[MT];
+  const auto load = [&](int64_t k0) {
+    const int64_t k = k0 + 8 * q;
+    const int64_t kc = (k < kend) ? k : kend - 8;
 #pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    const int64_t k = kbeg + 8 * q + t;
-    rn[t] = u32x4{0u, 0u, 0u, 0u};
-    if (colok && k < kend) rn[t] = *reinterpret_cast<const u32x4*>(xa + k * B + col);
-  }
+    for (int mt = 0; mt < MT; ++mt) nw[mt] = *reinterpret_cast<const u32x4*>(Mop + (mt * 16 + j) * K + kc);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) rn[t] = *reinterpret_cast<const u32x4*>(xa + (kc + t) * B + colc);
+  };
+  if (kbeg < kend) load(kbeg);
+  const u32x4 zero4 = u32x4{0u, 0u, 0u, 0u};
   for (int64_t k0 = kbeg; k0 < kend; k0 += 32) {
-    u32x4 r[8];
+    const bool kin = k0 + 8 * q < kend;
+    u32x4 r[8], mv[MT];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) r[t] = rn[t];
-    if (k0 + 32 < kend) {
+    for (int t = 0; t < 8; ++t) r[t] = kin ? rn[t] : zero4;
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int64_t k = k0 + 32 + 8 * q + t;
-        rn[t] = u32x4{0u, 0u, 0u, 0u};
-        if (colok && k < kend) rn[t] = *reinterpret_cast<const u32x4*>(xa + k * B + col);
-      }
-    }
-    u32x4 mv[MT];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      const int64_t kk = k0 + 8 * q;
-      mv[mt] = u32x4{0u, 0u, 0u, 0u};
-      if (kk < kend) mv[mt] = *reinterpret_cast<const u32x4*>(Mop + (mt * 16 + j) * K + kk);
-    }
+    for (int mt = 0; mt < MT; ++mt) mv[mt] = kin ? nw[mt] : zero4;
+    __builtin_amdgcn_sched_barrier(0);
+    load(k0 + 32);  // past kend: clamped, never used
+    __builtin_amdgcn_sched_barrier(0);
     // operand for column c (8 consecutive k of column col + c) is packed just before its
     // products, which keeps the register count low enough for two waves per SIMD
 #pragma unroll
