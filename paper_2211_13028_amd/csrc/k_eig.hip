@@ -710,7 +710,7 @@ __device__ __forceinline__ int sturm_count(const double* __restrict__ d, const d
 
 constexpr int kP1Waves = 4;
 constexpr int kP1Cols = kJN / kP1Waves;  // matrix columns held in registers per wave
-static_assert(kTriB >= 4 * kP1Waves * kJN + kJN, "phase-1 scratch must fit");
+static_assert(kTriB >= 4 * kP1Waves * kJN + 2 * kJN, "phase-1 scratch must fit");
 
 // Returns true (uniformly over the workgroup) when V and evals were written.
 __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n, int r, double* __restrict__ Vout,
@@ -727,12 +727,12 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
   const double dmax = wave_max_f64(lane < n ? fabs(M[lane * n + lane]) : 0.0);
   if (!(dmax > 0.0) || !(dmax < 1e300)) return false;  // zero or non-finite: Jacobi path
   const int ex = __builtin_amdgcn_frexp_exp(dmax);
-  // scratch in B: per-wave copies of v and w (in slot order, see below), partial products,
-  // and the column that the next reflector is formed from
+  // scratch in B: per-wave copies of v and w (in slot order, see below), partial products
+  // and the published column, both double-buffered by the parity of the step
   double* vbuf = B;                               // [wave][kJN]
   double* wbuf = B + kP1Waves * kJN;              // [wave][kJN]
-  double* part = B + 2 * kP1Waves * kJN;          // [wave][kJN]
-  double* colbuf = B + 4 * kP1Waves * kJN;        // [kJN]
+  double* part = B + 2 * kP1Waves * kJN;          // [2][wave][kJN]
+  double* colbuf = B + 4 * kP1Waves * kJN;        // [2][kJN]
   for (int idx = tid; idx < kJN * kAStride; idx += kJThreads) Am[idx] = 0.0;
   if (tid == 0) {
     ebits = 0;
@@ -743,10 +743,16 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
   //         reduction.  The matrix-vector product and the rank-2 update touch LDS only for
   //         broadcast reads of v and w, which each wave stores in slot order (entry j at
   //         (j % 4) 16 + j / 4); v stays in registers from the product to the update.
-  //         After the update of step k the wave that owns column k + 1 publishes that
-  //         column alone, and every wave forms the next reflector from it.  Rows and
-  //         columns past n are zero and carry v = w = 0; finished columns (j <= k) see
-  //         v_j = w_j = 0 and keep their values.
+  //         Every wave keeps column k, the one the reflector of step k is formed from, in
+  //         a register.  The wave that owns column k + 1 publishes it as it stands before
+  //         step k, together with its partial products; after the step's one barrier every
+  //         wave applies the step's rank-2 update to that copy with the same operands and
+  //         the same fused operations as the owner, so all copies agree bitwise and no
+  //         second barrier is needed.  The LDS areas written in a step alternate with the
+  //         parity of k: a wave writes an area again only two steps later, after every wave
+  //         has passed the barrier that follows its reads.  Rows and columns past n are zero
+  //         and carry v = w = 0; finished columns (j <= k) see v_j = w_j = 0 and keep their
+  //         values.
   const bool worker = wv < kP1Waves;
   const int slot_of_lane = (lane % kP1Waves) * kP1Cols + lane / kP1Waves;
   double ar[kP1Cols];
@@ -755,14 +761,18 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
     const int j = kP1Waves * t + wv;
     ar[t] = (worker && lane < n && j < n) ? __builtin_amdgcn_ldexp(M[lane * n + j], -ex) : 0.0;
   }
-  if (wv == 0) colbuf[lane] = ar[0];
+  // column 0 goes through the slot that step 1 writes, so step 0's write cannot overtake it
+  if (wv == 0) colbuf[kJN + lane] = ar[0];
   __syncthreads();
+  double xc = worker ? colbuf[kJN + lane] : 0.0;  // column k
   for (int k = 0; k + 2 < n; ++k) {
     const bool live = lane > k && lane < n;
+    double* partb = part + (k & 1) * (kP1Waves * kJN);
+    double* colb = colbuf + (k & 1) * kJN;
     double sigma = 0.0, tk = 0.0, v = 0.0;
     double vv[kP1Cols];
     if (worker) {
-      const double x = live ? colbuf[lane] : 0.0;
+      const double x = live ? xc : 0.0;
       sigma = wave_sum_f64((lane > k + 1 && lane < n) ? x * x : 0.0);
       const double alpha = readlane_f64(x, k + 1);
       double ek = alpha;
@@ -792,22 +802,31 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
         }
         acc = a0 + a1;
       }
-      part[wv * kJN + lane] = acc;
+      partb[wv * kJN + lane] = acc;
+      if (wv == (k + 1) % kP1Waves) {  // column k + 1 before this step's update
+        const int s = (k + 1) / kP1Waves;
+#pragma unroll
+        for (int t = 0; t < kP1Cols; ++t)
+          if (t == s) colb[lane] = ar[t];
+      }
       if (wv == 0) {
+        const double dk = readlane_f64(xc, k);
         if (lane > k + 1 && lane < n) Am[lane * kAStride + k] = v;  // Householder vector below the subdiagonal
         if (lane == 0) {
           tauS[k] = tk;
           eS[k] = ek;
-          dS[k] = colbuf[k];
+          dS[k] = dk;
         }
       }
     }
     __syncthreads();
     if (worker) {
+      const double cb = colb[lane];
+      double xn = cb;
       if (sigma != 0.0) {
         double p = 0.0;
 #pragma unroll
-        for (int w2 = 0; w2 < kP1Waves; ++w2) p += part[w2 * kJN + lane];
+        for (int w2 = 0; w2 < kP1Waves; ++w2) p += partb[w2 * kJN + lane];
         p = live ? tk * p : 0.0;
         const double K = 0.5 * tk * wave_sum_f64(p * v);
         const double w = fma(-K, v, p);
@@ -820,17 +839,14 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
           ar[t] = fma(-v, wj.x, fma(-w, vv[t], ar[t]));
           ar[t + 1] = fma(-v, wj.y, fma(-w, vv[t + 1], ar[t + 1]));
         }
+        // column k + 1 after the update, formed exactly as its owner forms it
+        const int sl = ((k + 1) % kP1Waves) * kP1Cols + (k + 1) / kP1Waves;
+        xn = fma(-v, myw[sl], fma(-w, vbuf[wv * kJN + sl], cb));
       }
-      if (wv == (k + 1) % kP1Waves) {
-        const int s = (k + 1) / kP1Waves;
-#pragma unroll
-        for (int t = 0; t < kP1Cols; ++t)
-          if (t == s) colbuf[lane] = ar[t];
-      }
+      xc = xn;
     }
-    __syncthreads();
   }
-  // the last 2 x 2 block: column n - 2 is published; A[n-1][n-1] sits with its owner
+  // the last 2 x 2 block: column n - 2 is in xc; A[n-1][n-1] sits with its owner
   if (wv == (n - 1) % kP1Waves && lane == n - 1) {
     const int slot = (n - 1) / kP1Waves;
     double c = ar[0];
@@ -838,9 +854,12 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
     for (int t = 1; t < kP1Cols; ++t) c = (t == slot) ? ar[t] : c;
     dS[n - 1] = c;
   }
-  if (tid == 0) {
-    dS[n - 2] = colbuf[n - 2];
-    eS[n - 2] = colbuf[n - 1];
+  if (wv == 0) {
+    const double d2 = readlane_f64(xc, n - 2), e2 = readlane_f64(xc, n - 1);
+    if (lane == 0) {
+      dS[n - 2] = d2;
+      eS[n - 2] = e2;
+    }
   }
   __syncthreads();
   for (int i = tid; i < kPad; i += kJThreads) {
