@@ -68,6 +68,9 @@ SKETCH_CASES = [
     ((20, 24, 30), (4, 10, 3)),      # subrank > 8: generic first level
     ((4, 512, 264), (3, 7, 5)),      # bf16 matrix-core pass: 4 row blocks, ragged column tail
     ((16, 96, 1040), (2, 8, 8)),     # bf16 matrix-core pass: 3 column blocks
+    ((6, 72, 136), (3, 5, 7)),       # bf16 matrix-core pass: the last 32-row step ends past the rows
+                                     # (three of its 8-row groups are clamped and zeroed), and two
+                                     # of the four waves have no columns
     ((20, 18, 16, 12), (4, 4, 4, 4)),  # 4-way: one tree level's matrix-core contractions share one
                                        # launch, the next level's differ in K % 4 (one launch each)
 ]
