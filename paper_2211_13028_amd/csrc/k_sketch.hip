@@ -348,30 +348,43 @@ __global__ __launch_bounds__(kZWThreads) __attribute__((amdgpu_waves_per_eu(3)))
 #pragma unroll
     for (int c = 0; c < 4; ++c) wacc[j][c] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  auto load_step = [&](int64_t pb, f32x4 (&r)[4][2]) {
+  // The next step's rows and PhiP values are loaded while the current step is multiplied.
+  // Loads carry no per-lane conditions: a row past pend reads row pend - 1 and a column
+  // group past qend the last group of the block (Q % 4 == 0); such values are zeroed when
+  // the step is taken over.  Without W the PhiP load reads an entry of PhiQ (in bounds:
+  // Z is then computed) and is unused.
+  const int64_t qcc[2] = {ok[0] ? qc[0] : qend - 4, ok[1] ? qc[1] : qend - 4};
+  f32x4 rn[4][2];
+  float ppn[4];
+  auto load_step = [&](int64_t pb) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int64_t p = pb + 4 * t + kg;
+      const int64_t pc = (p < pend) ? p : pend - 1;
+      ppn[t] = *(needW ? phiP + static_cast<int64_t>(li) * P + pc : phiQ + static_cast<int64_t>(li) * Q + (qend - 4));
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-        r[t][j] = (ok[j] && p < pend) ? *reinterpret_cast<const f32x4*>(xa + p * Q + qc[j]) : f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int j = 0; j < 2; ++j) rn[t][j] = *reinterpret_cast<const f32x4*>(xa + pc * Q + qcc[j]);
     }
   };
-  f32x4 rn[4][2];
-  load_step(pbeg, rn);
+  load_step(pbeg);
   int buf = 0;
   for (int64_t pb = pbeg; pb < pend; pb += 16) {
     f32x4 r[4][2];
+    float ppv[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < 4; ++t) {
+      const bool pin = pb + 4 * t + kg < pend;
 #pragma unroll
-      for (int j = 0; j < 2; ++j) r[t][j] = rn[t][j];
-    if (pb + 16 < pend) load_step(pb + 16, rn);
+      for (int j = 0; j < 2; ++j) r[t][j] = (ok[j] && pin) ? rn[t][j] : f32x4{0.f, 0.f, 0.f, 0.f};
+      ppv[t] = pin ? ppn[t] : 0.f;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    load_step(pb + 16);  // past pend: clamped, never used
+    __builtin_amdgcn_sched_barrier(0);
     if (needW) {
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const int64_t p = pb + 4 * t + kg;
-        const float pp = (p < pend) ? phiP[static_cast<int64_t>(li) * P + p] : 0.f;
+        const float pp = ppv[t];
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -392,8 +405,8 @@ __global__ __launch_bounds__(kZWThreads) __attribute__((amdgpu_waves_per_eu(3)))
         // PhiQ[li][qw + 16 kb + 4 kg .. + 3]: a small operand re-read from the caches each step
         // (holding it in registers would cost the occupancy)
         const int64_t qk = qw + 16 * kb + 4 * kg;
-        const f32x4 bq = (qk < qend) ? *reinterpret_cast<const f32x4*>(phiQ + static_cast<int64_t>(li) * Q + qk)
-                                     : f32x4{0.f, 0.f, 0.f, 0.f};
+        f32x4 bq = *reinterpret_cast<const f32x4*>(phiQ + static_cast<int64_t>(li) * Q + ((qk < qend) ? qk : qend - 4));
+        if (!(qk < qend)) bq = f32x4{0.f, 0.f, 0.f, 0.f};
         const f32x4 xr = *reinterpret_cast<const f32x4*>(my + li * kF32Stride + 16 * kb + 4 * kg);
 #pragma unroll
         for (int c = 0; c < 4; ++c) zacc = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[c], bq[c], zacc, 0, 0, 0);
