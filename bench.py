@@ -90,8 +90,8 @@ def main():
                     help="skip the 128^4 rSTHKron, 256^3 adjoint and 512-tensor batch measurements")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note, "
-                                   "not an implemented path", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "rtucker runs on one GPU only; sharding across GPUs is described in the "
+                                   "design notes, not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
