@@ -1,0 +1,70 @@
+"""Host-side checks of bench.py's bookkeeping (no GPU): the HBM traffic read from the
+committed byte-counter summary is reported only while the counted kernel's source is the
+one the counters were taken on."""
+import hashlib
+import importlib.util
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture()
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def _tree(tmp_path, src_text, digest, kernel="sketch_pass_bf16", nbytes=1234567):
+    src = tmp_path / "k.hip"
+    src.write_text(src_text)
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "hbm_counters_sketch_pass_bf16_1024x1024x512.md").write_text(
+        "summary text\n\n"
+        f"traffic_kernel: {kernel}\n"
+        f"traffic_bytes_per_launch: {nbytes}\n"
+        f"source_sha256(k.hip): {digest}\n")
+    return src
+
+
+def test_traffic_reported_while_source_matches(bench, tmp_path, monkeypatch):
+    text = "kernel source\n"
+    _tree(tmp_path, text, hashlib.sha256(text.encode()).hexdigest())
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.counter_traffic("sketch_pass_bf16") == 1234567
+
+
+def test_traffic_withheld_once_source_changes(bench, tmp_path, monkeypatch):
+    text = "kernel source\n"
+    src = _tree(tmp_path, text, hashlib.sha256(text.encode()).hexdigest())
+    src.write_text(text + "// edited\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.counter_traffic("sketch_pass_bf16") is None
+
+
+def test_traffic_withheld_for_another_kernel(bench, tmp_path, monkeypatch):
+    text = "kernel source\n"
+    _tree(tmp_path, text, hashlib.sha256(text.encode()).hexdigest())
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.counter_traffic("core_ttm1_bf16") is None
+
+
+def test_traffic_withheld_without_summary(bench, tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.counter_traffic("sketch_pass_bf16") is None
+
+
+def test_committed_summary_is_well_formed(bench):
+    # the committed summary names the dominant kernel, a positive byte count and a source file
+    # that exists; whether its hash still matches depends on later edits and is not asserted
+    text = open(os.path.join(ROOT, "profiles", "hbm_counters_sketch_pass_bf16_1024x1024x512.md")).read()
+    assert re.search(r"^traffic_kernel: sketch_pass_bf16$", text, re.M)
+    m = re.search(r"^traffic_bytes_per_launch: (\d+)$", text, re.M)
+    assert m and int(m.group(1)) > 0
+    m = re.search(r"^source_sha256\((\S+)\): [0-9a-f]{64}$", text, re.M)
+    assert m and os.path.exists(os.path.join(ROOT, m.group(1)))
