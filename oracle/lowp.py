@@ -101,21 +101,24 @@ _ROUND = {"f64": lambda v: np.asarray(v, dtype=np.float64), "f32": round_f32,
 
 
 def rhkron_emulated(X, r, phis, sketch_fmt: str, ttm_fmt: str, *, return_parts: bool = False):
-    """Factor-reuse rHKron with low-precision rounding at the GPU's rounding points.
+    """Factor-reuse rHKron (Alg. 4.4, Sec. 4.3) with low-precision rounding at the GPU's rounding points.
 
     Sketch: X and every Phi_k rounded to ``sketch_fmt``; products exact (float64).
     QR, truncation: float64.  Core: the first contraction (largest mode) takes X
     and U_hat rounded to ``ttm_fmt``; its result is stored in binary32, and the
-    later contractions take binary32 operands.
+    later contractions take binary32 operands (the last one's result is kept in
+    float64, as the GPU writes the core in binary64).
     """
     rs, rt = _ROUND[sketch_fmt], _ROUND[ttm_fmt]
     X = np.asarray(X, dtype=np.float64)
     d = X.ndim
     Xs = rs(X)
     ph = [rs(p) for p in phis]
-    Uhat = []
+    Uhat, Ys = [], []
     for n in range(d):
-        Q, _ = T.qr_pos(T.kron_sketch(Xs, ph, n))
+        Y = T.kron_sketch(Xs, ph, n)
+        Q, _ = T.qr_pos(Y)
+        Ys.append(Y)
         Uhat.append(Q)
     order = T.core_order(X.shape)
     Ghat = T.ttm(rt(X), rt(Uhat[order[0]]).T, order[0])
@@ -127,5 +130,38 @@ def rhkron_emulated(X, r, phis, sketch_fmt: str, ttm_fmt: str, *, return_parts: 
     G, Vs = T.sthosvd(Ghat, r)
     Us = [Uh @ V for Uh, V in zip(Uhat, Vs)]
     if return_parts:
-        return G, Us, {"Uhat": Uhat, "Ghat": Ghat, "V": Vs}
+        return G, Us, {"Uhat": Uhat, "Ghat": Ghat, "V": Vs, "Y": Ys}
+    return G, Us
+
+
+def rsthkron_emulated(X, r, phis, fmt: str, *, return_parts: bool = False):
+    """Sequentially truncated rSTHKron (Alg. 4.3, Sec. 4.2) with low-precision rounding
+    at the GPU's rounding points.
+
+    The working core starts as X rounded to ``fmt``.  Step j (modes in order
+    1..d) computes in the dtype of the current core: at the first step that is
+    ``fmt``, afterwards binary32.  The step's factors Phi_{j,k} and its U_hat_j
+    are rounded to that dtype; the sketch products and the contraction are exact
+    (float64), the sketch's QR is float64, and the contracted core is stored in
+    binary32 (except after the last step, whose result the GPU writes in
+    binary64).  The final STHOSVD truncation is float64.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    d = X.ndim
+    lowp = fmt != "f64"
+    Ghat = _ROUND[fmt](X)
+    Uhat, Ys = [], []
+    for j in range(d):
+        rj = _ROUND[fmt] if (j == 0 or not lowp) else round_f32
+        Y = T.unfold(T.multi_ttm(Ghat, {k: rj(phis[j][k]) for k in range(d) if k != j}), j)
+        Q, _ = T.qr_pos(Y)
+        Ys.append(Y)
+        Uhat.append(Q)
+        Ghat = T.ttm(Ghat, rj(Q).T, j)
+        if lowp and j < d - 1:
+            Ghat = round_f32(Ghat)
+    G, Vs = T.sthosvd(Ghat, r)
+    Us = [Uh @ V for Uh, V in zip(Uhat, Vs)]
+    if return_parts:
+        return G, Us, {"Uhat": Uhat, "Ghat": Ghat, "V": Vs, "Y": Ys}
     return G, Us

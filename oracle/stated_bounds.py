@@ -35,7 +35,9 @@ def field_1024():
     sph = [flat[j * 3:(j + 1) * 3] for j in range(3)]
     Gs, Us = T.rsthkron(X, r, sph)
     es = T.rel_error(X, Gs, Us)
-    return {"1024x1024x512 rHKron": (e64, eb, e8), "1024x1024x512 rSTHKron": (es, None, None)}
+    Gsb, Usb = L.rsthkron_emulated(X, r, sph, "bf16")
+    esb = T.rel_error(X, Gsb, Usb)
+    return {"1024x1024x512 rHKron": (e64, eb, e8), "1024x1024x512 rSTHKron": (es, esb, None)}
 
 
 def tensor_128():
@@ -48,7 +50,8 @@ def tensor_128():
     flat = synth.gaussians(synth.PHI_SEED, [sh for row in shapes for sh in row])
     sph = [flat[j * 4:(j + 1) * 4] for j in range(4)]
     G, U = T.rsthkron(X, r, sph)
-    return {"128^4 rSTHKron": (T.rel_error(X, G, U), None, None)}
+    Gb, Ub = L.rsthkron_emulated(X, r, sph, "bf16")
+    return {"128^4 rSTHKron": (T.rel_error(X, G, U), T.rel_error(X, Gb, Ub), None)}
 
 
 def batch_512(count=512):
