@@ -47,7 +47,9 @@ typedef enum {
   RT_ESHAPE = -2,     /* dimensions, ranks or sketch sizes inconsistent or beyond limits */
   RT_EDTYPE = -3,     /* dtype not supported by this entry point */
   RT_EWORKSPACE = -4, /* workspace NULL, misaligned or smaller than the query's answer */
-  RT_ENONFINITE = -5, /* NaN or Inf found in an input (reported by rtucker_rel_error_host) */
+                      /* (-5 is not used: rtucker_rel_error counts non-finite input
+                          entries in its device output instead, since it does not
+                          synchronise) */
   RT_EHIP = -6        /* a HIP runtime call failed */
 } rt_status;
 
@@ -127,10 +129,13 @@ int rtucker_sketch_pass(const rt_tensor* X, const double* phi_prev, int64_t s_pr
                         size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------ QR
- * Thin QR of a tall-skinny sketch (range-finder QR, Alg. 2.3): Y = Q R with
- * Householder reflections in binary64 and diag(R) >= 0, so Q is unique when Y
- * has full column rank; for rank-deficient Y, Q is an orthonormal basis whose
- * leading columns span range(Y).
+ * Thin QR of a tall-skinny sketch (range-finder QR, Alg. 2.3): Y = Q R in
+ * binary64 with diag(R) >= 0, so Q is unique when Y has full column rank.
+ * Method: CholeskyQR2 (Gram matrix, Cholesky factor, Q = Y R^-1, twice); when a
+ * Cholesky pivot falls below 1e-13 of the largest diagonal entry (Y numerically
+ * rank deficient) the call switches, on the device, to Householder reflections
+ * (tall-skinny QR), for which Q is an orthonormal basis whose leading columns
+ * span range(Y).
  *  Y: device, m x n row-major, dtype F32 or F64 (read, widened to binary64).
  *  Q: device, binary64, m x c row-major, c = min(m, n).
  *  R: device, binary64, c x n row-major (upper triangular), or NULL.
@@ -158,9 +163,11 @@ int rtucker_core(const rt_tensor* X, const double* const* U, const int64_t* l,
 
 /* ------------------------------------------------------------------ decompose
  * Full randomized Tucker decomposition [G; U_1..U_d] of X at ranks r with
- * oversampling p (Alg. 4.3 or 3.4): sketches, QR, core, then the holistic
+ * oversampling p (Alg. 4.3 or Alg. 4.4): sketches, QR, core, then the holistic
  * truncation STHOSVD(G_hat, r) in mode order 1..d (Sec. 4.1) computed in
- * binary64 (Gram matrices + cyclic Jacobi), and U_j = U_hat_j V_j.
+ * binary64 (Gram matrix of each core unfolding, its r_j leading eigenvectors by
+ * Householder tridiagonalisation, bisection and inverse iteration, with one-sided
+ * Jacobi as the fallback), and U_j = U_hat_j V_j.
  *  X:        dtype F64, F32 or BF16.
  *  X_sketch: NULL, or a tensor with X's dims used for the sketch instead of X
  *            (e.g. an F8E4M3 copy); RT_RHKRON only.
@@ -187,7 +194,9 @@ int rtucker_decompose(const rt_tensor* X, const rt_tensor* X_sketch, const int32
  * Squared norms for the relative reconstruction error (Sec. 5), in binary64 on
  * the device, by explicit residual (no cancellation-prone identity):
  *   out[0] = ||X - G x_1 U_1 ... x_d U_d||^2,  out[1] = ||X||^2,
- *   out[2] = ||G||^2,  out[3] = number of non-finite entries of X (as double).
+ *   out[2] = ||G||^2,  out[3] = number of non-finite (NaN or +-Inf) entries of X,
+ *   as a double.  Non-finite entries are left out of out[0] and out[1], so a
+ *   caller that finds out[3] > 0 knows the two norms cover the finite part only.
  *  G: device binary64 r_1 x ... x r_d; U[j]: device binary64 I_j x r_j.
  *  out: device, 4 doubles.  X: dtype F64, F32 or BF16. */
 int rtucker_rel_error_workspace(const rt_tensor* X, const int32_t* r, size_t* bytes);

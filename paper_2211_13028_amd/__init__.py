@@ -334,8 +334,11 @@ def rtucker_decompose(X, r, p, phis, algo="rhkron", s=None, X_sketch=None, G=Non
     return G, Us
 
 
-def rtucker_rel_error(X, G, Us):
-    """(relative error, dict of squared norms) by explicit residual on the device (synchronises)."""
+def rtucker_rel_error(X, G, Us, allow_nonfinite: bool = False):
+    """(relative error, dict of squared norms) by explicit residual on the device (synchronises).
+
+    Raises RtuckerError when X holds NaN or Inf entries, unless ``allow_nonfinite``:
+    then the norms cover the finite entries and ``nonfinite`` counts the others."""
     torch = _torch()
     xt = _tensor(X)
     r = [int(v) for v in G.shape]
@@ -346,14 +349,16 @@ def rtucker_rel_error(X, G, Us):
     _check(lib().rtucker_rel_error(ctypes.byref(xt), _ptr(G), _i32(r), _ptrs(Us), _ptr(out), _ptr(ws), wb,
                                    _stream(X.device)), "rtucker_rel_error")
     v = out.cpu().tolist()
-    if v[3] > 0:
+    if v[3] > 0 and not allow_nonfinite:
         raise RtuckerError(f"input has {int(v[3])} non-finite entries")
-    return (v[0] / v[1]) ** 0.5, {"res2": v[0], "x2": v[1], "g2": v[2], "nonfinite": v[3]}
+    return (v[0] / v[1]) ** 0.5 if v[1] > 0 else float("nan"), {"res2": v[0], "x2": v[1], "g2": v[2], "nonfinite": v[3]}
 
 
 def rtucker_convert(src, dst_dtype, scale_exp: int = 0):
     """Round src (float32/float64, device) * 2^scale_exp to float32 / bfloat16 / float8_e4m3fn."""
     torch = _torch()
+    if not src.is_contiguous():
+        raise RtuckerError("rtucker_convert: src must be contiguous (C order)")
     dst = torch.empty(src.shape, dtype=dst_dtype, device=src.device)
     _check(lib().rtucker_convert(_ptr(src), dtype_code(src), _ptr(dst), dtype_code(dst), src.numel(), int(scale_exp),
                                  _stream(src.device)), "rtucker_convert")
@@ -407,10 +412,12 @@ def rtucker_sq_residual(A, B, want_r: bool = True):
     """(sum (A-B)^2 as a 1-element float64 device tensor, R = A - B or None)."""
     torch = _torch()
     at = _tensor(A)
+    if B.shape != A.shape or B.dtype != A.dtype or B.device != A.device or not B.is_contiguous():
+        raise RtuckerError("rtucker_sq_residual: B must match A in shape, dtype and device, and be contiguous")
     R = torch.empty_like(A) if want_r else None
     out = torch.empty(1, dtype=torch.float64, device=A.device)
     ws, wb = _workspace(SQ_RESIDUAL_WS, A.device)
-    _check(lib().rtucker_sq_residual(ctypes.byref(at), _ptr(B.contiguous()), _ptr(R), _ptr(out), _ptr(ws), wb,
+    _check(lib().rtucker_sq_residual(ctypes.byref(at), _ptr(B), _ptr(R), _ptr(out), _ptr(ws), wb,
                                      _stream(A.device)), "rtucker_sq_residual")
     return out, R
 
@@ -419,7 +426,7 @@ def rtucker_scaled_diff(A, B=None, g=None, alpha: float = 1.0, out=None):
     """out = alpha * g * (A - B) elementwise (g: device float64 scalar tensor or None = 1; B None = 0)."""
     torch = _torch()
     at = _tensor(A)
-    if B is not None and (B.shape != A.shape or B.dtype != A.dtype or not B.is_contiguous()):
+    if B is not None and (B.shape != A.shape or B.dtype != A.dtype or B.device != A.device or not B.is_contiguous()):
         raise RtuckerError("rtucker_scaled_diff: B must match A")
     if g is not None and (g.dtype != torch.float64 or g.numel() != 1 or g.device != A.device):
         raise RtuckerError("rtucker_scaled_diff: g must be one float64 value on A's device")

@@ -1128,7 +1128,6 @@ const char* rtucker_status_string(int status) {
     case RT_ESHAPE: return "inconsistent or unsupported shape";
     case RT_EDTYPE: return "unsupported dtype";
     case RT_EWORKSPACE: return "workspace missing, misaligned or too small";
-    case RT_ENONFINITE: return "non-finite input";
     case RT_EHIP: return "HIP runtime error";
     default: return "unknown status";
   }

@@ -44,3 +44,17 @@ def sth_phis(dims, S, seed=synth.PHI_SEED):
 
 def subspace_gap(U, V):
     return float(np.linalg.norm(U @ U.T - V @ V.T, 2))
+
+
+def assert_entrywise(got, want, bound, tol, what=""):
+    """Element-by-element check |got - want| <= tol * bound, where ``bound`` is the same
+    contraction taken over the absolute values of its (rounded) operands: the scale of the
+    accumulation error of each entry, so cancellation in one entry cannot hide an error."""
+    got, want, bound = (np.asarray(a, dtype=np.float64) for a in (got, want, bound))
+    assert got.shape == want.shape == bound.shape, (got.shape, want.shape, bound.shape)
+    err = np.abs(got - want)
+    lim = tol * bound
+    bad = ~(err <= lim)
+    if bad.any():
+        ratio = np.max(err[bad] / np.maximum(lim[bad], 1e-300))
+        raise AssertionError(f"{what}: {int(bad.sum())} of {got.size} entries off, worst err/limit {ratio:.3g}")

@@ -148,3 +148,21 @@ def test_binding_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(rt, "LIB_PATH", "/nonexistent/librtucker.so")
     with pytest.raises(rt.RtuckerError):
         rt.lib()
+
+
+def test_binding_rejects_mismatched_operands():
+    """Operand checks that happen in the binding before any library call (no GPU needed)."""
+    import torch
+    A = torch.zeros((4, 5), dtype=torch.float64)
+    for B in (torch.zeros((4, 5), dtype=torch.float32), torch.zeros((5, 4), dtype=torch.float64),
+              torch.zeros((10, 5), dtype=torch.float64)[::2]):
+        with pytest.raises(rt.RtuckerError):
+            rt.rtucker_sq_residual(A, B)
+        with pytest.raises(rt.RtuckerError):
+            rt.rtucker_scaled_diff(A, B)
+    with pytest.raises(rt.RtuckerError):
+        rt.rtucker_convert(torch.zeros((6, 4), dtype=torch.float32).t(), torch.bfloat16)
+
+
+def test_status_code_minus_five_unused():
+    assert rt.lib().rtucker_status_string(-5) == b"unknown status"

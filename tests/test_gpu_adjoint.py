@@ -5,7 +5,7 @@ and at the 256^3 loss with fixed rank-24 factors."""
 import numpy as np
 import pytest
 
-from gpu_common import dev, host, pytestmark_skip, rt, say, synth, torch
+from gpu_common import assert_entrywise, dev, host, pytestmark_skip, rt, say, synth, torch
 from oracle import adjoint as AD
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(pytestmark_skip, reason="needs a GPU")]
@@ -28,8 +28,10 @@ def test_multi_ttm_forward(dt, tol, shape, ms, transpose):
     X = rng.standard_normal(shape)
     As = [rng.standard_normal((n, m) if transpose else (m, n)) for n, m in zip(shape, ms)]
     Y = rt.rtucker_multi_ttm(dev(X, dt), [dev(A, dt) for A in As], None, transpose)
-    ref = AD.multi_ttm_all(X, [A.T for A in As] if transpose else As)
-    assert _rel(host(Y), ref) <= tol
+    opA = [A.T for A in As] if transpose else As
+    ref = AD.multi_ttm_all(X, opA)
+    bound = AD.multi_ttm_all(np.abs(X), [np.abs(A) for A in opA])
+    assert_entrywise(host(Y), ref, bound, 10 * tol, "multi-TTM")
 
 
 @pytest.mark.parametrize("dt,tol", [(torch.float64, 1e-13), (torch.float32, 2e-6)])
@@ -47,10 +49,12 @@ def test_multi_ttm_backward_matches_oracle(dt, tol, transpose):
     Y.backward(dev(dY, dt))
     opA = [A.T for A in As] if transpose else As
     dX, dAs = AD.multi_ttm_grads(X, opA, dY)
-    assert _rel(host(Xd.grad), dX) <= tol
+    bX, bAs = AD.multi_ttm_grads(np.abs(X), [np.abs(A) for A in opA], np.abs(dY))
+    assert_entrywise(host(Xd.grad), dX, bX, 10 * tol, "dX")
     for k in range(3):
         want = dAs[k].T if transpose else dAs[k]
-        assert _rel(host(Ad[k].grad), want) <= tol
+        bound = bAs[k].T if transpose else bAs[k]
+        assert_entrywise(host(Ad[k].grad), want, bound, 10 * tol, f"dA_{k}")
 
 
 def test_multi_ttm_partial_modes_backward():
@@ -204,10 +208,11 @@ def test_mode_contract_layouts(dt, tol, shapeP, shapeQ, n):
     Pm, Qm = rng.standard_normal(shapeP), rng.standard_normal(shapeQ)
     from oracle import tucker as T
     want = T.unfold(Pm, n) @ T.unfold(Qm, n).T
+    bound = np.abs(T.unfold(Pm, n)) @ np.abs(T.unfold(Qm, n)).T
     got = rt.rtucker_mode_contract(dev(Pm, dt), dev(Qm, dt), n)
-    assert _rel(host(got), want) <= tol
+    assert_entrywise(host(got), want, bound, 10 * tol, "mode contraction")
     # accumulate into an existing result
     base = rng.standard_normal(want.shape)
     acc = dev(base, dt)
     rt.rtucker_mode_contract(dev(Pm, dt), dev(Qm, dt), n, out=acc)
-    assert _rel(host(acc), base + want) <= tol
+    assert_entrywise(host(acc), base + want, bound + np.abs(base), 10 * tol, "accumulated mode contraction")

@@ -1,11 +1,11 @@
 """GPU parity of the batched decomposition (grouped launches): every item
-against the FP64 oracle run on the same Phi, for uneven shapes of the
+against the FP64 oracle (bfloat16: the emulated-precision oracle) run on the same Phi, for uneven shapes of the
 many-small-tensors workload (dims U{32..192}^3, ranks U{4..16}^3, p = 4),
 plus graph capture, the autotuner and argument validation."""
 import numpy as np
 import pytest
 
-from gpu_common import dev, host, pytestmark_skip, rt, say, synth, torch
+from gpu_common import assert_entrywise, dev, host, pytestmark_skip, rt, say, synth, torch
 from oracle import lowp as LP
 from oracle import tucker as T
 
@@ -28,18 +28,59 @@ def _device_phis(phis):
     return [[dev(f) for f in ph] for ph in phis]
 
 
-def _check_error(e_dev, e_or, captured=1e-3):
-    """|de| <= 1e-5 where the decomposition captures the tensor (oracle error below `captured`:
-    1e-3 in binary32 for noise at 1e-4, 2e-2 in bfloat16 whose rounding floor is ~4e-3).  With very unbalanced ranks a Kronecker sketch can be rank
-    deficient (its rank is at most prod_{k != n} min(r_k, s_k)); the extra columns of U_hat
-    then span noise directions that a QR determines only to about cond * 2^-24, every
-    completion is correct, and the error agrees to 1 % only."""
+def capped_modes(r, s, Ys):
+    """Modes whose sketch cannot determine r_n directions (Sec. 4.3 reuse sketch).
+
+    The mode-n sketch X_(n) (kron_{k != n} Phi_k^T) of a tensor of Tucker rank r has
+    rank at most q_n = prod_{k != n} min(r_k, s_k); with unbalanced ranks q_n can fall
+    below r_n although prod s_k >= r_n + p.  Near-deficiency counts too: q_n is also
+    capped by the number of singular values of the oracle's sketch above 1e-3 of the
+    largest (ten times the 1e-4 noise of the workload).  Returns {n: q_n} for the
+    modes with q_n < r_n; the columns of U_hat_n beyond q_n then span directions set
+    by the noise, any of which a correct QR may return."""
+    out = {}
+    for n in range(3):
+        q = int(np.prod([min(r[k], s[k]) for k in range(3) if k != n]))
+        sv = np.linalg.svd(Ys[n], compute_uv=False)
+        q = min(q, int(np.sum(sv > 1e-3 * sv[0])))
+        if q < r[n]:
+            out[n] = q
+    return out
+
+
+def check_item(Xseen, G, Us, r, s, phis, dtype):
+    """One batch item against the oracle on the same Phi (the emulated-precision oracle
+    for bfloat16).  Uncapped items: |e_gpu - e_oracle| <= 1e-5.  Capped items: what the
+    sketch determines, i.e. the projection onto range(U_n) of the leading q_n left singular
+    vectors of the oracle's sketch, equal entry by entry to 1e-4, and the core equal to
+    X x_k U_k^T for the device's own factors.  Returns True when the item was capped."""
+    r = list(r)
+    if dtype == "f32":
+        Go, Uo, parts = T.rhkron(Xseen, r, phis, return_parts=True)
+        Ys = [T.kron_sketch(Xseen, phis, n) for n in range(3)]
+    else:
+        Go, Uo, parts = LP.rhkron_emulated(Xseen, r, phis, "bf16", "bf16", return_parts=True)
+        Ys = parts["Y"]
+    for k in range(3):
+        assert np.max(np.abs(Us[k].T @ Us[k] - np.eye(r[k]))) < 1e-10
+    e_dev = T.rel_error(Xseen, G, Us)
+    e_or = T.rel_error(Xseen, Go, Uo)
     assert np.isfinite(e_dev)
-    if e_or < captured:
+    cap = capped_modes(r, s, Ys)
+    if not cap:
         assert abs(e_dev - e_or) <= 1e-5, (e_dev, e_or)
-        return True
-    assert abs(e_dev - e_or) <= 1e-2 * e_or, (e_dev, e_or)
-    return False
+        return False
+    for n, q in cap.items():
+        Sd = np.linalg.svd(Ys[n], full_matrices=False)[0][:, :q]
+        pd = Us[n] @ (Us[n].T @ Sd)
+        po = Uo[n] @ (Uo[n].T @ Sd)
+        assert np.max(np.abs(pd - po)) <= 1e-4, (n, q, np.max(np.abs(pd - po)))
+    # the core is the projection of X on the device's factors (U_hat rounded to bfloat16 in
+    # the first contraction of the bfloat16 path: two bfloat16 units of the entry scale)
+    want = T.multi_ttm(Xseen, {k: Us[k].T for k in range(3)})
+    bound = T.multi_ttm(np.abs(Xseen), {k: np.abs(Us[k]).T for k in range(3)})
+    assert_entrywise(G, want, bound, 2e-5 if dtype == "f32" else 2.0 ** -7, "core of a capped item")
+    return True
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
@@ -51,21 +92,11 @@ def test_batched_matches_oracle(dtype):
     Xd = [rt.rtucker_convert(dev(X, torch.float32), tdt) if dtype == "bf16" else dev(X, torch.float32) for X in Xs]
     B = rt.Batch(Xd, ranks, P_OVER, _device_phis(phis))
     Gs, Us = B.run()
-    strict = 0
+    capped = 0
     for i, X in enumerate(Xs):
         Xseen = host(Xd[i])  # the values the device decomposed
-        e_dev = T.rel_error(Xseen, host(Gs[i]), [host(u) for u in Us[i]])
-        if dtype == "f32":
-            G, U = T.rhkron(Xseen, list(ranks[i]), phis[i])
-            e_or = T.rel_error(Xseen, G, U)
-        else:
-            G, U = LP.rhkron_emulated(Xseen, list(ranks[i]), phis[i], "bf16", "bf16")
-            e_or = T.rel_error(Xseen, G, U)
-        strict += _check_error(e_dev, e_or, 1e-3 if dtype == "f32" else 2e-2)
-        for k in range(3):
-            u = host(Us[i][k])
-            assert np.max(np.abs(u.T @ u - np.eye(ranks[i][k]))) < 1e-10
-    assert strict >= len(Xs) // 2
+        capped += check_item(Xseen, host(Gs[i]), [host(u) for u in Us[i]], ranks[i], s[i], phis[i], dtype)
+    say(f"  {capped} of {len(Xs)} items capped")
 
 
 def test_batched_equals_single_tensor_path():
@@ -107,26 +138,31 @@ def test_batched_graph_replay_and_autotune():
                 assert np.linalg.norm(a @ a.T - b @ b.T, 2) < 1e-4
 
 
-def test_batched_full_size_sampled():
-    """512 tensors of the many-small-tensors workload in FP32; 16 items checked against the oracle."""
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_batched_full_size_all_items(dtype):
+    """The 512-tensor workload (dims U{32..192}^3, ranks U{4..16}^3, p = 4), every item
+    against the oracle on the host: strict on every item whose sketches determine the
+    ranks, the determined part on the rest."""
     count = 512
     dims, ranks = synth.batch_specs(count)
     s = [rt.rtucker_sketch_sizes(d, r, P_OVER, "rhkron") for d, r in zip(dims, ranks)]
     phis = synth.batch_phis(dims, s)
-    say("batched full size: generating", count, "tensors")
-    Xd = [dev(synth.batch_tensor(i, d, r), torch.float32) for i, (d, r) in enumerate(zip(dims, ranks))]
+    say(f"batched full size {dtype}: generating", count, "tensors")
+    tdt = torch.float32 if dtype == "f32" else torch.bfloat16
+    Xd = []
+    for i, (d, r) in enumerate(zip(dims, ranks)):
+        x = dev(synth.batch_tensor(i, d, r), torch.float32)
+        Xd.append(rt.rtucker_convert(x, tdt) if dtype == "bf16" else x)
     B = rt.Batch(Xd, ranks, P_OVER, _device_phis(phis))
     Gs, Us = B.run()
     torch.cuda.synchronize()
+    capped = []
     for i in range(count):
-        assert bool(torch.isfinite(Gs[i]).all())
-    strict = 0
-    for i in np.random.default_rng(5).choice(count, 16, replace=False):
-        Xseen = host(Xd[i])
-        e_dev = T.rel_error(Xseen, host(Gs[i]), [host(u) for u in Us[i]])
-        G, U = T.rhkron(Xseen, list(ranks[i]), phis[i])
-        strict += _check_error(e_dev, T.rel_error(Xseen, G, U))
-    assert strict >= 8
+        if i % 64 == 0:
+            say(f"  item {i}")
+        if check_item(host(Xd[i]), host(Gs[i]), [host(u) for u in Us[i]], ranks[i], s[i], phis[i], dtype):
+            capped.append(i)
+    say(f"  {len(capped)} of {count} items capped: {capped}")
 
 
 def test_batched_validation():

@@ -3,7 +3,8 @@ r = 32, p = 8, s = 7), in the launch configuration the benchmark times.
 
 The FP64 oracle runs the whole decomposition on the host (seconds), so the
 relative reconstruction errors are compared directly: FP32 GPU vs FP64 oracle,
-BF16 / FP8-sketch GPU vs the emulated-precision oracle (|de| <= 1e-5), plus
+BF16 / FP8-sketch GPU (rHKron and rSTHKron) vs the emulated-precision oracle
+(|de| <= 1e-5), plus
 sampled sketch rows and the QR of the GPU sketch against the oracle."""
 import numpy as np
 import pytest
@@ -64,20 +65,24 @@ def test_fullsize_core_first_contraction_samples(work):
         assert abs(C[a, j, k] - want) <= 2e-6 * (np.abs(U32[:, a]) @ np.abs(col))
 
 
-@pytest.mark.parametrize("path", ["f32", "bf16", "f8sketch", "rsthkron_f32"])
+@pytest.mark.parametrize("path", ["f32", "bf16", "f8sketch", "rsthkron_f32", "rsthkron_bf16"])
 def test_fullsize_decompose_error(work, path):
     Xh, s, phis = work["Xh"], work["s"], work["phis"]
     X = Xh.astype(np.float64)
     say(f"full size decompose {path}")
-    if path == "rsthkron_f32":
+    if path.startswith("rsthkron"):
         S = rt.rtucker_sketch_sizes(DIMS, R, P, "rsthkron")
         cdim = [min(DIMS[k], int(np.prod([S[k][i] for i in range(3) if i != k]))) for k in range(3)]
         shapes = [None if k == j else (S[j][k], cdim[k] if k < j else DIMS[k]) for j in range(3) for k in range(3)]
         flat = synth.gaussians(synth.PHI_SEED, shapes)
         sph = [flat[j * 3:(j + 1) * 3] for j in range(3)]
-        G, Us = rt.rtucker_decompose(work["X32"], R, P, [[None if f is None else dev(f) for f in row] for row in sph],
+        Xin = work["X32"] if path == "rsthkron_f32" else rt.rtucker_convert(work["X32"], torch.bfloat16)
+        G, Us = rt.rtucker_decompose(Xin, R, P, [[None if f is None else dev(f) for f in row] for row in sph],
                                      algo="rsthkron", s=S)
-        Go, Uo = T.rsthkron(X, R, sph)
+        if path == "rsthkron_f32":
+            Go, Uo = T.rsthkron(X, R, sph)
+        else:
+            Go, Uo = L.rsthkron_emulated(X, R, sph, "bf16")
     elif path == "f32":
         G, Us = rt.rtucker_decompose(work["X32"], R, P, work["phis_d"], s=s)
         Go, Uo = T.rhkron(X, R, phis)
@@ -100,13 +105,14 @@ def test_fullsize_decompose_error(work, path):
         np.testing.assert_allclose(Uh.T @ Uh, np.eye(32), atol=1e-12)
 
 
-def test_fullsize_rsthkron_128_4way():
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_fullsize_rsthkron_128_4way(dtype):
     """128^4 FP32 tensor with a decaying 16^4 core, rSTHKron with every subrank 3, r = 16,
-    p = 6, in the launch configuration the benchmark times: error against the FP64 oracle,
-    and BF16 against the binary32 result (rSTHKron has no emulated oracle; BF16 only has to
-    stay within its rounding floor)."""
+    p = 6, in the launch configuration the benchmark times: the binary32 run against the
+    FP64 oracle, the bfloat16 run (X converted on the device) against the emulated-precision
+    oracle, both to |de| <= 1e-5."""
     dims4, r4 = (128, 128, 128, 128), [16, 16, 16, 16]
-    say("full size: generating the 128^4 tensor")
+    say(f"full size: generating the 128^4 tensor ({dtype})")
     core = synth.tucker_core_decay((16, 16, 16, 16), 6.0, seed=synth.DATA_SEED)
     Xh, _, _ = synth.random_tucker(dims4, (16, 16, 16, 16), 1e-3, seed=synth.DATA_SEED, core=core)
     Xh = Xh.astype(np.float32)
@@ -116,13 +122,15 @@ def test_fullsize_rsthkron_128_4way():
     ph = [flat[j * 4:(j + 1) * 4] for j in range(4)]
     X32 = torch.from_numpy(Xh).to(DEV)
     phd = [[None if f is None else dev(f) for f in row] for row in ph]
-    G, Us = rt.rtucker_decompose(X32, r4, 6, phd, algo="rsthkron", s=S)
+    Xin = X32 if dtype == "f32" else rt.rtucker_convert(X32, torch.bfloat16)
+    G, Us = rt.rtucker_decompose(Xin, r4, 6, phd, algo="rsthkron", s=S)
     e_dev, _ = rt.rtucker_rel_error(X32, G, Us)
-    say("full size: 128^4 oracle")
-    Go, Uo = T.rsthkron(Xh.astype(np.float64), r4, ph)
-    e_or = T.rel_error(Xh.astype(np.float64), Go, Uo)
+    say(f"full size: 128^4 oracle ({dtype})")
+    X64 = Xh.astype(np.float64)
+    if dtype == "f32":
+        Go, Uo = T.rsthkron(X64, r4, ph)
+    else:
+        Go, Uo = L.rsthkron_emulated(X64, r4, ph, "bf16")
+    e_or = T.rel_error(X64, Go, Uo)
+    say(f"  128^4 {dtype}: e_device={e_dev:.9e} e_oracle={e_or:.9e}")
     assert abs(e_dev - e_or) <= 1e-5, (e_dev, e_or)
-    X16 = rt.rtucker_convert(X32, torch.bfloat16)
-    G16, U16 = rt.rtucker_decompose(X16, r4, 6, phd, algo="rsthkron", s=S)
-    e16, _ = rt.rtucker_rel_error(X32, G16, U16)
-    assert e_dev <= e16 <= e_dev + 1e-2
