@@ -9,8 +9,11 @@ subranks s = 7 (sketch width 49), Gaussian Kronecker factors.  Synthetic data.
 One step = one full decomposition on the device (all-at-once sketch, FP64
 QR of the three sketches, core multi-TTM, FP64 STHOSVD truncation of the
 49^3 core, U = U_hat V), inputs resident in HBM.  The headline line times
-the BF16 path (X stored in bfloat16, MFMA with binary32 accumulation); the
-FP32 path, the FP8-sketch variant and rSTHKron are timed beside it.
+the FP32 path (binary32 tensor, binary32 matrix-core contractions).  The
+precision form is timed beside it: BF16 (sketch also FP8 e4m3) with X resident
+in the narrow format, and with X arriving in binary32 and the cast counted in
+the step; rSTHKron likewise.  Each path also reports its device time per phase
+(sketch, QR, core, truncation).
 
 value = algorithmic multi-TTM flops of one step (sketch + core contractions,
 unpadded) / step time, in TFLOP/s.
@@ -40,11 +43,12 @@ def log(*a):
 
 
 def counter_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed byte-counter summary, or None when the
+    """HBM bytes per launch of `kernel` from its committed byte-counter summary
+    (profiles/hbm_counters_<kernel>_1024x1024x512.md), or None when there is none or the
     kernel's source has changed since the counters were taken."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "hbm_counters_sketch_pass_bf16_1024x1024x512.md")
+    path = os.path.join(ROOT, "profiles", f"hbm_counters_{kernel}_1024x1024x512.md")
     try:
         text = open(path).read()
     except OSError:
@@ -83,7 +87,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-variants", action="store_true", help="time only the headline BF16 path")
+    ap.add_argument("--no-variants", action="store_true", help="time only the headline FP32 path")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device buffers three times (reference for the HBM byte counters)")
     ap.add_argument("--no-extras", action="store_true",
@@ -153,24 +157,51 @@ def main():
     step_flops = sk_flops + core_flops
     results = {}
 
-    # ---------------------------------------------------------------- headline: BF16
-    run16, G16, U16 = make_run(X16, sizes=s)
-    log("timing BF16 rHKron ...")
-    ms16 = time_steps(run16, args.steps, args.warmup)
-    e16, _ = rt.rtucker_rel_error(X32, G16, U16)
-    results["rhkron_bf16"] = {"ms": ms16, "rel_err": e16}
+    def phases_of(X, algo="rhkron", Xs=None, sizes=None, ph=None, reps=5):
+        """Median device time per phase over `reps` calls of the phase-timed entry point."""
+        nb = rt.rtucker_decompose_workspace(X, RANKS, P_OVER, algo, sizes, Xs)
+        ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
+        rows = []
+        for _ in range(reps):
+            _, _, pm = rt.rtucker_decompose_phases(X, RANKS, P_OVER, ph if ph is not None else phis, algo=algo,
+                                                   s=sizes, X_sketch=Xs, ws=ws)
+            rows.append(pm)
+        return {k: round(float(np.median([r[k] for r in rows])), 4) for k in rows[0]}
+
+    # ---------------------------------------------------------------- headline: FP32
+    run32, G32, U32 = make_run(X32, sizes=s)
+    log("timing FP32 rHKron (headline) ...")
+    ms32 = time_steps(run32, args.steps, args.warmup)
+    e32, _ = rt.rtucker_rel_error(X32, G32, U32)
+    results["rhkron_f32"] = {"ms": ms32, "rel_err": e32, "phases_ms": phases_of(X32, sizes=s)}
 
     if not args.no_variants:
-        run32, G32, U32 = make_run(X32, sizes=s)
-        log("timing FP32 rHKron ...")
-        ms32 = time_steps(run32, args.steps, args.warmup)
-        e32, _ = rt.rtucker_rel_error(X32, G32, U32)
-        results["rhkron_f32"] = {"ms": ms32, "rel_err": e32}
+        # BF16 with X resident in bfloat16, and with X arriving in binary32 (the cast timed in the step)
+        run16, G16, U16 = make_run(X16, sizes=s)
+        log("timing BF16 rHKron ...")
+        ms16 = time_steps(run16, args.steps, args.warmup)
+        e16, _ = rt.rtucker_rel_error(X32, G16, U16)
+        results["rhkron_bf16"] = {"ms": ms16, "rel_err": e16, "phases_ms": phases_of(X16, sizes=s)}
+
+        def run16_cast():
+            rt.rtucker_convert(X32, torch.bfloat16, out=X16)
+            run16()
+        ms = time_steps(run16_cast, args.steps, args.warmup)
+        e, _ = rt.rtucker_rel_error(X32, G16, U16)
+        results["rhkron_bf16_cast_counted"] = {"ms": ms, "rel_err": e}
         run8, G8, U8 = make_run(X16, Xs=X8, sizes=s)
         log("timing BF16 rHKron with FP8 sketch ...")
         ms8 = time_steps(run8, args.steps, args.warmup)
         e8, _ = rt.rtucker_rel_error(X32, G8, U8)
-        results["rhkron_bf16_f8sketch"] = {"ms": ms8, "rel_err": e8}
+        results["rhkron_bf16_f8sketch"] = {"ms": ms8, "rel_err": e8, "phases_ms": phases_of(X16, Xs=X8, sizes=s)}
+
+        def run8_cast():
+            rt.rtucker_convert(X32, torch.bfloat16, out=X16)
+            rt.rtucker_convert(X32, torch.float8_e4m3fn, out=X8)
+            run8()
+        ms = time_steps(run8_cast, args.steps, args.warmup)
+        e, _ = rt.rtucker_rel_error(X32, G8, U8)
+        results["rhkron_bf16_f8sketch_cast_counted"] = {"ms": ms, "rel_err": e}
         shapes = []
         cdim = [min(DIMS[k], int(np.prod([S[k][i] for i in range(3) if i != k]))) for k in range(3)]
         for j in range(3):
@@ -184,7 +215,14 @@ def main():
             log(f"timing {name} ...")
             ms = time_steps(fn, max(3, args.steps // 2), 2)
             e, _ = rt.rtucker_rel_error(X32, G, U)
-            results[name] = {"ms": ms, "rel_err": e}
+            results[name] = {"ms": ms, "rel_err": e, "phases_ms": phases_of(X, "rsthkron", sizes=S, ph=sphis)}
+            if name == "rsthkron_bf16":
+                def fn_cast():
+                    rt.rtucker_convert(X32, torch.bfloat16, out=X16)
+                    fn()
+                ms = time_steps(fn_cast, max(3, args.steps // 2), 2)
+                e, _ = rt.rtucker_rel_error(X32, G, U)
+                results["rsthkron_bf16_cast_counted"] = {"ms": ms, "rel_err": e}
 
     # ---------------------------------------------------------------- per-kernel rooflines
     N = int(np.prod(DIMS))
@@ -195,7 +233,10 @@ def main():
     def kernel_time(fn, reps=10):
         return time_steps(fn, reps, 2)
 
-    for tag, X, esz in (("bf16", X16, 2), ("f32", X32, 4)):
+    # the binary32 -> bfloat16 cast: 4 bytes read, 2 written per element
+    ms = kernel_time(lambda: rt.rtucker_convert(X32, torch.bfloat16, out=X16))
+    kernels["cast_f32_bf16"] = {"ms": ms, "GB/s": 6 * N / ms / 1e6, "alg_bytes": 6 * N}
+    for tag, X, esz in (("f32", X32, 4), ("bf16", X16, 2)):
         # first core contraction: X x_1 U_hat_1^T (MFMA), plus a tiny operand-rounding kernel
         ms = kernel_time(lambda: rt.rtucker_core(X, Uh, modes=[0]))
         byts = N * esz + ell[0] * (N // DIMS[0]) * 4 + DIMS[0] * ell[0] * esz
@@ -221,13 +262,13 @@ def main():
                                     "alg_bytes": byts, "alg_flops": fl}
         del Zb, Wb
 
-    # dominant kernel of the headline (BF16) step: the streaming sketch pass (the first core
-    # contraction takes about as long and is listed under "kernels")
-    dom = "sketch_pass_bf16"
+    # dominant kernel of the headline (FP32) step: the first core contraction, a dense contraction
+    # on the binary32 matrix cores (arithmetic intensity 23 flop/B, above the ridge)
+    dom = "core_ttm1_f32"
     kd = kernels[dom]
-    achieved = kd["GB/s"] * 1e9
-    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved / 1e9, 1), "peak": HBM_PEAK / 1e9,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4), "traffic": counter_traffic(dom)}
+    roofline = {"kernel": dom, "bound": "mfma", "achieved": round(kd["TFLOP/s"], 2), "peak": MFMA_PEAK["f32"] / 1e12,
+                "unit": "TFLOP/s", "frac": round(kd["TFLOP/s"] * 1e12 / MFMA_PEAK["f32"], 4),
+                "traffic": counter_traffic(dom)}
 
     extras = {}
     if not args.no_extras:
@@ -236,23 +277,9 @@ def main():
     # ---------------------------------------------------------------- CPU baseline (oracle, whole workload)
     cpu = None
     if not args.no_cpu_baseline:
-        from oracle import tucker as T
+        cpu = cpu_baseline(Xh, phis_h, step_flops)
 
-        log("timing the CPU oracle (numpy FP64) on the whole workload ...")
-        Xd64 = Xh.astype(np.float64)
-        times = []
-        for _ in range(3):
-            t1 = time.perf_counter()
-            T.rhkron(Xd64, list(RANKS), phis_h)
-            times.append(time.perf_counter() - t1)
-        dt = float(np.median(times))
-        del Xd64
-        cores = len(os.sched_getaffinity(0))
-        cpu = {"value": round(step_flops / dt / 1e12, 6), "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
-               "sample": f"whole workload (1024x1024x512, FP64 numpy/OpenBLAS rHKron incl. truncation), "
-                         f"median of 3 runs: {dt:.3f} s"}
-
-    value = step_flops / (ms16 / 1e3) / 1e12
+    value = step_flops / (ms32 / 1e3) / 1e12
     out = {
         "metric": "rHKron time + multi-TTM TFLOP/s, BF16-MFMA vs FP32 at stated rel. error",
         "value": round(value, 3),
@@ -260,23 +287,65 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms16, 4),
+        "ms_per_step": round(ms32, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16",
+        "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "rHKron 1024x1024x512 smooth field, r=32, p=8, s=7 (sketch width 49)",
                    "dims": list(DIMS), "ranks": list(RANKS), "p": P_OVER, "s": s,
                    "step_multi_ttm_gflop": round(step_flops / 1e9, 3)},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "paths": {k: {"ms": round(v["ms"], 4), "rel_err": v["rel_err"]} for k, v in results.items()},
+        "paths": {k: {kk: (round(vv, 4) if kk == "ms" else vv) for kk, vv in v.items()} for k, v in results.items()},
         "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kernels.items()},
         "other_workloads": extras,
     }
     print(json.dumps(out))
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(Xh, phis_h, step_flops):
+    """The FP64 oracle on the whole workload: all host cores, then one core (threadpoolctl)."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    from oracle import tucker as T
+
+    Xd64 = Xh.astype(np.float64)
+
+    def timed(reps):
+        times = []
+        for _ in range(reps):
+            t1 = time.perf_counter()
+            T.rhkron(Xd64, list(RANKS), phis_h)
+            times.append(time.perf_counter() - t1)
+        return float(np.median(times))
+
+    log("timing the CPU oracle (numpy FP64) on the whole workload, all cores ...")
+    info = [p for p in threadpool_info() if p.get("user_api") == "blas"]
+    threads = max([int(p.get("num_threads", 1)) for p in info] or [1])
+    blas = ", ".join(f"{p.get('internal_api')} {p.get('version')}" for p in info) or "unknown"
+    dt_all = timed(3)
+    log("timing the CPU oracle on one core ...")
+    with threadpool_limits(limits=1):
+        dt_one = timed(1)
+    del Xd64
+    return {"value": round(step_flops / dt_all / 1e12, 6), "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"whole workload (1024x1024x512, FP64 numpy rHKron incl. truncation), median of 3 runs on "
+                      f"{threads} BLAS threads: {dt_all:.3f} s; one thread: {dt_one:.3f} s",
+            "one_core": {"value": round(step_flops / dt_one / 1e12, 6), "seconds": round(dt_one, 3), "cores": 1},
+            "cpu_model": cpu_model(), "blas": blas}
 
 
 def run_extras(rt, synth, torch, dev, time_steps, log):

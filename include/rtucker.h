@@ -190,6 +190,20 @@ int rtucker_decompose(const rt_tensor* X, const rt_tensor* X_sketch, const int32
                       const int64_t* s, rt_algo algo, const double* const* phi, double* G,
                       double* const* U, void* ws, size_t ws_bytes, void* stream);
 
+/* The same decomposition with its time split by phase (the breakdown of Sec. 7.5-7.6
+ * in the paper's own terms): an event is recorded on `stream` at each phase boundary,
+ * the call synchronises `stream`, and phase_ms (host, 4 floats) receives the device
+ * time in milliseconds of
+ *   [0] sketch (operand rounding, the streaming pass and the tree contractions),
+ *   [1] QR of the sketches, [2] core multi-TTM, [3] truncation (STHOSVD of the core and
+ *   U_j = U_hat_j V_j),
+ * summed over the steps of Alg. 4.3 for RT_RSTHKRON.  Results equal rtucker_decompose's
+ * bit for bit.  RT_EINVAL if phase_ms is NULL. */
+int rtucker_decompose_phases(const rt_tensor* X, const rt_tensor* X_sketch, const int32_t* r,
+                             int32_t p, const int64_t* s, rt_algo algo, const double* const* phi,
+                             double* G, double* const* U, void* ws, size_t ws_bytes, void* stream,
+                             float* phase_ms);
+
 /* ------------------------------------------------------------------ error
  * Squared norms for the relative reconstruction error (Sec. 5), in binary64 on
  * the device, by explicit residual (no cancellation-prone identity):

@@ -62,6 +62,10 @@ _SIGS = {
     "rtucker_decompose": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "rtucker_decompose_phases": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                                ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                                ctypes.c_void_p]),
     "rtucker_rel_error_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "rtucker_rel_error": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
@@ -304,13 +308,7 @@ def rtucker_decompose_workspace(X, r, p, algo="rhkron", s=None, X_sketch=None) -
     return nb.value
 
 
-def rtucker_decompose(X, r, p, phis, algo="rhkron", s=None, X_sketch=None, G=None, Us=None, ws=None):
-    """Randomized Tucker decomposition; returns (G, [U_j]) in float64 on X's device.
-
-    ``phis``: rhkron -> d float64 device matrices (s_k x I_k); rsthkron -> d x d nested
-    list (None on the diagonal).  Preallocated ``G``, ``Us`` and workspace ``ws``
-    (uint8 tensor) may be passed to avoid allocations (e.g. under graph capture).
-    """
+def _decompose_args(X, r, p, phis, algo, s, X_sketch, G, Us, ws):
     torch = _torch()
     d = X.dim()
     xt = _tensor(X)
@@ -328,10 +326,33 @@ def rtucker_decompose(X, r, p, phis, algo="rhkron", s=None, X_sketch=None, G=Non
         flat = [phis[j][k] if k != j else None for j in range(d) for k in range(d)]
     else:
         flat = list(phis)
-    _check(lib().rtucker_decompose(ctypes.byref(xt), ctypes.byref(xs) if xs is not None else None, _i32(r), int(p),
-                                   _s_array(s, algo, d), ALGOS[algo], _ptrs(flat), _ptr(G), _ptrs(Us), _ptr(ws), wb,
-                                   _stream(X.device)), "rtucker_decompose")
+    args = (ctypes.byref(xt), ctypes.byref(xs) if xs is not None else None, _i32(r), int(p), _s_array(s, algo, d),
+            ALGOS[algo], _ptrs(flat), _ptr(G), _ptrs(Us), _ptr(ws), wb, _stream(X.device))
+    return args, G, Us, (xt, xs, ws, flat)
+
+
+def rtucker_decompose(X, r, p, phis, algo="rhkron", s=None, X_sketch=None, G=None, Us=None, ws=None):
+    """Randomized Tucker decomposition; returns (G, [U_j]) in float64 on X's device.
+
+    ``phis``: rhkron -> d float64 device matrices (s_k x I_k); rsthkron -> d x d nested
+    list (None on the diagonal).  Preallocated ``G``, ``Us`` and workspace ``ws``
+    (uint8 tensor) may be passed to avoid allocations (e.g. under graph capture).
+    """
+    args, G, Us, _keep = _decompose_args(X, r, p, phis, algo, s, X_sketch, G, Us, ws)
+    _check(lib().rtucker_decompose(*args), "rtucker_decompose")
     return G, Us
+
+
+PHASES = ("sketch", "qr", "core", "truncate")
+
+
+def rtucker_decompose_phases(X, r, p, phis, algo="rhkron", s=None, X_sketch=None, G=None, Us=None, ws=None):
+    """rtucker_decompose with the device time split by phase (synchronises):
+    returns (G, [U_j], {"sketch": ms, "qr": ms, "core": ms, "truncate": ms})."""
+    args, G, Us, _keep = _decompose_args(X, r, p, phis, algo, s, X_sketch, G, Us, ws)
+    ms = (ctypes.c_float * 4)()
+    _check(lib().rtucker_decompose_phases(*args, ms), "rtucker_decompose_phases")
+    return G, Us, {name: float(ms[i]) for i, name in enumerate(PHASES)}
 
 
 def rtucker_rel_error(X, G, Us, allow_nonfinite: bool = False):
@@ -354,15 +375,19 @@ def rtucker_rel_error(X, G, Us, allow_nonfinite: bool = False):
     return (v[0] / v[1]) ** 0.5 if v[1] > 0 else float("nan"), {"res2": v[0], "x2": v[1], "g2": v[2], "nonfinite": v[3]}
 
 
-def rtucker_convert(src, dst_dtype, scale_exp: int = 0):
-    """Round src (float32/float64, device) * 2^scale_exp to float32 / bfloat16 / float8_e4m3fn."""
+def rtucker_convert(src, dst_dtype, scale_exp: int = 0, out=None):
+    """Round src (float32/float64, device) * 2^scale_exp to float32 / bfloat16 / float8_e4m3fn
+    (into ``out`` when given: contiguous, same shape, dtype dst_dtype)."""
     torch = _torch()
     if not src.is_contiguous():
         raise RtuckerError("rtucker_convert: src must be contiguous (C order)")
-    dst = torch.empty(src.shape, dtype=dst_dtype, device=src.device)
-    _check(lib().rtucker_convert(_ptr(src), dtype_code(src), _ptr(dst), dtype_code(dst), src.numel(), int(scale_exp),
+    if out is None:
+        out = torch.empty(src.shape, dtype=dst_dtype, device=src.device)
+    elif out.shape != src.shape or out.dtype != dst_dtype or out.device != src.device or not out.is_contiguous():
+        raise RtuckerError("rtucker_convert: out must be contiguous, of src's shape and device, of dst_dtype")
+    _check(lib().rtucker_convert(_ptr(src), dtype_code(src), _ptr(out), dtype_code(out), src.numel(), int(scale_exp),
                                  _stream(src.device)), "rtucker_convert")
-    return dst
+    return out
 
 
 def rtucker_multi_ttm(X, As, modes=None, transpose: bool = False):

@@ -20,6 +20,9 @@ using namespace rt;
 namespace {
 
 // ------------------------------------------------------------------ context
+// phases of one decomposition, as reported by rtucker_decompose_phases
+enum { kPhaseSketch = 0, kPhaseQR = 1, kPhaseCore = 2, kPhaseTruncate = 3, kPhases = 4, kPhaseEnd = -1 };
+
 struct Ctx {
   bool dry;          // size workspace only, launch nothing
   bool check_ptrs;   // validate data pointers (compute calls)
@@ -30,6 +33,19 @@ struct Ctx {
   hipError_t err = hipSuccess;
   size_t peak = 0;
   std::vector<PrepTask> pending;  // operand roundings not yet launched (one batched launch)
+  // phase timing (rtucker_decompose_phases): an event at each phase boundary
+  std::vector<hipEvent_t>* marks = nullptr;
+  std::vector<int>* mark_phase = nullptr;
+  void mark(int phase) {
+    flush();
+    if (dry || !marks) return;
+    hipEvent_t e = nullptr;
+    chk(hipEventCreate(&e));
+    if (!e) return;
+    chk(hipEventRecord(e, st));
+    marks->push_back(e);
+    mark_phase->push_back(phase);
+  }
   void flush() {
     if (!pending.empty()) {
       if (!dry) chk(launch_prep_batch(pending.data(), static_cast<int>(pending.size()), st));
@@ -664,12 +680,14 @@ int plan_decompose(Ctx& c, const rt_tensor* X, const rt_tensor* Xs, const int32_
   if (algo == RT_RHKRON) {
     const Ten Tsk = Xs ? ten_of(Xs) : cur;
     std::vector<SketchOut> outs;
+    c.mark(kPhaseSketch);
     sketch_impl(c, Tsk, phi, s.data(), (1u << d) - 1u, outs);
     std::vector<QRJob> jobs(d);
     for (int n = 0; n < d; ++n) jobs[n] = QRJob{outs[n].Y.p, outs[n].A, outs[n].m, outs[n].B, Uhat[n], nullptr};
     void* w = c.take(qr_ws(jobs.data(), d));
-    c.flush();
+    c.mark(kPhaseQR);
     if (!c.dry) c.chk(launch_qr(jobs.data(), d, ctype(Tsk.dt), w, c.st));
+    c.mark(kPhaseCore);
     cur = core_impl(c, cur, Uhat.data(), cdim.data(), (1u << d) - 1u, nullptr, /*f64_out=*/true);
   } else {
     for (int j = 0; j < d; ++j) {
@@ -678,16 +696,20 @@ int plan_decompose(Ctx& c, const rt_tensor* X, const rt_tensor* Xs, const int32_
       if (phi)
         for (int k = 0; k < d; ++k) phij[k] = (k == j) ? nullptr : phi[j * d + k];
       std::vector<SketchOut> outs;
+      c.mark(kPhaseSketch);
       sketch_impl(c, cur, phij.data(), sj.data(), 1u << j, outs);
       QRJob job{outs[j].Y.p, outs[j].A, outs[j].m, outs[j].B, Uhat[j], nullptr};
       void* w = c.take(qr_ws(&job, 1));
-      c.flush();
+      c.mark(kPhaseQR);
       if (!c.dry) c.chk(launch_qr(&job, 1, ctype(cur.dt), w, c.st));
+      c.mark(kPhaseCore);
       cur = core_impl(c, cur, Uhat.data(), cdim.data(), 1u << j, nullptr, /*f64_out=*/j == d - 1);
     }
   }
+  c.mark(kPhaseTruncate);
   Ten G64 = to_f64(c, cur);
   truncate_impl(c, G64, r, Uhat.data(), I, G, U);
+  c.mark(kPhaseEnd);
   return RT_OK;
 }
 
@@ -1106,6 +1128,34 @@ int run(F&& plan, void* ws, size_t ws_bytes, void* stream) {
   return live.err == hipSuccess ? RT_OK : RT_EHIP;
 }
 
+// run() with an event at every phase boundary; synchronises `stream` and sums the
+// intervals per phase (milliseconds) into phase_ms[kPhases]
+template <typename F>
+int run_timed(F&& plan, void* ws, size_t ws_bytes, void* stream, float* phase_ms) {
+  Ctx dry{true, true, nullptr, 0, 0, nullptr};
+  int st = plan(dry);
+  if (st) return st;
+  st = check_ws(dry, ws, ws_bytes);
+  if (st) return st;
+  std::vector<hipEvent_t> marks;
+  std::vector<int> phase;
+  Ctx live{false, true, static_cast<char*>(ws), 0, ws_bytes, static_cast<hipStream_t>(stream)};
+  live.marks = &marks;
+  live.mark_phase = &phase;
+  st = plan(live);
+  live.flush();
+  if (st == RT_OK && live.err == hipSuccess) live.chk(hipStreamSynchronize(live.st));
+  for (int k = 0; k < kPhases; ++k) phase_ms[k] = 0.f;
+  for (size_t i = 0; i + 1 < marks.size(); ++i) {
+    float ms = 0.f;
+    if (live.err == hipSuccess) live.chk(hipEventElapsedTime(&ms, marks[i], marks[i + 1]));
+    if (phase[i] >= 0 && phase[i] < kPhases) phase_ms[phase[i]] += ms;
+  }
+  for (hipEvent_t e : marks) hipEventDestroy(e);
+  if (st) return st;
+  return live.err == hipSuccess ? RT_OK : RT_EHIP;
+}
+
 template <typename F>
 int query(F&& plan, size_t* bytes) {
   if (!bytes) return RT_EINVAL;
@@ -1176,6 +1226,14 @@ int rtucker_decompose(const rt_tensor* X, const rt_tensor* X_sketch, const int32
                       rt_algo algo, const double* const* phi, double* G, double* const* U, void* ws, size_t ws_bytes,
                       void* stream) {
   return run([&](Ctx& c) { return plan_decompose(c, X, X_sketch, r, p, s, algo, phi, G, U); }, ws, ws_bytes, stream);
+}
+
+int rtucker_decompose_phases(const rt_tensor* X, const rt_tensor* X_sketch, const int32_t* r, int32_t p,
+                             const int64_t* s, rt_algo algo, const double* const* phi, double* G, double* const* U,
+                             void* ws, size_t ws_bytes, void* stream, float* phase_ms) {
+  if (!phase_ms) return RT_EINVAL;
+  return run_timed([&](Ctx& c) { return plan_decompose(c, X, X_sketch, r, p, s, algo, phi, G, U); }, ws, ws_bytes,
+                   stream, phase_ms);
 }
 
 int rtucker_rel_error_workspace(const rt_tensor* X, const int32_t* r, size_t* bytes) {

@@ -1,5 +1,7 @@
 // Elementwise kernels: precision conversion, operand preparation, unfolding,
 // squared residual.  Plain memory-bound grid-stride loops.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace rt {
@@ -45,6 +47,81 @@ __global__ __launch_bounds__(kThreads) void convert_kernel(const void* src, rt_d
     const double x = load_as_f64(src, sdt, i) * scale;  // power-of-two scale: exact
     store_rounded(dst, ddt, ddt, i, x);
   }
+}
+
+// binary32 -> bfloat16 bits, round to nearest even: adding 0x7fff plus the lowest kept
+// bit to the bit pattern and dropping 16 bits is exact RNE for every finite binary32
+// value (subnormals included) and carries overflow into the infinity pattern.
+__device__ __forceinline__ uint32_t f32_bits_to_bf16(uint32_t u) {
+  if ((u & 0x7fffffffu) > 0x7f800000u) return ((u >> 16) & 0x8000u) | 0x7fc0u;  // NaN
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+// The binary32 -> bfloat16 (or E4M3) cast of a whole tensor, the one pass that turns an
+// FP32 input into the narrow operand of the precision form: each thread moves 4 x 16
+// bytes per iteration (four independent loads in flight) and writes 4 x 8 (4 x 4) bytes.
+constexpr int kCastVec = 4;  // float4 loads per thread per iteration
+
+template <bool kF8> struct CastOut;
+template <> struct CastOut<false> {
+  typedef uint2 vec;  // four bfloat16 values
+  __device__ static vec pack(float4 v) {
+    const uint32_t a = f32_bits_to_bf16(__float_as_uint(v.x)), b = f32_bits_to_bf16(__float_as_uint(v.y));
+    const uint32_t c = f32_bits_to_bf16(__float_as_uint(v.z)), d = f32_bits_to_bf16(__float_as_uint(v.w));
+    return uint2{a | (b << 16), c | (d << 16)};
+  }
+  __device__ static void one(void* dst, int64_t i, float x) {
+    static_cast<bf16_t*>(dst)[i] = static_cast<bf16_t>(f32_bits_to_bf16(__float_as_uint(x)));
+  }
+};
+template <> struct CastOut<true> {
+  typedef uint32_t vec;  // four E4M3 values (binary32 -> binary64 is exact, then one rounding)
+  __device__ static vec pack(float4 v) {
+    return static_cast<uint32_t>(f64_to_f8_bits(v.x)) | (static_cast<uint32_t>(f64_to_f8_bits(v.y)) << 8) |
+           (static_cast<uint32_t>(f64_to_f8_bits(v.z)) << 16) | (static_cast<uint32_t>(f64_to_f8_bits(v.w)) << 24);
+  }
+  __device__ static void one(void* dst, int64_t i, float x) { static_cast<f8_t*>(dst)[i] = f64_to_f8_bits(x); }
+};
+
+template <bool kF8>
+__global__ __launch_bounds__(kThreads) void cast_f32_kernel(const float4* __restrict__ src,
+                                                             typename CastOut<kF8>::vec* __restrict__ dst,
+                                                             int64_t nvec) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads * kCastVec;
+  for (int64_t base = static_cast<int64_t>(blockIdx.x) * kThreads * kCastVec + threadIdx.x; base < nvec;
+       base += stride) {
+    float4 v[kCastVec];
+#pragma unroll
+    for (int u = 0; u < kCastVec; ++u) {
+      const int64_t i = base + static_cast<int64_t>(u) * kThreads;
+      v[u] = i < nvec ? src[i] : float4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int u = 0; u < kCastVec; ++u) {
+      const int64_t i = base + static_cast<int64_t>(u) * kThreads;
+      if (i < nvec) dst[i] = CastOut<kF8>::pack(v[u]);
+    }
+  }
+}
+
+template <bool kF8>
+__global__ __launch_bounds__(kThreads) void cast_f32_tail_kernel(const float* __restrict__ src, void* dst,
+                                                                  int64_t off, int64_t n) {
+  const int64_t i = off + static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (i < n) CastOut<kF8>::one(dst, i, src[i]);
+}
+
+template <bool kF8>
+void launch_cast_f32(const float* src, void* dst, int64_t n, hipStream_t st) {
+  const int64_t nvec = n / 4;
+  if (nvec > 0) {
+    // enough workgroups to fill every CU many times over; each thread then loops
+    const int64_t per_block = static_cast<int64_t>(kThreads) * kCastVec;
+    const int64_t blocks = std::min<int64_t>(ceil_div(nvec, per_block), 256 * 32);
+    cast_f32_kernel<kF8><<<static_cast<unsigned>(blocks), kThreads, 0, st>>>(
+        reinterpret_cast<const float4*>(src), static_cast<typename CastOut<kF8>::vec*>(dst), nvec);
+  }
+  if (n > nvec * 4) cast_f32_tail_kernel<kF8><<<1, kThreads, 0, st>>>(src, dst, nvec * 4, n);
 }
 
 __global__ __launch_bounds__(kThreads) void prep_kernel(const double* src, int64_t m, int64_t K, bool trans,
@@ -175,6 +252,17 @@ int grid_for(int64_t n) {
 hipError_t launch_convert(const void* src, rt_dtype sdt, void* dst, rt_dtype ddt, int64_t n, int scale_exp,
                           hipStream_t st) {
   if (n == 0) return hipSuccess;
+  // binary32 sources at 16-byte alignment take the vectorised cast (no scaling: the
+  // E4M3 saturation would otherwise have to see the scaled value)
+  const bool vec_src = sdt == RT_F32 && scale_exp == 0 && (reinterpret_cast<uintptr_t>(src) & 15u) == 0;
+  if (vec_src && ddt == RT_BF16 && (reinterpret_cast<uintptr_t>(dst) & 7u) == 0) {
+    launch_cast_f32<false>(static_cast<const float*>(src), dst, n, st);
+    return hipGetLastError();
+  }
+  if (vec_src && ddt == RT_F8E4M3 && (reinterpret_cast<uintptr_t>(dst) & 3u) == 0) {
+    launch_cast_f32<true>(static_cast<const float*>(src), dst, n, st);
+    return hipGetLastError();
+  }
   const double scale = ldexp(1.0, scale_exp);
   convert_kernel<<<grid_for(n), kThreads, 0, st>>>(src, sdt, dst, ddt, n, scale);
   return hipGetLastError();

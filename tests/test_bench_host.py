@@ -19,12 +19,12 @@ def bench():
     return mod
 
 
-def _tree(tmp_path, src_text, digest, kernel="sketch_pass_bf16", nbytes=1234567):
+def _tree(tmp_path, src_text, digest, kernel="sketch_pass_bf16", nbytes=1234567, file_kernel="sketch_pass_bf16"):
     src = tmp_path / "k.hip"
     src.write_text(src_text)
     prof = tmp_path / "profiles"
     prof.mkdir()
-    (prof / "hbm_counters_sketch_pass_bf16_1024x1024x512.md").write_text(
+    (prof / f"hbm_counters_{file_kernel}_1024x1024x512.md").write_text(
         "summary text\n\n"
         f"traffic_kernel: {kernel}\n"
         f"traffic_bytes_per_launch: {nbytes}\n"
@@ -54,16 +54,27 @@ def test_traffic_withheld_for_another_kernel(bench, tmp_path, monkeypatch):
     assert bench.counter_traffic("core_ttm1_bf16") is None
 
 
+def test_traffic_withheld_when_summary_names_another_kernel(bench, tmp_path, monkeypatch):
+    text = "kernel source\n"
+    _tree(tmp_path, text, hashlib.sha256(text.encode()).hexdigest(), kernel="sketch_pass_bf16",
+          file_kernel="core_ttm1_f32")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.counter_traffic("core_ttm1_f32") is None
+
+
 def test_traffic_withheld_without_summary(bench, tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.counter_traffic("sketch_pass_bf16") is None
 
 
-def test_committed_summary_is_well_formed(bench):
-    # the committed summary names the dominant kernel, a positive byte count and a source file
-    # that exists; whether its hash still matches depends on later edits and is not asserted
-    text = open(os.path.join(ROOT, "profiles", "hbm_counters_sketch_pass_bf16_1024x1024x512.md")).read()
-    assert re.search(r"^traffic_kernel: sketch_pass_bf16$", text, re.M)
+@pytest.mark.parametrize("path", sorted(p for p in os.listdir(os.path.join(ROOT, "profiles"))
+                                        if p.startswith("hbm_counters_") and p.endswith("_1024x1024x512.md")))
+def test_committed_summary_is_well_formed(bench, path):
+    # each committed summary names its kernel, a positive byte count and a source file that
+    # exists; whether its hash still matches depends on later edits and is not asserted
+    text = open(os.path.join(ROOT, "profiles", path)).read()
+    kernel = path[len("hbm_counters_"):-len("_1024x1024x512.md")]
+    assert re.search(rf"^traffic_kernel: {kernel}$", text, re.M)
     m = re.search(r"^traffic_bytes_per_launch: (\d+)$", text, re.M)
     assert m and int(m.group(1)) > 0
     m = re.search(r"^source_sha256\((\S+)\): [0-9a-f]{64}$", text, re.M)

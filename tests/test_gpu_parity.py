@@ -53,6 +53,28 @@ def test_convert_f8_bit_exact(src):
     np.testing.assert_array_equal(got.float().cpu().numpy().astype(np.float64), L.f8_decode(got_bits))
 
 
+@pytest.mark.parametrize("dst", ["bf16", "f8"])
+@pytest.mark.parametrize("n,offset", [(1, 0), (3, 1), (4097, 0), (4097, 3), (1 << 20, 2), ((1 << 20) + 5, 0)])
+def test_convert_f32_vector_and_scalar_paths(dst, n, offset):
+    """The vectorised binary32 cast (16-byte aligned source) and the element-wise one
+    (misaligned source) give the same bits as the format definition, tails included."""
+    say("convert paths", dst, n, offset)
+    rng = np.random.default_rng(101 + n + offset)
+    x = (rng.standard_normal(n + offset) * np.exp2(rng.integers(-20, 10, n + offset))).astype(np.float32)
+    t = dev(x, torch.float32)[offset:]
+    tdt = torch.bfloat16 if dst == "bf16" else torch.float8_e4m3fn
+    got = rt.rtucker_convert(t, tdt)
+    xv = x[offset:].astype(np.float64)
+    if dst == "bf16":
+        bits = got.view(torch.int16).cpu().numpy().view(np.uint16)
+        np.testing.assert_array_equal(bits, L.bf16_bits(L.round_bf16(xv)))
+    else:
+        bits = got.view(torch.uint8).cpu().numpy()
+        np.testing.assert_array_equal(bits, L.f8_bits(L.round_f8(xv)))
+    out = torch.empty_like(got)
+    assert rt.rtucker_convert(t, tdt, out=out) is out and torch.equal(out.view(torch.uint8), got.view(torch.uint8))
+
+
 def test_convert_scale_exponent():
     x = np.array([1.0, 3.0, -0.75, 100.0])
     got = rt.rtucker_convert(dev(x, torch.float32), torch.float32, scale_exp=-3)
@@ -344,6 +366,26 @@ def test_decompose_bitwise_repeatable():
     G2, U2 = rt.rtucker_decompose(Xd, [6, 6, 6], 4, phis, s=s)
     torch.cuda.synchronize()
     assert torch.equal(G1, G2) and all(torch.equal(a, b) for a, b in zip(U1, U2))
+
+
+@pytest.mark.parametrize("algo", ["rhkron", "rsthkron"])
+def test_decompose_phases_bitwise_and_positive(algo):
+    """The phase-timed call returns the plain call's results bit for bit, and a positive time
+    for each of sketch, QR, core and truncation."""
+    X = synth.bumps_field((64, 72, 80), nbumps=20, noise_rel=1e-4, seed=14)
+    Xd = dev(X, torch.float32)
+    if algo == "rhkron":
+        s = [4, 4, 4]
+        phis = [dev(f) for f in reuse_phis(X.shape, s, seed=15)]
+    else:
+        s = T.subrank_matrix_sth([10, 10, 10])
+        phis = [[None if f is None else dev(f) for f in row] for row in sth_phis(X.shape, s, seed=15)]
+    G1, U1 = rt.rtucker_decompose(Xd, [6, 6, 6], 4, phis, algo=algo, s=s)
+    G2, U2, ph = rt.rtucker_decompose_phases(Xd, [6, 6, 6], 4, phis, algo=algo, s=s)
+    torch.cuda.synchronize()
+    assert torch.equal(G1, G2) and all(torch.equal(a, b) for a, b in zip(U1, U2))
+    assert set(ph) == {"sketch", "qr", "core", "truncate"}
+    assert all(v > 0.0 for v in ph.values()), ph
 
 
 def test_rel_error_matches_oracle():
