@@ -204,6 +204,23 @@ int rtucker_decompose_phases(const rt_tensor* X, const rt_tensor* X_sketch, cons
                              double* G, double* const* U, void* ws, size_t ws_bytes, void* stream,
                              float* phase_ms);
 
+/* Allocation-free form of rtucker_decompose, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Same arguments and results as rtucker_decompose without ws/ws_bytes:
+ * the workspace is a static device array of the library, RTUCKER_NOALLOC_SCRATCH_BYTES
+ * (64 MiB) per GPU, held until the process ends (enough for, e.g., 256^3 binary32 at
+ * ranks 16).  The call allocates nothing and copies nothing from the host; its first
+ * call on a device looks up that device's array.  Every call on one GPU uses the same
+ * array, so calls that overlap on one GPU (concurrent streams or threads) race; calls
+ * ordered on one stream do not.  No part of the array needs clearing between calls:
+ * every kernel initialises what it reads.
+ * RT_EWORKSPACE if rtucker_decompose_workspace() exceeds the array; RT_EHIP if the
+ * array's address cannot be obtained. */
+#define RTUCKER_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int rtucker_decompose_noalloc(const rt_tensor* X, const rt_tensor* X_sketch, const int32_t* r,
+                              int32_t p, const int64_t* s, rt_algo algo, const double* const* phi,
+                              double* G, double* const* U, void* stream);
+
 /* ------------------------------------------------------------------ error
  * Squared norms for the relative reconstruction error (Sec. 5), in binary64 on
  * the device, by explicit residual (no cancellation-prone identity):

@@ -66,6 +66,9 @@ _SIGS = {
                                                 ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                                 ctypes.c_void_p]),
+    "rtucker_decompose_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                                 ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.c_void_p, ctypes.c_void_p]),
     "rtucker_rel_error_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "rtucker_rel_error": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
@@ -340,6 +343,25 @@ def rtucker_decompose(X, r, p, phis, algo="rhkron", s=None, X_sketch=None, G=Non
     """
     args, G, Us, _keep = _decompose_args(X, r, p, phis, algo, s, X_sketch, G, Us, ws)
     _check(lib().rtucker_decompose(*args), "rtucker_decompose")
+    return G, Us
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def rtucker_decompose_noalloc(X, r, p, phis, G, Us, algo="rhkron", s=None, X_sketch=None):
+    """rtucker_decompose into the caller's G and U_j, with the library's static device scratch
+    as workspace (the C call allocates nothing; at most 64 MiB of workspace)."""
+    d = X.dim()
+    xt = _tensor(X)
+    xs = _tensor(X_sketch) if X_sketch is not None else None
+    if ALGOS[algo] == RT_RSTHKRON:
+        flat = [phis[j][k] if k != j else None for j in range(d) for k in range(d)]
+    else:
+        flat = list(phis)
+    _check(lib().rtucker_decompose_noalloc(ctypes.byref(xt), ctypes.byref(xs) if xs is not None else None, _i32(r),
+                                           int(p), _s_array(s, algo, d), ALGOS[algo], _ptrs(flat), _ptr(G), _ptrs(Us),
+                                           _stream(X.device)), "rtucker_decompose_noalloc")
     return G, Us
 
 

@@ -1168,6 +1168,31 @@ int query(F&& plan, size_t* bytes) {
 
 }  // namespace
 
+// ------------------------------------------------------------------ static scratch
+// Workspace of rtucker_decompose_noalloc: a file-scope device array, one copy per GPU
+// the library runs on, held until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in symbol): its device
+// address is looked up once per device with hipGetSymbolAddress and kept here.
+constexpr size_t kScratchBytes = static_cast<size_t>(RTUCKER_NOALLOC_SCRATCH_BYTES);
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;  // device ordinal -> address of that device's scratch
+
+int scratch_for_current_device(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return RT_EHIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return RT_EHIP;
+    it = g_scratch_ptr.emplace(dev, ptr).first;
+  }
+  *out = it->second;
+  return RT_OK;
+}
+
 // ====================================================================== C ABI
 extern "C" {
 
@@ -1234,6 +1259,21 @@ int rtucker_decompose_phases(const rt_tensor* X, const rt_tensor* X_sketch, cons
   if (!phase_ms) return RT_EINVAL;
   return run_timed([&](Ctx& c) { return plan_decompose(c, X, X_sketch, r, p, s, algo, phi, G, U); }, ws, ws_bytes,
                    stream, phase_ms);
+}
+
+int rtucker_decompose_noalloc(const rt_tensor* X, const rt_tensor* X_sketch, const int32_t* r, int32_t p,
+                              const int64_t* s, rt_algo algo, const double* const* phi, double* G, double* const* U,
+                              void* stream) {
+  size_t need = 0;
+  int st = query([&](Ctx& c) { return plan_decompose(c, X, X_sketch, r, p, s, algo, nullptr, nullptr, nullptr); },
+                 &need);
+  if (st) return st;
+  if (need > kScratchBytes) return RT_EWORKSPACE;
+  void* ws = nullptr;
+  st = scratch_for_current_device(&ws);
+  if (st) return st;
+  return run([&](Ctx& c) { return plan_decompose(c, X, X_sketch, r, p, s, algo, phi, G, U); }, ws, kScratchBytes,
+             stream);
 }
 
 int rtucker_rel_error_workspace(const rt_tensor* X, const int32_t* r, size_t* bytes) {
