@@ -36,6 +36,9 @@ RANKS = (32, 32, 32)
 P_OVER = 8
 HBM_PEAK = 8.0e12          # B/s
 MFMA_PEAK = {"f32": 157.3e12, "bf16": 2.5e15, "f8": 5.0e15}
+# (d, n, s) of the dimension-tree experiment timed here (the paper's third point, (3, 4000, 20),
+# needs subrank 20, beyond the one-pass sketch's limit of 8)
+E4_CASES = ((4, 500, 5), (5, 145, 3))
 
 
 def log(*a):
@@ -92,6 +95,9 @@ def main():
                     help="only copy 1 GiB device buffers three times (reference for the HBM byte counters)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 128^4 rSTHKron, 256^3 adjoint and 512-tensor batch measurements")
+    ap.add_argument("--no-paper-scale", action="store_true",
+                    help="skip the tensors of the paper's own scale (the dimension-tree experiment at ~256 GB "
+                         "and the 410^4 exact-rank tensor)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "rtucker runs on one GPU only; sharding across GPUs is described in the "
@@ -273,6 +279,8 @@ def main():
     extras = {}
     if not args.no_extras:
         extras = run_extras(rt, synth, torch, dev, time_steps, log)
+    if not args.no_paper_scale:
+        extras.update(run_paper_scale(rt, synth, torch, dev, time_steps, log, keep=[X32, X16, X8]))
 
     # ---------------------------------------------------------------- CPU baseline (oracle, whole workload)
     cpu = None
@@ -346,6 +354,86 @@ def cpu_baseline(Xh, phis_h, step_flops):
                       f"{threads} BLAS threads: {dt_all:.3f} s; one thread: {dt_one:.3f} s",
             "one_core": {"value": round(step_flops / dt_one / 1e12, 6), "seconds": round(dt_one, 3), "cores": 1},
             "cpu_model": cpu_model(), "blas": blas}
+
+
+def run_paper_scale(rt, synth, torch, dev, time_steps, log, keep=()):
+    """Workloads at the paper's own sizes, generated on the device (exact Tucker tensors):
+
+    * the dimension-tree experiment (Sec. 7.3): the sketch of every mode of a d-way n^d
+      binary32 tensor with s = subrank per mode, (d, n, s) = (4, 500, 5) and (5, 145, 3),
+      about 256 GB each; "tree on" = all modes in one call (one read of X
+      for the first level, memoised tree below it), "tree off" = one call per mode;
+    * the strong-scaling tensor (Sec. 7.4): 410^4 binary32 (113 GB), exact rank 20,
+      r = 20, p = 3, rHKron and rSTHKron on one GPU.
+    Each is skipped when the device lacks the memory."""
+    out = {}
+    torch.cuda.empty_cache()
+    held = sum(int(t.numel()) * t.element_size() for t in keep)
+
+    def room(nbytes):
+        free, _ = torch.cuda.mem_get_info()
+        return free >= nbytes + (24 << 30)
+
+    e4 = {}
+    for d, n, sub in E4_CASES:
+        key = f"d{d}_n{n}_s{sub}"
+        nbytes = 4 * n ** d
+        if not room(nbytes):
+            e4[key] = {"skipped": f"needs {nbytes / 2**30:.0f} GiB + 24 GiB free ({held / 2**30:.1f} GiB held)"}
+            continue
+        log(f"dimension-tree experiment {key}: generating {nbytes / 1e9:.0f} GB on the device ...")
+        core, F = synth.tucker_factors((n,) * d, [6] * d, seed=80 + d)
+        X = synth.tucker_on_device(core, F, dev, torch.float32)
+        sv = [sub] * d
+        phis = [torch.from_numpy(f).to(dev) for f in synth.gaussians(90 + d, [(sub, n)] * d)]
+        on = time_steps(lambda: rt.rtucker_sketch(X, phis, sv), 3, 1)
+
+        def tree_off():
+            for m in range(d):
+                rt.rtucker_sketch(X, phis, sv, modes=[m])
+        off = time_steps(tree_off, 2, 1)
+        e4[key] = {"tree_on_ms": round(on, 3), "tree_off_ms": round(off, 3), "speedup": round(off / on, 3),
+                   "tree_on_GB/s": round(nbytes / on / 1e6, 1),
+                   "tree_on_hbm_frac": round(nbytes / on / 1e6 / (HBM_PEAK / 1e9), 4)}
+        del X
+        torch.cuda.empty_cache()
+    out["e4_dimension_tree"] = e4
+
+    dims, r, p = (410,) * 4, [20] * 4, 3
+    nbytes = 4 * 410 ** 4
+    if room(int(nbytes * 1.25)):
+        log("generating the 410^4 exact-rank tensor (113 GB) on the device ...")
+        core, F = synth.tucker_factors(dims, r, seed=synth.DATA_SEED)
+        X = synth.tucker_on_device(core, F, dev, torch.float32)
+        for algo in ("rhkron", "rsthkron"):
+            S = rt.rtucker_sketch_sizes(dims, r, p, algo)
+            if algo == "rhkron":
+                shapes = [(S[k], dims[k]) for k in range(4)]
+            else:
+                cdim = [min(dims[k], int(np.prod([S[k][i] for i in range(4) if i != k]))) for k in range(4)]
+                shapes = [None if k == j else (S[j][k], cdim[k] if k < j else dims[k]) for j in range(4)
+                          for k in range(4)]
+            flat = [None if f is None else torch.from_numpy(f).to(dev) for f in synth.gaussians(synth.PHI_SEED, shapes)]
+            ph = flat if algo == "rhkron" else [flat[j * 4:(j + 1) * 4] for j in range(4)]
+            nb = rt.rtucker_decompose_workspace(X, r, p, algo, S)
+            ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
+            G = torch.empty(r, dtype=torch.float64, device=dev)
+            Us = [torch.empty((410, 20), dtype=torch.float64, device=dev) for _ in range(4)]
+            log(f"timing 410^4 {algo} ...")
+            ms = time_steps(lambda: rt.rtucker_decompose(X, r, p, ph, algo=algo, s=S, G=G, Us=Us, ws=ws), 5, 2)
+            _, _, phases = rt.rtucker_decompose_phases(X, r, p, ph, algo=algo, s=S, G=G, Us=Us, ws=ws)
+            del ws
+            torch.cuda.empty_cache()
+            e, _ = rt.rtucker_rel_error(X, G, Us)
+            gap = max(float(np.linalg.norm(u @ u.T - f @ f.T, 2)) for u, f in zip([u.cpu().numpy() for u in Us], F))
+            out[f"{algo}_410^4_f32"] = {"ms": round(ms, 3), "rel_err": e, "max_subspace_gap": gap,
+                                        "phases_ms": {k: round(v, 3) for k, v in phases.items()},
+                                        "read_GB/s": round(nbytes / ms / 1e6, 1)}
+        del X
+        torch.cuda.empty_cache()
+    else:
+        out["rhkron_410^4_f32"] = {"skipped": "not enough device memory"}
+    return out
 
 
 def run_extras(rt, synth, torch, dev, time_steps, log):

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -192,13 +193,38 @@ void sketch_impl(Ctx& c, const Ten& X, const double* const* phi, const int64_t* 
     mf = ct == RT_F32 && ttm_mfma_ok(RT_F32, Ab, dims[k], Bb, s[k]);
     last = ct == RT_F32 && !mf && Bb == 1 && ttm_mfma_last_ok(Ab, dims[k], s[k]);
   };
-  const auto chain_of = [&](int n) {
-    std::vector<int> chain;
-    if (n < S) chain.push_back(L);
-    for (int k = 0; k < S; ++k)
-      if (k != n) chain.push_back(k);
-    return chain;
-  };
+  // Memoised dimension tree below the two first-level nodes (Sec. 4.4): a node serves a
+  // set M of requested modes; every mode that is neither contracted yet nor in M is
+  // contracted at the node (last mode first), then M is split into halves, each served
+  // by its own child.  chains[n] lists the contractions from Z (n = S) or W to Y_n;
+  // targets whose chains share a prefix share the intermediate tensors of that prefix.
+  std::vector<std::vector<int>> chains(d);
+  std::function<void(std::vector<int>, std::vector<bool>, std::vector<int>)> assign =
+      [&](std::vector<int> M, std::vector<bool> done, std::vector<int> prefix) {
+        for (int k = d - 1; k >= 0; --k)
+          if (!done[k] && std::find(M.begin(), M.end(), k) == M.end()) {
+            prefix.push_back(k);
+            done[k] = true;
+          }
+        if (M.size() == 1) {
+          chains[M[0]] = prefix;
+          return;
+        }
+        const size_t half = (M.size() + 1) / 2;
+        assign(std::vector<int>(M.begin(), M.begin() + half), done, prefix);
+        assign(std::vector<int>(M.begin() + half, M.end()), done, prefix);
+      };
+  {
+    std::vector<int> MW;
+    for (int n = 0; n < d; ++n)
+      if ((mask >> n & 1u) && n != S) MW.push_back(n);
+    std::vector<bool> doneW(d, false), doneZ(d, false);
+    doneW[S] = true;
+    doneZ[L] = true;
+    if (!MW.empty()) assign(MW, doneW, {});
+    if (mask >> S & 1u) assign({S}, doneZ, {});
+  }
+  const auto chain_of = [&](int n) { return chains[n]; };
   for (int n = 0; n < d; ++n) {
     if (!(mask >> n & 1u)) continue;
     std::vector<int64_t> dims = (n == S) ? Z.dims : W.dims;
@@ -230,31 +256,35 @@ void sketch_impl(Ctx& c, const Ten& X, const double* const* phi, const int64_t* 
     if (needZ) Z = ttm(c, X, L, op[L], s[L]);
     if (needW) W = ttm(c, X, S, op[S], s[S]);
   }
-  // second and later levels of the tree: the contractions of one level are independent,
-  // so the binary32 matrix-core ones go out as one grouped launch
-  std::vector<Ten> cur(d);
-  std::vector<std::vector<int>> chains(d);
+  // second and later levels of the tree: one tensor per distinct chain prefix; the
+  // contractions of one level are independent, so the binary32 matrix-core ones go out
+  // as one grouped launch
+  typedef std::pair<int, std::vector<int>> NodeKey;  // (0: from Z, 1: from W; prefix)
+  std::map<NodeKey, Ten> node;
+  node[NodeKey{0, {}}] = Z;
+  node[NodeKey{1, {}}] = W;
   size_t levels = 0;
-  for (int n = 0; n < d; ++n) {
-    if (!(mask >> n & 1u)) continue;
-    cur[n] = (n == S) ? Z : W;
-    chains[n] = chain_of(n);
-    levels = std::max(levels, chains[n].size());
-  }
+  for (int n = 0; n < d; ++n)
+    if (mask >> n & 1u) levels = std::max(levels, chains[n].size());
   for (size_t lev = 0; lev < levels; ++lev) {
-    std::vector<F32Contraction> group;
-    std::vector<int> generic_modes, last_modes;
-    std::vector<void*> last_ws;
-    std::vector<Ten> next = cur;
+    // the distinct nodes of this level, in order of their first target
+    std::vector<NodeKey> keys;
     for (int n = 0; n < d; ++n) {
       if (!(mask >> n & 1u) || chains[n].size() <= lev) continue;
-      const int k = chains[n][lev];
-      const Ten& t = cur[n];
+      NodeKey key{n == S ? 0 : 1, std::vector<int>(chains[n].begin(), chains[n].begin() + lev + 1)};
+      if (std::find(keys.begin(), keys.end(), key) == keys.end()) keys.push_back(key);
+    }
+    std::vector<F32Contraction> group;
+    std::vector<NodeKey> generic_keys, last_keys;
+    std::vector<void*> last_ws;
+    for (const NodeKey& key : keys) {
+      const int k = key.second.back();
+      const Ten& t = node.at(NodeKey{key.first, std::vector<int>(key.second.begin(), key.second.end() - 1)});
       const int64_t Ab = t.before(k), K = t.dims[k], Bb = t.after(k), m = s[k];
       bool mf = false, last = false;
       tree_kind(t.dims, k, mf, last);
       if (!mf && !last) {
-        generic_modes.push_back(n);
+        generic_keys.push_back(key);
         continue;
       }
       if (!opm[k]) opm[k] = prep(c, phi ? phi[k] : nullptr, m, K, false, X.dt, RT_F32, ttm_mfma_mpad(m));
@@ -264,9 +294,9 @@ void sketch_impl(Ctx& c, const Ten& X, const double* const* phi, const int64_t* 
       o.dt = RT_F32;
       o.p = c.take(static_cast<size_t>(Ab) * m * Bb * sizeof(float));
       void* w = c.take(last ? ttm_mfma_last_ws(Ab, K, m) : ttm_mfma_ws(RT_F32, Ab, K, Bb, m));
-      next[n] = o;
+      node[key] = o;
       if (last) {
-        last_modes.push_back(n);
+        last_keys.push_back(key);
         last_ws.push_back(w);
       } else {
         group.push_back(F32Contraction{static_cast<const float*>(t.p), Ab, K, Bb, static_cast<const float*>(opm[k]), m,
@@ -275,21 +305,25 @@ void sketch_impl(Ctx& c, const Ten& X, const double* const* phi, const int64_t* 
     }
     c.flush();
     if (!c.dry) {
-      for (size_t i = 0; i < last_modes.size(); ++i) {
-        const int n = last_modes[i], k = chains[n][lev];
-        const Ten& t = cur[n];
+      for (size_t i = 0; i < last_keys.size(); ++i) {
+        const NodeKey& key = last_keys[i];
+        const int k = key.second.back();
+        const Ten& t = node.at(NodeKey{key.first, std::vector<int>(key.second.begin(), key.second.end() - 1)});
         c.chk(launch_ttm_mfma_last(static_cast<const float*>(t.p), t.before(k), t.dims[k],
                                    static_cast<const float*>(opm[k]), s[k],
-                                   static_cast<float*>(const_cast<void*>(next[n].p)), last_ws[i], c.st));
+                                   static_cast<float*>(const_cast<void*>(node.at(key).p)), last_ws[i], c.st));
       }
       c.chk(launch_ttm_mfma_f32_group(group.data(), static_cast<int>(group.size()), c.st));
     }
-    for (int n : generic_modes) {
-      const int k = chains[n][lev];
-      next[n] = ttm(c, cur[n], k, op[k], s[k]);
+    for (const NodeKey& key : generic_keys) {
+      const int k = key.second.back();
+      const Ten t = node.at(NodeKey{key.first, std::vector<int>(key.second.begin(), key.second.end() - 1)});
+      node[key] = ttm(c, t, k, op[k], s[k]);
     }
-    cur = next;
   }
+  std::vector<Ten> cur(d);
+  for (int n = 0; n < d; ++n)
+    if (mask >> n & 1u) cur[n] = node.at(NodeKey{n == S ? 0 : 1, chains[n]});
   out.assign(d, SketchOut{});
   for (int n = 0; n < d; ++n) {
     if (!(mask >> n & 1u)) continue;

@@ -165,3 +165,37 @@ def batch_phis(dims_list, s_list, seed: int = PHI_SEED):
     shapes = [(s[k], d[k]) for d, s in zip(dims_list, s_list) for k in range(3)]
     flat = gaussians(seed, shapes)
     return [flat[3 * i:3 * i + 3] for i in range(len(dims_list))]
+
+
+def tucker_factors(dims, ranks, seed: int = DATA_SEED, core=None):
+    """Core ~ N(0,1) (unless given) and orthonormal factors of a random Tucker tensor, without
+    assembling it: the inputs of ``tucker_on_device`` for tensors too large for host memory."""
+    rng = np.random.default_rng(seed)
+    if core is None:
+        core = rng.standard_normal(tuple(int(r) for r in ranks))
+    factors = [orthonormal(rng, int(n), int(c)) for n, c in zip(dims, core.shape)]
+    return core, factors
+
+
+def tucker_on_device(core, factors, device, dtype, chunk_elems: int = 1 << 28):
+    """Assemble core x_1 F_1 ... x_d F_d directly in device memory (torch matmuls in float64,
+    stored in ``dtype``), slab by slab along mode 1, so that host memory holds only the small
+    core and factors.  Input construction only: the decomposition's arithmetic runs elsewhere."""
+    import torch
+
+    d = core.ndim
+    dims = [int(f.shape[0]) for f in factors]
+    out = torch.empty(dims, dtype=dtype, device=device)
+    C = torch.as_tensor(core, dtype=torch.float64, device=device)
+    F = [torch.as_tensor(f, dtype=torch.float64, device=device) for f in factors]
+    # T = core x_2 F_2 ... x_d F_d  would be too large; contract modes 2..d per slab instead
+    rest = int(np.prod(dims[1:]))
+    rows = max(1, min(dims[0], chunk_elems // max(rest, 1)))
+    for i0 in range(0, dims[0], rows):
+        i1 = min(dims[0], i0 + rows)
+        T = torch.tensordot(F[0][i0:i1], C, dims=([1], [0]))  # (rows, r2, ..., rd)
+        for k in range(1, d):
+            T = torch.tensordot(T, F[k], dims=([1], [1]))  # contract the leading core mode, append I_k
+        out[i0:i1] = T.to(dtype)
+        del T
+    return out

@@ -96,6 +96,9 @@ SKETCH_CASES = [
                                      # of the four waves have no columns
     ((20, 18, 16, 12), (4, 4, 4, 4)),  # 4-way: one tree level's matrix-core contractions share one
                                        # launch, the next level's differ in K % 4 (one launch each)
+    ((6, 7, 5, 9, 40), (2, 2, 3, 2, 3)),  # 5-way: memoised tree, two shared prefixes below W
+    ((4, 5, 3, 6, 4, 36), (2, 3, 2, 2, 3, 2)),  # 6-way
+    ((12, 16, 20, 24, 64), (3, 3, 3, 3, 3)),  # 5-way with matrix-core tree contractions
 ]
 
 
