@@ -241,6 +241,39 @@ def rhkron(X: np.ndarray, r, phis, *, return_parts: bool = False):
     return G, Us
 
 
+def rhkron_noreuse(X: np.ndarray, r, phis, *, return_parts: bool = False):
+    """Randomized HOSVD with an independent set of Kronecker factors per mode (App. A).
+
+    ``phis[j][k]`` is Phi_{j,k} (s_{j,k} x I_k) for k != j; row j of the subrank matrix
+    S follows the rule of Sec. 4.2 (``subrank_matrix_sth``).  For every mode j: sketch
+    Y = X x_{k != j} Phi_{j,k}, thin QR of Y_(j) gives U_hat_j.  Then, as in the reuse
+    algorithm, G_hat = X x_1 U_hat_1^T ... x_d U_hat_d^T, STHOSVD(G_hat, r) and
+    U_j = U_hat_j V_j.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    d = X.ndim
+    Uhat = []
+    for j in range(d):
+        Y = multi_ttm(X, {k: phis[j][k] for k in range(d) if k != j})
+        Q, _ = qr_pos(unfold(Y, j))
+        Uhat.append(Q)
+    Ghat = X
+    for k in core_order(X.shape):
+        Ghat = ttm(Ghat, Uhat[k].T, k)
+    G, Vs = sthosvd(Ghat, r)
+    Us = [Uh @ V for Uh, V in zip(Uhat, Vs)]
+    if return_parts:
+        return G, Us, {"Uhat": Uhat, "Ghat": Ghat, "V": Vs}
+    return G, Us
+
+
+def noreuse_phi_shapes(dims, S):
+    """Shapes of Phi_{j,k} for the no-reuse algorithm (App. A): s_{j,k} x I_k (X is never
+    truncated before it is sketched).  Diagonal entries are None."""
+    d = len(dims)
+    return [[None if k == j else (int(S[j][k]), int(dims[k])) for k in range(d)] for j in range(d)]
+
+
 def sth_phi_shapes(dims, S):
     """Shapes of Phi_{j,k} for the sequentially truncated algorithm (Sec. 4.2).
 

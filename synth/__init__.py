@@ -199,3 +199,21 @@ def tucker_on_device(core, factors, device, dtype, chunk_elems: int = 1 << 28):
         out[i0:i1] = T.to(dtype)
         del T
     return out
+
+
+def srht_draws(seed: int, specs):
+    """Random draws of subsampled randomized Hadamard factors: for each (s, N, n) in
+    ``specs`` (None entries give None), s distinct row indices in [0, N) and n signs +-1
+    (int64 and float64 arrays), drawn in order with PCG64.  How a factor is formed from
+    them is the method's business, not this module's."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for sp in specs:
+        if sp is None:
+            out.append(None)
+            continue
+        s, N, n = (int(v) for v in sp)
+        rows = rng.choice(N, size=s, replace=False).astype(np.int64)
+        signs = rng.choice(np.array([-1.0, 1.0]), size=n)
+        out.append((rows, signs))
+    return out
