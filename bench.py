@@ -216,6 +216,28 @@ def main():
         flat = synth.gaussians(synth.PHI_SEED, shapes)
         sphis = [[None if f is None else torch.from_numpy(f).to(dev) for f in flat[j * 3:(j + 1) * 3]]
                  for j in range(3)]
+        # the sketch variants (FP32): an independent factor set per mode (App. A), and the reuse
+        # algorithm with subsampled randomized Hadamard factors made on the device (Sec. 5.1)
+        SN = rt.rtucker_sketch_sizes(DIMS, RANKS, P_OVER, "rhkron_noreuse")
+        nshapes = [None if k == j else (SN[j][k], DIMS[k]) for j in range(3) for k in range(3)]
+        nflat = synth.gaussians(synth.PHI_SEED, nshapes)
+        nphis = [[None if f is None else torch.from_numpy(f).to(dev) for f in nflat[j * 3:(j + 1) * 3]]
+                 for j in range(3)]
+        fn, G, U = make_run(X32, algo="rhkron_noreuse", sizes=SN, ph=nphis)
+        log("timing rhkron_noreuse_f32 ...")
+        ms = time_steps(fn, max(3, args.steps // 2), 2)
+        e, _ = rt.rtucker_rel_error(X32, G, U)
+        results["rhkron_noreuse_f32"] = {"ms": ms, "rel_err": e,
+                                         "phases_ms": phases_of(X32, "rhkron_noreuse", sizes=SN, ph=nphis)}
+        pads = [1 << (int(n) - 1).bit_length() for n in DIMS]
+        draws = synth.srht_draws(synth.PHI_SEED, [(s[k], pads[k], DIMS[k]) for k in range(3)])
+        sr_phis = [rt.rtucker_srht_factor(DIMS[k], torch.from_numpy(draws[k][0]).to(dev),
+                                          torch.from_numpy(draws[k][1]).to(dev)) for k in range(3)]
+        fn, G, U = make_run(X32, sizes=s, ph=sr_phis)
+        log("timing rhkron_srht_f32 ...")
+        ms = time_steps(fn, max(3, args.steps // 2), 2)
+        e, _ = rt.rtucker_rel_error(X32, G, U)
+        results["rhkron_srht_f32"] = {"ms": ms, "rel_err": e}
         for name, X in (("rsthkron_f32", X32), ("rsthkron_bf16", X16)):
             fn, G, U = make_run(X, algo="rsthkron", sizes=S, ph=sphis)
             log(f"timing {name} ...")

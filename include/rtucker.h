@@ -61,8 +61,10 @@ typedef enum {
 } rt_dtype;
 
 typedef enum {
-  RT_RHKRON = 0,   /* randomized HOSVD with Kronecker factor reuse (Alg. 4.4, Sec. 4.3) */
-  RT_RSTHKRON = 1  /* randomized STHOSVD with Kronecker products (Alg. 4.3, Sec. 4.2) */
+  RT_RHKRON = 0,          /* randomized HOSVD with Kronecker factor reuse (Alg. 4.4, Sec. 4.3) */
+  RT_RSTHKRON = 1,        /* randomized STHOSVD with Kronecker products (Alg. 4.3, Sec. 4.2) */
+  RT_RHKRON_NOREUSE = 2   /* randomized HOSVD with an independent Kronecker factor set per
+                             mode (App. A); subranks as the d x d matrix of Alg. 4.3 */
 } rt_algo;
 
 /* A dense C-order tensor in device memory. */
@@ -83,11 +85,11 @@ const char* rtucker_version(void);
  * Sketch sizes (Sec. 4.2 and 4.3, "choosing subranks").  Host only.
  *  RT_RHKRON:   s_out[d]:  s_i = ceil((prod_j ell_j)^(1/(d-1)) / ell_i), computed
  *               exactly in integers (least s with (s*ell_i)^(d-1) >= prod ell).
- *  RT_RSTHKRON: s_out[d*d] (row-major S, diagonal 1): row j holds d-1 integer
- *               factors of ell_j, each >= 2; when ell_j has no such split, ell_j
- *               is raised to the least value that has one (extra oversampling);
- *               the most balanced split (smallest largest factor) is taken and
- *               assigned to modes k != j in ascending order, largest first.
+ *  RT_RSTHKRON, RT_RHKRON_NOREUSE: s_out[d*d] (row-major S, diagonal 1): row j
+ *               holds d-1 integer factors of ell_j, each >= 2; when ell_j has no
+ *               such split, ell_j is raised to the least value that has one (extra
+ *               oversampling); the most balanced split (smallest largest factor) is
+ *               taken and assigned to modes k != j in ascending order, largest first.
  * Fails with RT_ESHAPE if r_n > I_n, and if any s_k exceeds the mode size it
  * will be applied to (I_k; for RT_RSTHKRON and k < j the truncated size). */
 int rtucker_sketch_sizes(int32_t d, const int64_t* dims, const int32_t* r, int32_t p,
@@ -171,14 +173,18 @@ int rtucker_core(const rt_tensor* X, const double* const* U, const int64_t* l,
  *  X:        dtype F64, F32 or BF16.
  *  X_sketch: NULL, or a tensor with X's dims used for the sketch instead of X
  *            (e.g. an F8E4M3 copy); RT_RHKRON only.
+ *  Sketch passes over X: one for RT_RHKRON (all modes, dimension tree), one per mode for
+ *  RT_RHKRON_NOREUSE, one per step on the shrinking core for RT_RSTHKRON.
  *  r[d], p:  1 <= r_n <= min(I_n, ltilde_n), p >= 0.
- *  s:        RT_RHKRON: d subranks; RT_RSTHKRON: d*d row-major subrank matrix
- *            (diagonal ignored); NULL = rtucker_sketch_sizes().  Must satisfy
- *            ltilde_n >= r_n + p.
- *  phi:      device binary64 Gaussian factors.  RT_RHKRON: phi[k] is s_k x I_k.
+ *  s:        RT_RHKRON: d subranks; RT_RSTHKRON, RT_RHKRON_NOREUSE: d*d row-major
+ *            subrank matrix (diagonal ignored); NULL = rtucker_sketch_sizes().  Must
+ *            satisfy ltilde_n >= r_n + p.
+ *  phi:      device binary64 random factors (Gaussian, or SRHT from
+ *            rtucker_srht_factor).  RT_RHKRON: phi[k] is s_k x I_k.
  *            RT_RSTHKRON: phi[j*d + k] (k != j) is s_{j,k} x n_k with n_k = c_k
  *            for k < j and I_k for k > j, where c_k = min(I_k, ltilde_k) is the
- *            truncated size of mode k.
+ *            truncated size of mode k.  RT_RHKRON_NOREUSE: phi[j*d + k] (k != j) is
+ *            s_{j,k} x I_k.
  *  G:        device binary64, r_1 x ... x r_d.
  *  U[j]:     device binary64, I_j x r_j.  Columns ordered by decreasing singular
  *            value of the core unfolding; each column's largest-magnitude entry
@@ -242,6 +248,20 @@ int rtucker_rel_error(const rt_tensor* X, const double* G, const int32_t* r,
  *  src_dtype: F64 or F32.  dst_dtype: F32, BF16 or F8E4M3.  n >= 0. */
 int rtucker_convert(const void* src, rt_dtype src_dtype, void* dst, rt_dtype dst_dtype,
                     int64_t n, int32_t scale_exp, void* stream);
+
+/* ------------------------------------------------------------------ SRHT factors
+ * A subsampled randomized Hadamard factor of the Kronecker sketch (Sec. 5.1):
+ *   Phi = (R H D)[:, :n],  phi[i*n + j] = signs[j] * H[rows[i]][j] / sqrt(N),
+ * with N the least power of two >= n (a mode of size n is read as zero-padded to N),
+ * H the N x N Walsh-Hadamard matrix in Sylvester order (H[a][b] = (-1)^popcount(a & b)),
+ * D = diag(signs) and R the selection of rows.  The result is a binary64 s x n row-major
+ * matrix, usable as phi[k] of rtucker_sketch / rtucker_decompose.
+ *  rows:  device, s distinct int64 in [0, N) (not checked: an index outside gives a
+ *         wrong factor, never an access outside the buffers);
+ *  signs: device, n binary64 values +-1;  phi: device, s x n binary64.
+ *  RT_ESHAPE unless 1 <= s <= N and n >= 1. */
+int rtucker_srht_factor(int64_t n, int64_t s, const int64_t* rows, const double* signs, double* phi,
+                        void* stream);
 
 /* ------------------------------------------------------------------ adjoint
  * Plain multi-TTM and its adjoint pieces, for differentiation (Sec. 2.1

@@ -19,7 +19,8 @@ MAX_D = 8
 
 RT_F64, RT_F32, RT_BF16, RT_F8E4M3 = 0, 1, 2, 3
 RT_RHKRON, RT_RSTHKRON = 0, 1
-ALGOS = {"rhkron": RT_RHKRON, "rsthkron": RT_RSTHKRON}
+RT_RHKRON_NOREUSE = 2
+ALGOS = {"rhkron": RT_RHKRON, "rsthkron": RT_RSTHKRON, "rhkron_noreuse": RT_RHKRON_NOREUSE}
 
 
 class RtuckerError(RuntimeError):
@@ -74,6 +75,8 @@ _SIGS = {
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "rtucker_convert": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int64,
                                        ctypes.c_int32, ctypes.c_void_p]),
+    "rtucker_srht_factor": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p]),
     "rtucker_multi_ttm_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
                                                    ctypes.c_void_p]),
     "rtucker_multi_ttm": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
@@ -294,7 +297,7 @@ def rtucker_core(X, Us, modes=None):
 def _s_array(s, algo, d):
     if s is None:
         return None
-    if ALGOS[algo] == RT_RSTHKRON:
+    if ALGOS[algo] != RT_RHKRON:
         flat = [int(v) for row in s for v in row]
     else:
         flat = [int(v) for v in s]
@@ -325,7 +328,7 @@ def _decompose_args(X, r, p, phis, algo, s, X_sketch, G, Us, ws):
         ws, wb = _workspace(nb, X.device)
     else:
         wb = int(ws.numel())
-    if ALGOS[algo] == RT_RSTHKRON:
+    if ALGOS[algo] != RT_RHKRON:
         flat = [phis[j][k] if k != j else None for j in range(d) for k in range(d)]
     else:
         flat = list(phis)
@@ -355,7 +358,7 @@ def rtucker_decompose_noalloc(X, r, p, phis, G, Us, algo="rhkron", s=None, X_ske
     d = X.dim()
     xt = _tensor(X)
     xs = _tensor(X_sketch) if X_sketch is not None else None
-    if ALGOS[algo] == RT_RSTHKRON:
+    if ALGOS[algo] != RT_RHKRON:
         flat = [phis[j][k] if k != j else None for j in range(d) for k in range(d)]
     else:
         flat = list(phis)
@@ -410,6 +413,19 @@ def rtucker_convert(src, dst_dtype, scale_exp: int = 0, out=None):
     _check(lib().rtucker_convert(_ptr(src), dtype_code(src), _ptr(out), dtype_code(out), src.numel(), int(scale_exp),
                                  _stream(src.device)), "rtucker_convert")
     return out
+
+
+def rtucker_srht_factor(n: int, rows, signs):
+    """SRHT factor (R H D)[:, :n] (s x n float64 on the device of ``rows``) from sampled rows
+    (int64 device tensor, s distinct values below the padded size) and n signs (float64)."""
+    torch = _torch()
+    if rows.dtype != torch.int64 or signs.dtype != torch.float64 or signs.numel() != int(n):
+        raise RtuckerError("rtucker_srht_factor: rows int64, signs float64 of length n")
+    rows, signs = rows.contiguous(), signs.contiguous()
+    phi = torch.empty((rows.numel(), int(n)), dtype=torch.float64, device=rows.device)
+    _check(lib().rtucker_srht_factor(int(n), rows.numel(), _ptr(rows), _ptr(signs), _ptr(phi), _stream(rows.device)),
+           "rtucker_srht_factor")
+    return phi
 
 
 def rtucker_multi_ttm(X, As, modes=None, transpose: bool = False):

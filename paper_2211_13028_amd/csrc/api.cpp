@@ -534,7 +534,7 @@ int sizes_impl(int d, const int64_t* dims, const int32_t* r, int32_t p, rt_algo 
       if (s[i] > dims[i]) return RT_ESHAPE;
     return RT_OK;
   }
-  if (algo != RT_RSTHKRON) return RT_EINVAL;
+  if (algo != RT_RSTHKRON && algo != RT_RHKRON_NOREUSE) return RT_EINVAL;
   if (d == 2) {
     for (int j = 0; j < 2; ++j) {
       s[j * 2 + j] = 1;
@@ -547,9 +547,11 @@ int sizes_impl(int d, const int64_t* dims, const int32_t* r, int32_t p, rt_algo 
       for (int k = 0; k < d; ++k) s[j * d + k] = (k == j) ? 1 : f[t++];
     }
   }
-  // sizes the factors act on: truncated c_k for k < j, I_k for k > j
+  // sizes the factors act on: for rSTHKron the truncated c_k for k < j and I_k for k > j;
+  // without reuse every factor acts on the untruncated X (I_k)
   std::vector<int64_t> cdim(d);
-  for (int k = 0; k < d; ++k) cdim[k] = std::min<int64_t>(dims[k], prod_except(s + k * d, d, k));
+  for (int k = 0; k < d; ++k)
+    cdim[k] = algo == RT_RSTHKRON ? std::min<int64_t>(dims[k], prod_except(s + k * d, d, k)) : dims[k];
   for (int j = 0; j < d; ++j)
     for (int k = 0; k < d; ++k)
       if (k != j && s[j * d + k] > (k < j ? cdim[k] : dims[k])) return RT_ESHAPE;
@@ -659,7 +661,7 @@ int plan_decompose(Ctx& c, const rt_tensor* X, const rt_tensor* Xs, const int32_
   if (X->dtype == RT_F8E4M3) return RT_EDTYPE;
   const int d = X->d;
   if (!r || p < 0) return RT_EINVAL;
-  if (algo != RT_RHKRON && algo != RT_RSTHKRON) return RT_EINVAL;
+  if (algo != RT_RHKRON && algo != RT_RSTHKRON && algo != RT_RHKRON_NOREUSE) return RT_EINVAL;
   if (Xs) {
     if (algo != RT_RHKRON) return RT_EINVAL;
     st = check_tensor(Xs, c.check_ptrs);
@@ -671,11 +673,11 @@ int plan_decompose(Ctx& c, const rt_tensor* X, const rt_tensor* Xs, const int32_
   std::vector<int64_t> I(X->dims, X->dims + d);
   for (int k = 0; k < d; ++k)
     if (r[k] < 1 || r[k] > I[k]) return RT_ESHAPE;
-  const int nS = (algo == RT_RHKRON) ? d : d * d;
+  const int nS = (algo == RT_RHKRON) ? d : d * d;  // rSTHKron and no-reuse: the d x d matrix S
   std::vector<int64_t> s(nS);
   if (s_in) {
     std::copy(s_in, s_in + nS, s.begin());
-    if (algo == RT_RSTHKRON)
+    if (algo != RT_RHKRON)
       for (int j = 0; j < d; ++j) s[j * d + j] = 1;
   } else {
     st = sizes_impl(d, X->dims, r, p, algo, s.data());
@@ -694,7 +696,8 @@ int plan_decompose(Ctx& c, const rt_tensor* X, const rt_tensor* Xs, const int32_
   } else {
     for (int j = 0; j < d; ++j)
       for (int k = 0; k < d; ++k)
-        if (k != j && (s[j * d + k] < 1 || s[j * d + k] > (k < j ? cdim[k] : I[k]))) return RT_ESHAPE;
+        if (k != j && (s[j * d + k] < 1 || s[j * d + k] > ((algo == RT_RSTHKRON && k < j) ? cdim[k] : I[k])))
+          return RT_ESHAPE;
   }
   if (c.check_ptrs) {
     if (!phi || !G || !U) return RT_EINVAL;
@@ -711,7 +714,29 @@ int plan_decompose(Ctx& c, const rt_tensor* X, const rt_tensor* Xs, const int32_
   std::vector<double*> Uhat(d);
   for (int n = 0; n < d; ++n) Uhat[n] = static_cast<double*>(c.take(static_cast<size_t>(I[n]) * cdim[n] * sizeof(double)));
   Ten cur = ten_of(X);
-  if (algo == RT_RHKRON) {
+  if (algo == RT_RHKRON_NOREUSE) {
+    // App. A: every mode's sketch with its own factors, each from one read of X (the
+    // first level of a one-mode dimension tree), then one QR launch for all modes and the
+    // core and truncation of the reuse algorithm
+    std::vector<SketchOut> outs(d);
+    c.mark(kPhaseSketch);
+    for (int j = 0; j < d; ++j) {
+      std::vector<int64_t> sj(s.begin() + j * d, s.begin() + (j + 1) * d);
+      std::vector<const double*> phij(d, nullptr);
+      if (phi)
+        for (int k = 0; k < d; ++k) phij[k] = (k == j) ? nullptr : phi[j * d + k];
+      std::vector<SketchOut> o;
+      sketch_impl(c, cur, phij.data(), sj.data(), 1u << j, o);
+      outs[j] = o[j];
+    }
+    std::vector<QRJob> jobs(d);
+    for (int n = 0; n < d; ++n) jobs[n] = QRJob{outs[n].Y.p, outs[n].A, outs[n].m, outs[n].B, Uhat[n], nullptr};
+    void* w = c.take(qr_ws(jobs.data(), d));
+    c.mark(kPhaseQR);
+    if (!c.dry) c.chk(launch_qr(jobs.data(), d, ctype(cur.dt), w, c.st));
+    c.mark(kPhaseCore);
+    cur = core_impl(c, cur, Uhat.data(), cdim.data(), (1u << d) - 1u, nullptr, /*f64_out=*/true);
+  } else if (algo == RT_RHKRON) {
     const Ten Tsk = Xs ? ten_of(Xs) : cur;
     std::vector<SketchOut> outs;
     c.mark(kPhaseSketch);
@@ -1328,6 +1353,19 @@ int rtucker_convert(const void* src, rt_dtype src_dtype, void* dst, rt_dtype dst
   if (n == 0) return RT_OK;
   if (!src || !dst) return RT_EINVAL;
   return launch_convert(src, src_dtype, dst, dst_dtype, n, scale_exp, static_cast<hipStream_t>(stream)) == hipSuccess
+             ? RT_OK
+             : RT_EHIP;
+}
+
+int rtucker_srht_factor(int64_t n, int64_t s, const int64_t* rows, const double* signs, double* phi,
+                        void* stream) {
+  if (n < 1 || s < 1) return RT_ESHAPE;
+  int64_t N = 1;
+  while (N < n) N *= 2;
+  if (s > N) return RT_ESHAPE;
+  if (!rows || !signs || !phi) return RT_EINVAL;
+  return launch_srht_factor(n, s, rows, signs, 1.0 / std::sqrt(static_cast<double>(N)), phi,
+                            static_cast<hipStream_t>(stream)) == hipSuccess
              ? RT_OK
              : RT_EHIP;
 }

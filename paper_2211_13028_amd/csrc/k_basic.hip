@@ -249,6 +249,26 @@ int grid_for(int64_t n) {
 
 }  // namespace
 
+// Walsh-Hadamard entries in Sylvester order: H[i][j] = (-1)^popcount(i & j).  One thread
+// per entry of the s x n factor (a few thousand entries).
+__global__ __launch_bounds__(kThreads) void srht_factor_kernel(int64_t n, int64_t s, const int64_t* __restrict__ rows,
+                                                                const double* __restrict__ signs, double inv,
+                                                                double* __restrict__ phi) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (t >= n * s) return;
+  const int64_t i = t / n, j = t - i * n;
+  const uint64_t bits = static_cast<uint64_t>(rows[i]) & static_cast<uint64_t>(j);
+  const double h = (__popcll(bits) & 1) ? -inv : inv;
+  phi[t] = h * signs[j];
+}
+
+hipError_t launch_srht_factor(int64_t n, int64_t s, const int64_t* rows, const double* signs, double inv_sqrt_N,
+                              double* phi, hipStream_t st) {
+  srht_factor_kernel<<<static_cast<unsigned>(ceil_div(n * s, kThreads)), kThreads, 0, st>>>(n, s, rows, signs,
+                                                                                            inv_sqrt_N, phi);
+  return hipGetLastError();
+}
+
 hipError_t launch_convert(const void* src, rt_dtype sdt, void* dst, rt_dtype ddt, int64_t n, int scale_exp,
                           hipStream_t st) {
   if (n == 0) return hipSuccess;

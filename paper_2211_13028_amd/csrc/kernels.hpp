@@ -8,6 +8,10 @@ namespace rt {
 
 // ------------------------------------------------------------------ k_basic.hip
 // dst[i] = round(src[i] * 2^scale_exp) (RNE); see rtucker_convert.
+// Phi = (R H D)[:, :n] for a subsampled randomized Hadamard factor: phi[i*n + j] =
+// signs[j] * (-1)^popcount(rows[i] & j) * inv_sqrt_N
+hipError_t launch_srht_factor(int64_t n, int64_t s, const int64_t* rows, const double* signs, double inv_sqrt_N,
+                              double* phi, hipStream_t st);
 hipError_t launch_convert(const void* src, rt_dtype sdt, void* dst, rt_dtype ddt, int64_t n,
                           int scale_exp, hipStream_t st);
 

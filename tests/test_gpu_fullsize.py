@@ -65,7 +65,8 @@ def test_fullsize_core_first_contraction_samples(work):
         assert abs(C[a, j, k] - want) <= 2e-6 * (np.abs(U32[:, a]) @ np.abs(col))
 
 
-@pytest.mark.parametrize("path", ["f32", "bf16", "f8sketch", "rsthkron_f32", "rsthkron_bf16"])
+@pytest.mark.parametrize("path", ["f32", "bf16", "f8sketch", "rsthkron_f32", "rsthkron_bf16", "noreuse_f32",
+                                  "srht_f32"])
 def test_fullsize_decompose_error(work, path):
     Xh, s, phis = work["Xh"], work["s"], work["phis"]
     X = Xh.astype(np.float64)
@@ -86,6 +87,22 @@ def test_fullsize_decompose_error(work, path):
     elif path == "f32":
         G, Us = rt.rtucker_decompose(work["X32"], R, P, work["phis_d"], s=s)
         Go, Uo = T.rhkron(X, R, phis)
+    elif path == "noreuse_f32":
+        S = rt.rtucker_sketch_sizes(DIMS, R, P, "rhkron_noreuse")
+        shapes = T.noreuse_phi_shapes(DIMS, S)
+        flat = synth.gaussians(synth.PHI_SEED, [sh for row in shapes for sh in row])
+        nph = [flat[j * 3:(j + 1) * 3] for j in range(3)]
+        G, Us = rt.rtucker_decompose(work["X32"], R, P, [[None if f is None else dev(f) for f in row] for row in nph],
+                                     algo="rhkron_noreuse", s=S)
+        Go, Uo = T.rhkron_noreuse(X, R, nph)
+    elif path == "srht_f32":
+        from oracle import srht as H
+        draws = synth.srht_draws(synth.PHI_SEED, [(s[k], H.padded_size(DIMS[k]), DIMS[k]) for k in range(3)])
+        sph = [H.srht_factor(DIMS[k], *draws[k]) for k in range(3)]
+        sph_d = [rt.rtucker_srht_factor(DIMS[k], torch.as_tensor(draws[k][0], device=DEV), dev(draws[k][1]))
+                 for k in range(3)]
+        G, Us = rt.rtucker_decompose(work["X32"], R, P, sph_d, s=s)
+        Go, Uo = T.rhkron(X, R, sph)
     elif path == "bf16":
         X16 = rt.rtucker_convert(work["X32"], torch.bfloat16)
         G, Us = rt.rtucker_decompose(X16, R, P, work["phis_d"], s=s)
