@@ -288,6 +288,16 @@ def main():
         fl = sk_flops
         kernels[f"sketch_{tag}"] = {"ms": ms, "GB/s": byts / ms / 1e6, "TFLOP/s": fl / ms / 1e9,
                                     "alg_bytes": byts, "alg_flops": fl}
+        if tag == "f32":
+            # the SRHT sketch of the last mode by a fast Walsh-Hadamard transform, beside the
+            # dense-factor pass above (which also makes W): same read of X, s outputs per fiber
+            pad = 1 << (DIMS[2] - 1).bit_length()
+            (rows, signs), = synth.srht_draws(synth.PHI_SEED, [(s[2], pad, DIMS[2])])
+            rows_d, signs_d = torch.from_numpy(rows).to(dev), torch.from_numpy(signs).to(dev)
+            Zs = rt.rtucker_srht_sketch_last(X, rows_d, signs_d, Z=Zb)
+            ms = kernel_time(lambda: rt.rtucker_srht_sketch_last(X, rows_d, signs_d, Z=Zs))
+            byts = N * esz + Zb.numel() * 4
+            kernels["srht_fwht_last_f32"] = {"ms": ms, "GB/s": byts / ms / 1e6, "alg_bytes": byts}
         del Zb, Wb
 
     # dominant kernel of the headline (FP32) step: the first core contraction, a dense contraction

@@ -263,6 +263,17 @@ int rtucker_convert(const void* src, rt_dtype src_dtype, void* dst, rt_dtype dst
 int rtucker_srht_factor(int64_t n, int64_t s, const int64_t* rows, const double* signs, double* phi,
                         void* stream);
 
+/* The SRHT sketch of the contiguous last mode by a fast Walsh-Hadamard transform:
+ *   Z = X x_d Phi  with Phi = (R H D)[:, :Q] as in rtucker_srht_factor (Q = I_d),
+ * in O(log N) operations per entry of X instead of s.  Each fiber of Q values is signed,
+ * zero-padded to N, transformed, scaled by 1/sqrt(N) and sampled at `rows`.
+ *  X: F32, 1 <= d <= 8, any sizes, Q <= 4096 (N <= 4096); Z: device binary32, X's dims
+ *  with the last replaced by s, C order.  1 <= s <= min(64, N).  rows: device int64,
+ *  s distinct values in [0, N) (reduced modulo N, not checked); signs: device binary64,
+ *  Q values +-1.  Arithmetic in binary32. */
+int rtucker_srht_sketch_last(const rt_tensor* X, int64_t s, const int64_t* rows, const double* signs,
+                             float* Z, void* stream);
+
 /* ------------------------------------------------------------------ adjoint
  * Plain multi-TTM and its adjoint pieces, for differentiation (Sec. 2.1
  * multi-TTM; the adjoint of Y = X x_k A_k is dX = dY x_k A_k^T and

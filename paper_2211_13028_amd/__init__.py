@@ -77,6 +77,8 @@ _SIGS = {
                                        ctypes.c_int32, ctypes.c_void_p]),
     "rtucker_srht_factor": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_void_p]),
+    "rtucker_srht_sketch_last": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                                ctypes.c_void_p, ctypes.c_void_p]),
     "rtucker_multi_ttm_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
                                                    ctypes.c_void_p]),
     "rtucker_multi_ttm": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
@@ -426,6 +428,23 @@ def rtucker_srht_factor(n: int, rows, signs):
     _check(lib().rtucker_srht_factor(int(n), rows.numel(), _ptr(rows), _ptr(signs), _ptr(phi), _stream(rows.device)),
            "rtucker_srht_factor")
     return phi
+
+
+def rtucker_srht_sketch_last(X, rows, signs, Z=None):
+    """Z = X x_last (R H D)[:, :Q] by a fast Walsh-Hadamard transform (float32 X)."""
+    torch = _torch()
+    xt = _tensor(X)
+    if rows.dtype != torch.int64 or signs.dtype != torch.float64 or signs.numel() != X.shape[-1]:
+        raise RtuckerError("rtucker_srht_sketch_last: rows int64, signs float64 of the last mode's length")
+    rows, signs = rows.contiguous(), signs.contiguous()
+    shape = tuple(X.shape[:-1]) + (rows.numel(),)
+    if Z is None:
+        Z = torch.empty(shape, dtype=torch.float32, device=X.device)
+    elif tuple(Z.shape) != shape or Z.dtype != torch.float32 or not Z.is_contiguous():
+        raise RtuckerError("rtucker_srht_sketch_last: Z has the wrong shape, dtype or layout")
+    _check(lib().rtucker_srht_sketch_last(ctypes.byref(xt), rows.numel(), _ptr(rows), _ptr(signs), _ptr(Z),
+                                          _stream(X.device)), "rtucker_srht_sketch_last")
+    return Z
 
 
 def rtucker_multi_ttm(X, As, modes=None, transpose: bool = False):

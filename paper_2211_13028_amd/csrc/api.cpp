@@ -1370,6 +1370,22 @@ int rtucker_srht_factor(int64_t n, int64_t s, const int64_t* rows, const double*
              : RT_EHIP;
 }
 
+int rtucker_srht_sketch_last(const rt_tensor* X, int64_t s, const int64_t* rows, const double* signs, float* Z,
+                             void* stream) {
+  int64_t n = 0;
+  const int st = check_flat(X, &n);
+  if (st) return st;
+  if (X->dtype != RT_F32) return RT_EDTYPE;
+  const int64_t Q = X->dims[X->d - 1];
+  if (!srht_last_ok(Q, s)) return RT_ESHAPE;
+  if (n == 0) return RT_OK;
+  if (!rows || !signs || !Z) return RT_EINVAL;
+  return launch_srht_last(static_cast<const float*>(X->data), n / Q, Q, rows, signs, s, Z,
+                          static_cast<hipStream_t>(stream)) == hipSuccess
+             ? RT_OK
+             : RT_EHIP;
+}
+
 int rtucker_multi_ttm_workspace(const rt_tensor* X, const int64_t* m, uint32_t mode_mask, size_t* bytes) {
   return query([&](Ctx& c) { return plan_multi_ttm(c, X, nullptr, m, mode_mask, 1, nullptr); }, bytes);
 }

@@ -198,10 +198,14 @@ constexpr bool kPrefetchF32 = true;  // binary32 kernel: next k block loaded dur
 // Work unit = (a, 128-column chunk, k-split part).  Y (or a split-K partial) is
 // written for rows i < m only.
 // One work unit (a wave) of the binary32 contraction; unit < A * chunks * ksplit.
-template <int MT, bool VM>
+// TAIL > 0 (with VM): rows 16 MT .. 16 MT + TAIL - 1 of M are not a whole 16-row matrix-core
+// tile, and are multiplied on the vector ALU from the X values the lane already holds
+// (m = 49 = 3 x 16 + 1 would otherwise pad a fourth tile: 31 % more matrix-core work).
+template <int MT, bool VM, int TAIL = 0>
 __device__ __forceinline__ void ttm_f32_unit(const float* __restrict__ X, int64_t A, int64_t K, int64_t B,
                                              const float* __restrict__ Mop, int64_t m, int64_t chunks, int ksplit,
                                              int64_t kper, float* __restrict__ Y, int64_t unit) {
+  static_assert(TAIL == 0 || VM, "vector-ALU tail rows need K % 4 == 0");
   const int lane = threadIdx.x % kWave;
   const int ks = static_cast<int>(unit % ksplit);
   const int64_t ac = unit / ksplit;
@@ -233,6 +237,10 @@ __device__ __forceinline__ void ttm_f32_unit(const float* __restrict__ X, int64_
   const f32x4 zero4 = f32x4{0.f, 0.f, 0.f, 0.f};
   f32x4 n0[4], n1[4];
   float nw[MT][4];
+  f32x4 ntw[TAIL > 0 ? TAIL : 1];
+  f32x4 tacc[TAIL > 0 ? TAIL : 1][2];
+#pragma unroll
+  for (int r = 0; r < TAIL; ++r) tacc[r][0] = tacc[r][1] = f32x4{0.f, 0.f, 0.f, 0.f};
   const auto load_block = [&](int64_t k0) {
     const int64_t kl = k0 + 4 * q;
 #pragma unroll
@@ -251,6 +259,8 @@ __device__ __forceinline__ void ttm_f32_unit(const float* __restrict__ X, int64_
 #pragma unroll
         for (int s = 0; s < 4; ++s) nw[mt][s] = v[s];
       }
+#pragma unroll
+      for (int r = 0; r < TAIL; ++r) ntw[r] = *reinterpret_cast<const f32x4*>(Mop + (MT * 16 + r) * K + km);
     } else {
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
@@ -262,6 +272,7 @@ __device__ __forceinline__ void ttm_f32_unit(const float* __restrict__ X, int64_
   for (int64_t k0 = kbeg; k0 < kend; k0 += 16) {
     f32x4 y0[4], y1[4];
     float w[4][MT];
+    f32x4 tw[TAIL > 0 ? TAIL : 1];
     const int64_t kl = k0 + 4 * q;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -271,6 +282,8 @@ __device__ __forceinline__ void ttm_f32_unit(const float* __restrict__ X, int64_
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) w[s][mt] = kin ? nw[mt][s] : 0.f;
     }
+#pragma unroll
+    for (int r = 0; r < TAIL; ++r) tw[r] = ntw[r];
     // the next block's loads go out before this block's products (the scheduler may
     // move neither the operand take-over below them nor them into the products)
     __builtin_amdgcn_sched_barrier(0);
@@ -287,9 +300,37 @@ __device__ __forceinline__ void ttm_f32_unit(const float* __restrict__ X, int64_
         }
       }
     }
+    // tail rows: the lane's four k of the block against its eight columns (y past kend
+    // are zero, and the clamped loads of the tail rows are finite)
+#pragma unroll
+    for (int r = 0; r < TAIL; ++r)
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          tacc[r][0][c] = fmaf(tw[r][s], y0[s][c], tacc[r][0][c]);
+          tacc[r][1][c] = fmaf(tw[r][s], y1[s][c], tacc[r][1][c]);
+        }
     if (!kPrefetchF32 && k0 + 16 < kend) load_block(k0 + 16);
   }
   float* ya = Y + (static_cast<int64_t>(ks) * A + a) * m * B;
+  // tail rows: the four lane groups q hold the partial sums of k = 4 q + s of every block;
+  // add them in a fixed order (lane j collects groups 0..3) and store from group 0
+#pragma unroll
+  for (int r = 0; r < TAIL; ++r) {
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      f32x4 v = tacc[r][g];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const float p1 = __shfl(v[c], j + 16), p2 = __shfl(v[c], j + 32), p3 = __shfl(v[c], j + 48);
+        v[c] = ((v[c] + p1) + p2) + p3;
+      }
+      const int64_t i = MT * 16 + r;
+      const int64_t c0 = b0 + 64 * g + 4 * j;
+      if (q == 0 && i < m && c0 < B) *reinterpret_cast<f32x4*>(ya + i * B + c0) = v;
+    }
+  }
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
 #pragma unroll
@@ -308,14 +349,14 @@ __device__ __forceinline__ void ttm_f32_unit(const float* __restrict__ X, int64_
   }
 }
 
-template <int MT, bool VM>
+template <int MT, bool VM, int TAIL = 0>
 __global__ __launch_bounds__(kMfmaThreads) void ttm_mfma_f32_kernel(const float* __restrict__ X, int64_t A, int64_t K,
                                                                     int64_t B, const float* __restrict__ Mop,
                                                                     int64_t m, int64_t chunks, int ksplit,
                                                                     int64_t kper, float* __restrict__ Y) {
   const int64_t unit = static_cast<int64_t>(blockIdx.x) * (kMfmaThreads / kWave) + threadIdx.x / kWave;
   if (unit >= A * chunks * ksplit) return;
-  ttm_f32_unit<MT, VM>(X, A, K, B, Mop, m, chunks, ksplit, kper, Y, unit);
+  ttm_f32_unit<MT, VM, TAIL>(X, A, K, B, Mop, m, chunks, ksplit, kper, Y, unit);
 }
 
 // Independent binary32 contractions of one shape class in one launch: job q owns the
@@ -641,7 +682,19 @@ hipError_t launch_ttm_mfma_ws(const void* X, rt_dtype xdt, int64_t A, int64_t K,
   ttm_mfma_bf16_kernel<MTV><<<grid, kMfmaThreads, 0, st>>>(static_cast<const bf16_t*>(X), A, K, B,          \
                                                            static_cast<const bf16_t*>(Mop), m, p.chunks,    \
                                                            p.ksplit, p.kper, out)
-  if (xdt == RT_F32) {
+  // rows past the last whole 16-row tile on the vector ALU when there are at most two
+  const int tail = (K % 4 == 0 && m % 16 != 0 && m % 16 <= 2 && m > 16) ? static_cast<int>(m % 16) : 0;
+  const int MTfull = static_cast<int>(m / 16);
+#define RT_LAUNCH_F32_TAIL(MTV, TV)                                                                            ttm_mfma_f32_kernel<MTV, true, TV><<<grid, kMfmaThreads, 0, st>>>(static_cast<const float*>(X), A, K, B,                                                                       static_cast<const float*>(Mop), m,                                                                           p.chunks, p.ksplit, p.kper, out)
+  if (xdt == RT_F32 && tail > 0) {
+    if (MTfull == 1) {
+      if (tail == 1) RT_LAUNCH_F32_TAIL(1, 1); else RT_LAUNCH_F32_TAIL(1, 2);
+    } else if (MTfull == 2) {
+      if (tail == 1) RT_LAUNCH_F32_TAIL(2, 1); else RT_LAUNCH_F32_TAIL(2, 2);
+    } else {
+      if (tail == 1) RT_LAUNCH_F32_TAIL(3, 1); else RT_LAUNCH_F32_TAIL(3, 2);
+    }
+  } else if (xdt == RT_F32) {
     switch (MT) {
       case 1: RT_LAUNCH_F32(1); break;
       case 2: RT_LAUNCH_F32(2); break;
@@ -657,6 +710,7 @@ hipError_t launch_ttm_mfma_ws(const void* X, rt_dtype xdt, int64_t A, int64_t K,
     }
   }
 #undef RT_LAUNCH_F32
+#undef RT_LAUNCH_F32_TAIL
 #undef RT_LAUNCH_BF16
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || p.ksplit == 1) return e;

@@ -12,6 +12,10 @@ namespace rt {
 // signs[j] * (-1)^popcount(rows[i] & j) * inv_sqrt_N
 hipError_t launch_srht_factor(int64_t n, int64_t s, const int64_t* rows, const double* signs, double inv_sqrt_N,
                               double* phi, hipStream_t st);
+// Z = X x_last (R H D)[:, :Q] by a fast Walsh-Hadamard transform per fiber (Q <= 4096)
+bool srht_last_ok(int64_t Q, int64_t s);
+hipError_t launch_srht_last(const float* X, int64_t fibers, int64_t Q, const int64_t* rows, const double* signs,
+                            int64_t s, float* Z, hipStream_t st);
 hipError_t launch_convert(const void* src, rt_dtype sdt, void* dst, rt_dtype ddt, int64_t n,
                           int scale_exp, hipStream_t st);
 

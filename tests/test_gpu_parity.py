@@ -226,6 +226,23 @@ def test_core_single_modes():
         assert_entrywise(G, want, bound, 2e-5, f"core mode {k}")
 
 
+@pytest.mark.parametrize("m", [17, 18, 33, 34, 49, 50, 48, 19])
+@pytest.mark.parametrize("K", [1024, 92, 90])
+def test_core_first_contraction_tail_rows(m, K):
+    """Factor widths one or two rows past a whole 16-row tile take the vector-ALU tail in
+    the binary32 matrix-core contraction (K % 4 == 0), the others the padded tiles."""
+    say("core tail rows", m, K)
+    rng = np.random.default_rng(402 + m + K)
+    dims = (K, 24, 40)
+    X = L.round_f32(rng.standard_normal(dims))
+    U = np.linalg.qr(rng.standard_normal((K, m)))[0]
+    G = host(rt.rtucker_core(dev(X, torch.float32), [dev(U), None, None], modes=[0]))
+    Ur = L.round_f32(U)
+    want = T.ttm(X, Ur.T, 0)
+    bound = T.ttm(np.abs(X), np.abs(Ur).T, 0)
+    assert_entrywise(G, want, bound, 2e-5, f"core m={m} K={K}")
+
+
 # ------------------------------------------------------------------ decomposition
 def _decompose_and_compare(X, Xd, r, p, algo, phis, s, tol_e, Xsk=None, emulate=None):
     phis_d = [dev(f) for f in phis] if algo == "rhkron" else [[dev(f) if f is not None else None for f in row]

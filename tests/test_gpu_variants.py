@@ -109,3 +109,26 @@ def test_noreuse_recovers_where_reuse_is_capped():
     assert e_reuse > 1e-3 and e_nr < 1e-12
     for U, A in zip(Us, F):
         assert subspace_gap(host(U), A) < 1e-10
+
+
+@pytest.mark.parametrize("shape,s", [((37, 150, 530), 7), ((5, 64), 4), ((3, 10), 5), ((2, 4096), 64), ((7, 3, 1), 1),
+                                     ((64, 33, 512), 7), ((9, 2000), 20)])
+def test_srht_fast_transform_sketch(shape, s):
+    """The fast-transform SRHT sketch of the last mode against the oracle's dense factor,
+    entry by entry (binary32 adds over log2 N stages)."""
+    say("srht fast transform", shape, s)
+    Q = shape[-1]
+    (rows, signs), = synth.srht_draws(70 + Q + s, [(s, H.padded_size(Q), Q)])
+    X = np.random.default_rng(71).standard_normal(shape).astype(np.float32).astype(np.float64)
+    Z = rt.rtucker_srht_sketch_last(dev(X, torch.float32), torch.as_tensor(rows, device="cuda:0"), dev(signs))
+    Phi = H.srht_factor(Q, rows, signs)
+    want = T.ttm(X, Phi, len(shape) - 1)
+    bound = T.ttm(np.abs(X), np.abs(Phi), len(shape) - 1)
+    from gpu_common import assert_entrywise
+    assert_entrywise(host(Z), want, bound, 2e-6 * max(1, int(np.log2(H.padded_size(Q)))), "SRHT sketch")
+
+
+def test_srht_fast_transform_rejects_long_modes():
+    X = torch.zeros((2, 5000), dtype=torch.float32, device="cuda:0")
+    with pytest.raises(rt.RtuckerError):
+        rt.rtucker_srht_sketch_last(X, torch.zeros(3, dtype=torch.int64, device="cuda:0"), dev(np.ones(5000)))
