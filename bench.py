@@ -252,6 +252,21 @@ def main():
                 e, _ = rt.rtucker_rel_error(X32, G, U)
                 results["rsthkron_bf16_cast_counted"] = {"ms": ms, "rel_err": e}
 
+    if not args.no_variants:
+        # the deterministic STHOSVD (Alg. 2.2) on the device: the baseline of the paper's
+        # "randomized vs STHOSVD" comparisons
+        Gd = torch.empty(RANKS, dtype=torch.float64, device=dev)
+        Ud = [torch.empty((DIMS[j], RANKS[j]), dtype=torch.float64, device=dev) for j in range(3)]
+        nbs = rt.rtucker_sthosvd_workspace(X32, RANKS)
+        wss = torch.empty(max(nbs, 256), dtype=torch.uint8, device=dev)
+        its = []
+        log("timing the deterministic STHOSVD ...")
+        ms = time_steps(lambda: its.append(rt.rtucker_sthosvd(X32, RANKS, G=Gd, Us=Ud, ws=wss)[2]), 3, 1)
+        e, _ = rt.rtucker_rel_error(X32, Gd, Ud)
+        results["sthosvd_f32"] = {"ms": ms, "rel_err": e, "subspace_iterations": its[-1],
+                                  "ratio_to_rhkron_f32": round(ms / ms32, 2)}
+        del wss
+
     # ---------------------------------------------------------------- per-kernel rooflines
     N = int(np.prod(DIMS))
     kernels = {}
@@ -461,6 +476,20 @@ def run_paper_scale(rt, synth, torch, dev, time_steps, log, keep=()):
             out[f"{algo}_410^4_f32"] = {"ms": round(ms, 3), "rel_err": e, "max_subspace_gap": gap,
                                         "phases_ms": {k: round(v, 3) for k, v in phases.items()},
                                         "read_GB/s": round(nbytes / ms / 1e6, 1)}
+        G = torch.empty(r, dtype=torch.float64, device=dev)
+        Us = [torch.empty((410, 20), dtype=torch.float64, device=dev) for _ in range(4)]
+        nb = rt.rtucker_sthosvd_workspace(X, r)
+        ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
+        log("timing 410^4 deterministic STHOSVD ...")
+        ms = time_steps(lambda: rt.rtucker_sthosvd(X, r, G=G, Us=Us, ws=ws), 2, 1)
+        del ws
+        torch.cuda.empty_cache()
+        e, _ = rt.rtucker_rel_error(X, G, Us)
+        out["sthosvd_410^4_f32"] = {"ms": round(ms, 3), "rel_err": e}
+        for algo in ("rhkron", "rsthkron"):
+            key = f"{algo}_410^4_f32"
+            if key in out and "ms" in out[key]:
+                out[key]["speedup_over_sthosvd"] = round(ms / out[key]["ms"], 2)
         del X
         torch.cuda.empty_cache()
     else:

@@ -50,7 +50,9 @@ typedef enum {
                       /* (-5 is not used: rtucker_rel_error counts non-finite input
                           entries in its device output instead, since it does not
                           synchronise) */
-  RT_EHIP = -6        /* a HIP runtime call failed */
+  RT_EHIP = -6,       /* a HIP runtime call failed */
+  RT_ENOTCONVERGED = -7 /* an iterative eigensolver stopped at its iteration limit
+                           (rtucker_sthosvd; the outputs hold its last iterate) */
 } rt_status;
 
 typedef enum {
@@ -226,6 +228,26 @@ int rtucker_decompose_phases(const rt_tensor* X, const rt_tensor* X_sketch, cons
 int rtucker_decompose_noalloc(const rt_tensor* X, const rt_tensor* X_sketch, const int32_t* r,
                               int32_t p, const int64_t* s, rt_algo algo, const double* const* phi,
                               double* G, double* const* U, void* stream);
+
+/* ------------------------------------------------------------------ deterministic STHOSVD
+ * The deterministic sequentially truncated HOSVD (Alg. 2.2) of X at ranks r, the baseline
+ * the randomized algorithms are compared with (Sec. 7.4-7.5): for j = 1..d, V_j = the r_j
+ * leading eigenvectors of the Gram matrix of the current tensor's mode-j unfolding
+ * (products of the binary32 or binary64 entries accumulated in binary64: a binary32 Gram
+ * matrix would lose the trailing eigenvalues, whose sum is the squared error), then the
+ * tensor is contracted with V_j^T in mode j.  G = the final tensor, U_j = V_j.
+ * Eigenvectors: the one-workgroup solver of the truncation for I_j <= 64; for larger
+ * modes subspace iteration on 64 vectors with Rayleigh-Ritz every 4 iterations until
+ * max_i ||M v_i - theta_i v_i|| <= 1e-12 theta_1 (at most 400 iterations; the host reads
+ * one value per check).  Columns in decreasing eigenvalue order, each column's
+ * largest-magnitude entry positive.
+ *  X: F64 or F32.  r[j] <= I_j, and r[j] <= 32 when I_j > 64 (<= 64 otherwise).
+ *  G: device binary64 r_1 x ... x r_d.  U[j]: device binary64 I_j x r_j.
+ *  iterations (host, nullable): subspace iterations summed over the modes.
+ *  Synchronises `stream`.  RT_ENOTCONVERGED when a mode hit the iteration limit. */
+int rtucker_sthosvd_workspace(const rt_tensor* X, const int32_t* r, size_t* bytes);
+int rtucker_sthosvd(const rt_tensor* X, const int32_t* r, double* G, double* const* U,
+                    int32_t* iterations, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------ error
  * Squared norms for the relative reconstruction error (Sec. 5), in binary64 on

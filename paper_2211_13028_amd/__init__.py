@@ -70,6 +70,9 @@ _SIGS = {
     "rtucker_decompose_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                                  ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                                  ctypes.c_void_p, ctypes.c_void_p]),
+    "rtucker_sthosvd_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "rtucker_sthosvd": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "rtucker_rel_error_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "rtucker_rel_error": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
@@ -368,6 +371,35 @@ def rtucker_decompose_noalloc(X, r, p, phis, G, Us, algo="rhkron", s=None, X_ske
                                            int(p), _s_array(s, algo, d), ALGOS[algo], _ptrs(flat), _ptr(G), _ptrs(Us),
                                            _stream(X.device)), "rtucker_decompose_noalloc")
     return G, Us
+
+
+def rtucker_sthosvd_workspace(X, r) -> int:
+    nb = ctypes.c_size_t()
+    xt = _tensor(X)
+    _check(lib().rtucker_sthosvd_workspace(ctypes.byref(xt), _i32(r), ctypes.byref(nb)), "rtucker_sthosvd_workspace")
+    return int(nb.value)
+
+
+def rtucker_sthosvd(X, r, G=None, Us=None, ws=None):
+    """Deterministic STHOSVD (Alg. 2.2) on the device; returns (G, [U_j], subspace iterations).
+    Synchronises."""
+    torch = _torch()
+    d = X.dim()
+    xt = _tensor(X)
+    nb = ctypes.c_size_t()
+    _check(lib().rtucker_sthosvd_workspace(ctypes.byref(xt), _i32(r), ctypes.byref(nb)), "rtucker_sthosvd_workspace")
+    if G is None:
+        G = torch.empty([int(v) for v in r], dtype=torch.float64, device=X.device)
+    if Us is None:
+        Us = [torch.empty((X.shape[j], int(r[j])), dtype=torch.float64, device=X.device) for j in range(d)]
+    if ws is None:
+        ws, wb = _workspace(nb.value, X.device)
+    else:
+        wb = int(ws.numel())
+    it = ctypes.c_int32(0)
+    _check(lib().rtucker_sthosvd(ctypes.byref(xt), _i32(r), _ptr(G), _ptrs(Us), ctypes.byref(it), _ptr(ws), wb,
+                                 _stream(X.device)), "rtucker_sthosvd")
+    return G, Us, int(it.value)
 
 
 PHASES = ("sketch", "qr", "core", "truncate")

@@ -772,6 +772,111 @@ int plan_decompose(Ctx& c, const rt_tensor* X, const rt_tensor* Xs, const int32_
   return RT_OK;
 }
 
+// ------------------------------------------------------------------ deterministic STHOSVD
+// Alg. 2.2 on the device: for j = 1..d, the r_j leading eigenvectors V_j of the Gram matrix
+// M_j of the current tensor's mode-j unfolding, then the contraction with V_j^T.  Gram
+// matrices up to 64 x 64 go to the one-workgroup eigensolver; larger ones to subspace
+// iteration on a block of 64 vectors, with a Rayleigh-Ritz step and a residual check every
+// few iterations (the host reads one number per check), until
+// max_i ||M v_i - theta_i v_i|| <= 1e-12 theta_1.
+constexpr int kSubBlock = 64;
+constexpr int kSubMaxIter = 400;
+constexpr int kSubCheck = 4;
+constexpr double kSubTol = 1e-12;
+
+int subspace_top(Ctx& c, const double* M, int64_t n, int64_t r, double* V, int32_t* iters) {
+  const int b = kSubBlock;
+  double* Q = static_cast<double*>(c.take(static_cast<size_t>(n) * b * sizeof(double)));
+  double* Z = static_cast<double*>(c.take(static_cast<size_t>(n) * b * sizeof(double)));
+  double* H = static_cast<double*>(c.take(static_cast<size_t>(b) * b * sizeof(double)));
+  double* Yv = static_cast<double*>(c.take(static_cast<size_t>(b) * r * sizeof(double)));
+  double* theta = static_cast<double*>(c.take(static_cast<size_t>(r) * sizeof(double)));
+  double* MV = static_cast<double*>(c.take(static_cast<size_t>(n) * r * sizeof(double)));
+  double* res = static_cast<double*>(c.take(sizeof(double)));
+  void* wz = c.take(ttm_generic_ws(RT_F64, 1, n, b, n));
+  void* wv = c.take(ttm_generic_ws(RT_F64, 1, n, r, n));
+  void* wh = c.take(mode_contract_ws(RT_F64, n, b, b, 1));
+  QRJob job{Z, 1, n, b, Q, nullptr};
+  void* wq = c.take(qr_ws(&job, 1));
+  c.flush();
+  if (c.dry) return RT_OK;
+  c.chk(launch_subspace_start(Z, n, b, c.st));
+  c.chk(launch_qr(&job, 1, RT_F64, wq, c.st));
+  const SmallGemmJob ritz{Q, Yv, V, n, b, static_cast<int32_t>(r)};
+  int it = 0;
+  bool done = false;
+  while (!done && c.err == hipSuccess) {
+    c.chk(launch_ttm_generic(Q, RT_F64, 1, n, b, M, n, Z, wz, c.st));  // Z = M Q
+    ++it;
+    if (it % kSubCheck == 0 || it >= kSubMaxIter) {
+      // Rayleigh-Ritz on span(Q): H = Q^T M Q, its r leading eigenpairs, V = Q Y
+      c.chk(launch_mode_contract(Q, Z, RT_F64, n, b, b, 1, H, wh, c.st));
+      c.chk(launch_sym_eig_top(H, b, r, Yv, theta, c.st));
+      c.chk(launch_small_gemm_f64(&ritz, 1, c.st));
+      c.chk(launch_ttm_generic(V, RT_F64, 1, n, r, M, n, MV, wv, c.st));
+      c.chk(launch_ritz_residual(MV, V, theta, n, static_cast<int>(r), res, c.st));
+      double h = 1.0;
+      c.chk(hipMemcpyAsync(&h, res, sizeof(double), hipMemcpyDeviceToHost, c.st));
+      c.chk(hipStreamSynchronize(c.st));
+      if (h <= kSubTol) done = true;
+      else if (it >= kSubMaxIter) break;
+    }
+    if (!done) c.chk(launch_qr(&job, 1, RT_F64, wq, c.st));  // Q = orth(M Q)
+  }
+  c.chk(launch_column_sign(V, n, static_cast<int>(r), c.st));
+  if (iters) *iters += it;
+  return done ? RT_OK : RT_ENOTCONVERGED;
+}
+
+int plan_sthosvd(Ctx& c, const rt_tensor* X, const int32_t* r, double* G, double* const* U, int32_t* iters) {
+  int st = check_tensor(X, c.check_ptrs);
+  if (st) return st;
+  if (X->dtype != RT_F64 && X->dtype != RT_F32) return RT_EDTYPE;
+  if (!r) return RT_EINVAL;
+  const int d = X->d;
+  for (int j = 0; j < d; ++j)
+    if (r[j] < 1 || r[j] > X->dims[j] || r[j] > (X->dims[j] <= 64 ? 64 : 32)) return RT_ESHAPE;
+  if (c.check_ptrs) {
+    if (!G || !U) return RT_EINVAL;
+    for (int j = 0; j < d; ++j)
+      if (!U[j]) return RT_EINVAL;
+  }
+  if (iters) *iters = 0;
+  Ten cur = ten_of(X);
+  int status = RT_OK;
+  for (int j = 0; j < d; ++j) {
+    const int64_t n = cur.dims[j], A = cur.before(j), B = cur.after(j), rj = r[j];
+    double* M = static_cast<double*>(c.take(static_cast<size_t>(n) * n * sizeof(double)));
+    void* mcws = c.take(cur.dt == RT_F64 ? mode_contract_ws(RT_F64, A, n, n, B) : gram_wide_ws(A, n, B));
+    c.flush();
+    if (!c.dry) {
+      if (cur.dt == RT_F64)
+        c.chk(launch_mode_contract(cur.p, cur.p, RT_F64, A, n, n, B, M, mcws, c.st));
+      else  // binary32 tensor: products accumulated in binary64
+        c.chk(launch_gram_wide(static_cast<const float*>(cur.p), A, n, B, M, mcws, c.st));
+    }
+    double* V = U ? U[j] : nullptr;
+    if (n <= 64) {
+      if (!c.dry) c.chk(launch_sym_eig_top(M, n, rj, V, nullptr, c.st));
+    } else {
+      const int sst = subspace_top(c, M, n, rj, V, iters);
+      if (sst == RT_ENOTCONVERGED) status = sst;
+    }
+    std::vector<const double*> Us(d, nullptr);
+    std::vector<int64_t> l(d, 0);
+    Us[j] = V;
+    l[j] = rj;
+    const bool last = j == d - 1;
+    cur = core_impl(c, cur, Us.data(), l.data(), 1u << j, (last && cur.dt == RT_F64) ? G : nullptr);
+  }
+  if (cur.dt != RT_F64 && !c.dry) {
+    int64_t n = 1;
+    for (int j = 0; j < d; ++j) n *= r[j];
+    c.chk(launch_convert(cur.p, cur.dt, G, RT_F64, n, 0, c.st));
+  }
+  return status;
+}
+
 int plan_rel_error(Ctx& c, const rt_tensor* X, const double* G, const int32_t* r, const double* const* U,
                    double* out) {
   int st = check_tensor(X, c.check_ptrs);
@@ -1263,6 +1368,7 @@ const char* rtucker_status_string(int status) {
     case RT_EDTYPE: return "unsupported dtype";
     case RT_EWORKSPACE: return "workspace missing, misaligned or too small";
     case RT_EHIP: return "HIP runtime error";
+    case RT_ENOTCONVERGED: return "iterative eigensolver did not converge";
     default: return "unknown status";
   }
 }
@@ -1333,6 +1439,18 @@ int rtucker_decompose_noalloc(const rt_tensor* X, const rt_tensor* X_sketch, con
   if (st) return st;
   return run([&](Ctx& c) { return plan_decompose(c, X, X_sketch, r, p, s, algo, phi, G, U); }, ws, kScratchBytes,
              stream);
+}
+
+int rtucker_sthosvd_workspace(const rt_tensor* X, const int32_t* r, size_t* bytes) {
+  return query([&](Ctx& c) { return plan_sthosvd(c, X, r, nullptr, nullptr, nullptr); }, bytes);
+}
+
+int rtucker_sthosvd(const rt_tensor* X, const int32_t* r, double* G, double* const* U, int32_t* iterations,
+                    void* ws, size_t ws_bytes, void* stream) {
+  const int st = run([&](Ctx& c) { return plan_sthosvd(c, X, r, G, U, c.dry ? nullptr : iterations); }, ws,
+                     ws_bytes, stream);
+  if (st != RT_OK) return st;
+  return hipStreamSynchronize(static_cast<hipStream_t>(stream)) == hipSuccess ? RT_OK : RT_EHIP;
 }
 
 int rtucker_rel_error_workspace(const rt_tensor* X, const int32_t* r, size_t* bytes) {

@@ -21,8 +21,9 @@ constexpr int kMCThreads = 256;
 // one 64 x 64 output tile (rows i0.., columns j0..) summed over t in [t0, t1);
 // thread (ty, tx) accumulates rows 4 ty.., columns 4 tx..  The operands of the next
 // 16 t are loaded into registers while the current 16 are multiplied from LDS.
-template <typename T>
-__device__ __forceinline__ void mode_contract_tile(const T* __restrict__ P, const T* __restrict__ Q, int64_t A,
+// (TIn: the operands' type, widened to T on load; T: LDS staging and accumulation)
+template <typename T, typename TIn = T>
+__device__ __forceinline__ void mode_contract_tile(const TIn* __restrict__ P, const TIn* __restrict__ Q, int64_t A,
                                                    int64_t mP, int64_t mQ, int64_t B, int64_t t0, int64_t t1,
                                                    int64_t i0, int64_t j0, T (&acc)[4][4]) {
   __shared__ T sP[kMCK][kMCTile + 1];
@@ -50,8 +51,8 @@ __device__ __forceinline__ void mode_contract_tile(const T* __restrict__ P, cons
       int64_t a = ta, b = tb + dt;
       while (b >= B) { b -= B; ++a; }
       const bool in = tbase + lt + dt < t1;
-      pv[rep] = (in && i0 + ii < mP) ? P[a * mP * B + (i0 + ii) * B + b] : T(0);
-      qv[rep] = (in && j0 + ii < mQ) ? Q[a * mQ * B + (j0 + ii) * B + b] : T(0);
+      pv[rep] = (in && i0 + ii < mP) ? static_cast<T>(P[a * mP * B + (i0 + ii) * B + b]) : T(0);
+      qv[rep] = (in && j0 + ii < mQ) ? static_cast<T>(Q[a * mQ * B + (j0 + ii) * B + b]) : T(0);
     }
     tb += kMCK;
     while (tb >= B) { tb -= B; ++ta; }
@@ -101,6 +102,127 @@ __global__ __launch_bounds__(kMCThreads) void mode_contract_kernel(const T* __re
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) out[(ty * 4 + u) * kMCTile + tx * 4 + v] = acc[u][v];
+}
+
+// Gram matrix X_(n) X_(n)^T of a binary32 (A, m, B) view, accumulated in binary64 (the
+// deterministic STHOSVD: a binary32 Gram matrix would bury the trailing eigenvalues, whose
+// share of ||X||^2 is the squared error, under its rounding).  The staging of the binary32
+// matrix-core contraction below, with binary64 16x16x4 matrix-core products of the widened
+// (exact) values.  Only the tiles on or above the diagonal are computed (the others exit at
+// once); the reduction mirrors them.
+typedef double mc_f64x4 __attribute__((ext_vector_type(4)));
+typedef float mc_f32x4v __attribute__((ext_vector_type(4)));
+constexpr int kGWT = 64;                // t staged per round
+constexpr int kGWStride = kGWT + 2;     // doubles per LDS row (even: aligned double pairs)
+__global__ __launch_bounds__(256) void gram_wide_kernel(const float* __restrict__ X, int64_t A, int64_t m, int64_t B,
+                                                        int64_t chunk, int tiles1, bool vec,
+                                                        double* __restrict__ part) {
+  __shared__ double sP[kMCTile * kGWStride];
+  __shared__ double sQ[kMCTile * kGWStride];
+  const int tile = blockIdx.x;
+  const int ti = tile / tiles1, tj = tile % tiles1;
+  if (ti > tj) return;
+  const bool diag = ti == tj;  // P and Q blocks coincide: stage one
+  const int64_t i0 = static_cast<int64_t>(ti) * kMCTile, j0 = static_cast<int64_t>(tj) * kMCTile;
+  const int64_t total = A * B;
+  const int64_t t0 = static_cast<int64_t>(blockIdx.y) * chunk;
+  const int64_t t1 = (t0 + chunk < total) ? t0 + chunk : total;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int r16 = lane % 16, q = lane / 16;
+  const int64_t nP = (m - i0 < kMCTile) ? m - i0 : kMCTile;
+  const int64_t nQ = (m - j0 < kMCTile) ? m - j0 : kMCTile;
+  const int njt = static_cast<int>((nQ + 15) / 16);
+  const bool wave_rows = 16 * wave < nP;
+  const double* sQr = diag ? sP : sQ;
+  mc_f64x4 acc[4];
+#pragma unroll
+  for (int js = 0; js < 4; ++js) acc[js] = mc_f64x4{0.0, 0.0, 0.0, 0.0};
+  // vec (B % 64 == 0, X 16-byte aligned; the plan's chunks are multiples of 64): 16-byte loads, thread -> (row tid / 16 + 16 rep, t 4 (tid % 16) ..);
+  // otherwise element loads, thread -> (row tid % 64, t tid / 64 + 4 rep)
+  const int vt = 4 * (threadIdx.x % 16), vr = threadIdx.x / 16;
+  for (int64_t tb = t0; tb < t1; tb += kGWT) {
+    __syncthreads();
+    if (vec) {
+      // the whole round lies in one (a, b) row segment: tb % B + 64 <= B, t1 - tb is a multiple of 64
+      const int64_t a = tb / B, b = tb - (tb / B) * B + vt;
+#pragma unroll
+      for (int rep = 0; rep < 4; ++rep) {
+        const int ii = vr + 16 * rep;
+        mc_f32x4v p4 = (ii < nP) ? *reinterpret_cast<const mc_f32x4v*>(X + a * m * B + (i0 + ii) * B + b)
+                                 : mc_f32x4v{0.f, 0.f, 0.f, 0.f};
+        double* dp = sP + ii * kGWStride + vt;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) dp[e] = static_cast<double>(p4[e]);
+        if (!diag) {
+          mc_f32x4v q4 = (ii < nQ) ? *reinterpret_cast<const mc_f32x4v*>(X + a * m * B + (j0 + ii) * B + b)
+                                   : mc_f32x4v{0.f, 0.f, 0.f, 0.f};
+          double* dq = sQ + ii * kGWStride + vt;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) dq[e] = static_cast<double>(q4[e]);
+        }
+      }
+    } else {
+      const int li = threadIdx.x % kMCTile;
+#pragma unroll 4
+      for (int r = 0; r < kGWT / 4; ++r) {
+        const int tt = threadIdx.x / kMCTile + 4 * r;
+        const int64_t t = tb + tt;
+        const bool tin = t < t1;
+        const int64_t a = tin ? t / B : 0, b = tin ? t - (t / B) * B : 0;
+        sP[li * kGWStride + tt] = (tin && li < nP) ? static_cast<double>(X[a * m * B + (i0 + li) * B + b]) : 0.0;
+        if (!diag)
+          sQ[li * kGWStride + tt] = (tin && li < nQ) ? static_cast<double>(X[a * m * B + (j0 + li) * B + b]) : 0.0;
+      }
+    }
+    __syncthreads();
+    if (wave_rows) {
+#pragma unroll 4
+      for (int k0 = 0; k0 < kGWT; k0 += 4) {
+        const double av = sP[(16 * wave + r16) * kGWStride + k0 + q];
+#pragma unroll
+        for (int js = 0; js < 4; ++js)
+          if (js < njt) {
+            const double bv = sQr[(16 * js + r16) * kGWStride + k0 + q];
+            acc[js] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[js], 0, 0, 0);
+          }
+      }
+    }
+  }
+  if (!wave_rows) return;
+  // binary64 16x16x4 result layout: value v of lane (r16, q) is row q + 4 v, column r16
+  double* out = part + (static_cast<int64_t>(blockIdx.y) * gridDim.x + tile) * kMCTile * kMCTile;
+#pragma unroll
+  for (int js = 0; js < 4; ++js)
+    if (js < njt) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[(16 * wave + q + 4 * v) * kMCTile + 16 * js + r16] = acc[js][v];
+    }
+}
+
+// out[i][j] (m x m) = sum over chunks of the upper tiles' partials, (i, j) below the diagonal
+// tile read transposed from tile (j, i); 16 lanes per element, fixed order
+__global__ __launch_bounds__(256) void gram_wide_reduce(const double* __restrict__ part, int nchunks, int tiles1,
+                                                        int64_t m, double* __restrict__ out) {
+  const int64_t total = m * m;
+  const int sub = threadIdx.x % 16;
+  const int64_t idx = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) / 16;
+  const bool valid = idx < total;
+  double s = 0.0;
+  if (valid) {
+    int64_t i = idx / m, j = idx - (idx / m) * m;
+    if (i / kMCTile > j / kMCTile) {
+      const int64_t t = i;
+      i = j;
+      j = t;
+    }
+    const int tile = static_cast<int>((i / kMCTile) * tiles1 + (j / kMCTile));
+    const int64_t off = (i % kMCTile) * kMCTile + (j % kMCTile);
+    const int tiles = tiles1 * tiles1;
+    for (int c = sub; c < nchunks; c += 16) s += part[(static_cast<int64_t>(c) * tiles + tile) * kMCTile * kMCTile + off];
+  }
+#pragma unroll
+  for (int o = 8; o >= 1; o >>= 1) s += __shfl_xor(s, o, 16);
+  if (valid && sub == 0) out[idx] = s;
 }
 
 // Gram matrix of one binary64 (A, m, B) view per workgroup (m <= 64), batched
@@ -1197,6 +1319,46 @@ size_t mode_contract_ws(rt_dtype dt, int64_t A, int64_t mP, int64_t mQ, int64_t 
   return align256(static_cast<size_t>(p.nchunks) * p.tilesP * p.tilesQ * kMCTile * kMCTile * dtype_size(dt));
 }
 
+namespace {
+struct WidePlan {
+  int tiles1;
+  int64_t chunk;
+  int nchunks;
+};
+WidePlan wide_plan(int64_t A, int64_t m, int64_t B) {
+  WidePlan p;
+  p.tiles1 = static_cast<int>(ceil_div(m, kMCTile));
+  const int64_t upper = static_cast<int64_t>(p.tiles1) * (p.tiles1 + 1) / 2;
+  const int64_t total = A * B;
+  // about 2048 working workgroups (8 per CU), at least 64 t per workgroup
+  int64_t want = 2048 / upper;
+  if (want < 1) want = 1;
+  int64_t chunk = ceil_div(total, want);
+  if (chunk < 64) chunk = 64;
+  chunk = ceil_div(chunk, kGWT) * kGWT;
+  p.chunk = chunk;
+  p.nchunks = static_cast<int>(ceil_div(total, chunk));
+  if (p.nchunks < 1) p.nchunks = 1;
+  return p;
+}
+}  // namespace
+
+size_t gram_wide_ws(int64_t A, int64_t m, int64_t B) {
+  const WidePlan p = wide_plan(A, m, B);
+  return align256(static_cast<size_t>(p.nchunks) * p.tiles1 * p.tiles1 * kMCTile * kMCTile * sizeof(double));
+}
+
+hipError_t launch_gram_wide(const float* X, int64_t A, int64_t m, int64_t B, double* out, void* ws, hipStream_t st) {
+  const WidePlan p = wide_plan(A, m, B);
+  const dim3 grid(p.tiles1 * p.tiles1, p.nchunks);
+  // 16-byte loads when rows hold whole 64-t rounds and X is 16-byte aligned
+  const bool vec = (B % kGWT == 0) && (reinterpret_cast<uintptr_t>(X) & 15u) == 0;
+  gram_wide_kernel<<<grid, kMCThreads, 0, st>>>(X, A, m, B, p.chunk, p.tiles1, vec, static_cast<double*>(ws));
+  const unsigned g2 = static_cast<unsigned>(ceil_div(m * m * 16, 256));
+  gram_wide_reduce<<<g2, 256, 0, st>>>(static_cast<const double*>(ws), p.nchunks, p.tiles1, m, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_mode_contract(const void* P, const void* Q, rt_dtype dt, int64_t A, int64_t mP, int64_t mQ,
                                 int64_t B, void* out, void* ws, hipStream_t st, bool accumulate) {
   const MCPlan p = mc_plan(dt, A, mP, mQ, B);
@@ -1287,6 +1449,87 @@ hipError_t launch_small_gemm_f64(const SmallGemmJob* jobs, int count, hipStream_
   }
   const dim3 grid(static_cast<unsigned>(ceil_div(mmax, kSGRows)), static_cast<unsigned>(count));
   small_gemm_f64_kernel<<<grid, 256, 0, st>>>(tab);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ subspace iteration pieces
+// (eigenvectors of the large Gram matrices of the deterministic STHOSVD, n > 64)
+
+// Q[i][c] = fixed pseudo-random start block (n x b), MurmurHash3 finaliser of (i, c)
+__global__ __launch_bounds__(256) void subspace_start_kernel(double* __restrict__ Q, int64_t n, int b) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (t >= n * b) return;
+  uint32_t h = static_cast<uint32_t>(t * 2654435761ull + 12345u);
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  Q[t] = static_cast<double>(h) * 0x1p-32 - 0.5;
+}
+
+// out[0] = max_i ||MV[:, i] - theta_i V[:, i]|| / theta_0 (MV, V: n x r row-major), one
+// workgroup: thread c % r sums column c over every (256 / r)-th row, fixed order
+__global__ __launch_bounds__(256) void ritz_residual_kernel(const double* __restrict__ MV,
+                                                            const double* __restrict__ V,
+                                                            const double* __restrict__ theta, int64_t n, int r,
+                                                            double* __restrict__ out) {
+  __shared__ double part[256];
+  const int t = threadIdx.x;
+  const int per = 256 / r;  // row groups
+  double acc = 0.0;
+  const int c = t % r, g = t / r;
+  if (g < per)
+    for (int64_t i = g; i < n; i += per) {
+      const double d = MV[i * r + c] - theta[c] * V[i * r + c];
+      acc = fma(d, d, acc);
+    }
+  part[t] = (g < per) ? acc : 0.0;
+  __syncthreads();
+  if (t == 0) {
+    double worst = 0.0;
+    for (int cc = 0; cc < r; ++cc) {
+      double s = 0.0;
+      for (int gg = 0; gg < per; ++gg) s += part[gg * r + cc];
+      worst = fmax(worst, sqrt(s));
+    }
+    out[0] = worst / fmax(fabs(theta[0]), 1e-300);
+  }
+}
+
+// make every column's largest-magnitude entry (first on ties) positive; one wave per column
+__global__ __launch_bounds__(64) void column_sign_kernel(double* __restrict__ V, int64_t n, int r) {
+  const int c = blockIdx.x;
+  const int lane = threadIdx.x;
+  double best = -1.0;
+  int64_t where = 0;
+  for (int64_t i = lane; i < n; i += 64) {
+    const double a = fabs(V[i * r + c]);
+    if (a > best) { best = a; where = i; }
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double ob = __shfl_xor(best, off);
+    const int64_t ow = __shfl_xor(where, off);
+    if (ob > best || (ob == best && ow < where)) { best = ob; where = ow; }
+  }
+  const bool flip = V[where * r + c] < 0.0;
+  if (flip)
+    for (int64_t i = lane; i < n; i += 64) V[i * r + c] = -V[i * r + c];
+}
+
+hipError_t launch_subspace_start(double* Q, int64_t n, int b, hipStream_t st) {
+  subspace_start_kernel<<<static_cast<unsigned>(ceil_div(n * b, 256)), 256, 0, st>>>(Q, n, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_ritz_residual(const double* MV, const double* V, const double* theta, int64_t n, int r,
+                                double* out, hipStream_t st) {
+  ritz_residual_kernel<<<1, 256, 0, st>>>(MV, V, theta, n, r, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_column_sign(double* V, int64_t n, int r, hipStream_t st) {
+  column_sign_kernel<<<static_cast<unsigned>(r), 64, 0, st>>>(V, n, r);
   return hipGetLastError();
 }
 

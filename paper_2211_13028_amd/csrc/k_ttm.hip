@@ -359,6 +359,21 @@ __global__ __launch_bounds__(kMfmaThreads) void ttm_mfma_f32_kernel(const float*
   ttm_f32_unit<MT, VM, TAIL>(X, A, K, B, Mop, m, chunks, ksplit, kper, Y, unit);
 }
 
+// The same for at most three 16-row tiles, held to 256 registers so that two waves share
+// each SIMD: a wave has one block of X in flight besides the one it multiplies, so with one
+// wave per SIMD (the compiler's choice otherwise: about 300 vector and matrix registers) the
+// loads in flight per CU cover too little of the memory latency.  (With four tiles the
+// limit would spill.)
+template <int MT, bool VM, int TAIL = 0>
+__global__ __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(2))) void ttm_mfma_f32_occ2_kernel(
+    const float* __restrict__ X, int64_t A, int64_t K, int64_t B, const float* __restrict__ Mop, int64_t m,
+    int64_t chunks, int ksplit, int64_t kper, float* __restrict__ Y) {
+  static_assert(MT <= 3, "four tiles do not fit two waves per SIMD");
+  const int64_t unit = static_cast<int64_t>(blockIdx.x) * (kMfmaThreads / kWave) + threadIdx.x / kWave;
+  if (unit >= A * chunks * ksplit) return;
+  ttm_f32_unit<MT, VM, TAIL>(X, A, K, B, Mop, m, chunks, ksplit, kper, Y, unit);
+}
+
 // Independent binary32 contractions of one shape class in one launch: job q owns the
 // units [unit0_q, unit0_q + A_q chunks_q ksplit_q).
 struct F32Job {
@@ -669,15 +684,16 @@ hipError_t launch_ttm_mfma_ws(const void* X, rt_dtype xdt, int64_t A, int64_t K,
   const int64_t units = A * p.chunks * p.ksplit;
   const unsigned grid = static_cast<unsigned>(ceil_div(units, kMfmaThreads / kWave));
   const int MT = static_cast<int>(ttm_mfma_mpad(m) / 16);
-#define RT_LAUNCH_F32(MTV)                                                                                  \
+#define RT_LAUNCH_F32_K(KERNEL, MTV)                                                                        \
   if (K % 4 == 0)                                                                                           \
-    ttm_mfma_f32_kernel<MTV, true><<<grid, kMfmaThreads, 0, st>>>(static_cast<const float*>(X), A, K, B,    \
-                                                                  static_cast<const float*>(Mop), m,        \
-                                                                  p.chunks, p.ksplit, p.kper, out);         \
+    KERNEL<MTV, true><<<grid, kMfmaThreads, 0, st>>>(static_cast<const float*>(X), A, K, B,                 \
+                                                     static_cast<const float*>(Mop), m, p.chunks, p.ksplit,  \
+                                                     p.kper, out);                                          \
   else                                                                                                      \
-    ttm_mfma_f32_kernel<MTV, false><<<grid, kMfmaThreads, 0, st>>>(static_cast<const float*>(X), A, K, B,   \
-                                                                   static_cast<const float*>(Mop), m,       \
-                                                                   p.chunks, p.ksplit, p.kper, out)
+    KERNEL<MTV, false><<<grid, kMfmaThreads, 0, st>>>(static_cast<const float*>(X), A, K, B,                \
+                                                      static_cast<const float*>(Mop), m, p.chunks, p.ksplit, \
+                                                      p.kper, out)
+#define RT_LAUNCH_F32(MTV) RT_LAUNCH_F32_K(ttm_mfma_f32_occ2_kernel, MTV)
 #define RT_LAUNCH_BF16(MTV)                                                                                 \
   ttm_mfma_bf16_kernel<MTV><<<grid, kMfmaThreads, 0, st>>>(static_cast<const bf16_t*>(X), A, K, B,          \
                                                            static_cast<const bf16_t*>(Mop), m, p.chunks,    \
@@ -699,7 +715,7 @@ hipError_t launch_ttm_mfma_ws(const void* X, rt_dtype xdt, int64_t A, int64_t K,
       case 1: RT_LAUNCH_F32(1); break;
       case 2: RT_LAUNCH_F32(2); break;
       case 3: RT_LAUNCH_F32(3); break;
-      default: RT_LAUNCH_F32(4); break;
+      default: RT_LAUNCH_F32_K(ttm_mfma_f32_kernel, 4); break;
     }
   } else {
     switch (MT) {
@@ -710,6 +726,7 @@ hipError_t launch_ttm_mfma_ws(const void* X, rt_dtype xdt, int64_t A, int64_t K,
     }
   }
 #undef RT_LAUNCH_F32
+#undef RT_LAUNCH_F32_K
 #undef RT_LAUNCH_F32_TAIL
 #undef RT_LAUNCH_BF16
   hipError_t e = hipGetLastError();

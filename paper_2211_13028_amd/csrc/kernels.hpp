@@ -150,6 +150,11 @@ hipError_t launch_mode_contract(const void* P, const void* Q, rt_dtype dt, int64
                                 int64_t mQ, int64_t B, void* out, void* ws, hipStream_t st,
                                 bool accumulate = false);
 
+// out = X_(n) X_(n)^T (m x m, binary64) of a binary32 (A, m, B) view, accumulated in binary64
+size_t gram_wide_ws(int64_t A, int64_t m, int64_t B);
+hipError_t launch_gram_wide(const float* X, int64_t A, int64_t m, int64_t B, double* out, void* ws,
+                            hipStream_t st);
+
 // Leading eigenpairs (binary64) of a symmetric positive semidefinite n x n matrix
 // (n <= 64): Householder tridiagonalisation, multisection and inverse iteration for
 // r <= 32, one-sided Jacobi on a pivoted Cholesky factor otherwise or when the first
@@ -169,6 +174,13 @@ struct SmallGemmJob {
 hipError_t launch_small_gemm_f64(const SmallGemmJob* jobs, int count, hipStream_t st);
 hipError_t launch_sym_eig_top(const double* M, int64_t n, int64_t r, double* V, double* evals,
                               hipStream_t st);
+// subspace iteration pieces for Gram matrices larger than 64 x 64 (deterministic STHOSVD):
+// a fixed pseudo-random n x b start block; max_i ||(M V)_i - theta_i V_i|| / theta_0 of
+// Ritz pairs (r <= 64); the sign rule (largest-magnitude entry positive) on n x r columns
+hipError_t launch_subspace_start(double* Q, int64_t n, int b, hipStream_t st);
+hipError_t launch_ritz_residual(const double* MV, const double* V, const double* theta, int64_t n, int r,
+                                double* out, hipStream_t st);
+hipError_t launch_column_sign(double* V, int64_t n, int r, hipStream_t st);
 
 // ------------------------------------------------------------------ k_norm.hip
 // Residual of X viewed as (I1, Brest) against U1 (I1 x r1) times T (r1 x Brest),

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     L = rt.lib()
-    for code in range(0, -7, -1):
+    for code in range(0, -8, -1):
         assert L.rtucker_status_string(code)
     assert L.rtucker_status_string(1) == b"unknown status"
 

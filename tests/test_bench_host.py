@@ -79,3 +79,15 @@ def test_committed_summary_is_well_formed(bench, path):
     assert m and int(m.group(1)) > 0
     m = re.search(r"^source_sha256\((\S+)\): [0-9a-f]{64}$", text, re.M)
     assert m and os.path.exists(os.path.join(ROOT, m.group(1)))
+
+
+def test_bench_calls_only_existing_binding_functions():
+    """Every rt.<name> that bench.py and the GPU tests call exists in the binding (a missing one
+    would only show on the GPU machine)."""
+    import paper_2211_13028_amd as rt
+    names = set()
+    for path in [os.path.join(ROOT, "bench.py"), os.path.join(ROOT, "__graft_entry__.py")] + [
+            os.path.join(ROOT, "tests", f) for f in os.listdir(os.path.join(ROOT, "tests")) if f.endswith(".py")]:
+        names |= set(re.findall(r"\brt\.(rtucker_\w+|Batch|NOALLOC_\w+)", open(path).read()))
+    missing = sorted(n for n in names if not hasattr(rt, n))
+    assert not missing, missing

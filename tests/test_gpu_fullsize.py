@@ -151,3 +151,20 @@ def test_fullsize_rsthkron_128_4way(dtype):
     e_or = T.rel_error(X64, Go, Uo)
     say(f"  128^4 {dtype}: e_device={e_dev:.9e} e_oracle={e_or:.9e}")
     assert abs(e_dev - e_or) <= 1e-5, (e_dev, e_or)
+
+
+def test_fullsize_sthosvd_matches_oracle_golden(work):
+    """The deterministic STHOSVD of the workload against the oracle's value, stored by
+    tests/golden/make_sthosvd_golden.py (numpy SVD per mode, float64)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sthosvd_1024x1024x512.txt")
+    want = {ln.split()[0]: float(ln.split()[1]) for ln in open(path) if ln.strip() and not ln.startswith("#")}
+    say("full size: deterministic STHOSVD")
+    G, Us, it = rt.rtucker_sthosvd(work["X32"], R)
+    e_dev, _ = rt.rtucker_rel_error(work["X32"], G, Us)
+    say(f"  sthosvd: e_device={e_dev:.9e} e_oracle={want['rel_error']:.9e} iterations={it}")
+    assert abs(e_dev - want["rel_error"]) <= 1e-5
+    assert abs(float(torch.linalg.norm(G)) - want["core_norm"]) <= 1e-5 * want["core_norm"]
+    for U in Us:
+        Uh = host(U)
+        np.testing.assert_allclose(Uh.T @ Uh, np.eye(32), atol=1e-12)
