@@ -21,6 +21,10 @@ SOURCES = ["api.cpp", "k_basic.hip", "k_ttm.hip", "k_sketch.hip", "k_qr.hip", "k
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# The eigensolver file's matrix-core loops keep their accumulators in ordinary VGPRs: with the
+# compiler's default choice of accumulation registers, the binary64 Gram loop copied every
+# accumulator out and back around each unrolled group of products.
+FILE_FLAGS = {"k_eig.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _hipcc() -> str:
@@ -33,7 +37,7 @@ def _hipcc() -> str:
 def _compile(src: str) -> str:
     obj = os.path.join(OUT, os.path.splitext(src)[0] + ".o")
     lang = ["-x", "hip"]
-    cmd = [_hipcc(), *lang, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [_hipcc(), *lang, *FLAGS, *FILE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

@@ -796,8 +796,9 @@ int subspace_top(Ctx& c, const double* M, int64_t n, int64_t r, double* V, int32
   void* wz = c.take(ttm_generic_ws(RT_F64, 1, n, b, n));
   void* wv = c.take(ttm_generic_ws(RT_F64, 1, n, r, n));
   void* wh = c.take(mode_contract_ws(RT_F64, n, b, b, 1));
+  double* T = static_cast<double*>(c.take(static_cast<size_t>(n) * b * sizeof(double)));
   QRJob job{Z, 1, n, b, Q, nullptr};
-  void* wq = c.take(qr_ws(&job, 1));
+  void* wq = c.take(orth_ws(n, b));
   c.flush();
   if (c.dry) return RT_OK;
   c.chk(launch_subspace_start(Z, n, b, c.st));
@@ -821,7 +822,8 @@ int subspace_top(Ctx& c, const double* M, int64_t n, int64_t r, double* V, int32
       if (h <= kSubTol) done = true;
       else if (it >= kSubMaxIter) break;
     }
-    if (!done) c.chk(launch_qr(&job, 1, RT_F64, wq, c.st));  // Q = orth(M Q)
+    // Q = orth(M Q): the columns of M Q are as ill-conditioned as the spectrum of M is wide
+    if (!done) c.chk(launch_orth(Z, n, b, T, Q, wq, c.st));
   }
   c.chk(launch_column_sign(V, n, static_cast<int>(r), c.st));
   if (iters) *iters += it;

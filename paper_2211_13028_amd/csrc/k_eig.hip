@@ -106,91 +106,121 @@ __global__ __launch_bounds__(kMCThreads) void mode_contract_kernel(const T* __re
 
 // Gram matrix X_(n) X_(n)^T of a binary32 (A, m, B) view, accumulated in binary64 (the
 // deterministic STHOSVD: a binary32 Gram matrix would bury the trailing eigenvalues, whose
-// share of ||X||^2 is the squared error, under its rounding).  The staging of the binary32
-// matrix-core contraction below, with binary64 16x16x4 matrix-core products of the widened
-// (exact) values.  Only the tiles on or above the diagonal are computed (the others exit at
-// once); the reduction mirrors them.
+// share of ||X||^2 is the squared error, under its rounding).  64 x 64 output tiles on or
+// above the diagonal only (the reduction mirrors them), each summed over one chunk of t;
+// binary64 16x16x4 matrix-core products of the widened (exact) binary32 values.
+//  * operands stay binary32 in LDS (half the footprint: four workgroups per CU) and are
+//    widened as they are read;
+//  * the next 64 t are fetched into registers while the current 64 are multiplied;
+//  * workgroups are numbered so that all tiles of one chunk run on one XCD (the hardware
+//    deals consecutive workgroups round-robin to the eight XCDs), so each XCD's L2 holds
+//    the rows its tiles share and X streams from HBM about once.
 typedef double mc_f64x4 __attribute__((ext_vector_type(4)));
 typedef float mc_f32x4v __attribute__((ext_vector_type(4)));
 constexpr int kGWT = 64;                // t staged per round
-constexpr int kGWStride = kGWT + 2;     // doubles per LDS row (even: aligned double pairs)
-__global__ __launch_bounds__(256) void gram_wide_kernel(const float* __restrict__ X, int64_t A, int64_t m, int64_t B,
-                                                        int64_t chunk, int tiles1, bool vec,
-                                                        double* __restrict__ part) {
-  __shared__ double sP[kMCTile * kGWStride];
-  __shared__ double sQ[kMCTile * kGWStride];
-  const int tile = blockIdx.x;
-  const int ti = tile / tiles1, tj = tile % tiles1;
-  if (ti > tj) return;
+constexpr int kGWStride = kGWT + 4;     // floats per LDS row: 16-byte rows, conflict-free column reads
+constexpr int kXcds = 8;
+template <bool vec>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void gram_wide_kernel(
+    const float* __restrict__ X, int64_t A, int64_t m, int64_t B, int64_t chunk, int tiles1, int upper, int64_t work,
+    double* __restrict__ part) {
+  __shared__ __align__(16) float sP[kMCTile * kGWStride];
+  __shared__ __align__(16) float sQ[kMCTile * kGWStride];
+  // XCD-aware numbering: hardware workgroup h runs on XCD h % 8; logical id = XCD-major
+  const int64_t per = static_cast<int64_t>(gridDim.x) / kXcds;
+  const int64_t logical = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+  if (logical >= work) return;
+  const int c = static_cast<int>(logical / upper);
+  int rem = static_cast<int>(logical % upper), ti = 0;
+  while (rem >= tiles1 - ti) {  // row-major enumeration of the upper tiles
+    rem -= tiles1 - ti;
+    ++ti;
+  }
+  const int tj = ti + rem;
   const bool diag = ti == tj;  // P and Q blocks coincide: stage one
   const int64_t i0 = static_cast<int64_t>(ti) * kMCTile, j0 = static_cast<int64_t>(tj) * kMCTile;
   const int64_t total = A * B;
-  const int64_t t0 = static_cast<int64_t>(blockIdx.y) * chunk;
+  const int64_t t0 = static_cast<int64_t>(c) * chunk;
   const int64_t t1 = (t0 + chunk < total) ? t0 + chunk : total;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int r16 = lane % 16, q = lane / 16;
   const int64_t nP = (m - i0 < kMCTile) ? m - i0 : kMCTile;
   const int64_t nQ = (m - j0 < kMCTile) ? m - j0 : kMCTile;
-  const int njt = static_cast<int>((nQ + 15) / 16);
-  const bool wave_rows = 16 * wave < nP;
-  const double* sQr = diag ? sP : sQ;
+  const float* sQr = diag ? sP : sQ;
   mc_f64x4 acc[4];
 #pragma unroll
   for (int js = 0; js < 4; ++js) acc[js] = mc_f64x4{0.0, 0.0, 0.0, 0.0};
-  // vec (B % 64 == 0, X 16-byte aligned; the plan's chunks are multiples of 64): 16-byte loads, thread -> (row tid / 16 + 16 rep, t 4 (tid % 16) ..);
-  // otherwise element loads, thread -> (row tid % 64, t tid / 64 + 4 rep)
+  // vec (B % 64 == 0, X 16-byte aligned, chunks multiples of 64): a round lies in one
+  // (a, b) row segment; thread -> rows tid / 16 + 16 rep, t 4 (tid % 16) .. + 3.
+  // Otherwise element loads: thread -> row tid % 64, t tid / 64 + 4 rep.
   const int vt = 4 * (threadIdx.x % 16), vr = threadIdx.x / 16;
-  for (int64_t tb = t0; tb < t1; tb += kGWT) {
-    __syncthreads();
-    if (vec) {
-      // the whole round lies in one (a, b) row segment: tb % B + 64 <= B, t1 - tb is a multiple of 64
+  const int li = threadIdx.x % kMCTile, lt = threadIdx.x / kMCTile;
+  mc_f32x4v pv[4], qv[4];
+  auto fetch = [&](int64_t tb) {
+    if constexpr (vec) {
       const int64_t a = tb / B, b = tb - (tb / B) * B + vt;
 #pragma unroll
       for (int rep = 0; rep < 4; ++rep) {
         const int ii = vr + 16 * rep;
-        mc_f32x4v p4 = (ii < nP) ? *reinterpret_cast<const mc_f32x4v*>(X + a * m * B + (i0 + ii) * B + b)
-                                 : mc_f32x4v{0.f, 0.f, 0.f, 0.f};
-        double* dp = sP + ii * kGWStride + vt;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) dp[e] = static_cast<double>(p4[e]);
-        if (!diag) {
-          mc_f32x4v q4 = (ii < nQ) ? *reinterpret_cast<const mc_f32x4v*>(X + a * m * B + (j0 + ii) * B + b)
-                                   : mc_f32x4v{0.f, 0.f, 0.f, 0.f};
-          double* dq = sQ + ii * kGWStride + vt;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) dq[e] = static_cast<double>(q4[e]);
-        }
+        pv[rep] = (ii < nP) ? *reinterpret_cast<const mc_f32x4v*>(X + a * m * B + (i0 + ii) * B + b)
+                            : mc_f32x4v{0.f, 0.f, 0.f, 0.f};
+        qv[rep] = (!diag && ii < nQ) ? *reinterpret_cast<const mc_f32x4v*>(X + a * m * B + (j0 + ii) * B + b)
+                                     : mc_f32x4v{0.f, 0.f, 0.f, 0.f};
       }
     } else {
-      const int li = threadIdx.x % kMCTile;
-#pragma unroll 4
-      for (int r = 0; r < kGWT / 4; ++r) {
-        const int tt = threadIdx.x / kMCTile + 4 * r;
-        const int64_t t = tb + tt;
-        const bool tin = t < t1;
-        const int64_t a = tin ? t / B : 0, b = tin ? t - (t / B) * B : 0;
-        sP[li * kGWStride + tt] = (tin && li < nP) ? static_cast<double>(X[a * m * B + (i0 + li) * B + b]) : 0.0;
-        if (!diag)
-          sQ[li * kGWStride + tt] = (tin && li < nQ) ? static_cast<double>(X[a * m * B + (j0 + li) * B + b]) : 0.0;
-      }
-    }
-    __syncthreads();
-    if (wave_rows) {
-#pragma unroll 4
-      for (int k0 = 0; k0 < kGWT; k0 += 4) {
-        const double av = sP[(16 * wave + r16) * kGWStride + k0 + q];
 #pragma unroll
-        for (int js = 0; js < 4; ++js)
-          if (js < njt) {
-            const double bv = sQr[(16 * js + r16) * kGWStride + k0 + q];
-            acc[js] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[js], 0, 0, 0);
-          }
+      for (int rep = 0; rep < 4; ++rep)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t t = tb + lt + 4 * (4 * rep + e);
+          const bool tin = t < t1;
+          const int64_t a = tin ? t / B : 0, b = tin ? t - (t / B) * B : 0;
+          pv[rep][e] = (tin && li < nP) ? X[a * m * B + (i0 + li) * B + b] : 0.f;
+          qv[rep][e] = (tin && !diag && li < nQ) ? X[a * m * B + (j0 + li) * B + b] : 0.f;
+        }
+    }
+  };
+  auto stage = [&]() {
+    if constexpr (vec) {
+#pragma unroll
+      for (int rep = 0; rep < 4; ++rep) {
+        const int ii = vr + 16 * rep;
+        *reinterpret_cast<mc_f32x4v*>(sP + ii * kGWStride + vt) = pv[rep];
+        if (!diag) *reinterpret_cast<mc_f32x4v*>(sQ + ii * kGWStride + vt) = qv[rep];
+      }
+    } else {
+#pragma unroll
+      for (int rep = 0; rep < 4; ++rep)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int tt = lt + 4 * (4 * rep + e);
+          sP[li * kGWStride + tt] = pv[rep][e];
+          if (!diag) sQ[li * kGWStride + tt] = qv[rep][e];
+        }
+    }
+  };
+  fetch(t0);
+  for (int64_t tb = t0; tb < t1; tb += kGWT) {
+    __syncthreads();
+    stage();
+    __syncthreads();
+    if (tb + kGWT < t1) fetch(tb + kGWT);
+    // every wave multiplies all four column tiles: rows past the matrix are zero in LDS,
+    // so their products vanish, and the loop stays branch-free
+#pragma unroll 4
+    for (int k0 = 0; k0 < kGWT; k0 += 4) {
+      const double av = static_cast<double>(sP[(16 * wave + r16) * kGWStride + k0 + q]);
+#pragma unroll
+      for (int js = 0; js < 4; ++js) {
+        const double bv = static_cast<double>(sQr[(16 * js + r16) * kGWStride + k0 + q]);
+        acc[js] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[js], 0, 0, 0);
       }
     }
   }
-  if (!wave_rows) return;
+  if (16 * wave >= nP) return;
   // binary64 16x16x4 result layout: value v of lane (r16, q) is row q + 4 v, column r16
-  double* out = part + (static_cast<int64_t>(blockIdx.y) * gridDim.x + tile) * kMCTile * kMCTile;
+  double* out = part + (static_cast<int64_t>(c) * tiles1 * tiles1 + ti * tiles1 + tj) * kMCTile * kMCTile;
+  const int njt = static_cast<int>((nQ + 15) / 16);
 #pragma unroll
   for (int js = 0; js < 4; ++js)
     if (js < njt) {
@@ -330,16 +360,14 @@ __global__ __launch_bounds__(256) void mode_contract_mfma_kernel(const float* __
       }
     }
     __syncthreads();
-    if (wave_rows) {
+    // branch-free: rows past the matrix are zero in LDS (see the binary64 Gram kernel)
 #pragma unroll
-      for (int k0 = 0; k0 < kMCT; k0 += 4) {
-        const float av = sP[(16 * wave + r16) * kMCStride + k0 + q];
+    for (int k0 = 0; k0 < kMCT; k0 += 4) {
+      const float av = sP[(16 * wave + r16) * kMCStride + k0 + q];
 #pragma unroll
-        for (int js = 0; js < 4; ++js)
-          if (js < njt) {
-            const float bv = sQ[(16 * js + r16) * kMCStride + k0 + q];
-            acc[js] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[js], 0, 0, 0);
-          }
+      for (int js = 0; js < 4; ++js) {
+        const float bv = sQ[(16 * js + r16) * kMCStride + k0 + q];
+        acc[js] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[js], 0, 0, 0);
       }
     }
   }
@@ -1322,19 +1350,19 @@ size_t mode_contract_ws(rt_dtype dt, int64_t A, int64_t mP, int64_t mQ, int64_t 
 namespace {
 struct WidePlan {
   int tiles1;
-  int64_t chunk;
+  int upper;      // tiles on or above the diagonal
+  int64_t chunk;  // t per workgroup, a multiple of 64
   int nchunks;
 };
 WidePlan wide_plan(int64_t A, int64_t m, int64_t B) {
   WidePlan p;
   p.tiles1 = static_cast<int>(ceil_div(m, kMCTile));
-  const int64_t upper = static_cast<int64_t>(p.tiles1) * (p.tiles1 + 1) / 2;
+  p.upper = p.tiles1 * (p.tiles1 + 1) / 2;
   const int64_t total = A * B;
-  // about 2048 working workgroups (8 per CU), at least 64 t per workgroup
-  int64_t want = 2048 / upper;
-  if (want < 1) want = 1;
+  // about 4096 working workgroups (four rounds of four per CU), at least 64 t each
+  int64_t want = ceil_div(static_cast<int64_t>(4096), static_cast<int64_t>(p.upper));
   int64_t chunk = ceil_div(total, want);
-  if (chunk < 64) chunk = 64;
+  if (chunk < kGWT) chunk = kGWT;
   chunk = ceil_div(chunk, kGWT) * kGWT;
   p.chunk = chunk;
   p.nchunks = static_cast<int>(ceil_div(total, chunk));
@@ -1350,10 +1378,16 @@ size_t gram_wide_ws(int64_t A, int64_t m, int64_t B) {
 
 hipError_t launch_gram_wide(const float* X, int64_t A, int64_t m, int64_t B, double* out, void* ws, hipStream_t st) {
   const WidePlan p = wide_plan(A, m, B);
-  const dim3 grid(p.tiles1 * p.tiles1, p.nchunks);
+  const int64_t work = static_cast<int64_t>(p.upper) * p.nchunks;
+  const int64_t blocks = ceil_div(work, static_cast<int64_t>(kXcds)) * kXcds;  // whole XCD rows
   // 16-byte loads when rows hold whole 64-t rounds and X is 16-byte aligned
   const bool vec = (B % kGWT == 0) && (reinterpret_cast<uintptr_t>(X) & 15u) == 0;
-  gram_wide_kernel<<<grid, kMCThreads, 0, st>>>(X, A, m, B, p.chunk, p.tiles1, vec, static_cast<double*>(ws));
+  if (vec)
+    gram_wide_kernel<true><<<static_cast<unsigned>(blocks), kMCThreads, 0, st>>>(X, A, m, B, p.chunk, p.tiles1,
+                                                                               p.upper, work, static_cast<double*>(ws));
+  else
+    gram_wide_kernel<false><<<static_cast<unsigned>(blocks), kMCThreads, 0, st>>>(X, A, m, B, p.chunk, p.tiles1,
+                                                                                p.upper, work, static_cast<double*>(ws));
   const unsigned g2 = static_cast<unsigned>(ceil_div(m * m * 16, 256));
   gram_wide_reduce<<<g2, 256, 0, st>>>(static_cast<const double*>(ws), p.nchunks, p.tiles1, m, out);
   return hipGetLastError();

@@ -348,6 +348,24 @@ __global__ __launch_bounds__(256) void cq_chol_kernel(TAB tab, int second) {
     fullR[kRows * wv + t][lane] = gr[t];
   }
   __syncthreads();
+  const double shift = second ? J.shift2 : J.shift1;
+  if (shift > 0.0) {
+    // shifted Cholesky QR: factor G + s I, s = shift * trace(G).  Its pivots are at least
+    // s, so it cannot break down, and Y R^-1 spans the columns of Y with a condition
+    // number of order 1 / sqrt(shift) at worst (Fukaya et al., SIAM J. Sci. Comput. 2020)
+    double tr = (lane < n) ? fullL[lane][lane] : 0.0;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) tr += __shfl_xor(tr, off);  // same bits in every lane
+    const double sh = shift * tr;
+    __syncthreads();  // every wave has read the diagonal
+#pragma unroll
+    for (int t = 0; t < kRows; ++t)
+      if (kRows * wv + t == lane && lane < n) {
+        gl[t] += sh;
+        fullL[lane][lane] = gl[t];
+      }
+    __syncthreads();
+  }
   double dj = (lane < n) ? fullL[lane][lane] : 0.0;
   double dmax = dj;
 #pragma unroll
@@ -642,7 +660,8 @@ hipError_t qr_level(std::vector<Mat>& mats, bool launch, Bump& ws, hipStream_t s
 
 // Plans (and, when launch is true, enqueues) the QR of a set of jobs:
 // CholeskyQR2 with a Householder fallback for m >= n, Householder otherwise.
-hipError_t qr_plan(const QRJob* jobs, int count, rt_dtype ydt, bool launch, Bump& ws, hipStream_t st) {
+hipError_t qr_plan(const QRJob* jobs, int count, rt_dtype ydt, bool launch, Bump& ws, hipStream_t st,
+                   double shift = 0.0) {
   std::vector<Mat> hh;
   CJobTable tab;
   int nc = 0;
@@ -667,6 +686,7 @@ hipError_t qr_plan(const QRJob* jobs, int count, rt_dtype ydt, bool launch, Bump
       J.Q1 = static_cast<double*>(ws.take(static_cast<size_t>(M.m) * M.n * sizeof(double)));
       J.flag = static_cast<int32_t*>(ws.take(sizeof(int32_t)));
       J.Q = M.Q; J.Rout = M.R;
+      J.shift1 = J.shift2 = shift;
       M.flag = J.flag;
       tab.t[nc++] = J;
       if (J.chunks > max_chunks) max_chunks = J.chunks;
@@ -706,6 +726,23 @@ size_t qr_ws(const QRJob* jobs, int count) {
 hipError_t launch_qr(const QRJob* jobs, int count, rt_dtype ydt, void* ws, hipStream_t st) {
   Bump b{static_cast<char*>(ws), 0};
   return qr_plan(jobs, count, ydt, true, b, st);
+}
+
+size_t orth_ws(int64_t m, int n) {
+  const QRJob job{nullptr, 1, m, n, nullptr, nullptr};
+  return qr_ws(&job, 1);
+}
+
+hipError_t launch_orth(const double* Y, int64_t m, int n, double* T, double* Q, void* ws, hipStream_t st) {
+  // shift factor 11 (m n + n (n + 1)) u of shifted Cholesky QR, applied to trace(G) >= ||Y||_2^2
+  const double shift = 11.0 * (static_cast<double>(m) * n + static_cast<double>(n) * (n + 1)) * 0x1p-53;
+  const QRJob pre{Y, 1, m, n, T, nullptr};
+  Bump b{static_cast<char*>(ws), 0};
+  hipError_t e = qr_plan(&pre, 1, RT_F64, true, b, st, shift);
+  if (e != hipSuccess) return e;
+  const QRJob fin{T, 1, m, n, Q, nullptr};
+  Bump b2{static_cast<char*>(ws), 0};
+  return qr_plan(&fin, 1, RT_F64, true, b2, st);
 }
 
 hipError_t launch_qr_grouped(const GQrJob* jobs, int count, rt_dtype ydt, hipStream_t st) {

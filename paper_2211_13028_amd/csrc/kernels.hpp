@@ -140,6 +140,12 @@ constexpr int kMaxQRJobs = 8;
 constexpr int kMaxQRCols = 64;
 size_t qr_ws(const QRJob* jobs, int count);
 hipError_t launch_qr(const QRJob* jobs, int count, rt_dtype ydt, void* ws, hipStream_t st);
+// Orthonormal basis Q (m x n, m >= n) of the columns of a binary64 m x n matrix Y that may
+// be ill-conditioned or numerically rank-deficient (the subspace iteration's M Q): two
+// shifted Cholesky QR passes into T (m x n scratch), then CholeskyQR2 of T (Householder
+// if that breaks down).  ws: orth_ws(m, n) bytes.
+size_t orth_ws(int64_t m, int n);
+hipError_t launch_orth(const double* Y, int64_t m, int n, double* T, double* Q, void* ws, hipStream_t st);
 
 // ------------------------------------------------------------------ k_eig.hip
 // out[i][j] = sum_{a,b} P[a,i,b] * Q[a,j,b], P: (A, mP, B), Q: (A, mQ, B); same dtype
@@ -255,7 +261,8 @@ hipError_t launch_qr_grouped(const GQrJob* jobs, int count, rt_dtype ydt, hipStr
 // path's fast QR), many jobs per launch.  Per job: part = 2 x chunks x 64 x 64
 // binary64 (chunks = ceil(m / 64)), R1, R2: 64 x 64, Q1: m x n, Q: m x n (ld n),
 // Rout (may be null): n x n, flag: set to 1 when a Cholesky pivot breaks down (the
-// job must then be redone by the Householder kernel).
+// job must then be redone by the Householder kernel).  shift1 / shift2 > 0 make the
+// pass-1 / pass-2 factorisation a shifted one, of G + shift * trace(G) * I (zero: plain).
 struct GCholQRJob {
   const void* Y;
   int64_t A, m, B;
@@ -268,6 +275,7 @@ struct GCholQRJob {
   double* Q;
   double* Rout;
   int32_t* flag;
+  double shift1, shift2;
 };
 hipError_t launch_cholqr2_grouped(const GCholQRJob* jobs, int count, int max_chunks, rt_dtype ydt, hipStream_t st);
 
