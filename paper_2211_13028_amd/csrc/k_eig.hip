@@ -120,7 +120,12 @@ typedef float mc_f32x4v __attribute__((ext_vector_type(4)));
 constexpr int kGWT = 64;                // t staged per round
 constexpr int kGWStride = kGWT + 4;     // floats per LDS row: 16-byte rows, conflict-free column reads
 constexpr int kXcds = 8;
-template <bool vec>
+// operand loads: kGWVec, 16-byte groups along t (B % 4 == 0, X 16-byte aligned; chunks are
+// multiples of 64, so every group of four lies in one (a, b) row); kGWTFast, element loads with
+// the lanes along t (B >= 64: a round crosses at most one row boundary); kGWRowFast,
+// element loads with the lanes along the mode index (short rows, e.g. B = 1)
+enum GWLoad { kGWVec = 0, kGWTFast = 1, kGWRowFast = 2 };
+template <int LOAD>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void gram_wide_kernel(
     const float* __restrict__ X, int64_t A, int64_t m, int64_t B, int64_t chunk, int tiles1, int upper, int64_t work,
     double* __restrict__ part) {
@@ -150,29 +155,54 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void g
   mc_f64x4 acc[4];
 #pragma unroll
   for (int js = 0; js < 4; ++js) acc[js] = mc_f64x4{0.0, 0.0, 0.0, 0.0};
-  // vec (B % 64 == 0, X 16-byte aligned, chunks multiples of 64): a round lies in one
-  // (a, b) row segment; thread -> rows tid / 16 + 16 rep, t 4 (tid % 16) .. + 3.
-  // Otherwise element loads: thread -> row tid % 64, t tid / 64 + 4 rep.
-  const int vt = 4 * (threadIdx.x % 16), vr = threadIdx.x / 16;
-  const int li = threadIdx.x % kMCTile, lt = threadIdx.x / kMCTile;
+  const int vt = 4 * (threadIdx.x % 16), vr = threadIdx.x / 16;  // kGWVec roles
+  const int lt = threadIdx.x % kWave, lr = threadIdx.x / kWave;    // kGWTFast roles
+  const int li = threadIdx.x % kMCTile, lq = threadIdx.x / kMCTile; // kGWRowFast roles
   mc_f32x4v pv[4], qv[4];
   auto fetch = [&](int64_t tb) {
-    if constexpr (vec) {
-      const int64_t a = tb / B, b = tb - (tb / B) * B + vt;
+    if constexpr (LOAD == kGWVec) {
+      // thread -> rows tid / 16 + 16 rep, t 4 (tid % 16) .. + 3; tb and B are multiples
+      // of 4, so a group of four never straddles a row boundary (a round may)
+      const int64_t t = tb + vt;
+      const bool tin = t < t1;
+      const int64_t a = tin ? t / B : 0, b = tin ? t - (t / B) * B : 0;
 #pragma unroll
       for (int rep = 0; rep < 4; ++rep) {
         const int ii = vr + 16 * rep;
-        pv[rep] = (ii < nP) ? *reinterpret_cast<const mc_f32x4v*>(X + a * m * B + (i0 + ii) * B + b)
-                            : mc_f32x4v{0.f, 0.f, 0.f, 0.f};
-        qv[rep] = (!diag && ii < nQ) ? *reinterpret_cast<const mc_f32x4v*>(X + a * m * B + (j0 + ii) * B + b)
-                                     : mc_f32x4v{0.f, 0.f, 0.f, 0.f};
+        pv[rep] = (tin && ii < nP) ? *reinterpret_cast<const mc_f32x4v*>(X + a * m * B + (i0 + ii) * B + b)
+                                   : mc_f32x4v{0.f, 0.f, 0.f, 0.f};
+        qv[rep] = (tin && !diag && ii < nQ) ? *reinterpret_cast<const mc_f32x4v*>(X + a * m * B + (j0 + ii) * B + b)
+                                            : mc_f32x4v{0.f, 0.f, 0.f, 0.f};
       }
-    } else {
+    } else if constexpr (LOAD == kGWTFast) {
+      // thread -> t = tb + tid % 64, rows tid / 64 + 4 k (a wave reads 64 consecutive t of a row)
+      int64_t a = tb / B, b = tb - (tb / B) * B + lt;
+      if (b >= B) {
+        b -= B;
+        ++a;
+      }
+      const bool tin = tb + lt < t1;
+      // row ii = lr + 4 k: the lane's address advances by the uniform 4 B per k
+      const float* pp = X + a * m * B + (i0 + lr) * B + b;
+      const float* qp = X + a * m * B + (j0 + lr) * B + b;
+      const int64_t step = 4 * B;
 #pragma unroll
       for (int rep = 0; rep < 4; ++rep)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int64_t t = tb + lt + 4 * (4 * rep + e);
+          const int ii = lr + 4 * (4 * rep + e);
+          pv[rep][e] = (tin && ii < nP) ? *pp : 0.f;
+          qv[rep][e] = (tin && !diag && ii < nQ) ? *qp : 0.f;
+          pp += step;
+          qp += step;
+        }
+    } else {
+      // thread -> row tid % 64, t = tb + tid / 64 + 4 k
+#pragma unroll
+      for (int rep = 0; rep < 4; ++rep)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t t = tb + lq + 4 * (4 * rep + e);
           const bool tin = t < t1;
           const int64_t a = tin ? t / B : 0, b = tin ? t - (t / B) * B : 0;
           pv[rep][e] = (tin && li < nP) ? X[a * m * B + (i0 + li) * B + b] : 0.f;
@@ -181,19 +211,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void g
     }
   };
   auto stage = [&]() {
-    if constexpr (vec) {
+    if constexpr (LOAD == kGWVec) {
 #pragma unroll
       for (int rep = 0; rep < 4; ++rep) {
         const int ii = vr + 16 * rep;
         *reinterpret_cast<mc_f32x4v*>(sP + ii * kGWStride + vt) = pv[rep];
         if (!diag) *reinterpret_cast<mc_f32x4v*>(sQ + ii * kGWStride + vt) = qv[rep];
       }
+    } else if constexpr (LOAD == kGWTFast) {
+#pragma unroll
+      for (int rep = 0; rep < 4; ++rep)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int ii = lr + 4 * (4 * rep + e);
+          sP[ii * kGWStride + lt] = pv[rep][e];
+          if (!diag) sQ[ii * kGWStride + lt] = qv[rep][e];
+        }
     } else {
 #pragma unroll
       for (int rep = 0; rep < 4; ++rep)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int tt = lt + 4 * (4 * rep + e);
+          const int tt = lq + 4 * (4 * rep + e);
           sP[li * kGWStride + tt] = pv[rep][e];
           if (!diag) sQ[li * kGWStride + tt] = qv[rep][e];
         }
@@ -1359,8 +1398,10 @@ WidePlan wide_plan(int64_t A, int64_t m, int64_t B) {
   p.tiles1 = static_cast<int>(ceil_div(m, kMCTile));
   p.upper = p.tiles1 * (p.tiles1 + 1) / 2;
   const int64_t total = A * B;
-  // about 4096 working workgroups (four rounds of four per CU), at least 64 t each
-  int64_t want = ceil_div(static_cast<int64_t>(4096), static_cast<int64_t>(p.upper));
+  // at most 4096 working workgroups (four rounds of four per CU, none left for a short
+  // fifth), at least 64 t each
+  int64_t want = 4096 / p.upper;
+  if (want < 1) want = 1;
   int64_t chunk = ceil_div(total, want);
   if (chunk < kGWT) chunk = kGWT;
   chunk = ceil_div(chunk, kGWT) * kGWT;
@@ -1380,14 +1421,16 @@ hipError_t launch_gram_wide(const float* X, int64_t A, int64_t m, int64_t B, dou
   const WidePlan p = wide_plan(A, m, B);
   const int64_t work = static_cast<int64_t>(p.upper) * p.nchunks;
   const int64_t blocks = ceil_div(work, static_cast<int64_t>(kXcds)) * kXcds;  // whole XCD rows
-  // 16-byte loads when rows hold whole 64-t rounds and X is 16-byte aligned
-  const bool vec = (B % kGWT == 0) && (reinterpret_cast<uintptr_t>(X) & 15u) == 0;
+  // 16-byte loads when rows hold whole groups of four and X is 16-byte aligned
+  const bool vec = (B % 4 == 0) && (reinterpret_cast<uintptr_t>(X) & 15u) == 0;
+  const unsigned nb = static_cast<unsigned>(blocks);
+  double* part = static_cast<double*>(ws);
   if (vec)
-    gram_wide_kernel<true><<<static_cast<unsigned>(blocks), kMCThreads, 0, st>>>(X, A, m, B, p.chunk, p.tiles1,
-                                                                               p.upper, work, static_cast<double*>(ws));
+    gram_wide_kernel<kGWVec><<<nb, kMCThreads, 0, st>>>(X, A, m, B, p.chunk, p.tiles1, p.upper, work, part);
+  else if (B >= kGWT)
+    gram_wide_kernel<kGWTFast><<<nb, kMCThreads, 0, st>>>(X, A, m, B, p.chunk, p.tiles1, p.upper, work, part);
   else
-    gram_wide_kernel<false><<<static_cast<unsigned>(blocks), kMCThreads, 0, st>>>(X, A, m, B, p.chunk, p.tiles1,
-                                                                                p.upper, work, static_cast<double*>(ws));
+    gram_wide_kernel<kGWRowFast><<<nb, kMCThreads, 0, st>>>(X, A, m, B, p.chunk, p.tiles1, p.upper, work, part);
   const unsigned g2 = static_cast<unsigned>(ceil_div(m * m * 16, 256));
   gram_wide_reduce<<<g2, 256, 0, st>>>(static_cast<const double*>(ws), p.nchunks, p.tiles1, m, out);
   return hipGetLastError();
