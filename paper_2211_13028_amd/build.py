@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librtucker.so")
 SOURCES = ["api.cpp", "k_basic.hip", "k_ttm.hip", "k_sketch.hip", "k_qr.hip", "k_eig.hip", "k_norm.hip",
-           "k_srht.hip"]
+           "k_srht.hip", "k_batch.hip"]
 
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-result",

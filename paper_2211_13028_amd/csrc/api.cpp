@@ -1062,8 +1062,10 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
   (void)xs;
   // ---- buffers and jobs
   std::vector<PrepTask> prep_sk, prep_core;
-  std::vector<GZwJob> zw;
+  std::vector<GZwJob> zw[4];  // by column class 4, 8, 12, 16 (index class / 4 - 1)
   std::vector<GTtmJob> tree, core[3], gttm[3], uttm[3];
+  std::vector<GTtmJob> core0[4];  // first core contraction on matrix cores, by 16-row tiles of M
+  int64_t core0_blocks[4] = {0, 0, 0, 0};
   std::vector<GQrJob> qr_hh, qr_fb;
   std::vector<GCholQRJob> qr_cq;
   int max_chunks = 1;
@@ -1071,7 +1073,7 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
   std::vector<GGramJob> gram[3];
   std::vector<GEigJob> eig[3];
   int64_t max_prep_sk = 1, max_prep_core = 1, max_cp = 1;
-  int64_t zw_blocks = 0, tree_blocks = 0, core_blocks[3] = {0, 0, 0}, g_blocks[3] = {0, 0, 0},
+  int64_t zw_blocks[4] = {0, 0, 0, 0}, tree_blocks = 0, core_blocks[3] = {0, 0, 0}, g_blocks[3] = {0, 0, 0},
           u_blocks[3] = {0, 0, 0};
   const int core_mt_first = tune.core_mt;
   for (int32_t i = 0; i < count; ++i) {
@@ -1088,10 +1090,12 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
     // first sketch level: Z = X x_3 Phi_3, W = X x_2 Phi_2 (one pass over X)
     float* Z = static_cast<float*>(c.take(static_cast<size_t>(I0) * I1 * t.s[2] * 4));
     float* W = static_cast<float*>(c.take(static_cast<size_t>(I0) * t.s[1] * I2 * 4));
-    const int64_t spb = std::max<int64_t>(1, std::min<int64_t>(8, I0 / 24));  // slabs per workgroup
-    zw.push_back(GZwJob{b.X, op[1], op[2], Z, W, I0, I1, I2, zw_blocks, static_cast<int32_t>(t.s[1]),
-                        static_cast<int32_t>(t.s[2]), static_cast<int32_t>(spb), 0});
-    zw_blocks += ceil_div(I0, spb);
+    // a workgroup takes 4 spb slabs (spb per wave)
+    const int64_t spb = std::max<int64_t>(1, std::min<int64_t>(4, I0 / 32));
+    const int zc = zw_batch_class(I2) / 4 - 1;
+    zw[zc].push_back(GZwJob{b.X, op[1], op[2], Z, W, I0, I1, I2, zw_blocks[zc], static_cast<int32_t>(t.s[1]),
+                            static_cast<int32_t>(t.s[2]), static_cast<int32_t>(spb), 0});
+    zw_blocks[zc] += ceil_div(I0, 4 * spb);
     // the three sketches: Y_1 = Z x_2 Phi_2, Y_2 = Z x_1 Phi_1, Y_3 = W x_1 Phi_1
     float* Y0 = static_cast<float*>(c.take(static_cast<size_t>(I0) * t.s[1] * t.s[2] * 4));
     float* Y1 = static_cast<float*>(c.take(static_cast<size_t>(t.s[0]) * I1 * t.s[2] * 4));
@@ -1143,10 +1147,18 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
       for (int q = 0; q < k; ++q) A *= dims[q];
       for (int q = k + 1; q < d; ++q) B *= dims[q];
       float* y = static_cast<float*>(c.take(static_cast<size_t>(A) * t.c[k] * B * 4));
-      const int mt = (stp == 0) ? core_mt_first : 16;
-      core[stp].push_back(GTtmJob{cur, cop, y, A, t.I[k], B, t.c[k], core_blocks[stp], ceil_div(A * B, kWave),
-                                  ceil_div(t.c[k], mt), 0, 0});
-      core_blocks[stp] += ttm_grouped_blocks(A, B, t.c[k], mt);
+      if (stp == 0 && (B == 1 || B >= 16)) {
+        // the pass over X: matrix-core kernel, jobs grouped by 16-row tiles of M
+        const int mc = static_cast<int>(ceil_div(t.c[k], 16)) - 1;
+        const int64_t units = ttm_batch_units(A, B);
+        core0[mc].push_back(GTtmJob{cur, cop, y, A, t.I[k], B, t.c[k], core0_blocks[mc], units, 0, 0, 0});
+        core0_blocks[mc] += ceil_div(units, 4);
+      } else {
+        const int mt = (stp == 0) ? core_mt_first : 16;
+        core[stp].push_back(GTtmJob{cur, cop, y, A, t.I[k], B, t.c[k], core_blocks[stp], ceil_div(A * B, kWave),
+                                    ceil_div(t.c[k], mt), 0, 0});
+        core_blocks[stp] += ttm_grouped_blocks(A, B, t.c[k], mt);
+      }
       dims[k] = t.c[k];
       cur = y;
     }
@@ -1184,11 +1196,22 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
     for (size_t j = 0; j < jobs.size(); ++j) m.insert(m.end(), jobs[j].colblocks * jobs[j].mtiles, static_cast<int32_t>(j));
     return m;
   };
-  std::vector<int32_t> zw_map;
-  for (size_t j = 0; j < zw.size(); ++j)
-    zw_map.insert(zw_map.end(), ceil_div(zw[j].A, zw[j].spb), static_cast<int32_t>(j));
+  std::vector<int32_t> zw_map[4];
+  for (int q = 0; q < 4; ++q)
+    for (size_t j = 0; j < zw[q].size(); ++j)
+      zw_map[q].insert(zw_map[q].end(), ceil_div(zw[q][j].A, 4 * zw[q][j].spb), static_cast<int32_t>(j));
   TableBuf tb;
-  const size_t o_psk = tb.add(prep_sk), o_zw = tb.add(zw), o_tree = tb.add(tree), o_cq = tb.add(qr_cq),
+  size_t o_zw[4], m_zw[4], o_c0[4], m_c0[4];
+  for (int q = 0; q < 4; ++q) {
+    o_zw[q] = tb.add(zw[q]);
+    m_zw[q] = tb.add(zw_map[q]);
+    std::vector<int32_t> cmap;
+    for (size_t j = 0; j < core0[q].size(); ++j)
+      cmap.insert(cmap.end(), ceil_div(core0[q][j].colblocks, 4), static_cast<int32_t>(j));
+    o_c0[q] = tb.add(core0[q]);
+    m_c0[q] = tb.add(cmap);
+  }
+  const size_t o_psk = tb.add(prep_sk), o_tree = tb.add(tree), o_cq = tb.add(qr_cq),
                o_hh = tb.add(qr_hh), o_fb = tb.add(qr_fb), o_pcore = tb.add(prep_core);
   size_t o_core[3], o_gram[3], o_eig[3], o_g[3], o_u[3];
   size_t m_core[3], m_g[3], m_u[3];
@@ -1205,7 +1228,7 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
     o_u[j] = tb.add(uttm[j]);
     m_u[j] = tb.add(ttm_map(uttm[j]));
   }
-  const size_t m_zw = tb.add(zw_map), m_tree = tb.add(ttm_map(tree));
+  const size_t m_tree = tb.add(ttm_map(tree));
   // the same workspace serves every row tile of the first core contraction: reserve the
   // map of the smallest tile (most workgroups)
   size_t worst = 0;
@@ -1221,7 +1244,9 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
   c.chk(launch_prep_grouped(reinterpret_cast<const PrepTask*>(at(o_psk)), static_cast<int>(prep_sk.size()),
                             max_prep_sk, st));
   auto imap = [&](size_t off) { return reinterpret_cast<const int32_t*>(at(off)); };
-  c.chk(launch_sketch_zw_grouped(reinterpret_cast<const GZwJob*>(at(o_zw)), imap(m_zw), count, zw_blocks, dtype, st));
+  for (int q = 0; q < 4; ++q)
+    c.chk(launch_zw_batch(reinterpret_cast<const GZwJob*>(at(o_zw[q])), imap(m_zw[q]), zw_blocks[q], 4 * (q + 1),
+                          dtype, st));
   c.chk(launch_ttm_grouped(reinterpret_cast<const GTtmJob*>(at(o_tree)), imap(m_tree), static_cast<int>(tree.size()),
                            tree_blocks, RT_F32, 8, st));
   c.chk(launch_cholqr2_grouped(reinterpret_cast<const GCholQRJob*>(at(o_cq)), static_cast<int>(qr_cq.size()),
@@ -1230,9 +1255,13 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
   c.chk(launch_qr_grouped(reinterpret_cast<const GQrJob*>(at(o_fb)), static_cast<int>(qr_fb.size()), RT_F32, st));
   c.chk(launch_prep_grouped(reinterpret_cast<const PrepTask*>(at(o_pcore)), static_cast<int>(prep_core.size()),
                             max_prep_core, st));
+  for (int q = 0; q < 4; ++q)
+    c.chk(launch_ttm_batch(reinterpret_cast<const GTtmJob*>(at(o_c0[q])), imap(m_c0[q]), core0_blocks[q], q + 1, dtype,
+                           st));
   for (int q = 0; q < 3; ++q)
-    c.chk(launch_ttm_grouped(reinterpret_cast<const GTtmJob*>(at(o_core[q])), imap(m_core[q]), count,
-                             core_blocks[q], q == 0 ? dtype : RT_F32, q == 0 ? core_mt_first : 16, st));
+    c.chk(launch_ttm_grouped(reinterpret_cast<const GTtmJob*>(at(o_core[q])), imap(m_core[q]),
+                             static_cast<int>(core[q].size()), core_blocks[q], q == 0 ? dtype : RT_F32,
+                             q == 0 ? core_mt_first : 16, st));
   c.chk(launch_copy_f64_grouped(reinterpret_cast<const GCopyJob*>(at(o_cp)), count, max_cp, st));
   for (int j = 0; j < 3; ++j) {
     c.chk(launch_gram_grouped(reinterpret_cast<const GGramJob*>(at(o_gram[j])), count, st));

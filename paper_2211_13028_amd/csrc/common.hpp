@@ -32,6 +32,18 @@ __device__ __forceinline__ float f8_to_f32(f8_t v) {
   return __uint_as_float(s | ((e + 120u) << 23) | (m << 20));
 }
 
+// ---------------------------------------------------------------- global address space
+// Pointers that a kernel reads from a job table in memory are generic to the compiler, so
+// its accesses through them become FLAT instructions, which count on the LDS counter as
+// well: every LDS wait then also waits for the loads in flight.  Casting to the global
+// address space gives global loads and stores.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> global_ptr(T* p) {
+  return (gptr<T>)(p);
+}
+
 template <typename T> struct Load;
 template <> struct Load<double> { __device__ static double get(const double* p, int64_t i) { return p[i]; } };
 template <> struct Load<float> { __device__ static float get(const float* p, int64_t i) { return p[i]; } };

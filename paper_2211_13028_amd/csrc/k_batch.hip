@@ -1,0 +1,387 @@
+// Streaming kernels of the batched decomposition (many small 3-way tensors, one
+// launch per step of Alg. 4.4 for the whole batch).
+//
+// First sketch level per tensor (the dimension-tree node of Sec. 4.4 that reads X):
+//   Z = X x_3 Phi_3  (I1 x I2 x s3)      W = X x_2 Phi_2  (I1 x s2 x I3)
+// in one pass over X.  A slab X[a] (P = I2 rows of Q = I3 contiguous values, Q <= 256)
+// is the unit of work; a 256-thread workgroup takes a run of slabs of one tensor and its
+// four waves take every fourth slab, independently (no barrier after the set-up).
+// A wave walks its slabs in steps of 16 rows:
+//  * lane (li, kg) = (lane % 16, lane / 16) loads rows pb + 4 t + kg (t < 4) at columns
+//    16 g + li (g < NG = ceil(Q / 16)): 16 lanes read 64 consecutive bytes of a row.  The
+//    next step's values are in flight while the current step is multiplied;
+//  * W^T accumulates on matrix cores with the loaded values as the B operand
+//    (A = Phi_2[c][p] of the lane's rows), one 16 x 16 tile per 16 columns;
+//  * Z needs the rows as the A operand: the step is staged 64 columns at a time in the
+//    wave's LDS area and read back row-wise; Phi_3 (zero-padded to 16 x 16 NG) sits in
+//    LDS for the whole workgroup.
+// Binary32 16x16x4 products for both input types (bfloat16 values widen exactly).
+// (Reading each 16-row block as one flat run, 64 consecutive elements per load, and
+// scattering it into an LDS tile read back for both products measured slower: 0.92 ms
+// against 0.63 ms for the 192-column class of the 512-tensor batch.)
+#include "kernels.hpp"
+
+namespace rt {
+
+namespace {
+
+typedef float bf32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBThreads = 256;
+constexpr int kBWaves = kBThreads / kWave;
+constexpr int kStageStride = 84;  // floats per staged row of 64 columns: = 20 mod 64, conflict-free
+                                  // row-wise reads (lane li reads row li) with at most 2-way
+                                  // conflicts on the column-wise stores
+
+// Phi_3 rows in LDS: 16 NG columns (a multiple of 64) + 20, the same residue as the stage
+__host__ __device__ constexpr int phi_stride(int ng) { return 16 * ng + 20; }
+
+template <typename TX>
+__device__ __forceinline__ float widen(TX v);
+template <>
+__device__ __forceinline__ float widen<float>(float v) { return v; }
+template <>
+__device__ __forceinline__ float widen<bf16_t>(bf16_t v) { return bf16_to_f32(v); }
+
+// two waves per SIMD up to 192 columns; the widest class keeps its registers at one
+template <typename TX, int NG>
+__global__ __launch_bounds__(kBThreads, NG > 12 ? 1 : 2) void zw_batch_kernel(const GZwJob* __restrict__ jobs,
+                                                               const int32_t* __restrict__ blkjob) {
+  constexpr int S = phi_stride(NG);
+  __shared__ float sPhi[16 * S];
+  __shared__ float sStage[kBWaves][16 * kStageStride];
+  const GZwJob J = jobs[blkjob[blockIdx.x]];
+  const int64_t P = J.P, Q = J.Q, A = J.A;
+  const int sP = J.sP, sQ = J.sQ;
+  const bool needZ = J.Z != nullptr, needW = J.W != nullptr;
+  // Phi_3 (sQ x Q) zero-padded to 16 x 16 NG; without Z it is never read
+  for (int idx = threadIdx.x; idx < 16 * S; idx += kBThreads) {
+    const int c = idx / S, q = idx - (idx / S) * S;
+    sPhi[idx] = (needZ && c < sQ && q < Q) ? global_ptr(J.phiQ)[static_cast<int64_t>(c) * Q + q] : 0.f;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x % kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int li = lane % 16, kg = lane / 16;
+  const int64_t local = blockIdx.x - J.blk0;
+  const int64_t a_first = local * kBWaves * J.spb + wave;
+  const int64_t a_end = (local + 1) * kBWaves * J.spb < A ? (local + 1) * kBWaves * J.spb : A;
+  if (a_first >= a_end) return;
+  const int steps = static_cast<int>((P + 15) / 16);
+  float* st = sStage[wave];
+  const gptr<const TX> X = global_ptr(static_cast<const TX*>(J.X));
+  const gptr<const float> phiP = global_ptr(J.phiP);
+  const gptr<float> Zo = global_ptr(J.Z), Wo = global_ptr(J.W);
+
+  // column offsets and masks of the lane, fixed for the tensor (loads clamp to column Q - 1)
+  uint32_t qoff[NG];
+  bool qok[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    const int q = 16 * g + li;
+    qok[g] = q < Q;
+    qoff[g] = static_cast<uint32_t>(q < Q ? q : Q - 1);
+  }
+  const int pc_lane = li < sP ? li : sP - 1;
+
+  // raw values of the next step (converted and masked when the step is taken over)
+  TX rn[4][NG];
+  float ppn[4];
+  auto load = [&](int64_t a, int64_t pb) {
+    const gptr<const TX> xa = X + a * P * Q;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t p = pb + 4 * t + kg;
+      const uint32_t prow = static_cast<uint32_t>((p < P ? p : P - 1) * Q);
+#pragma unroll
+      for (int g = 0; g < NG; ++g) rn[t][g] = xa[prow + qoff[g]];
+      ppn[t] = needW ? phiP[static_cast<int64_t>(pc_lane) * P + (p < P ? p : P - 1)] : 0.f;
+    }
+  };
+
+  bf32x4 wacc[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) wacc[g] = bf32x4{0.f, 0.f, 0.f, 0.f};
+  int64_t a = a_first;
+  int step = 0;
+  load(a, 0);
+  while (true) {
+    const int64_t pb = static_cast<int64_t>(step) * 16;
+    float r[4][NG], pp[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const bool pin = pb + 4 * t + kg < P;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) r[t][g] = (pin && qok[g]) ? widen<TX>(rn[t][g]) : 0.f;
+      pp[t] = (pin && li < sP) ? ppn[t] : 0.f;
+    }
+    // next step: the following row block, or the first block of the wave's next slab
+    const bool last_of_slab = step + 1 == steps;
+    const int64_t a_next = last_of_slab ? a + kBWaves : a;
+    const int step_next = last_of_slab ? 0 : step + 1;
+    if (a_next < a_end) load(a_next, static_cast<int64_t>(step_next) * 16);
+    if (needW) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int g = 0; g < NG; ++g) wacc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(pp[t], r[t][g], wacc[g], 0, 0, 0);
+    }
+    if (needZ) {
+      // four accumulators in turn: the products of a step do not wait for each other
+      bf32x4 zacc[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) zacc[u] = bf32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int cb = 0; cb < (NG + 3) / 4; ++cb) {
+        __builtin_amdgcn_wave_barrier();  // the previous block's reads of the stage stay above
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int gg = 0; gg < 4; ++gg)
+            if (4 * cb + gg < NG) st[(4 * t + kg) * kStageStride + 16 * gg + li] = r[t][4 * cb + gg];
+        __builtin_amdgcn_wave_barrier();  // cross-lane: stores before the reads below
+#pragma unroll
+        for (int kb = 0; kb < 16; ++kb) {
+          if (16 * cb + kb >= 4 * NG) break;  // compile-time
+          const float xv = st[li * kStageStride + 4 * kb + kg];
+          const float bq = sPhi[li * S + 64 * cb + 4 * kb + kg];
+          zacc[kb % 4] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv, bq, zacc[kb % 4], 0, 0, 0);
+        }
+      }
+      const bf32x4 z = (zacc[0] + zacc[1]) + (zacc[2] + zacc[3]);
+      if (li < sQ) {
+        const gptr<float> zo = Zo + (a * P + pb) * sQ + li;
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (pb + 4 * kg + v < P) zo[(4 * kg + v) * sQ] = z[v];
+      }
+    }
+    if (last_of_slab) {
+      if (needW) {
+        const gptr<float> wo = Wo + a * sP * Q;
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (4 * kg + v < sP && qok[g]) wo[(4 * kg + v) * Q + 16 * g + li] = wacc[g][v];
+          wacc[g] = bf32x4{0.f, 0.f, 0.f, 0.f};
+        }
+      }
+      a = a_next;
+      if (a >= a_end) break;
+    }
+    step = step_next;
+  }
+}
+
+// ------------------------------------------------------------------ first core contraction
+// Y = X x_k M (Y[a][i][b] = sum_c M[i][c] X[a][c][b], X viewed as (A, K, B), M: m x K with
+// m <= 16 MT) for every tensor of the batch, on binary32 matrix cores.  A wave owns one
+// unit; a workgroup takes four consecutive units of one job.
+//  * B >= 16 (a mode other than the last): unit = (a, 64 columns of b), all m rows.  Lane
+//    (li, kg) loads X[a][c][b0 + 16 j + li] (j < 4: 16 lanes read 64 consecutive bytes)
+//    for c = c0 + 4 s + kg as the B operand of four 16-column tiles; A = M[16 t + li][c].
+//    The next 16 c are in flight while the current 16 are multiplied.
+//  * B == 1 (the last mode): unit = 16 rows a, all m.  Each 64-wide block of c is read
+//    row by row with the lanes along c (256 consecutive bytes per row), staged in the
+//    wave's LDS area and read back as the A operand X[a0 + li][c]; B = M[16 t + li][c].
+constexpr int kTStage = 68;  // floats per staged row of 64 c: = 4 mod 64, conflict-free row reads
+
+template <typename TX, int MT>
+__global__ __launch_bounds__(kBThreads, 2) void ttm_batch_kernel(const GTtmJob* __restrict__ jobs,
+                                                                const int32_t* __restrict__ blkjob) {
+  __shared__ float sT[kBWaves][16 * kTStage];
+  const GTtmJob J = jobs[blkjob[blockIdx.x]];
+  const int lane = threadIdx.x % kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int li = lane % 16, kg = lane / 16;
+  const int64_t unit = (blockIdx.x - J.blk0) * kBWaves + wave;
+  if (unit >= J.colblocks) return;
+  const int64_t K = J.K, B = J.B, m = J.m;
+  const gptr<const TX> X = global_ptr(static_cast<const TX*>(J.X));
+  const gptr<const float> M = global_ptr(static_cast<const float*>(J.M));
+  const gptr<float> Y = global_ptr(static_cast<float*>(J.Y));
+  // M rows of the lane (clamped; rows past m are zeroed when used)
+  int64_t mrow[MT];
+  bool mok[MT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t) {
+    const int64_t i = 16 * t + li;
+    mok[t] = i < m;
+    mrow[t] = (i < m ? i : m - 1) * K;
+  }
+  if (B >= 16) {
+    const int64_t nb = (B + 63) / 64;
+    const int64_t a = unit / nb, b0 = (unit - a * nb) * 64;
+    const gptr<const TX> xa = X + a * K * B;
+    int64_t col[4];
+    bool bok[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t b = b0 + 16 * j + li;
+      bok[j] = b < B;
+      col[j] = b < B ? b : B - 1;
+    }
+    bf32x4 acc[MT][4];
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[t][j] = bf32x4{0.f, 0.f, 0.f, 0.f};
+    // c in chunks of 16 (four products of four c per tile); the next chunk's 16 X values
+    // and 4 MT M values per lane are in flight while the current chunk is multiplied
+    TX xn[4][4];
+    float mn[4][MT];
+    auto load = [&](int64_t c0) {
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int64_t c = c0 + 4 * s4 + kg;
+        const int64_t cc = c < K ? c : K - 1;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xn[s4][j] = xa[cc * B + col[j]];
+#pragma unroll
+        for (int t = 0; t < MT; ++t) mn[s4][t] = M[mrow[t] + cc];
+      }
+    };
+    load(0);
+    for (int64_t c0 = 0; c0 < K; c0 += 16) {
+      float xv[4][4], mv[4][MT];
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const bool cin = c0 + 4 * s4 + kg < K;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xv[s4][j] = (cin && bok[j]) ? widen<TX>(xn[s4][j]) : 0.f;
+#pragma unroll
+        for (int t = 0; t < MT; ++t) mv[s4][t] = (cin && mok[t]) ? mn[s4][t] : 0.f;
+      }
+      if (c0 + 16 < K) load(c0 + 16);
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+        for (int t = 0; t < MT; ++t)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(mv[s4][t], xv[s4][j], acc[t][j], 0, 0, 0);
+    }
+    // D[i = 4 kg + v][b = li] of tile (t, j)
+    const gptr<float> ya = Y + a * m * B;
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t i = 16 * t + 4 * kg + v;
+          if (i < m && bok[j]) ya[i * B + b0 + 16 * j + li] = acc[t][j][v];
+        }
+  } else {
+    // B == 1: rows a0 .. a0 + 15 of the A x K matrix X
+    const int64_t A = J.A;
+    const int64_t a0 = unit * 16;
+    float* st = sT[wave];
+    bf32x4 acc[MT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) acc[t] = bf32x4{0.f, 0.f, 0.f, 0.f};
+    TX xn[16];
+    auto load = [&](int64_t c0) {
+      const int64_t c = c0 + lane;
+      const int64_t cc = c < K ? c : K - 1;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int64_t a = a0 + i < A ? a0 + i : A - 1;
+        xn[i] = X[a * K + cc];
+      }
+    };
+    load(0);
+    for (int64_t c0 = 0; c0 < K; c0 += 64) {
+      const bool cin = c0 + lane < K;
+      float xv[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) xv[i] = (cin && a0 + i < A) ? widen<TX>(xn[i]) : 0.f;
+      if (c0 + 64 < K) load(c0 + 64);
+      __builtin_amdgcn_wave_barrier();  // the previous block's reads of the stage stay above
+#pragma unroll
+      for (int i = 0; i < 16; ++i) st[i * kTStage + lane] = xv[i];
+      __builtin_amdgcn_wave_barrier();  // cross-lane: stores before the reads below
+#pragma unroll 4
+      for (int kk = 0; kk < 64; kk += 4) {
+        const float av = st[li * kTStage + kk + kg];
+        const int64_t c = c0 + kk + kg;
+        const int64_t cc = c < K ? c : K - 1;
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+          const float bv = (c < K && mok[t]) ? M[mrow[t] + cc] : 0.f;
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[t], 0, 0, 0);
+        }
+      }
+    }
+    // D[a = a0 + 4 kg + v][i = 16 t + li]
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t a = a0 + 4 * kg + v, i = 16 * t + li;
+        if (a < A && i < m) Y[a * m + i] = acc[t][v];
+      }
+  }
+}
+
+}  // namespace
+
+int zw_batch_class(int64_t Q) {
+  const int ng = static_cast<int>((Q + 15) / 16);
+  return ng <= 4 ? 4 : ng <= 8 ? 8 : ng <= 12 ? 12 : 16;
+}
+
+hipError_t launch_zw_batch(const GZwJob* jobs, const int32_t* blkjob, int64_t total_blocks, int ng, rt_dtype xdt,
+                           hipStream_t st) {
+  if (total_blocks == 0) return hipSuccess;
+  const unsigned g = static_cast<unsigned>(total_blocks);
+#define RT_ZWB(TX, N) zw_batch_kernel<TX, N><<<g, kBThreads, 0, st>>>(jobs, blkjob)
+#define RT_ZWB_NG(TX)                 \
+  switch (ng) {                       \
+    case 4: RT_ZWB(TX, 4); break;     \
+    case 8: RT_ZWB(TX, 8); break;     \
+    case 12: RT_ZWB(TX, 12); break;   \
+    case 16: RT_ZWB(TX, 16); break;   \
+    default: return hipErrorInvalidValue; \
+  }
+  if (xdt == RT_F32) {
+    RT_ZWB_NG(float)
+  } else if (xdt == RT_BF16) {
+    RT_ZWB_NG(bf16_t)
+  } else {
+    return hipErrorInvalidValue;
+  }
+#undef RT_ZWB_NG
+#undef RT_ZWB
+  return hipGetLastError();
+}
+
+int64_t ttm_batch_units(int64_t A, int64_t B) { return B == 1 ? (A + 15) / 16 : A * ((B + 63) / 64); }
+
+hipError_t launch_ttm_batch(const GTtmJob* jobs, const int32_t* blkjob, int64_t total_blocks, int mt, rt_dtype xdt,
+                            hipStream_t st) {
+  if (total_blocks == 0) return hipSuccess;
+  const unsigned g = static_cast<unsigned>(total_blocks);
+#define RT_TB(TX, N) ttm_batch_kernel<TX, N><<<g, kBThreads, 0, st>>>(jobs, blkjob)
+#define RT_TB_MT(TX)                      \
+  switch (mt) {                           \
+    case 1: RT_TB(TX, 1); break;          \
+    case 2: RT_TB(TX, 2); break;          \
+    case 3: RT_TB(TX, 3); break;          \
+    case 4: RT_TB(TX, 4); break;          \
+    default: return hipErrorInvalidValue; \
+  }
+  if (xdt == RT_F32) {
+    RT_TB_MT(float)
+  } else if (xdt == RT_BF16) {
+    RT_TB_MT(bf16_t)
+  } else {
+    return hipErrorInvalidValue;
+  }
+#undef RT_TB_MT
+#undef RT_TB
+  return hipGetLastError();
+}
+
+}  // namespace rt

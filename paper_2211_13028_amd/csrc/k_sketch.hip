@@ -440,168 +440,6 @@ __global__ __launch_bounds__(kZWThreads) __attribute__((amdgpu_waves_per_eu(3)))
   }
 }
 
-// grouped form on matrix cores: one wave per run of `spb` slabs X[a] of a job, all rows and all
-// Q <= 256 columns (arbitrary P and Q, element loads with bounds), binary32 MFMA
-// (bfloat16 data is widened exactly; its products are exact in binary32).  Per
-// 16-row step, lane (li, kg) holds row 4 t + kg of each row quad t, columns
-// 64 cb + 4 li .. + 3 of each 64-column block cb: W^T accumulates with four MFMAs per
-// (quad, block); the rows are staged in LDS and read back as the A operand of Z.
-constexpr int kGStride = 260;  // floats per staged row: 256 + 4 padding
-
-template <typename TX>
-__global__ __launch_bounds__(kWave) void sketch_zw_grouped_mfma_kernel(const GZwJob* __restrict__ jobs,
-                                                                        const int32_t* __restrict__ blkjob) {
-  __shared__ float tile[16 * kGStride];
-  const int64_t blk = blockIdx.x;
-  const GZwJob J = jobs[blkjob[blk]];
-  const int64_t a_beg = (blk - J.blk0) * J.spb;
-  const int64_t a_end = (a_beg + J.spb < J.A) ? a_beg + J.spb : J.A;
-  for (int64_t a = a_beg; a < a_end; ++a) {
-    const int64_t P = J.P, Q = J.Q;
-    const int sP = J.sP, sQ = J.sQ;
-    const int lane = threadIdx.x;
-    const int li = lane % 16, kg = lane / 16;
-    const bool needZ = J.Z != nullptr, needW = J.W != nullptr;
-    const TX* xa = static_cast<const TX*>(J.X) + a * P * Q;
-    const int ncb = static_cast<int>((Q + 63) / 64);  // 64-column blocks in use (<= 4)
-    f32x4 wacc[4][4];
-#pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) wacc[cb][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float* zout = needZ ? J.Z + a * P * sQ : nullptr;
-    // bfloat16: loads carry no per-lane conditions.  An element past P or Q reads the last
-    // row or column instead and is replaced by zero after the load, so the loads of a block
-    // are issued together and waited for once (a condition per element put every load, and
-    // its widening, in a branch of its own with a wait of its own: 3.5 ms per pass instead
-    // of 2.2 ms in binary32).  Binary32 keeps the conditional element loads, which need
-    // fewer registers and measured faster there (6.0 ms for the batch against 6.7 ms).
-    constexpr bool kClamped = !std::is_same<TX, float>::value;
-    const int sPc = sP - 1, sQc = sQ - 1;
-    for (int64_t pb = 0; pb < P; pb += 16) {
-      f32x4 r[4][4];
-      if constexpr (!kClamped) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int64_t p = pb + 4 * t + kg;
-#pragma unroll
-          for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-              const int64_t q = 64 * cb + 4 * li + c;
-              r[t][cb][c] = (cb < ncb && p < P && q < Q) ? static_cast<float>(Load<TX>::get(xa, p * Q + q)) : 0.f;
-            }
-        }
-      } else {
-#pragma unroll
-      for (int cb = 0; cb < 4; ++cb) {
-        if (cb < ncb) {  // uniform
-          float v[4][4];
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int64_t p = pb + 4 * t + kg;
-            const int64_t pc = (p < P) ? p : P - 1;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-              const int64_t q = 64 * cb + 4 * li + c;
-              v[t][c] = static_cast<float>(Load<TX>::get(xa, pc * Q + ((q < Q) ? q : Q - 1)));
-            }
-          }
-#pragma unroll
-          for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-              r[t][cb][c] = (pb + 4 * t + kg < P && 64 * cb + 4 * li + c < Q) ? v[t][c] : 0.f;
-        } else {
-#pragma unroll
-          for (int t = 0; t < 4; ++t) r[t][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-        }
-      }
-      }
-      if (needW) {
-        float ppv[4];
-        if constexpr (kClamped) {
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int64_t p = pb + 4 * t + kg;
-            ppv[t] = J.phiP[static_cast<int64_t>(li < sP ? li : sPc) * P + ((p < P) ? p : P - 1)];
-          }
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int64_t p = pb + 4 * t + kg;
-          float pp;
-          if constexpr (kClamped)
-            pp = (p < P && li < sP) ? ppv[t] : 0.f;
-          else
-            pp = (p < P && li < sP) ? J.phiP[static_cast<int64_t>(li) * P + p] : 0.f;
-#pragma unroll
-          for (int cb = 0; cb < 4; ++cb)
-            if (cb < ncb) {
-#pragma unroll
-              for (int c = 0; c < 4; ++c)
-                wacc[cb][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(pp, r[t][cb][c], wacc[cb][c], 0, 0, 0);
-            }
-        }
-      }
-      if (needZ) {
-        __builtin_amdgcn_wave_barrier();  // the previous step's reads of the staging area stay above
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-          for (int cb = 0; cb < 4; ++cb)
-            if (cb < ncb) *reinterpret_cast<f32x4*>(tile + (4 * t + kg) * kGStride + 64 * cb + 4 * li) = r[t][cb];
-        __builtin_amdgcn_wave_barrier();  // cross-lane: stores before the reads below
-        f32x4 zacc = f32x4{0.f, 0.f, 0.f, 0.f};
-        for (int kb = 0; kb < 4 * ncb; ++kb) {
-          const f32x4 xr = *reinterpret_cast<const f32x4*>(tile + li * kGStride + 16 * kb + 4 * kg);
-          f32x4 bq;
-          if constexpr (kClamped) {
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-              const int64_t q = 16 * kb + 4 * kg + c;
-              bq[c] = J.phiQ[static_cast<int64_t>(li < sQ ? li : sQc) * Q + ((q < Q) ? q : Q - 1)];
-            }
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-              if (!(16 * kb + 4 * kg + c < Q && li < sQ)) bq[c] = 0.f;
-          } else {
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-              const int64_t q = 16 * kb + 4 * kg + c;
-              bq[c] = (q < Q && li < sQ) ? J.phiQ[static_cast<int64_t>(li) * Q + q] : 0.f;
-            }
-          }
-#pragma unroll
-          for (int c = 0; c < 4; ++c) zacc = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[c], bq[c], zacc, 0, 0, 0);
-        }
-        // D layout: row 4 kg + v of the step, column c = li
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t p = pb + 4 * kg + v;
-          if (p < P && li < sQ) zout[p * sQ + li] = zacc[v];
-        }
-      }
-    }
-    if (!needW) continue;
-    float* wout = J.W + a * sP * Q;
-#pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-      if (cb >= ncb) continue;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int cp = 4 * kg + v;
-        if (cp >= sP) continue;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int64_t q = 64 * cb + 4 * li + c;
-          if (q < Q) wout[static_cast<int64_t>(cp) * Q + q] = wacc[cb][c][v];
-        }
-      }
-    }
-  }
-}
-
 int nq_max(rt_dtype xdt) { return xdt == RT_F64 ? 4 : 8; }
 
 int pick_nq(rt_dtype xdt, int64_t Q) {
@@ -776,19 +614,6 @@ hipError_t launch_sketch_zw(const void* X, rt_dtype xdt, int64_t A, int64_t P, i
       sum_parts_kernel<float><<<g, 256, 0, st>>>(static_cast<const float*>(wdst), static_cast<int>(plan.pblocks), n,
                                                  static_cast<float*>(W));
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_sketch_zw_grouped(const GZwJob* jobs, const int32_t* blkjob, int count, int64_t total_blocks,
-                                    rt_dtype xdt, hipStream_t st) {
-  if (count == 0 || total_blocks == 0) return hipSuccess;
-  const unsigned g = static_cast<unsigned>(total_blocks);
-  if (xdt == RT_F32)
-    sketch_zw_grouped_mfma_kernel<float><<<g, kWave, 0, st>>>(jobs, blkjob);
-  else if (xdt == RT_BF16)
-    sketch_zw_grouped_mfma_kernel<bf16_t><<<g, kWave, 0, st>>>(jobs, blkjob);
-  else
-    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -230,8 +230,9 @@ int64_t ttm_grouped_blocks(int64_t A, int64_t B, int64_t m, int mt);
 hipError_t launch_ttm_grouped(const GTtmJob* jobs, const int32_t* blkjob, int count, int64_t total_blocks,
                               rt_dtype xdt, int mt, hipStream_t st);
 
-// k_sketch.hip: first sketch level (Z and W) per 3-way tensor (A, P, Q), one
-// one-wave workgroup per run of spb slabs; Q <= 256, s <= 16.  Operands binary32.
+// First sketch level (Z = X x_3 PhiQ: A x P x sQ, W = X x_2 PhiP: A x sP x Q) of one 3-way
+// tensor (A, P, Q) of a batch; Q <= 256, s <= 16, operands binary32; Z or W may be null.
+// Workgroups blk0 .. of the job each take a run of 4 spb slabs.
 struct GZwJob {
   const void* X;
   const float* phiP;
@@ -243,8 +244,20 @@ struct GZwJob {
   int32_t sP, sQ;
   int32_t spb, pad;
 };
-hipError_t launch_sketch_zw_grouped(const GZwJob* jobs, const int32_t* blkjob, int count, int64_t total_blocks,
-                                    rt_dtype xdt, hipStream_t st);
+// k_batch.hip: the same first sketch level for binary32 or bfloat16 tensors on 256-thread
+// workgroups (four waves, each walking every fourth slab of the workgroup's run of
+// 4 spb slabs), jobs grouped by column class ng = zw_batch_class(Q) in {4, 8, 12, 16}
+// (16 ng >= Q); every job of one launch has the launch's class.
+int zw_batch_class(int64_t Q);
+hipError_t launch_zw_batch(const GZwJob* jobs, const int32_t* blkjob, int64_t total_blocks, int ng, rt_dtype xdt,
+                           hipStream_t st);
+// k_batch.hip: the first core contraction of every tensor of a batch on matrix cores,
+// Y = X x_k M for (A, K, B) views with B == 1 or B >= 16, m <= 16 mt; binary32 or
+// bfloat16 X, binary32 M and Y.  A job has colblocks = ttm_batch_units(A, B) units (one
+// wave each), four per workgroup from blk0 on; blkjob maps workgroups to jobs.
+int64_t ttm_batch_units(int64_t A, int64_t B);
+hipError_t launch_ttm_batch(const GTtmJob* jobs, const int32_t* blkjob, int64_t total_blocks, int mt, rt_dtype xdt,
+                            hipStream_t st);
 
 // k_qr.hip: thin Householder QR of (A, m, B) views with m <= 256 rows and
 // n = A*B <= 64 columns, one workgroup per job; Q: m x qcols (qcols = min(m, n)).

@@ -50,7 +50,7 @@ def capped_modes(r, s, Ys):
 
 def check_item(Xseen, G, Us, r, s, phis, dtype):
     """One batch item against the oracle on the same Phi (the emulated-precision oracle
-    for bfloat16).  Uncapped items: |e_gpu - e_oracle| <= 1e-5.  Capped items: what the
+    for bfloat16).  Uncapped items: |e_gpu - e_oracle| <= 1e-5 (bfloat16: 3e-5).  Capped items: what the
     sketch determines, i.e. the projection onto range(U_n) of the leading q_n left singular
     vectors of the oracle's sketch, equal entry by entry to 1e-4, and the core equal to
     X x_k U_k^T for the device's own factors.  Returns True when the item was capped."""
@@ -68,7 +68,14 @@ def check_item(Xseen, G, Us, r, s, phis, dtype):
     assert np.isfinite(e_dev)
     cap = capped_modes(r, s, Ys)
     if not cap:
-        assert abs(e_dev - e_or) <= 1e-5, (e_dev, e_or)
+        # bfloat16: the columns of U_hat past the ranks follow the sketch's noise (here the
+        # rounding of X to bfloat16, about 2e-3 of each entry), and their bfloat16 roundings
+        # in the first core contraction enter e.  A relative change of the sketch of a few
+        # binary32 units (the device accumulates it in binary32, the oracle in binary64)
+        # moves e by up to about 1.2e-5 on items of this workload (emulated oracle, sketch
+        # perturbed by 32 units of 2^-24), so e is determined to that level only.
+        tol = 1e-5 if dtype == "f32" else 3e-5
+        assert abs(e_dev - e_or) <= tol, (e_dev, e_or)
         return False
     for n, q in cap.items():
         Sd = np.linalg.svd(Ys[n], full_matrices=False)[0][:, :q]
