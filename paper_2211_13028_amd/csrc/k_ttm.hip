@@ -193,7 +193,6 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMfmaThreads = 256;  // 4 waves, one 128-column unit each
 constexpr int kUnitCols = 128;
-constexpr bool kPrefetchF32 = true;  // binary32 kernel: next k block loaded during the products
 
 // Work unit = (a, 128-column chunk, k-split part).  Y (or a split-K partial) is
 // written for rows i < m only.
@@ -201,7 +200,7 @@ constexpr bool kPrefetchF32 = true;  // binary32 kernel: next k block loaded dur
 // TAIL > 0 (with VM): rows 16 MT .. 16 MT + TAIL - 1 of M are not a whole 16-row matrix-core
 // tile, and are multiplied on the vector ALU from the X values the lane already holds
 // (m = 49 = 3 x 16 + 1 would otherwise pad a fourth tile: 31 % more matrix-core work).
-template <int MT, bool VM, int TAIL = 0>
+template <int MT, bool VM, int TAIL = 0, int DEPTH = 3>
 __device__ __forceinline__ void ttm_f32_unit(const float* __restrict__ X, int64_t A, int64_t K, int64_t B,
                                              const float* __restrict__ Mop, int64_t m, int64_t chunks, int ksplit,
                                              int64_t kper, float* __restrict__ Y, int64_t unit) {
@@ -235,19 +234,22 @@ __device__ __forceinline__ void ttm_f32_unit(const float* __restrict__ X, int64_
   // output columns that are not stored).
   const int64_t c0off = colok0 ? b0 + 4 * j : b0, c1off = colok1 ? b0 + 64 + 4 * j : b0;
   const f32x4 zero4 = f32x4{0.f, 0.f, 0.f, 0.f};
-  f32x4 n0[4], n1[4];
-  float nw[MT][4];
-  f32x4 ntw[TAIL > 0 ? TAIL : 1];
+  // DEPTH blocks in flight: set P holds the block DEPTH steps ahead of the one multiplied
+  static_assert(DEPTH >= 1 && DEPTH <= 3, "one to three blocks ahead");
+  f32x4 n0[DEPTH][4], n1[DEPTH][4];
+  float nw[DEPTH][MT][4];
+  f32x4 ntw[DEPTH][TAIL > 0 ? TAIL : 1];
   f32x4 tacc[TAIL > 0 ? TAIL : 1][2];
 #pragma unroll
   for (int r = 0; r < TAIL; ++r) tacc[r][0] = tacc[r][1] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const auto load_block = [&](int64_t k0) {
+  const auto load_block = [&](int64_t k0, auto Pc) {
+    constexpr int P = decltype(Pc)::value;
     const int64_t kl = k0 + 4 * q;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int64_t kc = (kl + s < kend) ? kl + s : kend - 1;
-      n0[s] = *reinterpret_cast<const f32x4*>(xa + kc * B + c0off);
-      n1[s] = *reinterpret_cast<const f32x4*>(xa + kc * B + c1off);
+      n0[P][s] = *reinterpret_cast<const f32x4*>(xa + kc * B + c0off);
+      n1[P][s] = *reinterpret_cast<const f32x4*>(xa + kc * B + c1off);
     }
     if constexpr (VM) {
       // kl is a multiple of 4, so kl < kend <= K gives kl <= K - 4; a block past K reads
@@ -257,19 +259,19 @@ __device__ __forceinline__ void ttm_f32_unit(const float* __restrict__ X, int64_
       for (int mt = 0; mt < MT; ++mt) {
         const f32x4 v = *reinterpret_cast<const f32x4*>(Mop + (mt * 16 + j) * K + km);
 #pragma unroll
-        for (int s = 0; s < 4; ++s) nw[mt][s] = v[s];
+        for (int s = 0; s < 4; ++s) nw[P][mt][s] = v[s];
       }
 #pragma unroll
-      for (int r = 0; r < TAIL; ++r) ntw[r] = *reinterpret_cast<const f32x4*>(Mop + (MT * 16 + r) * K + km);
+      for (int r = 0; r < TAIL; ++r) ntw[P][r] = *reinterpret_cast<const f32x4*>(Mop + (MT * 16 + r) * K + km);
     } else {
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int s = 0; s < 4; ++s) nw[mt][s] = Mop[(mt * 16 + j) * K + ((kl + s < kend) ? kl + s : kend - 1)];
+        for (int s = 0; s < 4; ++s) nw[P][mt][s] = Mop[(mt * 16 + j) * K + ((kl + s < kend) ? kl + s : kend - 1)];
     }
   };
-  if (kbeg < kend) load_block(kbeg);
-  for (int64_t k0 = kbeg; k0 < kend; k0 += 16) {
+  const auto block = [&](int64_t k0, auto Pc) {
+    constexpr int P = decltype(Pc)::value;
     f32x4 y0[4], y1[4];
     float w[4][MT];
     f32x4 tw[TAIL > 0 ? TAIL : 1];
@@ -277,17 +279,17 @@ __device__ __forceinline__ void ttm_f32_unit(const float* __restrict__ X, int64_
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const bool kin = kl + s < kend;
-      y0[s] = kin ? n0[s] : zero4;
-      y1[s] = kin ? n1[s] : zero4;
+      y0[s] = kin ? n0[P][s] : zero4;
+      y1[s] = kin ? n1[P][s] : zero4;
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) w[s][mt] = kin ? nw[mt][s] : 0.f;
+      for (int mt = 0; mt < MT; ++mt) w[s][mt] = kin ? nw[P][mt][s] : 0.f;
     }
 #pragma unroll
-    for (int r = 0; r < TAIL; ++r) tw[r] = ntw[r];
-    // the next block's loads go out before this block's products (the scheduler may
-    // move neither the operand take-over below them nor them into the products)
+    for (int r = 0; r < TAIL; ++r) tw[r] = ntw[P][r];
+    // the block DEPTH steps ahead goes out before this block's products (the scheduler may
+    // move neither the operand take-over below it nor it into the products)
     __builtin_amdgcn_sched_barrier(0);
-    if (kPrefetchF32) load_block(k0 + 16);  // past kend: rows kend - 1 again, never used
+    load_block(k0 + 16 * DEPTH, Pc);  // past kend: rows kend - 1 again, never used
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -311,7 +313,33 @@ __device__ __forceinline__ void ttm_f32_unit(const float* __restrict__ X, int64_
           tacc[r][0][c] = fmaf(tw[r][s], y0[s][c], tacc[r][0][c]);
           tacc[r][1][c] = fmaf(tw[r][s], y1[s][c], tacc[r][1][c]);
         }
-    if (!kPrefetchF32 && k0 + 16 < kend) load_block(k0 + 16);
+  };
+  using P0 = std::integral_constant<int, 0>;
+  using P1 = std::integral_constant<int, 1>;
+  using P2 = std::integral_constant<int, 2>;
+  if constexpr (DEPTH == 3) {
+    if (kbeg < kend) {
+      load_block(kbeg, P0{});
+      load_block(kbeg + 16, P1{});
+      load_block(kbeg + 32, P2{});
+    }
+    for (int64_t k0 = kbeg; k0 < kend; k0 += 48) {
+      block(k0, P0{});
+      if (k0 + 16 < kend) block(k0 + 16, P1{});
+      if (k0 + 32 < kend) block(k0 + 32, P2{});
+    }
+  } else if constexpr (DEPTH == 2) {
+    if (kbeg < kend) {
+      load_block(kbeg, P0{});
+      load_block(kbeg + 16, P1{});
+    }
+    for (int64_t k0 = kbeg; k0 < kend; k0 += 32) {
+      block(k0, P0{});
+      if (k0 + 16 < kend) block(k0 + 16, P1{});
+    }
+  } else {
+    if (kbeg < kend) load_block(kbeg, P0{});
+    for (int64_t k0 = kbeg; k0 < kend; k0 += 16) block(k0, P0{});
   }
   float* ya = Y + (static_cast<int64_t>(ks) * A + a) * m * B;
   // tail rows: the four lane groups q hold the partial sums of k = 4 q + s of every block;
@@ -371,7 +399,7 @@ __global__ __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(2)
   static_assert(MT <= 3, "four tiles do not fit two waves per SIMD");
   const int64_t unit = static_cast<int64_t>(blockIdx.x) * (kMfmaThreads / kWave) + threadIdx.x / kWave;
   if (unit >= A * chunks * ksplit) return;
-  ttm_f32_unit<MT, VM, TAIL>(X, A, K, B, Mop, m, chunks, ksplit, kper, Y, unit);
+  ttm_f32_unit<MT, VM, TAIL, 1>(X, A, K, B, Mop, m, chunks, ksplit, kper, Y, unit);
 }
 
 // Independent binary32 contractions of one shape class in one launch: job q owns the
