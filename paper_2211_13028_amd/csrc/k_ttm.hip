@@ -11,6 +11,8 @@
 //    output tile (m padded to a multiple of 16) and streams X rows once; the
 //    prepared M operand is read from L2.  bfloat16 operands are re-packed in
 //    registers so that each lane holds 8 consecutive k of one column.
+#include <utility>
+
 #include "kernels.hpp"
 
 namespace rt {
@@ -200,6 +202,12 @@ constexpr int kUnitCols = 128;
 // TAIL > 0 (with VM): rows 16 MT .. 16 MT + TAIL - 1 of M are not a whole 16-row matrix-core
 // tile, and are multiplied on the vector ALU from the X values the lane already holds
 // (m = 49 = 3 x 16 + 1 would otherwise pad a fourth tile: 31 % more matrix-core work).
+// f(integral_constant<int, I>) for I = 0, 1, ... in order
+template <class F, int... I>
+__device__ __forceinline__ void for_each_index(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+
 template <int MT, bool VM, int TAIL = 0, int DEPTH = 3>
 __device__ __forceinline__ void ttm_f32_unit(const float* __restrict__ X, int64_t A, int64_t K, int64_t B,
                                              const float* __restrict__ Mop, int64_t m, int64_t chunks, int ksplit,
@@ -235,7 +243,7 @@ __device__ __forceinline__ void ttm_f32_unit(const float* __restrict__ X, int64_
   const int64_t c0off = colok0 ? b0 + 4 * j : b0, c1off = colok1 ? b0 + 64 + 4 * j : b0;
   const f32x4 zero4 = f32x4{0.f, 0.f, 0.f, 0.f};
   // DEPTH blocks in flight: set P holds the block DEPTH steps ahead of the one multiplied
-  static_assert(DEPTH >= 1 && DEPTH <= 3, "one to three blocks ahead");
+  static_assert(DEPTH >= 1 && DEPTH <= 4, "one to four blocks ahead (four measured slower than three: registers)");
   f32x4 n0[DEPTH][4], n1[DEPTH][4];
   float nw[DEPTH][MT][4];
   f32x4 ntw[DEPTH][TAIL > 0 ? TAIL : 1];
@@ -314,33 +322,15 @@ __device__ __forceinline__ void ttm_f32_unit(const float* __restrict__ X, int64_
           tacc[r][1][c] = fmaf(tw[r][s], y1[s][c], tacc[r][1][c]);
         }
   };
-  using P0 = std::integral_constant<int, 0>;
-  using P1 = std::integral_constant<int, 1>;
-  using P2 = std::integral_constant<int, 2>;
-  if constexpr (DEPTH == 3) {
-    if (kbeg < kend) {
-      load_block(kbeg, P0{});
-      load_block(kbeg + 16, P1{});
-      load_block(kbeg + 32, P2{});
-    }
-    for (int64_t k0 = kbeg; k0 < kend; k0 += 48) {
-      block(k0, P0{});
-      if (k0 + 16 < kend) block(k0 + 16, P1{});
-      if (k0 + 32 < kend) block(k0 + 32, P2{});
-    }
-  } else if constexpr (DEPTH == 2) {
-    if (kbeg < kend) {
-      load_block(kbeg, P0{});
-      load_block(kbeg + 16, P1{});
-    }
-    for (int64_t k0 = kbeg; k0 < kend; k0 += 32) {
-      block(k0, P0{});
-      if (k0 + 16 < kend) block(k0 + 16, P1{});
-    }
-  } else {
-    if (kbeg < kend) load_block(kbeg, P0{});
-    for (int64_t k0 = kbeg; k0 < kend; k0 += 16) block(k0, P0{});
-  }
+  constexpr auto sets = std::make_integer_sequence<int, DEPTH>{};
+  if (kbeg < kend) for_each_index([&](auto Pc) { load_block(kbeg + 16 * decltype(Pc)::value, Pc); }, sets);
+  for (int64_t k0 = kbeg; k0 < kend; k0 += 16 * DEPTH)
+    for_each_index(
+        [&](auto Pc) {
+          const int64_t kb = k0 + 16 * decltype(Pc)::value;
+          if (kb < kend) block(kb, Pc);
+        },
+        sets);
   float* ya = Y + (static_cast<int64_t>(ks) * A + a) * m * B;
   // tail rows: the four lane groups q hold the partial sums of k = 4 q + s of every block;
   // add them in a fixed order (lane j collects groups 0..3) and store from group 0
