@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 #include "../../include/rtucker.h"
 
 namespace rt {
@@ -42,6 +44,12 @@ using gptr = __attribute__((address_space(1))) T*;
 template <typename T>
 __device__ __forceinline__ gptr<T> global_ptr(T* p) {
   return (gptr<T>)(p);
+}
+
+// f(integral_constant<int, I>) for I = 0, 1, ... in order
+template <class F, int... I>
+__device__ __forceinline__ void for_each_index(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
 }
 
 template <typename T> struct Load;

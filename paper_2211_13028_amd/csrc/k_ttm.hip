@@ -11,8 +11,6 @@
 //    output tile (m padded to a multiple of 16) and streams X rows once; the
 //    prepared M operand is read from L2.  bfloat16 operands are re-packed in
 //    registers so that each lane holds 8 consecutive k of one column.
-#include <utility>
-
 #include "kernels.hpp"
 
 namespace rt {
@@ -202,12 +200,6 @@ constexpr int kUnitCols = 128;
 // TAIL > 0 (with VM): rows 16 MT .. 16 MT + TAIL - 1 of M are not a whole 16-row matrix-core
 // tile, and are multiplied on the vector ALU from the X values the lane already holds
 // (m = 49 = 3 x 16 + 1 would otherwise pad a fourth tile: 31 % more matrix-core work).
-// f(integral_constant<int, I>) for I = 0, 1, ... in order
-template <class F, int... I>
-__device__ __forceinline__ void for_each_index(F&& f, std::integer_sequence<int, I...>) {
-  (f(std::integral_constant<int, I>{}), ...);
-}
-
 template <int MT, bool VM, int TAIL = 0, int DEPTH = 3>
 __device__ __forceinline__ void ttm_f32_unit(const float* __restrict__ X, int64_t A, int64_t K, int64_t B,
                                              const float* __restrict__ Mop, int64_t m, int64_t chunks, int ksplit,
