@@ -546,8 +546,15 @@ def run_extras(rt, synth, torch, dev, time_steps, log):
     # recomputation (2 passes); R written and read 4 times; X_hat, P R and dX written once each
     nbytes = X3.numel() * 4
     alg = nbytes * (2 + 2) + nbytes * (1 + 4) + nbytes * 3
+    # the same step recorded once in a graph and replayed (no Python or launch overhead)
+    log("timing the 256^3 projection loss as a captured graph ...")
+    graph, _ = RA.capture_projection_step(X3, U3)
+    ms_g = time_steps(graph.replay, 20, 3)
     out["projection_loss_256^3_f32"] = {"ms": round(ms, 4), "alg_bytes": alg, "GB/s": round(alg / ms / 1e6, 1),
-                                        "hbm_frac": round(alg / ms / 1e6 / (HBM_PEAK / 1e9), 4)}
+                                        "hbm_frac": round(alg / ms / 1e6 / (HBM_PEAK / 1e9), 4),
+                                        "graph_ms": round(ms_g, 4),
+                                        "graph_hbm_frac": round(alg / ms_g / 1e6 / (HBM_PEAK / 1e9), 4)}
+    del graph
     del X3, U3
     torch.cuda.empty_cache()
     # ---- 512 tensors, dims U{32..192}^3, ranks U{4..16}^3, p = 4, grouped launches
@@ -563,7 +570,7 @@ def run_extras(rt, synth, torch, dev, time_steps, log):
     for tag, Xs in (("f32", X32), ("bf16", [rt.rtucker_convert(x, torch.bfloat16) for x in X32])):
         B = rt.Batch(Xs, ranks, 4, php)
         B.run()
-        mt = B.autotune()
+        mt, spb = B.autotune()
         B.upload()
         log(f"timing the 512-tensor batch {tag} ...")
         ms = time_steps(B.launch, 10, 2)
@@ -573,6 +580,7 @@ def run_extras(rt, synth, torch, dev, time_steps, log):
         out[f"batch512_{tag}"] = {"ms": round(ms, 4), "tensors_per_s": round(count / (ms / 1e3), 1),
                                   "alg_bytes": alg, "GB/s": round(alg / ms / 1e6, 1),
                                   "hbm_frac": round(alg / ms / 1e6 / (HBM_PEAK / 1e9), 4), "core_row_tile": mt,
+                                  "sketch_slabs_per_wave": spb,
                                   "max_rel_err_sampled": max(errs)}
         del B
     return out

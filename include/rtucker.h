@@ -351,11 +351,22 @@ int rtucker_scaled_diff(const rt_tensor* A, const void* B, const double* g, doub
  * rtucker_decompose_batched_launch: only enqueues the kernels, reading the
  *  tables left in ws by an upload with the same arguments.  It copies nothing
  *  from the host and allocates nothing, so it can be captured in a graph.
- * rtucker_decompose_batched_autotune: times the whole batch for each row tile
- *  of the first core contraction (8, 16, 32 rows), keeps the fastest for this
- *  batch signature (sizes, ranks, subranks, p, dtype) for the rest of the
- *  process, writes it to *chosen (nullable), and leaves the matching tables in ws.
- *  It synchronises `stream`. */
+ * rtucker_decompose_batched_autotune: times the whole batch for each pair of a
+ *  row tile of the vector-ALU core contractions (8, 16, 32 rows) and a number of
+ *  slabs that a wave of the sketch pass takes in turn (at most 1, 2 or 4), keeps
+ *  the fastest for this batch signature (sizes, ranks, subranks, p, dtype) for the
+ *  rest of the process, writes chosen[0] = row tile and chosen[1] = slabs
+ *  (chosen: nullable, 2 int32), and leaves the matching tables in ws.  It
+ *  synchronises `stream`.  When the environment variable RTUCKER_TUNE_CACHE names
+ *  a file, the choice is also appended to it ("<signature key, 16 hex digits>
+ *  <row tile> <slabs>" per line), and every batched call of a process that has the
+ *  variable set reads the file once per path before it looks a signature up, so a
+ *  later process starts tuned; lines that do not parse are skipped.  The slabs
+ *  setting does not change any result; the row tile changes the summation order
+ *  of the vector-ALU contractions only.
+ * rtucker_decompose_batched_tuning: host only; the setting the batched calls would
+ *  use now for this signature (the cache, else the defaults 16 and 4): tuning[0] =
+ *  row tile, tuning[1] = slabs, and *key = the signature key of the cache file. */
 typedef struct {
   const void* X;
   int64_t dims[3];
@@ -377,6 +388,8 @@ int rtucker_decompose_batched_launch(int32_t count, const rt_batch_item* items, 
 int rtucker_decompose_batched_autotune(int32_t count, const rt_batch_item* items, int32_t p,
                                        rt_dtype dtype, void* ws, size_t ws_bytes, void* stream,
                                        int32_t* chosen);
+int rtucker_decompose_batched_tuning(int32_t count, const rt_batch_item* items, int32_t p, rt_dtype dtype,
+                                     int32_t* tuning, uint64_t* key);
 
 #ifdef __cplusplus
 }

@@ -106,6 +106,8 @@ _SIGS = {
     "rtucker_decompose_batched_autotune": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
                                                           ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
                                                           ctypes.c_void_p, ctypes.c_void_p]),
+    "rtucker_decompose_batched_tuning": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                                                        ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -566,6 +568,16 @@ def make_batch_items(Xs, ranks, phis, Gs, Us, s=None):
     return items
 
 
+def batched_tuning(items, count: int, p: int, dtype: int):
+    """Host query: (row tile, slabs per wave, signature key) that the batched calls would use
+    for these items now (the tuning cache, else the defaults)."""
+    tun = (ctypes.c_int32 * 2)()
+    key = ctypes.c_uint64()
+    _check(lib().rtucker_decompose_batched_tuning(int(count), items, int(p), int(dtype), tun, ctypes.byref(key)),
+           "rtucker_decompose_batched_tuning")
+    return int(tun[0]), int(tun[1]), int(key.value)
+
+
 def rtucker_decompose_batched(Xs, ranks, p, phis, s=None, Gs=None, Us=None, ws=None):
     """Factor-reuse decomposition of many 3-way tensors (one dtype: float32 or bfloat16)."""
     torch = _torch()
@@ -628,11 +640,15 @@ class Batch:
         _check(lib().rtucker_decompose_batched_launch(*self._args()), "rtucker_decompose_batched_launch")
         return self.Gs, self.Us
 
-    def autotune(self) -> int:
-        chosen = ctypes.c_int32()
-        _check(lib().rtucker_decompose_batched_autotune(*self._args(), ctypes.byref(chosen)),
-               "rtucker_decompose_batched_autotune")
-        return int(chosen.value)
+    def autotune(self):
+        """Time every setting, keep the fastest; returns (row tile, slabs per wave)."""
+        chosen = (ctypes.c_int32 * 2)()
+        _check(lib().rtucker_decompose_batched_autotune(*self._args(), chosen), "rtucker_decompose_batched_autotune")
+        return int(chosen[0]), int(chosen[1])
+
+    def tuning(self):
+        """The setting the batched calls use now: (row tile, slabs per wave, signature key)."""
+        return batched_tuning(self.items, len(self.Xs), self.p, self.dt)
 
     def capture(self):
         """A torch CUDA graph whose replay runs ``launch`` (the tables must be uploaded)."""

@@ -12,6 +12,10 @@ C ABI; these classes only order the calls.
 * ``ProjectionLoss`` -- L = ||X - (X x_k U_k^T) x_k U_k||^2, the Tucker
   reconstruction loss with fixed factors, with its whole backward pass fused
   into library calls (no gradient is summed outside the kernels).
+* ``capture_projection_step`` -- one forward + backward of that loss recorded in a
+  CUDA (HIP) graph: the library's calls neither synchronise nor copy to the host,
+  so a replay re-runs every kernel of the step without the Python and launch
+  overhead of about 60 calls.
 """
 from __future__ import annotations
 
@@ -164,3 +168,29 @@ def sq_residual(A, B):
 def projection_loss(X, Us):
     """Differentiable ||X - (X x_k U_k^T) x_k U_k||^2 (float64 scalar)."""
     return ProjectionLoss.apply(X, *Us)
+
+
+def capture_projection_step(X, Us, warmup: int = 2):
+    """Record one forward + backward of ``projection_loss(X, Us)`` in a CUDA graph.
+
+    X and the U_k are static tensors (requires_grad set as wanted).  Returns
+    ``(graph, loss)``: each ``graph.replay()`` recomputes ``loss`` and rewrites
+    X.grad and U_k.grad in place (the gradients are allocated inside the graph, so
+    they are overwritten, not accumulated).  The warm-up runs on a side stream of
+    default priority, as graph capture requires."""
+    ts = [X, *Us]
+    side = torch.cuda.Stream(device=X.device)
+    side.wait_stream(torch.cuda.current_stream(X.device))
+    with torch.cuda.stream(side):
+        for _ in range(warmup):
+            for t in ts:
+                t.grad = None
+            projection_loss(X, Us).backward()
+    torch.cuda.current_stream(X.device).wait_stream(side)
+    for t in ts:
+        t.grad = None
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        loss = projection_loss(X, Us)
+        loss.backward()
+    return graph, loss

@@ -8,10 +8,13 @@
 // what the live call consumes.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <map>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "kernels.hpp"
@@ -997,18 +1000,24 @@ int plan_mode_contract(Ctx& c, const rt_tensor* P, const rt_tensor* Q, int32_t n
 // launch-only mode uses tables already in place, so it performs no host-device
 // copies and can be captured in a graph.
 struct BatchTune {
-  int core_mt = 16;    // row tile of the first core contraction (8, 16 or 32)
+  int core_mt = 16;  // row tile of the vector-ALU core contractions (8, 16 or 32)
+  int spb_cap = 4;   // most slabs a wave of the sketch pass takes in turn (1, 2 or 4)
 };
 
 enum class BatchMode { kFull, kUploadOnly, kLaunchOnly };
 
+// Job tables, packed at 256-byte boundaries.  `bound` is the size the tables can take under
+// any tuning (a map whose length depends on the tuning counts at its longest), so the
+// workspace, which the tables open, does not depend on the tuning.
 struct TableBuf {
   std::vector<unsigned char> bytes;
+  size_t bound = 0;
   template <typename T>
-  size_t add(const std::vector<T>& v) {
+  size_t add(const std::vector<T>& v, size_t max_count = 0) {
     const size_t off = align256(bytes.size());
     bytes.resize(off + v.size() * sizeof(T));
     if (!v.empty()) std::memcpy(bytes.data() + off, v.data(), v.size() * sizeof(T));
+    bound += align256((max_count > v.size() ? max_count : v.size()) * sizeof(T));
     return off;
   }
 };
@@ -1018,6 +1027,7 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
   if (count < 1 || !items || p < 0) return RT_EINVAL;
   if (dtype != RT_F32 && dtype != RT_BF16) return RT_EDTYPE;
   if (tune.core_mt != 8 && tune.core_mt != 16 && tune.core_mt != 32) return RT_EINVAL;
+  if (tune.spb_cap != 1 && tune.spb_cap != 2 && tune.spb_cap != 4) return RT_EINVAL;
   const int d = 3;
   struct It {
     int64_t I[3], s[3], c[3];
@@ -1091,7 +1101,7 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
     float* Z = static_cast<float*>(c.take(static_cast<size_t>(I0) * I1 * t.s[2] * 4));
     float* W = static_cast<float*>(c.take(static_cast<size_t>(I0) * t.s[1] * I2 * 4));
     // a workgroup takes 4 spb slabs (spb per wave)
-    const int64_t spb = std::max<int64_t>(1, std::min<int64_t>(4, I0 / 32));
+    const int64_t spb = std::max<int64_t>(1, std::min<int64_t>(tune.spb_cap, I0 / 32));
     const int zc = zw_batch_class(I2) / 4 - 1;
     zw[zc].push_back(GZwJob{b.X, op[1], op[2], Z, W, I0, I1, I2, zw_blocks[zc], static_cast<int32_t>(t.s[1]),
                             static_cast<int32_t>(t.s[2]), static_cast<int32_t>(spb), 0});
@@ -1204,7 +1214,9 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
   size_t o_zw[4], m_zw[4], o_c0[4], m_c0[4];
   for (int q = 0; q < 4; ++q) {
     o_zw[q] = tb.add(zw[q]);
-    m_zw[q] = tb.add(zw_map[q]);
+    size_t most = 0;  // one slab per wave
+    for (const GZwJob& j : zw[q]) most += static_cast<size_t>(ceil_div(j.A, 4));
+    m_zw[q] = tb.add(zw_map[q], most);
     std::vector<int32_t> cmap;
     for (size_t j = 0; j < core0[q].size(); ++j)
       cmap.insert(cmap.end(), ceil_div(core0[q][j].colblocks, 4), static_cast<int32_t>(j));
@@ -1217,7 +1229,9 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
   size_t m_core[3], m_g[3], m_u[3];
   for (int q = 0; q < 3; ++q) {
     o_core[q] = tb.add(core[q]);
-    m_core[q] = tb.add(ttm_map(core[q]));
+    size_t most = 0;  // the first contraction's smallest row tile (8) has the most workgroups
+    for (const GTtmJob& j : core[q]) most += static_cast<size_t>(j.colblocks * (q == 0 ? ceil_div(j.m, 8) : j.mtiles));
+    m_core[q] = tb.add(ttm_map(core[q]), most);
   }
   const size_t o_cp = tb.add(cp);
   for (int j = 0; j < 3; ++j) {
@@ -1229,11 +1243,7 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
     m_u[j] = tb.add(ttm_map(uttm[j]));
   }
   const size_t m_tree = tb.add(ttm_map(tree));
-  // the same workspace serves every row tile of the first core contraction: reserve the
-  // map of the smallest tile (most workgroups)
-  size_t worst = 0;
-  for (const GTtmJob& j : core[0]) worst += static_cast<size_t>(j.colblocks * (ceil_div(j.m, 8) - j.mtiles)) * 4;
-  char* tables = static_cast<char*>(c.take(tb.bytes.size() + align256(worst)));
+  char* tables = static_cast<char*>(c.take(tb.bound));
   if (c.dry) return RT_OK;
   if (mode != BatchMode::kLaunchOnly) {
     c.chk(hipMemcpyWithStream(tables, tb.bytes.data(), tb.bytes.size(), hipMemcpyHostToDevice, c.st));
@@ -1298,8 +1308,45 @@ uint64_t batch_key(int32_t count, const rt_batch_item* items, int32_t p, rt_dtyp
   return h;
 }
 
+// Tuning cache file (environment variable RTUCKER_TUNE_CACHE): one line per batch
+// signature, "<key, 16 hex digits> <row tile> <slabs per wave>", appended by the autotuner
+// and read when a process first plans with that path set (later lines win).  Lines that
+// do not parse, or hold values the plan does not accept, are skipped.
+std::string g_tune_path_loaded;
+
+void load_tune_file_locked() {
+  const char* path = std::getenv("RTUCKER_TUNE_CACHE");
+  if (!path || !*path || g_tune_path_loaded == path) return;
+  g_tune_path_loaded = path;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char line[256];
+  while (std::fgets(line, sizeof line, f)) {
+    unsigned long long key = 0;
+    int mt = 0, spb = 0;
+    if (std::sscanf(line, "%16llx %d %d", &key, &mt, &spb) != 3) continue;
+    if ((mt != 8 && mt != 16 && mt != 32) || (spb != 1 && spb != 2 && spb != 4)) continue;
+    BatchTune t;
+    t.core_mt = mt;
+    t.spb_cap = spb;
+    g_tune[static_cast<uint64_t>(key)] = t;
+  }
+  std::fclose(f);
+}
+
+void save_tune_locked(uint64_t key, const BatchTune& t) {
+  g_tune[key] = t;
+  const char* path = std::getenv("RTUCKER_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;  // the cache is an optimisation: an unwritable path only loses it
+  std::fprintf(f, "%016llx %d %d\n", static_cast<unsigned long long>(key), t.core_mt, t.spb_cap);
+  std::fclose(f);
+}
+
 BatchTune tune_for(int32_t count, const rt_batch_item* items, int32_t p, rt_dtype dtype) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
+  load_tune_file_locked();
   auto it = g_tune.find(batch_key(count, items, p, dtype));
   return it == g_tune.end() ? BatchTune{} : it->second;
 }
@@ -1610,11 +1657,23 @@ int rtucker_decompose_batched_launch(int32_t count, const rt_batch_item* items, 
              stream);
 }
 
+int rtucker_decompose_batched_tuning(int32_t count, const rt_batch_item* items, int32_t p, rt_dtype dtype,
+                                     int32_t* tuning, uint64_t* key) {
+  if (count < 1 || !items || !tuning || p < 0) return RT_EINVAL;
+  if (dtype != RT_F32 && dtype != RT_BF16) return RT_EDTYPE;
+  const BatchTune t = tune_for(count, items, p, dtype);
+  tuning[0] = t.core_mt;
+  tuning[1] = t.spb_cap;
+  if (key) *key = batch_key(count, items, p, dtype);
+  return RT_OK;
+}
+
 int rtucker_decompose_batched_autotune(int32_t count, const rt_batch_item* items, int32_t p, rt_dtype dtype,
                                        void* ws, size_t ws_bytes, void* stream, int32_t* chosen) {
-  const int cand[3] = {8, 16, 32};
+  const int mts[3] = {8, 16, 32};
+  const int spbs[3] = {1, 2, 4};
   float best_ms = -1.0f;
-  int best = 16;
+  BatchTune best;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return RT_EHIP;
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -1622,9 +1681,10 @@ int rtucker_decompose_batched_autotune(int32_t count, const rt_batch_item* items
     return RT_EHIP;
   }
   int status = RT_OK;
-  for (int ci = 0; ci < 3 && status == RT_OK; ++ci) {
+  for (int ci = 0; ci < 9 && status == RT_OK; ++ci) {
     BatchTune tune;
-    tune.core_mt = cand[ci];
+    tune.core_mt = mts[ci % 3];
+    tune.spb_cap = spbs[ci / 3];
     auto plan = [&](Ctx& c, BatchMode m) { return plan_batched_impl(c, count, items, p, dtype, tune, m); };
     status = run([&](Ctx& c) { return plan(c, BatchMode::kUploadOnly); }, ws, ws_bytes, stream);
     if (status) break;
@@ -1643,7 +1703,7 @@ int rtucker_decompose_batched_autotune(int32_t count, const rt_batch_item* items
     }
     if (best_ms < 0.0f || ms < best_ms) {
       best_ms = ms;
-      best = cand[ci];
+      best = tune;
     }
   }
   (void)hipEventDestroy(e0);
@@ -1651,11 +1711,13 @@ int rtucker_decompose_batched_autotune(int32_t count, const rt_batch_item* items
   if (status) return status;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    BatchTune t;
-    t.core_mt = best;
-    g_tune[batch_key(count, items, p, dtype)] = t;
+    load_tune_file_locked();
+    save_tune_locked(batch_key(count, items, p, dtype), best);
   }
-  if (chosen) *chosen = best;
+  if (chosen) {
+    chosen[0] = best.core_mt;
+    chosen[1] = best.spb_cap;
+  }
   // leave the tables of the chosen setting in the workspace for a following launch-only call
   return run([&](Ctx& c) { return plan_batched(c, count, items, p, dtype, BatchMode::kUploadOnly); }, ws, ws_bytes,
              stream);

@@ -166,3 +166,55 @@ def test_binding_rejects_mismatched_operands():
 
 def test_status_code_minus_five_unused():
     assert rt.lib().rtucker_status_string(-5) == b"unknown status"
+
+
+def _fake_batch(dims_list, ranks_list):
+    items = (rt.rt_batch_item * len(dims_list))()
+    for i, (d, r) in enumerate(zip(dims_list, ranks_list)):
+        it = items[i]
+        it.X = 0x1000
+        it.G = 0x1000
+        for k in range(3):
+            it.dims[k], it.r[k], it.s[k] = d[k], r[k], 0
+            it.phi[k] = 0x1000
+            it.U[k] = 0x1000
+    return items
+
+
+def test_batch_tuning_cache_file(tmp_path, monkeypatch):
+    """The autotuner's cache: defaults without a file; a file line for the batch's signature
+    key sets the tuning; unparsable lines and values the plan rejects are skipped."""
+    items = _fake_batch([(37, 41, 43), (50, 33, 61)], [(5, 6, 7), (4, 4, 9)])
+    monkeypatch.delenv("RTUCKER_TUNE_CACHE", raising=False)
+    mt, spb, key = rt.batched_tuning(items, 2, 4, rt.RT_F32)
+    assert (mt, spb) == (16, 4)
+    other = rt.batched_tuning(items, 2, 5, rt.RT_F32)[2]
+    assert other != key  # p is part of the signature
+    path = tmp_path / "tune.txt"
+    path.write_text(f"not a line\n{key:016x} 8 2\n{key:016x} 7 3\n{other:016x} 32 1\n")
+    monkeypatch.setenv("RTUCKER_TUNE_CACHE", str(path))
+    assert rt.batched_tuning(items, 2, 4, rt.RT_F32)[:2] == (8, 2)
+    assert rt.batched_tuning(items, 2, 5, rt.RT_F32)[:2] == (32, 1)
+    with pytest.raises(rt.RtuckerError):
+        rt.batched_tuning(items, 2, 4, rt.RT_F64)
+
+
+def test_batch_workspace_independent_of_tuning(tmp_path, monkeypatch):
+    """The batched workspace holds the job tables for every setting the autotuner may pick:
+    the query gives the same size whatever the cache says."""
+    dims = [(150, 40, 70), (192, 100, 33), (64, 64, 64)]
+    ranks = [(6, 5, 4), (8, 8, 8), (4, 9, 5)]
+    items = _fake_batch(dims, ranks)
+    L = rt.lib()
+    nb = ctypes.c_size_t()
+    monkeypatch.delenv("RTUCKER_TUNE_CACHE", raising=False)
+    assert L.rtucker_decompose_batched_workspace(3, items, 4, rt.RT_F32, ctypes.byref(nb)) == 0
+    base = nb.value
+    key = rt.batched_tuning(items, 3, 4, rt.RT_F32)[2]
+    for mt, spb in ((8, 1), (32, 2), (16, 4)):
+        path = tmp_path / f"t{mt}_{spb}.txt"
+        path.write_text(f"{key:016x} {mt} {spb}\n")
+        monkeypatch.setenv("RTUCKER_TUNE_CACHE", str(path))
+        assert rt.batched_tuning(items, 3, 4, rt.RT_F32)[:2] == (mt, spb)
+        assert L.rtucker_decompose_batched_workspace(3, items, 4, rt.RT_F32, ctypes.byref(nb)) == 0
+        assert nb.value == base, (mt, spb)

@@ -125,8 +125,9 @@ def test_batched_graph_replay_and_autotune():
     Gs, Us = B.run()
     ref_G = [host(g).copy() for g in Gs]
     ref_U = [[host(u).copy() for u in us] for us in Us]
-    chosen = B.autotune()
-    assert chosen in (8, 16, 32)
+    chosen, spb = B.autotune()
+    assert chosen in (8, 16, 32) and spb in (1, 2, 4)
+    assert B.tuning()[:2] == (chosen, spb)
     B.upload()
     g = B.capture()
     for rep in range(3):
