@@ -1074,14 +1074,17 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
   std::vector<PrepTask> prep_sk, prep_core;
   std::vector<GZwJob> zw[4];  // by column class 4, 8, 12, 16 (index class / 4 - 1)
   std::vector<GTtmJob> tree, core[3], gttm[3], uttm[3];
-  std::vector<GTtmJob> core0[4];  // first core contraction on matrix cores, by 16-row tiles of M
-  int64_t core0_blocks[4] = {0, 0, 0, 0};
+  // core contractions on the batched matrix-core kernel, by step and 16-row tiles of M
+  // (index: step, B == 1, 16-row tiles of M minus one)
+  std::vector<GTtmJob> cb[3][2][4];
+  int64_t cb_blocks[3][2][4] = {};
   std::vector<GQrJob> qr_hh, qr_fb;
-  std::vector<GCholQRJob> qr_cq;
-  int max_chunks = 1;
+  std::vector<GCholQRJob> qr_cq[2];  // by width class: at most 32 columns, at most 64
+  int max_chunks[2] = {1, 1};
   std::vector<GCopyJob> cp;
   std::vector<GGramJob> gram[3];
   std::vector<GEigJob> eig[3];
+  int gram_mmax[3] = {0, 0, 0};
   int64_t max_prep_sk = 1, max_prep_core = 1, max_cp = 1;
   int64_t zw_blocks[4] = {0, 0, 0, 0}, tree_blocks = 0, core_blocks[3] = {0, 0, 0}, g_blocks[3] = {0, 0, 0},
           u_blocks[3] = {0, 0, 0};
@@ -1134,11 +1137,12 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
         double* R2 = static_cast<double*>(c.take(2 * 64 * 64 * 8));  // R2, then R2^-1
         double* Q1 = static_cast<double*>(c.take(static_cast<size_t>(t.I[n]) * ncol * 8));
         int32_t* flag = static_cast<int32_t*>(c.take(sizeof(int32_t)));
-        qr_cq.push_back(GCholQRJob{Ys[n], YA[n], t.I[n], YB[n], static_cast<int32_t>(ncol), part,
-                                   static_cast<int32_t>(chunks), R1, R2, Q1, Uh[n], nullptr, flag});
+        const int wc = ncol <= 32 ? 0 : 1;
+        qr_cq[wc].push_back(GCholQRJob{Ys[n], YA[n], t.I[n], YB[n], static_cast<int32_t>(ncol), part,
+                                       static_cast<int32_t>(chunks), R1, R2, Q1, Uh[n], nullptr, flag});
         qr_fb.push_back(GQrJob{Ys[n], YA[n], t.I[n], YB[n], Uh[n], static_cast<int32_t>(ncol),
                                static_cast<int32_t>(t.c[n]), flag});
-        max_chunks = std::max<int>(max_chunks, static_cast<int>(chunks));
+        max_chunks[wc] = std::max<int>(max_chunks[wc], static_cast<int>(chunks));
       } else {
         qr_hh.push_back(GQrJob{Ys[n], YA[n], t.I[n], YB[n], Uh[n], static_cast<int32_t>(ncol),
                                static_cast<int32_t>(t.c[n]), nullptr});
@@ -1157,12 +1161,13 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
       for (int q = 0; q < k; ++q) A *= dims[q];
       for (int q = k + 1; q < d; ++q) B *= dims[q];
       float* y = static_cast<float*>(c.take(static_cast<size_t>(A) * t.c[k] * B * 4));
-      if (stp == 0 && (B == 1 || B >= 16)) {
-        // the pass over X: matrix-core kernel, jobs grouped by 16-row tiles of M
-        const int mc = static_cast<int>(ceil_div(t.c[k], 16)) - 1;
+      if (ttm_batch_fits(t.I[k], B, t.c[k])) {
+        // matrix-core kernel (the pass over X and the later steps), jobs grouped by path and 16-row tiles of M
+        const int mc = static_cast<int>(ceil_div(t.c[k], 16)) - 1, rw = B == 1 ? 1 : 0;
         const int64_t units = ttm_batch_units(A, B);
-        core0[mc].push_back(GTtmJob{cur, cop, y, A, t.I[k], B, t.c[k], core0_blocks[mc], units, 0, 0, 0});
-        core0_blocks[mc] += ceil_div(units, 4);
+        cb[stp][rw][mc].push_back(
+            GTtmJob{cur, cop, y, A, t.I[k], B, t.c[k], cb_blocks[stp][rw][mc], units, ttm_batch_row_tiles(A, B), 0, 0});
+        cb_blocks[stp][rw][mc] += ttm_batch_blocks(A, B);
       } else {
         const int mt = (stp == 0) ? core_mt_first : 16;
         core[stp].push_back(GTtmJob{cur, cop, y, A, t.I[k], B, t.c[k], core_blocks[stp], ceil_div(A * B, kWave),
@@ -1188,6 +1193,7 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
       double* M = static_cast<double*>(c.take(static_cast<size_t>(cj) * cj * 8));
       double* V = static_cast<double*>(c.take(static_cast<size_t>(cj) * t.r[j] * 8));
       gram[j].push_back(GGramJob{gcur, M, A, cj, B});
+      gram_mmax[j] = std::max<int>(gram_mmax[j], static_cast<int>(cj));
       eig[j].push_back(GEigJob{M, V, static_cast<int32_t>(cj), t.r[j]});
       double* gnext = (j == d - 1) ? b.G : static_cast<double*>(c.take(static_cast<size_t>(A) * t.r[j] * B * 8));
       gttm[j].push_back(GTtmJob{gcur, V, gnext, A, cj, B, t.r[j], g_blocks[j], ceil_div(A * B, kWave),
@@ -1211,19 +1217,22 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
     for (size_t j = 0; j < zw[q].size(); ++j)
       zw_map[q].insert(zw_map[q].end(), ceil_div(zw[q][j].A, 4 * zw[q][j].spb), static_cast<int32_t>(j));
   TableBuf tb;
-  size_t o_zw[4], m_zw[4], o_c0[4], m_c0[4];
+  size_t o_zw[4], m_zw[4], o_cb[3][2][4], m_cb[3][2][4];
   for (int q = 0; q < 4; ++q) {
     o_zw[q] = tb.add(zw[q]);
     size_t most = 0;  // one slab per wave
     for (const GZwJob& j : zw[q]) most += static_cast<size_t>(ceil_div(j.A, 4));
     m_zw[q] = tb.add(zw_map[q], most);
-    std::vector<int32_t> cmap;
-    for (size_t j = 0; j < core0[q].size(); ++j)
-      cmap.insert(cmap.end(), ceil_div(core0[q][j].colblocks, 4), static_cast<int32_t>(j));
-    o_c0[q] = tb.add(core0[q]);
-    m_c0[q] = tb.add(cmap);
+    for (int stp = 0; stp < 3; ++stp)
+      for (int rw = 0; rw < 2; ++rw) {
+        std::vector<int32_t> cmap;
+        for (size_t j = 0; j < cb[stp][rw][q].size(); ++j)
+          cmap.insert(cmap.end(), ttm_batch_blocks(cb[stp][rw][q][j].A, cb[stp][rw][q][j].B), static_cast<int32_t>(j));
+        o_cb[stp][rw][q] = tb.add(cb[stp][rw][q]);
+        m_cb[stp][rw][q] = tb.add(cmap);
+      }
   }
-  const size_t o_psk = tb.add(prep_sk), o_tree = tb.add(tree), o_cq = tb.add(qr_cq),
+  const size_t o_psk = tb.add(prep_sk), o_tree = tb.add(tree), o_cq0 = tb.add(qr_cq[0]), o_cq1 = tb.add(qr_cq[1]),
                o_hh = tb.add(qr_hh), o_fb = tb.add(qr_fb), o_pcore = tb.add(prep_core);
   size_t o_core[3], o_gram[3], o_eig[3], o_g[3], o_u[3];
   size_t m_core[3], m_g[3], m_u[3];
@@ -1259,22 +1268,26 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
                           dtype, st));
   c.chk(launch_ttm_grouped(reinterpret_cast<const GTtmJob*>(at(o_tree)), imap(m_tree), static_cast<int>(tree.size()),
                            tree_blocks, RT_F32, 8, st));
-  c.chk(launch_cholqr2_grouped(reinterpret_cast<const GCholQRJob*>(at(o_cq)), static_cast<int>(qr_cq.size()),
-                               max_chunks, RT_F32, st));
+  c.chk(launch_cholqr2_grouped(reinterpret_cast<const GCholQRJob*>(at(o_cq0)), static_cast<int>(qr_cq[0].size()),
+                               max_chunks[0], RT_F32, st, 32));
+  c.chk(launch_cholqr2_grouped(reinterpret_cast<const GCholQRJob*>(at(o_cq1)), static_cast<int>(qr_cq[1].size()),
+                               max_chunks[1], RT_F32, st, 64));
   c.chk(launch_qr_grouped(reinterpret_cast<const GQrJob*>(at(o_hh)), static_cast<int>(qr_hh.size()), RT_F32, st));
   c.chk(launch_qr_grouped(reinterpret_cast<const GQrJob*>(at(o_fb)), static_cast<int>(qr_fb.size()), RT_F32, st));
   c.chk(launch_prep_grouped(reinterpret_cast<const PrepTask*>(at(o_pcore)), static_cast<int>(prep_core.size()),
                             max_prep_core, st));
-  for (int q = 0; q < 4; ++q)
-    c.chk(launch_ttm_batch(reinterpret_cast<const GTtmJob*>(at(o_c0[q])), imap(m_c0[q]), core0_blocks[q], q + 1, dtype,
-                           st));
-  for (int q = 0; q < 3; ++q)
-    c.chk(launch_ttm_grouped(reinterpret_cast<const GTtmJob*>(at(o_core[q])), imap(m_core[q]),
-                             static_cast<int>(core[q].size()), core_blocks[q], q == 0 ? dtype : RT_F32,
-                             q == 0 ? core_mt_first : 16, st));
+  for (int stp = 0; stp < 3; ++stp) {
+    for (int rw = 0; rw < 2; ++rw)
+      for (int q = 0; q < 4; ++q)
+        c.chk(launch_ttm_batch(reinterpret_cast<const GTtmJob*>(at(o_cb[stp][rw][q])), imap(m_cb[stp][rw][q]),
+                               cb_blocks[stp][rw][q], q + 1, rw == 1, stp == 0 ? dtype : RT_F32, st));
+    c.chk(launch_ttm_grouped(reinterpret_cast<const GTtmJob*>(at(o_core[stp])), imap(m_core[stp]),
+                             static_cast<int>(core[stp].size()), core_blocks[stp], stp == 0 ? dtype : RT_F32,
+                             stp == 0 ? core_mt_first : 16, st));
+  }
   c.chk(launch_copy_f64_grouped(reinterpret_cast<const GCopyJob*>(at(o_cp)), count, max_cp, st));
   for (int j = 0; j < 3; ++j) {
-    c.chk(launch_gram_grouped(reinterpret_cast<const GGramJob*>(at(o_gram[j])), count, st));
+    c.chk(launch_gram_grouped(reinterpret_cast<const GGramJob*>(at(o_gram[j])), count, st, gram_mmax[j]));
     c.chk(launch_eig_grouped(reinterpret_cast<const GEigJob*>(at(o_eig[j])), count, st));
     c.chk(launch_ttm_grouped(reinterpret_cast<const GTtmJob*>(at(o_g[j])), imap(m_g[j]), count, g_blocks[j], RT_F64,
                              16, st));

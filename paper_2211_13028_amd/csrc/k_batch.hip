@@ -19,6 +19,8 @@
 // (Reading each 16-row block as one flat run, 64 consecutive elements per load, and
 // scattering it into an LDS tile read back for both products measured slower: 0.92 ms
 // against 0.63 ms for the 192-column class of the 512-tensor batch.)
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace rt {
@@ -54,19 +56,12 @@ __global__ __launch_bounds__(kBThreads, NG > 12 ? 1 : 2) void zw_batch_kernel(co
   const int64_t P = J.P, Q = J.Q, A = J.A;
   const int sP = J.sP, sQ = J.sQ;
   const bool needZ = J.Z != nullptr, needW = J.W != nullptr;
-  // Phi_3 (sQ x Q) zero-padded to 16 x 16 NG; without Z it is never read
-  for (int idx = threadIdx.x; idx < 16 * S; idx += kBThreads) {
-    const int c = idx / S, q = idx - (idx / S) * S;
-    sPhi[idx] = (needZ && c < sQ && q < Q) ? global_ptr(J.phiQ)[static_cast<int64_t>(c) * Q + q] : 0.f;
-  }
-  __syncthreads();
   const int lane = threadIdx.x % kWave;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int li = lane % 16, kg = lane / 16;
   const int64_t local = blockIdx.x - J.blk0;
   const int64_t a_first = local * kBWaves * J.spb + wave;
   const int64_t a_end = (local + 1) * kBWaves * J.spb < A ? (local + 1) * kBWaves * J.spb : A;
-  if (a_first >= a_end) return;
   const int steps = static_cast<int>((P + 15) / 16);
   float* st = sStage[wave];
   const gptr<const TX> X = global_ptr(static_cast<const TX*>(J.X));
@@ -82,6 +77,7 @@ __global__ __launch_bounds__(kBThreads, NG > 12 ? 1 : 2) void zw_batch_kernel(co
     qok[g] = q < Q;
     qoff[g] = static_cast<uint32_t>(q < Q ? q : Q - 1);
   }
+
   const int pc_lane = li < sP ? li : sP - 1;
 
   // raw values of the next step (converted and masked when the step is taken over)
@@ -98,13 +94,22 @@ __global__ __launch_bounds__(kBThreads, NG > 12 ? 1 : 2) void zw_batch_kernel(co
       ppn[t] = needW ? phiP[static_cast<int64_t>(pc_lane) * P + (p < P ? p : P - 1)] : 0.f;
     }
   };
+  // the wave's first block is in flight while Phi_3 is staged
+  if (a_first < a_end) load(a_first, 0);
+
+  // Phi_3 (sQ x Q) zero-padded to 16 x 16 NG; without Z it is never read
+  for (int idx = threadIdx.x; idx < 16 * S; idx += kBThreads) {
+    const int c = idx / S, q = idx - (idx / S) * S;
+    sPhi[idx] = (needZ && c < sQ && q < Q) ? global_ptr(J.phiQ)[static_cast<int64_t>(c) * Q + q] : 0.f;
+  }
+  __syncthreads();
+  if (a_first >= a_end) return;
 
   bf32x4 wacc[NG];
 #pragma unroll
   for (int g = 0; g < NG; ++g) wacc[g] = bf32x4{0.f, 0.f, 0.f, 0.f};
   int64_t a = a_first;
   int step = 0;
-  load(a, 0);
   while (true) {
     const int64_t pb = static_cast<int64_t>(step) * 16;
     float r[4][NG], pp[4];
@@ -174,93 +179,156 @@ __global__ __launch_bounds__(kBThreads, NG > 12 ? 1 : 2) void zw_batch_kernel(co
   }
 }
 
-// ------------------------------------------------------------------ first core contraction
+// ------------------------------------------------------------------ core contractions
 // Y = X x_k M (Y[a][i][b] = sum_c M[i][c] X[a][c][b], X viewed as (A, K, B), M: m x K with
-// m <= 16 MT) for every tensor of the batch, on binary32 matrix cores.  A wave owns one
-// unit; a workgroup takes four consecutive units of one job.
-//  * B >= 16 (a mode other than the last): unit = (a, 64 columns of b), all m rows.  Lane
-//    (li, kg) loads X[a][c][b0 + 16 j + li] (j < 4: 16 lanes read 64 consecutive bytes)
-//    for c = c0 + 4 s + kg as the B operand of four 16-column tiles; A = M[16 t + li][c].
-//    The next 16 c are in flight while the current 16 are multiplied.
-//  * B == 1 (the last mode): unit = 16 rows a, all m.  Each 64-wide block of c is read
-//    row by row with the lanes along c (256 consecutive bytes per row), staged in the
-//    wave's LDS area and read back as the A operand X[a0 + li][c]; B = M[16 t + li][c].
+// m <= 16 MT, K <= 256) for every tensor of the batch, on matrix cores.  A wave owns one
+// unit (B == 1: four); a workgroup works on one job.
+//  * B >= 16 (a mode other than the last): unit = (a, 64 columns of b), all m rows.  M is
+//    staged once per workgroup in LDS (zero past m and past K).  Lane (li, kg) loads
+//    X[a][c][b0 + 16 j + li] (j < 4: 16 lanes read consecutive elements of a row) as the
+//    B operand of four 16-column tiles:
+//     - binary32 X: c = c0 + 4 s + kg (s < 4) per chunk of 16 c, 16x16x4 binary32 products
+//       with A = M[16 t + li][c] read from LDS stored c-major;
+//     - bfloat16 X: c = c0 + 8 kg + e (e < 8) per chunk of 32 c, packed in pairs for
+//       16x16x32 bfloat16 products with A = M[16 t + li][c0 + 8 kg ..] (eight consecutive
+//       bfloat16 of the LDS copy stored row-major; M holds bfloat16 values, so the products
+//       are exact and only the binary32 accumulation order differs from the binary32 path).
+//    The next chunk is in flight while the current one is multiplied; columns past B read
+//    column B - 1 (their outputs are not stored) and rows past K are zeroed.
+//  * B == 1 (the last mode): unit = 16 rows a, all m, up to four units per wave.  M is staged
+//    in LDS as [c][16 MT].  Each 64-wide block of c is read row by row with the lanes
+//    along c (256 consecutive bytes per row), staged in the wave's LDS area and read back
+//    as the A operand X[a0 + li][c]; B = M[16 t + li][c].
+// (Reading M from global memory, 16 rows of one lane group at a time, measured 15-20 %
+// slower; three chunks in flight per wave instead of one measured slower.)
 constexpr int kTStage = 68;  // floats per staged row of 64 c: = 4 mod 64, conflict-free row reads
+constexpr int kTBMaxK = 256;
+typedef __bf16 tb_bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t tb_u32x4 __attribute__((ext_vector_type(4)));
 
-template <typename TX, int MT>
+template <typename TX, int MT, bool ROWS>
 __global__ __launch_bounds__(kBThreads, 2) void ttm_batch_kernel(const GTtmJob* __restrict__ jobs,
                                                                 const int32_t* __restrict__ blkjob) {
-  __shared__ float sT[kBWaves][16 * kTStage];
+  constexpr bool kBF = std::is_same<TX, bf16_t>::value;
+  // LDS: M (B >= 16: binary32 [c][16 MT], or bfloat16 [16 MT][kMS]; B == 1: binary32
+  // [c][16 MT]), then for B == 1 the per-wave stages
+  constexpr int kLds = kTBMaxK * 16 * MT + (ROWS ? kBWaves * 16 * kTStage : 0);
+  __shared__ __align__(16) float lds[kLds];
+  float* const sM = lds;
   const GTtmJob J = jobs[blkjob[blockIdx.x]];
   const int lane = threadIdx.x % kWave;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int li = lane % 16, kg = lane / 16;
   const int64_t unit = (blockIdx.x - J.blk0) * kBWaves + wave;
-  if (unit >= J.colblocks) return;
   const int64_t K = J.K, B = J.B, m = J.m;
   const gptr<const TX> X = global_ptr(static_cast<const TX*>(J.X));
   const gptr<const float> M = global_ptr(static_cast<const float*>(J.M));
   const gptr<float> Y = global_ptr(static_cast<float*>(J.Y));
-  // M rows of the lane (clamped; rows past m are zeroed when used)
-  int64_t mrow[MT];
-  bool mok[MT];
-#pragma unroll
-  for (int t = 0; t < MT; ++t) {
-    const int64_t i = 16 * t + li;
-    mok[t] = i < m;
-    mrow[t] = (i < m ? i : m - 1) * K;
-  }
-  if (B >= 16) {
+  if constexpr (!ROWS) {
+    constexpr int kCh = kBF ? 32 : 16;      // c per chunk
+    constexpr int kRows = kBF ? 8 : 4;      // rows per lane per chunk
+    const int64_t Kp = (K + kCh - 1) / kCh * kCh;
+    const int kMS = static_cast<int>(Kp) + 8;  // bfloat16 row stride: 16-byte rows
+    const bool live = unit < J.colblocks;
     const int64_t nb = (B + 63) / 64;
-    const int64_t a = unit / nb, b0 = (unit - a * nb) * 64;
+    const int64_t a = live ? unit / nb : 0, b0 = live ? (unit - a * nb) * 64 : 0;
     const gptr<const TX> xa = X + a * K * B;
     int64_t col[4];
-    bool bok[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int64_t b = b0 + 16 * j + li;
-      bok[j] = b < B;
       col[j] = b < B ? b : B - 1;
     }
+    // raw values of the next chunk: binary32 rows c0 + 4 e + kg; bfloat16 rows
+    // c0 + 8 kg + 2 w, c0 + 8 kg + 2 w + 1 packed in one word (low half first)
+    float xn[kBF ? 1 : 4][4];
+    uint32_t xp[kBF ? 4 : 1][4];
+    auto load = [&](int64_t c0) {
+      if constexpr (kBF) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          const int64_t c = c0 + 8 * kg + 2 * w;
+          const int64_t c1 = c < K ? c : K - 1, c2 = c + 1 < K ? c + 1 : K - 1;
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            xp[w][j] = static_cast<uint32_t>(xa[c1 * B + col[j]]) | (static_cast<uint32_t>(xa[c2 * B + col[j]]) << 16);
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t c = c0 + 4 * e + kg;
+          const int64_t cc = c < K ? c : K - 1;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) xn[e][j] = widen<TX>(xa[cc * B + col[j]]);
+        }
+      }
+    };
+    if (live) load(0);  // in flight while M is staged
+    // stage M (zero past m and past K)
+    const int64_t rows = 16 * MT;
+    for (int64_t idx = threadIdx.x; idx < Kp * rows; idx += kBThreads) {
+      const int64_t c = idx / rows, i = idx - c * rows;
+      const float v = (c < K && i < m) ? M[i * K + c] : 0.f;
+      if constexpr (kBF)
+        reinterpret_cast<bf16_t*>(sM)[i * kMS + c] = static_cast<bf16_t>(__float_as_uint(v) >> 16);
+      else
+        sM[idx] = v;
+    }
+    __syncthreads();
+    if (!live) return;
     bf32x4 acc[MT][4];
 #pragma unroll
     for (int t = 0; t < MT; ++t)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[t][j] = bf32x4{0.f, 0.f, 0.f, 0.f};
-    // c in chunks of 16 (four products of four c per tile); the next chunk's 16 X values
-    // and 4 MT M values per lane are in flight while the current chunk is multiplied
-    TX xn[4][4];
-    float mn[4][MT];
-    auto load = [&](int64_t c0) {
+    for (int64_t c0 = 0; c0 < K; c0 += kCh) {
+      const bool full = c0 + kCh <= K;  // uniform: only the last chunk has rows past K
+      if constexpr (kBF) {
+        // B operand of tile j: rows c0 + 8 kg + e of column j, element e (pairs packed)
+        tb_u32x4 op[4];
 #pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) {
-        const int64_t c = c0 + 4 * s4 + kg;
-        const int64_t cc = c < K ? c : K - 1;
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) xn[s4][j] = xa[cc * B + col[j]];
+          for (int w = 0; w < 4; ++w) {
+            uint32_t v = xp[w][j];
+            if (!full) {
+              const int64_t c = c0 + 8 * kg + 2 * w;
+              v &= (c < K ? 0x0000ffffu : 0u) | (c + 1 < K ? 0xffff0000u : 0u);
+            }
+            op[j][w] = v;
+          }
+        if (c0 + kCh < K) load(c0 + kCh);
+        const bf16_t* mb = reinterpret_cast<const bf16_t*>(sM);
 #pragma unroll
-        for (int t = 0; t < MT; ++t) mn[s4][t] = M[mrow[t] + cc];
-      }
-    };
-    load(0);
-    for (int64_t c0 = 0; c0 < K; c0 += 16) {
-      float xv[4][4], mv[4][MT];
-#pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) {
-        const bool cin = c0 + 4 * s4 + kg < K;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) xv[s4][j] = (cin && bok[j]) ? widen<TX>(xn[s4][j]) : 0.f;
-#pragma unroll
-        for (int t = 0; t < MT; ++t) mv[s4][t] = (cin && mok[t]) ? mn[s4][t] : 0.f;
-      }
-      if (c0 + 16 < K) load(c0 + 16);
-#pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4)
-#pragma unroll
-        for (int t = 0; t < MT; ++t)
+        for (int t = 0; t < MT; ++t) {
+          const tb_u32x4 av = *reinterpret_cast<const tb_u32x4*>(mb + (16 * t + li) * kMS + c0 + 8 * kg);
 #pragma unroll
           for (int j = 0; j < 4; ++j)
-            acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(mv[s4][t], xv[s4][j], acc[t][j], 0, 0, 0);
+            acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(tb_bf16x8, av),
+                                                                __builtin_bit_cast(tb_bf16x8, op[j]), acc[t][j], 0,
+                                                                0, 0);
+        }
+      } else {
+        float xv[4][4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const bool cin = full || c0 + 4 * e + kg < K;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) xv[e][j] = cin ? xn[e][j] : 0.f;
+        }
+        if (c0 + kCh < K) load(c0 + kCh);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float* mc = sM + (c0 + 4 * e + kg) * rows + li;
+#pragma unroll
+          for (int t = 0; t < MT; ++t) {
+            const float mv = mc[16 * t];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(mv, xv[e][j], acc[t][j], 0, 0, 0);
+          }
+        }
+      }
     }
     // D[i = 4 kg + v][b = li] of tile (t, j)
     const gptr<float> ya = Y + a * m * B;
@@ -270,19 +338,22 @@ __global__ __launch_bounds__(kBThreads, 2) void ttm_batch_kernel(const GTtmJob* 
       for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int64_t i = 16 * t + 4 * kg + v;
-          if (i < m && bok[j]) ya[i * B + b0 + 16 * j + li] = acc[t][j][v];
+          const int64_t i = 16 * t + 4 * kg + v, b = b0 + 16 * j + li;
+          if (i < m && b < B) ya[i * B + b] = acc[t][j][v];
         }
   } else {
-    // B == 1: rows a0 .. a0 + 15 of the A x K matrix X
+    // B == 1: tiles of 16 rows a of the A x K matrix X.  A workgroup takes 4 U consecutive
+    // tiles (U = J.mtiles, from ttm_batch_row_tiles); wave w takes tiles 4 u + w (u < U),
+    // and the first block of its next tile is in flight during the last block of the
+    // current one.
     const int64_t A = J.A;
-    const int64_t a0 = unit * 16;
-    float* st = sT[wave];
-    bf32x4 acc[MT];
-#pragma unroll
-    for (int t = 0; t < MT; ++t) acc[t] = bf32x4{0.f, 0.f, 0.f, 0.f};
+    const int64_t U = J.mtiles;
+    const int64_t tile0 = (blockIdx.x - J.blk0) * kBWaves * U + wave;
+    const int64_t tile_end = J.colblocks;
+    const int64_t rows = 16 * MT;
+    float* st = lds + kTBMaxK * 16 * MT + wave * 16 * kTStage;
     TX xn[16];
-    auto load = [&](int64_t c0) {
+    auto load = [&](int64_t a0, int64_t c0) {
       const int64_t c = c0 + lane;
       const int64_t cc = c < K ? c : K - 1;
 #pragma unroll
@@ -291,37 +362,50 @@ __global__ __launch_bounds__(kBThreads, 2) void ttm_batch_kernel(const GTtmJob* 
         xn[i] = X[a * K + cc];
       }
     };
-    load(0);
-    for (int64_t c0 = 0; c0 < K; c0 += 64) {
-      const bool cin = c0 + lane < K;
-      float xv[16];
+    if (tile0 < tile_end) load(tile0 * 16, 0);  // in flight while M is staged
+    // stage M as [c][16 MT] (zero past m and past K, up to the next multiple of 64)
+    const int64_t Kp = (K + 63) / 64 * 64;
+    for (int64_t idx = threadIdx.x; idx < Kp * rows; idx += kBThreads) {
+      const int64_t c = idx / rows, i = idx - c * rows;
+      sM[idx] = (c < K && i < m) ? M[i * K + c] : 0.f;
+    }
+    __syncthreads();
+    const int64_t tile_last = tile0 + kBWaves * (U - 1) < tile_end ? tile0 + kBWaves * (U - 1) : tile_end - 1;
+    for (int64_t tile = tile0; tile <= tile_last; tile += kBWaves) {
+      const int64_t a0 = tile * 16;
+      bf32x4 acc[MT];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) xv[i] = (cin && a0 + i < A) ? widen<TX>(xn[i]) : 0.f;
-      if (c0 + 64 < K) load(c0 + 64);
-      __builtin_amdgcn_wave_barrier();  // the previous block's reads of the stage stay above
+      for (int t = 0; t < MT; ++t) acc[t] = bf32x4{0.f, 0.f, 0.f, 0.f};
+      for (int64_t c0 = 0; c0 < K; c0 += 64) {
+        const bool cin = c0 + lane < K;
+        float xv[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) st[i * kTStage + lane] = xv[i];
-      __builtin_amdgcn_wave_barrier();  // cross-lane: stores before the reads below
+        for (int i = 0; i < 16; ++i) xv[i] = (cin && a0 + i < A) ? widen<TX>(xn[i]) : 0.f;
+        if (c0 + 64 < K)
+          load(a0, c0 + 64);
+        else if (tile + kBWaves <= tile_last)
+          load(a0 + 16 * kBWaves, 0);
+        __builtin_amdgcn_wave_barrier();  // the previous block's reads of the stage stay above
+#pragma unroll
+        for (int i = 0; i < 16; ++i) st[i * kTStage + lane] = xv[i];
+        __builtin_amdgcn_wave_barrier();  // cross-lane: stores before the reads below
 #pragma unroll 4
-      for (int kk = 0; kk < 64; kk += 4) {
-        const float av = st[li * kTStage + kk + kg];
-        const int64_t c = c0 + kk + kg;
-        const int64_t cc = c < K ? c : K - 1;
+        for (int kk = 0; kk < 64; kk += 4) {
+          const float av = st[li * kTStage + kk + kg];
+          const float* mc = sM + (c0 + kk + kg) * rows + li;
 #pragma unroll
-        for (int t = 0; t < MT; ++t) {
-          const float bv = (c < K && mok[t]) ? M[mrow[t] + cc] : 0.f;
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[t], 0, 0, 0);
+          for (int t = 0; t < MT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, mc[16 * t], acc[t], 0, 0, 0);
         }
       }
+      // D[a = a0 + 4 kg + v][i = 16 t + li]
+#pragma unroll
+      for (int t = 0; t < MT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t a = a0 + 4 * kg + v, i = 16 * t + li;
+          if (a < A && i < m) Y[a * m + i] = acc[t][v];
+        }
     }
-    // D[a = a0 + 4 kg + v][i = 16 t + li]
-#pragma unroll
-    for (int t = 0; t < MT; ++t)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t a = a0 + 4 * kg + v, i = 16 * t + li;
-        if (a < A && i < m) Y[a * m + i] = acc[t][v];
-      }
   }
 }
 
@@ -358,12 +442,26 @@ hipError_t launch_zw_batch(const GZwJob* jobs, const int32_t* blkjob, int64_t to
 }
 
 int64_t ttm_batch_units(int64_t A, int64_t B) { return B == 1 ? (A + 15) / 16 : A * ((B + 63) / 64); }
+bool ttm_batch_fits(int64_t K, int64_t B, int64_t m) { return (B == 1 || B >= 16) && K <= kTBMaxK && m <= 64; }
+int64_t ttm_batch_row_tiles(int64_t A, int64_t B) {
+  if (B != 1) return 1;
+  const int64_t units = ttm_batch_units(A, B);
+  return units >= 1024 ? 4 : units >= 512 ? 2 : 1;  // long jobs: fewer M stagings per row
+}
+int64_t ttm_batch_blocks(int64_t A, int64_t B) {
+  const int64_t per = kBWaves * ttm_batch_row_tiles(A, B);
+  return (ttm_batch_units(A, B) + per - 1) / per;
+}
 
-hipError_t launch_ttm_batch(const GTtmJob* jobs, const int32_t* blkjob, int64_t total_blocks, int mt, rt_dtype xdt,
-                            hipStream_t st) {
+hipError_t launch_ttm_batch(const GTtmJob* jobs, const int32_t* blkjob, int64_t total_blocks, int mt, bool rows,
+                            rt_dtype xdt, hipStream_t st) {
   if (total_blocks == 0) return hipSuccess;
   const unsigned g = static_cast<unsigned>(total_blocks);
-#define RT_TB(TX, N) ttm_batch_kernel<TX, N><<<g, kBThreads, 0, st>>>(jobs, blkjob)
+#define RT_TB(TX, N)                                                         \
+  if (rows)                                                                  \
+    ttm_batch_kernel<TX, N, true><<<g, kBThreads, 0, st>>>(jobs, blkjob);    \
+  else                                                                       \
+    ttm_batch_kernel<TX, N, false><<<g, kBThreads, 0, st>>>(jobs, blkjob)
 #define RT_TB_MT(TX)                      \
   switch (mt) {                           \
     case 1: RT_TB(TX, 1); break;          \

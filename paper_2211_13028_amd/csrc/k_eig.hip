@@ -309,6 +309,64 @@ __global__ __launch_bounds__(kMCThreads) void gram_grouped_kernel(const GGramJob
     }
 }
 
+// Gram matrix of one binary64 (A, m, B) view per workgroup for m <= 32 (the cores of the
+// batched decomposition).  The view is read 64 t = (a, b) at a time into an LDS stage (the
+// next 64 t are in flight while the current ones are multiplied); thread (ty, tx) forms
+// rows 2 ty, 2 ty + 1 and columns 2 tx, 2 tx + 1 of the 32 x 32 result, each entry a
+// sequential fused sum over t in increasing order (so out[i][j] and out[j][i] agree
+// bitwise).  A * B < 2^31.
+constexpr int kGST = 64;                                  // t per stage
+constexpr int kGSStride = 34;                             // even: 16-byte aligned pairs
+constexpr int kGSPer = kGST * 32 / kMCThreads;            // values each thread loads per stage
+__global__ __launch_bounds__(kMCThreads) void gram_small_grouped_kernel(const GGramJob* __restrict__ jobs) {
+  __shared__ __align__(16) double sG[kGST][kGSStride];
+  const GGramJob J = jobs[blockIdx.x];
+  const uint32_t m = static_cast<uint32_t>(J.m), B = static_cast<uint32_t>(J.B);
+  const uint32_t T = static_cast<uint32_t>(J.A * J.B);
+  const int tid = threadIdx.x;
+  // load roles, following memory order: t fastest when rows of b are long, the mode index
+  // fastest otherwise
+  const bool tfast = B >= static_cast<uint32_t>(kGST);
+  const uint32_t lt = tfast ? tid % kGST : tid / 32, li = tfast ? tid / kGST : tid % 32;
+  const uint32_t tstep = tfast ? 0 : kMCThreads / 32, istep = tfast ? kMCThreads / kGST : 0;
+  double v[kGSPer];
+  auto load = [&](uint32_t t0) {
+#pragma unroll
+    for (int q = 0; q < kGSPer; ++q) {
+      const uint32_t t = t0 + lt + tstep * q, i = li + istep * q;
+      const uint32_t a = t / B, b = t - a * B;
+      v[q] = (t < T && i < m) ? J.G[(static_cast<int64_t>(a) * m + i) * B + b] : 0.0;
+    }
+  };
+  const int tx = tid % 16, ty = tid / 16;
+  double acc[2][2] = {};
+  load(0);
+  for (uint32_t t0 = 0; t0 < T; t0 += kGST) {
+    __syncthreads();  // the previous stage has been read
+#pragma unroll
+    for (int q = 0; q < kGSPer; ++q) sG[lt + tstep * q][li + istep * q] = v[q];
+    __syncthreads();
+    if (t0 + kGST < T) load(t0 + kGST);
+    const uint32_t tn = T - t0 < static_cast<uint32_t>(kGST) ? T - t0 : kGST;
+#pragma unroll 4
+    for (uint32_t tt = 0; tt < tn; ++tt) {
+      const double2 a = *reinterpret_cast<const double2*>(&sG[tt][2 * ty]);
+      const double2 b = *reinterpret_cast<const double2*>(&sG[tt][2 * tx]);
+      acc[0][0] = fma(a.x, b.x, acc[0][0]);
+      acc[0][1] = fma(a.x, b.y, acc[0][1]);
+      acc[1][0] = fma(a.y, b.x, acc[1][0]);
+      acc[1][1] = fma(a.y, b.y, acc[1][1]);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+      const uint32_t i = 2 * ty + u, j = 2 * tx + w;
+      if (i < m && j < m) J.out[i * m + j] = acc[u][w];
+    }
+}
+
 // out = sum over chunks of the partial tiles: 16 lanes per output element, each
 // summing every 16th chunk, then a fixed butterfly (deterministic order).
 template <typename T>
@@ -1615,9 +1673,12 @@ hipError_t launch_sym_eig_top(const double* M, int64_t n, int64_t r, double* V, 
   return hipGetLastError();
 }
 
-hipError_t launch_gram_grouped(const GGramJob* jobs, int count, hipStream_t st) {
+hipError_t launch_gram_grouped(const GGramJob* jobs, int count, hipStream_t st, int max_m) {
   if (count == 0) return hipSuccess;
-  gram_grouped_kernel<<<static_cast<unsigned>(count), kMCThreads, 0, st>>>(jobs);
+  if (max_m <= 32)
+    gram_small_grouped_kernel<<<static_cast<unsigned>(count), kMCThreads, 0, st>>>(jobs);
+  else
+    gram_grouped_kernel<<<static_cast<unsigned>(count), kMCThreads, 0, st>>>(jobs);
   return hipGetLastError();
 }
 

@@ -260,85 +260,89 @@ struct CTabPtr {
 };
 
 
-// partial Gram of one 64-row chunk of Y (first pass)
-template <typename TY, typename TAB>
+// partial Gram of one 64-row chunk of Y (first pass); C (32 or 64) bounds the columns and
+// thread (ty, tx) owns a (C / 16) x (C / 16) block of the C x C partial
+template <typename TY, typename TAB, int C = kCols>
 __global__ __launch_bounds__(256) void cq_gram_kernel(TAB tab) {
-  __shared__ double sy[kGramRows][kCols + 1];
+  constexpr int kO = C / 16;
+  constexpr int kStep = 256 / C;  // rows between a thread's loads
+  __shared__ double sy[kGramRows][C + 1];
   const CJob& J = tab[blockIdx.y];
   if (static_cast<int>(blockIdx.x) >= J.chunks) return;
   // the breakdown flag of the job starts cleared (every later kernel reads it)
   if (blockIdx.x == 0 && threadIdx.x == 0) *J.flag = 0;
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kGramRows;
-  // thread: column j of rows rr0 + 4 q; every load is issued before the first LDS store
-  constexpr int kPer = kGramRows * kCols / 256;
-  const int j = static_cast<int>(threadIdx.x) % kCols, rr0 = static_cast<int>(threadIdx.x) / kCols;
+  // thread: column j of rows rr0 + kStep q; every load is issued before the first LDS store
+  constexpr int kPer = kGramRows * C / 256;
+  const int j = static_cast<int>(threadIdx.x) % C, rr0 = static_cast<int>(threadIdx.x) / C;
   const TY* ys = static_cast<const TY*>(J.Y) + col_offset(j, J.m, J.B);
   double yv[kPer];
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
-    const int64_t r = r0 + rr0 + 4 * q;
+    const int64_t r = r0 + rr0 + kStep * q;
     yv[q] = (r < J.m && j < J.n) ? static_cast<double>(ys[r * J.B]) : 0.0;
   }
 #pragma unroll
-  for (int q = 0; q < kPer; ++q) sy[rr0 + 4 * q][j] = yv[q];
+  for (int q = 0; q < kPer; ++q) sy[rr0 + kStep * q][j] = yv[q];
   __syncthreads();
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  double acc[4][4] = {};
+  double acc[kO][kO] = {};
   for (int rr = 0; rr < kGramRows; ++rr) {
-    double a[4], b[4];
+    double a[kO], b[kO];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) { a[u] = sy[rr][ty * 4 + u]; b[u] = sy[rr][tx * 4 + u]; }
+    for (int u = 0; u < kO; ++u) { a[u] = sy[rr][ty * kO + u]; b[u] = sy[rr][tx * kO + u]; }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < kO; ++u)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+      for (int v = 0; v < kO; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
   }
-  double* out = J.part + static_cast<int64_t>(blockIdx.x) * kCols * kCols;
+  double* out = J.part + static_cast<int64_t>(blockIdx.x) * C * C;
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int u = 0; u < kO; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) out[(ty * 4 + u) * kCols + tx * 4 + v] = acc[u][v];
+    for (int v = 0; v < kO; ++v) out[(ty * kO + u) * C + tx * kO + v] = acc[u][v];
 }
 
 
 // Sum the partial Grams (fixed order), factor G = R^T R (upper R) and form R^-1: the
 // symmetric elimination on [G | I] turns the left block into R and the right block into
-// R^-T.  Four waves; thread (wave w, lane j) keeps column j of rows 16 w .. 16 w + 15 of
-// both blocks in registers for the whole factorisation.  After each step the wave that
+// R^-T.  Four waves; thread (wave w, lane j) keeps column j of rows C/4 w .. C/4 (w + 1) - 1
+// of both blocks in registers for the whole factorisation (C = 32: lanes 32 .. 63 hold no
+// column and store nothing).  After each step the wave that
 // owns the next pivot row stores all its 16 rows to LDS (static register indices; rows
 // that are not being eliminated keep their values, so concurrent readers of the current
 // row see the same bits), and a step touches LDS only for reads of that row.  Every wave keeps the diagonal in registers (lane j:
-// G[j][j], updated with the same rounding as the matrix).  R goes to the first kCols^2
+// G[j][j], updated with the same rounding as the matrix).  R goes to the first C^2
 // doubles of the job's R1 / R2 buffer, R^-1 to the second.
-template <typename TAB>
+template <typename TAB, int C = kCols>
 __global__ __launch_bounds__(256) void cq_chol_kernel(TAB tab, int second) {
   constexpr int kW = 256 / kWave;
-  constexpr int kRows = kCols / kW;
-  __shared__ __align__(16) double fullL[kCols][kCols];  // the rows of the owner of the next row
-  __shared__ __align__(16) double fullR[kCols][kCols];
-  __shared__ double Rs[kCols][kCols + 1];
-  __shared__ double Xs[kCols][kCols + 1];
+  constexpr int kRows = C / kW;
+  __shared__ __align__(16) double fullL[C][kWave];  // the rows of the owner of the next row
+  __shared__ __align__(16) double fullR[C][kWave];
+  __shared__ double Rs[C][C + 1];
+  __shared__ double Xs[C][C + 1];
   const CJob& J = tab[blockIdx.x];
   if (*J.flag) return;  // cleared by cq_gram_kernel before the first pass
   const int n = J.n;
   const int lane = static_cast<int>(threadIdx.x) % kWave, wv = static_cast<int>(threadIdx.x) / kWave;
-  const double* part = J.part + (second ? static_cast<int64_t>(J.chunks) * kCols * kCols : 0);
+  const double* part = J.part + (second ? static_cast<int64_t>(J.chunks) * C * C : 0);
   double gl[kRows], gr[kRows];
 #pragma unroll
   for (int t = 0; t < kRows; ++t) gl[t] = 0.0;
   // chunk partials in chunk order; the loads of two chunks are in flight together
 #pragma unroll 2
   for (int c = 0; c < J.chunks; ++c) {
-    const double* pc = part + static_cast<int64_t>(c) * kCols * kCols + kRows * wv * kCols + lane;
+    const double* pc = part + static_cast<int64_t>(c) * C * C + kRows * wv * C + (lane < C ? lane : 0);
     double v[kRows];
 #pragma unroll
-    for (int t = 0; t < kRows; ++t) v[t] = pc[t * kCols];
+    for (int t = 0; t < kRows; ++t) v[t] = lane < C ? pc[t * C] : 0.0;
 #pragma unroll
     for (int t = 0; t < kRows; ++t) gl[t] += v[t];
   }
 #pragma unroll
   for (int t = 0; t < kRows; ++t) gr[t] = (kRows * wv + t == lane) ? 1.0 : 0.0;
-  for (int idx = threadIdx.x; idx < kCols * (kCols + 1); idx += 256) {
+  for (int idx = threadIdx.x; idx < C * (C + 1); idx += 256) {
     (&Rs[0][0])[idx] = 0.0;
     (&Xs[0][0])[idx] = 0.0;
   }
@@ -374,7 +378,7 @@ __global__ __launch_bounds__(256) void cq_chol_kernel(TAB tab, int second) {
   // the loop is unrolled over k, so the owner of the next pivot row stores that row alone
   // (its register slot is static), and the other steps' stores are skipped
 #pragma clang loop unroll(full)
-  for (int k = 0; k < kCols; ++k) {
+  for (int k = 0; k < C; ++k) {
     if (k >= n || broke) continue;  // uniform
     const double lk = fullL[k][lane], rk = fullR[k][lane];
     double li[kRows];
@@ -417,16 +421,16 @@ __global__ __launch_bounds__(256) void cq_chol_kernel(TAB tab, int second) {
     return;
   }
   double* R = second ? J.R2 : J.R1;
-  for (int idx = threadIdx.x; idx < kCols * kCols; idx += 256) {
-    const int i = idx / kCols, j = idx % kCols;
+  for (int idx = threadIdx.x; idx < C * C; idx += 256) {
+    const int i = idx / C, j = idx % C;
     const bool in = i < n && j < n && j >= i;
     R[idx] = in ? Rs[i][j] : 0.0;
-    R[kCols * kCols + idx] = in ? Xs[i][j] : 0.0;
+    R[C * C + idx] = in ? Xs[i][j] : 0.0;
   }
   if (second && J.Rout) {
     // R = R2 R1 with R1 staged in LDS (the inverse array is free now)
     __syncthreads();
-    for (int idx = threadIdx.x; idx < n * kCols; idx += 256) Xs[idx / kCols][idx % kCols] = J.R1[idx];
+    for (int idx = threadIdx.x; idx < n * C; idx += 256) Xs[idx / C][idx % C] = J.R1[idx];
     __syncthreads();
     for (int idx = threadIdx.x; idx < n * n; idx += 256) {
       const int i = idx / n, j = idx % n;
@@ -443,92 +447,102 @@ __global__ __launch_bounds__(256) void cq_chol_kernel(TAB tab, int second) {
 }
 
 // 64 rows of Q = Y R^-1 per workgroup as a product with the explicit inverse from
-// cq_chol_kernel (4 x 4 outputs per thread); the first pass also stores Q1 and the
+// cq_chol_kernel (4 x C/16 outputs per thread); the first pass also stores Q1 and the
 // partial Gram of its rows
-template <typename TY, typename TAB>
+template <typename TY, typename TAB, int C = kCols>
 __global__ __launch_bounds__(256) void cq_apply_kernel(TAB tab, int second) {
-  constexpr int kS = kCols + 2;  // even row stride keeps the double2 reads aligned
+  constexpr int kS = C + 2;  // even row stride keeps the double2 reads aligned
+  constexpr int kO = C / 16;
+  constexpr int kStep = 256 / C;
   __shared__ __align__(16) double sy[kGramRows][kS];
-  __shared__ __align__(16) double sx[kCols][kS];
+  __shared__ __align__(16) double sx[C][kS];
   const CJob& J = tab[blockIdx.y];
   if (static_cast<int>(blockIdx.x) >= J.chunks) return;
   if (*J.flag) return;
   const int n = J.n;
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kGramRows;
-  const double* Xg = (second ? J.R2 : J.R1) + kCols * kCols;
+  const double* Xg = (second ? J.R2 : J.R1) + C * C;
   {
-    // thread: column j of rows rr0 + 4 q; every load is issued before the first LDS store
-    constexpr int kPer = kGramRows * kCols / 256;
-    const int j = static_cast<int>(threadIdx.x) % kCols, rr0 = static_cast<int>(threadIdx.x) / kCols;
+    // thread: column j of rows rr0 + kStep q (of the Y chunk, and of R^-1 for rows below
+    // C); every load is issued before the first LDS store
+    constexpr int kPer = kGramRows * C / 256;
+    constexpr int kPerX = C * C / 256;
+    const int j = static_cast<int>(threadIdx.x) % C, rr0 = static_cast<int>(threadIdx.x) / C;
     const TY* ys = static_cast<const TY*>(J.Y) + col_offset(j, J.m, J.B);
-    double yv[kPer], xv[kPer];
+    double yv[kPer], xv[kPerX];
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-      const int rr = rr0 + 4 * q;
-      const int64_t r = r0 + rr;
+      const int64_t r = r0 + rr0 + kStep * q;
       double v = 0.0;
       if (r < J.m && j < n) v = second ? J.Q1[r * n + j] : static_cast<double>(ys[r * J.B]);
       yv[q] = v;
-      xv[q] = Xg[rr * kCols + j];
     }
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      sy[rr0 + 4 * q][j] = yv[q];
-      sx[rr0 + 4 * q][j] = xv[q];
-    }
+    for (int q = 0; q < kPerX; ++q) xv[q] = Xg[(rr0 + kStep * q) * C + j];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) sy[rr0 + kStep * q][j] = yv[q];
+#pragma unroll
+    for (int q = 0; q < kPerX; ++q) sx[rr0 + kStep * q][j] = xv[q];
   }
   __syncthreads();
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   {
-    double acc[4][4] = {};
+    double acc[4][kO] = {};
 #pragma unroll 4
     for (int t = 0; t < n; ++t) {
-      double a[4];
+      double a[4], b[kO];
 #pragma unroll
       for (int u = 0; u < 4; ++u) a[u] = sy[ty * 4 + u][t];
-      const double2 b0 = *reinterpret_cast<const double2*>(&sx[t][tx * 4]);
-      const double2 b1 = *reinterpret_cast<const double2*>(&sx[t][tx * 4 + 2]);
-      const double b[4] = {b0.x, b0.y, b1.x, b1.y};
+#pragma unroll
+      for (int v = 0; v < kO; v += 2) {
+        const double2 bv = *reinterpret_cast<const double2*>(&sx[t][tx * kO + v]);
+        b[v] = bv.x;
+        b[v + 1] = bv.y;
+      }
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+        for (int v = 0; v < kO; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
     }
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) sy[ty * 4 + u][tx * 4 + v] = acc[u][v];
+      for (int v = 0; v < kO; ++v) sy[ty * 4 + u][tx * kO + v] = acc[u][v];
   }
   __syncthreads();
   double* out = second ? J.Q : J.Q1;
-  for (int idx = threadIdx.x; idx < kGramRows * kCols; idx += 256) {
-    const int rr = idx / kCols, j = idx % kCols;
+  for (int idx = threadIdx.x; idx < kGramRows * C; idx += 256) {
+    const int rr = idx / C, j = idx % C;
     const int64_t r = r0 + rr;
     if (r < J.m && j < n) out[r * n + j] = sy[rr][j];
   }
   if (second) return;
   // partial Gram of these Q1 rows for the second pass (rows past m and columns past n
   // are zero: the inputs there were zero)
-  double g[4][4] = {};
+  double g[kO][kO] = {};
 #pragma unroll 4
   for (int rr = 0; rr < kGramRows; ++rr) {
-    const double2 a0 = *reinterpret_cast<const double2*>(&sy[rr][ty * 4]);
-    const double2 a1 = *reinterpret_cast<const double2*>(&sy[rr][ty * 4 + 2]);
-    const double2 b0 = *reinterpret_cast<const double2*>(&sy[rr][tx * 4]);
-    const double2 b1 = *reinterpret_cast<const double2*>(&sy[rr][tx * 4 + 2]);
-    const double a[4] = {a0.x, a0.y, a1.x, a1.y};
-    const double b[4] = {b0.x, b0.y, b1.x, b1.y};
+    double a[kO], b[kO];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int v = 0; v < kO; v += 2) {
+      const double2 av = *reinterpret_cast<const double2*>(&sy[rr][ty * kO + v]);
+      const double2 bv = *reinterpret_cast<const double2*>(&sy[rr][tx * kO + v]);
+      a[v] = av.x;
+      a[v + 1] = av.y;
+      b[v] = bv.x;
+      b[v + 1] = bv.y;
+    }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) g[u][v] = fma(a[u], b[v], g[u][v]);
+    for (int u = 0; u < kO; ++u)
+#pragma unroll
+      for (int v = 0; v < kO; ++v) g[u][v] = fma(a[u], b[v], g[u][v]);
   }
-  double* gp = J.part + (static_cast<int64_t>(J.chunks) + blockIdx.x) * kCols * kCols;
+  double* gp = J.part + (static_cast<int64_t>(J.chunks) + blockIdx.x) * C * C;
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int u = 0; u < kO; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) gp[(ty * 4 + u) * kCols + tx * 4 + v] = g[u][v];
+    for (int v = 0; v < kO; ++v) gp[(ty * kO + u) * C + tx * kO + v] = g[u][v];
 }
 
 
@@ -754,21 +768,33 @@ hipError_t launch_qr_grouped(const GQrJob* jobs, int count, rt_dtype ydt, hipStr
   return hipGetLastError();
 }
 
-hipError_t launch_cholqr2_grouped(const GCholQRJob* jobs, int count, int max_chunks, rt_dtype ydt, hipStream_t st) {
-  if (count == 0) return hipSuccess;
-  const CTabPtr tp{jobs};
+namespace {
+template <int C>
+void cholqr2_grouped(const CTabPtr tp, int count, int max_chunks, rt_dtype ydt, hipStream_t st) {
   const dim3 g1(static_cast<unsigned>(max_chunks), static_cast<unsigned>(count));
   if (ydt == RT_F64) {
-    cq_gram_kernel<double><<<g1, 256, 0, st>>>(tp);
-    cq_chol_kernel<<<count, 256, 0, st>>>(tp, 0);
-    cq_apply_kernel<double><<<g1, 256, 0, st>>>(tp, 0);
+    cq_gram_kernel<double, CTabPtr, C><<<g1, 256, 0, st>>>(tp);
+    cq_chol_kernel<CTabPtr, C><<<count, 256, 0, st>>>(tp, 0);
+    cq_apply_kernel<double, CTabPtr, C><<<g1, 256, 0, st>>>(tp, 0);
   } else {
-    cq_gram_kernel<float><<<g1, 256, 0, st>>>(tp);
-    cq_chol_kernel<<<count, 256, 0, st>>>(tp, 0);
-    cq_apply_kernel<float><<<g1, 256, 0, st>>>(tp, 0);
+    cq_gram_kernel<float, CTabPtr, C><<<g1, 256, 0, st>>>(tp);
+    cq_chol_kernel<CTabPtr, C><<<count, 256, 0, st>>>(tp, 0);
+    cq_apply_kernel<float, CTabPtr, C><<<g1, 256, 0, st>>>(tp, 0);
   }
-  cq_chol_kernel<<<count, 256, 0, st>>>(tp, 1);
-  cq_apply_kernel<double><<<g1, 256, 0, st>>>(tp, 1);
+  cq_chol_kernel<CTabPtr, C><<<count, 256, 0, st>>>(tp, 1);
+  cq_apply_kernel<double, CTabPtr, C><<<g1, 256, 0, st>>>(tp, 1);
+}
+}  // namespace
+
+hipError_t launch_cholqr2_grouped(const GCholQRJob* jobs, int count, int max_chunks, rt_dtype ydt, hipStream_t st,
+                                  int cols) {
+  if (count == 0) return hipSuccess;
+  if (cols != 32 && cols != 64) return hipErrorInvalidValue;
+  const CTabPtr tp{jobs};
+  if (cols == 32)
+    cholqr2_grouped<32>(tp, count, max_chunks, ydt, st);
+  else
+    cholqr2_grouped<64>(tp, count, max_chunks, ydt, st);
   return hipGetLastError();
 }
 

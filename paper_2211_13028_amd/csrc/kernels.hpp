@@ -251,13 +251,18 @@ struct GZwJob {
 int zw_batch_class(int64_t Q);
 hipError_t launch_zw_batch(const GZwJob* jobs, const int32_t* blkjob, int64_t total_blocks, int ng, rt_dtype xdt,
                            hipStream_t st);
-// k_batch.hip: the first core contraction of every tensor of a batch on matrix cores,
-// Y = X x_k M for (A, K, B) views with B == 1 or B >= 16, m <= 16 mt; binary32 or
-// bfloat16 X, binary32 M and Y.  A job has colblocks = ttm_batch_units(A, B) units (one
-// wave each), four per workgroup from blk0 on; blkjob maps workgroups to jobs.
+// k_batch.hip: core contractions of every tensor of a batch on matrix cores,
+// Y = X x_k M for (A, K, B) views with B == 1 (rows = true) or B >= 16 (rows = false),
+// K <= 256, m <= 16 mt (ttm_batch_fits); binary32 or bfloat16 X, binary32 M (bfloat16
+// values for bfloat16 X) and Y.  A job has colblocks = ttm_batch_units(A, B) units (one
+// wave each, B == 1: 16-row tiles), taking ttm_batch_blocks(A, B) workgroups from blk0 on;
+// blkjob maps workgroups to jobs.
 int64_t ttm_batch_units(int64_t A, int64_t B);
-hipError_t launch_ttm_batch(const GTtmJob* jobs, const int32_t* blkjob, int64_t total_blocks, int mt, rt_dtype xdt,
-                            hipStream_t st);
+int64_t ttm_batch_blocks(int64_t A, int64_t B);
+int64_t ttm_batch_row_tiles(int64_t A, int64_t B);  // the job's mtiles (B == 1: units per wave)
+bool ttm_batch_fits(int64_t K, int64_t B, int64_t m);
+hipError_t launch_ttm_batch(const GTtmJob* jobs, const int32_t* blkjob, int64_t total_blocks, int mt, bool rows,
+                            rt_dtype xdt, hipStream_t st);
 
 // k_qr.hip: thin Householder QR of (A, m, B) views with m <= 256 rows and
 // n = A*B <= 64 columns, one workgroup per job; Q: m x qcols (qcols = min(m, n)).
@@ -290,7 +295,11 @@ struct GCholQRJob {
   int32_t* flag;
   double shift1, shift2;
 };
-hipError_t launch_cholqr2_grouped(const GCholQRJob* jobs, int count, int max_chunks, rt_dtype ydt, hipStream_t st);
+// cols (32 or 64): every job of the launch has n <= cols, and its buffers are read with
+// cols in place of 64 (part: 2 x chunks x cols x cols, R1 / R2: 2 x cols x cols), so
+// 64-column allocations serve both widths.
+hipError_t launch_cholqr2_grouped(const GCholQRJob* jobs, int count, int max_chunks, rt_dtype ydt, hipStream_t st,
+                                  int cols = 64);
 
 // k_eig.hip: Gram matrices out = G_(n) G_(n)^T of binary64 (A, m, B) views
 // (m <= 64), and the eigensolver of launch_sym_eig_top, one workgroup per job.
@@ -299,7 +308,8 @@ struct GGramJob {
   double* out;
   int64_t A, m, B;
 };
-hipError_t launch_gram_grouped(const GGramJob* jobs, int count, hipStream_t st);
+// max_m: the largest m of the jobs (<= 64); at most 32 selects the small-core kernel (A B < 2^31)
+hipError_t launch_gram_grouped(const GGramJob* jobs, int count, hipStream_t st, int max_m = 64);
 struct GEigJob {
   const double* M;
   double* V;
