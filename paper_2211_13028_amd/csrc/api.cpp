@@ -1084,7 +1084,7 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
   std::vector<GCopyJob> cp;
   std::vector<GGramJob> gram[3];
   std::vector<GEigJob> eig[3];
-  int gram_mmax[3] = {0, 0, 0};
+  int gram_mmax[3] = {0, 0, 0}, eig_rmax[3] = {0, 0, 0};
   int64_t max_prep_sk = 1, max_prep_core = 1, max_cp = 1;
   int64_t zw_blocks[4] = {0, 0, 0, 0}, tree_blocks = 0, core_blocks[3] = {0, 0, 0}, g_blocks[3] = {0, 0, 0},
           u_blocks[3] = {0, 0, 0};
@@ -1195,6 +1195,7 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
       gram[j].push_back(GGramJob{gcur, M, A, cj, B});
       gram_mmax[j] = std::max<int>(gram_mmax[j], static_cast<int>(cj));
       eig[j].push_back(GEigJob{M, V, static_cast<int32_t>(cj), t.r[j]});
+      eig_rmax[j] = std::max<int>(eig_rmax[j], t.r[j]);
       double* gnext = (j == d - 1) ? b.G : static_cast<double*>(c.take(static_cast<size_t>(A) * t.r[j] * B * 8));
       gttm[j].push_back(GTtmJob{gcur, V, gnext, A, cj, B, t.r[j], g_blocks[j], ceil_div(A * B, kWave),
                                 ceil_div(t.r[j], 16), 1, 0});
@@ -1288,7 +1289,7 @@ int plan_batched_impl(Ctx& c, int32_t count, const rt_batch_item* items, int32_t
   c.chk(launch_copy_f64_grouped(reinterpret_cast<const GCopyJob*>(at(o_cp)), count, max_cp, st));
   for (int j = 0; j < 3; ++j) {
     c.chk(launch_gram_grouped(reinterpret_cast<const GGramJob*>(at(o_gram[j])), count, st, gram_mmax[j]));
-    c.chk(launch_eig_grouped(reinterpret_cast<const GEigJob*>(at(o_eig[j])), count, st));
+    c.chk(launch_eig_grouped(reinterpret_cast<const GEigJob*>(at(o_eig[j])), count, st, eig_rmax[j]));
     c.chk(launch_ttm_grouped(reinterpret_cast<const GTtmJob*>(at(o_g[j])), imap(m_g[j]), count, g_blocks[j], RT_F64,
                              16, st));
     c.chk(launch_ttm_grouped(reinterpret_cast<const GTtmJob*>(at(o_u[j])), imap(m_u[j]), count, u_blocks[j], RT_F64,

@@ -842,11 +842,9 @@ constexpr int kTriMaxR = 32;
 constexpr int kMsGroup = 8;    // lanes per eigenvalue in the multisection (r <= 32: four waves)
 constexpr int kMsIters = 18;   // 9^18 > 2^57: the bracket reaches rounding level of |T|
 constexpr int kInvIters = 2;
-constexpr int kEStride = kTriMaxR + 1;
-// scratch region B (doubles): five n x 32 arrays of the inverse iteration; aliased by the
-// per-wave vectors and partial sums of phase 1, by E and F of phase 4, and by the Jacobi L
-constexpr int kTriB = 5 * kJN * kTriMaxR;
-static_assert(kTriB >= kJN * kLStride, "Jacobi columns must fit the tridiagonal scratch");
+// scratch region B (doubles): five n x RM arrays of the inverse iteration (RM: the bound on
+// r); aliased by the per-wave vectors and partial sums of phase 1, by E and F of phase 4,
+// and by the Jacobi L
 
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ double dpp_rows_f64(double v, double old) {
@@ -957,9 +955,10 @@ __device__ __forceinline__ int sturm_count(const double* __restrict__ d, const d
 
 constexpr int kP1Waves = 4;
 constexpr int kP1Cols = kJN / kP1Waves;  // matrix columns held in registers per wave
-static_assert(kTriB >= 4 * kP1Waves * kJN + 2 * kJN, "phase-1 scratch must fit");
 
-// Returns true (uniformly over the workgroup) when V and evals were written.
+// Returns true (uniformly over the workgroup) when V and evals were written.  RM (32 or
+// 16) bounds r: the scratch B holds 5 kJN RM doubles.
+template <int RM>
 __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n, int r, double* __restrict__ Vout,
                                             double* __restrict__ evals, double* __restrict__ Am,
                                             double* __restrict__ B) {
@@ -1131,7 +1130,7 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
   }
   __syncthreads();
   // ---- 2. multisection: group g brackets the g-th largest eigenvalue
-  if (tid < kMsGroup * kTriMaxR) {
+  if (tid < kMsGroup * RM) {
     const int g = tid / kMsGroup, sub = tid % kMsGroup;
     const int target = n - 1 - g;  // count(x) > target  <=>  x above the g-th largest
     double a = bounds[0], b = bounds[1];
@@ -1153,7 +1152,7 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
   __syncthreads();
   // ---- 3. inverse iteration, lane m of wave 0 for eigenvalue m.  Loops run over rows with
   //         the row data for the next iterations loaded ahead (unrolled by four).
-  auto F = [&](int f, int i, int m) -> double& { return B[(f * kJN + i) * kTriMaxR + m]; };
+  auto F = [&](int f, int i, int m) -> double& { return B[(f * kJN + i) * RM + m]; };
   constexpr int IU0 = 0, U1 = 1, U2 = 2, ML = 3, ZZ = 4;
   if (wv == 0 && lane < r) {
     const int m = lane;
@@ -1227,8 +1226,8 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
   }
   __syncthreads();
   // ---- 4. orthogonality check E = Z^T Z - I (upper triangle) and residual check
-  double* E = B;                          // r x r, stride kEStride (the LU factors are dead now)
-  double* Fm = B + kTriMaxR * kEStride;   // I - E/2 + 3 E^2 / 8
+  double* E = B;                          // r x r, stride (RM + 1) (the LU factors are dead now)
+  double* Fm = B + RM * (RM + 1);   // I - E/2 + 3 E^2 / 8
   double emax = 0.0;
   for (int q = tid; q < r * r; q += kJThreads) {
     const int a = q / r, c = q - (q / r) * r;
@@ -1244,16 +1243,16 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
     }
     for (; i < n; ++i) s0 = fma(F(ZZ, i, a), F(ZZ, i, c), s0);
     const double eac = ((s0 + s1) + (s2 + s3)) - (a == c ? 1.0 : 0.0);
-    E[a * kEStride + c] = eac;
-    E[c * kEStride + a] = eac;
+    E[a * (RM + 1) + c] = eac;
+    E[c * (RM + 1) + a] = eac;
     emax = fmax(emax, fabs(eac));
   }
-  constexpr int kPer = (kJN * kTriMaxR + kJThreads - 1) / kJThreads;
+  constexpr int kPer = (kJN * RM + kJThreads - 1) / kJThreads;
   double rmax = 0.0;
 #pragma unroll
   for (int t = 0; t < kPer; ++t) {
     const int q = tid + t * kJThreads;
-    const int i = q / kTriMaxR, m = q % kTriMaxR;
+    const int i = q / RM, m = q % RM;
     if (i < n && m < r) {
       double tz = fma(dS[i] - lamS[m], F(ZZ, i, m), 0.0);
       if (i > 0) tz = fma(eS[i - 1], F(ZZ, i - 1, m), tz);
@@ -1279,25 +1278,25 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
     for (int q = tid; q < r * r; q += kJThreads) {
       const int a = q / r, c = q - (q / r) * r;
       double sacc = 0.0;
-      for (int b2 = 0; b2 < r; ++b2) sacc = fma(E[a * kEStride + b2], E[b2 * kEStride + c], sacc);
-      Fm[a * kEStride + c] = fma(0.375, sacc, fma(-0.5, E[a * kEStride + c], a == c ? 1.0 : 0.0));
+      for (int b2 = 0; b2 < r; ++b2) sacc = fma(E[a * (RM + 1) + b2], E[b2 * (RM + 1) + c], sacc);
+      Fm[a * (RM + 1) + c] = fma(0.375, sacc, fma(-0.5, E[a * (RM + 1) + c], a == c ? 1.0 : 0.0));
     }
     __syncthreads();
     double zn[kPer];
 #pragma unroll
     for (int t = 0; t < kPer; ++t) {
       const int q = tid + t * kJThreads;
-      const int i = q / kTriMaxR, m = q % kTriMaxR;
+      const int i = q / RM, m = q % RM;
       double sacc = 0.0;
       if (i < n && m < r)
-        for (int c = 0; c < r; ++c) sacc = fma(F(ZZ, i, c), Fm[c * kEStride + m], sacc);
+        for (int c = 0; c < r; ++c) sacc = fma(F(ZZ, i, c), Fm[c * (RM + 1) + m], sacc);
       zn[t] = sacc;
     }
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < kPer; ++t) {
       const int q = tid + t * kJThreads;
-      const int i = q / kTriMaxR, m = q % kTriMaxR;
+      const int i = q / RM, m = q % RM;
       if (i < n && m < r) F(ZZ, i, m) = zn[t];
     }
     __syncthreads();
@@ -1415,12 +1414,15 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
   return true;
 }
 
+template <int RM>
 __device__ __forceinline__ void eig_body(const double* __restrict__ M, int n, int r, double* __restrict__ Vout,
                                          double* __restrict__ evals) {
   __shared__ __align__(16) double Am[kJN * kAStride];
-  __shared__ __align__(16) double B[kTriB];
-  if (n >= 3 && r <= kTriMaxR) {
-    if (eig_tridiag(M, n, r, Vout, evals, Am, B)) return;
+  static_assert(5 * kJN * RM >= kJN * kLStride, "Jacobi columns must fit the tridiagonal scratch");
+  static_assert(5 * kJN * RM >= 4 * kP1Waves * kJN + 2 * kJN, "phase-1 scratch must fit");
+  __shared__ __align__(16) double B[5 * kJN * RM];
+  if (n >= 3 && r <= RM) {
+    if (eig_tridiag<RM>(M, n, r, Vout, evals, Am, B)) return;
     __syncthreads();
   }
   eig_jacobi(M, n, r, Vout, evals, Am, B);
@@ -1429,12 +1431,14 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ M, int n, in
 __global__ __launch_bounds__(kJThreads) void eig_onesided_kernel(const double* __restrict__ M, int n, int r,
                                                                  double* __restrict__ Vout,
                                                                  double* __restrict__ evals) {
-  eig_body(M, n, r, Vout, evals);
+  eig_body<kTriMaxR>(M, n, r, Vout, evals);
 }
 
+// RM = 16 (every job r <= 16) halves the scratch, so two workgroups share a CU
+template <int RM>
 __global__ __launch_bounds__(kJThreads) void eig_grouped_kernel(const GEigJob* __restrict__ jobs) {
   const GEigJob J = jobs[blockIdx.x];
-  eig_body(J.M, J.n, J.r, J.V, nullptr);
+  eig_body<RM>(J.M, J.n, J.r, J.V, nullptr);
 }
 
 }  // namespace
@@ -1682,9 +1686,12 @@ hipError_t launch_gram_grouped(const GGramJob* jobs, int count, hipStream_t st, 
   return hipGetLastError();
 }
 
-hipError_t launch_eig_grouped(const GEigJob* jobs, int count, hipStream_t st) {
+hipError_t launch_eig_grouped(const GEigJob* jobs, int count, hipStream_t st, int max_r) {
   if (count == 0) return hipSuccess;
-  eig_grouped_kernel<<<static_cast<unsigned>(count), kJThreads, 0, st>>>(jobs);
+  if (max_r <= 16)
+    eig_grouped_kernel<16><<<static_cast<unsigned>(count), kJThreads, 0, st>>>(jobs);
+  else
+    eig_grouped_kernel<kTriMaxR><<<static_cast<unsigned>(count), kJThreads, 0, st>>>(jobs);
   return hipGetLastError();
 }
 

@@ -315,6 +315,7 @@ struct GEigJob {
   double* V;
   int32_t n, r;
 };
-hipError_t launch_eig_grouped(const GEigJob* jobs, int count, hipStream_t st);
+// max_r: the largest r of the jobs; at most 16 selects the half-scratch variant
+hipError_t launch_eig_grouped(const GEigJob* jobs, int count, hipStream_t st, int max_r = 32);
 
 }  // namespace rt
