@@ -179,6 +179,155 @@ __global__ __launch_bounds__(kBThreads, NG > 12 ? 1 : 2) void zw_batch_kernel(co
   }
 }
 
+// bfloat16 X: the same pass with 16x16x16 bfloat16 products (binary32 accumulation; Phi_2 and
+// Phi_3 hold bfloat16 values, so every product is exact and only the accumulation order
+// differs from the binary32 path).  Lane (li, kg) loads rows pb + 4 kg + e (e < 4) at
+// columns 16 g + li, four consecutive k of one column as the B operand of W^T (A = Phi_2[li]
+// at the same rows); for Z the step is staged in binary32 as above and read back four
+// consecutive columns of row li at a time (A), with Phi_3 kept in LDS as bfloat16 (B).  A
+// quarter of the binary32 path's matrix-core instructions.
+typedef short zb_s16x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t zb_u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t zb_pack(uint32_t lo16, uint32_t hi16) { return lo16 | (hi16 << 16); }
+__device__ __forceinline__ uint32_t zb_pack_f(float lo, float hi) {
+  return (__float_as_uint(lo) >> 16) | (__float_as_uint(hi) & 0xffff0000u);
+}
+
+template <int NG>
+__global__ __launch_bounds__(kBThreads, NG > 12 ? 1 : 2) void zw_batch_bf16_kernel(const GZwJob* __restrict__ jobs,
+                                                                    const int32_t* __restrict__ blkjob) {
+  constexpr int S16 = 16 * NG + 8;  // bfloat16 per Phi_3 row (8-byte reads stay aligned)
+  __shared__ __align__(16) bf16_t sPhi16[16 * S16];
+  __shared__ __align__(16) float sStage[kBWaves][16 * kStageStride];
+  const GZwJob J = jobs[blkjob[blockIdx.x]];
+  const int64_t P = J.P, Q = J.Q, A = J.A;
+  const int sP = J.sP, sQ = J.sQ;
+  const bool needZ = J.Z != nullptr, needW = J.W != nullptr;
+  const int lane = threadIdx.x % kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int li = lane % 16, kg = lane / 16;
+  const int64_t local = blockIdx.x - J.blk0;
+  const int64_t a_first = local * kBWaves * J.spb + wave;
+  const int64_t a_end = (local + 1) * kBWaves * J.spb < A ? (local + 1) * kBWaves * J.spb : A;
+  const int steps = static_cast<int>((P + 15) / 16);
+  float* st = sStage[wave];
+  const gptr<const bf16_t> X = global_ptr(static_cast<const bf16_t*>(J.X));
+  const gptr<const float> phiP = global_ptr(J.phiP);
+  const gptr<float> Zo = global_ptr(J.Z), Wo = global_ptr(J.W);
+  uint32_t qoff[NG];
+  bool qok[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    const int q = 16 * g + li;
+    qok[g] = q < Q;
+    qoff[g] = static_cast<uint32_t>(q < Q ? q : Q - 1);
+  }
+  const int pc_lane = li < sP ? li : sP - 1;
+  // raw values of the next step: rows pb + 4 kg + e
+  bf16_t rn[4][NG];
+  float ppn[4];
+  auto load = [&](int64_t a, int64_t pb) {
+    const gptr<const bf16_t> xa = X + a * P * Q;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t p = pb + 4 * kg + e;
+      const uint32_t prow = static_cast<uint32_t>((p < P ? p : P - 1) * Q);
+#pragma unroll
+      for (int g = 0; g < NG; ++g) rn[e][g] = xa[prow + qoff[g]];
+      ppn[e] = needW ? phiP[static_cast<int64_t>(pc_lane) * P + (p < P ? p : P - 1)] : 0.f;
+    }
+  };
+  if (a_first < a_end) load(a_first, 0);  // in flight while Phi_3 is staged
+  for (int idx = threadIdx.x; idx < 16 * S16; idx += kBThreads) {
+    const int c = idx / S16, q = idx - (idx / S16) * S16;
+    const float v = (needZ && c < sQ && q < Q) ? global_ptr(J.phiQ)[static_cast<int64_t>(c) * Q + q] : 0.f;
+    sPhi16[idx] = static_cast<bf16_t>(__float_as_uint(v) >> 16);
+  }
+  __syncthreads();
+  if (a_first >= a_end) return;
+
+  bf32x4 wacc[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) wacc[g] = bf32x4{0.f, 0.f, 0.f, 0.f};
+  int64_t a = a_first;
+  int step = 0;
+  while (true) {
+    const int64_t pb = static_cast<int64_t>(step) * 16;
+    // operands of the step, zero past P, past Q and past s2: pairs of rows packed per word
+    uint32_t rp[2][NG], pw[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const bool in0 = pb + 4 * kg + 2 * h < P, in1 = pb + 4 * kg + 2 * h + 1 < P;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        const uint32_t lo = (in0 && qok[g]) ? static_cast<uint32_t>(rn[2 * h][g]) : 0u;
+        const uint32_t hi = (in1 && qok[g]) ? static_cast<uint32_t>(rn[2 * h + 1][g]) : 0u;
+        rp[h][g] = zb_pack(lo, hi);
+      }
+      const bool pl = li < sP;
+      pw[h] = zb_pack_f((in0 && pl) ? ppn[2 * h] : 0.f, (in1 && pl) ? ppn[2 * h + 1] : 0.f);
+    }
+    const bool last_of_slab = step + 1 == steps;
+    const int64_t a_next = last_of_slab ? a + kBWaves : a;
+    const int step_next = last_of_slab ? 0 : step + 1;
+    if (a_next < a_end) load(a_next, static_cast<int64_t>(step_next) * 16);
+    if (needW) {
+      const zb_s16x4 av = __builtin_bit_cast(zb_s16x4, zb_u32x2{pw[0], pw[1]});
+#pragma unroll
+      for (int g = 0; g < NG; ++g)
+        wacc[g] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+            av, __builtin_bit_cast(zb_s16x4, zb_u32x2{rp[0][g], rp[1][g]}), wacc[g], 0, 0, 0);
+    }
+    if (needZ) {
+      bf32x4 zacc[2] = {bf32x4{0.f, 0.f, 0.f, 0.f}, bf32x4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+      for (int cb = 0; cb < (NG + 3) / 4; ++cb) {
+        __builtin_amdgcn_wave_barrier();  // the previous block's reads of the stage stay above
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int gg = 0; gg < 4; ++gg)
+            if (4 * cb + gg < NG)
+              st[(4 * kg + e) * kStageStride + 16 * gg + li] =
+                  __uint_as_float((rp[e / 2][4 * cb + gg] >> (16 * (e % 2))) << 16);
+        __builtin_amdgcn_wave_barrier();  // cross-lane: stores before the reads below
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          if (4 * cb + kk >= NG) break;  // compile-time
+          const bf32x4 xr = *reinterpret_cast<const bf32x4*>(st + li * kStageStride + 16 * kk + 4 * kg);
+          const zb_u32x2 bq = *reinterpret_cast<const zb_u32x2*>(sPhi16 + li * S16 + 64 * cb + 16 * kk + 4 * kg);
+          const zb_s16x4 xa4 = __builtin_bit_cast(zb_s16x4, zb_u32x2{zb_pack_f(xr[0], xr[1]), zb_pack_f(xr[2], xr[3])});
+          zacc[kk % 2] =
+              __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xa4, __builtin_bit_cast(zb_s16x4, bq), zacc[kk % 2], 0, 0, 0);
+        }
+      }
+      const bf32x4 z = zacc[0] + zacc[1];
+      if (li < sQ) {
+        const gptr<float> zo = Zo + (a * P + pb) * sQ + li;
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (pb + 4 * kg + v < P) zo[(4 * kg + v) * sQ] = z[v];
+      }
+    }
+    if (last_of_slab) {
+      if (needW) {
+        const gptr<float> wo = Wo + a * sP * Q;
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (4 * kg + v < sP && qok[g]) wo[(4 * kg + v) * Q + 16 * g + li] = wacc[g][v];
+          wacc[g] = bf32x4{0.f, 0.f, 0.f, 0.f};
+        }
+      }
+      a = a_next;
+      if (a >= a_end) break;
+    }
+    step = step_next;
+  }
+}
+
 // ------------------------------------------------------------------ core contractions
 // Y = X x_k M (Y[a][i][b] = sum_c M[i][c] X[a][c][b], X viewed as (A, K, B), M: m x K with
 // m <= 16 MT, K <= 256) for every tensor of the batch, on matrix cores.  A wave owns one
@@ -432,7 +581,13 @@ hipError_t launch_zw_batch(const GZwJob* jobs, const int32_t* blkjob, int64_t to
   if (xdt == RT_F32) {
     RT_ZWB_NG(float)
   } else if (xdt == RT_BF16) {
-    RT_ZWB_NG(bf16_t)
+    switch (ng) {
+      case 4: zw_batch_bf16_kernel<4><<<g, kBThreads, 0, st>>>(jobs, blkjob); break;
+      case 8: zw_batch_bf16_kernel<8><<<g, kBThreads, 0, st>>>(jobs, blkjob); break;
+      case 12: zw_batch_bf16_kernel<12><<<g, kBThreads, 0, st>>>(jobs, blkjob); break;
+      case 16: zw_batch_bf16_kernel<16><<<g, kBThreads, 0, st>>>(jobs, blkjob); break;
+      default: return hipErrorInvalidValue;
+    }
   } else {
     return hipErrorInvalidValue;
   }
