@@ -574,14 +574,20 @@ def run_extras(rt, synth, torch, dev, time_steps, log):
         B.upload()
         log(f"timing the 512-tensor batch {tag} ...")
         ms = time_steps(B.launch, 10, 2)
+        graph = B.capture()  # the same launches replayed from a captured graph
+        ms_g = time_steps(graph.replay, 10, 2)
         esz = 4 if tag == "f32" else 2
         alg = 2 * nel * esz  # two reads of every tensor: the sketch pass and the first core contraction
         errs = [rt.rtucker_rel_error(X32[i], B.Gs[i], B.Us[i])[0] for i in range(0, count, 64)]
         out[f"batch512_{tag}"] = {"ms": round(ms, 4), "tensors_per_s": round(count / (ms / 1e3), 1),
                                   "alg_bytes": alg, "GB/s": round(alg / ms / 1e6, 1),
-                                  "hbm_frac": round(alg / ms / 1e6 / (HBM_PEAK / 1e9), 4), "core_row_tile": mt,
-                                  "sketch_slabs_per_wave": spb,
+                                  "hbm_frac": round(alg / ms / 1e6 / (HBM_PEAK / 1e9), 4),
+                                  "graph_ms": round(ms_g, 4),
+                                  "graph_tensors_per_s": round(count / (ms_g / 1e3), 1),
+                                  "graph_hbm_frac": round(alg / ms_g / 1e6 / (HBM_PEAK / 1e9), 4),
+                                  "core_row_tile": mt, "sketch_slabs_per_wave": spb,
                                   "max_rel_err_sampled": max(errs)}
+        del graph
         del B
     return out
 
