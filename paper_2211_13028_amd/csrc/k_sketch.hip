@@ -312,17 +312,23 @@ __global__ __launch_bounds__(kZWThreads) __attribute__((amdgpu_waves_per_eu(3)))
 //  * W^T: A = PhiP[c][p] (one value per lane), B = the loaded groups, component c
 //    giving columns 4 n + c, so four MFMAs cover 64 columns per row quad;
 //  * Z: the 16 x 128 tile is staged row-major in the wave's LDS area and read back
-//    with lane (row li, 4 consecutive columns at 4 kg) as A; PhiQ (read from the
-//    caches) is B.  Partial Z rows are added across the waves in LDS (fixed order).
+//    with lane (row li, 4 consecutive columns at 4 kg) as A; PhiQ is B, staged in LDS
+//    once per workgroup when s <= 8 (read from the caches, the 16 rows of a lane group
+//    touched 16 cache lines per load every step), else read from the caches.  Partial Z
+//    rows are added across the waves in LDS (fixed order).
 // Requires Q % 4 == 0; P, A arbitrary; s <= 16.
 constexpr int kF32Stride = 132;  // floats per staged row: 128 + 4 padding
+constexpr int kPhiQRows = 8;                     // PhiQ rows kept in LDS (s <= 8)
+constexpr int kPhiQStride = kZWColsMfma + 8;     // floats per row: 16-byte rows, rows 8 banks apart
 
+template <bool QLDS>
 __global__ __launch_bounds__(kZWThreads) __attribute__((amdgpu_waves_per_eu(3))) void sketch_zw_f32_mfma_kernel(
     const float* __restrict__ X, int64_t A, int64_t P, int64_t Q, const float* __restrict__ phiP, int sP,
     const float* __restrict__ phiQ, int sQ, int64_t rows_per_block, int qblocks, int pblocks,
     float* __restrict__ Zo, float* __restrict__ Wo) {
   __shared__ float tile[kZWWaves][16 * kF32Stride];
   __shared__ float zpart[2][kZWWaves][16 * 16];
+  __shared__ __align__(16) float sPhiQ[QLDS ? kPhiQRows * kPhiQStride : 4];  // PhiQ rows < 8 of the block's columns
   const int lane = threadIdx.x % kWave;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int64_t blk = blockIdx.x;
@@ -366,7 +372,17 @@ __global__ __launch_bounds__(kZWThreads) __attribute__((amdgpu_waves_per_eu(3)))
       for (int j = 0; j < 2; ++j) rn[t][j] = *reinterpret_cast<const f32x4*>(xa + pc * Q + qcc[j]);
     }
   };
-  load_step(pbeg);
+  load_step(pbeg);  // in flight while PhiQ is staged
+  // PhiQ (sQ <= 8) for the block's 512 columns in LDS, zero past sQ and past qend
+  if (QLDS && needZ) {
+    for (int g = threadIdx.x; g < kPhiQRows * (kZWColsMfma / 4); g += kZWThreads) {
+      const int c = g / (kZWColsMfma / 4), q4 = 4 * (g % (kZWColsMfma / 4));
+      f32x4 v = f32x4{0.f, 0.f, 0.f, 0.f};
+      if (c < sQ && q0 + q4 < qend) v = *reinterpret_cast<const f32x4*>(phiQ + static_cast<int64_t>(c) * Q + q0 + q4);
+      *reinterpret_cast<f32x4*>(&sPhiQ[c * kPhiQStride + q4]) = v;
+    }
+  }
+  __syncthreads();
   int buf = 0;
   for (int64_t pb = pbeg; pb < pend; pb += 16) {
     f32x4 r[4][2];
@@ -405,8 +421,14 @@ __global__ __launch_bounds__(kZWThreads) __attribute__((amdgpu_waves_per_eu(3)))
         // PhiQ[li][qw + 16 kb + 4 kg .. + 3]: a small operand re-read from the caches each step
         // (holding it in registers would cost the occupancy)
         const int64_t qk = qw + 16 * kb + 4 * kg;
-        f32x4 bq = *reinterpret_cast<const f32x4*>(phiQ + static_cast<int64_t>(li) * Q + ((qk < qend) ? qk : qend - 4));
-        if (!(qk < qend)) bq = f32x4{0.f, 0.f, 0.f, 0.f};
+        f32x4 bq;
+        if constexpr (QLDS) {
+          bq = *reinterpret_cast<const f32x4*>(&sPhiQ[(li & (kPhiQRows - 1)) * kPhiQStride + (qk - q0)]);
+          if (li >= kPhiQRows) bq = f32x4{0.f, 0.f, 0.f, 0.f};
+        } else {
+          bq = *reinterpret_cast<const f32x4*>(phiQ + static_cast<int64_t>(li) * Q + ((qk < qend) ? qk : qend - 4));
+          if (!(qk < qend)) bq = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
         const f32x4 xr = *reinterpret_cast<const f32x4*>(my + li * kF32Stride + 16 * kb + 4 * kg);
 #pragma unroll
         for (int c = 0; c < 4; ++c) zacc = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[c], bq[c], zacc, 0, 0, 0);
@@ -553,11 +575,18 @@ hipError_t launch_sketch_zw(const void* X, rt_dtype xdt, int64_t A, int64_t P, i
   const int isP = static_cast<int>(sP), isQ = static_cast<int>(sQ);
   if (plan.mfma) {
     const int64_t blocks = A * plan.pblocks * plan.qblocks;
-    if (xdt == RT_F32)
-      sketch_zw_f32_mfma_kernel<<<static_cast<unsigned>(blocks), kZWThreads, 0, st>>>(
-          static_cast<const float*>(X), A, P, Q, static_cast<const float*>(phiP16), isP,
-          static_cast<const float*>(phiQ16), isQ, plan.rows_per_block, static_cast<int>(plan.qblocks),
-          static_cast<int>(plan.pblocks), static_cast<float*>(zdst), static_cast<float*>(wdst));
+    if (xdt == RT_F32) {
+      if (sQ <= kPhiQRows)
+        sketch_zw_f32_mfma_kernel<true><<<static_cast<unsigned>(blocks), kZWThreads, 0, st>>>(
+            static_cast<const float*>(X), A, P, Q, static_cast<const float*>(phiP16), isP,
+            static_cast<const float*>(phiQ16), isQ, plan.rows_per_block, static_cast<int>(plan.qblocks),
+            static_cast<int>(plan.pblocks), static_cast<float*>(zdst), static_cast<float*>(wdst));
+      else
+        sketch_zw_f32_mfma_kernel<false><<<static_cast<unsigned>(blocks), kZWThreads, 0, st>>>(
+            static_cast<const float*>(X), A, P, Q, static_cast<const float*>(phiP16), isP,
+            static_cast<const float*>(phiQ16), isQ, plan.rows_per_block, static_cast<int>(plan.qblocks),
+            static_cast<int>(plan.pblocks), static_cast<float*>(zdst), static_cast<float*>(wdst));
+    }
     else if (xdt == RT_F8E4M3)
       sketch_zw_bf16_mfma_kernel<f8_t><<<static_cast<unsigned>(blocks), kZWThreads, 0, st>>>(
           static_cast<const f8_t*>(X), A, P, Q, static_cast<const bf16_t*>(phiP16), isP,
