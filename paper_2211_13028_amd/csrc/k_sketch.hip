@@ -329,6 +329,7 @@ __global__ __launch_bounds__(kZWThreads) __attribute__((amdgpu_waves_per_eu(3)))
   __shared__ float tile[kZWWaves][16 * kF32Stride];
   __shared__ float zpart[2][kZWWaves][16 * 16];
   __shared__ __align__(16) float sPhiQ[QLDS ? kPhiQRows * kPhiQStride : 4];  // PhiQ rows < 8 of the block's columns
+  __shared__ float sPhiP[QLDS ? 2 * 256 : 1];  // PhiP of a step, [parity][p - pb][c]
   const int lane = threadIdx.x % kWave;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int64_t blk = blockIdx.x;
@@ -367,12 +368,26 @@ __global__ __launch_bounds__(kZWThreads) __attribute__((amdgpu_waves_per_eu(3)))
     for (int t = 0; t < 4; ++t) {
       const int64_t p = pb + 4 * t + kg;
       const int64_t pc = (p < pend) ? p : pend - 1;
-      ppn[t] = *(needW ? phiP + static_cast<int64_t>(li) * P + pc : phiQ + static_cast<int64_t>(li) * Q + (qend - 4));
+      if constexpr (!QLDS)
+        ppn[t] = *(needW ? phiP + static_cast<int64_t>(li) * P + pc : phiQ + static_cast<int64_t>(li) * Q + (qend - 4));
 #pragma unroll
       for (int j = 0; j < 2; ++j) rn[t][j] = *reinterpret_cast<const f32x4*>(xa + pc * Q + qcc[j]);
     }
   };
   load_step(pbeg);  // in flight while PhiQ is staged
+  // QLDS: the PhiP rows of a step are staged in LDS during the step before (thread: c = tid / 16,
+  // p = pb + tid % 16, zero past pend), loaded one step earlier still; the Z path's barrier
+  // of each step orders the stores before the next step's reads
+  const int pc_c = threadIdx.x / 16, pc_p = threadIdx.x % 16;
+  const auto phip_at = [&](int64_t pb) {
+    const int64_t p = pb + pc_p;
+    return (needW && p < pend) ? phiP[static_cast<int64_t>(pc_c) * P + p] : 0.f;
+  };
+  float pvn = 0.f;
+  if constexpr (QLDS) {
+    sPhiP[pc_p * 16 + pc_c] = phip_at(pbeg);
+    pvn = phip_at(pbeg + 16);
+  }
   // PhiQ (sQ <= 8) for the block's 512 columns in LDS, zero past sQ and past qend
   if (QLDS && needZ) {
     for (int g = threadIdx.x; g < kPhiQRows * (kZWColsMfma / 4); g += kZWThreads) {
@@ -392,7 +407,14 @@ __global__ __launch_bounds__(kZWThreads) __attribute__((amdgpu_waves_per_eu(3)))
       const bool pin = pb + 4 * t + kg < pend;
 #pragma unroll
       for (int j = 0; j < 2; ++j) r[t][j] = (ok[j] && pin) ? rn[t][j] : f32x4{0.f, 0.f, 0.f, 0.f};
-      ppv[t] = pin ? ppn[t] : 0.f;
+      if constexpr (QLDS)
+        ppv[t] = pin ? sPhiP[buf * 256 + (4 * t + kg) * 16 + li] : 0.f;
+      else
+        ppv[t] = pin ? ppn[t] : 0.f;
+    }
+    if constexpr (QLDS) {
+      sPhiP[(buf ^ 1) * 256 + pc_p * 16 + pc_c] = pvn;  // the next step's rows
+      pvn = phip_at(pb + 32);
     }
     __builtin_amdgcn_sched_barrier(0);
     load_step(pb + 16);  // past pend: clamped, never used
@@ -576,7 +598,7 @@ hipError_t launch_sketch_zw(const void* X, rt_dtype xdt, int64_t A, int64_t P, i
   if (plan.mfma) {
     const int64_t blocks = A * plan.pblocks * plan.qblocks;
     if (xdt == RT_F32) {
-      if (sQ <= kPhiQRows)
+      if (sQ <= kPhiQRows && zdst != nullptr)
         sketch_zw_f32_mfma_kernel<true><<<static_cast<unsigned>(blocks), kZWThreads, 0, st>>>(
             static_cast<const float*>(X), A, P, Q, static_cast<const float*>(phiP16), isP,
             static_cast<const float*>(phiQ16), isQ, plan.rows_per_block, static_cast<int>(plan.qblocks),
