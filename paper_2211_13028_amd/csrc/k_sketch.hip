@@ -311,13 +311,13 @@ __global__ __launch_bounds__(kZWThreads) __attribute__((amdgpu_waves_per_eu(3)))
 // 4t + kg of each row quad t as two 16-byte groups (columns 4 li.. and 64 + 4 li..):
 //  * W^T: A = PhiP[c][p] (one value per lane), B = the loaded groups, component c
 //    giving columns 4 n + c, so four MFMAs cover 64 columns per row quad;
-//  * Z: the 16 x 128 tile is staged row-major in the wave's LDS area and read back
-//    with lane (row li, 4 consecutive columns at 4 kg) as A; PhiQ is B, staged in LDS
+//  * Z: the 16 x 128 tile is staged row-major in the wave's LDS area, 64 columns at a
+//    time, and read back with lane (row li, 4 consecutive columns at 4 kg) as A; PhiQ is B, staged in LDS
 //    once per workgroup when s <= 8 (read from the caches, the 16 rows of a lane group
 //    touched 16 cache lines per load every step), else read from the caches.  Partial Z
 //    rows are added across the waves in LDS (fixed order).
 // Requires Q % 4 == 0; P, A arbitrary; s <= 16.
-constexpr int kF32Stride = 132;  // floats per staged row: 128 + 4 padding
+constexpr int kF32Stride = 68;  // floats per staged row: 64 + 4 padding (rows four banks apart)
 constexpr int kPhiQRows = 8;                     // PhiQ rows kept in LDS (s <= 8)
 constexpr int kPhiQStride = kZWColsMfma + 8;     // floats per row: 16-byte rows, rows 8 banks apart
 
@@ -431,15 +431,17 @@ __global__ __launch_bounds__(kZWThreads) __attribute__((amdgpu_waves_per_eu(3)))
       }
     }
     if (needZ) {
-      __builtin_amdgcn_wave_barrier();  // the previous step's reads of the staging area stay above
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) *reinterpret_cast<f32x4*>(my + (4 * t + kg) * kF32Stride + 64 * j + 4 * li) = r[t][j];
-      __builtin_amdgcn_wave_barrier();  // cross-lane: stores before the reads below
       f32x4 zacc = f32x4{0.f, 0.f, 0.f, 0.f};
+      // the 16 x 128 tile in two halves of 64 columns (a 16 x 64 stage per wave)
 #pragma unroll
       for (int kb = 0; kb < 8; ++kb) {
+        if (kb % 4 == 0) {
+          __builtin_amdgcn_wave_barrier();  // the previous half's reads of the stage stay above
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            *reinterpret_cast<f32x4*>(my + (4 * t + kg) * kF32Stride + 4 * li) = r[t][kb / 4];
+          __builtin_amdgcn_wave_barrier();  // cross-lane: stores before the reads below
+        }
         // PhiQ[li][qw + 16 kb + 4 kg .. + 3]: a small operand re-read from the caches each step
         // (holding it in registers would cost the occupancy)
         const int64_t qk = qw + 16 * kb + 4 * kg;
@@ -451,7 +453,7 @@ __global__ __launch_bounds__(kZWThreads) __attribute__((amdgpu_waves_per_eu(3)))
           bq = *reinterpret_cast<const f32x4*>(phiQ + static_cast<int64_t>(li) * Q + ((qk < qend) ? qk : qend - 4));
           if (!(qk < qend)) bq = f32x4{0.f, 0.f, 0.f, 0.f};
         }
-        const f32x4 xr = *reinterpret_cast<const f32x4*>(my + li * kF32Stride + 16 * kb + 4 * kg);
+        const f32x4 xr = *reinterpret_cast<const f32x4*>(my + li * kF32Stride + 16 * (kb % 4) + 4 * kg);
 #pragma unroll
         for (int c = 0; c < 4; ++c) zacc = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[c], bq[c], zacc, 0, 0, 0);
       }
