@@ -394,21 +394,24 @@ __global__ __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(2)
 // cache lines per load, as many line accesses as the X loads themselves (the kernel ran
 // 23 % faster in a timing build without the M loads).  Waves past the last unit run the
 // loop on unit 0's data and store nothing.
-constexpr int kMWin = 192;              // k per window: four rounds of three 16-k blocks
+constexpr int kMWin = 192;              // k per window: whole rounds of DEPTH 16-k blocks
+// two waves per SIMD with two blocks of X in flight each (measured 10 % faster than one wave
+// with three; three tiles plus two tail rows take one block, to stay within 256 registers)
+constexpr int mlds_depth(int mt, int tail) { return (mt == 3 && tail == 2) ? 1 : 2; }
 constexpr int kMWinStride = kMWin + 4;  // floats per staged row: 16-byte rows, rows four banks apart
 
-template <int MT, int TAIL>
-__global__ __launch_bounds__(kMfmaThreads) void ttm_mfma_f32_mlds_kernel(const float* __restrict__ X, int64_t A,
+template <int MT, int TAIL, int DEPTH, bool OCC2>
+__global__ __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(OCC2 ? 2 : 1))) void ttm_mfma_f32_mlds_kernel(const float* __restrict__ X, int64_t A,
                                                                          int64_t K, int64_t B,
                                                                          const float* __restrict__ Mop,
                                                                          int64_t m, int64_t chunks,
                                                                          float* __restrict__ Y) {
-  constexpr int DEPTH = 3;
-  static_assert(16 * DEPTH * 4 == kMWin, "a window is four rounds of DEPTH blocks");
+  constexpr int kRounds = kMWin / (16 * DEPTH);  // rounds of DEPTH blocks per window
+  static_assert(kRounds * 16 * DEPTH == kMWin, "a window is whole rounds of DEPTH blocks");
   constexpr int kRows = 16 * MT + TAIL;
   constexpr int kF4 = kMWin / 4;        // 16-byte groups per staged row
   constexpr int kGroups = kRows * kF4;  // per window
-  constexpr int kPer = (kGroups + 4 * kMfmaThreads - 1) / (4 * kMfmaThreads);  // per thread and round
+  constexpr int kPer = (kGroups + kRounds * kMfmaThreads - 1) / (kRounds * kMfmaThreads);  // per thread and round
   __shared__ __align__(16) float sMw[2][kRows * kMWinStride];
   const int tid = threadIdx.x;
   const int lane = tid % kWave;
@@ -515,13 +518,13 @@ __global__ __launch_bounds__(kMfmaThreads) void ttm_mfma_f32_mlds_kernel(const f
   for_each_index([&](auto Pc) { load_block(16 * decltype(Pc)::value, Pc); }, sets);
   // window 0 before the loop
 #pragma unroll
-  for (int round = 0; round < 4; ++round) {
+  for (int round = 0; round < kRounds; ++round) {
     stage_load(0, round);
     stage_store(0, round);
   }
   __syncthreads();
   for (int64_t k0 = 0; k0 < K; k0 += 16 * DEPTH) {
-    const int round = static_cast<int>((k0 / (16 * DEPTH)) % 4);
+    const int round = static_cast<int>((k0 / (16 * DEPTH)) % kRounds);
     const bool more = kw + kMWin < K;
     if (more) stage_load(kw + kMWin, round);
     for_each_index(
@@ -531,7 +534,7 @@ __global__ __launch_bounds__(kMfmaThreads) void ttm_mfma_f32_mlds_kernel(const f
         },
         sets);
     if (more) stage_store(buf ^ 1, round);
-    if (round == 3 || k0 + 16 * DEPTH >= K) {
+    if (round == kRounds - 1 || k0 + 16 * DEPTH >= K) {
       __syncthreads();  // the window is read by every wave and the next one staged
       buf ^= 1;
       kw += kMWin;
@@ -901,7 +904,8 @@ hipError_t launch_ttm_mfma_ws(const void* X, rt_dtype xdt, int64_t A, int64_t K,
   const int MTfull = static_cast<int>(m / 16);
 #define RT_LAUNCH_F32_TAIL(MTV, TV)                                                                         \
   if (p.ksplit == 1)                                                                                         \
-    ttm_mfma_f32_mlds_kernel<MTV, TV><<<grid, kMfmaThreads, 0, st>>>(static_cast<const float*>(X), A, K, B,  \
+    ttm_mfma_f32_mlds_kernel<MTV, TV, mlds_depth(MTV, TV), true><<<grid, kMfmaThreads, 0, st>>>(             \
+        static_cast<const float*>(X), A, K, B,                                                               \
                                                                      static_cast<const float*>(Mop), m,      \
                                                                      p.chunks, out);                         \
   else                                                                                                       \
