@@ -824,9 +824,9 @@ __device__ __forceinline__ void eig_jacobi(const double* __restrict__ M, int n, 
 // ------------------------------------------------------------------ tridiagonal eigensolver
 // The r <= 32 leading eigenpairs of the Gram matrix, in four phases on one workgroup:
 //  1. Householder reduction to tridiagonal form, T = Q^T A Q with Q = H_0 ... H_{n-3};
-//  2. the r largest eigenvalues of T by multisection: 8 lanes per eigenvalue evaluate the
+//  2. the r largest eigenvalues of T by multisection: 16 lanes per eigenvalue evaluate the
 //     Sturm count (sign changes of the leading principal minors, a three-term recurrence
-//     rescaled by powers of two) at 8 interior points of its bracket, which shrinks 9x
+//     rescaled by powers of two) at 16 interior points of its bracket, which shrinks 17x
 //     per step;
 //  3. eigenvectors of T by inverse iteration, one lane per eigenvalue: LU of T - lambda I
 //     with partial pivoting (tiny pivots raised to eps |T|), two solves from a fixed
@@ -839,8 +839,9 @@ __device__ __forceinline__ void eig_jacobi(const double* __restrict__ M, int n, 
 // independent, the caller falls back to the Jacobi solver.  The phases are sequential
 // chains of about 50 steps each instead of the ~350 rounds of Jacobi sweeps.
 constexpr int kTriMaxR = 32;
-constexpr int kMsGroup = 8;    // lanes per eigenvalue in the multisection (r <= 32: four waves)
-constexpr int kMsIters = 18;   // 9^18 > 2^57: the bracket reaches rounding level of |T|
+constexpr int kMsGroup = 16;   // lanes per eigenvalue in the multisection (r <= 32: eight waves)
+constexpr int kMsIters = 14;   // 17^14 > 2^57: the bracket reaches rounding level of |T|
+static_assert(kMsGroup * kTriMaxR <= kJThreads, "one lane group per eigenvalue");
 constexpr int kInvIters = 2;
 // scratch region B (doubles): five n x RM arrays of the inverse iteration (RM: the bound on
 // r); aliased by the per-wave vectors and partial sums of phase 1, by E and F of phase 4,
