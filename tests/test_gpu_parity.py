@@ -243,6 +243,27 @@ def test_core_first_contraction_tail_rows(m, K):
     assert_entrywise(G, want, bound, 2e-5, f"core m={m} K={K}")
 
 
+@pytest.mark.parametrize("m", [17, 49, 50])
+@pytest.mark.parametrize("K", [92, 212])
+def test_core_first_contraction_unsplit(m, K):
+    """Enough columns that k is not split (2049 128-column units: the last workgroup has
+    three idle waves, the last unit 124 columns), so the binary32 tail-row contraction stages
+    U_hat in LDS: one partial window of k (K = 92) or a full one and a partial one (K = 212)."""
+    say("core unsplit", m, K)
+    rng = np.random.default_rng(403 + m + K)
+    B = 128 * 2049 - 4
+    dims = (K, 4, B // 4)
+    X = L.round_f32(rng.standard_normal((K, B), dtype=np.float32).astype(np.float64)).reshape(dims)
+    U = np.linalg.qr(rng.standard_normal((K, m)))[0]
+    G = host(rt.rtucker_core(dev(X, torch.float32), [dev(U), None, None], modes=[0])).reshape(m, B)
+    Ur = L.round_f32(U)
+    cols = np.r_[0:512, B - 700:B]  # the first units and the ragged last ones
+    Xc = X.reshape(K, B)[:, cols]
+    want = Ur.T @ Xc
+    bound = np.abs(Ur).T @ np.abs(Xc)
+    assert_entrywise(G[:, cols], want, bound, 2e-5, f"core unsplit m={m} K={K}")
+
+
 # ------------------------------------------------------------------ decomposition
 def _decompose_and_compare(X, Xd, r, p, algo, phis, s, tol_e, Xsk=None, emulate=None):
     phis_d = [dev(f) for f in phis] if algo == "rhkron" else [[dev(f) if f is not None else None for f in row]
@@ -448,7 +469,8 @@ def test_rel_error_counts_nonfinite(dt):
 # ------------------------------------------------------------------ the streaming sketch pass alone
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f8"])
 @pytest.mark.parametrize("shape,sp,sl", [((37, 150, 530), 7, 7), ((64, 64, 64), 4, 4), ((11, 13, 17, 70), 3, 5),
-                                         ((20, 24, 30), 9, 10), ((1024, 1024 // 8, 512 // 4), 7, 7)])
+                                         ((20, 24, 30), 9, 10), ((1024, 1024 // 8, 512 // 4), 7, 7),
+                                         ((8, 40, 132), 9, 12)])  # s of the last mode past 8 (PhiQ not in LDS)
 def test_sketch_pass(dtype, shape, sp, sl):
     say("sketch pass", shape, sp, sl, dtype)
     rng = np.random.default_rng(51)
@@ -478,3 +500,6 @@ def test_sketch_pass(dtype, shape, sp, sl):
     # one output only
     Z2, W2 = rt.rtucker_sketch_pass(Xd, dev(Pp), dev(Pl), want=(True, False))
     assert W2 is None and np.array_equal(host(Z2), host(Z))
+    Z3, W3 = rt.rtucker_sketch_pass(Xd, dev(Pp), dev(Pl), want=(False, True))
+    assert Z3 is None
+    assert_entrywise(host(W3), Wr, T.ttm(np.abs(Xs), np.abs(Pp_), d - 2), tol, "W alone")
