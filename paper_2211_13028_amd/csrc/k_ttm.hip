@@ -388,7 +388,7 @@ __global__ __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(2)
 // K % 4 == 0 (rows 16 MT .. 16 MT + TAIL - 1 on the vector ALU as above).  The four waves
 // of a workgroup take four consecutive units, which share the k loop, so M is staged once
 // per workgroup in windows of kMWin k, double-buffered: every thread stages a share of the
-// next window during each round of three 16-k blocks of the current one, and a barrier
+// next window during each round of DEPTH 16-k blocks of the current one, and a barrier
 // closes each window.  A lane's A operand (16 rows, four consecutive k) is then one 16-byte
 // LDS read per tile; read from the caches instead, the 16 rows of a lane group touch 16
 // cache lines per load, as many line accesses as the X loads themselves (the kernel ran
@@ -401,11 +401,9 @@ constexpr int mlds_depth(int mt, int tail) { return (mt == 3 && tail == 2) ? 1 :
 constexpr int kMWinStride = kMWin + 4;  // floats per staged row: 16-byte rows, rows four banks apart
 
 template <int MT, int TAIL, int DEPTH, bool OCC2>
-__global__ __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(OCC2 ? 2 : 1))) void ttm_mfma_f32_mlds_kernel(const float* __restrict__ X, int64_t A,
-                                                                         int64_t K, int64_t B,
-                                                                         const float* __restrict__ Mop,
-                                                                         int64_t m, int64_t chunks,
-                                                                         float* __restrict__ Y) {
+__global__ __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(OCC2 ? 2 : 1))) void
+ttm_mfma_f32_mlds_kernel(const float* __restrict__ X, int64_t A, int64_t K, int64_t B, const float* __restrict__ Mop,
+                         int64_t m, int64_t chunks, float* __restrict__ Y) {
   constexpr int kRounds = kMWin / (16 * DEPTH);  // rounds of DEPTH blocks per window
   static_assert(kRounds * 16 * DEPTH == kMWin, "a window is whole rounds of DEPTH blocks");
   constexpr int kRows = 16 * MT + TAIL;
