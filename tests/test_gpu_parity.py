@@ -264,6 +264,27 @@ def test_core_first_contraction_unsplit(m, K):
     assert_entrywise(G[:, cols], want, bound, 2e-5, f"core unsplit m={m} K={K}")
 
 
+@pytest.mark.parametrize("m", [17, 49])
+@pytest.mark.parametrize("K", [96, 200])
+def test_core_first_contraction_unsplit_bf16(m, K):
+    """The bfloat16 matrix-core contraction without a split over k: 2049 units (three idle
+    waves in the last workgroup, a ragged last unit), K = 96 and 200."""
+    say("core unsplit bf16", m, K)
+    rng = np.random.default_rng(404 + m + K)
+    B = 128 * 2049 - 8
+    dims = (K, 8, B // 8)
+    X = L.round_bf16(rng.standard_normal((K, B), dtype=np.float32).astype(np.float64)).reshape(dims)
+    U = np.linalg.qr(rng.standard_normal((K, m)))[0]
+    Xd = rt.rtucker_convert(dev(X, torch.float32), torch.bfloat16)
+    G = host(rt.rtucker_core(Xd, [dev(U), None, None], modes=[0])).reshape(m, B)
+    Ur = L.round_bf16(U)
+    cols = np.r_[0:512, B - 700:B]
+    Xc = X.reshape(K, B)[:, cols]
+    want = Ur.T @ Xc
+    bound = np.abs(Ur).T @ np.abs(Xc)
+    assert_entrywise(G[:, cols], want, bound, 2e-5, f"core unsplit bf16 m={m} K={K}")
+
+
 # ------------------------------------------------------------------ decomposition
 def _decompose_and_compare(X, Xd, r, p, algo, phis, s, tol_e, Xsk=None, emulate=None):
     phis_d = [dev(f) for f in phis] if algo == "rhkron" else [[dev(f) if f is not None else None for f in row]
