@@ -824,10 +824,10 @@ __device__ __forceinline__ void eig_jacobi(const double* __restrict__ M, int n, 
 // ------------------------------------------------------------------ tridiagonal eigensolver
 // The r <= 32 leading eigenpairs of the Gram matrix, in four phases on one workgroup:
 //  1. Householder reduction to tridiagonal form, T = Q^T A Q with Q = H_0 ... H_{n-3};
-//  2. the r largest eigenvalues of T by multisection: 16 lanes per eigenvalue evaluate the
+//  2. the r largest eigenvalues of T by multisection: G lanes per eigenvalue evaluate the
 //     Sturm count (sign changes of the leading principal minors, a three-term recurrence
-//     rescaled by powers of two) at 16 interior points of its bracket, which shrinks 17x
-//     per step;
+//     rescaled by powers of two) at G interior points of its bracket, which shrinks
+//     (G + 1)x per step (G = 16 for r <= 16, else 8, so at most four waves count);
 //  3. eigenvectors of T by inverse iteration, one lane per eigenvalue: LU of T - lambda I
 //     with partial pivoting (tiny pivots raised to eps |T|), two solves from a fixed
 //     pseudo-random start vector;
@@ -839,9 +839,12 @@ __device__ __forceinline__ void eig_jacobi(const double* __restrict__ M, int n, 
 // independent, the caller falls back to the Jacobi solver.  The phases are sequential
 // chains of about 50 steps each instead of the ~350 rounds of Jacobi sweeps.
 constexpr int kTriMaxR = 32;
-constexpr int kMsGroup = 16;   // lanes per eigenvalue in the multisection (r <= 32: eight waves)
-constexpr int kMsIters = 14;   // 17^14 > 2^57: the bracket reaches rounding level of |T|
-static_assert(kMsGroup * kTriMaxR <= kJThreads, "one lane group per eigenvalue");
+// Multisection widths: the Sturm counts are issue-bound, so the lane groups are sized to
+// keep at most one counting wave per SIMD (r <= 16: 16 lanes, 17^14 > 2^57; r <= 32:
+// 8 lanes, 9^18 > 2^57); either way the bracket reaches rounding level of |T|.
+constexpr int kMsLanes = 256;
+static_assert(16 * 16 <= kMsLanes && 8 * kTriMaxR <= kMsLanes && kMsLanes <= kJThreads,
+              "one lane group per eigenvalue");
 constexpr int kInvIters = 2;
 // scratch region B (doubles): five n x RM arrays of the inverse iteration (RM: the bound on
 // r); aliased by the per-wave vectors and partial sums of phase 1, by E and F of phase 4,
@@ -954,7 +957,35 @@ __device__ __forceinline__ int sturm_count(const double* __restrict__ d, const d
   return static_cast<int>(cnt);
 }
 
-constexpr int kP1Waves = 4;
+// Multisection for the r largest eigenvalues of T (d, e2 padded as sturm_count reads them):
+// lanes G g .. G g + G - 1 bracket the g-th largest; ITERS steps shrink [lo, hi] by
+// (G + 1)^ITERS.  lam[g] = the midpoint of the final bracket.
+template <int G, int ITERS>
+__device__ __forceinline__ void multisect(const double* __restrict__ d, const double* __restrict__ e2,
+                                          const double* __restrict__ bounds, int n, int r,
+                                          double* __restrict__ lam) {
+  static_assert(kWave % G == 0 && G <= 32, "lane groups within a wave");
+  const int tid = threadIdx.x;
+  if (tid >= G * r) return;
+  const int g = tid / G, sub = tid % G;
+  const int target = n - 1 - g;  // count(x) > target  <=>  x above the g-th largest
+  double a = bounds[0], b = bounds[1];
+  const double cl = static_cast<double>(sub + 1) / (G + 1);
+  for (int it = 0; it < ITERS; ++it) {
+    const double wd = b - a;
+    const int cnt = sturm_count(d, e2, n, fma(wd, cl, a));
+    const unsigned long long bal = __ballot(cnt > target);
+    const unsigned bits = static_cast<unsigned>(bal >> (G * (g % (kWave / G)))) & ((1u << G) - 1u);
+    const int l = bits ? __builtin_ctz(bits) : G;
+    const double na = (l == 0) ? a : fma(wd, static_cast<double>(l) / (G + 1), a);
+    const double nb = (l == G) ? b : fma(wd, static_cast<double>(l + 1) / (G + 1), a);
+    a = na;
+    b = nb;
+  }
+  if (sub == 0) lam[g] = 0.5 * (a + b);
+}
+
+constexpr int kP1Waves = 8;  // (measured: 4% faster than four waves of 16 columns)
 constexpr int kP1Cols = kJN / kP1Waves;  // matrix columns held in registers per wave
 
 // Returns true (uniformly over the workgroup) when V and evals were written.  RM (32 or
@@ -985,11 +1016,11 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
     ebits = 0;
     rbits = 0;
   }
-  // ---- 1. Householder tridiagonalisation on four waves (one per SIMD).  Column j of the
-  //         matrix lives in registers of wave j % 4, slot j / 4 (lane = row), for the whole
+  // ---- 1. Householder tridiagonalisation on eight waves (two per SIMD).  Column j of the
+  //         matrix lives in registers of wave j % 8, slot j / 8 (lane = row), for the whole
   //         reduction.  The matrix-vector product and the rank-2 update touch LDS only for
   //         broadcast reads of v and w, which each wave stores in slot order (entry j at
-  //         (j % 4) 16 + j / 4); v stays in registers from the product to the update.
+  //         (j % 8) 8 + j / 8); v stays in registers from the product to the update.
   //         Every wave keeps column k, the one the reflector of step k is formed from, in
   //         a register.  The wave that owns column k + 1 publishes it as it stands before
   //         step k, together with its partial products; after the step's one barrier every
@@ -1131,25 +1162,10 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
   }
   __syncthreads();
   // ---- 2. multisection: group g brackets the g-th largest eigenvalue
-  if (tid < kMsGroup * RM) {
-    const int g = tid / kMsGroup, sub = tid % kMsGroup;
-    const int target = n - 1 - g;  // count(x) > target  <=>  x above the g-th largest
-    double a = bounds[0], b = bounds[1];
-    const double cl = static_cast<double>(sub + 1) / (kMsGroup + 1);
-    for (int it = 0; it < kMsIters; ++it) {
-      const double wd = b - a;
-      const int cnt = (g < r) ? sturm_count(dS, e2S, n, fma(wd, cl, a)) : 0;
-      const unsigned long long bal = __ballot(cnt > target);
-      const unsigned bits =
-          static_cast<unsigned>(bal >> (kMsGroup * (g % (kWave / kMsGroup)))) & ((1u << kMsGroup) - 1u);
-      const int l = bits ? __builtin_ctz(bits) : kMsGroup;
-      const double na = (l == 0) ? a : fma(wd, static_cast<double>(l) / (kMsGroup + 1), a);
-      const double nb = (l == kMsGroup) ? b : fma(wd, static_cast<double>(l + 1) / (kMsGroup + 1), a);
-      a = na;
-      b = nb;
-    }
-    if (g < r && sub == 0) lamS[g] = 0.5 * (a + b);
-  }
+  if (r > 16)
+    multisect<8, 18>(dS, e2S, bounds, n, r, lamS);
+  else
+    multisect<16, 14>(dS, e2S, bounds, n, r, lamS);
   __syncthreads();
   // ---- 3. inverse iteration, lane m of wave 0 for eigenvalue m.  Loops run over rows with
   //         the row data for the next iterations loaded ahead (unrolled by four).
