@@ -423,11 +423,20 @@ void truncate_impl(Ctx& c, Ten G, const int32_t* r, double* const* Uhat, const s
       c.chk(launch_mode_contract(G.p, G.p, RT_F64, A, cj, cj, B, gram, mcws, c.st));
       c.chk(launch_sym_eig_top(gram, cj, rj, V, nullptr, c.st));
     }
-    G = ttm(c, G, j, V, rj, (j == d - 1) ? Gout : nullptr, /*mtrans=*/true);
+    if (j == d - 1 && G.dt == RT_F64) {
+      // the last mode is the fastest: G x_d V^T is the row-major product G_(rows) V, which
+      // joins the factor updates' launch
+      if (!c.dry)
+        ups.push_back(SmallGemmJob{static_cast<const double*>(G.p), V, Gout, A, static_cast<int32_t>(cj),
+                                   static_cast<int32_t>(rj)});
+    } else {
+      G = ttm(c, G, j, V, rj, (j == d - 1) ? Gout : nullptr, /*mtrans=*/true);
+    }
     if (!c.dry)  // (a workspace query passes no factor arrays)
       ups.push_back(SmallGemmJob{Uhat[j], V, Uout[j], I[j], static_cast<int32_t>(cj), static_cast<int32_t>(rj)});
   }
-  // the factor updates do not feed the truncation: one launch for all modes at the end
+  // the factor updates (and the last mode's contraction) do not feed the truncation: one
+  // launch at the end
   if (!c.dry)
     for (size_t i = 0; i < ups.size(); i += kMaxSmallGemm)
       c.chk(launch_small_gemm_f64(ups.data() + i, static_cast<int>(std::min<size_t>(kMaxSmallGemm, ups.size() - i)),
