@@ -985,8 +985,10 @@ __device__ __forceinline__ void multisect(const double* __restrict__ d, const do
   if (sub == 0) lam[g] = 0.5 * (a + b);
 }
 
-constexpr int kP1Waves = 8;  // (measured: 4% faster than four waves of 16 columns)
-constexpr int kP1Cols = kJN / kP1Waves;  // matrix columns held in registers per wave
+// Waves of the Householder reduction: eight (two per SIMD; measured 4 % faster than four)
+// when the solve has its CU to itself (RM = 32), four when two solves share a CU (RM = 16).
+constexpr int p1_waves(int rm) { return rm == 16 ? 4 : 8; }
+constexpr int kP1MaxWaves = 8;
 
 // Returns true (uniformly over the workgroup) when V and evals were written.  RM (32 or
 // 16) bounds r: the scratch B holds 5 kJN RM doubles.
@@ -995,6 +997,8 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
                                             double* __restrict__ evals, double* __restrict__ Am,
                                             double* __restrict__ B) {
   constexpr int kPad = kJN + 3 * kStBlk;  // tridiagonal arrays padded for the blocked Sturm loop
+  constexpr int kP1Waves = p1_waves(RM);
+  constexpr int kP1Cols = kJN / kP1Waves;  // matrix columns held in registers per wave
   __shared__ double dS[kPad], eS[kPad], e2S[kPad], tauS[kJN], lamS[kJN];
   __shared__ double bounds[3];
   __shared__ unsigned long long ebits, rbits;
@@ -1016,11 +1020,11 @@ __device__ __forceinline__ bool eig_tridiag(const double* __restrict__ M, int n,
     ebits = 0;
     rbits = 0;
   }
-  // ---- 1. Householder tridiagonalisation on eight waves (two per SIMD).  Column j of the
-  //         matrix lives in registers of wave j % 8, slot j / 8 (lane = row), for the whole
+  // ---- 1. Householder tridiagonalisation on W = p1_waves(RM) waves.  Column j of the
+  //         matrix lives in registers of wave j % W, slot j / W (lane = row), for the whole
   //         reduction.  The matrix-vector product and the rank-2 update touch LDS only for
   //         broadcast reads of v and w, which each wave stores in slot order (entry j at
-  //         (j % 8) 8 + j / 8); v stays in registers from the product to the update.
+  //         (j % W) (64 / W) + j / W); v stays in registers from the product to the update.
   //         Every wave keeps column k, the one the reflector of step k is formed from, in
   //         a register.  The wave that owns column k + 1 publishes it as it stands before
   //         step k, together with its partial products; after the step's one barrier every
@@ -1436,7 +1440,7 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ M, int n, in
                                          double* __restrict__ evals) {
   __shared__ __align__(16) double Am[kJN * kAStride];
   static_assert(5 * kJN * RM >= kJN * kLStride, "Jacobi columns must fit the tridiagonal scratch");
-  static_assert(5 * kJN * RM >= 4 * kP1Waves * kJN + 2 * kJN, "phase-1 scratch must fit");
+  static_assert(5 * kJN * RM >= 4 * kP1MaxWaves * kJN + 2 * kJN, "phase-1 scratch must fit");
   __shared__ __align__(16) double B[5 * kJN * RM];
   if (n >= 3 && r <= RM) {
     if (eig_tridiag<RM>(M, n, r, Vout, evals, Am, B)) return;
