@@ -168,7 +168,8 @@ hipError_t launch_gram_wide(const float* X, int64_t A, int64_t m, int64_t B, dou
 // of the r largest eigenvalues, in decreasing order, each column's largest-magnitude
 // entry (first on ties) made positive.  evals (may be null): those r eigenvalues.
 // C = A B for up to kMaxSmallGemm binary64 jobs in one launch (row-major; A: m x k,
-// B: k x n, k, n <= 64), 64 rows of C per workgroup: the factor updates U_j = U_hat_j V_j.
+// B: k x n, k, n <= 64), 64 rows of C per workgroup: the factor updates U_j = U_hat_j V_j
+// and the truncation's last-mode contraction.
 constexpr int kMaxSmallGemm = 8;
 struct SmallGemmJob {
   const double* A;
