@@ -430,6 +430,31 @@ def test_decompose_bitwise_repeatable():
     assert torch.equal(G1, G2) and all(torch.equal(a, b) for a, b in zip(U1, U2))
 
 
+def test_decompose_two_streams_in_flight():
+    """Decompositions enqueued alternately on two streams (own workspaces and outputs, one
+    shared input) return the one-at-a-time results bit for bit."""
+    X = synth.bumps_field((96, 80, 72), nbumps=20, noise_rel=1e-4, seed=16)
+    Xd = dev(X, torch.float32)
+    s = [4, 4, 4]
+    phis = [dev(f) for f in reuse_phis(X.shape, s, seed=17)]
+    G0, U0 = rt.rtucker_decompose(Xd, [6, 6, 6], 4, phis, s=s)
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    nb = rt.rtucker_decompose_workspace(Xd, [6, 6, 6], 4, "rhkron", s)
+    wss = [torch.empty(max(nb, 256), dtype=torch.uint8, device=DEV) for _ in range(2)]
+    outs = []
+    for i in range(6):
+        k = i % 2
+        with torch.cuda.stream(streams[k]):
+            G = torch.empty((6, 6, 6), dtype=torch.float64, device=DEV)
+            Us = [torch.empty((n, 6), dtype=torch.float64, device=DEV) for n in X.shape]
+            rt.rtucker_decompose(Xd, [6, 6, 6], 4, phis, s=s, G=G, Us=Us, ws=wss[k])
+            outs.append((G, Us))
+    torch.cuda.synchronize()
+    for G, Us in outs:
+        assert torch.equal(G, G0) and all(torch.equal(a, b) for a, b in zip(Us, U0))
+
+
 @pytest.mark.parametrize("algo", ["rhkron", "rsthkron"])
 def test_decompose_phases_bitwise_and_positive(algo):
     """The phase-timed call returns the plain call's results bit for bit, and a positive time
