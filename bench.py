@@ -182,33 +182,6 @@ def main():
     results["rhkron_f32"] = {"ms": ms32, "rel_err": e32, "phases_ms": phases_of(X32, sizes=s)}
 
     if not args.no_variants:
-        # Two independent FP32 decompositions in flight, on two streams of default priority
-        # with their own workspaces and outputs: the phases that occupy a few CUs (QR and the
-        # truncation's eigensolves) of one overlap the streaming phases of the other.  Host
-        # clock over 2 * steps decompositions; a throughput figure beside the headline, whose
-        # `value` stays the one-at-a-time step.
-        runA, GA, UA = make_run(X32, sizes=s)
-        runB, GB, UB = make_run(X32, sizes=s)
-        sA, sB = torch.cuda.Stream(), torch.cuda.Stream()
-
-        def in_flight(k):
-            for i in range(k):
-                with torch.cuda.stream(sA if i % 2 == 0 else sB):
-                    (runA if i % 2 == 0 else runB)()
-
-        log("timing two FP32 decompositions in flight ...")
-        in_flight(2 * args.warmup)
-        torch.cuda.synchronize()
-        t_a = time.perf_counter()
-        in_flight(2 * args.steps)
-        torch.cuda.synchronize()
-        ms2 = (time.perf_counter() - t_a) * 1e3 / (2 * args.steps)
-        eA, _ = rt.rtucker_rel_error(X32, GA, UA)
-        eB, _ = rt.rtucker_rel_error(X32, GB, UB)
-        results["rhkron_f32_two_in_flight"] = {"ms_per_decomposition": round(ms2, 4), "streams": 2,
-                                               "rel_err": max(eA, eB), "TFLOP/s": round(step_flops / ms2 / 1e9, 2)}
-
-    if not args.no_variants:
         # BF16 with X resident in bfloat16, and with X arriving in binary32 (the cast timed in the step)
         run16, G16, U16 = make_run(X16, sizes=s)
         log("timing BF16 rHKron ...")

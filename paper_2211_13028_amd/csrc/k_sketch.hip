@@ -540,9 +540,13 @@ ZWPlan sketch_zw_plan(rt_dtype xdt, int64_t A, int64_t P, int64_t Q, int64_t sP,
   if (p.mfma) {
     // Row split for the matrix-core pass: 768 workgroups are resident at once
     // (3 per CU).  Cost in units of "one row per resident workgroup":
-    //   rounds(pb) * rows_per_block  +  partial-W traffic of pb row ranges,
+    //   rows_per_block * max(1, workgroups / 768)  +  partial-W traffic of pb row ranges,
     // with the W partials (written and re-read, binary32) converted at the
-    // 1 KiB of X that one row of 512 bfloat16 columns is.
+    // 1 KiB of X that one row of 512 bfloat16 columns is.  A grid of at least one full
+    // round streams at about the same rate whether its last round is full or not (the
+    // pass is bound by HBM), so rounds count fractionally; a grid below one round is
+    // bound by its longest workgroup.  (Counting the last round as full chose three row
+    // ranges for 1024 x 1024 x 512 binary32, 20 us per decomposition slower than one.)
     const int64_t resident = 768;
     const int64_t step = mf32 ? 16 : 32;  // rows per step of the kernel
     const double row_bytes = static_cast<double>(resident) * kZWColsMfma * (mf32 ? 4 : 2);
@@ -553,7 +557,8 @@ ZWPlan sketch_zw_plan(rt_dtype xdt, int64_t A, int64_t P, int64_t Q, int64_t sP,
       const int64_t pbs = ceil_div(P, rows);
       if (pbs != pb || (pb > 1 && rows < 128)) continue;
       const int64_t wgs = A * p.qblocks * pb;
-      const double t = static_cast<double>(ceil_div(wgs, resident)) * rows +
+      const double rounds = wgs > resident ? static_cast<double>(wgs) / resident : 1.0;
+      const double t = rounds * rows +
                        (pb > 1 && needW ? 2.0 * pb * A * sP * Q * 4.0 / row_bytes : 0.0);
       if (best_rows == 0 || t < best) {
         best = t;
