@@ -306,17 +306,18 @@ __global__ __launch_bounds__(256) void cq_gram_kernel(TAB tab) {
 
 // Sum the partial Grams (fixed order), factor G = R^T R (upper R) and form R^-1: the
 // symmetric elimination on [G | I] turns the left block into R and the right block into
-// R^-T.  Four waves; thread (wave w, lane j) keeps column j of rows C/4 w .. C/4 (w + 1) - 1
-// of both blocks in registers for the whole factorisation (C = 32: lanes 32 .. 63 hold no
+// R^-T.  W = NT / 64 waves (eight for one matrix per launch, measured 4 % faster than four; four
+// in the batched launches, where many workgroups share the CUs); thread (wave w, lane j) keeps
+// column j of rows C/W w .. C/W (w + 1) - 1 of both blocks in registers for the whole factorisation (C = 32: lanes 32 .. 63 hold no
 // column and store nothing).  After each step the wave that
-// owns the next pivot row stores all its 16 rows to LDS (static register indices; rows
+// owns the next pivot row stores all its C/W rows to LDS (static register indices; rows
 // that are not being eliminated keep their values, so concurrent readers of the current
 // row see the same bits), and a step touches LDS only for reads of that row.  Every wave keeps the diagonal in registers (lane j:
 // G[j][j], updated with the same rounding as the matrix).  R goes to the first C^2
 // doubles of the job's R1 / R2 buffer, R^-1 to the second.
-template <typename TAB, int C = kCols>
-__global__ __launch_bounds__(256) void cq_chol_kernel(TAB tab, int second) {
-  constexpr int kW = 256 / kWave;
+template <typename TAB, int C = kCols, int NT = 256>
+__global__ __launch_bounds__(NT) void cq_chol_kernel(TAB tab, int second) {
+  constexpr int kW = NT / kWave;
   constexpr int kRows = C / kW;
   __shared__ __align__(16) double fullL[C][kWave];  // the rows of the owner of the next row
   __shared__ __align__(16) double fullR[C][kWave];
@@ -342,7 +343,7 @@ __global__ __launch_bounds__(256) void cq_chol_kernel(TAB tab, int second) {
   }
 #pragma unroll
   for (int t = 0; t < kRows; ++t) gr[t] = (kRows * wv + t == lane) ? 1.0 : 0.0;
-  for (int idx = threadIdx.x; idx < C * (C + 1); idx += 256) {
+  for (int idx = threadIdx.x; idx < C * (C + 1); idx += NT) {
     (&Rs[0][0])[idx] = 0.0;
     (&Xs[0][0])[idx] = 0.0;
   }
@@ -421,7 +422,7 @@ __global__ __launch_bounds__(256) void cq_chol_kernel(TAB tab, int second) {
     return;
   }
   double* R = second ? J.R2 : J.R1;
-  for (int idx = threadIdx.x; idx < C * C; idx += 256) {
+  for (int idx = threadIdx.x; idx < C * C; idx += NT) {
     const int i = idx / C, j = idx % C;
     const bool in = i < n && j < n && j >= i;
     R[idx] = in ? Rs[i][j] : 0.0;
@@ -430,9 +431,9 @@ __global__ __launch_bounds__(256) void cq_chol_kernel(TAB tab, int second) {
   if (second && J.Rout) {
     // R = R2 R1 with R1 staged in LDS (the inverse array is free now)
     __syncthreads();
-    for (int idx = threadIdx.x; idx < n * C; idx += 256) Xs[idx / C][idx % C] = J.R1[idx];
+    for (int idx = threadIdx.x; idx < n * C; idx += NT) Xs[idx / C][idx % C] = J.R1[idx];
     __syncthreads();
-    for (int idx = threadIdx.x; idx < n * n; idx += 256) {
+    for (int idx = threadIdx.x; idx < n * n; idx += NT) {
       const int i = idx / n, j = idx % n;
       double s0 = 0.0, s1 = 0.0;
       int t = i;
@@ -714,14 +715,14 @@ hipError_t qr_plan(const QRJob* jobs, int count, rt_dtype ydt, bool launch, Bump
     const CTabVal tv{tab};
     if (ydt == RT_F64) {
       cq_gram_kernel<double><<<g1, 256, 0, st>>>(tv);
-      cq_chol_kernel<<<nc, 256, 0, st>>>(tv, 0);
+      cq_chol_kernel<CTabVal, kCols, 512><<<nc, 512, 0, st>>>(tv, 0);
       cq_apply_kernel<double><<<g1, 256, 0, st>>>(tv, 0);
     } else {
       cq_gram_kernel<float><<<g1, 256, 0, st>>>(tv);
-      cq_chol_kernel<<<nc, 256, 0, st>>>(tv, 0);
+      cq_chol_kernel<CTabVal, kCols, 512><<<nc, 512, 0, st>>>(tv, 0);
       cq_apply_kernel<float><<<g1, 256, 0, st>>>(tv, 0);
     }
-    cq_chol_kernel<<<nc, 256, 0, st>>>(tv, 1);
+    cq_chol_kernel<CTabVal, kCols, 512><<<nc, 512, 0, st>>>(tv, 1);
     cq_apply_kernel<double><<<g1, 256, 0, st>>>(tv, 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
